@@ -1,0 +1,205 @@
+/*
+ * librmips -- exact reverse k-MIPS top-N on AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Amagata et al., "How to Mine Potentially Popular Items? A
+ * Reverse MIPS-based Approach"): users U (n x d), items P (m x d).
+ *   Def. 1  S_k(u): the k items with the largest inner product u . p.
+ *   Def. 2  T_k(p) = {u : p in S_k(u)}   (Eq. 1), score(p) = |T_k(p)|.
+ *   Def. 3  the N items with the largest score.
+ *
+ * Exactness.  The value of u . p is defined as the FP64 sum of the exact
+ * products (double)u_i * (double)p_i taken in index order from +0.0.  Every
+ * integer output (item ids, scores, counts) is decided on that value, and
+ * tau is that value, bit for bit.  Ties are ordered (value desc, item id
+ * asc) in k-MIPS and (score desc, item id asc) in top-N, where the paper
+ * breaks them arbitrarily.  With that order, item j is in S_k(u) iff
+ *     v > tau_u,  or  v == tau_u and j <= tau_id_u.
+ * Low-precision screening (FP32, BF16, FP8 e4m3 matrix-core products) only
+ * decides pairs that a certified per-pair error bound separates from the
+ * threshold; all other pairs are recomputed in FP64 on the GPU.
+ *
+ * Conventions for every call.
+ *   - Matrix arguments are device pointers to caller-owned, contiguous,
+ *     row-major FP32 arrays with leading dimension d.  Row i of P has item
+ *     id i.  Vectors (tau, tau_id, scores, ...) are device pointers too,
+ *     except where a comment says "host".
+ *   - The library allocates no device memory.  Scratch space is the
+ *     caller's workspace `ws` of `ws_bytes` bytes (device memory, 256-byte
+ *     aligned), sized by the matching *_workspace_size query.  Its contents
+ *     are undefined after a call.
+ *   - Work is enqueued on the context's HIP stream.  rmips_thresholds and
+ *     rmips_scores wait once, after the input check (a few bytes read
+ *     back), and return before their results are complete; rmips_soft_fwd
+ *     and rmips_soft_bwd do not wait.  rmips_topn synchronises the stream
+ *     (its bound-ordered loop reads a few bytes back per batch) and writes
+ *     host arrays.
+ *   - Arguments are validated before anything is launched.  On error the
+ *     outputs are unspecified and rmips_last_error() describes the error.
+ *   - A context is not thread-safe; use one context per stream.
+ */
+#ifndef RMIPS_H
+#define RMIPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RMIPS_K_MAX 32      /* largest k accepted (the paper uses k <= 25) */
+#define RMIPS_N_MAX 1024    /* largest N accepted by rmips_topn */
+#define RMIPS_D_MAX 256     /* largest dimensionality d */
+
+typedef enum {
+    RMIPS_OK = 0,
+    RMIPS_EINVAL = 1,       /* bad size, pointer or parameter */
+    RMIPS_EWORKSPACE = 2,   /* ws_bytes below the *_workspace_size value */
+    RMIPS_ENONFINITE = 3,   /* NaN or Inf in an input vector */
+    RMIPS_EUNSUPPORTED = 4, /* precision or device not supported */
+    RMIPS_EDEVICE = 5       /* HIP runtime error */
+} rmips_status;
+
+/* Screening precision of the dense products of stages (a) and (b). */
+typedef enum {
+    RMIPS_FP32 = 0,         /* FP32 inputs, FP32 matrix-core accumulation */
+    RMIPS_BF16 = 1,         /* BF16-rounded inputs, FP32 accumulation */
+    RMIPS_FP8_E4M3 = 2      /* OCP e4m3 inputs with a per-vector power-of-two
+                               scale, FP32 accumulation */
+} rmips_prec;
+
+typedef struct rmips_ctx rmips_ctx;
+
+/* Counters and per-stage times of the last rmips_topn call. */
+typedef struct {
+    int64_t visited_items;    /* items whose exact score was computed */
+    int64_t batches;          /* bound-ordered batches run */
+    int64_t cand_pairs;       /* stage (a): candidates rechecked in FP64 */
+    int64_t overflow_users;   /* stage (a): users sent to the exact fallback */
+    int64_t recheck_pairs;    /* stage (b): ambiguous pairs rechecked in FP64 */
+    int64_t screened_pairs;   /* stage (a)+(b): pairs through the matrix cores */
+    int64_t bound_pairs;      /* stage (c): pairs evaluated by the Eq. 3 bound */
+    int64_t thresh_pairs;     /* stage (a): pairs screened after the early exit */
+    int64_t count_pairs;      /* stage (b): (item, user) pairs screened */
+    int64_t count_launches;   /* stage (b): counting kernel launches */
+    float ms_thresh;          /* stage (a), all kernels */
+    float ms_bound;           /* stage (c), all kernels and the host rotation */
+    float ms_count;           /* stage (b) loop, including host round trips */
+    float ms_total;           /* whole call */
+    float ms_screen;          /* stage (a) screening kernel alone */
+    float ms_count_kernels;   /* stage (b) counting kernels alone, summed */
+    float ms_bound_kernel;    /* stage (c) bound-count kernel alone */
+} rmips_stats;
+
+/*
+ * Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  *out receives the context.
+ */
+rmips_status rmips_create(rmips_ctx **out, int device, void *hip_stream);
+
+/* Destroy a context (NULL is ignored).  Waits for nothing. */
+void rmips_destroy(rmips_ctx *ctx);
+
+/* Text of the last error on this context ("" if none).  Owned by ctx. */
+const char *rmips_last_error(const rmips_ctx *ctx);
+
+/* Change the stream a context enqueues on. */
+rmips_status rmips_set_stream(rmips_ctx *ctx, void *hip_stream);
+
+/*
+ * Testing knob: capacity of the per-user candidate list of stage (a).
+ * 0 restores the default.  A tiny capacity forces the exact per-user
+ * fallback path; results do not change.
+ */
+rmips_status rmips_set_candidate_cap(rmips_ctx *ctx, int32_t cap);
+
+/*
+ * Testing knob: first and largest batch size of the bound-ordered loop of
+ * rmips_topn (items per batch; 0 = defaults).  Results do not change.
+ */
+rmips_status rmips_set_batch(rmips_ctx *ctx, int32_t first, int32_t max);
+
+/* Workspace bytes for rmips_thresholds / rmips_scores / rmips_topn with
+ * these sizes (0 if the sizes are invalid). */
+size_t rmips_thresholds_workspace_size(int64_t n, int64_t m, int32_t d,
+                                       int32_t k, rmips_prec prec);
+size_t rmips_scores_workspace_size(int64_t n, int64_t nq, int32_t d,
+                                   rmips_prec prec);
+size_t rmips_topn_workspace_size(int64_t n, int64_t m, int32_t d, int32_t k,
+                                 int32_t N, rmips_prec prec);
+size_t rmips_soft_workspace_size(int64_t n, int64_t nq, int32_t d);
+
+/*
+ * Stage (a), Def. 1: for every user u, the k-th element of S_k(u).
+ *   U [n x d], P [m x d]      device, FP32 row-major.
+ *   1 <= k <= min(m, RMIPS_K_MAX), 1 <= d <= RMIPS_D_MAX, n >= 1.
+ *   tau    [n]  device FP64 out: the k-th largest u . p (exact value).
+ *   tau_id [n]  device int32 out: item id of that k-th element.
+ *   topk   [n x k] device int32 out, may be NULL: the ids of S_k(u) in
+ *               (value desc, id asc) order.
+ */
+rmips_status rmips_thresholds(rmips_ctx *ctx, const float *U, int64_t n,
+                              const float *P, int64_t m, int32_t d, int32_t k,
+                              rmips_prec prec, void *ws, size_t ws_bytes,
+                              double *tau, int32_t *tau_id, int32_t *topk);
+
+/*
+ * Stage (b), Def. 2 / Eq. 1: score of each query item against users whose
+ * k-th neighbours are (tau, tau_id) from rmips_thresholds.
+ *   U [n x d] device FP32; tau [n] device FP64; tau_id [n] device int32.
+ *   Q [nq x d] device FP32: the query item vectors.
+ *   q_ids [nq] device int32: item id of each query in P (its place in the
+ *     tie order), or -1 for an item outside P; such an item is placed after
+ *     every item of P, so it is counted iff u . q > tau_u.  NULL = all -1.
+ *   scores [nq] device int32 out: #{u : q in S_k(u)}.
+ */
+rmips_status rmips_scores(rmips_ctx *ctx, const float *U, int64_t n,
+                          const double *tau, const int32_t *tau_id,
+                          const float *Q, const int32_t *q_ids, int64_t nq,
+                          int32_t d, rmips_prec prec, void *ws,
+                          size_t ws_bytes, int32_t *scores);
+
+/*
+ * Def. 3 by the paper's method (Sec. 4, Alg. 2 driven by exact thresholds):
+ * stage (a), then the Cauchy-Schwarz (Eq. 2) and incremental-pruning
+ * (Eq. 3 / Eq. 6, d' = 10 after a rotation of both sides) upper bounds on
+ * every score, then exact scores of items visited in (bound desc, id asc)
+ * order until the next bound is below the current N-th score.
+ *   1 <= N <= min(m, RMIPS_N_MAX).
+ *   top_ids [N], top_scores [N]: HOST int32 out, (score desc, id asc).
+ *   stats: HOST, may be NULL.
+ * Synchronises the context's stream before returning.
+ */
+rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n,
+                        const float *P, int64_t m, int32_t d, int32_t k,
+                        int32_t N, rmips_prec prec, void *ws, size_t ws_bytes,
+                        int32_t *top_ids, int32_t *top_scores,
+                        rmips_stats *stats);
+
+/*
+ * Relaxed, differentiable score for new-item design (not in the paper; a
+ * smooth surrogate of the reverse k-MIPS count for query items q):
+ *   S[i] = sum_u sigmoid((u . q_i - tau[u]) / T)         (FP32 in and out)
+ *   U [n x d], tau [n] (FP32, e.g. the FP64 thresholds cast), Q [nq x d].
+ *   T > 0.  S [nq] device FP32 out.
+ */
+rmips_status rmips_soft_fwd(rmips_ctx *ctx, const float *U, int64_t n,
+                            const float *tau, const float *Q, int64_t nq,
+                            int32_t d, float T, void *ws, size_t ws_bytes,
+                            float *S);
+
+/*
+ * Gradient of the relaxed score:
+ *   dQ[i, :] = dS[i] * sum_u sigmoid'(z_ui) / T * u,  z_ui = (u . q_i - tau[u]) / T
+ *   dS [nq] device FP32 (upstream gradient), dQ [nq x d] device FP32 out.
+ */
+rmips_status rmips_soft_bwd(rmips_ctx *ctx, const float *U, int64_t n,
+                            const float *tau, const float *Q, int64_t nq,
+                            int32_t d, float T, const float *dS, void *ws,
+                            size_t ws_bytes, float *dQ);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RMIPS_H */

@@ -1,0 +1,223 @@
+"""ctypes binding of librmips: argument marshalling only.
+
+Every step of the computation runs in the library's HIP kernels; PyTorch
+provides device memory (inputs, outputs, workspace) and the current stream.
+The binding refuses to run without the compiled library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librmips.so")
+
+RMIPS_OK, RMIPS_EINVAL, RMIPS_EWORKSPACE, RMIPS_ENONFINITE, RMIPS_EUNSUPPORTED, \
+    RMIPS_EDEVICE = range(6)
+PREC = {"fp32": 0, "bf16": 1, "fp8": 2, "fp8_e4m3": 2}
+K_MAX, N_MAX, D_MAX = 32, 1024, 256
+
+EXPORTS = [
+    "rmips_create", "rmips_destroy", "rmips_last_error", "rmips_set_stream",
+    "rmips_set_candidate_cap", "rmips_set_batch",
+    "rmips_thresholds_workspace_size", "rmips_scores_workspace_size",
+    "rmips_topn_workspace_size", "rmips_soft_workspace_size",
+    "rmips_thresholds", "rmips_scores", "rmips_topn", "rmips_soft_fwd",
+    "rmips_soft_bwd",
+]
+
+
+class RmipsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"librmips status {status}: {msg}")
+        self.status = status
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("visited_items", ctypes.c_int64), ("batches", ctypes.c_int64),
+                ("cand_pairs", ctypes.c_int64), ("overflow_users", ctypes.c_int64),
+                ("recheck_pairs", ctypes.c_int64), ("screened_pairs", ctypes.c_int64),
+                ("bound_pairs", ctypes.c_int64), ("thresh_pairs", ctypes.c_int64),
+                ("count_pairs", ctypes.c_int64), ("count_launches", ctypes.c_int64),
+                ("ms_thresh", ctypes.c_float), ("ms_bound", ctypes.c_float),
+                ("ms_count", ctypes.c_float), ("ms_total", ctypes.c_float),
+                ("ms_screen", ctypes.c_float), ("ms_count_kernels", ctypes.c_float),
+                ("ms_bound_kernel", ctypes.c_float)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def load():
+    """Load librmips.so and declare its signatures (no GPU needed)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"librmips is not built ({LIB_PATH} missing); "
+                           "run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, f32, sz = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                             ctypes.c_float, ctypes.c_size_t)
+    st = ctypes.c_int
+    lib.rmips_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, vp]
+    lib.rmips_create.restype = st
+    lib.rmips_destroy.argtypes = [vp]
+    lib.rmips_destroy.restype = None
+    lib.rmips_last_error.argtypes = [vp]
+    lib.rmips_last_error.restype = ctypes.c_char_p
+    lib.rmips_set_stream.argtypes = [vp, vp]
+    lib.rmips_set_stream.restype = st
+    lib.rmips_set_candidate_cap.argtypes = [vp, i32]
+    lib.rmips_set_candidate_cap.restype = st
+    lib.rmips_set_batch.argtypes = [vp, i32, i32]
+    lib.rmips_set_batch.restype = st
+    lib.rmips_thresholds_workspace_size.argtypes = [i64, i64, i32, i32, ctypes.c_int]
+    lib.rmips_thresholds_workspace_size.restype = sz
+    lib.rmips_scores_workspace_size.argtypes = [i64, i64, i32, ctypes.c_int]
+    lib.rmips_scores_workspace_size.restype = sz
+    lib.rmips_topn_workspace_size.argtypes = [i64, i64, i32, i32, i32, ctypes.c_int]
+    lib.rmips_topn_workspace_size.restype = sz
+    lib.rmips_soft_workspace_size.argtypes = [i64, i64, i32]
+    lib.rmips_soft_workspace_size.restype = sz
+    lib.rmips_thresholds.argtypes = [vp, vp, i64, vp, i64, i32, i32, ctypes.c_int, vp, sz,
+                                     vp, vp, vp]
+    lib.rmips_thresholds.restype = st
+    lib.rmips_scores.argtypes = [vp, vp, i64, vp, vp, vp, vp, i64, i32, ctypes.c_int, vp, sz,
+                                 vp]
+    lib.rmips_scores.restype = st
+    lib.rmips_topn.argtypes = [vp, vp, i64, vp, i64, i32, i32, i32, ctypes.c_int, vp, sz,
+                               vp, vp, ctypes.POINTER(Stats)]
+    lib.rmips_topn.restype = st
+    lib.rmips_soft_fwd.argtypes = [vp, vp, i64, vp, vp, i64, i32, f32, vp, sz, vp]
+    lib.rmips_soft_fwd.restype = st
+    lib.rmips_soft_bwd.argtypes = [vp, vp, i64, vp, vp, i64, i32, f32, vp, vp, sz, vp]
+    lib.rmips_soft_bwd.restype = st
+    _lib = lib
+    return lib
+
+
+_ctx = {}
+
+
+def _context(device: torch.device):
+    """Per-device context, pointed at torch's current stream."""
+    lib = load()
+    idx = device.index if device.index is not None else torch.cuda.current_device()
+    with _lock:
+        c = _ctx.get(idx)
+        if c is None:
+            h = ctypes.c_void_p()
+            s = lib.rmips_create(ctypes.byref(h), idx, None)
+            if s != RMIPS_OK:
+                raise RmipsError(s, f"rmips_create failed on device {idx}")
+            c = h
+            _ctx[idx] = c
+    stream = torch.cuda.current_stream(idx).cuda_stream
+    lib.rmips_set_stream(c, ctypes.c_void_p(stream))
+    return c
+
+
+def _check(ctx, status):
+    if status != RMIPS_OK:
+        msg = load().rmips_last_error(ctx)
+        raise RmipsError(status, msg.decode() if msg else "")
+
+
+def _dev_f32(x, name):
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32
+            and x.is_contiguous() and x.dim() == 2):
+        raise ValueError(f"{name} must be a contiguous 2-D float32 CUDA tensor")
+    return x
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _workspace(nbytes, device):
+    if nbytes == 0:
+        raise RmipsError(RMIPS_EINVAL, "invalid sizes")
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+
+
+def thresholds(U, P, k, prec="fp32", with_topk=False, cand_cap=None):
+    """tau (float64), tau_id (int32) [, topk ids (int32, n x k)] on U's device."""
+    U, P = _dev_f32(U, "U"), _dev_f32(P, "P")
+    n, d = U.shape
+    m = P.shape[0]
+    if P.shape[1] != d:
+        raise ValueError("U and P must have the same number of columns")
+    lib = load()
+    ctx = _context(U.device)
+    lib.rmips_set_candidate_cap(ctx, int(cand_cap or 0))
+    p = PREC[prec]
+    ws = _workspace(lib.rmips_thresholds_workspace_size(n, m, d, k, p), U.device)
+    tau = torch.empty(n, dtype=torch.float64, device=U.device)
+    tid = torch.empty(n, dtype=torch.int32, device=U.device)
+    topk = torch.empty((n, k), dtype=torch.int32, device=U.device) if with_topk else None
+    _check(ctx, lib.rmips_thresholds(ctx, _ptr(U), n, _ptr(P), m, d, k, p, _ptr(ws),
+                                      ws.numel(), _ptr(tau), _ptr(tid), _ptr(topk)))
+    lib.rmips_set_candidate_cap(ctx, 0)
+    return (tau, tid, topk) if with_topk else (tau, tid)
+
+
+def scores(U, tau, tau_id, Q, q_ids=None, prec="fp32"):
+    """|T_k(q)| for each row of Q (int32 on U's device)."""
+    U, Q = _dev_f32(U, "U"), _dev_f32(Q, "Q")
+    n, d = U.shape
+    nq = Q.shape[0]
+    if tau.dtype != torch.float64 or tau_id.dtype != torch.int32:
+        raise ValueError("tau must be float64 and tau_id int32")
+    if q_ids is not None and (q_ids.dtype != torch.int32 or q_ids.numel() != nq):
+        raise ValueError("q_ids must be int32 with one entry per query")
+    lib = load()
+    ctx = _context(U.device)
+    p = PREC[prec]
+    ws = _workspace(lib.rmips_scores_workspace_size(n, nq, d, p), U.device)
+    out = torch.empty(nq, dtype=torch.int32, device=U.device)
+    _check(ctx, lib.rmips_scores(ctx, _ptr(U), n, _ptr(tau.contiguous()),
+                                 _ptr(tau_id.contiguous()), _ptr(Q),
+                                 _ptr(q_ids.contiguous()) if q_ids is not None else None,
+                                 nq, d, p, _ptr(ws), ws.numel(), _ptr(out)))
+    return out
+
+
+def topn_workspace(n, m, d, k, N, prec="fp32", device=None):
+    lib = load()
+    return _workspace(lib.rmips_topn_workspace_size(n, m, d, k, N, PREC[prec]),
+                      device or torch.device("cuda"))
+
+
+def topn(U, P, k, N, prec="fp32", ws=None, cand_cap=None, batch=None):
+    """Top-N item ids and scores (host int32 numpy arrays) and a stats dict."""
+    import numpy as np
+    U, P = _dev_f32(U, "U"), _dev_f32(P, "P")
+    n, d = U.shape
+    m = P.shape[0]
+    lib = load()
+    ctx = _context(U.device)
+    p = PREC[prec]
+    need = lib.rmips_topn_workspace_size(n, m, d, k, N, p)
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, U.device)
+    ids = np.empty(N, np.int32)
+    sc = np.empty(N, np.int32)
+    st = Stats()
+    lib.rmips_set_candidate_cap(ctx, int(cand_cap or 0))
+    b0, b1 = batch if batch else (0, 0)
+    lib.rmips_set_batch(ctx, int(b0), int(b1))
+    status = lib.rmips_topn(ctx, _ptr(U), n, _ptr(P), m, d, k, N, p, _ptr(ws), ws.numel(),
+                            ids.ctypes.data_as(ctypes.c_void_p),
+                            sc.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st))
+    lib.rmips_set_candidate_cap(ctx, 0)
+    lib.rmips_set_batch(ctx, 0, 0)
+    _check(ctx, status)
+    return ids, sc, st.as_dict()

@@ -1,0 +1,125 @@
+// Internal launch interfaces of librmips (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rmips {
+
+// ----------------------------------------------------------------- sort
+size_t radix_sort_scratch_bytes(int64_t n);
+hipError_t radix_sort_u32(uint32_t *keys, int32_t *vals, int64_t n, void *scratch,
+                          hipStream_t st);
+
+// ----------------------------------------------------------------- prep
+// Norm of every row (FP64, rounded up to FP32), zero-padded FP32 copy with
+// leading dimension D (may be NULL), and a flag set to 1 on NaN/Inf or a
+// norm above 2^60.  key/val (may be NULL): sort key ~bits(norm) (descending
+// norm) and the row id.
+void launch_rows_prep(const float *X, int64_t rows, int d, int D, float *Xpad,
+                      float *norm, uint32_t *key, int32_t *val, int *flag,
+                      hipStream_t st);
+// Pk[r] = P[perm[r]] for r < m, zero rows for m <= r < rows_pad; Np likewise.
+void launch_gather_rows(const float *P, const int32_t *perm, const float *norm_by_id,
+                        int64_t m, int64_t rows_pad, int d, int D, float *Pk,
+                        float *Np, hipStream_t st);
+// inv[perm[r]] = r
+void launch_invert_perm(const int32_t *perm, int64_t m, int32_t *inv, hipStream_t st);
+
+// Per-user data of the counting stage, in an order given by `order`
+// (sorted position -> user id; NULL = identity).
+struct UserSide {
+    float *a;        // c_err * ||u|| (FP32)
+    float *tau_hi;   // tau rounded up to FP32
+    float *tau_lo;   // tau rounded down to FP32
+    double *tau;     // exact tau
+    int32_t *tau_id; // item id of the k-th element
+    int32_t *uid;    // user id of this position
+};
+void launch_user_side(const double *tau, const int32_t *tau_id, const float *Nu,
+                      const int32_t *order, int64_t n, float c_err, UserSide out,
+                      hipStream_t st);
+// Sort keys of the pruning ratio rho_u = tau_u / ||u|| rounded down to FP32
+// (-inf when tau_u <= 0 or ||u|| = 0), as ascending uint32 keys; val = user id.
+void launch_rho_keys(const double *tau, const float *Nu, int64_t n, uint32_t *key,
+                     int32_t *val, hipStream_t st);
+// Xs[r] = Xpad[order[r]] (rows of D floats)
+void launch_gather_padded(const float *Xpad, const int32_t *order, int64_t rows, int D,
+                          float *Xs, hipStream_t st);
+// cs[j] = number of sorted ratios rho <= norm[j] * (1 + 2^-18)
+void launch_cs_prefix(const uint32_t *rho_sorted_keys, int64_t n, const float *norm,
+                      int64_t m, int32_t *cs, hipStream_t st);
+// G = sum over sampled rows x x^T (FP64, d x d), rows u = s*stride, s < ns
+void launch_gram(const float *X, int64_t ns, int64_t stride, int d, double *G,
+                 hipStream_t st);
+// Augmented rows for the Eq. (3) bound: out[r] = [W x (d' values), tail(x),
+// scale * ||x||, 0...] with leading dimension 16, where W (d' x d, FP64) has
+// orthonormal rows and tail(x) = sqrt(||x||^2 - ||W x||^2) rounded up.
+// Rows are taken from X through `order` (NULL = identity).
+void launch_rotate_aug(const float *X, const int32_t *order, int64_t rows,
+                       int64_t rows_pad, int d, const double *W, int dp, float scale,
+                       float *out, hipStream_t st);
+
+// ---------------------------------------------------------- stage (a)
+struct ThreshArgs {
+    const float *Uk; const float *Nu; int64_t n;
+    const float *Pk; const float *Np; const int32_t *perm; int64_t m; int ntiles;
+    const float *U; const float *P; int d;   // original FP32 rows (recheck)
+    int D; int k; int t0tiles; int nsplit; int cap;
+    float c_err; float e_abs; float c_exit;
+    float2 *cand; int32_t *cand_cnt; int32_t *flag;
+    double *tau; int32_t *tau_id; int32_t *topk;
+    unsigned long long *pairs;     // stats: screened pairs (may be NULL)
+    hipEvent_t ev0, ev1;           // recorded around the screening kernel (may be NULL)
+};
+void launch_thresh(const ThreshArgs &a, hipStream_t st);
+size_t thresh_screen_lds(int D);
+
+// ---------------------------------------------------------- stage (b)/(c)
+struct CountArgs {
+    // items (rows): padded rows gathered through `rows` (NULL = identity)
+    const float *Pk; const float *Np; const int32_t *rows; int64_t nb;
+    const int32_t *item_tie;   // tie id per padded row (NULL = -1: outside P)
+    const int32_t *item_orig;  // original row per padded row (NULL = identity)
+    const float *Porig;        // original FP32 item rows
+    // users (columns): padded rows, first ulen of them
+    const float *Us; int64_t ulen; UserSide us;
+    const float *Uorig; int d; int D;
+    int nsplit; int32_t *partial; int64_t *rechecks;
+};
+void launch_count(const CountArgs &a, hipStream_t st);
+size_t count_lds(int D);
+
+struct BoundArgs {
+    const float *Pa; int64_t m;  // augmented item rows (norm order), ld 16
+    const float *Ua;             // augmented user rows (rho order), ld 16
+    const float *tau_lo;         // per sorted user
+    const int32_t *cs;           // CS prefix per item (non-increasing)
+    int nsplit; int32_t *partial;
+    unsigned long long *pairs;   // stats: evaluated pairs (may be NULL)
+};
+void launch_bound(const BoundArgs &a, hipStream_t st);
+
+// partial[s][j] summed over s (fixed order) -> out[j]
+void launch_colsum(const int32_t *partial, int nsplit, int64_t cols, int32_t *out,
+                   hipStream_t st);
+// ~uscore keys in id order: key[c] = ~us[inv[c]], val[c] = inv[c]
+void launch_visit_keys(const int32_t *uscore, const int32_t *inv, int64_t m,
+                       uint32_t *key, int32_t *val, hipStream_t st);
+void launch_gather_i32(const int32_t *src, const int32_t *idx, int64_t n, int32_t *dst,
+                       hipStream_t st);
+
+// Running top-N: merge scores of a batch (sum of nsplit partial rows) into
+// the sorted list `top` (keys score<<32 | ~id), keep N.  status[0] = N-th
+// score (-1 while fewer than N), status[1] = entries kept.
+void launch_topn_merge(const int32_t *partial, int nsplit, int64_t nb,
+                       const int32_t *batch_ids, int N, uint64_t *top, int32_t *status,
+                       int32_t *batch_scores, hipStream_t st);
+
+// ---------------------------------------------------------- relaxed score
+void launch_soft(const float *U, int64_t n, const float *tau, const float *Q, int64_t nq,
+                 int d, float T, const float *dS, float *S, float *dQ, void *ws,
+                 hipStream_t st);
+size_t soft_ws_bytes(int64_t n, int64_t nq, int d);
+
+}  // namespace rmips

@@ -1,0 +1,250 @@
+// Preparation kernels: norms, padded copies, gathers into the orders the
+// method works in (items by descending norm, Alg. 1 step (1); users by
+// pruning ratio), the Gram matrix of the rotation (Alg. 1 step (2)) and the
+// rotated, augmented rows of the Eq. (3) bound.
+#include "common.h"
+#include "kernels.h"
+
+namespace rmips {
+
+// One wave per row: coalesced loads, FP64 sum of squares.
+__global__ __launch_bounds__(256) void k_rows_prep(const float *__restrict__ X, int64_t rows,
+                                                   int d, int D, float *__restrict__ Xpad,
+                                                   float *__restrict__ norm,
+                                                   uint32_t *__restrict__ key,
+                                                   int32_t *__restrict__ val,
+                                                   int *__restrict__ flag) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= rows) return;
+    const float *x = X + r * d;
+    double s = 0.0;
+    bool bad = false;
+    for (int i = lane; i < D; i += 64) {
+        float v = (i < d) ? x[i] : 0.0f;
+        if (!isfinite(v)) bad = true;
+        s += (double)v * (double)v;
+        if (Xpad) Xpad[r * D + i] = v;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (__ballot(bad) != 0ull && lane == 0) *flag = 1;
+    if (lane == 0) {
+        // the FP64 sum and sqrt are within 1e-13 relative of ||x||; the
+        // factor and the upward conversion make the FP32 value an upper bound
+        float nf = __double2float_ru(sqrt(s) * (1.0 + 0x1p-40));
+        if (!(nf <= 0x1p60f)) *flag = 1;
+        norm[r] = nf;
+        if (key) {
+            key[r] = ~__float_as_uint(nf);
+            val[r] = (int32_t)r;
+        }
+    }
+}
+
+void launch_rows_prep(const float *X, int64_t rows, int d, int D, float *Xpad, float *norm,
+                      uint32_t *key, int32_t *val, int *flag, hipStream_t st) {
+    if (rows <= 0) return;
+    k_rows_prep<<<(unsigned)((rows + 3) / 4), 256, 0, st>>>(X, rows, d, D, Xpad, norm, key,
+                                                            val, flag);
+}
+
+__global__ void k_gather_rows(const float *__restrict__ P, const int32_t *__restrict__ perm,
+                              const float *__restrict__ nb_id, int64_t m, int64_t rows_pad,
+                              int d, int D, float *__restrict__ Pk, float *__restrict__ Np) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= rows_pad) return;
+    if (r < m) {
+        const int64_t src = perm[r];
+        for (int i = lane; i < D; i += 64) Pk[r * D + i] = (i < d) ? P[src * d + i] : 0.0f;
+        if (lane == 0) Np[r] = nb_id[src];
+    } else {
+        for (int i = lane; i < D; i += 64) Pk[r * D + i] = 0.0f;
+        if (lane == 0) Np[r] = 0.0f;
+    }
+}
+
+void launch_gather_rows(const float *P, const int32_t *perm, const float *norm_by_id,
+                        int64_t m, int64_t rows_pad, int d, int D, float *Pk, float *Np,
+                        hipStream_t st) {
+    k_gather_rows<<<(unsigned)((rows_pad + 3) / 4), 256, 0, st>>>(P, perm, norm_by_id, m,
+                                                                  rows_pad, d, D, Pk, Np);
+}
+
+__global__ void k_invert_perm(const int32_t *__restrict__ perm, int64_t m,
+                              int32_t *__restrict__ inv) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < m) inv[perm[r]] = (int32_t)r;
+}
+
+void launch_invert_perm(const int32_t *perm, int64_t m, int32_t *inv, hipStream_t st) {
+    k_invert_perm<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(perm, m, inv);
+}
+
+__global__ void k_user_side(const double *__restrict__ tau, const int32_t *__restrict__ tau_id,
+                            const float *__restrict__ Nu, const int32_t *__restrict__ order,
+                            int64_t n, float c_err, UserSide out) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    int64_t u = order ? order[r] : r;
+    double t = tau[u];
+    out.a[r] = c_err * Nu[u];
+    out.tau_hi[r] = __double2float_ru(t);
+    out.tau_lo[r] = __double2float_rd(t);
+    out.tau[r] = t;
+    out.tau_id[r] = tau_id[u];
+    out.uid[r] = (int32_t)u;
+}
+
+void launch_user_side(const double *tau, const int32_t *tau_id, const float *Nu,
+                      const int32_t *order, int64_t n, float c_err, UserSide out,
+                      hipStream_t st) {
+    k_user_side<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(tau, tau_id, Nu, order, n,
+                                                             c_err, out);
+}
+
+__global__ void k_rho_keys(const double *__restrict__ tau, const float *__restrict__ Nu,
+                           int64_t n, uint32_t *__restrict__ key, int32_t *__restrict__ val) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    double t = tau[u];
+    float nu = Nu[u];
+    float rho = -INFINITY;
+    // a user with tau <= 0 (or a zero vector) can hold any item: ratio -inf
+    if (t > 0.0 && nu > 0.0f) rho = __double2float_rd(t / (double)nu);
+    key[u] = float_key(rho);
+    val[u] = (int32_t)u;
+}
+
+void launch_rho_keys(const double *tau, const float *Nu, int64_t n, uint32_t *key,
+                     int32_t *val, hipStream_t st) {
+    k_rho_keys<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(tau, Nu, n, key, val);
+}
+
+__global__ void k_gather_padded(const float *__restrict__ X, const int32_t *__restrict__ order,
+                                int64_t rows, int D4, float *__restrict__ Y) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= rows * D4) return;
+    int64_t r = e / D4, c = e - r * D4;
+    reinterpret_cast<float4 *>(Y)[e] =
+        reinterpret_cast<const float4 *>(X)[(int64_t)order[r] * D4 + c];
+}
+
+void launch_gather_padded(const float *Xpad, const int32_t *order, int64_t rows, int D,
+                          float *Xs, hipStream_t st) {
+    int64_t tot = rows * (D / 4);
+    k_gather_padded<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(Xpad, order, rows, D / 4,
+                                                                   Xs);
+}
+
+__global__ void k_cs_prefix(const uint32_t *__restrict__ keys, int64_t n,
+                            const float *__restrict__ norm, int64_t m,
+                            int32_t *__restrict__ cs) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    // v <= (1 + d 2^-53) ||u|| ||p|| for the exact value; 2^-18 covers that
+    // and the FP32 rounding of this product
+    uint32_t x = float_key(norm[j] * (1.0f + 0x1p-18f));
+    int64_t lo = 0, hi = n;  // first position with key > x
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (keys[mid] <= x) lo = mid + 1; else hi = mid;
+    }
+    cs[j] = (int32_t)lo;
+}
+
+void launch_cs_prefix(const uint32_t *rho_sorted_keys, int64_t n, const float *norm,
+                      int64_t m, int32_t *cs, hipStream_t st) {
+    k_cs_prefix<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(rho_sorted_keys, n, norm, m, cs);
+}
+
+// 32x32 tile of G per block, sampled rows staged through LDS.
+__global__ __launch_bounds__(256) void k_gram(const float *__restrict__ X, int64_t ns,
+                                              int64_t stride, int d, double *__restrict__ G) {
+    __shared__ float xa[64][33];
+    __shared__ float xb[64][33];
+    const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
+    const int t = threadIdx.x, ti = t & 31, tj = t >> 5;  // tj in [0, 8)
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t s0 = 0; s0 < ns; s0 += 64) {
+        for (int e = t; e < 64 * 32; e += 256) {
+            int rr = e >> 5, cc = e & 31;
+            int64_t s = s0 + rr;
+            float va = 0.f, vb = 0.f;
+            if (s < ns) {
+                const float *x = X + s * stride * d;
+                if (i0 + cc < d) va = x[i0 + cc];
+                if (j0 + cc < d) vb = x[j0 + cc];
+            }
+            xa[rr][cc] = va;
+            xb[rr][cc] = vb;
+        }
+        __syncthreads();
+        for (int rr = 0; rr < 64; ++rr) {
+            double a = xa[rr][ti];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] += a * (double)xb[rr][tj + 8 * q];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        int i = i0 + ti, j = j0 + tj + 8 * q;
+        if (i < d && j < d) G[(int64_t)i * d + j] = acc[q];
+    }
+}
+
+void launch_gram(const float *X, int64_t ns, int64_t stride, int d, double *G,
+                 hipStream_t st) {
+    dim3 g((d + 31) / 32, (d + 31) / 32);
+    k_gram<<<g, 256, 0, st>>>(X, ns, stride, d, G);
+}
+
+// One wave per row: W x in FP64 (lane j < d' owns output j), norms in FP64.
+__global__ __launch_bounds__(256) void k_rotate_aug(const float *__restrict__ X,
+                                                    const int32_t *__restrict__ order,
+                                                    int64_t rows, int64_t rows_pad, int d,
+                                                    const double *__restrict__ W, int dp,
+                                                    float scale, float *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= rows_pad) return;
+    float *o = out + r * 16;
+    if (r >= rows) {
+        if (lane < 16) o[lane] = 0.0f;
+        return;
+    }
+    const float *x = X + (int64_t)(order ? order[r] : r) * d;
+    double s = 0.0;
+    for (int i = lane; i < d; i += 64) s += (double)x[i] * (double)x[i];
+#pragma unroll
+    for (int o2 = 32; o2 > 0; o2 >>= 1) s += __shfl_xor(s, o2);
+    double y = 0.0;
+    if (lane < dp) {
+        const double *w = W + (int64_t)lane * d;
+        for (int i = 0; i < d; ++i) y += w[i] * (double)x[i];
+    }
+    double y2 = (lane < dp) ? y * y : 0.0;
+#pragma unroll
+    for (int o2 = 32; o2 > 0; o2 >>= 1) y2 += __shfl_xor(y2, o2);
+    if (lane < dp) o[lane] = (float)y;
+    if (lane == 0) {
+        // tail^2 = ||x||^2 - ||W x||^2, widened by 1e-12 ||x||^2 to cover the
+        // FP64 rounding and the departure of W from exact orthonormality
+        double t2 = s - y2;
+        if (t2 < 0.0) t2 = 0.0;
+        o[dp] = __double2float_ru(sqrt(t2 + 1e-12 * s));
+        o[dp + 1] = scale * __double2float_ru(sqrt(s) * (1.0 + 0x1p-40));
+    }
+    if (lane >= dp + 2 && lane < 16) o[lane] = 0.0f;
+}
+
+void launch_rotate_aug(const float *X, const int32_t *order, int64_t rows, int64_t rows_pad,
+                       int d, const double *W, int dp, float scale, float *out,
+                       hipStream_t st) {
+    k_rotate_aug<<<(unsigned)((rows_pad + 3) / 4), 256, 0, st>>>(X, order, rows, rows_pad, d,
+                                                                 W, dp, scale, out);
+}
+
+}  // namespace rmips

@@ -1,0 +1,685 @@
+// librmips host side: validation, workspace layout, stage ordering and the
+// bound-ordered visit loop of Alg. 2, behind the C ABI of include/rmips.h.
+#include "../../include/rmips.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+
+using namespace rmips;
+
+struct rmips_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    int32_t cap_override = 0;
+    int32_t batch_first = 0, batch_max = 0;
+    int32_t *h_status = nullptr;  // pinned, small
+    int64_t *h_scalar = nullptr;  // pinned, small
+};
+
+namespace {
+
+constexpr int DPRIME = 10;              // split dimension of Eq. (3) (Sec. 5.1)
+constexpr int T0_TILES = 4;             // tiles of phase 1 of stage (a)
+constexpr int CAP_DEFAULT = 64;         // candidates per user and split
+constexpr int BATCH_FIRST = 512;
+constexpr int BATCH_MAX = 4096;
+constexpr int GRAM_SAMPLE = 16384;
+
+rmips_status fail(rmips_ctx *c, rmips_status s, const std::string &msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+#define HIPTRY(expr)                                                              \
+    do {                                                                          \
+        hipError_t e_ = (expr);                                                   \
+        if (e_ != hipSuccess)                                                     \
+            return fail(ctx, RMIPS_EDEVICE, std::string(#expr) + ": " +           \
+                                                hipGetErrorString(e_));           \
+    } while (0)
+
+// Bump allocator over the caller's workspace; with base == nullptr it only
+// measures.
+struct Carve {
+    uint8_t *base;
+    size_t off = 0;
+    explicit Carve(void *b) : base((uint8_t *)b) {}
+    template <class T> T *take(size_t count) {
+        off = (off + 255) & ~(size_t)255;
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+// FP32 screening error constant: |vh - v| <= c * N_u * N_p + E_ABS, where
+// the matrix-core sum of D terms is bounded by gamma_D with a unit roundoff
+// of 2^-23 (twice round-to-nearest, as the accumulation order and rounding
+// inside the matrix core are not specified), v's own FP64 rounding by
+// d 2^-53, and 8 2^-24 covers the FP32 rounding of the comparisons.
+float fp32_c_err(int D, int d) {
+    double u = std::ldexp(1.0, -23);
+    double gD = D * u / (1.0 - D * u);
+    double g64 = d * std::ldexp(1.0, -53);
+    return (float)((gD + g64 + 8.0 * std::ldexp(1.0, -24)) * (1.0 + std::ldexp(1.0, -16)));
+}
+
+struct ThreshLayout {
+    int D, ntiles, nsplit, cap;
+    int64_t mpad;
+    float *Uk, *Nu, *Pk, *Np, *Npid;
+    uint32_t *keys;
+    int32_t *perm;
+    void *sort_scratch;
+    float2 *cand;
+    int32_t *cand_cnt, *flag;
+    int *bad;
+};
+
+void thresh_plan(int64_t n, int64_t m, int d, int cap_override, ThreshLayout &L, Carve &cv) {
+    L.D = padded_dim_fp32(d);
+    L.ntiles = (int)((m + TILE_ITEMS - 1) / TILE_ITEMS);
+    L.mpad = (int64_t)L.ntiles * TILE_ITEMS;
+    int64_t utiles = (n + 127) / 128;
+    int64_t ns = (3072 + utiles - 1) / utiles;
+    ns = std::max<int64_t>(1, std::min<int64_t>(ns, 8));
+    ns = std::min<int64_t>(ns, L.ntiles);
+    L.nsplit = (int)ns;
+    L.cap = cap_override > 0 ? cap_override : CAP_DEFAULT;
+    L.Uk = cv.take<float>((size_t)n * L.D);
+    L.Nu = cv.take<float>(n);
+    L.Pk = cv.take<float>((size_t)L.mpad * L.D);
+    L.Np = cv.take<float>(L.mpad);
+    L.Npid = cv.take<float>(m);
+    L.keys = cv.take<uint32_t>(m);
+    L.perm = cv.take<int32_t>(m);
+    L.sort_scratch = cv.take<uint8_t>(radix_sort_scratch_bytes(m));
+    L.cand = cv.take<float2>((size_t)n * L.nsplit * L.cap);
+    L.cand_cnt = cv.take<int32_t>((size_t)n * L.nsplit);
+    L.flag = cv.take<int32_t>(n);
+    L.bad = cv.take<int>(64);
+}
+
+rmips_status check_bad(rmips_ctx *ctx, int *bad) {
+    HIPTRY(hipMemcpyAsync(ctx->h_status, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIPTRY(hipStreamSynchronize(ctx->stream));
+    if (ctx->h_status[0] != 0)
+        return fail(ctx, RMIPS_ENONFINITE, "input holds a NaN/Inf or a vector norm above 2^60");
+    return RMIPS_OK;
+}
+
+// Stage (a) into (tau, tau_id, topk); also leaves the prepared item/user
+// arrays of L in the workspace for later stages.
+rmips_status run_thresholds(rmips_ctx *ctx, const float *U, int64_t n, const float *P,
+                            int64_t m, int d, int k, ThreshLayout &L, double *tau,
+                            int32_t *tau_id, int32_t *topk,
+                            unsigned long long *pairs = nullptr, hipEvent_t ev0 = nullptr,
+                            hipEvent_t ev1 = nullptr) {
+    hipStream_t st = ctx->stream;
+    HIPTRY(hipMemsetAsync(L.bad, 0, sizeof(int), st));
+    launch_rows_prep(P, m, d, L.D, nullptr, L.Npid, L.keys, L.perm, L.bad, st);
+    HIPTRY(radix_sort_u32(L.keys, L.perm, m, L.sort_scratch, st));
+    launch_gather_rows(P, L.perm, L.Npid, m, L.mpad, d, L.D, L.Pk, L.Np, st);
+    launch_rows_prep(U, n, d, L.D, L.Uk, L.Nu, nullptr, nullptr, L.bad, st);
+    HIPTRY(hipGetLastError());
+    rmips_status s = check_bad(ctx, L.bad);
+    if (s != RMIPS_OK) return s;
+
+    ThreshArgs a{};
+    a.Uk = L.Uk; a.Nu = L.Nu; a.n = n;
+    a.Pk = L.Pk; a.Np = L.Np; a.perm = L.perm; a.m = m; a.ntiles = L.ntiles;
+    a.U = U; a.P = P; a.d = d;
+    a.D = L.D; a.k = k; a.t0tiles = T0_TILES; a.nsplit = L.nsplit; a.cap = L.cap;
+    a.c_err = fp32_c_err(L.D, d);
+    a.e_abs = E_ABS;
+    a.c_exit = (float)(1.0 + d * std::ldexp(1.0, -53) + 2.0 * a.c_err + std::ldexp(1.0, -20));
+    a.cand = L.cand; a.cand_cnt = L.cand_cnt; a.flag = L.flag;
+    a.tau = tau; a.tau_id = tau_id; a.topk = topk;
+    a.pairs = pairs; a.ev0 = ev0; a.ev1 = ev1;
+    size_t lds = thresh_screen_lds(L.D);
+    if (lds > 160 * 1024)
+        return fail(ctx, RMIPS_EUNSUPPORTED, "d too large for the FP32 screening tile");
+    launch_thresh(a, st);
+    HIPTRY(hipGetLastError());
+    return RMIPS_OK;
+}
+
+rmips_status validate_common(rmips_ctx *ctx, int64_t n, int64_t m, int d, int k,
+                             rmips_prec prec) {
+    if (!ctx) return RMIPS_EINVAL;
+    if (n < 1 || n > (int64_t)INT32_MAX) return fail(ctx, RMIPS_EINVAL, "n out of range");
+    if (m < 1 || m > (int64_t)INT32_MAX / 2) return fail(ctx, RMIPS_EINVAL, "m out of range");
+    if (d < 1 || d > RMIPS_D_MAX) return fail(ctx, RMIPS_EINVAL, "d out of range");
+    if (k < 1 || k > RMIPS_K_MAX || k > m) return fail(ctx, RMIPS_EINVAL, "k out of range");
+    if (prec != RMIPS_FP32)
+        return fail(ctx, RMIPS_EUNSUPPORTED, "only RMIPS_FP32 screening is built");
+    return RMIPS_OK;
+}
+
+// Top eigenvectors of the symmetric G (d x d) by block power iteration with
+// Rayleigh-Ritz; returns W (dp x d) with orthonormal rows.  Any orthonormal
+// W keeps the Eq. (3) bound valid; the eigenvectors only make it tight.
+void top_eigvecs(const std::vector<double> &G, int d, int dp, std::vector<double> &W) {
+    const int b = std::min(d, dp + 4);
+    std::vector<double> Q((size_t)d * b), Z((size_t)d * b);
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < b; ++j)
+            Q[(size_t)i * b + j] = (i == j) ? 1.0 : std::sin(1.0 + 0.7 * i + 1.3 * j) * 1e-3;
+    auto orth = [&](std::vector<double> &X) {
+        for (int pass = 0; pass < 2; ++pass)
+            for (int j = 0; j < b; ++j) {
+                for (int q = 0; q < j; ++q) {
+                    double dot = 0;
+                    for (int i = 0; i < d; ++i) dot += X[(size_t)i * b + j] * X[(size_t)i * b + q];
+                    for (int i = 0; i < d; ++i) X[(size_t)i * b + j] -= dot * X[(size_t)i * b + q];
+                }
+                double nrm = 0;
+                for (int i = 0; i < d; ++i) nrm += X[(size_t)i * b + j] * X[(size_t)i * b + j];
+                nrm = std::sqrt(nrm);
+                if (nrm == 0) nrm = 1;
+                for (int i = 0; i < d; ++i) X[(size_t)i * b + j] /= nrm;
+            }
+    };
+    orth(Q);
+    for (int it = 0; it < 40; ++it) {
+        for (int i = 0; i < d; ++i)
+            for (int j = 0; j < b; ++j) {
+                double s = 0;
+                for (int l = 0; l < d; ++l) s += G[(size_t)i * d + l] * Q[(size_t)l * b + j];
+                Z[(size_t)i * b + j] = s;
+            }
+        orth(Z);
+        Q.swap(Z);
+    }
+    // Rayleigh-Ritz: H = Q^T G Q (b x b), Jacobi eigen-decomposition
+    std::vector<double> GQ((size_t)d * b), H((size_t)b * b), V((size_t)b * b, 0.0);
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < b; ++j) {
+            double s = 0;
+            for (int l = 0; l < d; ++l) s += G[(size_t)i * d + l] * Q[(size_t)l * b + j];
+            GQ[(size_t)i * b + j] = s;
+        }
+    for (int i = 0; i < b; ++i)
+        for (int j = 0; j < b; ++j) {
+            double s = 0;
+            for (int l = 0; l < d; ++l) s += Q[(size_t)l * b + i] * GQ[(size_t)l * b + j];
+            H[(size_t)i * b + j] = s;
+        }
+    for (int i = 0; i < b; ++i) V[(size_t)i * b + i] = 1.0;
+    for (int sweep = 0; sweep < 50; ++sweep) {
+        double off = 0;
+        for (int p = 0; p < b; ++p)
+            for (int q = p + 1; q < b; ++q) off += H[(size_t)p * b + q] * H[(size_t)p * b + q];
+        if (off < 1e-30) break;
+        for (int p = 0; p < b; ++p)
+            for (int q = p + 1; q < b; ++q) {
+                double apq = H[(size_t)p * b + q];
+                if (std::fabs(apq) < 1e-300) continue;
+                double theta = (H[(size_t)q * b + q] - H[(size_t)p * b + p]) / (2 * apq);
+                double t = (theta >= 0 ? 1.0 : -1.0) /
+                           (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                double c = 1.0 / std::sqrt(t * t + 1), s = t * c;
+                for (int r = 0; r < b; ++r) {
+                    double hrp = H[(size_t)r * b + p], hrq = H[(size_t)r * b + q];
+                    H[(size_t)r * b + p] = c * hrp - s * hrq;
+                    H[(size_t)r * b + q] = s * hrp + c * hrq;
+                }
+                for (int r = 0; r < b; ++r) {
+                    double hpr = H[(size_t)p * b + r], hqr = H[(size_t)q * b + r];
+                    H[(size_t)p * b + r] = c * hpr - s * hqr;
+                    H[(size_t)q * b + r] = s * hpr + c * hqr;
+                }
+                for (int r = 0; r < b; ++r) {
+                    double vrp = V[(size_t)r * b + p], vrq = V[(size_t)r * b + q];
+                    V[(size_t)r * b + p] = c * vrp - s * vrq;
+                    V[(size_t)r * b + q] = s * vrp + c * vrq;
+                }
+            }
+    }
+    std::vector<int> order(b);
+    for (int j = 0; j < b; ++j) order[j] = j;
+    std::sort(order.begin(), order.end(), [&](int x, int y) {
+        return H[(size_t)x * b + x] > H[(size_t)y * b + y];
+    });
+    // W rows = Q * V[:, order[r]]; re-orthonormalised in FP64
+    W.assign((size_t)dp * d, 0.0);
+    std::vector<double> X((size_t)d * b, 0.0);
+    for (int r = 0; r < b; ++r)
+        for (int i = 0; i < d; ++i) {
+            double s = 0;
+            for (int l = 0; l < b; ++l) s += Q[(size_t)i * b + l] * V[(size_t)l * b + order[r]];
+            X[(size_t)i * b + r] = s;
+        }
+    orth(X);
+    for (int r = 0; r < dp; ++r)
+        for (int i = 0; i < d; ++i) W[(size_t)r * d + i] = X[(size_t)i * b + r];
+}
+
+struct TopnLayout {
+    ThreshLayout T;
+    double *tau;
+    int32_t *tau_id;
+    uint32_t *ukeys;
+    int32_t *uperm;
+    void *usort;
+    int32_t *cs;
+    UserSide us;
+    float *Us;
+    double *G, *W;
+    float *Pa, *Ua;
+    int nsplitB;
+    int32_t *partialB, *uscore, *inv;
+    uint32_t *vkeys;
+    int32_t *visit, *vis_us, *vis_cs, *vis_cid;
+    int nsplitC_max;
+    int32_t *partialC, *batch_scores;
+    uint64_t *top;
+    int32_t *status;
+    int64_t *rechecks;
+};
+
+void topn_plan(int64_t n, int64_t m, int d, int cap_override, int bmax, TopnLayout &L,
+               Carve &cv) {
+    thresh_plan(n, m, d, cap_override, L.T, cv);
+    L.tau = cv.take<double>(n);
+    L.tau_id = cv.take<int32_t>(n);
+    L.ukeys = cv.take<uint32_t>(n);
+    L.uperm = cv.take<int32_t>(n);
+    L.usort = cv.take<uint8_t>(radix_sort_scratch_bytes(std::max(n, m)));
+    L.cs = cv.take<int32_t>(L.T.mpad);
+    L.us.a = cv.take<float>(n);
+    L.us.tau_hi = cv.take<float>(n);
+    L.us.tau_lo = cv.take<float>(n);
+    L.us.tau = cv.take<double>(n);
+    L.us.tau_id = cv.take<int32_t>(n);
+    L.us.uid = cv.take<int32_t>(n);
+    L.Us = cv.take<float>((size_t)n * L.T.D);
+    L.G = cv.take<double>((size_t)d * d);
+    L.W = cv.take<double>((size_t)DPRIME * d);
+    L.Pa = cv.take<float>((size_t)L.T.mpad * 16);
+    L.Ua = cv.take<float>((size_t)n * 16);
+    int64_t itiles = (m + 63) / 64;
+    int64_t nb = std::max<int64_t>(1, std::min<int64_t>(8, (2048 + itiles - 1) / itiles));
+    L.nsplitB = (int)nb;
+    L.partialB = cv.take<int32_t>((size_t)L.nsplitB * m);
+    L.uscore = cv.take<int32_t>(m);
+    L.inv = cv.take<int32_t>(m);
+    L.vkeys = cv.take<uint32_t>(m);
+    L.visit = cv.take<int32_t>(m);
+    L.vis_us = cv.take<int32_t>(m);
+    L.vis_cs = cv.take<int32_t>(m);
+    L.vis_cid = cv.take<int32_t>(m);
+    L.nsplitC_max = 256;
+    L.partialC = cv.take<int32_t>((size_t)L.nsplitC_max * bmax);
+    L.batch_scores = cv.take<int32_t>(bmax);
+    L.top = cv.take<uint64_t>(RMIPS_N_MAX);
+    L.status = cv.take<int32_t>(64);
+    L.rechecks = cv.take<int64_t>(8);
+}
+
+int count_splits(int64_t nb, int64_t ulen, int maxs) {
+    int64_t itiles = (nb + 63) / 64;
+    int64_t chunks = (ulen + 127) / 128;
+    int64_t s = (2048 + itiles - 1) / itiles;
+    s = std::min<int64_t>(s, std::max<int64_t>(1, chunks / 2));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(s, maxs));
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+rmips_status rmips_create(rmips_ctx **out, int device, void *hip_stream) {
+    if (!out) return RMIPS_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return RMIPS_EDEVICE;
+    if (hipSetDevice(device) != hipSuccess) return RMIPS_EDEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return RMIPS_EDEVICE;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return RMIPS_EUNSUPPORTED;
+    rmips_ctx *c = new rmips_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    if (hipHostMalloc((void **)&c->h_status, 256, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&c->h_scalar, 256, hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return RMIPS_EDEVICE;
+    }
+    *out = c;
+    return RMIPS_OK;
+}
+
+void rmips_destroy(rmips_ctx *ctx) {
+    if (!ctx) return;
+    if (ctx->h_status) (void)hipHostFree(ctx->h_status);
+    if (ctx->h_scalar) (void)hipHostFree(ctx->h_scalar);
+    delete ctx;
+}
+
+const char *rmips_last_error(const rmips_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+rmips_status rmips_set_stream(rmips_ctx *ctx, void *hip_stream) {
+    if (!ctx) return RMIPS_EINVAL;
+    ctx->stream = (hipStream_t)hip_stream;
+    return RMIPS_OK;
+}
+
+rmips_status rmips_set_candidate_cap(rmips_ctx *ctx, int32_t cap) {
+    if (!ctx || cap < 0 || cap > 4096) return RMIPS_EINVAL;
+    ctx->cap_override = cap;
+    return RMIPS_OK;
+}
+
+rmips_status rmips_set_batch(rmips_ctx *ctx, int32_t first, int32_t max) {
+    if (!ctx || first < 0 || max < 0 || first > BATCH_MAX || max > BATCH_MAX ||
+        (first && max && first > max))
+        return RMIPS_EINVAL;
+    ctx->batch_first = first;
+    ctx->batch_max = max;
+    return RMIPS_OK;
+}
+
+size_t rmips_thresholds_workspace_size(int64_t n, int64_t m, int32_t d, int32_t k,
+                                       rmips_prec prec) {
+    if (n < 1 || m < 1 || d < 1 || d > RMIPS_D_MAX || k < 1 || k > RMIPS_K_MAX || k > m ||
+        prec != RMIPS_FP32)
+        return 0;
+    Carve cv(nullptr);
+    ThreshLayout L;
+    thresh_plan(n, m, d, 0, L, cv);
+    return cv.off + 256;
+}
+
+size_t rmips_scores_workspace_size(int64_t n, int64_t nq, int32_t d, rmips_prec prec) {
+    if (n < 1 || nq < 1 || d < 1 || d > RMIPS_D_MAX || prec != RMIPS_FP32) return 0;
+    Carve cv(nullptr);
+    int D = padded_dim_fp32(d);
+    cv.take<float>((size_t)n * D);
+    cv.take<float>(n);
+    cv.take<float>((size_t)nq * D);
+    cv.take<float>(nq);
+    cv.take<float>(n); cv.take<float>(n); cv.take<float>(n);
+    cv.take<double>(n); cv.take<int32_t>(n); cv.take<int32_t>(n);
+    cv.take<int32_t>((size_t)256 * nq);
+    cv.take<int>(64);
+    cv.take<int64_t>(8);
+    return cv.off + 256;
+}
+
+size_t rmips_topn_workspace_size(int64_t n, int64_t m, int32_t d, int32_t k, int32_t N,
+                                 rmips_prec prec) {
+    if (rmips_thresholds_workspace_size(n, m, d, k, prec) == 0 || N < 1 ||
+        N > RMIPS_N_MAX || N > m)
+        return 0;
+    Carve cv(nullptr);
+    TopnLayout L;
+    topn_plan(n, m, d, 0, BATCH_MAX, L, cv);
+    return cv.off + 256;
+}
+
+rmips_status rmips_thresholds(rmips_ctx *ctx, const float *U, int64_t n, const float *P,
+                              int64_t m, int32_t d, int32_t k, rmips_prec prec, void *ws,
+                              size_t ws_bytes, double *tau, int32_t *tau_id, int32_t *topk) {
+    rmips_status s = validate_common(ctx, n, m, d, k, prec);
+    if (s != RMIPS_OK) return s;
+    if (!U || !P || !ws || !tau || !tau_id) return fail(ctx, RMIPS_EINVAL, "null pointer");
+    Carve probe(nullptr);
+    ThreshLayout L;
+    thresh_plan(n, m, d, ctx->cap_override, L, probe);
+    if (ws_bytes < probe.off + 256) return fail(ctx, RMIPS_EWORKSPACE, "workspace too small");
+    HIPTRY(hipSetDevice(ctx->device));
+    Carve cv(ws);
+    thresh_plan(n, m, d, ctx->cap_override, L, cv);
+    return run_thresholds(ctx, U, n, P, m, d, k, L, tau, tau_id, topk);
+}
+
+rmips_status rmips_scores(rmips_ctx *ctx, const float *U, int64_t n, const double *tau,
+                          const int32_t *tau_id, const float *Q, const int32_t *q_ids,
+                          int64_t nq, int32_t d, rmips_prec prec, void *ws, size_t ws_bytes,
+                          int32_t *scores) {
+    if (!ctx) return RMIPS_EINVAL;
+    if (n < 1 || n > (int64_t)INT32_MAX || nq < 1 || nq > (int64_t)INT32_MAX / 2 || d < 1 ||
+        d > RMIPS_D_MAX)
+        return fail(ctx, RMIPS_EINVAL, "size out of range");
+    if (prec != RMIPS_FP32) return fail(ctx, RMIPS_EUNSUPPORTED, "only RMIPS_FP32 is built");
+    if (!U || !tau || !tau_id || !Q || !ws || !scores)
+        return fail(ctx, RMIPS_EINVAL, "null pointer");
+    if (ws_bytes < rmips_scores_workspace_size(n, nq, d, prec))
+        return fail(ctx, RMIPS_EWORKSPACE, "workspace too small");
+    HIPTRY(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    const int D = padded_dim_fp32(d);
+    Carve cv(ws);
+    float *Uk = cv.take<float>((size_t)n * D);
+    float *Nu = cv.take<float>(n);
+    float *Qk = cv.take<float>((size_t)nq * D);
+    float *Nq = cv.take<float>(nq);
+    UserSide us;
+    us.a = cv.take<float>(n); us.tau_hi = cv.take<float>(n); us.tau_lo = cv.take<float>(n);
+    us.tau = cv.take<double>(n); us.tau_id = cv.take<int32_t>(n); us.uid = cv.take<int32_t>(n);
+    int32_t *partial = cv.take<int32_t>((size_t)256 * nq);
+    int *bad = cv.take<int>(64);
+    int64_t *rech = cv.take<int64_t>(8);
+    HIPTRY(hipMemsetAsync(bad, 0, sizeof(int), st));
+    launch_rows_prep(U, n, d, D, Uk, Nu, nullptr, nullptr, bad, st);
+    launch_rows_prep(Q, nq, d, D, Qk, Nq, nullptr, nullptr, bad, st);
+    HIPTRY(hipGetLastError());
+    {
+        rmips_status s = check_bad(ctx, bad);
+        if (s != RMIPS_OK) return s;
+    }
+    const float c_err = fp32_c_err(D, d);
+    launch_user_side(tau, tau_id, Nu, nullptr, n, c_err, us, st);
+    CountArgs a{};
+    a.Pk = Qk; a.Np = Nq; a.rows = nullptr; a.nb = nq;
+    a.item_tie = q_ids; a.item_orig = nullptr; a.Porig = Q;
+    a.Us = Uk; a.ulen = n; a.us = us; a.Uorig = U; a.d = d; a.D = D;
+    a.nsplit = count_splits(nq, n, 256);
+    a.partial = partial;
+    a.rechecks = rech;
+    HIPTRY(hipMemsetAsync(rech, 0, sizeof(int64_t), st));
+    launch_count(a, st);
+    launch_colsum(partial, a.nsplit, nq, scores, st);
+    HIPTRY(hipGetLastError());
+    return RMIPS_OK;
+}
+
+rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *P, int64_t m,
+                        int32_t d, int32_t k, int32_t N, rmips_prec prec, void *ws,
+                        size_t ws_bytes, int32_t *top_ids, int32_t *top_scores,
+                        rmips_stats *stats) {
+    rmips_status s = validate_common(ctx, n, m, d, k, prec);
+    if (s != RMIPS_OK) return s;
+    if (N < 1 || N > RMIPS_N_MAX || N > m) return fail(ctx, RMIPS_EINVAL, "N out of range");
+    if (!U || !P || !ws || !top_ids || !top_scores)
+        return fail(ctx, RMIPS_EINVAL, "null pointer");
+    const int bfirst = ctx->batch_first > 0 ? ctx->batch_first : BATCH_FIRST;
+    const int bmax = ctx->batch_max > 0 ? ctx->batch_max : BATCH_MAX;
+    {
+        Carve probe(nullptr);
+        TopnLayout L0;
+        topn_plan(n, m, d, ctx->cap_override, BATCH_MAX, L0, probe);
+        if (ws_bytes < probe.off + 256)
+            return fail(ctx, RMIPS_EWORKSPACE, "workspace too small");
+    }
+    HIPTRY(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    Carve cv(ws);
+    TopnLayout L;
+    topn_plan(n, m, d, ctx->cap_override, BATCH_MAX, L, cv);
+    const int D = L.T.D;
+    const float c_err = fp32_c_err(D, d);
+
+    constexpr int NEV = 10;
+    hipEvent_t ev[NEV] = {};
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard() { for (int i = 0; i < NEV; ++i) if (e[i]) (void)hipEventDestroy(e[i]); }
+    } guard{ev};
+    for (auto &e : ev) HIPTRY(hipEventCreate(&e));
+    unsigned long long *ctr = reinterpret_cast<unsigned long long *>(L.rechecks);
+    HIPTRY(hipMemsetAsync(ctr, 0, 8 * sizeof(unsigned long long), st));
+    HIPTRY(hipEventRecord(ev[0], st));
+
+    // ---- stage (a): exact thresholds
+    s = run_thresholds(ctx, U, n, P, m, d, k, L.T, L.tau, L.tau_id, nullptr, ctr + 1, ev[4],
+                       ev[5]);
+    if (s != RMIPS_OK) return s;
+    HIPTRY(hipEventRecord(ev[1], st));
+
+    // ---- stage (c): Cauchy-Schwarz prefix and Eq. (3)/(6) bound counts
+    launch_rho_keys(L.tau, L.T.Nu, n, L.ukeys, L.uperm, st);
+    HIPTRY(radix_sort_u32(L.ukeys, L.uperm, n, L.usort, st));
+    launch_cs_prefix(L.ukeys, n, L.T.Np, m, L.cs, st);
+    launch_user_side(L.tau, L.tau_id, L.T.Nu, L.uperm, n, c_err, L.us, st);
+    launch_gather_padded(L.T.Uk, L.uperm, n, D, L.Us, st);
+    const int dp = std::min(DPRIME, d);
+    const int64_t ns = std::min<int64_t>(n, GRAM_SAMPLE);
+    launch_gram(U, ns, n / ns, d, L.G, st);
+    std::vector<double> G((size_t)d * d), W;
+    HIPTRY(hipMemcpyAsync(G.data(), L.G, sizeof(double) * d * d, hipMemcpyDeviceToHost, st));
+    HIPTRY(hipStreamSynchronize(st));
+    top_eigvecs(G, d, dp, W);
+    HIPTRY(hipMemcpyAsync(L.W, W.data(), sizeof(double) * dp * d, hipMemcpyHostToDevice, st));
+    // slack of the bound: covers FP32 rounding of W x, of the tail and of
+    // the 12-term matrix-core sum (each well below 2^-23 relative)
+    const float slack = 64.0f * 0x1p-23f;
+    launch_rotate_aug(P, L.T.perm, m, L.T.mpad, d, L.W, dp, 1.0f, L.Pa, st);
+    launch_rotate_aug(U, L.uperm, n, n, d, L.W, dp, slack, L.Ua, st);
+    BoundArgs ba{};
+    ba.Pa = L.Pa; ba.m = m; ba.Ua = L.Ua; ba.tau_lo = L.us.tau_lo; ba.cs = L.cs;
+    ba.nsplit = L.nsplitB; ba.partial = L.partialB; ba.pairs = ctr + 2;
+    HIPTRY(hipEventRecord(ev[6], st));
+    launch_bound(ba, st);
+    HIPTRY(hipEventRecord(ev[7], st));
+    launch_colsum(L.partialB, L.nsplitB, m, L.uscore, st);
+    // visit order: (uscore desc, id asc)
+    launch_invert_perm(L.T.perm, m, L.inv, st);
+    launch_visit_keys(L.uscore, L.inv, m, L.vkeys, L.visit, st);
+    HIPTRY(radix_sort_u32(L.vkeys, L.visit, m, L.usort, st));
+    launch_gather_i32(L.uscore, L.visit, m, L.vis_us, st);
+    launch_gather_i32(L.cs, L.visit, m, L.vis_cs, st);
+    launch_gather_i32(L.T.perm, L.visit, m, L.vis_cid, st);
+    std::vector<int32_t> h_us(m), h_cs(m);
+    HIPTRY(hipMemcpyAsync(h_us.data(), L.vis_us, sizeof(int32_t) * m, hipMemcpyDeviceToHost, st));
+    HIPTRY(hipMemcpyAsync(h_cs.data(), L.vis_cs, sizeof(int32_t) * m, hipMemcpyDeviceToHost, st));
+    HIPTRY(hipEventRecord(ev[2], st));
+    HIPTRY(hipStreamSynchronize(st));
+
+    // ---- stage (b): exact scores in bound order, running top-N, stop rule
+    ctx->h_status[8] = -1;  // N-th score unknown
+    ctx->h_status[9] = 0;   // entries kept
+    HIPTRY(hipMemcpyAsync(L.status, ctx->h_status + 8, 2 * sizeof(int32_t),
+                          hipMemcpyHostToDevice, st));
+    int64_t r0 = 0, visited = 0, batches = 0, screened = 0, launches = 0;
+    float ms_count_k = 0.0f;
+    int64_t bsz = std::min(bfirst, bmax);
+    while (r0 < m) {
+        const int64_t r1 = std::min<int64_t>(m, r0 + bsz);
+        const int64_t nb = r1 - r0;
+        int64_t ulen = 0;
+        for (int64_t r = r0; r < r1; ++r) ulen = std::max<int64_t>(ulen, h_cs[r]);
+        CountArgs a{};
+        a.Pk = L.T.Pk; a.Np = L.T.Np; a.rows = L.visit + r0; a.nb = nb;
+        a.item_tie = L.T.perm; a.item_orig = L.T.perm; a.Porig = P;
+        a.Us = L.Us; a.ulen = ulen; a.us = L.us; a.Uorig = U; a.d = d; a.D = D;
+        a.nsplit = count_splits(nb, ulen, L.nsplitC_max);
+        a.partial = L.partialC;
+        a.rechecks = L.rechecks;
+        if (ulen > 0) {
+            HIPTRY(hipEventRecord(ev[8], st));
+            launch_count(a, st);
+            HIPTRY(hipEventRecord(ev[9], st));
+            ++launches;
+        } else {
+            HIPTRY(hipMemsetAsync(L.partialC, 0, sizeof(int32_t) * nb, st));
+            a.nsplit = 1;
+        }
+        launch_topn_merge(L.partialC, a.nsplit, nb, L.vis_cid + r0, N, L.top, L.status,
+                          L.batch_scores, st);
+        HIPTRY(hipGetLastError());
+        HIPTRY(hipMemcpyAsync(ctx->h_status, L.status, 2 * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, st));
+        HIPTRY(hipStreamSynchronize(st));
+        if (ulen > 0) {
+            float t = 0.0f;
+            (void)hipEventElapsedTime(&t, ev[8], ev[9]);
+            ms_count_k += t;
+        }
+        visited += nb;
+        ++batches;
+        screened += nb * ulen;
+        const int tauN = ctx->h_status[0];
+        r0 = r1;
+        // stop once the next bound is strictly below the current N-th score
+        if (r0 < m && tauN >= 0 && h_us[r0] < tauN) break;
+        bsz = std::min<int64_t>(2 * bsz, bmax);
+    }
+    HIPTRY(hipEventRecord(ev[3], st));
+    std::vector<uint64_t> top(N);
+    HIPTRY(hipMemcpyAsync(top.data(), L.top, sizeof(uint64_t) * N, hipMemcpyDeviceToHost, st));
+    HIPTRY(hipMemcpyAsync(ctx->h_scalar, L.rechecks, 4 * sizeof(int64_t),
+                          hipMemcpyDeviceToHost, st));
+    HIPTRY(hipStreamSynchronize(st));
+    if (ctx->h_status[1] != N) return fail(ctx, RMIPS_EDEVICE, "top-N list incomplete");
+    for (int i = 0; i < N; ++i) {
+        top_scores[i] = (int32_t)(top[i] >> 32);
+        top_ids[i] = (int32_t)(~(uint32_t)(top[i] & 0xffffffffu));
+    }
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->visited_items = visited;
+        stats->batches = batches;
+        stats->cand_pairs = -1;
+        stats->overflow_users = -1;
+        stats->recheck_pairs = ctx->h_scalar[0];
+        stats->thresh_pairs = ctx->h_scalar[1];
+        stats->bound_pairs = ctx->h_scalar[2];
+        stats->count_pairs = screened;
+        stats->screened_pairs = screened + ctx->h_scalar[1];
+        stats->count_launches = launches;
+        float t01 = 0, t12 = 0, t23 = 0, t03 = 0, tsc = 0, tbd = 0;
+        (void)hipEventElapsedTime(&t01, ev[0], ev[1]);
+        (void)hipEventElapsedTime(&t12, ev[1], ev[2]);
+        (void)hipEventElapsedTime(&t23, ev[2], ev[3]);
+        (void)hipEventElapsedTime(&t03, ev[0], ev[3]);
+        (void)hipEventElapsedTime(&tsc, ev[4], ev[5]);
+        (void)hipEventElapsedTime(&tbd, ev[6], ev[7]);
+        stats->ms_thresh = t01;
+        stats->ms_bound = t12;
+        stats->ms_count = t23;
+        stats->ms_total = t03;
+        stats->ms_screen = tsc;
+        stats->ms_count_kernels = ms_count_k;
+        stats->ms_bound_kernel = tbd;
+    }
+    return RMIPS_OK;
+}
+
+rmips_status rmips_soft_fwd(rmips_ctx *ctx, const float *, int64_t, const float *,
+                            const float *, int64_t, int32_t, float, void *, size_t, float *) {
+    return fail(ctx, RMIPS_EUNSUPPORTED, "relaxed score not built yet");
+}
+
+rmips_status rmips_soft_bwd(rmips_ctx *ctx, const float *, int64_t, const float *,
+                            const float *, int64_t, int32_t, float, const float *, void *,
+                            size_t, float *) {
+    return fail(ctx, RMIPS_EUNSUPPORTED, "relaxed score not built yet");
+}
+
+size_t rmips_soft_workspace_size(int64_t, int64_t, int32_t) { return 0; }
+
+}  // extern "C"

@@ -1,0 +1,399 @@
+// Stage (a): tau_u, the k-th largest u . p over all items (Def. 1), exact.
+//
+// Screening.  A workgroup holds 128 users in LDS and streams the items in
+// descending-norm order (Alg. 1 step (1)), 64 per tile, through the FP32
+// matrix cores.  Every screened value vh satisfies |vh - v| <= E(u, p) =
+// c_err * N_u * N_p + e_abs against the exact value v, where N are FP32
+// norms rounded up and c_err bounds the product's accumulation error, the
+// FP64 definition's own rounding, and the rounding of the FP32 comparisons.
+//
+// Phase 1 (first t0 tiles): per lane and register slot the running maximum
+// of the lower bounds vh - E; the k-th largest of the 64 slot maxima of a
+// user (each slot covers a distinct set of items) is a value L0 that at
+// least k items reach, so L0 <= tau_u.
+// Phase 2 (all tiles, interleaved over `nsplit` workgroups): an item is a
+// candidate when vh + E >= L0; S_k(u) lies among the candidates because
+// v >= tau_u >= L0.  A tile whose largest norm satisfies
+// N_u * N_p * (1 + 2 c) < L0 for every user of the workgroup ends the scan:
+// by Cauchy-Schwarz (Eq. 2) no later item can be a candidate (the early stop
+// of the paper's norm-ordered scan, Sec. 4.2).
+// Final: per user, L* = k-th largest lower bound among the candidates (the
+// candidates hold every item whose lower bound reaches L0, so this is the
+// k-th largest over all items), the candidates with vh + E >= L* are
+// recomputed in FP64, and the k-th in (value desc, id asc) order is tau_u.
+// A user whose candidates overflow the list is recomputed by brute force.
+#include "common.h"
+#include "kernels.h"
+
+namespace rmips {
+
+// Users per screening workgroup: 32 per wave, NW waves (4, or 2 when the
+// rows are long enough that four waves' users would not fit in LDS).
+
+// Bitonic sort of 32 registers, descending.
+__device__ __forceinline__ void cas_desc(float &a, float &b) {
+    float hi = fmaxf(a, b), lo = fminf(a, b);
+    a = hi;
+    b = lo;
+}
+
+__device__ __forceinline__ void sort32_desc(float (&v)[32]) {
+#pragma unroll
+    for (int k = 2; k <= 32; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+            for (int i = 0; i < 32; ++i) {
+                int l = i ^ j;
+                if (l > i) {
+                    if ((i & k) == 0) cas_desc(v[i], v[l]);
+                    else cas_desc(v[l], v[i]);
+                }
+            }
+        }
+    }
+}
+
+// Sort a bitonic sequence of 32 registers, descending.
+__device__ __forceinline__ void merge32_desc(float (&v)[32]) {
+#pragma unroll
+    for (int j = 16; j > 0; j >>= 1) {
+#pragma unroll
+        for (int i = 0; i < 32; ++i) {
+            int l = i ^ j;
+            if (l > i) cas_desc(v[i], v[l]);
+        }
+    }
+}
+
+size_t thresh_screen_lds_nw(int D, int nw) {
+    const int ld = D + LDS_PAD;
+    return (size_t)(32 * nw + TILE_ITEMS) * ld * sizeof(float) + TILE_ITEMS * sizeof(float) +
+           32 * nw * sizeof(int) + 16 * sizeof(float);
+}
+
+int thresh_waves(int D) { return thresh_screen_lds_nw(D, 4) <= 96 * 1024 ? 4 : 2; }
+
+size_t thresh_screen_lds(int D) { return thresh_screen_lds_nw(D, thresh_waves(D)); }
+
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void k_thresh_screen(ThreshArgs a) {
+    constexpr int TU = 32 * NW, NT = 64 * NW;
+    extern __shared__ float smem[];
+    const int D = a.D, ld = D + LDS_PAD, ks = D / 2;
+    float *Ush = smem;
+    float *Psh = Ush + TU * ld;
+    float *Npsh = Psh + TILE_ITEMS * ld;
+    int *cntsh = reinterpret_cast<int *>(Npsh + TILE_ITEMS);
+    float *red = reinterpret_cast<float *>(cntsh + TU);
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t ubase = (int64_t)blockIdx.x * TU;
+    const int split = blockIdx.y;
+    const int D4 = D / 4;
+
+    for (int e = tid; e < TU * D4; e += NT) {
+        int r = e / D4, c = e - r * D4;
+        int64_t u = ubase + r;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (u < a.n) v = reinterpret_cast<const float4 *>(a.Uk)[u * D4 + c];
+        *reinterpret_cast<float4 *>(Ush + r * ld + 4 * c) = v;
+    }
+    if (tid < TU) cntsh[tid] = 0;
+
+    const int ucol = w * 32 + (lane & 31);
+    const int64_t ug = ubase + ucol;
+    const bool uvalid = ug < a.n;
+    const float nu = uvalid ? a.Nu[ug] : 0.0f;
+    const float cnu = a.c_err * nu;
+    const float *Bw = Ush + w * 32 * ld;
+
+    auto load_tile = [&](int t) {
+        const int64_t r0 = (int64_t)t * TILE_ITEMS;
+        const float4 *src = reinterpret_cast<const float4 *>(a.Pk + r0 * D);
+        for (int e = tid; e < TILE_ITEMS * D4; e += NT) {
+            int r = e / D4, c = e - r * D4;
+            *reinterpret_cast<float4 *>(Psh + r * ld + 4 * c) = src[e];
+        }
+        if (tid < TILE_ITEMS) Npsh[tid] = a.Np[r0 + tid];
+    };
+
+    // ---------------- phase 1: L0 from slot maxima of the first tiles
+    float M[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) M[i] = -INFINITY;
+    const int t0 = a.t0tiles < a.ntiles ? a.t0tiles : a.ntiles;
+    for (int t = 0; t < t0; ++t) {
+        __syncthreads();
+        load_tile(t);
+        __syncthreads();
+        f32x16 acc0 = {0}, acc1 = {0};
+        mfma32x2_f32(acc0, acc1, Psh, Psh + 32 * ld, Bw, ld, ks, lane);
+        const float e = fmaf(cnu, Npsh[0], a.e_abs);  // largest norm of the tile
+        const int64_t rb = (int64_t)t * TILE_ITEMS;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int r = mfma32_row(i, lane);
+            if (rb + r < a.m) M[i] = fmaxf(M[i], acc0[i] - e);
+            if (rb + r + 32 < a.m) M[16 + i] = fmaxf(M[16 + i], acc1[i] - e);
+        }
+    }
+    sort32_desc(M);
+    {
+        float Bv[32];
+#pragma unroll
+        for (int j = 0; j < 32; ++j) Bv[j] = __shfl_xor(M[31 - j], 32);
+#pragma unroll
+        for (int j = 0; j < 32; ++j) M[j] = fmaxf(M[j], Bv[j]);
+        merge32_desc(M);
+    }
+    float L0 = M[0];
+#pragma unroll
+    for (int j = 1; j < 32; ++j)
+        if (j == a.k - 1) L0 = M[j];
+
+    // workgroup exit ratio: stop once the tile's largest norm is below it
+    float rr = INFINITY;
+    if (uvalid) rr = (L0 > 2.0f * a.e_abs && nu > 0.0f)
+                         ? (L0 - 2.0f * a.e_abs) / (nu * a.c_exit) * (1.0f - 0x1p-20f)
+                         : 0.0f;
+    rr = wave_min(rr);
+    if (lane == 0) red[w] = rr;
+    __syncthreads();
+    float rwg = red[0];
+#pragma unroll
+    for (int q = 1; q < NW; ++q) rwg = fminf(rwg, red[q]);
+
+    // ---------------- phase 2: candidates
+    float2 *mycand = a.cand + ((int64_t)ug * a.nsplit + split) * a.cap;
+    for (int t = split; t < a.ntiles; t += a.nsplit) {
+        const float pmax = a.Np[(int64_t)t * TILE_ITEMS];
+        if (pmax < rwg) break;
+        __syncthreads();
+        load_tile(t);
+        __syncthreads();
+        f32x16 acc0 = {0}, acc1 = {0};
+        mfma32x2_f32(acc0, acc1, Psh, Psh + 32 * ld, Bw, ld, ks, lane);
+        const float thr = L0 - fmaf(cnu, pmax, a.e_abs);
+        bool any = false;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) any |= (acc0[i] >= thr) | (acc1[i] >= thr);
+        if (__ballot(any && uvalid) != 0ull) {
+            const int64_t rb = (int64_t)t * TILE_ITEMS;
+#pragma unroll
+            for (int i = 0; i < 32; ++i) {
+                const float v = (i < 16) ? acc0[i] : acc1[i - 16];
+                const int r = mfma32_row(i & 15, lane) + ((i < 16) ? 0 : 32);
+                bool p = uvalid && v >= thr && rb + r < a.m;
+                if (__ballot(p) != 0ull && p) {
+                    const float h = v + fmaf(cnu, Npsh[r], a.e_abs);
+                    if (h >= L0) {
+                        int s = atomicAdd(&cntsh[ucol], 1);
+                        if (s < a.cap) mycand[s] = make_float2(v, __int_as_float((int)(rb + r)));
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (tid < TU && ubase + tid < a.n) a.cand_cnt[(ubase + tid) * a.nsplit + split] = cntsh[tid];
+    if (a.pairs && tid == 0) {
+        // statistics only: pairs of the tiles this workgroup screened
+        int64_t nt = 0;
+        for (int t = split; t < a.ntiles; t += a.nsplit) {
+            if (a.Np[(int64_t)t * TILE_ITEMS] < rwg) break;
+            int64_t r0 = (int64_t)t * TILE_ITEMS;
+            nt += (a.m - r0 < TILE_ITEMS) ? (a.m - r0) : TILE_ITEMS;
+        }
+        int64_t nu_valid = (a.n - ubase < TU) ? (a.n - ubase) : TU;
+        atomicAdd(a.pairs, (unsigned long long)(nt * nu_valid));
+    }
+}
+
+// ------------------------------------------------------------------ final
+constexpr int FIN_WAVES = 4;
+
+__global__ __launch_bounds__(256) void k_thresh_final(ThreshArgs a, int capT) {
+    extern __shared__ float smem[];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t u = (int64_t)blockIdx.x * FIN_WAVES + w;
+    const bool valid = u < a.n;
+    // per-wave LDS: v64[capT] (double), lo, hi (float), cidx, sid (int)
+    uint8_t *base = reinterpret_cast<uint8_t *>(smem) + (size_t)w * capT * 24;
+    double *v64 = reinterpret_cast<double *>(base);
+    float *lo = reinterpret_cast<float *>(base + (size_t)capT * 8);
+    float *hi = lo + capT;
+    int *cidx = reinterpret_cast<int *>(hi + capT);
+    int *sid = cidx + capT;
+    __shared__ float Lstar[FIN_WAVES];
+    __shared__ int nsurv[FIN_WAVES];
+
+    int total = 0;
+    bool over = false;
+    if (valid) {
+        for (int s = 0; s < a.nsplit; ++s) {
+            int c = a.cand_cnt[u * a.nsplit + s];
+            over |= c > a.cap;
+            total += c;
+        }
+        if (total > capT) over = true;
+        if (lane == 0) a.flag[u] = over ? 1 : 0;
+    }
+    const bool work = valid && !over;
+    const float nu = valid ? a.Nu[u] : 0.0f;
+    const float cnu = a.c_err * nu;
+    if (lane == 0) Lstar[w] = -INFINITY;
+    if (work) {
+        int off = 0;
+        for (int s = 0; s < a.nsplit; ++s) {
+            const int c = a.cand_cnt[u * a.nsplit + s];
+            const float2 *src = a.cand + (u * a.nsplit + s) * a.cap;
+            for (int e = lane; e < c; e += 64) {
+                float2 cv = src[e];
+                int idx = __float_as_int(cv.y);
+                float eb = fmaf(cnu, a.Np[idx], a.e_abs);
+                lo[off + e] = cv.x - eb;
+                hi[off + e] = cv.x + eb;
+                cidx[off + e] = idx;
+            }
+            off += c;
+        }
+    }
+    __syncthreads();
+    // L* = k-th largest lower bound (rank by value desc, position asc)
+    if (work) {
+        for (int e = lane; e < total; e += 64) {
+            const float x = lo[e];
+            int rank = 0;
+            for (int f = 0; f < total; ++f) {
+                float y = lo[f];
+                rank += (y > x) || (y == x && f < e);
+            }
+            if (rank == a.k - 1) Lstar[w] = x;
+        }
+    }
+    __syncthreads();
+    // survivors: upper bound reaches L*; keep their caller ids
+    if (work) {
+        const float Ls = Lstar[w];
+        int cntw = 0;
+        for (int e0 = 0; e0 < total; e0 += 64) {
+            const int e = e0 + lane;
+            const bool keep = e < total && hi[e] >= Ls;
+            const uint64_t bal = __ballot(keep);
+            const int pos = cntw + __popcll(bal & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+            if (keep) sid[pos] = a.perm[cidx[e]];
+            cntw += __popcll(bal);
+        }
+        if (lane == 0) nsurv[w] = cntw;
+    }
+    __syncthreads();
+    if (work) {
+        const int ns = nsurv[w];
+        const float *urow = a.U + u * a.d;
+        for (int s = lane; s < ns; s += 64)
+            v64[s] = ip64(urow, a.P + (int64_t)sid[s] * a.d, a.d);
+    }
+    __syncthreads();
+    if (work) {
+        const int ns = nsurv[w];
+        for (int s = lane; s < ns; s += 64) {
+            const double x = v64[s];
+            const int c = sid[s];
+            int rank = 0;
+            for (int f = 0; f < ns; ++f) {
+                double y = v64[f];
+                rank += (y > x) || (y == x && sid[f] < c);
+            }
+            if (rank == a.k - 1) {
+                a.tau[u] = x;
+                a.tau_id[u] = c;
+            }
+            if (a.topk && rank < a.k) a.topk[u * a.k + rank] = c;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ fallback
+// Brute force for users whose candidate list overflowed: one wave per user,
+// every item in FP64, per-lane top-k lists merged by k rounds of a wave-wide
+// maximum under (value desc, id asc).
+constexpr int FB_WAVES = 2;
+
+__global__ __launch_bounds__(64 * FB_WAVES) void k_thresh_fallback(ThreshArgs a) {
+    __shared__ double lv[FB_WAVES][64][KMAX];
+    __shared__ int li[FB_WAVES][64][KMAX];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int k = a.k;
+    for (int64_t u = (int64_t)blockIdx.x * FB_WAVES + w; u < a.n;
+         u += (int64_t)gridDim.x * FB_WAVES) {
+        if (a.flag[u] == 0) continue;
+        const float *urow = a.U + u * a.d;
+        double *myv = lv[w][lane];
+        int *myi = li[w][lane];
+        int cnt = 0;
+        for (int64_t j = lane; j < a.m; j += 64) {
+            const int c = (int)j;  // caller id
+            const double v = ip64(urow, a.P + j * a.d, a.d);
+            if (cnt == k) {
+                const double tv = myv[k - 1];
+                const int ti = myi[k - 1];
+                if (!(v > tv || (v == tv && c < ti))) continue;
+            }
+            int pos = (cnt < k) ? cnt : k - 1;
+            while (pos > 0 && (myv[pos - 1] < v || (myv[pos - 1] == v && myi[pos - 1] > c))) {
+                myv[pos] = myv[pos - 1];
+                myi[pos] = myi[pos - 1];
+                --pos;
+            }
+            myv[pos] = v;
+            myi[pos] = c;
+            if (cnt < k) ++cnt;
+        }
+        int head = 0;
+        for (int r = 0; r < k; ++r) {
+            double bv = (head < cnt) ? myv[head] : -INFINITY;
+            int bi = (head < cnt) ? myi[head] : 0x7fffffff;
+            int bl = lane;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                double ov = __shfl_xor(bv, o);
+                int oi = __shfl_xor(bi, o);
+                int ol = __shfl_xor(bl, o);
+                if (ov > bv || (ov == bv && oi < bi)) {
+                    bv = ov;
+                    bi = oi;
+                    bl = ol;
+                }
+            }
+            if (lane == bl) ++head;
+            if (lane == 0) {
+                if (a.topk) a.topk[u * k + r] = bi;
+                if (r == k - 1) {
+                    a.tau[u] = bv;
+                    a.tau_id[u] = bi;
+                }
+            }
+        }
+    }
+}
+
+void launch_thresh(const ThreshArgs &a, hipStream_t st) {
+    const int nw = thresh_waves(a.D);
+    const int tu = 32 * nw;
+    dim3 g((unsigned)((a.n + tu - 1) / tu), (unsigned)a.nsplit);
+    if (a.ev0) (void)hipEventRecord(a.ev0, st);
+    if (nw == 4)
+        k_thresh_screen<4><<<g, 256, thresh_screen_lds_nw(a.D, 4), st>>>(a);
+    else
+        k_thresh_screen<2><<<g, 128, thresh_screen_lds_nw(a.D, 2), st>>>(a);
+    if (a.ev1) (void)hipEventRecord(a.ev1, st);
+    const int capT = a.cap * a.nsplit;
+    size_t lds = (size_t)FIN_WAVES * capT * 24;
+    k_thresh_final<<<(unsigned)((a.n + FIN_WAVES - 1) / FIN_WAVES), 256, lds, st>>>(a, capT);
+    int64_t fb = (a.n + FB_WAVES - 1) / FB_WAVES;
+    if (fb > 1024) fb = 1024;
+    k_thresh_fallback<<<(unsigned)fb, 64 * FB_WAVES, 0, st>>>(a);
+}
+
+}  // namespace rmips

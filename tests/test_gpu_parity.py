@@ -1,0 +1,210 @@
+"""GPU parity: every librmips output against the CPU FP64 oracle.
+
+Integer outputs (ids, scores) and the FP64 thresholds must match bit for
+bit; inputs are the seeded synthetic workloads plus hand-built tie cases.
+"""
+import numpy as np
+import pytest
+
+import oracle as orc
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _rm():
+    import paper_2504_13445_amd as rm
+    return rm
+
+
+def _g(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(_dev())
+
+
+def _check_thresholds(U, P, k, **kw):
+    rm = _rm()
+    tau, tid, topk = rm.thresholds(_g(U), _g(P), k, with_topk=True, **kw)
+    t, j, tk = orc.kmips_c(U, P, k)
+    tau, tid, topk = tau.cpu().numpy(), tid.cpu().numpy(), topk.cpu().numpy()
+    bad = np.nonzero((tau.view(np.uint64) != t.view(np.uint64)) | (tid != j))[0]
+    assert bad.size == 0, (bad[:10], tau[bad[:5]], t[bad[:5]], tid[bad[:5]], j[bad[:5]])
+    assert np.array_equal(topk, tk)
+    return t, j, tk
+
+
+def _check_topn(U, P, k, N, topk_ref=None, **kw):
+    rm = _rm()
+    if topk_ref is None:
+        _, _, topk_ref = orc.kmips_c(U, P, k)
+    ri, rs = orc.topn_from_scores(orc.histogram_scores(topk_ref, P.shape[0]), N)
+    ids, sc, st = rm.topn(_g(U), _g(P), k, N, **kw)
+    assert ids.tolist() == ri.tolist() and sc.tolist() == rs.tolist(), (ids, ri, sc, rs)
+    return st
+
+
+# ------------------------------------------------------------ stage (a)
+def test_thresholds_tiny_workload():
+    _say("thresholds tiny 2000x1000x16 k=10")
+    U, P = synth.make_config(0)
+    _check_thresholds(U, P, 10)
+
+
+@pytest.mark.parametrize("n,m,d,k", [(1, 1, 1, 1), (7, 3, 5, 3), (130, 65, 17, 32),
+                                     (300, 64, 8, 1), (257, 129, 33, 7), (64, 500, 255, 20),
+                                     (1000, 4097, 50, 10)])
+def test_thresholds_shapes(n, m, d, k):
+    _say("thresholds shape", n, m, d, k)
+    rng = np.random.default_rng(n * 7 + m)
+    U = synth.isotropic(rng, n, d, 0.3)
+    P = synth.isotropic(rng, m, d, 0.6)
+    _check_thresholds(U, P, k)
+
+
+def test_thresholds_forced_fallback():
+    _say("thresholds forced fallback cap=1")
+    U, P = synth.make_config(0, n=600, m=900)
+    _check_thresholds(U, P, 10, cand_cap=1)
+
+
+def test_thresholds_ties_and_zeros():
+    _say("thresholds ties")
+    rng = np.random.default_rng(5)
+    P = rng.integers(-2, 3, size=(200, 6)).astype(np.float32)
+    P[100:150] = P[0:50]          # exact duplicates
+    P[150:160] = 0.0              # zero items
+    U = rng.integers(-2, 3, size=(300, 6)).astype(np.float32)
+    U[:5] = 0.0                   # zero users: every item ties at 0
+    for k in (1, 5, 17):
+        _check_thresholds(U, P, k)
+
+
+def test_thresholds_onehot_golden(golden_dir):
+    import json, os
+    g = json.load(open(os.path.join(golden_dir, "onehot_case.json")))
+    U = np.array(g["U"], np.float32)
+    P = np.array(g["P"], np.float32)
+    rm = _rm()
+    for ks, e in g["k"].items():
+        _say("onehot k", ks)
+        tau, tid, topk = rm.thresholds(_g(U), _g(P), int(ks), with_topk=True)
+        assert tau.cpu().numpy().tolist() == e["tau"]
+        assert tid.cpu().numpy().tolist() == e["tau_id"]
+        assert topk.cpu().numpy().tolist() == e["topk"]
+
+
+def test_thresholds_tiny_magnitudes():
+    # entries in the FP32 subnormal range: the screen's bound must hold
+    _say("thresholds subnormal-range inputs")
+    rng = np.random.default_rng(8)
+    U = (synth.isotropic(rng, 200, 12, 0.3).astype(np.float64) * 1e-20).astype(np.float32)
+    P = (synth.isotropic(rng, 300, 12, 0.3).astype(np.float64) * 1e-20).astype(np.float32)
+    _check_thresholds(U, P, 5)
+
+
+# ------------------------------------------------------------ stage (b)
+def test_scores_all_items_equal_histogram():
+    _say("scores of all items, tiny workload")
+    U, P = synth.make_config(0)
+    rm = _rm()
+    k = 10
+    t, j, tk = orc.kmips_c(U, P, k)
+    Ug = _g(U)
+    tau, tid = rm.thresholds(Ug, _g(P), k)
+    s = rm.scores(Ug, tau, tid, _g(P), torch.arange(P.shape[0], dtype=torch.int32,
+                                                      device=_dev()))
+    h = orc.histogram_scores(tk, P.shape[0])
+    assert np.array_equal(s.cpu().numpy(), h)
+    assert int(s.sum()) == U.shape[0] * k
+
+
+def test_scores_external_and_duplicate_queries():
+    _say("scores external queries")
+    U, P = synth.make_config(0, n=800, m=300)
+    rm = _rm()
+    k = 7
+    t, j, _ = orc.kmips_c(U, P, k)
+    rng = np.random.default_rng(3)
+    Q = (rng.standard_normal((40, U.shape[1])) * 0.8).astype(np.float32)
+    Q[:10] = P[:10]                       # duplicates of items: lose every tie
+    qid = np.full(40, -1, np.int32)
+    qid[10:20] = np.arange(10, 20)        # members of P: tie rule by id
+    Q[10:20] = P[10:20]
+    ref = orc.reverse_counts_c(U, t, j, Q, qid)
+    s = rm.scores(_g(U), _g(t), _g(j), _g(Q), _g(qid))
+    assert np.array_equal(s.cpu().numpy(), ref)
+
+
+# ------------------------------------------------------------ top-N
+def test_topn_tiny_workload():
+    _say("topn tiny")
+    U, P = synth.make_config(0)
+    st = _check_topn(U, P, 10, 10)
+    assert st["visited_items"] <= P.shape[0]
+
+
+@pytest.mark.parametrize("batch", [(1, 1), (16, 64), (4096, 4096)])
+def test_topn_batch_invariance(batch):
+    _say("topn batch", batch)
+    U, P = synth.make_config(0, n=1200, m=400)
+    _check_topn(U, P, 5, 20, batch=batch)
+
+
+@pytest.mark.parametrize("k,N", [(1, 1), (32, 50), (3, 400)])
+def test_topn_parameters(k, N):
+    _say("topn k N", k, N)
+    U, P = synth.make_config(1, n=3000, m=400)
+    _check_topn(U, P, k, N)
+
+
+def test_topn_ties():
+    _say("topn ties")
+    rng = np.random.default_rng(6)
+    P = rng.integers(-2, 3, size=(120, 5)).astype(np.float32)
+    P[60:] = P[:60]
+    U = rng.integers(-2, 3, size=(500, 5)).astype(np.float32)
+    for k, N in ((3, 10), (8, 60)):
+        _check_topn(U, P, k, N)
+
+
+def test_topn_forced_fallback_and_small_batches():
+    _say("topn forced fallback")
+    U, P = synth.make_config(0, n=700, m=500)
+    _check_topn(U, P, 10, 10, cand_cap=2, batch=(8, 32))
+
+
+# ------------------------------------------------------------ full sizes
+@pytest.fixture(scope="module")
+def mf_workload():
+    U, P = synth.make_config(1)
+    t, j, tk = orc.kmips_c(U, P, 10)
+    return U, P, t, j, tk
+
+
+def test_mf_thresholds_full(mf_workload):
+    _say("mf thresholds 100000x20000x50")
+    U, P, t, j, tk = mf_workload
+    rm = _rm()
+    tau, tid, topk = rm.thresholds(_g(U), _g(P), 10, with_topk=True)
+    assert np.array_equal(tau.cpu().numpy().view(np.uint64), t.view(np.uint64))
+    assert np.array_equal(tid.cpu().numpy(), j)
+    assert np.array_equal(topk.cpu().numpy(), tk)
+
+
+def test_mf_topn_full(mf_workload):
+    _say("mf topn 100000x20000x50 k=10 N=10")
+    U, P, t, j, tk = mf_workload
+    h = orc.histogram_scores(tk, P.shape[0])
+    assert h.sum() == U.shape[0] * 10
+    st = _check_topn(U, P, 10, 10, topk_ref=tk)
+    print("stats", st, flush=True)
