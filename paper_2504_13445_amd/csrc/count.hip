@@ -2,30 +2,19 @@
 // stage (c): the Eq. (3)/(6) upper-bound counts uscore(p) and the running
 // top-N of the bound-ordered visit (Alg. 2).
 //
-// Both counting kernels keep a tile of 64 items in LDS and stream users
-// through LDS 128 at a time; the matrix cores give an FP32 value per
-// (item, user) pair, each lane owns one user column and 16 item rows of a
-// 32x32 block, and counts accumulate per lane and item row, so no global
-// atomics are needed: each workgroup writes one partial count per item,
-// and a second pass sums the partials in a fixed order.
+// Both counting kernels keep a tile of items in LDS and stream users through
+// LDS; the matrix cores give an FP32 value per (item, user) pair, each lane
+// owns one user column and 16 item rows of a 32x32 block, and counts
+// accumulate per lane and item row, so no global atomics are needed: each
+// workgroup writes one partial count per item, and a second pass sums the
+// partials in a fixed order.
 #include "common.h"
 #include "kernels.h"
 
 namespace rmips {
 
-constexpr int CI = 64;    // items per counting workgroup
+constexpr int CI = 64;    // items per bound-count workgroup
 constexpr int CU = 128;   // users per streamed chunk of the bound kernel
-
-// The counting kernel streams 32 users per wave; NW = 4 waves, or 2 when
-// long rows would not fit four waves' users in LDS.
-size_t count_lds_nw(int D, int nw) {
-    const int ld = D + LDS_PAD;
-    return (size_t)(CI + 32 * nw) * ld * sizeof(float) + nw * CI * sizeof(int);
-}
-
-int count_waves(int D) { return count_lds_nw(D, 4) <= 96 * 1024 ? 4 : 2; }
-
-size_t count_lds(int D) { return count_lds_nw(D, count_waves(D)); }
 
 // Sum of a per-slot count over the 32 lanes of each half-wave; afterwards
 // lanes 0 and 32 hold the totals of their rows.
@@ -35,24 +24,91 @@ __device__ __forceinline__ int half_sum(int x) {
     return x;
 }
 
+// Counting workgroup: NW waves, each owning 32 items (the row operand,
+// kept in LDS for the whole kernel); users stream through LDS 64 at a time
+// (two column blocks), double-buffered where LDS allows, so the next chunk
+// loads while the current one is multiplied.
+constexpr int CNT_USERS = 64;            // users per chunk
+constexpr int AMB_CAP = 512;             // deferred FP64 rechecks per workgroup
+
+// Counting configuration: nw waves (32 items each), nb user buffers.
+struct CountCfg { int nw, nb, pf; };
+
+size_t count_lds_cfg(int D, int nw, int nb) {
+    const int ld = D + LDS_PAD;
+    return (size_t)(32 * nw + nb * CNT_USERS) * ld * sizeof(float) +
+           AMB_CAP * sizeof(int2) + 32 * nw * sizeof(int) + 16;
+}
+
+CountCfg count_cfg(int D) {
+    CountCfg c{4, 2, 0};
+    if (count_lds_cfg(D, 4, 2) > 96 * 1024) c.nw = 2;
+    if (count_lds_cfg(D, c.nw, 2) > 160 * 1024) c.nb = 1;
+    const int need = CNT_USERS * (D / 4), nt = 64 * c.nw;
+    if (c.nb == 2) c.pf = (need <= 4 * nt) ? 4 : (need <= 8 * nt) ? 8 : 0;
+    return c;
+}
+
+size_t count_lds(int D) {
+    CountCfg c = count_cfg(D);
+    return count_lds_cfg(D, c.nw, c.nb);
+}
+
+// Rows A (shared) against two column blocks B0, B1.
+__device__ __forceinline__ void mfma32x2_rows(f32x16 &acc0, f32x16 &acc1, const float *A,
+                                              const float *B0, const float *B1, int ld,
+                                              int ks, int lane) {
+    const int r = lane & 31, h = lane >> 5;
+    const float *a = A + r * ld + h * ks;
+    const float *b0 = B0 + r * ld + h * ks;
+    const float *b1 = B1 + r * ld + h * ks;
+    for (int s = 0; s < ks; s += 4) {
+        f32x4 av = *reinterpret_cast<const f32x4 *>(a + s);
+        f32x4 bv0 = *reinterpret_cast<const f32x4 *>(b0 + s);
+        f32x4 bv1 = *reinterpret_cast<const f32x4 *>(b1 + s);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q], bv0[q], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q], bv1[q], acc1, 0, 0, 0);
+        }
+    }
+}
+
+// FP64 decision of one (item row, user) pair by the tie rule.
+__device__ __forceinline__ bool recheck_pair(const CountArgs &a, int64_t row, int64_t us) {
+    const int64_t uid = a.us.uid[us];
+    const int64_t orow = a.item_orig ? a.item_orig[row] : row;
+    int tie = a.item_tie ? a.item_tie[row] : -1;
+    if (tie < 0) tie = 0x7fffffff;  // outside P: after every item of P
+    const double v = ip64(a.Uorig + uid * a.d, a.Porig + orow * a.d, a.d);
+    return in_topk(v, tie, a.us.tau[us], a.us.tau_id[us]);
+}
+
 // Exact count.  For a pair with screened value vh and bound E:
 //   vh - E > tau_hi  =>  v > tau_u           (in S_k(u))
 //   vh + E < tau_lo  =>  v < tau_u           (not in S_k(u))
-// and otherwise the pair is recomputed in FP64 and decided by the tie rule.
-template <int NW>
+// E is taken with the largest item norm of the wave's 32 items, so both
+// tests fold into two per-user thresholds; other pairs are recomputed in
+// FP64 and decided by the tie rule.
+// NW waves of 32 items; NB user buffers; PF float4 of a user chunk staged
+// per thread (0 = chunks are loaded synchronously into LDS).
+template <int NW, int PF, int NB>
 __global__ __launch_bounds__(64 * NW) void k_count(CountArgs a) {
-    constexpr int CUW = 32 * NW, NT = 64 * NW;
+    constexpr int NT = 64 * NW, CNT_ITEMS = 32 * NW;
     extern __shared__ float smem[];
     const int D = a.D, ld = D + LDS_PAD, ks = D / 2, D4 = D / 4;
     float *Psh = smem;
-    float *Ush = Psh + CI * ld;
-    int *wsum = reinterpret_cast<int *>(Ush + CUW * ld);  // [NW][CI]
+    float *Ush0 = Psh + CNT_ITEMS * ld;
+    float *Ush1 = Ush0 + (NB - 1) * CNT_USERS * ld;
+    int2 *amb = reinterpret_cast<int2 *>(Ush0 + NB * CNT_USERS * ld);
+    int *cntl = reinterpret_cast<int *>(amb + AMB_CAP);
+    int *ambn = cntl + CNT_ITEMS;
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int64_t ib = (int64_t)blockIdx.x * CI;
+    const int64_t ib = (int64_t)blockIdx.x * CNT_ITEMS;
     const int split = blockIdx.y;
 
-    for (int e = tid; e < CI * D4; e += NT) {
+    for (int e = tid; e < CNT_ITEMS * D4; e += NT) {
         int r = e / D4, c = e - r * D4;
         int64_t it = ib + r;
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -62,106 +118,168 @@ __global__ __launch_bounds__(64 * NW) void k_count(CountArgs a) {
         }
         *reinterpret_cast<float4 *>(Psh + r * ld + 4 * c) = v;
     }
-    // this lane's 32 item rows: norm (0 for rows past the batch)
-    float np[32];
-    bool rvalid[32];
-#pragma unroll
-    for (int i = 0; i < 32; ++i) {
-        const int r = mfma32_row(i & 15, lane) + ((i < 16) ? 0 : 32);
-        const int64_t it = ib + r;
-        rvalid[i] = it < a.nb;
-        np[i] = 0.0f;
-        if (rvalid[i]) np[i] = a.Np[a.rows ? a.rows[it] : it];
-    }
-    int cnt[32];
-#pragma unroll
-    for (int i = 0; i < 32; ++i) cnt[i] = 0;
-    int64_t nrecheck = 0;
+    if (tid < CNT_ITEMS) cntl[tid] = 0;
+    if (tid == 0) *ambn = 0;
 
-    const int64_t nchunks = (a.ulen + CUW - 1) / CUW;
-    for (int64_t ch = split; ch < nchunks; ch += a.nsplit) {
-        const int64_t u0 = ch * CUW;
-        __syncthreads();
-        for (int e = tid; e < CUW * D4; e += NT) {
-            int r = e / D4, c = e - r * D4;
-            int64_t us = u0 + r;
+    // largest norm among this wave's 32 items; row validity bits
+    float npmax = 0.0f;
+    {
+        const int64_t it = ib + w * 32 + (lane & 31);
+        if (it < a.nb) npmax = a.Np[a.rows ? a.rows[it] : it];
+#pragma unroll
+        for (int o = 1; o < 32; o <<= 1) npmax = fmaxf(npmax, __shfl_xor(npmax, o));
+    }
+    uint32_t rvalid = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+        rvalid |= (ib + w * 32 + mfma32_row(i, lane) < a.nb) ? (1u << i) : 0u;
+
+    int cnt[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) cnt[i] = 0;
+
+    const int64_t nchunks = (a.ulen + CNT_USERS - 1) / CNT_USERS;
+    const int nvec = CNT_USERS * D4;  // float4 per chunk
+    constexpr int PFN = PF > 0 ? PF : 1;
+    int qrow[PFN], qg[PFN], ql[PFN];  // row in chunk, float4 offset in row, LDS offset
+#pragma unroll
+    for (int q = 0; q < PFN; ++q) {
+        const int e = tid + q * NT;
+        const int r = e / D4, c = e - r * D4;
+        qrow[q] = (e < nvec) ? r : CNT_USERS;
+        qg[q] = c;
+        ql[q] = r * ld + 4 * c;
+    }
+    float4 pf[PFN];
+    auto fetch = [&](int64_t ch) {
+        const int64_t u0 = ch * CNT_USERS;
+#pragma unroll
+        for (int q = 0; q < PFN; ++q) {
             float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (us < a.ulen) v = reinterpret_cast<const float4 *>(a.Us)[us * D4 + c];
-            *reinterpret_cast<float4 *>(Ush + r * ld + 4 * c) = v;
+            if (qrow[q] < CNT_USERS && u0 + qrow[q] < a.ulen)
+                v = reinterpret_cast<const float4 *>(a.Us)[(u0 + qrow[q]) * D4 + qg[q]];
+            pf[q] = v;
         }
-        __syncthreads();
-        const int64_t us = u0 + w * 32 + (lane & 31);
-        const bool cvalid = us < a.ulen;
-        const float ua = cvalid ? a.us.a[us] : 0.0f;
-        const float thi = cvalid ? a.us.tau_hi[us] : INFINITY;
-        const float tlo = cvalid ? a.us.tau_lo[us] : INFINITY;
+    };
+    auto stash = [&](float *dst) {
+#pragma unroll
+        for (int q = 0; q < PFN; ++q)
+            if (qrow[q] < CNT_USERS) *reinterpret_cast<float4 *>(dst + ql[q]) = pf[q];
+    };
+    auto load_sync = [&](int64_t ch, float *dst) {
+        const int64_t u0 = ch * CNT_USERS;
+        for (int e = tid; e < nvec; e += NT) {
+            const int r = e / D4, c = e - r * D4;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (u0 + r < a.ulen) v = reinterpret_cast<const float4 *>(a.Us)[(u0 + r) * D4 + c];
+            *reinterpret_cast<float4 *>(dst + r * ld + 4 * c) = v;
+        }
+    };
+
+    int64_t ch = split;
+    if (ch < nchunks) {
+        if (PF > 0) {
+            fetch(ch);
+            stash(Ush0);
+        } else {
+            load_sync(ch, Ush0);
+        }
+    }
+    __syncthreads();
+    int buf = 0;
+    for (; ch < nchunks; ch += a.nsplit) {
+        const int64_t nxt = ch + a.nsplit;
+        if (PF > 0 && nxt < nchunks) fetch(nxt);
+        const float *Ub = buf ? Ush1 : Ush0;
+        const int64_t us0 = ch * CNT_USERS + (lane & 31), us1 = us0 + 32;
+        // a column past the last user is "out" for every row: tout = +inf
+        float tin0 = INFINITY, tout0 = INFINITY, tin1 = INFINITY, tout1 = INFINITY;
+        const bool c0 = us0 < a.ulen, c1 = us1 < a.ulen;
+        if (c0) {
+            const float e = fmaf(a.us.a[us0], npmax, E_ABS);
+            tin0 = a.us.tau_hi[us0] + e;
+            tout0 = a.us.tau_lo[us0] - e;
+        }
+        if (c1) {
+            const float e = fmaf(a.us.a[us1], npmax, E_ABS);
+            tin1 = a.us.tau_hi[us1] + e;
+            tout1 = a.us.tau_lo[us1] - e;
+        }
         f32x16 acc0 = {0}, acc1 = {0};
-        mfma32x2_f32(acc0, acc1, Psh, Psh + 32 * ld, Ush + w * 32 * ld, ld, ks, lane);
-        bool amb_any = false;
-        uint32_t ambm = 0;
+        mfma32x2_rows(acc0, acc1, Psh + w * 32 * ld, Ub, Ub + 32 * ld, ld, ks, lane);
+        uint32_t ambm0 = 0, ambm1 = 0;
 #pragma unroll
-        for (int i = 0; i < 32; ++i) {
-            const float v = (i < 16) ? acc0[i] : acc1[i - 16];
-            const float e = fmaf(ua, np[i], E_ABS);
-            const bool in = (v - e) > thi;
-            const bool out = (v + e) < tlo;
-            cnt[i] += in ? 1 : 0;
-            const bool amb = !(in || out) && cvalid && rvalid[i];
-            ambm |= amb ? (1u << i) : 0u;
-            amb_any |= amb;
+        for (int i = 0; i < 16; ++i) {
+            const float v0 = acc0[i], v1 = acc1[i];
+            const bool in0 = v0 > tin0, in1 = v1 > tin1;
+            cnt[i] += (in0 ? 1 : 0) + (in1 ? 1 : 0);
+            ambm0 |= (!in0 && !(v0 < tout0)) ? (1u << i) : 0u;
+            ambm1 |= (!in1 && !(v1 < tout1)) ? (1u << i) : 0u;
         }
-        if (__ballot(amb_any) != 0ull) {
-            const int64_t uid = cvalid ? a.us.uid[us] : 0;
-            const double tau = cvalid ? a.us.tau[us] : 0.0;
-            const int tid_k = cvalid ? a.us.tau_id[us] : 0;
-            const float *urow = a.Uorig + uid * a.d;
-#pragma unroll
+        ambm0 = c0 ? (ambm0 & rvalid) : 0u;
+        ambm1 = c1 ? (ambm1 & rvalid) : 0u;
+        if (__ballot((ambm0 | ambm1) != 0u) != 0ull) {
+#pragma unroll 1
             for (int i = 0; i < 32; ++i) {
-                const bool amb = (ambm >> i) & 1u;
-                if (__ballot(amb) != 0ull && amb) {
-                    const int r = mfma32_row(i & 15, lane) + ((i < 16) ? 0 : 32);
-                    const int64_t it = ib + r;
-                    const int64_t row = a.rows ? a.rows[it] : it;
-                    const int64_t orow = a.item_orig ? a.item_orig[row] : row;
-                    const int tie = a.item_tie ? a.item_tie[row] : 0x7fffffff;
-                    const double v = ip64(urow, a.Porig + orow * a.d, a.d);
-                    cnt[i] += in_topk(v, tie < 0 ? 0x7fffffff : tie, tau, tid_k) ? 1 : 0;
-                    ++nrecheck;
+                const bool p = ((i < 16 ? ambm0 : ambm1) >> (i & 15)) & 1u;
+                if (p) {
+                    const int rl = w * 32 + mfma32_row(i & 15, lane);
+                    const int64_t us = (i < 16) ? us0 : us1;
+                    const int s = atomicAdd(ambn, 1);
+                    if (s < AMB_CAP) {
+                        amb[s] = make_int2(rl, (int)us);
+                    } else {
+                        const int64_t row = a.rows ? a.rows[ib + rl] : ib + rl;
+                        if (recheck_pair(a, row, us)) atomicAdd(&cntl[rl], 1);
+                    }
                 }
             }
         }
+        if (nxt < nchunks) {
+            if (NB == 1) {
+                __syncthreads();  // every wave is done with the only buffer
+                load_sync(nxt, Ush0);
+            } else if (PF > 0) {
+                stash(buf ? Ush0 : Ush1);
+            } else {
+                load_sync(nxt, buf ? Ush0 : Ush1);
+            }
+        }
+        __syncthreads();
+        if (NB == 2) buf ^= 1;
     }
-    // reduce: rows of half 0 live in lanes 0..31, of half 1 in 32..63
-#pragma unroll
-    for (int i = 0; i < 32; ++i) {
-        const int s = half_sum(cnt[i]);
-        const int r = mfma32_row(i & 15, lane) + ((i < 16) ? 0 : 32);
-        if ((lane & 31) == 0) wsum[w * CI + r] = s;
+    // deferred FP64 rechecks, spread over the whole workgroup
+    const int nall = *ambn;
+    const int na = nall < AMB_CAP ? nall : AMB_CAP;
+    for (int e = tid; e < na; e += NT) {
+        const int2 q = amb[e];
+        const int64_t row = a.rows ? a.rows[ib + q.x] : ib + q.x;
+        if (recheck_pair(a, row, q.y)) atomicAdd(&cntl[q.x], 1);
     }
     __syncthreads();
-    if (tid < CI) {
-        const int64_t it = ib + tid;
-        int s = 0;
 #pragma unroll
-        for (int q = 0; q < NW; ++q) s += wsum[q * CI + tid];
-        if (it < a.nb) a.partial[(int64_t)split * a.nb + it] = s;
+    for (int i = 0; i < 16; ++i) {
+        const int s = half_sum(cnt[i]);
+        const int rl = w * 32 + mfma32_row(i, lane);
+        if ((lane & 31) == 0 && ib + rl < a.nb)
+            a.partial[(int64_t)split * a.nb + ib + rl] = s + cntl[rl];
     }
-    if (a.rechecks) {
-        int64_t tot = nrecheck;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o);
-        if (lane == 0 && tot) atomicAdd(reinterpret_cast<unsigned long long *>(a.rechecks),
-                                        (unsigned long long)tot);
-    }
+    if (a.rechecks && tid == 0 && nall > 0)
+        atomicAdd(reinterpret_cast<unsigned long long *>(a.rechecks), (unsigned long long)nall);
 }
 
 void launch_count(const CountArgs &a, hipStream_t st) {
     if (a.nb <= 0) return;
-    dim3 g((unsigned)((a.nb + CI - 1) / CI), (unsigned)a.nsplit);
-    if (count_waves(a.D) == 4)
-        k_count<4><<<g, 256, count_lds_nw(a.D, 4), st>>>(a);
-    else
-        k_count<2><<<g, 128, count_lds_nw(a.D, 2), st>>>(a);
+    const CountCfg c = count_cfg(a.D);
+    const size_t lds = count_lds_cfg(a.D, c.nw, c.nb);
+    dim3 g((unsigned)((a.nb + 32 * c.nw - 1) / (32 * c.nw)), (unsigned)a.nsplit);
+    if (c.nw == 4 && c.pf == 4) k_count<4, 4, 2><<<g, 256, lds, st>>>(a);
+    else if (c.nw == 4 && c.pf == 8) k_count<4, 8, 2><<<g, 256, lds, st>>>(a);
+    else if (c.nw == 4) k_count<4, 0, 2><<<g, 256, lds, st>>>(a);
+    else if (c.nb == 2 && c.pf == 4) k_count<2, 4, 2><<<g, 128, lds, st>>>(a);
+    else if (c.nb == 2 && c.pf == 8) k_count<2, 8, 2><<<g, 128, lds, st>>>(a);
+    else if (c.nb == 2) k_count<2, 0, 2><<<g, 128, lds, st>>>(a);
+    else k_count<2, 0, 1><<<g, 128, lds, st>>>(a);
 }
 
 // Eq. (3)/(6) bound count over the users of the item tile's Cauchy-Schwarz
@@ -283,12 +401,11 @@ void launch_gather_i32(const int32_t *src, const int32_t *idx, int64_t n, int32_
 // sorted (bitonic, descending keys score<<32 | ~id) in LDS.
 constexpr int TOPN_CAP = 8192;
 
-__global__ __launch_bounds__(1024) void k_topn_merge(const int32_t *__restrict__ partial,
-                                                     int nsplit, int64_t nb,
+__global__ __launch_bounds__(1024) void k_topn_merge(const int32_t *__restrict__ scores,
+                                                     int64_t nb,
                                                      const int32_t *__restrict__ batch_ids,
                                                      int N, uint64_t *__restrict__ top,
-                                                     int32_t *__restrict__ status,
-                                                     int32_t *__restrict__ batch_scores) {
+                                                     int32_t *__restrict__ status) {
     __shared__ uint64_t key[TOPN_CAP];
     __shared__ int cnt;
     const int t = threadIdx.x;
@@ -298,9 +415,7 @@ __global__ __launch_bounds__(1024) void k_topn_merge(const int32_t *__restrict__
     for (int i = t; i < kept; i += 1024) key[i] = top[i];
     __syncthreads();
     for (int64_t j = t; j < nb; j += 1024) {
-        int s = 0;
-        for (int q = 0; q < nsplit; ++q) s += partial[(int64_t)q * nb + j];
-        if (batch_scores) batch_scores[j] = s;
+        const int s = scores[j];
         if (s >= tauN) {
             int pos = atomicAdd(&cnt, 1);
             key[pos] = ((uint64_t)(uint32_t)s << 32) | (uint64_t)(~(uint32_t)batch_ids[j]);
@@ -336,11 +451,9 @@ __global__ __launch_bounds__(1024) void k_topn_merge(const int32_t *__restrict__
     }
 }
 
-void launch_topn_merge(const int32_t *partial, int nsplit, int64_t nb, const int32_t *batch_ids,
-                       int N, uint64_t *top, int32_t *status, int32_t *batch_scores,
-                       hipStream_t st) {
-    k_topn_merge<<<1, 1024, 0, st>>>(partial, nsplit, nb, batch_ids, N, top, status,
-                                     batch_scores);
+void launch_topn_merge(const int32_t *scores, int64_t nb, const int32_t *batch_ids, int N,
+                       uint64_t *top, int32_t *status, hipStream_t st) {
+    k_topn_merge<<<1, 1024, 0, st>>>(scores, nb, batch_ids, N, top, status);
 }
 
 }  // namespace rmips

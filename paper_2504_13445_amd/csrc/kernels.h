@@ -49,8 +49,10 @@ void launch_gather_padded(const float *Xpad, const int32_t *order, int64_t rows,
 // cs[j] = number of sorted ratios rho <= norm[j] * (1 + 2^-18)
 void launch_cs_prefix(const uint32_t *rho_sorted_keys, int64_t n, const float *norm,
                       int64_t m, int32_t *cs, hipStream_t st);
-// G = sum over sampled rows x x^T (FP64, d x d), rows u = s*stride, s < ns
-void launch_gram(const float *X, int64_t ns, int64_t stride, int d, double *G,
+// G = sum over sampled rows x x^T (FP64, d x d), rows u = s*stride, s < ns;
+// scratch holds gram_scratch_bytes(d) bytes of per-slice partial sums
+size_t gram_scratch_bytes(int d);
+void launch_gram(const float *X, int64_t ns, int64_t stride, int d, double *G, double *scratch,
                  hipStream_t st);
 // Augmented rows for the Eq. (3) bound: out[r] = [W x (d' values), tail(x),
 // scale * ||x||, 0...] with leading dimension 16, where W (d' x d, FP64) has
@@ -109,12 +111,11 @@ void launch_visit_keys(const int32_t *uscore, const int32_t *inv, int64_t m,
 void launch_gather_i32(const int32_t *src, const int32_t *idx, int64_t n, int32_t *dst,
                        hipStream_t st);
 
-// Running top-N: merge scores of a batch (sum of nsplit partial rows) into
-// the sorted list `top` (keys score<<32 | ~id), keep N.  status[0] = N-th
-// score (-1 while fewer than N), status[1] = entries kept.
-void launch_topn_merge(const int32_t *partial, int nsplit, int64_t nb,
-                       const int32_t *batch_ids, int N, uint64_t *top, int32_t *status,
-                       int32_t *batch_scores, hipStream_t st);
+// Running top-N: merge the exact scores of a batch into the sorted list
+// `top` (keys score<<32 | ~id), keep N.  status[0] = N-th score (-1 while
+// fewer than N), status[1] = entries kept.  nb <= 4096, N <= 1024.
+void launch_topn_merge(const int32_t *scores, int64_t nb, const int32_t *batch_ids, int N,
+                       uint64_t *top, int32_t *status, hipStream_t st);
 
 // ---------------------------------------------------------- relaxed score
 void launch_soft(const float *U, int64_t n, const float *tau, const float *Q, int64_t nq,

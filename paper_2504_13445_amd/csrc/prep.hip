@@ -159,20 +159,26 @@ void launch_cs_prefix(const uint32_t *rho_sorted_keys, int64_t n, const float *n
     k_cs_prefix<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(rho_sorted_keys, n, norm, m, cs);
 }
 
-// 32x32 tile of G per block, sampled rows staged through LDS.
+// 32x32 tile of G per block over one slice of the sampled rows (blockIdx.z),
+// staged through LDS; slices are summed afterwards in a fixed order.
+constexpr int GRAM_SLICES = 64;
+
 __global__ __launch_bounds__(256) void k_gram(const float *__restrict__ X, int64_t ns,
-                                              int64_t stride, int d, double *__restrict__ G) {
+                                              int64_t stride, int d, double *__restrict__ Gp) {
     __shared__ float xa[64][33];
     __shared__ float xb[64][33];
     const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
     const int t = threadIdx.x, ti = t & 31, tj = t >> 5;  // tj in [0, 8)
+    const int64_t per = (ns + GRAM_SLICES - 1) / GRAM_SLICES;
+    const int64_t sb = (int64_t)blockIdx.z * per;
+    const int64_t se = (sb + per < ns) ? sb + per : ns;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t s0 = 0; s0 < ns; s0 += 64) {
+    for (int64_t s0 = sb; s0 < se; s0 += 64) {
         for (int e = t; e < 64 * 32; e += 256) {
             int rr = e >> 5, cc = e & 31;
             int64_t s = s0 + rr;
             float va = 0.f, vb = 0.f;
-            if (s < ns) {
+            if (s < se) {
                 const float *x = X + s * stride * d;
                 if (i0 + cc < d) va = x[i0 + cc];
                 if (j0 + cc < d) vb = x[j0 + cc];
@@ -188,6 +194,7 @@ __global__ __launch_bounds__(256) void k_gram(const float *__restrict__ X, int64
         }
         __syncthreads();
     }
+    double *G = Gp + (int64_t)blockIdx.z * d * d;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         int i = i0 + ti, j = j0 + tj + 8 * q;
@@ -195,56 +202,86 @@ __global__ __launch_bounds__(256) void k_gram(const float *__restrict__ X, int64
     }
 }
 
-void launch_gram(const float *X, int64_t ns, int64_t stride, int d, double *G,
-                 hipStream_t st) {
-    dim3 g((d + 31) / 32, (d + 31) / 32);
-    k_gram<<<g, 256, 0, st>>>(X, ns, stride, d, G);
+__global__ void k_gram_sum(const double *__restrict__ Gp, int dd, double *__restrict__ G) {
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= dd) return;
+    double s = 0.0;
+    for (int z = 0; z < GRAM_SLICES; ++z) s += Gp[(int64_t)z * dd + e];
+    G[e] = s;
 }
 
-// One wave per row: W x in FP64 (lane j < d' owns output j), norms in FP64.
+size_t gram_scratch_bytes(int d) { return (size_t)GRAM_SLICES * d * d * sizeof(double); }
+
+void launch_gram(const float *X, int64_t ns, int64_t stride, int d, double *G, double *scratch,
+                 hipStream_t st) {
+    dim3 g((d + 31) / 32, (d + 31) / 32, GRAM_SLICES);
+    k_gram<<<g, 256, 0, st>>>(X, ns, stride, d, scratch);
+    k_gram_sum<<<(d * d + 255) / 256, 256, 0, st>>>(scratch, d * d, G);
+}
+
+// One thread per row: W x in FP64 with W staged in LDS, norms in FP64.
+constexpr int DP_MAX = 14;
+
 __global__ __launch_bounds__(256) void k_rotate_aug(const float *__restrict__ X,
                                                     const int32_t *__restrict__ order,
                                                     int64_t rows, int64_t rows_pad, int d,
                                                     const double *__restrict__ W, int dp,
                                                     float scale, float *__restrict__ out) {
-    const int lane = threadIdx.x & 63;
-    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    __shared__ double Ws[DP_MAX * 256];
+    for (int e = threadIdx.x; e < dp * d; e += blockDim.x) Ws[e] = W[e];
+    __syncthreads();
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= rows_pad) return;
     float *o = out + r * 16;
     if (r >= rows) {
-        if (lane < 16) o[lane] = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) o[j] = 0.0f;
         return;
     }
     const float *x = X + (int64_t)(order ? order[r] : r) * d;
+    double y[DP_MAX];
+#pragma unroll
+    for (int j = 0; j < DP_MAX; ++j) y[j] = 0.0;
     double s = 0.0;
-    for (int i = lane; i < d; i += 64) s += (double)x[i] * (double)x[i];
+    for (int i = 0; i < d; ++i) {
+        const double xi = (double)x[i];
+        s += xi * xi;
 #pragma unroll
-    for (int o2 = 32; o2 > 0; o2 >>= 1) s += __shfl_xor(s, o2);
-    double y = 0.0;
-    if (lane < dp) {
-        const double *w = W + (int64_t)lane * d;
-        for (int i = 0; i < d; ++i) y += w[i] * (double)x[i];
+        for (int j = 0; j < DP_MAX; ++j)
+            if (j < dp) y[j] += Ws[j * d + i] * xi;
     }
-    double y2 = (lane < dp) ? y * y : 0.0;
+    double y2 = 0.0;
+    float ov[16];
 #pragma unroll
-    for (int o2 = 32; o2 > 0; o2 >>= 1) y2 += __shfl_xor(y2, o2);
-    if (lane < dp) o[lane] = (float)y;
-    if (lane == 0) {
-        // tail^2 = ||x||^2 - ||W x||^2, widened by 1e-12 ||x||^2 to cover the
-        // FP64 rounding and the departure of W from exact orthonormality
-        double t2 = s - y2;
-        if (t2 < 0.0) t2 = 0.0;
-        o[dp] = __double2float_ru(sqrt(t2 + 1e-12 * s));
-        o[dp + 1] = scale * __double2float_ru(sqrt(s) * (1.0 + 0x1p-40));
+    for (int j = 0; j < 16; ++j) ov[j] = 0.0f;
+#pragma unroll
+    for (int j = 0; j < DP_MAX; ++j)
+        if (j < dp) {
+            y2 += y[j] * y[j];
+            ov[j] = (float)y[j];
+        }
+    // tail^2 = ||x||^2 - ||W x||^2, widened by 1e-12 ||x||^2 to cover the
+    // FP64 rounding and the departure of W from exact orthonormality
+    double t2 = s - y2;
+    if (t2 < 0.0) t2 = 0.0;
+    const float tail = __double2float_ru(sqrt(t2 + 1e-12 * s));
+    const float nrm = scale * __double2float_ru(sqrt(s) * (1.0 + 0x1p-40));
+#pragma unroll
+    for (int j = 0; j < DP_MAX + 2; ++j) {
+        if (j == dp) ov[j] = tail;
+        if (j == dp + 1) ov[j] = nrm;
     }
-    if (lane >= dp + 2 && lane < 16) o[lane] = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        reinterpret_cast<float4 *>(o)[q] = make_float4(ov[4 * q], ov[4 * q + 1], ov[4 * q + 2],
+                                                       ov[4 * q + 3]);
 }
 
 void launch_rotate_aug(const float *X, const int32_t *order, int64_t rows, int64_t rows_pad,
                        int d, const double *W, int dp, float scale, float *out,
                        hipStream_t st) {
-    k_rotate_aug<<<(unsigned)((rows_pad + 3) / 4), 256, 0, st>>>(X, order, rows, rows_pad, d,
-                                                                 W, dp, scale, out);
+    k_rotate_aug<<<(unsigned)((rows_pad + 255) / 256), 256, 0, st>>>(X, order, rows, rows_pad,
+                                                                     d, W, dp, scale, out);
 }
 
 }  // namespace rmips

@@ -275,7 +275,7 @@ struct TopnLayout {
     int32_t *cs;
     UserSide us;
     float *Us;
-    double *G, *W;
+    double *G, *Gs, *W;
     float *Pa, *Ua;
     int nsplitB;
     int32_t *partialB, *uscore, *inv;
@@ -305,6 +305,7 @@ void topn_plan(int64_t n, int64_t m, int d, int cap_override, int bmax, TopnLayo
     L.us.uid = cv.take<int32_t>(n);
     L.Us = cv.take<float>((size_t)n * L.T.D);
     L.G = cv.take<double>((size_t)d * d);
+    L.Gs = cv.take<double>(gram_scratch_bytes(d) / sizeof(double));
     L.W = cv.take<double>((size_t)DPRIME * d);
     L.Pa = cv.take<float>((size_t)L.T.mpad * 16);
     L.Ua = cv.take<float>((size_t)n * 16);
@@ -548,7 +549,7 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     launch_gather_padded(L.T.Uk, L.uperm, n, D, L.Us, st);
     const int dp = std::min(DPRIME, d);
     const int64_t ns = std::min<int64_t>(n, GRAM_SAMPLE);
-    launch_gram(U, ns, n / ns, d, L.G, st);
+    launch_gram(U, ns, n / ns, d, L.G, L.Gs, st);
     std::vector<double> G((size_t)d * d), W;
     HIPTRY(hipMemcpyAsync(G.data(), L.G, sizeof(double) * d * d, hipMemcpyDeviceToHost, st));
     HIPTRY(hipStreamSynchronize(st));
@@ -586,8 +587,11 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
                           hipMemcpyHostToDevice, st));
     int64_t r0 = 0, visited = 0, batches = 0, screened = 0, launches = 0;
     float ms_count_k = 0.0f;
+    // First batch: the items with the largest bounds.  After it, the items
+    // that can still enter the top-N are exactly those whose bound reaches
+    // the current N-th score: a prefix of the visit order, scored next.
     int64_t bsz = std::min(bfirst, bmax);
-    while (r0 < m) {
+    while (r0 < m && bsz > 0) {
         const int64_t r1 = std::min<int64_t>(m, r0 + bsz);
         const int64_t nb = r1 - r0;
         int64_t ulen = 0;
@@ -603,13 +607,12 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
             HIPTRY(hipEventRecord(ev[8], st));
             launch_count(a, st);
             HIPTRY(hipEventRecord(ev[9], st));
+            launch_colsum(L.partialC, a.nsplit, nb, L.batch_scores, st);
             ++launches;
         } else {
-            HIPTRY(hipMemsetAsync(L.partialC, 0, sizeof(int32_t) * nb, st));
-            a.nsplit = 1;
+            HIPTRY(hipMemsetAsync(L.batch_scores, 0, sizeof(int32_t) * nb, st));
         }
-        launch_topn_merge(L.partialC, a.nsplit, nb, L.vis_cid + r0, N, L.top, L.status,
-                          L.batch_scores, st);
+        launch_topn_merge(L.batch_scores, nb, L.vis_cid + r0, N, L.top, L.status, st);
         HIPTRY(hipGetLastError());
         HIPTRY(hipMemcpyAsync(ctx->h_status, L.status, 2 * sizeof(int32_t),
                               hipMemcpyDeviceToHost, st));
@@ -624,9 +627,14 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
         screened += nb * ulen;
         const int tauN = ctx->h_status[0];
         r0 = r1;
-        // stop once the next bound is strictly below the current N-th score
-        if (r0 < m && tauN >= 0 && h_us[r0] < tauN) break;
-        bsz = std::min<int64_t>(2 * bsz, bmax);
+        if (tauN < 0) {
+            bsz = bmax;  // fewer than N items seen so far
+            continue;
+        }
+        // items whose bound is strictly below the N-th score cannot enter
+        int64_t e = r0;
+        while (e < m && h_us[e] >= tauN) ++e;
+        bsz = std::min<int64_t>(e - r0, bmax);
     }
     HIPTRY(hipEventRecord(ev[3], st));
     std::vector<uint64_t> top(N);

@@ -66,25 +66,80 @@ __device__ __forceinline__ void merge32_desc(float (&v)[32]) {
     }
 }
 
-size_t thresh_screen_lds_nw(int D, int nw) {
+// Screening configuration: nw waves (32 users each) and nb item-tile
+// buffers in LDS (2 = the next tile loads while the current one is used).
+struct ScreenCfg { int nw, nb, pf; };
+
+size_t thresh_screen_lds_cfg(int D, int nw, int nb) {
     const int ld = D + LDS_PAD;
-    return (size_t)(32 * nw + TILE_ITEMS) * ld * sizeof(float) + TILE_ITEMS * sizeof(float) +
-           32 * nw * sizeof(int) + 16 * sizeof(float);
+    return (size_t)(32 * nw + nb * TILE_ITEMS) * ld * sizeof(float) +
+           nb * TILE_ITEMS * sizeof(float) + 32 * nw * sizeof(int) + 16 * sizeof(float);
 }
 
-int thresh_waves(int D) { return thresh_screen_lds_nw(D, 4) <= 96 * 1024 ? 4 : 2; }
+ScreenCfg screen_cfg(int D) {
+    ScreenCfg c{4, 2, 0};
+    if (thresh_screen_lds_cfg(D, 4, 2) > 96 * 1024) c.nw = 2;
+    if (thresh_screen_lds_cfg(D, c.nw, 2) > 160 * 1024) c.nb = 1;
+    const int need = TILE_ITEMS * (D / 4), nt = 64 * c.nw;
+    if (c.nb == 2) c.pf = (need <= 4 * nt) ? 4 : (need <= 8 * nt) ? 8 : 0;
+    return c;
+}
 
-size_t thresh_screen_lds(int D) { return thresh_screen_lds_nw(D, thresh_waves(D)); }
+size_t thresh_screen_lds(int D) {
+    ScreenCfg c = screen_cfg(D);
+    return thresh_screen_lds_cfg(D, c.nw, c.nb);
+}
 
-template <int NW>
+// Item tile t (64 rows of D floats and their norms) into registers, then
+// into LDS buffer b; or straight into LDS.
+template <int PFN, int NT>
+__device__ __forceinline__ void tile_fetch(float4 (&pf)[PFN], float &pfn, const float *Pk,
+                                           const float *Np, int t, int D, int nvec, int tid) {
+    const float4 *src = reinterpret_cast<const float4 *>(Pk + (int64_t)t * TILE_ITEMS * D);
+#pragma unroll
+    for (int q = 0; q < PFN; ++q) {
+        const int e = tid + q * NT;
+        pf[q] = (e < nvec) ? src[e] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    if (tid < TILE_ITEMS) pfn = Np[(int64_t)t * TILE_ITEMS + tid];
+}
+
+template <int PFN, int NT>
+__device__ __forceinline__ void tile_stash(const float4 (&pf)[PFN], float pfn, float *Pbase,
+                                           float *Nbase, int b, int ld, int D4, int nvec,
+                                           int tid) {
+#pragma unroll
+    for (int q = 0; q < PFN; ++q) {
+        const int e = tid + q * NT;
+        if (e < nvec) {
+            const int r = e / D4, c = e - r * D4;
+            *reinterpret_cast<float4 *>(Pbase + (b * TILE_ITEMS + r) * ld + 4 * c) = pf[q];
+        }
+    }
+    if (tid < TILE_ITEMS) Nbase[b * TILE_ITEMS + tid] = pfn;
+}
+
+template <int NT>
+__device__ __forceinline__ void tile_load(const float *Pk, const float *Np, int t, float *Pbase,
+                                          float *Nbase, int b, int D, int ld, int D4, int nvec,
+                                          int tid) {
+    const float4 *src = reinterpret_cast<const float4 *>(Pk + (int64_t)t * TILE_ITEMS * D);
+    for (int e = tid; e < nvec; e += NT) {
+        const int r = e / D4, c = e - r * D4;
+        *reinterpret_cast<float4 *>(Pbase + (b * TILE_ITEMS + r) * ld + 4 * c) = src[e];
+    }
+    if (tid < TILE_ITEMS) Nbase[b * TILE_ITEMS + tid] = Np[(int64_t)t * TILE_ITEMS + tid];
+}
+
+template <int NW, int PF, int NB>
 __global__ __launch_bounds__(64 * NW) void k_thresh_screen(ThreshArgs a) {
     constexpr int TU = 32 * NW, NT = 64 * NW;
     extern __shared__ float smem[];
     const int D = a.D, ld = D + LDS_PAD, ks = D / 2;
     float *Ush = smem;
-    float *Psh = Ush + TU * ld;
-    float *Npsh = Psh + TILE_ITEMS * ld;
-    int *cntsh = reinterpret_cast<int *>(Npsh + TILE_ITEMS);
+    float *Pbase = Ush + TU * ld;                     // two item tiles
+    float *Nbase = Pbase + NB * TILE_ITEMS * ld;      // their norms
+    int *cntsh = reinterpret_cast<int *>(Nbase + NB * TILE_ITEMS);
     float *red = reinterpret_cast<float *>(cntsh + TU);
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -108,105 +163,123 @@ __global__ __launch_bounds__(64 * NW) void k_thresh_screen(ThreshArgs a) {
     const float cnu = a.c_err * nu;
     const float *Bw = Ush + w * 32 * ld;
 
-    auto load_tile = [&](int t) {
-        const int64_t r0 = (int64_t)t * TILE_ITEMS;
-        const float4 *src = reinterpret_cast<const float4 *>(a.Pk + r0 * D);
-        for (int e = tid; e < TILE_ITEMS * D4; e += NT) {
-            int r = e / D4, c = e - r * D4;
-            *reinterpret_cast<float4 *>(Psh + r * ld + 4 * c) = src[e];
-        }
-        if (tid < TILE_ITEMS) Npsh[tid] = a.Np[r0 + tid];
-    };
+    // tile sequence: phase 1 = tiles 0..t0-1, phase 2 = split, split+nsplit, ...
+    const int t0 = a.t0tiles < a.ntiles ? a.t0tiles : a.ntiles;
+    auto tile_of = [&](int it) { return it < t0 ? it : split + (it - t0) * a.nsplit; };
 
-    // ---------------- phase 1: L0 from slot maxima of the first tiles
+    const int nvec = TILE_ITEMS * D4;
+    constexpr int PFN = PF > 0 ? PF : 1;
+    float4 pf[PFN];
+    float pfn = 0.0f;
+
     float M[32];
 #pragma unroll
     for (int i = 0; i < 32; ++i) M[i] = -INFINITY;
-    const int t0 = a.t0tiles < a.ntiles ? a.t0tiles : a.ntiles;
-    for (int t = 0; t < t0; ++t) {
-        __syncthreads();
-        load_tile(t);
-        __syncthreads();
-        f32x16 acc0 = {0}, acc1 = {0};
-        mfma32x2_f32(acc0, acc1, Psh, Psh + 32 * ld, Bw, ld, ks, lane);
-        const float e = fmaf(cnu, Npsh[0], a.e_abs);  // largest norm of the tile
-        const int64_t rb = (int64_t)t * TILE_ITEMS;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int r = mfma32_row(i, lane);
-            if (rb + r < a.m) M[i] = fmaxf(M[i], acc0[i] - e);
-            if (rb + r + 32 < a.m) M[16 + i] = fmaxf(M[16 + i], acc1[i] - e);
-        }
-    }
-    sort32_desc(M);
-    {
-        float Bv[32];
-#pragma unroll
-        for (int j = 0; j < 32; ++j) Bv[j] = __shfl_xor(M[31 - j], 32);
-#pragma unroll
-        for (int j = 0; j < 32; ++j) M[j] = fmaxf(M[j], Bv[j]);
-        merge32_desc(M);
-    }
-    float L0 = M[0];
-#pragma unroll
-    for (int j = 1; j < 32; ++j)
-        if (j == a.k - 1) L0 = M[j];
-
-    // workgroup exit ratio: stop once the tile's largest norm is below it
-    float rr = INFINITY;
-    if (uvalid) rr = (L0 > 2.0f * a.e_abs && nu > 0.0f)
-                         ? (L0 - 2.0f * a.e_abs) / (nu * a.c_exit) * (1.0f - 0x1p-20f)
-                         : 0.0f;
-    rr = wave_min(rr);
-    if (lane == 0) red[w] = rr;
-    __syncthreads();
-    float rwg = red[0];
-#pragma unroll
-    for (int q = 1; q < NW; ++q) rwg = fminf(rwg, red[q]);
-
-    // ---------------- phase 2: candidates
+    float L0 = -INFINITY, rwg = INFINITY;
     float2 *mycand = a.cand + ((int64_t)ug * a.nsplit + split) * a.cap;
-    for (int t = split; t < a.ntiles; t += a.nsplit) {
-        const float pmax = a.Np[(int64_t)t * TILE_ITEMS];
-        if (pmax < rwg) break;
-        __syncthreads();
-        load_tile(t);
-        __syncthreads();
+    int64_t ntile_p2 = 0;
+
+    if (PF > 0) {
+        tile_fetch<PFN, NT>(pf, pfn, a.Pk, a.Np, 0, D, nvec, tid);
+        tile_stash<PFN, NT>(pf, pfn, Pbase, Nbase, 0, ld, D4, nvec, tid);
+    } else {
+        tile_load<NT>(a.Pk, a.Np, 0, Pbase, Nbase, 0, D, ld, D4, nvec, tid);
+    }
+    __syncthreads();
+    int buf = 0;
+    for (int it = 0;; ++it) {
+        const int t = tile_of(it);
+        if (it >= t0) {
+            if (t >= a.ntiles) break;
+            if (a.Np[(int64_t)t * TILE_ITEMS] < rwg) break;  // Cauchy-Schwarz exit
+            ++ntile_p2;
+        }
+        const int tn = tile_of(it + 1);
+        const bool pre = tn < a.ntiles;
+        if (PF > 0 && pre) tile_fetch<PFN, NT>(pf, pfn, a.Pk, a.Np, tn, D, nvec, tid);
+        const float *Psh = Pbase + buf * TILE_ITEMS * ld;
+        const float *Nsh = Nbase + buf * TILE_ITEMS;
+        const float pmax = Nsh[0];  // largest norm of the tile
         f32x16 acc0 = {0}, acc1 = {0};
         mfma32x2_f32(acc0, acc1, Psh, Psh + 32 * ld, Bw, ld, ks, lane);
-        const float thr = L0 - fmaf(cnu, pmax, a.e_abs);
-        bool any = false;
+        const int64_t rb = (int64_t)t * TILE_ITEMS;
+        if (it < t0) {
+            // phase 1: per-slot maxima of the lower bounds vh - E
+            const float e = fmaf(cnu, pmax, a.e_abs);
 #pragma unroll
-        for (int i = 0; i < 16; ++i) any |= (acc0[i] >= thr) | (acc1[i] >= thr);
-        if (__ballot(any && uvalid) != 0ull) {
-            const int64_t rb = (int64_t)t * TILE_ITEMS;
+            for (int i = 0; i < 16; ++i) {
+                const int r = mfma32_row(i, lane);
+                if (rb + r < a.m) M[i] = fmaxf(M[i], acc0[i] - e);
+                if (rb + r + 32 < a.m) M[16 + i] = fmaxf(M[16 + i], acc1[i] - e);
+            }
+            if (it == t0 - 1) {
+                sort32_desc(M);
+                float Bv[32];
 #pragma unroll
-            for (int i = 0; i < 32; ++i) {
-                const float v = (i < 16) ? acc0[i] : acc1[i - 16];
-                const int r = mfma32_row(i & 15, lane) + ((i < 16) ? 0 : 32);
-                bool p = uvalid && v >= thr && rb + r < a.m;
-                if (__ballot(p) != 0ull && p) {
-                    const float h = v + fmaf(cnu, Npsh[r], a.e_abs);
-                    if (h >= L0) {
-                        int s = atomicAdd(&cntsh[ucol], 1);
-                        if (s < a.cap) mycand[s] = make_float2(v, __int_as_float((int)(rb + r)));
+                for (int j = 0; j < 32; ++j) Bv[j] = __shfl_xor(M[31 - j], 32);
+#pragma unroll
+                for (int j = 0; j < 32; ++j) M[j] = fmaxf(M[j], Bv[j]);
+                merge32_desc(M);
+                L0 = M[0];
+#pragma unroll
+                for (int j = 1; j < 32; ++j)
+                    if (j == a.k - 1) L0 = M[j];
+                // exit ratio: stop once a tile's largest norm is below it
+                float rr = INFINITY;
+                if (uvalid)
+                    rr = (L0 > 2.0f * a.e_abs && nu > 0.0f)
+                             ? (L0 - 2.0f * a.e_abs) / (nu * a.c_exit) * (1.0f - 0x1p-20f)
+                             : 0.0f;
+                rr = wave_min(rr);
+                if (lane == 0) red[w] = rr;
+            }
+        } else {
+            // phase 2: candidates vh + E >= L0
+            const float thr = L0 - fmaf(cnu, pmax, a.e_abs);
+            bool any = false;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) any |= (acc0[i] >= thr) | (acc1[i] >= thr);
+            if (__ballot(any && uvalid) != 0ull) {
+#pragma unroll
+                for (int i = 0; i < 32; ++i) {
+                    const float v = (i < 16) ? acc0[i] : acc1[i - 16];
+                    const int r = mfma32_row(i & 15, lane) + ((i < 16) ? 0 : 32);
+                    const bool p = uvalid && v >= thr && rb + r < a.m;
+                    if (p) {
+                        const float h = v + fmaf(cnu, Nsh[r], a.e_abs);
+                        if (h >= L0) {
+                            int s = atomicAdd(&cntsh[ucol], 1);
+                            if (s < a.cap)
+                                mycand[s] = make_float2(v, __int_as_float((int)(rb + r)));
+                        }
                     }
                 }
             }
         }
+        if (pre) {
+            if (NB == 1) {
+                __syncthreads();  // every wave is done with the only buffer
+                tile_load<NT>(a.Pk, a.Np, tn, Pbase, Nbase, 0, D, ld, D4, nvec, tid);
+            } else if (PF > 0) {
+                tile_stash<PFN, NT>(pf, pfn, Pbase, Nbase, buf ^ 1, ld, D4, nvec, tid);
+            } else {
+                tile_load<NT>(a.Pk, a.Np, tn, Pbase, Nbase, buf ^ 1, D, ld, D4, nvec, tid);
+            }
+        }
+        __syncthreads();
+        if (it == t0 - 1) {
+            rwg = red[0];
+#pragma unroll
+            for (int q = 1; q < NW; ++q) rwg = fminf(rwg, red[q]);
+        }
+        if (NB == 2) buf ^= 1;
     }
     __syncthreads();
     if (tid < TU && ubase + tid < a.n) a.cand_cnt[(ubase + tid) * a.nsplit + split] = cntsh[tid];
     if (a.pairs && tid == 0) {
-        // statistics only: pairs of the tiles this workgroup screened
-        int64_t nt = 0;
-        for (int t = split; t < a.ntiles; t += a.nsplit) {
-            if (a.Np[(int64_t)t * TILE_ITEMS] < rwg) break;
-            int64_t r0 = (int64_t)t * TILE_ITEMS;
-            nt += (a.m - r0 < TILE_ITEMS) ? (a.m - r0) : TILE_ITEMS;
-        }
-        int64_t nu_valid = (a.n - ubase < TU) ? (a.n - ubase) : TU;
-        atomicAdd(a.pairs, (unsigned long long)(nt * nu_valid));
+        // statistics only: pairs of the phase-2 tiles this workgroup screened
+        const int64_t nu_valid = (a.n - ubase < TU) ? (a.n - ubase) : TU;
+        atomicAdd(a.pairs, (unsigned long long)(ntile_p2 * TILE_ITEMS * nu_valid));
     }
 }
 
@@ -379,18 +452,22 @@ __global__ __launch_bounds__(64 * FB_WAVES) void k_thresh_fallback(ThreshArgs a)
 }
 
 void launch_thresh(const ThreshArgs &a, hipStream_t st) {
-    const int nw = thresh_waves(a.D);
-    const int tu = 32 * nw;
+    const ScreenCfg c = screen_cfg(a.D);
+    const int tu = 32 * c.nw;
+    const size_t lds = thresh_screen_lds_cfg(a.D, c.nw, c.nb);
     dim3 g((unsigned)((a.n + tu - 1) / tu), (unsigned)a.nsplit);
     if (a.ev0) (void)hipEventRecord(a.ev0, st);
-    if (nw == 4)
-        k_thresh_screen<4><<<g, 256, thresh_screen_lds_nw(a.D, 4), st>>>(a);
-    else
-        k_thresh_screen<2><<<g, 128, thresh_screen_lds_nw(a.D, 2), st>>>(a);
+    if (c.nw == 4 && c.pf == 4) k_thresh_screen<4, 4, 2><<<g, 256, lds, st>>>(a);
+    else if (c.nw == 4 && c.pf == 8) k_thresh_screen<4, 8, 2><<<g, 256, lds, st>>>(a);
+    else if (c.nw == 4) k_thresh_screen<4, 0, 2><<<g, 256, lds, st>>>(a);
+    else if (c.nb == 2 && c.pf == 4) k_thresh_screen<2, 4, 2><<<g, 128, lds, st>>>(a);
+    else if (c.nb == 2 && c.pf == 8) k_thresh_screen<2, 8, 2><<<g, 128, lds, st>>>(a);
+    else if (c.nb == 2) k_thresh_screen<2, 0, 2><<<g, 128, lds, st>>>(a);
+    else k_thresh_screen<2, 0, 1><<<g, 128, lds, st>>>(a);
     if (a.ev1) (void)hipEventRecord(a.ev1, st);
     const int capT = a.cap * a.nsplit;
-    size_t lds = (size_t)FIN_WAVES * capT * 24;
-    k_thresh_final<<<(unsigned)((a.n + FIN_WAVES - 1) / FIN_WAVES), 256, lds, st>>>(a, capT);
+    const size_t lds_fin = (size_t)FIN_WAVES * capT * 24;
+    k_thresh_final<<<(unsigned)((a.n + FIN_WAVES - 1) / FIN_WAVES), 256, lds_fin, st>>>(a, capT);
     int64_t fb = (a.n + FB_WAVES - 1) / FB_WAVES;
     if (fb > 1024) fb = 1024;
     k_thresh_fallback<<<(unsigned)fb, 64 * FB_WAVES, 0, st>>>(a);
