@@ -2,8 +2,8 @@
 
 Python side of the C ABI in include/rmips.h; see _lib for the calls.
 """
-from ._lib import (EXPORTS, K_MAX, N_MAX, D_MAX, RmipsError, load, scores,
-                   thresholds, topn, topn_workspace)
+from ._lib import (EXPORTS, K_MAX, N_MAX, D_MAX, RmipsError, SoftScore, load,
+                   scores, soft_bwd, soft_fwd, thresholds, topn, topn_workspace)
 
-__all__ = ["EXPORTS", "K_MAX", "N_MAX", "D_MAX", "RmipsError", "load", "scores",
-           "thresholds", "topn", "topn_workspace"]
+__all__ = ["EXPORTS", "K_MAX", "N_MAX", "D_MAX", "RmipsError", "SoftScore", "load",
+           "scores", "soft_bwd", "soft_fwd", "thresholds", "topn", "topn_workspace"]

@@ -221,3 +221,57 @@ def topn(U, P, k, N, prec="fp32", ws=None, cand_cap=None, batch=None):
     lib.rmips_set_batch(ctx, 0, 0)
     _check(ctx, status)
     return ids, sc, st.as_dict()
+
+
+def _soft_args(U, tau, Q, T):
+    U, Q = _dev_f32(U, "U"), _dev_f32(Q, "Q")
+    if tau.dtype != torch.float32 or tau.dim() != 1 or tau.numel() != U.shape[0]:
+        raise ValueError("tau must be a float32 vector with one entry per user")
+    if U.shape[1] != Q.shape[1]:
+        raise ValueError("U and Q must have the same number of columns")
+    return U, tau.contiguous(), Q, float(T)
+
+
+def soft_fwd(U, tau, Q, T):
+    """S[i] = sum_u sigmoid((u . q_i - tau_u) / T), float32 on U's device."""
+    U, tau, Q, T = _soft_args(U, tau, Q, T)
+    n, d = U.shape
+    nq = Q.shape[0]
+    lib = load()
+    ctx = _context(U.device)
+    ws = _workspace(lib.rmips_soft_workspace_size(n, nq, d), U.device)
+    S = torch.empty(nq, dtype=torch.float32, device=U.device)
+    _check(ctx, lib.rmips_soft_fwd(ctx, _ptr(U), n, _ptr(tau), _ptr(Q), nq, d, T, _ptr(ws),
+                                   ws.numel(), _ptr(S)))
+    return S
+
+
+def soft_bwd(U, tau, Q, T, dS):
+    """dQ[i] = dS[i] * sum_u sigmoid'(z_ui) / T * u, float32 on U's device."""
+    U, tau, Q, T = _soft_args(U, tau, Q, T)
+    n, d = U.shape
+    nq = Q.shape[0]
+    dS = dS.to(torch.float32).contiguous()
+    lib = load()
+    ctx = _context(U.device)
+    ws = _workspace(lib.rmips_soft_workspace_size(n, nq, d), U.device)
+    dQ = torch.empty((nq, d), dtype=torch.float32, device=U.device)
+    _check(ctx, lib.rmips_soft_bwd(ctx, _ptr(U), n, _ptr(tau), _ptr(Q), nq, d, T, _ptr(dS),
+                                   _ptr(ws), ws.numel(), _ptr(dQ)))
+    return dQ
+
+
+class SoftScore(torch.autograd.Function):
+    """Relaxed score S(Q) with the library's backward kernel; the gradient
+    flows to Q only (users and thresholds are data)."""
+
+    @staticmethod
+    def forward(ctx, Q, U, tau, T):
+        ctx.save_for_backward(Q, U, tau)
+        ctx.T = float(T)
+        return soft_fwd(U, tau, Q.contiguous(), T)
+
+    @staticmethod
+    def backward(ctx, dS):
+        Q, U, tau = ctx.saved_tensors
+        return soft_bwd(U, tau, Q.contiguous(), ctx.T, dS), None, None, None

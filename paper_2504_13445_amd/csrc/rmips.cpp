@@ -677,17 +677,45 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     return RMIPS_OK;
 }
 
-rmips_status rmips_soft_fwd(rmips_ctx *ctx, const float *, int64_t, const float *,
-                            const float *, int64_t, int32_t, float, void *, size_t, float *) {
-    return fail(ctx, RMIPS_EUNSUPPORTED, "relaxed score not built yet");
+static rmips_status soft_common(rmips_ctx *ctx, const float *U, int64_t n, const float *tau,
+                                const float *Q, int64_t nq, int32_t d, float T, void *ws,
+                                size_t ws_bytes) {
+    if (!ctx) return RMIPS_EINVAL;
+    if (n < 1 || nq < 1 || nq > (int64_t)INT32_MAX / 2 || d < 1 || d > RMIPS_D_MAX)
+        return fail(ctx, RMIPS_EINVAL, "size out of range");
+    if (!(T > 0.0f) || !std::isfinite(T)) return fail(ctx, RMIPS_EINVAL, "T must be > 0");
+    if (!U || !tau || !Q || !ws) return fail(ctx, RMIPS_EINVAL, "null pointer");
+    if (ws_bytes < rmips_soft_workspace_size(n, nq, d))
+        return fail(ctx, RMIPS_EWORKSPACE, "workspace too small");
+    HIPTRY(hipSetDevice(ctx->device));
+    return RMIPS_OK;
 }
 
-rmips_status rmips_soft_bwd(rmips_ctx *ctx, const float *, int64_t, const float *,
-                            const float *, int64_t, int32_t, float, const float *, void *,
-                            size_t, float *) {
-    return fail(ctx, RMIPS_EUNSUPPORTED, "relaxed score not built yet");
+rmips_status rmips_soft_fwd(rmips_ctx *ctx, const float *U, int64_t n, const float *tau,
+                            const float *Q, int64_t nq, int32_t d, float T, void *ws,
+                            size_t ws_bytes, float *S) {
+    rmips_status s = soft_common(ctx, U, n, tau, Q, nq, d, T, ws, ws_bytes);
+    if (s != RMIPS_OK) return s;
+    if (!S) return fail(ctx, RMIPS_EINVAL, "null pointer");
+    launch_soft(U, n, tau, Q, nq, d, T, nullptr, S, nullptr, ws, ctx->stream);
+    HIPTRY(hipGetLastError());
+    return RMIPS_OK;
 }
 
-size_t rmips_soft_workspace_size(int64_t, int64_t, int32_t) { return 0; }
+rmips_status rmips_soft_bwd(rmips_ctx *ctx, const float *U, int64_t n, const float *tau,
+                            const float *Q, int64_t nq, int32_t d, float T, const float *dS,
+                            void *ws, size_t ws_bytes, float *dQ) {
+    rmips_status s = soft_common(ctx, U, n, tau, Q, nq, d, T, ws, ws_bytes);
+    if (s != RMIPS_OK) return s;
+    if (!dS || !dQ) return fail(ctx, RMIPS_EINVAL, "null pointer");
+    launch_soft(U, n, tau, Q, nq, d, T, dS, nullptr, dQ, ws, ctx->stream);
+    HIPTRY(hipGetLastError());
+    return RMIPS_OK;
+}
+
+size_t rmips_soft_workspace_size(int64_t n, int64_t nq, int32_t d) {
+    if (n < 1 || nq < 1 || d < 1 || d > RMIPS_D_MAX) return 0;
+    return soft_ws_bytes(n, nq, d);
+}
 
 }  // extern "C"
