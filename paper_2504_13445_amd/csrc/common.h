@@ -8,6 +8,12 @@ namespace rmips {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+// Screening precisions (values of rmips_prec).
+enum { PREC_FP32 = 0, PREC_BF16 = 1, PREC_FP8 = 2 };
 
 constexpr int WAVE = 64;
 constexpr int KMAX = 32;          // largest k (matches RMIPS_K_MAX)
@@ -21,6 +27,18 @@ constexpr float E_ABS = 0x1p-99f;
 // is fed four k-steps at a time from LDS (one 16-byte read per lane), and
 // each half-wave owns a contiguous half of the row, so D is a multiple of 8.
 __host__ __device__ inline int padded_dim_fp32(int d) { return (d + 7) & ~7; }
+
+// Padded dimensionality and element size per screening precision: each
+// half-wave owns half of the row; a BF16 step takes 8 elements per lane
+// (D multiple of 16), an FP8 step 32 (D multiple of 64).
+__host__ __device__ inline int padded_dim(int prec, int d) {
+    return prec == PREC_FP32 ? (d + 7) & ~7 : prec == PREC_BF16 ? (d + 15) & ~15 : (d + 63) & ~63;
+}
+__host__ __device__ inline int elem_bytes(int prec) {
+    return prec == PREC_FP32 ? 4 : prec == PREC_BF16 ? 2 : 1;
+}
+// LDS row stride in bytes (16 bytes of padding spread the banks).
+__host__ __device__ inline int lds_row_bytes(int prec, int D) { return D * elem_bytes(prec) + 16; }
 
 // Output layout of a 32x32 matrix-core block: lane l holds column (l & 31)
 // and, in register i, row 8*(i/4) + 4*(l/32) + (i%4).
@@ -69,6 +87,152 @@ __device__ __forceinline__ void mfma32x2_f32(f32x16 &acc0, f32x16 &acc1,
             acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av1[q], bv[q], acc1, 0, 0, 0);
         }
     }
+}
+
+// Products over rows of length D held in LDS (byte pointers, row stride ls
+// bytes), for each precision.  As above, half-wave h feeds the dims
+// [h*D/2, (h+1)*D/2) of its row, which pairs the same dims of A and B.
+template <int PREC> struct MM;
+
+template <> struct MM<PREC_FP32> {
+    // acc0 += A0 B^T, acc1 += A1 B^T (32x32 blocks)
+    static __device__ __forceinline__ void rows2(f32x16 &c0, f32x16 &c1, const uint8_t *A0,
+                                                 const uint8_t *A1, const uint8_t *B, int ls,
+                                                 int D, int lane) {
+        const int r = lane & 31, h = lane >> 5, off = r * ls + h * (D / 2) * 4;
+        const float *a0 = reinterpret_cast<const float *>(A0 + off);
+        const float *a1 = reinterpret_cast<const float *>(A1 + off);
+        const float *b = reinterpret_cast<const float *>(B + off);
+        for (int s = 0; s < D / 2; s += 4) {
+            f32x4 x0 = *reinterpret_cast<const f32x4 *>(a0 + s);
+            f32x4 x1 = *reinterpret_cast<const f32x4 *>(a1 + s);
+            f32x4 y = *reinterpret_cast<const f32x4 *>(b + s);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(x0[q], y[q], c0, 0, 0, 0);
+                c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(x1[q], y[q], c1, 0, 0, 0);
+            }
+        }
+    }
+    // acc0 += A B0^T, acc1 += A B1^T
+    static __device__ __forceinline__ void cols2(f32x16 &c0, f32x16 &c1, const uint8_t *A,
+                                                 const uint8_t *B0, const uint8_t *B1, int ls,
+                                                 int D, int lane) {
+        const int r = lane & 31, h = lane >> 5, off = r * ls + h * (D / 2) * 4;
+        const float *a = reinterpret_cast<const float *>(A + off);
+        const float *b0 = reinterpret_cast<const float *>(B0 + off);
+        const float *b1 = reinterpret_cast<const float *>(B1 + off);
+        for (int s = 0; s < D / 2; s += 4) {
+            f32x4 x = *reinterpret_cast<const f32x4 *>(a + s);
+            f32x4 y0 = *reinterpret_cast<const f32x4 *>(b0 + s);
+            f32x4 y1 = *reinterpret_cast<const f32x4 *>(b1 + s);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(x[q], y0[q], c0, 0, 0, 0);
+                c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(x[q], y1[q], c1, 0, 0, 0);
+            }
+        }
+    }
+};
+
+template <> struct MM<PREC_BF16> {
+    static __device__ __forceinline__ void rows2(f32x16 &c0, f32x16 &c1, const uint8_t *A0,
+                                                 const uint8_t *A1, const uint8_t *B, int ls,
+                                                 int D, int lane) {
+        const int r = lane & 31, h = lane >> 5, off = r * ls + h * (D / 2) * 2;
+        const uint8_t *a0 = A0 + off, *a1 = A1 + off, *b = B + off;
+        for (int s = 0; s < D; s += 16) {  // bytes of 8 elements per step
+            bf16x8 x0 = *reinterpret_cast<const bf16x8 *>(a0 + s);
+            bf16x8 x1 = *reinterpret_cast<const bf16x8 *>(a1 + s);
+            bf16x8 y = *reinterpret_cast<const bf16x8 *>(b + s);
+            c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x0, y, c0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x1, y, c1, 0, 0, 0);
+        }
+    }
+    static __device__ __forceinline__ void cols2(f32x16 &c0, f32x16 &c1, const uint8_t *A,
+                                                 const uint8_t *B0, const uint8_t *B1, int ls,
+                                                 int D, int lane) {
+        const int r = lane & 31, h = lane >> 5, off = r * ls + h * (D / 2) * 2;
+        const uint8_t *a = A + off, *b0 = B0 + off, *b1 = B1 + off;
+        for (int s = 0; s < D; s += 16) {
+            bf16x8 x = *reinterpret_cast<const bf16x8 *>(a + s);
+            bf16x8 y0 = *reinterpret_cast<const bf16x8 *>(b0 + s);
+            bf16x8 y1 = *reinterpret_cast<const bf16x8 *>(b1 + s);
+            c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, y0, c0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, y1, c1, 0, 0, 0);
+        }
+    }
+};
+
+template <> struct MM<PREC_FP8> {
+    // OCP e4m3 operands (format code 0), unit block scales (E8M0 127 = 2^0)
+    static __device__ __forceinline__ i32x8 ld32(const uint8_t *p) {
+        i32x4 lo = *reinterpret_cast<const i32x4 *>(p);
+        i32x4 hi = *reinterpret_cast<const i32x4 *>(p + 16);
+        return i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    }
+    static __device__ __forceinline__ void rows2(f32x16 &c0, f32x16 &c1, const uint8_t *A0,
+                                                 const uint8_t *A1, const uint8_t *B, int ls,
+                                                 int D, int lane) {
+        const int r = lane & 31, h = lane >> 5, off = r * ls + h * (D / 2);
+        const uint8_t *a0 = A0 + off, *a1 = A1 + off, *b = B + off;
+        for (int s = 0; s < D / 2; s += 32) {
+            i32x8 x0 = ld32(a0 + s), x1 = ld32(a1 + s), y = ld32(b + s);
+            c0 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x0, y, c0, 0, 0, 0, 0x7f7f7f7f,
+                                                                 0, 0x7f7f7f7f);
+            c1 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x1, y, c1, 0, 0, 0, 0x7f7f7f7f,
+                                                                 0, 0x7f7f7f7f);
+        }
+    }
+    static __device__ __forceinline__ void cols2(f32x16 &c0, f32x16 &c1, const uint8_t *A,
+                                                 const uint8_t *B0, const uint8_t *B1, int ls,
+                                                 int D, int lane) {
+        const int r = lane & 31, h = lane >> 5, off = r * ls + h * (D / 2);
+        const uint8_t *a = A + off, *b0 = B0 + off, *b1 = B1 + off;
+        for (int s = 0; s < D / 2; s += 32) {
+            i32x8 x = ld32(a + s), y0 = ld32(b0 + s), y1 = ld32(b1 + s);
+            c0 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x, y0, c0, 0, 0, 0, 0x7f7f7f7f,
+                                                                 0, 0x7f7f7f7f);
+            c1 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x, y1, c1, 0, 0, 0, 0x7f7f7f7f,
+                                                                 0, 0x7f7f7f7f);
+        }
+    }
+};
+
+// Round to nearest even BF16; returns the bits, q = the value represented.
+__device__ __forceinline__ uint16_t to_bf16(float x, float &q) {
+    uint32_t b = __float_as_uint(x);
+    b += 0x7fffu + ((b >> 16) & 1u);
+    const uint16_t h = (uint16_t)(b >> 16);
+    q = __uint_as_float((uint32_t)h << 16);
+    return h;
+}
+
+// Round to nearest even OCP FP8 e4m3 (bias 7, largest finite 448, no
+// infinities); |y| <= 448 is required.  Returns the byte, q = its value.
+__device__ __forceinline__ uint8_t to_e4m3(float y, float &q) {
+    const float a = fabsf(y);
+    const uint8_t sg = (y < 0.0f) ? 0x80 : 0x00;
+    if (a == 0.0f) {
+        q = 0.0f;
+        return 0;
+    }
+    int e = (int)((__float_as_uint(a) >> 23) & 0xff) - 127;  // floor(log2 a) for normal a
+    if (e < -6) e = -6;                                        // subnormal range: step 2^-9
+    const float step = __uint_as_float((uint32_t)(e - 3 + 127) << 23);
+    float m = rintf(a / step) * step;                          // exact scaling, RNE
+    int em = (int)((__float_as_uint(m) >> 23) & 0xff) - 127;
+    uint8_t code;
+    if (m == 0.0f) {
+        code = 0;
+    } else if (em < -6) {                                      // subnormal: mant * 2^-9
+        code = (uint8_t)(m * 512.0f);
+    } else {
+        const uint32_t mant = (__float_as_uint(m) >> 20) & 0x7u;
+        code = (uint8_t)(((em + 7) << 3) | mant);
+    }
+    q = (y < 0.0f) ? -m : m;
+    return (uint8_t)(sg | code);
 }
 
 // Exact value of u . p: FP64 sum of the exact products of the FP32 inputs,

@@ -31,47 +31,28 @@ __device__ __forceinline__ int half_sum(int x) {
 constexpr int CNT_USERS = 64;            // users per chunk
 constexpr int AMB_CAP = 512;             // deferred FP64 rechecks per workgroup
 
-// Counting configuration: nw waves (32 items each), nb user buffers.
+// Counting configuration: nw waves (32 items each), nb user buffers, pf
+// 16-byte vectors of a user chunk staged per thread.
 struct CountCfg { int nw, nb, pf; };
 
-size_t count_lds_cfg(int D, int nw, int nb) {
-    const int ld = D + LDS_PAD;
-    return (size_t)(32 * nw + nb * CNT_USERS) * ld * sizeof(float) +
-           AMB_CAP * sizeof(int2) + 32 * nw * sizeof(int) + 16;
+size_t count_lds_cfg(int prec, int D, int nw, int nb) {
+    const int ls = lds_row_bytes(prec, D);
+    return (size_t)(32 * nw + nb * CNT_USERS) * ls + AMB_CAP * sizeof(int2) +
+           32 * nw * sizeof(int) + 16;
 }
 
-CountCfg count_cfg(int D) {
+CountCfg count_cfg(int prec, int D) {
     CountCfg c{4, 2, 0};
-    if (count_lds_cfg(D, 4, 2) > 96 * 1024) c.nw = 2;
-    if (count_lds_cfg(D, c.nw, 2) > 160 * 1024) c.nb = 1;
-    const int need = CNT_USERS * (D / 4), nt = 64 * c.nw;
+    if (count_lds_cfg(prec, D, 4, 2) > 96 * 1024) c.nw = 2;
+    if (count_lds_cfg(prec, D, c.nw, 2) > 160 * 1024) c.nb = 1;
+    const int need = CNT_USERS * D * elem_bytes(prec) / 16, nt = 64 * c.nw;
     if (c.nb == 2) c.pf = (need <= 4 * nt) ? 4 : (need <= 8 * nt) ? 8 : 0;
     return c;
 }
 
-size_t count_lds(int D) {
-    CountCfg c = count_cfg(D);
-    return count_lds_cfg(D, c.nw, c.nb);
-}
-
-// Rows A (shared) against two column blocks B0, B1.
-__device__ __forceinline__ void mfma32x2_rows(f32x16 &acc0, f32x16 &acc1, const float *A,
-                                              const float *B0, const float *B1, int ld,
-                                              int ks, int lane) {
-    const int r = lane & 31, h = lane >> 5;
-    const float *a = A + r * ld + h * ks;
-    const float *b0 = B0 + r * ld + h * ks;
-    const float *b1 = B1 + r * ld + h * ks;
-    for (int s = 0; s < ks; s += 4) {
-        f32x4 av = *reinterpret_cast<const f32x4 *>(a + s);
-        f32x4 bv0 = *reinterpret_cast<const f32x4 *>(b0 + s);
-        f32x4 bv1 = *reinterpret_cast<const f32x4 *>(b1 + s);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q], bv0[q], acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q], bv1[q], acc1, 0, 0, 0);
-        }
-    }
+size_t count_lds(int prec, int D) {
+    CountCfg c = count_cfg(prec, D);
+    return count_lds_cfg(prec, D, c.nw, c.nb);
 }
 
 // FP64 decision of one (item row, user) pair by the tie rule.
@@ -87,93 +68,117 @@ __device__ __forceinline__ bool recheck_pair(const CountArgs &a, int64_t row, in
 // Exact count.  For a pair with screened value vh and bound E:
 //   vh - E > tau_hi  =>  v > tau_u           (in S_k(u))
 //   vh + E < tau_lo  =>  v < tau_u           (not in S_k(u))
-// E is taken with the largest item norm of the wave's 32 items, so both
+// E is taken with the largest N, Nh and R of the wave's 32 items, so both
 // tests fold into two per-user thresholds; other pairs are recomputed in
 // FP64 and decided by the tie rule.
-// NW waves of 32 items; NB user buffers; PF float4 of a user chunk staged
-// per thread (0 = chunks are loaded synchronously into LDS).
-template <int NW, int PF, int NB>
+// NW waves of 32 items; NB user buffers; PF 16-byte vectors of a user chunk
+// staged per thread (0 = chunks are loaded synchronously into LDS).
+template <int PREC, int NW, int PF, int NB>
 __global__ __launch_bounds__(64 * NW) void k_count(CountArgs a) {
     constexpr int NT = 64 * NW, CNT_ITEMS = 32 * NW;
-    extern __shared__ float smem[];
-    const int D = a.D, ld = D + LDS_PAD, ks = D / 2, D4 = D / 4;
-    float *Psh = smem;
-    float *Ush0 = Psh + CNT_ITEMS * ld;
-    float *Ush1 = Ush0 + (NB - 1) * CNT_USERS * ld;
-    int2 *amb = reinterpret_cast<int2 *>(Ush0 + NB * CNT_USERS * ld);
+    extern __shared__ __align__(16) uint8_t smem8[];
+    const int D = a.D, ls = lds_row_bytes(PREC, D), w16 = D * elem_bytes(PREC) / 16;
+    uint8_t *Psh = smem8;
+    uint8_t *Ush0 = Psh + CNT_ITEMS * ls;
+    uint8_t *Ush1 = Ush0 + (NB - 1) * CNT_USERS * ls;
+    int2 *amb = reinterpret_cast<int2 *>(Ush0 + NB * CNT_USERS * ls);
     int *cntl = reinterpret_cast<int *>(amb + AMB_CAP);
     int *ambn = cntl + CNT_ITEMS;
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t ib = (int64_t)blockIdx.x * CNT_ITEMS;
     const int split = blockIdx.y;
+    const uint4 *Pq = reinterpret_cast<const uint4 *>(a.Pq);
+    const uint4 *Us = reinterpret_cast<const uint4 *>(a.Us);
 
-    for (int e = tid; e < CNT_ITEMS * D4; e += NT) {
-        int r = e / D4, c = e - r * D4;
+    for (int e = tid; e < CNT_ITEMS * w16; e += NT) {
+        int r = e / w16, c = e - r * w16;
         int64_t it = ib + r;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        uint4 v = make_uint4(0, 0, 0, 0);
         if (it < a.nb) {
             int64_t row = a.rows ? a.rows[it] : it;
-            v = reinterpret_cast<const float4 *>(a.Pk)[row * D4 + c];
+            v = Pq[row * w16 + c];
         }
-        *reinterpret_cast<float4 *>(Psh + r * ld + 4 * c) = v;
+        *reinterpret_cast<uint4 *>(Psh + r * ls + 16 * c) = v;
     }
     if (tid < CNT_ITEMS) cntl[tid] = 0;
     if (tid == 0) *ambn = 0;
 
-    // largest norm among this wave's 32 items; row validity bits
-    float npmax = 0.0f;
+    // largest N, Nh, R among this wave's 32 items; row validity bits; row scales
+    float mn = 0.0f, mh = 0.0f, mr = 0.0f;
     {
         const int64_t it = ib + w * 32 + (lane & 31);
-        if (it < a.nb) npmax = a.Np[a.rows ? a.rows[it] : it];
+        if (it < a.nb) {
+            const int64_t row = a.rows ? a.rows[it] : it;
+            mn = a.Np[row];
+            mh = a.Nhp[row];
+            mr = a.Rp[row];
+        }
 #pragma unroll
-        for (int o = 1; o < 32; o <<= 1) npmax = fmaxf(npmax, __shfl_xor(npmax, o));
+        for (int o = 1; o < 32; o <<= 1) {
+            mn = fmaxf(mn, __shfl_xor(mn, o));
+            mh = fmaxf(mh, __shfl_xor(mh, o));
+            mr = fmaxf(mr, __shfl_xor(mr, o));
+        }
     }
     uint32_t rvalid = 0;
+    float srow[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i)
-        rvalid |= (ib + w * 32 + mfma32_row(i, lane) < a.nb) ? (1u << i) : 0u;
+    for (int i = 0; i < 16; ++i) {
+        const int64_t it = ib + w * 32 + mfma32_row(i, lane);
+        const bool ok = it < a.nb;
+        rvalid |= ok ? (1u << i) : 0u;
+        srow[i] = 1.0f;
+        if (PREC == PREC_FP8 && ok) srow[i] = a.sp[a.rows ? a.rows[it] : it];
+    }
 
     int cnt[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) cnt[i] = 0;
 
     const int64_t nchunks = (a.ulen + CNT_USERS - 1) / CNT_USERS;
-    const int nvec = CNT_USERS * D4;  // float4 per chunk
+    const int nvec = CNT_USERS * w16;  // 16-byte vectors per chunk
     constexpr int PFN = PF > 0 ? PF : 1;
-    int qrow[PFN], qg[PFN], ql[PFN];  // row in chunk, float4 offset in row, LDS offset
+    int qrow[PFN], qg[PFN], ql[PFN];  // row in chunk, vector in row, LDS offset
 #pragma unroll
     for (int q = 0; q < PFN; ++q) {
         const int e = tid + q * NT;
-        const int r = e / D4, c = e - r * D4;
+        const int r = e / w16, c = e - r * w16;
         qrow[q] = (e < nvec) ? r : CNT_USERS;
         qg[q] = c;
-        ql[q] = r * ld + 4 * c;
+        ql[q] = r * ls + 16 * c;
     }
-    float4 pf[PFN];
+    uint4 pf[PFN];
     auto fetch = [&](int64_t ch) {
         const int64_t u0 = ch * CNT_USERS;
 #pragma unroll
         for (int q = 0; q < PFN; ++q) {
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (qrow[q] < CNT_USERS && u0 + qrow[q] < a.ulen)
-                v = reinterpret_cast<const float4 *>(a.Us)[(u0 + qrow[q]) * D4 + qg[q]];
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (qrow[q] < CNT_USERS && u0 + qrow[q] < a.ulen) v = Us[(u0 + qrow[q]) * w16 + qg[q]];
             pf[q] = v;
         }
     };
-    auto stash = [&](float *dst) {
+    auto stash = [&](uint8_t *dst) {
 #pragma unroll
         for (int q = 0; q < PFN; ++q)
-            if (qrow[q] < CNT_USERS) *reinterpret_cast<float4 *>(dst + ql[q]) = pf[q];
+            if (qrow[q] < CNT_USERS) *reinterpret_cast<uint4 *>(dst + ql[q]) = pf[q];
     };
-    auto load_sync = [&](int64_t ch, float *dst) {
+    auto load_sync = [&](int64_t ch, uint8_t *dst) {
         const int64_t u0 = ch * CNT_USERS;
         for (int e = tid; e < nvec; e += NT) {
-            const int r = e / D4, c = e - r * D4;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (u0 + r < a.ulen) v = reinterpret_cast<const float4 *>(a.Us)[(u0 + r) * D4 + c];
-            *reinterpret_cast<float4 *>(dst + r * ld + 4 * c) = v;
+            const int r = e / w16, c = e - r * w16;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (u0 + r < a.ulen) v = Us[(u0 + r) * w16 + c];
+            *reinterpret_cast<uint4 *>(dst + r * ls + 16 * c) = v;
         }
+    };
+    // thresholds of one user column against this wave's items (scaled units)
+    auto thresholds = [&](int64_t us, float &tin, float &tout) {
+        const float nu = a.us.N[us], nhu = a.us.Nh[us], ru = a.us.R[us], su = a.us.s[us];
+        const float e = fmaf(ru, mn, fmaf(nhu, mr, fmaf(a.c_err * nhu, mh, fmaf(a.c2 * nu, mn,
+                                                                                 a.e_abs))));
+        tin = (a.us.tau_hi[us] + e) / su;   // exact: su is a power of two
+        tout = (a.us.tau_lo[us] - e) / su;
     };
 
     int64_t ch = split;
@@ -190,27 +195,21 @@ __global__ __launch_bounds__(64 * NW) void k_count(CountArgs a) {
     for (; ch < nchunks; ch += a.nsplit) {
         const int64_t nxt = ch + a.nsplit;
         if (PF > 0 && nxt < nchunks) fetch(nxt);
-        const float *Ub = buf ? Ush1 : Ush0;
+        const uint8_t *Ub = buf ? Ush1 : Ush0;
         const int64_t us0 = ch * CNT_USERS + (lane & 31), us1 = us0 + 32;
         // a column past the last user is "out" for every row: tout = +inf
         float tin0 = INFINITY, tout0 = INFINITY, tin1 = INFINITY, tout1 = INFINITY;
         const bool c0 = us0 < a.ulen, c1 = us1 < a.ulen;
-        if (c0) {
-            const float e = fmaf(a.us.a[us0], npmax, E_ABS);
-            tin0 = a.us.tau_hi[us0] + e;
-            tout0 = a.us.tau_lo[us0] - e;
-        }
-        if (c1) {
-            const float e = fmaf(a.us.a[us1], npmax, E_ABS);
-            tin1 = a.us.tau_hi[us1] + e;
-            tout1 = a.us.tau_lo[us1] - e;
-        }
+        if (c0) thresholds(us0, tin0, tout0);
+        if (c1) thresholds(us1, tin1, tout1);
         f32x16 acc0 = {0}, acc1 = {0};
-        mfma32x2_rows(acc0, acc1, Psh + w * 32 * ld, Ub, Ub + 32 * ld, ld, ks, lane);
+        // rows: this wave's items (shared); columns: the two user blocks
+        MM<PREC>::cols2(acc0, acc1, Psh + w * 32 * ls, Ub, Ub + 32 * ls, ls, D, lane);
         uint32_t ambm0 = 0, ambm1 = 0;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            const float v0 = acc0[i], v1 = acc1[i];
+            const float v0 = (PREC == PREC_FP8) ? acc0[i] * srow[i] : acc0[i];
+            const float v1 = (PREC == PREC_FP8) ? acc1[i] * srow[i] : acc1[i];
             const bool in0 = v0 > tin0, in1 = v1 > tin1;
             cnt[i] += (in0 ? 1 : 0) + (in1 ? 1 : 0);
             ambm0 |= (!in0 && !(v0 < tout0)) ? (1u << i) : 0u;
@@ -270,16 +269,23 @@ __global__ __launch_bounds__(64 * NW) void k_count(CountArgs a) {
 
 void launch_count(const CountArgs &a, hipStream_t st) {
     if (a.nb <= 0) return;
-    const CountCfg c = count_cfg(a.D);
-    const size_t lds = count_lds_cfg(a.D, c.nw, c.nb);
+    const CountCfg c = count_cfg(a.prec, a.D);
+    const size_t lds = count_lds_cfg(a.prec, a.D, c.nw, c.nb);
     dim3 g((unsigned)((a.nb + 32 * c.nw - 1) / (32 * c.nw)), (unsigned)a.nsplit);
-    if (c.nw == 4 && c.pf == 4) k_count<4, 4, 2><<<g, 256, lds, st>>>(a);
-    else if (c.nw == 4 && c.pf == 8) k_count<4, 8, 2><<<g, 256, lds, st>>>(a);
-    else if (c.nw == 4) k_count<4, 0, 2><<<g, 256, lds, st>>>(a);
-    else if (c.nb == 2 && c.pf == 4) k_count<2, 4, 2><<<g, 128, lds, st>>>(a);
-    else if (c.nb == 2 && c.pf == 8) k_count<2, 8, 2><<<g, 128, lds, st>>>(a);
-    else if (c.nb == 2) k_count<2, 0, 2><<<g, 128, lds, st>>>(a);
-    else k_count<2, 0, 1><<<g, 128, lds, st>>>(a);
+#define RMIPS_COUNT(P)                                                                 \
+    do {                                                                               \
+        if (c.nw == 4 && c.pf == 4) k_count<P, 4, 4, 2><<<g, 256, lds, st>>>(a);       \
+        else if (c.nw == 4 && c.pf == 8) k_count<P, 4, 8, 2><<<g, 256, lds, st>>>(a);  \
+        else if (c.nw == 4) k_count<P, 4, 0, 2><<<g, 256, lds, st>>>(a);               \
+        else if (c.nb == 2 && c.pf == 4) k_count<P, 2, 4, 2><<<g, 128, lds, st>>>(a);  \
+        else if (c.nb == 2 && c.pf == 8) k_count<P, 2, 8, 2><<<g, 128, lds, st>>>(a);  \
+        else if (c.nb == 2) k_count<P, 2, 0, 2><<<g, 128, lds, st>>>(a);               \
+        else k_count<P, 2, 0, 1><<<g, 128, lds, st>>>(a);                              \
+    } while (0)
+    if (a.prec == PREC_FP32) RMIPS_COUNT(PREC_FP32);
+    else if (a.prec == PREC_BF16) RMIPS_COUNT(PREC_BF16);
+    else RMIPS_COUNT(PREC_FP8);
+#undef RMIPS_COUNT
 }
 
 // Eq. (3)/(6) bound count over the users of the item tile's Cauchy-Schwarz

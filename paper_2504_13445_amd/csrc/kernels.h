@@ -26,10 +26,19 @@ void launch_gather_rows(const float *P, const int32_t *perm, const float *norm_b
 // inv[perm[r]] = r
 void launch_invert_perm(const int32_t *perm, int64_t m, int32_t *inv, hipStream_t st);
 
+// Padded, quantized copy of rows (see k_quant): Xq holds rows_pad rows of
+// D elements of the precision's type; group rows share a scale.
+void launch_quant(int prec, const float *X, const int32_t *order, int64_t rows,
+                  int64_t rows_pad, int d, int D, int group, void *Xq, float *N, float *Nh,
+                  float *R, float *sc, unsigned int *rmax, int *flag, hipStream_t st);
+
 // Per-user data of the counting stage, in an order given by `order`
 // (sorted position -> user id; NULL = identity).
 struct UserSide {
-    float *a;        // c_err * ||u|| (FP32)
+    float *N;        // ||u|| rounded up
+    float *Nh;       // ||u_q|| (quantized copy) rounded up
+    float *R;        // ||u - u_q|| rounded up
+    float *s;        // power-of-two scale of the quantized copy
     float *tau_hi;   // tau rounded up to FP32
     float *tau_lo;   // tau rounded down to FP32
     double *tau;     // exact tau
@@ -37,15 +46,15 @@ struct UserSide {
     int32_t *uid;    // user id of this position
 };
 void launch_user_side(const double *tau, const int32_t *tau_id, const float *Nu,
-                      const int32_t *order, int64_t n, float c_err, UserSide out,
-                      hipStream_t st);
+                      const float *Nhu, const float *Ru, const float *su,
+                      const int32_t *order, int64_t n, UserSide out, hipStream_t st);
 // Sort keys of the pruning ratio rho_u = tau_u / ||u|| rounded down to FP32
 // (-inf when tau_u <= 0 or ||u|| = 0), as ascending uint32 keys; val = user id.
 void launch_rho_keys(const double *tau, const float *Nu, int64_t n, uint32_t *key,
                      int32_t *val, hipStream_t st);
-// Xs[r] = Xpad[order[r]] (rows of D floats)
-void launch_gather_padded(const float *Xpad, const int32_t *order, int64_t rows, int D,
-                          float *Xs, hipStream_t st);
+// Y[r] = X[order[r]], rows of row_bytes (a multiple of 16)
+void launch_gather_padded(const void *X, const int32_t *order, int64_t rows, int row_bytes,
+                          void *Y, hipStream_t st);
 // cs[j] = number of sorted ratios rho <= norm[j] * (1 + 2^-18)
 void launch_cs_prefix(const uint32_t *rho_sorted_keys, int64_t n, const float *norm,
                       int64_t m, int32_t *cs, hipStream_t st);
@@ -64,33 +73,47 @@ void launch_rotate_aug(const float *X, const int32_t *order, int64_t rows,
 
 // ---------------------------------------------------------- stage (a)
 struct ThreshArgs {
-    const float *Uk; const float *Nu; int64_t n;
-    const float *Pk; const float *Np; const int32_t *perm; int64_t m; int ntiles;
-    const float *U; const float *P; int d;   // original FP32 rows (recheck)
+    int prec;
+    // users (caller order): quantized rows, N, Nh, R, scale
+    const void *Uq; const float *Nu; const float *Nhu; const float *Ru; const float *su;
+    int64_t n;
+    // items (norm order): quantized rows (ntiles * 64), N, Nh, R, scale per item
+    const void *Pq; const float *Np; const float *Nhp; const float *Rp; const float *sp;
+    const float *tmax_nh; const float *tmax_r;  // per tile maxima of Nh and R
+    const unsigned int *rmax_bits;              // largest R/N over the items
+    const int32_t *perm; int64_t m; int ntiles;
+    const float *U; const float *P; int d;      // original FP32 rows (recheck)
     int D; int k; int t0tiles; int nsplit; int cap;
-    float c_err; float e_abs; float c_exit;
+    float c_err; float c2; float e_abs; float g64;
     float2 *cand; int32_t *cand_cnt; int32_t *flag;
     double *tau; int32_t *tau_id; int32_t *topk;
     unsigned long long *pairs;     // stats: screened pairs (may be NULL)
     hipEvent_t ev0, ev1;           // recorded around the screening kernel (may be NULL)
 };
 void launch_thresh(const ThreshArgs &a, hipStream_t st);
-size_t thresh_screen_lds(int D);
+size_t thresh_screen_lds(int prec, int D);
+// per-tile maxima of Nh and R (64 items per tile)
+void launch_tile_max(const float *Nh, const float *R, int ntiles, float *tmax_nh, float *tmax_r,
+                     hipStream_t st);
 
 // ---------------------------------------------------------- stage (b)/(c)
 struct CountArgs {
-    // items (rows): padded rows gathered through `rows` (NULL = identity)
-    const float *Pk; const float *Np; const int32_t *rows; int64_t nb;
+    int prec;
+    // items (rows): quantized rows gathered through `rows` (NULL = identity),
+    // per row N, Nh, R, scale
+    const void *Pq; const float *Np; const float *Nhp; const float *Rp; const float *sp;
+    const int32_t *rows; int64_t nb;
     const int32_t *item_tie;   // tie id per padded row (NULL = -1: outside P)
     const int32_t *item_orig;  // original row per padded row (NULL = identity)
     const float *Porig;        // original FP32 item rows
-    // users (columns): padded rows, first ulen of them
-    const float *Us; int64_t ulen; UserSide us;
+    // users (columns): quantized rows, first ulen of them
+    const void *Us; int64_t ulen; UserSide us;
     const float *Uorig; int d; int D;
+    float c_err; float c2; float e_abs;
     int nsplit; int32_t *partial; int64_t *rechecks;
 };
 void launch_count(const CountArgs &a, hipStream_t st);
-size_t count_lds(int D);
+size_t count_lds(int prec, int D);
 
 struct BoundArgs {
     const float *Pa; int64_t m;  // augmented item rows (norm order), ld 16

@@ -49,6 +49,139 @@ void launch_rows_prep(const float *X, int64_t rows, int d, int D, float *Xpad, f
                                                             val, flag);
 }
 
+// Padded, quantized copy of rows, 64 rows per block (wave w takes rows w,
+// w+4, ...).  Row r of the output is row order[r] of X (identity if NULL);
+// rows past `rows` are zero.  Rows of a group share one power-of-two scale
+// s (FP8: the smallest with max |x_i| / s <= 448; FP32 and BF16: 1).  Per
+// row: N = ||x||, Nh = ||xq||, R = ||x - xq|| (FP64 sums, rounded up to
+// FP32), sc = s; the largest R/N of the rows goes to *rmax (a monotone
+// atomic maximum of non-negative floats).
+template <int PREC>
+__global__ __launch_bounds__(256) void k_quant(const float *__restrict__ X,
+                                               const int32_t *__restrict__ order, int64_t rows,
+                                               int64_t rows_pad, int d, int D, int group,
+                                               uint8_t *__restrict__ Xq, float *__restrict__ N,
+                                               float *__restrict__ Nh, float *__restrict__ R,
+                                               float *__restrict__ sc,
+                                               unsigned int *__restrict__ rmax,
+                                               int *__restrict__ flag) {
+    __shared__ float rowmax[64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * 64;
+    // pass 1: max |x_i| per row
+    for (int i = w; i < 64; i += 4) {
+        const int64_t r = r0 + i;
+        float mx = 0.0f;
+        if (r < rows) {
+            const float *x = X + (int64_t)(order ? order[r] : r) * d;
+            bool bad = false;
+            for (int c = lane; c < d; c += 64) {
+                const float v = x[c];
+                bad |= !isfinite(v);
+                mx = fmaxf(mx, fabsf(v));
+            }
+            if (__ballot(bad) != 0ull && lane == 0) *flag = 1;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+        if (lane == 0) rowmax[i] = mx;
+    }
+    __syncthreads();
+    // pass 2: quantize with the group's scale, residual sums in FP64
+    for (int i = w; i < 64; i += 4) {
+        const int64_t r = r0 + i;
+        float s = 1.0f;
+        if (PREC == PREC_FP8) {
+            const int g0 = (i / group) * group;
+            float mx = 0.0f;
+            for (int j = g0; j < g0 + group && j < 64; ++j) mx = fmaxf(mx, rowmax[j]);
+            if (mx > 0.0f) {
+                // smallest power of two s with mx / s <= 448
+                int e;
+                frexpf(mx / 448.0f, &e);  // mx/448 = f * 2^e, f in [0.5, 1)
+                s = ldexpf(1.0f, e);
+                if (mx / ldexpf(1.0f, e - 1) <= 448.0f) s = ldexpf(1.0f, e - 1);
+            }
+        }
+        const float inv = 1.0f / s;  // exact: s is a power of two
+        double sx = 0.0, sq = 0.0, sr = 0.0;
+        const float *x = (r < rows) ? X + (int64_t)(order ? order[r] : r) * d : nullptr;
+        for (int c = lane; c < D; c += 64) {
+            const float v = (x && c < d) ? x[c] : 0.0f;
+            float q;
+            if (PREC == PREC_FP32) {
+                q = v;
+                reinterpret_cast<float *>(Xq)[r * D + c] = v;
+            } else if (PREC == PREC_BF16) {
+                reinterpret_cast<uint16_t *>(Xq)[r * D + c] = to_bf16(v, q);
+            } else {
+                float yq;
+                Xq[r * D + c] = to_e4m3(v * inv, yq);
+                q = yq * s;
+            }
+            sx += (double)v * (double)v;
+            sq += (double)q * (double)q;
+            const double df = (double)v - (double)q;  // exact: both are FP32
+            sr += df * df;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            sx += __shfl_xor(sx, o);
+            sq += __shfl_xor(sq, o);
+            sr += __shfl_xor(sr, o);
+        }
+        if (lane == 0 && r < rows_pad) {
+            const double up = 1.0 + 0x1p-40;
+            const float nx = __double2float_ru(sqrt(sx) * up);
+            const float rr = (PREC == PREC_FP32) ? 0.0f : __double2float_ru(sqrt(sr) * up);
+            if (!(nx <= 0x1p60f)) *flag = 1;
+            N[r] = nx;
+            Nh[r] = (PREC == PREC_FP32) ? nx : __double2float_ru(sqrt(sq) * up);
+            R[r] = rr;
+            sc[r] = s;
+            if (rmax && nx > 0.0f) atomicMax(rmax, __float_as_uint(__double2float_ru((double)rr / (double)nx)));
+        }
+    }
+}
+
+void launch_quant(int prec, const float *X, const int32_t *order, int64_t rows,
+                  int64_t rows_pad, int d, int D, int group, void *Xq, float *N, float *Nh,
+                  float *R, float *sc, unsigned int *rmax, int *flag, hipStream_t st) {
+    const unsigned g = (unsigned)((rows_pad + 63) / 64);
+    uint8_t *q = reinterpret_cast<uint8_t *>(Xq);
+    if (prec == PREC_FP32)
+        k_quant<PREC_FP32><<<g, 256, 0, st>>>(X, order, rows, rows_pad, d, D, group, q, N, Nh, R,
+                                              sc, rmax, flag);
+    else if (prec == PREC_BF16)
+        k_quant<PREC_BF16><<<g, 256, 0, st>>>(X, order, rows, rows_pad, d, D, group, q, N, Nh, R,
+                                              sc, rmax, flag);
+    else
+        k_quant<PREC_FP8><<<g, 256, 0, st>>>(X, order, rows, rows_pad, d, D, group, q, N, Nh, R,
+                                             sc, rmax, flag);
+}
+
+__global__ void k_tile_max(const float *__restrict__ Nh, const float *__restrict__ R, int ntiles,
+                           float *__restrict__ tnh, float *__restrict__ tr) {
+    const int lane = threadIdx.x & 63;
+    const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (t >= ntiles) return;
+    float a = Nh[(int64_t)t * 64 + lane], b = R[(int64_t)t * 64 + lane];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a = fmaxf(a, __shfl_xor(a, o));
+        b = fmaxf(b, __shfl_xor(b, o));
+    }
+    if (lane == 0) {
+        tnh[t] = a;
+        tr[t] = b;
+    }
+}
+
+void launch_tile_max(const float *Nh, const float *R, int ntiles, float *tmax_nh, float *tmax_r,
+                     hipStream_t st) {
+    k_tile_max<<<(unsigned)((ntiles + 3) / 4), 256, 0, st>>>(Nh, R, ntiles, tmax_nh, tmax_r);
+}
+
 __global__ void k_gather_rows(const float *__restrict__ P, const int32_t *__restrict__ perm,
                               const float *__restrict__ nb_id, int64_t m, int64_t rows_pad,
                               int d, int D, float *__restrict__ Pk, float *__restrict__ Np) {
@@ -83,13 +216,17 @@ void launch_invert_perm(const int32_t *perm, int64_t m, int32_t *inv, hipStream_
 }
 
 __global__ void k_user_side(const double *__restrict__ tau, const int32_t *__restrict__ tau_id,
-                            const float *__restrict__ Nu, const int32_t *__restrict__ order,
-                            int64_t n, float c_err, UserSide out) {
+                            const float *__restrict__ Nu, const float *__restrict__ Nhu,
+                            const float *__restrict__ Ru, const float *__restrict__ su,
+                            const int32_t *__restrict__ order, int64_t n, UserSide out) {
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
     int64_t u = order ? order[r] : r;
     double t = tau[u];
-    out.a[r] = c_err * Nu[u];
+    out.N[r] = Nu[u];
+    out.Nh[r] = Nhu[u];
+    out.R[r] = Ru[u];
+    out.s[r] = su[u];
     out.tau_hi[r] = __double2float_ru(t);
     out.tau_lo[r] = __double2float_rd(t);
     out.tau[r] = t;
@@ -98,10 +235,10 @@ __global__ void k_user_side(const double *__restrict__ tau, const int32_t *__res
 }
 
 void launch_user_side(const double *tau, const int32_t *tau_id, const float *Nu,
-                      const int32_t *order, int64_t n, float c_err, UserSide out,
-                      hipStream_t st) {
-    k_user_side<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(tau, tau_id, Nu, order, n,
-                                                             c_err, out);
+                      const float *Nhu, const float *Ru, const float *su,
+                      const int32_t *order, int64_t n, UserSide out, hipStream_t st) {
+    k_user_side<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(tau, tau_id, Nu, Nhu, Ru, su, order,
+                                                             n, out);
 }
 
 __global__ void k_rho_keys(const double *__restrict__ tau, const float *__restrict__ Nu,
@@ -122,20 +259,21 @@ void launch_rho_keys(const double *tau, const float *Nu, int64_t n, uint32_t *ke
     k_rho_keys<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(tau, Nu, n, key, val);
 }
 
-__global__ void k_gather_padded(const float *__restrict__ X, const int32_t *__restrict__ order,
-                                int64_t rows, int D4, float *__restrict__ Y) {
+__global__ void k_gather_padded(const uint4 *__restrict__ X, const int32_t *__restrict__ order,
+                                int64_t rows, int W16, uint4 *__restrict__ Y) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= rows * D4) return;
-    int64_t r = e / D4, c = e - r * D4;
-    reinterpret_cast<float4 *>(Y)[e] =
-        reinterpret_cast<const float4 *>(X)[(int64_t)order[r] * D4 + c];
+    if (e >= rows * W16) return;
+    int64_t r = e / W16, c = e - r * W16;
+    Y[e] = X[(int64_t)order[r] * W16 + c];
 }
 
-void launch_gather_padded(const float *Xpad, const int32_t *order, int64_t rows, int D,
-                          float *Xs, hipStream_t st) {
-    int64_t tot = rows * (D / 4);
-    k_gather_padded<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(Xpad, order, rows, D / 4,
-                                                                   Xs);
+// Ys[r] = Xs[order[r]], rows of row_bytes (a multiple of 16)
+void launch_gather_padded(const void *X, const int32_t *order, int64_t rows, int row_bytes,
+                          void *Y, hipStream_t st) {
+    const int W16 = row_bytes / 16;
+    int64_t tot = rows * W16;
+    k_gather_padded<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(
+        reinterpret_cast<const uint4 *>(X), order, rows, W16, reinterpret_cast<uint4 *>(Y));
 }
 
 __global__ void k_cs_prefix(const uint32_t *__restrict__ keys, int64_t n,

@@ -62,22 +62,31 @@ struct Carve {
     }
 };
 
-// FP32 screening error constant: |vh - v| <= c * N_u * N_p + E_ABS, where
-// the matrix-core sum of D terms is bounded by gamma_D with a unit roundoff
-// of 2^-23 (twice round-to-nearest, as the accumulation order and rounding
-// inside the matrix core are not specified), v's own FP64 rounding by
-// d 2^-53, and 8 2^-24 covers the FP32 rounding of the comparisons.
-float fp32_c_err(int D, int d) {
-    double u = std::ldexp(1.0, -23);
-    double gD = D * u / (1.0 - D * u);
-    double g64 = d * std::ldexp(1.0, -53);
-    return (float)((gD + g64 + 8.0 * std::ldexp(1.0, -24)) * (1.0 + std::ldexp(1.0, -16)));
+// Screening error constants: |vh - v| <= R_u N_p + Nh_u R_p + c Nh_u Nh_p +
+// c2 N_u N_p + E_ABS.  c = gamma_D bounds the matrix-core sum of D products
+// with a unit roundoff of 2^-23 (twice round-to-nearest, as the order and
+// rounding inside the matrix core are not specified); c2 covers v's own
+// FP64 rounding (d 2^-53) and the FP32 rounding of the comparisons (8 2^-24).
+struct ErrConst { float c, c2, g64; };
+
+ErrConst err_const(int D, int d) {
+    const double u = std::ldexp(1.0, -23), slack = 1.0 + std::ldexp(1.0, -16);
+    const double g64 = d * std::ldexp(1.0, -53);
+    ErrConst e;
+    e.c = (float)(D * u / (1.0 - D * u) * slack);
+    e.c2 = (float)((g64 + 8.0 * std::ldexp(1.0, -24)) * slack);
+    e.g64 = (float)(g64 * slack);
+    return e;
 }
 
 struct ThreshLayout {
-    int D, ntiles, nsplit, cap;
+    int prec, D, rowb, ntiles, nsplit, cap;
     int64_t mpad;
-    float *Uk, *Nu, *Pk, *Np, *Npid;
+    void *Uq, *Pq;
+    float *Nu, *Nhu, *Ru, *su;          // users, caller order
+    float *Np, *Nhp, *Rp, *sp, *Npid;   // items, norm order (Npid: by id)
+    float *tmax_nh, *tmax_r;
+    unsigned int *rmax;
     uint32_t *keys;
     int32_t *perm;
     void *sort_scratch;
@@ -86,8 +95,11 @@ struct ThreshLayout {
     int *bad;
 };
 
-void thresh_plan(int64_t n, int64_t m, int d, int cap_override, ThreshLayout &L, Carve &cv) {
-    L.D = padded_dim_fp32(d);
+void thresh_plan(int prec, int64_t n, int64_t m, int d, int cap_override, ThreshLayout &L,
+                 Carve &cv) {
+    L.prec = prec;
+    L.D = padded_dim(prec, d);
+    L.rowb = L.D * elem_bytes(prec);
     L.ntiles = (int)((m + TILE_ITEMS - 1) / TILE_ITEMS);
     L.mpad = (int64_t)L.ntiles * TILE_ITEMS;
     int64_t utiles = (n + 127) / 128;
@@ -95,11 +107,22 @@ void thresh_plan(int64_t n, int64_t m, int d, int cap_override, ThreshLayout &L,
     ns = std::max<int64_t>(1, std::min<int64_t>(ns, 8));
     ns = std::min<int64_t>(ns, L.ntiles);
     L.nsplit = (int)ns;
-    L.cap = cap_override > 0 ? cap_override : CAP_DEFAULT;
-    L.Uk = cv.take<float>((size_t)n * L.D);
-    L.Nu = cv.take<float>(n);
-    L.Pk = cv.take<float>((size_t)L.mpad * L.D);
+    L.cap = cap_override > 0 ? cap_override : (prec == RMIPS_FP8_E4M3 ? 4 * CAP_DEFAULT
+                                                                      : CAP_DEFAULT);
+    const int64_t npad = (n + 63) / 64 * 64;
+    L.Uq = cv.take<uint8_t>((size_t)npad * L.rowb);
+    L.Nu = cv.take<float>(npad);
+    L.Nhu = cv.take<float>(npad);
+    L.Ru = cv.take<float>(npad);
+    L.su = cv.take<float>(npad);
+    L.Pq = cv.take<uint8_t>((size_t)L.mpad * L.rowb);
     L.Np = cv.take<float>(L.mpad);
+    L.Nhp = cv.take<float>(L.mpad);
+    L.Rp = cv.take<float>(L.mpad);
+    L.sp = cv.take<float>(L.mpad);
+    L.tmax_nh = cv.take<float>(L.ntiles);
+    L.tmax_r = cv.take<float>(L.ntiles);
+    L.rmax = cv.take<unsigned int>(64);
     L.Npid = cv.take<float>(m);
     L.keys = cv.take<uint32_t>(m);
     L.perm = cv.take<int32_t>(m);
@@ -127,28 +150,33 @@ rmips_status run_thresholds(rmips_ctx *ctx, const float *U, int64_t n, const flo
                             hipEvent_t ev1 = nullptr) {
     hipStream_t st = ctx->stream;
     HIPTRY(hipMemsetAsync(L.bad, 0, sizeof(int), st));
+    HIPTRY(hipMemsetAsync(L.rmax, 0, sizeof(unsigned int), st));
     launch_rows_prep(P, m, d, L.D, nullptr, L.Npid, L.keys, L.perm, L.bad, st);
     HIPTRY(radix_sort_u32(L.keys, L.perm, m, L.sort_scratch, st));
-    launch_gather_rows(P, L.perm, L.Npid, m, L.mpad, d, L.D, L.Pk, L.Np, st);
-    launch_rows_prep(U, n, d, L.D, L.Uk, L.Nu, nullptr, nullptr, L.bad, st);
+    launch_quant(L.prec, P, L.perm, m, L.mpad, d, L.D, TILE_ITEMS, L.Pq, L.Np, L.Nhp, L.Rp,
+                 L.sp, L.rmax, L.bad, st);
+    launch_tile_max(L.Nhp, L.Rp, L.ntiles, L.tmax_nh, L.tmax_r, st);
+    launch_quant(L.prec, U, nullptr, n, n, d, L.D, 1, L.Uq, L.Nu, L.Nhu, L.Ru, L.su, nullptr,
+                 L.bad, st);
     HIPTRY(hipGetLastError());
     rmips_status s = check_bad(ctx, L.bad);
     if (s != RMIPS_OK) return s;
 
+    const ErrConst ec = err_const(L.D, d);
     ThreshArgs a{};
-    a.Uk = L.Uk; a.Nu = L.Nu; a.n = n;
-    a.Pk = L.Pk; a.Np = L.Np; a.perm = L.perm; a.m = m; a.ntiles = L.ntiles;
+    a.prec = L.prec;
+    a.Uq = L.Uq; a.Nu = L.Nu; a.Nhu = L.Nhu; a.Ru = L.Ru; a.su = L.su; a.n = n;
+    a.Pq = L.Pq; a.Np = L.Np; a.Nhp = L.Nhp; a.Rp = L.Rp; a.sp = L.sp;
+    a.tmax_nh = L.tmax_nh; a.tmax_r = L.tmax_r; a.rmax_bits = L.rmax;
+    a.perm = L.perm; a.m = m; a.ntiles = L.ntiles;
     a.U = U; a.P = P; a.d = d;
     a.D = L.D; a.k = k; a.t0tiles = T0_TILES; a.nsplit = L.nsplit; a.cap = L.cap;
-    a.c_err = fp32_c_err(L.D, d);
-    a.e_abs = E_ABS;
-    a.c_exit = (float)(1.0 + d * std::ldexp(1.0, -53) + 2.0 * a.c_err + std::ldexp(1.0, -20));
+    a.c_err = ec.c; a.c2 = ec.c2; a.e_abs = E_ABS; a.g64 = ec.g64;
     a.cand = L.cand; a.cand_cnt = L.cand_cnt; a.flag = L.flag;
     a.tau = tau; a.tau_id = tau_id; a.topk = topk;
     a.pairs = pairs; a.ev0 = ev0; a.ev1 = ev1;
-    size_t lds = thresh_screen_lds(L.D);
-    if (lds > 160 * 1024)
-        return fail(ctx, RMIPS_EUNSUPPORTED, "d too large for the FP32 screening tile");
+    if (thresh_screen_lds(L.prec, L.D) > 160 * 1024 || (size_t)L.cap * L.nsplit * 24 > 150 * 1024)
+        return fail(ctx, RMIPS_EUNSUPPORTED, "screening tile or candidate lists exceed LDS");
     launch_thresh(a, st);
     HIPTRY(hipGetLastError());
     return RMIPS_OK;
@@ -161,8 +189,8 @@ rmips_status validate_common(rmips_ctx *ctx, int64_t n, int64_t m, int d, int k,
     if (m < 1 || m > (int64_t)INT32_MAX / 2) return fail(ctx, RMIPS_EINVAL, "m out of range");
     if (d < 1 || d > RMIPS_D_MAX) return fail(ctx, RMIPS_EINVAL, "d out of range");
     if (k < 1 || k > RMIPS_K_MAX || k > m) return fail(ctx, RMIPS_EINVAL, "k out of range");
-    if (prec != RMIPS_FP32)
-        return fail(ctx, RMIPS_EUNSUPPORTED, "only RMIPS_FP32 screening is built");
+    if (prec != RMIPS_FP32 && prec != RMIPS_BF16 && prec != RMIPS_FP8_E4M3)
+        return fail(ctx, RMIPS_EUNSUPPORTED, "unknown screening precision");
     return RMIPS_OK;
 }
 
@@ -170,12 +198,14 @@ rmips_status validate_common(rmips_ctx *ctx, int64_t n, int64_t m, int d, int k,
 // Rayleigh-Ritz; returns W (dp x d) with orthonormal rows.  Any orthonormal
 // W keeps the Eq. (3) bound valid; the eigenvectors only make it tight.
 void top_eigvecs(const std::vector<double> &G, int d, int dp, std::vector<double> &W) {
-    const int b = std::min(d, dp + 4);
+    const int b = std::min(d, dp + 6);
+    // Q, Z: d x b row-major
     std::vector<double> Q((size_t)d * b), Z((size_t)d * b);
     for (int i = 0; i < d; ++i)
         for (int j = 0; j < b; ++j)
             Q[(size_t)i * b + j] = (i == j) ? 1.0 : std::sin(1.0 + 0.7 * i + 1.3 * j) * 1e-3;
     auto orth = [&](std::vector<double> &X) {
+        // modified Gram-Schmidt over columns, twice for orthogonality to FP64 precision
         for (int pass = 0; pass < 2; ++pass)
             for (int j = 0; j < b; ++j) {
                 for (int q = 0; q < j; ++q) {
@@ -186,29 +216,32 @@ void top_eigvecs(const std::vector<double> &G, int d, int dp, std::vector<double
                 double nrm = 0;
                 for (int i = 0; i < d; ++i) nrm += X[(size_t)i * b + j] * X[(size_t)i * b + j];
                 nrm = std::sqrt(nrm);
-                if (nrm == 0) nrm = 1;
-                for (int i = 0; i < d; ++i) X[(size_t)i * b + j] /= nrm;
+                const double inv = (nrm > 0) ? 1.0 / nrm : 0.0;
+                for (int i = 0; i < d; ++i) X[(size_t)i * b + j] *= inv;
             }
     };
-    orth(Q);
-    for (int it = 0; it < 40; ++it) {
-        for (int i = 0; i < d; ++i)
-            for (int j = 0; j < b; ++j) {
-                double s = 0;
-                for (int l = 0; l < d; ++l) s += G[(size_t)i * d + l] * Q[(size_t)l * b + j];
-                Z[(size_t)i * b + j] = s;
+    auto gmul = [&](const std::vector<double> &X, std::vector<double> &Y) {
+        std::fill(Y.begin(), Y.end(), 0.0);
+        for (int i = 0; i < d; ++i) {
+            double *y = &Y[(size_t)i * b];
+            for (int l = 0; l < d; ++l) {
+                const double g = G[(size_t)i * d + l];
+                const double *x = &X[(size_t)l * b];
+                for (int j = 0; j < b; ++j) y[j] += g * x[j];
             }
+        }
+    };
+    orth(Q);
+    // block power iteration; any orthonormal result keeps the bound valid,
+    // convergence only makes it tighter
+    for (int it = 0; it < 12; ++it) {
+        gmul(Q, Z);
         orth(Z);
         Q.swap(Z);
     }
     // Rayleigh-Ritz: H = Q^T G Q (b x b), Jacobi eigen-decomposition
     std::vector<double> GQ((size_t)d * b), H((size_t)b * b), V((size_t)b * b, 0.0);
-    for (int i = 0; i < d; ++i)
-        for (int j = 0; j < b; ++j) {
-            double s = 0;
-            for (int l = 0; l < d; ++l) s += G[(size_t)i * d + l] * Q[(size_t)l * b + j];
-            GQ[(size_t)i * b + j] = s;
-        }
+    gmul(Q, GQ);
     for (int i = 0; i < b; ++i)
         for (int j = 0; j < b; ++j) {
             double s = 0;
@@ -274,7 +307,7 @@ struct TopnLayout {
     void *usort;
     int32_t *cs;
     UserSide us;
-    float *Us;
+    void *Us;
     double *G, *Gs, *W;
     float *Pa, *Ua;
     int nsplitB;
@@ -288,22 +321,29 @@ struct TopnLayout {
     int64_t *rechecks;
 };
 
-void topn_plan(int64_t n, int64_t m, int d, int cap_override, int bmax, TopnLayout &L,
-               Carve &cv) {
-    thresh_plan(n, m, d, cap_override, L.T, cv);
+void user_side_plan(int64_t n, UserSide &us, Carve &cv) {
+    us.N = cv.take<float>(n);
+    us.Nh = cv.take<float>(n);
+    us.R = cv.take<float>(n);
+    us.s = cv.take<float>(n);
+    us.tau_hi = cv.take<float>(n);
+    us.tau_lo = cv.take<float>(n);
+    us.tau = cv.take<double>(n);
+    us.tau_id = cv.take<int32_t>(n);
+    us.uid = cv.take<int32_t>(n);
+}
+
+void topn_plan(int prec, int64_t n, int64_t m, int d, int cap_override, int bmax,
+               TopnLayout &L, Carve &cv) {
+    thresh_plan(prec, n, m, d, cap_override, L.T, cv);
     L.tau = cv.take<double>(n);
     L.tau_id = cv.take<int32_t>(n);
     L.ukeys = cv.take<uint32_t>(n);
     L.uperm = cv.take<int32_t>(n);
     L.usort = cv.take<uint8_t>(radix_sort_scratch_bytes(std::max(n, m)));
     L.cs = cv.take<int32_t>(L.T.mpad);
-    L.us.a = cv.take<float>(n);
-    L.us.tau_hi = cv.take<float>(n);
-    L.us.tau_lo = cv.take<float>(n);
-    L.us.tau = cv.take<double>(n);
-    L.us.tau_id = cv.take<int32_t>(n);
-    L.us.uid = cv.take<int32_t>(n);
-    L.Us = cv.take<float>((size_t)n * L.T.D);
+    user_side_plan(n, L.us, cv);
+    L.Us = cv.take<uint8_t>((size_t)n * L.T.rowb);
     L.G = cv.take<double>((size_t)d * d);
     L.Gs = cv.take<double>(gram_scratch_bytes(d) / sizeof(double));
     L.W = cv.take<double>((size_t)DPRIME * d);
@@ -393,30 +433,52 @@ rmips_status rmips_set_batch(rmips_ctx *ctx, int32_t first, int32_t max) {
     return RMIPS_OK;
 }
 
+static bool prec_ok(rmips_prec p) {
+    return p == RMIPS_FP32 || p == RMIPS_BF16 || p == RMIPS_FP8_E4M3;
+}
+
 size_t rmips_thresholds_workspace_size(int64_t n, int64_t m, int32_t d, int32_t k,
                                        rmips_prec prec) {
     if (n < 1 || m < 1 || d < 1 || d > RMIPS_D_MAX || k < 1 || k > RMIPS_K_MAX || k > m ||
-        prec != RMIPS_FP32)
+        !prec_ok(prec))
         return 0;
     Carve cv(nullptr);
     ThreshLayout L;
-    thresh_plan(n, m, d, 0, L, cv);
+    thresh_plan(prec, n, m, d, 0, L, cv);
     return cv.off + 256;
 }
 
+struct ScoresLayout {
+    int D, rowb;
+    void *Uq, *Qq;
+    float *Nu, *Nhu, *Ru, *su, *Nq, *Nhq, *Rq, *sq;
+    UserSide us;
+    int32_t *partial;
+    int *bad;
+    int64_t *rech;
+};
+
+void scores_plan(int prec, int64_t n, int64_t nq, int d, ScoresLayout &L, Carve &cv) {
+    L.D = padded_dim(prec, d);
+    L.rowb = L.D * elem_bytes(prec);
+    const int64_t npad = (n + 63) / 64 * 64, qpad = (nq + 63) / 64 * 64;
+    L.Uq = cv.take<uint8_t>((size_t)npad * L.rowb);
+    L.Nu = cv.take<float>(npad); L.Nhu = cv.take<float>(npad);
+    L.Ru = cv.take<float>(npad); L.su = cv.take<float>(npad);
+    L.Qq = cv.take<uint8_t>((size_t)qpad * L.rowb);
+    L.Nq = cv.take<float>(qpad); L.Nhq = cv.take<float>(qpad);
+    L.Rq = cv.take<float>(qpad); L.sq = cv.take<float>(qpad);
+    user_side_plan(n, L.us, cv);
+    L.partial = cv.take<int32_t>((size_t)256 * nq);
+    L.bad = cv.take<int>(64);
+    L.rech = cv.take<int64_t>(8);
+}
+
 size_t rmips_scores_workspace_size(int64_t n, int64_t nq, int32_t d, rmips_prec prec) {
-    if (n < 1 || nq < 1 || d < 1 || d > RMIPS_D_MAX || prec != RMIPS_FP32) return 0;
+    if (n < 1 || nq < 1 || d < 1 || d > RMIPS_D_MAX || !prec_ok(prec)) return 0;
     Carve cv(nullptr);
-    int D = padded_dim_fp32(d);
-    cv.take<float>((size_t)n * D);
-    cv.take<float>(n);
-    cv.take<float>((size_t)nq * D);
-    cv.take<float>(nq);
-    cv.take<float>(n); cv.take<float>(n); cv.take<float>(n);
-    cv.take<double>(n); cv.take<int32_t>(n); cv.take<int32_t>(n);
-    cv.take<int32_t>((size_t)256 * nq);
-    cv.take<int>(64);
-    cv.take<int64_t>(8);
+    ScoresLayout L;
+    scores_plan(prec, n, nq, d, L, cv);
     return cv.off + 256;
 }
 
@@ -427,7 +489,7 @@ size_t rmips_topn_workspace_size(int64_t n, int64_t m, int32_t d, int32_t k, int
         return 0;
     Carve cv(nullptr);
     TopnLayout L;
-    topn_plan(n, m, d, 0, BATCH_MAX, L, cv);
+    topn_plan(prec, n, m, d, 0, BATCH_MAX, L, cv);
     return cv.off + 256;
 }
 
@@ -439,11 +501,11 @@ rmips_status rmips_thresholds(rmips_ctx *ctx, const float *U, int64_t n, const f
     if (!U || !P || !ws || !tau || !tau_id) return fail(ctx, RMIPS_EINVAL, "null pointer");
     Carve probe(nullptr);
     ThreshLayout L;
-    thresh_plan(n, m, d, ctx->cap_override, L, probe);
+    thresh_plan(prec, n, m, d, ctx->cap_override, L, probe);
     if (ws_bytes < probe.off + 256) return fail(ctx, RMIPS_EWORKSPACE, "workspace too small");
     HIPTRY(hipSetDevice(ctx->device));
     Carve cv(ws);
-    thresh_plan(n, m, d, ctx->cap_override, L, cv);
+    thresh_plan(prec, n, m, d, ctx->cap_override, L, cv);
     return run_thresholds(ctx, U, n, P, m, d, k, L, tau, tau_id, topk);
 }
 
@@ -455,45 +517,41 @@ rmips_status rmips_scores(rmips_ctx *ctx, const float *U, int64_t n, const doubl
     if (n < 1 || n > (int64_t)INT32_MAX || nq < 1 || nq > (int64_t)INT32_MAX / 2 || d < 1 ||
         d > RMIPS_D_MAX)
         return fail(ctx, RMIPS_EINVAL, "size out of range");
-    if (prec != RMIPS_FP32) return fail(ctx, RMIPS_EUNSUPPORTED, "only RMIPS_FP32 is built");
+    if (!prec_ok(prec)) return fail(ctx, RMIPS_EUNSUPPORTED, "unknown screening precision");
     if (!U || !tau || !tau_id || !Q || !ws || !scores)
         return fail(ctx, RMIPS_EINVAL, "null pointer");
     if (ws_bytes < rmips_scores_workspace_size(n, nq, d, prec))
         return fail(ctx, RMIPS_EWORKSPACE, "workspace too small");
     HIPTRY(hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
-    const int D = padded_dim_fp32(d);
     Carve cv(ws);
-    float *Uk = cv.take<float>((size_t)n * D);
-    float *Nu = cv.take<float>(n);
-    float *Qk = cv.take<float>((size_t)nq * D);
-    float *Nq = cv.take<float>(nq);
-    UserSide us;
-    us.a = cv.take<float>(n); us.tau_hi = cv.take<float>(n); us.tau_lo = cv.take<float>(n);
-    us.tau = cv.take<double>(n); us.tau_id = cv.take<int32_t>(n); us.uid = cv.take<int32_t>(n);
-    int32_t *partial = cv.take<int32_t>((size_t)256 * nq);
-    int *bad = cv.take<int>(64);
-    int64_t *rech = cv.take<int64_t>(8);
-    HIPTRY(hipMemsetAsync(bad, 0, sizeof(int), st));
-    launch_rows_prep(U, n, d, D, Uk, Nu, nullptr, nullptr, bad, st);
-    launch_rows_prep(Q, nq, d, D, Qk, Nq, nullptr, nullptr, bad, st);
+    ScoresLayout L;
+    scores_plan(prec, n, nq, d, L, cv);
+    HIPTRY(hipMemsetAsync(L.bad, 0, sizeof(int), st));
+    launch_quant(prec, U, nullptr, n, n, d, L.D, 1, L.Uq, L.Nu, L.Nhu, L.Ru, L.su, nullptr,
+                 L.bad, st);
+    launch_quant(prec, Q, nullptr, nq, nq, d, L.D, 1, L.Qq, L.Nq, L.Nhq, L.Rq, L.sq, nullptr,
+                 L.bad, st);
     HIPTRY(hipGetLastError());
     {
-        rmips_status s = check_bad(ctx, bad);
+        rmips_status s = check_bad(ctx, L.bad);
         if (s != RMIPS_OK) return s;
     }
-    const float c_err = fp32_c_err(D, d);
-    launch_user_side(tau, tau_id, Nu, nullptr, n, c_err, us, st);
+    const ErrConst ec = err_const(L.D, d);
+    launch_user_side(tau, tau_id, L.Nu, L.Nhu, L.Ru, L.su, nullptr, n, L.us, st);
     CountArgs a{};
-    a.Pk = Qk; a.Np = Nq; a.rows = nullptr; a.nb = nq;
+    a.prec = prec;
+    a.Pq = L.Qq; a.Np = L.Nq; a.Nhp = L.Nhq; a.Rp = L.Rq; a.sp = L.sq;
+    a.rows = nullptr; a.nb = nq;
     a.item_tie = q_ids; a.item_orig = nullptr; a.Porig = Q;
-    a.Us = Uk; a.ulen = n; a.us = us; a.Uorig = U; a.d = d; a.D = D;
+    a.Us = L.Uq; a.ulen = n; a.us = L.us; a.Uorig = U; a.d = d; a.D = L.D;
+    a.c_err = ec.c; a.c2 = ec.c2; a.e_abs = E_ABS;
     a.nsplit = count_splits(nq, n, 256);
-    a.partial = partial;
-    a.rechecks = rech;
-    HIPTRY(hipMemsetAsync(rech, 0, sizeof(int64_t), st));
+    a.partial = L.partial;
+    a.rechecks = L.rech;
+    HIPTRY(hipMemsetAsync(L.rech, 0, sizeof(int64_t), st));
     launch_count(a, st);
-    launch_colsum(partial, a.nsplit, nq, scores, st);
+    launch_colsum(L.partial, a.nsplit, nq, scores, st);
     HIPTRY(hipGetLastError());
     return RMIPS_OK;
 }
@@ -512,7 +570,7 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     {
         Carve probe(nullptr);
         TopnLayout L0;
-        topn_plan(n, m, d, ctx->cap_override, BATCH_MAX, L0, probe);
+        topn_plan(prec, n, m, d, ctx->cap_override, BATCH_MAX, L0, probe);
         if (ws_bytes < probe.off + 256)
             return fail(ctx, RMIPS_EWORKSPACE, "workspace too small");
     }
@@ -520,9 +578,9 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     hipStream_t st = ctx->stream;
     Carve cv(ws);
     TopnLayout L;
-    topn_plan(n, m, d, ctx->cap_override, BATCH_MAX, L, cv);
+    topn_plan(prec, n, m, d, ctx->cap_override, BATCH_MAX, L, cv);
     const int D = L.T.D;
-    const float c_err = fp32_c_err(D, d);
+    const ErrConst ec = err_const(D, d);
 
     constexpr int NEV = 10;
     hipEvent_t ev[NEV] = {};
@@ -542,17 +600,20 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     HIPTRY(hipEventRecord(ev[1], st));
 
     // ---- stage (c): Cauchy-Schwarz prefix and Eq. (3)/(6) bound counts
-    launch_rho_keys(L.tau, L.T.Nu, n, L.ukeys, L.uperm, st);
-    HIPTRY(radix_sort_u32(L.ukeys, L.uperm, n, L.usort, st));
-    launch_cs_prefix(L.ukeys, n, L.T.Np, m, L.cs, st);
-    launch_user_side(L.tau, L.tau_id, L.T.Nu, L.uperm, n, c_err, L.us, st);
-    launch_gather_padded(L.T.Uk, L.uperm, n, D, L.Us, st);
+    // The rotation's Gram matrix goes to the host first; the host computes
+    // its eigenvectors while the GPU orders the users.
     const int dp = std::min(DPRIME, d);
     const int64_t ns = std::min<int64_t>(n, GRAM_SAMPLE);
     launch_gram(U, ns, n / ns, d, L.G, L.Gs, st);
     std::vector<double> G((size_t)d * d), W;
     HIPTRY(hipMemcpyAsync(G.data(), L.G, sizeof(double) * d * d, hipMemcpyDeviceToHost, st));
-    HIPTRY(hipStreamSynchronize(st));
+    HIPTRY(hipEventRecord(ev[3], st));
+    launch_rho_keys(L.tau, L.T.Nu, n, L.ukeys, L.uperm, st);
+    HIPTRY(radix_sort_u32(L.ukeys, L.uperm, n, L.usort, st));
+    launch_cs_prefix(L.ukeys, n, L.T.Np, m, L.cs, st);
+    launch_user_side(L.tau, L.tau_id, L.T.Nu, L.T.Nhu, L.T.Ru, L.T.su, L.uperm, n, L.us, st);
+    launch_gather_padded(L.T.Uq, L.uperm, n, L.T.rowb, L.Us, st);
+    HIPTRY(hipEventSynchronize(ev[3]));
     top_eigvecs(G, d, dp, W);
     HIPTRY(hipMemcpyAsync(L.W, W.data(), sizeof(double) * dp * d, hipMemcpyHostToDevice, st));
     // slack of the bound: covers FP32 rounding of W x, of the tail and of
@@ -597,9 +658,12 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
         int64_t ulen = 0;
         for (int64_t r = r0; r < r1; ++r) ulen = std::max<int64_t>(ulen, h_cs[r]);
         CountArgs a{};
-        a.Pk = L.T.Pk; a.Np = L.T.Np; a.rows = L.visit + r0; a.nb = nb;
+        a.prec = prec;
+        a.Pq = L.T.Pq; a.Np = L.T.Np; a.Nhp = L.T.Nhp; a.Rp = L.T.Rp; a.sp = L.T.sp;
+        a.rows = L.visit + r0; a.nb = nb;
         a.item_tie = L.T.perm; a.item_orig = L.T.perm; a.Porig = P;
         a.Us = L.Us; a.ulen = ulen; a.us = L.us; a.Uorig = U; a.d = d; a.D = D;
+        a.c_err = ec.c; a.c2 = ec.c2; a.e_abs = E_ABS;
         a.nsplit = count_splits(nb, ulen, L.nsplitC_max);
         a.partial = L.partialC;
         a.rechecks = L.rechecks;

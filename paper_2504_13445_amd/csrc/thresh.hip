@@ -1,11 +1,14 @@
 // Stage (a): tau_u, the k-th largest u . p over all items (Def. 1), exact.
 //
-// Screening.  A workgroup holds 128 users in LDS and streams the items in
-// descending-norm order (Alg. 1 step (1)), 64 per tile, through the FP32
-// matrix cores.  Every screened value vh satisfies |vh - v| <= E(u, p) =
-// c_err * N_u * N_p + e_abs against the exact value v, where N are FP32
-// norms rounded up and c_err bounds the product's accumulation error, the
-// FP64 definition's own rounding, and the rounding of the FP32 comparisons.
+// Screening.  A workgroup holds 32 users per wave in LDS and streams the
+// items in descending-norm order (Alg. 1 step (1)), 64 per tile, through
+// the matrix cores in FP32, BF16 or FP8 (e4m3, a power-of-two scale per
+// user and per item tile).  With N = ||x||, Nh = ||xq|| and R = ||x - xq||
+// of the quantized copies xq (all rounded up), every screened value vh
+// satisfies |vh - v| <= E(u, p) = R_u N_p + Nh_u R_p + c Nh_u Nh_p +
+// c2 N_u N_p + e_abs against the exact value v: the quantisation error by
+// Cauchy-Schwarz, c bounds the matrix-core accumulation, c2 the FP64
+// definition's own rounding and the FP32 comparisons.
 //
 // Phase 1 (first t0 tiles): per lane and register slot the running maximum
 // of the lower bounds vh - E; the k-th largest of the 64 slot maxima of a
@@ -16,7 +19,8 @@
 // v >= tau_u >= L0.  A tile whose largest norm satisfies
 // N_u * N_p * (1 + 2 c) < L0 for every user of the workgroup ends the scan:
 // by Cauchy-Schwarz (Eq. 2) no later item can be a candidate (the early stop
-// of the paper's norm-ordered scan, Sec. 4.2).
+// of the paper's norm-ordered scan, Sec. 4.2); the quantisation terms enter
+// through the largest R_p / N_p over all items.
 // Final: per user, L* = k-th largest lower bound among the candidates (the
 // candidates hold every item whose lower bound reaches L0, so this is the
 // k-th largest over all items), the candidates with vh + E >= L* are
@@ -66,93 +70,116 @@ __device__ __forceinline__ void merge32_desc(float (&v)[32]) {
     }
 }
 
-// Screening configuration: nw waves (32 users each) and nb item-tile
-// buffers in LDS (2 = the next tile loads while the current one is used).
+// Screening configuration: nw waves (32 users each), nb item-tile buffers
+// in LDS (2 = the next tile loads while the current one is used), pf 16-byte
+// vectors of a tile staged per thread (0 = tiles load synchronously).
 struct ScreenCfg { int nw, nb, pf; };
 
-size_t thresh_screen_lds_cfg(int D, int nw, int nb) {
-    const int ld = D + LDS_PAD;
-    return (size_t)(32 * nw + nb * TILE_ITEMS) * ld * sizeof(float) +
-           nb * TILE_ITEMS * sizeof(float) + 32 * nw * sizeof(int) + 16 * sizeof(float);
+size_t thresh_screen_lds_cfg(int prec, int D, int nw, int nb) {
+    const int ls = lds_row_bytes(prec, D);
+    return (size_t)(32 * nw + nb * TILE_ITEMS) * ls + (size_t)nb * 3 * TILE_ITEMS * 4 +
+           32 * nw * sizeof(int) + 16 * sizeof(float);
 }
 
-ScreenCfg screen_cfg(int D) {
+ScreenCfg screen_cfg(int prec, int D) {
     ScreenCfg c{4, 2, 0};
-    if (thresh_screen_lds_cfg(D, 4, 2) > 96 * 1024) c.nw = 2;
-    if (thresh_screen_lds_cfg(D, c.nw, 2) > 160 * 1024) c.nb = 1;
-    const int need = TILE_ITEMS * (D / 4), nt = 64 * c.nw;
+    if (thresh_screen_lds_cfg(prec, D, 4, 2) > 96 * 1024) c.nw = 2;
+    if (thresh_screen_lds_cfg(prec, D, c.nw, 2) > 160 * 1024) c.nb = 1;
+    const int need = TILE_ITEMS * D * elem_bytes(prec) / 16, nt = 64 * c.nw;
     if (c.nb == 2) c.pf = (need <= 4 * nt) ? 4 : (need <= 8 * nt) ? 8 : 0;
     return c;
 }
 
-size_t thresh_screen_lds(int D) {
-    ScreenCfg c = screen_cfg(D);
-    return thresh_screen_lds_cfg(D, c.nw, c.nb);
+size_t thresh_screen_lds(int prec, int D) {
+    ScreenCfg c = screen_cfg(prec, D);
+    return thresh_screen_lds_cfg(prec, D, c.nw, c.nb);
 }
 
-// Item tile t (64 rows of D floats and their norms) into registers, then
-// into LDS buffer b; or straight into LDS.
+// Item tile t (64 rows of D elements, and per item N, Nh, R) into registers,
+// then into LDS buffer b; or straight into LDS.
+struct TileIO {
+    const uint4 *src;   // the tile's rows, 16-byte vectors
+    int nvec;           // 16-byte vectors per tile
+    int w16;            // 16-byte vectors per row
+    int ls;             // LDS row stride (bytes)
+};
+
 template <int PFN, int NT>
-__device__ __forceinline__ void tile_fetch(float4 (&pf)[PFN], float &pfn, const float *Pk,
-                                           const float *Np, int t, int D, int nvec, int tid) {
-    const float4 *src = reinterpret_cast<const float4 *>(Pk + (int64_t)t * TILE_ITEMS * D);
+__device__ __forceinline__ void tile_fetch(uint4 (&pf)[PFN], float (&pn)[3], const ThreshArgs &a,
+                                           const TileIO &io, int t, int tid) {
+    const uint4 *src = io.src + (int64_t)t * io.nvec;
 #pragma unroll
     for (int q = 0; q < PFN; ++q) {
         const int e = tid + q * NT;
-        pf[q] = (e < nvec) ? src[e] : make_float4(0.f, 0.f, 0.f, 0.f);
+        pf[q] = (e < io.nvec) ? src[e] : make_uint4(0, 0, 0, 0);
     }
-    if (tid < TILE_ITEMS) pfn = Np[(int64_t)t * TILE_ITEMS + tid];
+    if (tid < TILE_ITEMS) {
+        const int64_t r = (int64_t)t * TILE_ITEMS + tid;
+        pn[0] = a.Np[r];
+        pn[1] = a.Nhp[r];
+        pn[2] = a.Rp[r];
+    }
 }
 
 template <int PFN, int NT>
-__device__ __forceinline__ void tile_stash(const float4 (&pf)[PFN], float pfn, float *Pbase,
-                                           float *Nbase, int b, int ld, int D4, int nvec,
-                                           int tid) {
+__device__ __forceinline__ void tile_stash(const uint4 (&pf)[PFN], const float (&pn)[3],
+                                           uint8_t *Pbase, float *Nbase, int b,
+                                           const TileIO &io, int tid) {
 #pragma unroll
     for (int q = 0; q < PFN; ++q) {
         const int e = tid + q * NT;
-        if (e < nvec) {
-            const int r = e / D4, c = e - r * D4;
-            *reinterpret_cast<float4 *>(Pbase + (b * TILE_ITEMS + r) * ld + 4 * c) = pf[q];
+        if (e < io.nvec) {
+            const int r = e / io.w16, c = e - r * io.w16;
+            *reinterpret_cast<uint4 *>(Pbase + (b * TILE_ITEMS + r) * io.ls + 16 * c) = pf[q];
         }
     }
-    if (tid < TILE_ITEMS) Nbase[b * TILE_ITEMS + tid] = pfn;
+    if (tid < TILE_ITEMS) {
+        float *nb = Nbase + b * 3 * TILE_ITEMS;
+        nb[tid] = pn[0];
+        nb[TILE_ITEMS + tid] = pn[1];
+        nb[2 * TILE_ITEMS + tid] = pn[2];
+    }
 }
 
 template <int NT>
-__device__ __forceinline__ void tile_load(const float *Pk, const float *Np, int t, float *Pbase,
-                                          float *Nbase, int b, int D, int ld, int D4, int nvec,
-                                          int tid) {
-    const float4 *src = reinterpret_cast<const float4 *>(Pk + (int64_t)t * TILE_ITEMS * D);
-    for (int e = tid; e < nvec; e += NT) {
-        const int r = e / D4, c = e - r * D4;
-        *reinterpret_cast<float4 *>(Pbase + (b * TILE_ITEMS + r) * ld + 4 * c) = src[e];
+__device__ __forceinline__ void tile_load(const ThreshArgs &a, const TileIO &io, int t,
+                                          uint8_t *Pbase, float *Nbase, int b, int tid) {
+    const uint4 *src = io.src + (int64_t)t * io.nvec;
+    for (int e = tid; e < io.nvec; e += NT) {
+        const int r = e / io.w16, c = e - r * io.w16;
+        *reinterpret_cast<uint4 *>(Pbase + (b * TILE_ITEMS + r) * io.ls + 16 * c) = src[e];
     }
-    if (tid < TILE_ITEMS) Nbase[b * TILE_ITEMS + tid] = Np[(int64_t)t * TILE_ITEMS + tid];
+    if (tid < TILE_ITEMS) {
+        const int64_t r = (int64_t)t * TILE_ITEMS + tid;
+        float *nb = Nbase + b * 3 * TILE_ITEMS;
+        nb[tid] = a.Np[r];
+        nb[TILE_ITEMS + tid] = a.Nhp[r];
+        nb[2 * TILE_ITEMS + tid] = a.Rp[r];
+    }
 }
 
-template <int NW, int PF, int NB>
+template <int PREC, int NW, int PF, int NB>
 __global__ __launch_bounds__(64 * NW) void k_thresh_screen(ThreshArgs a) {
     constexpr int TU = 32 * NW, NT = 64 * NW;
-    extern __shared__ float smem[];
-    const int D = a.D, ld = D + LDS_PAD, ks = D / 2;
-    float *Ush = smem;
-    float *Pbase = Ush + TU * ld;                     // two item tiles
-    float *Nbase = Pbase + NB * TILE_ITEMS * ld;      // their norms
-    int *cntsh = reinterpret_cast<int *>(Nbase + NB * TILE_ITEMS);
+    extern __shared__ __align__(16) uint8_t smem8[];
+    const int D = a.D, ls = lds_row_bytes(PREC, D), rowb = D * elem_bytes(PREC);
+    uint8_t *Ush = smem8;
+    uint8_t *Pbase = Ush + TU * ls;                                   // item tiles
+    float *Nbase = reinterpret_cast<float *>(Pbase + NB * TILE_ITEMS * ls);  // N, Nh, R
+    int *cntsh = reinterpret_cast<int *>(Nbase + NB * 3 * TILE_ITEMS);
     float *red = reinterpret_cast<float *>(cntsh + TU);
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t ubase = (int64_t)blockIdx.x * TU;
     const int split = blockIdx.y;
-    const int D4 = D / 4;
+    const int w16 = rowb / 16;
 
-    for (int e = tid; e < TU * D4; e += NT) {
-        int r = e / D4, c = e - r * D4;
+    for (int e = tid; e < TU * w16; e += NT) {
+        int r = e / w16, c = e - r * w16;
         int64_t u = ubase + r;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (u < a.n) v = reinterpret_cast<const float4 *>(a.Uk)[u * D4 + c];
-        *reinterpret_cast<float4 *>(Ush + r * ld + 4 * c) = v;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (u < a.n) v = reinterpret_cast<const uint4 *>(a.Uq)[u * w16 + c];
+        *reinterpret_cast<uint4 *>(Ush + r * ls + 16 * c) = v;
     }
     if (tid < TU) cntsh[tid] = 0;
 
@@ -160,17 +187,29 @@ __global__ __launch_bounds__(64 * NW) void k_thresh_screen(ThreshArgs a) {
     const int64_t ug = ubase + ucol;
     const bool uvalid = ug < a.n;
     const float nu = uvalid ? a.Nu[ug] : 0.0f;
-    const float cnu = a.c_err * nu;
-    const float *Bw = Ush + w * 32 * ld;
+    const float nhu = uvalid ? a.Nhu[ug] : 0.0f;
+    const float ru = uvalid ? a.Ru[ug] : 0.0f;
+    const float su = uvalid ? a.su[ug] : 1.0f;
+    const uint8_t *Bw = Ush + w * 32 * ls;
+    const float rmax = __uint_as_float(*a.rmax_bits);
+
+    // error bound of this user against a tile: E(u,p) <= eu(maxN, maxNh, maxR)
+    auto ebound = [&](float n_p, float nh_p, float r_p) {
+        return fmaf(ru, n_p, fmaf(nhu, r_p, fmaf(a.c_err * nhu, nh_p, fmaf(a.c2 * nu, n_p, a.e_abs))));
+    };
 
     // tile sequence: phase 1 = tiles 0..t0-1, phase 2 = split, split+nsplit, ...
     const int t0 = a.t0tiles < a.ntiles ? a.t0tiles : a.ntiles;
     auto tile_of = [&](int it) { return it < t0 ? it : split + (it - t0) * a.nsplit; };
 
-    const int nvec = TILE_ITEMS * D4;
+    TileIO io;
+    io.src = reinterpret_cast<const uint4 *>(a.Pq);
+    io.w16 = w16;
+    io.nvec = TILE_ITEMS * w16;
+    io.ls = ls;
     constexpr int PFN = PF > 0 ? PF : 1;
-    float4 pf[PFN];
-    float pfn = 0.0f;
+    uint4 pf[PFN];
+    float pn[3] = {0.f, 0.f, 0.f};
 
     float M[32];
 #pragma unroll
@@ -180,10 +219,10 @@ __global__ __launch_bounds__(64 * NW) void k_thresh_screen(ThreshArgs a) {
     int64_t ntile_p2 = 0;
 
     if (PF > 0) {
-        tile_fetch<PFN, NT>(pf, pfn, a.Pk, a.Np, 0, D, nvec, tid);
-        tile_stash<PFN, NT>(pf, pfn, Pbase, Nbase, 0, ld, D4, nvec, tid);
+        tile_fetch<PFN, NT>(pf, pn, a, io, 0, tid);
+        tile_stash<PFN, NT>(pf, pn, Pbase, Nbase, 0, io, tid);
     } else {
-        tile_load<NT>(a.Pk, a.Np, 0, Pbase, Nbase, 0, D, ld, D4, nvec, tid);
+        tile_load<NT>(a, io, 0, Pbase, Nbase, 0, tid);
     }
     __syncthreads();
     int buf = 0;
@@ -196,21 +235,22 @@ __global__ __launch_bounds__(64 * NW) void k_thresh_screen(ThreshArgs a) {
         }
         const int tn = tile_of(it + 1);
         const bool pre = tn < a.ntiles;
-        if (PF > 0 && pre) tile_fetch<PFN, NT>(pf, pfn, a.Pk, a.Np, tn, D, nvec, tid);
-        const float *Psh = Pbase + buf * TILE_ITEMS * ld;
-        const float *Nsh = Nbase + buf * TILE_ITEMS;
-        const float pmax = Nsh[0];  // largest norm of the tile
-        f32x16 acc0 = {0}, acc1 = {0};
-        mfma32x2_f32(acc0, acc1, Psh, Psh + 32 * ld, Bw, ld, ks, lane);
+        if (PF > 0 && pre) tile_fetch<PFN, NT>(pf, pn, a, io, tn, tid);
+        const uint8_t *Psh = Pbase + buf * TILE_ITEMS * ls;
+        const float *Nsh = Nbase + buf * 3 * TILE_ITEMS;
         const int64_t rb = (int64_t)t * TILE_ITEMS;
+        // tile maxima: N is sorted (first item), Nh and R from the precomputed arrays
+        const float e_t = ebound(Nsh[0], a.tmax_nh[t], a.tmax_r[t]);
+        const float sc = su * a.sp[rb];  // product scale of this (user, tile)
+        f32x16 acc0 = {0}, acc1 = {0};
+        MM<PREC>::rows2(acc0, acc1, Psh, Psh + 32 * ls, Bw, ls, D, lane);
         if (it < t0) {
             // phase 1: per-slot maxima of the lower bounds vh - E
-            const float e = fmaf(cnu, pmax, a.e_abs);
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int r = mfma32_row(i, lane);
-                if (rb + r < a.m) M[i] = fmaxf(M[i], acc0[i] - e);
-                if (rb + r + 32 < a.m) M[16 + i] = fmaxf(M[16 + i], acc1[i] - e);
+                if (rb + r < a.m) M[i] = fmaxf(M[i], fmaf(acc0[i], sc, -e_t));
+                if (rb + r + 32 < a.m) M[16 + i] = fmaxf(M[16 + i], fmaf(acc1[i], sc, -e_t));
             }
             if (it == t0 - 1) {
                 sort32_desc(M);
@@ -224,29 +264,34 @@ __global__ __launch_bounds__(64 * NW) void k_thresh_screen(ThreshArgs a) {
 #pragma unroll
                 for (int j = 1; j < 32; ++j)
                     if (j == a.k - 1) L0 = M[j];
-                // exit ratio: stop once a tile's largest norm is below it
+                // exit ratio: vh + E <= K_u * N_p + 2 e_abs for every item p
                 float rr = INFINITY;
-                if (uvalid)
-                    rr = (L0 > 2.0f * a.e_abs && nu > 0.0f)
-                             ? (L0 - 2.0f * a.e_abs) / (nu * a.c_exit) * (1.0f - 0x1p-20f)
+                if (uvalid) {
+                    const float K = nu * (1.0f + a.g64 + 2.0f * a.c2) + 2.0f * ru +
+                                    2.0f * nhu * (rmax + a.c_err * (1.0f + rmax));
+                    rr = (L0 > 2.0f * a.e_abs && K > 0.0f)
+                             ? (L0 - 2.0f * a.e_abs) / K * (1.0f - 0x1p-20f)
                              : 0.0f;
+                }
                 rr = wave_min(rr);
                 if (lane == 0) red[w] = rr;
             }
         } else {
-            // phase 2: candidates vh + E >= L0
-            const float thr = L0 - fmaf(cnu, pmax, a.e_abs);
+            // phase 2: candidates vh + E >= L0, first on the tile bound
+            const float thr = (L0 - e_t) / sc;  // exact: sc is a power of two
             bool any = false;
 #pragma unroll
             for (int i = 0; i < 16; ++i) any |= (acc0[i] >= thr) | (acc1[i] >= thr);
             if (__ballot(any && uvalid) != 0ull) {
 #pragma unroll
                 for (int i = 0; i < 32; ++i) {
-                    const float v = (i < 16) ? acc0[i] : acc1[i - 16];
+                    const float v = ((i < 16) ? acc0[i] : acc1[i - 16]) * sc;
                     const int r = mfma32_row(i & 15, lane) + ((i < 16) ? 0 : 32);
-                    const bool p = uvalid && v >= thr && rb + r < a.m;
+                    const bool p = uvalid && ((i < 16) ? acc0[i] : acc1[i - 16]) >= thr &&
+                                   rb + r < a.m;
                     if (p) {
-                        const float h = v + fmaf(cnu, Nsh[r], a.e_abs);
+                        const float h = v + ebound(Nsh[r], Nsh[TILE_ITEMS + r],
+                                                   Nsh[2 * TILE_ITEMS + r]);
                         if (h >= L0) {
                             int s = atomicAdd(&cntsh[ucol], 1);
                             if (s < a.cap)
@@ -259,11 +304,11 @@ __global__ __launch_bounds__(64 * NW) void k_thresh_screen(ThreshArgs a) {
         if (pre) {
             if (NB == 1) {
                 __syncthreads();  // every wave is done with the only buffer
-                tile_load<NT>(a.Pk, a.Np, tn, Pbase, Nbase, 0, D, ld, D4, nvec, tid);
+                tile_load<NT>(a, io, tn, Pbase, Nbase, 0, tid);
             } else if (PF > 0) {
-                tile_stash<PFN, NT>(pf, pfn, Pbase, Nbase, buf ^ 1, ld, D4, nvec, tid);
+                tile_stash<PFN, NT>(pf, pn, Pbase, Nbase, buf ^ 1, io, tid);
             } else {
-                tile_load<NT>(a.Pk, a.Np, tn, Pbase, Nbase, buf ^ 1, D, ld, D4, nvec, tid);
+                tile_load<NT>(a, io, tn, Pbase, Nbase, buf ^ 1, tid);
             }
         }
         __syncthreads();
@@ -289,7 +334,8 @@ constexpr int FIN_WAVES = 4;
 __global__ __launch_bounds__(256) void k_thresh_final(ThreshArgs a, int capT) {
     extern __shared__ float smem[];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int64_t u = (int64_t)blockIdx.x * FIN_WAVES + w;
+    const int nw = blockDim.x >> 6;  // waves per block (one user each)
+    const int64_t u = (int64_t)blockIdx.x * nw + w;
     const bool valid = u < a.n;
     // per-wave LDS: v64[capT] (double), lo, hi (float), cidx, sid (int)
     uint8_t *base = reinterpret_cast<uint8_t *>(smem) + (size_t)w * capT * 24;
@@ -314,7 +360,8 @@ __global__ __launch_bounds__(256) void k_thresh_final(ThreshArgs a, int capT) {
     }
     const bool work = valid && !over;
     const float nu = valid ? a.Nu[u] : 0.0f;
-    const float cnu = a.c_err * nu;
+    const float nhu = valid ? a.Nhu[u] : 0.0f;
+    const float ru = valid ? a.Ru[u] : 0.0f;
     if (lane == 0) Lstar[w] = -INFINITY;
     if (work) {
         int off = 0;
@@ -324,7 +371,10 @@ __global__ __launch_bounds__(256) void k_thresh_final(ThreshArgs a, int capT) {
             for (int e = lane; e < c; e += 64) {
                 float2 cv = src[e];
                 int idx = __float_as_int(cv.y);
-                float eb = fmaf(cnu, a.Np[idx], a.e_abs);
+                const float eb =
+                    fmaf(ru, a.Np[idx],
+                         fmaf(nhu, a.Rp[idx],
+                              fmaf(a.c_err * nhu, a.Nhp[idx], fmaf(a.c2 * nu, a.Np[idx], a.e_abs))));
                 lo[off + e] = cv.x - eb;
                 hi[off + e] = cv.x + eb;
                 cidx[off + e] = idx;
@@ -452,22 +502,31 @@ __global__ __launch_bounds__(64 * FB_WAVES) void k_thresh_fallback(ThreshArgs a)
 }
 
 void launch_thresh(const ThreshArgs &a, hipStream_t st) {
-    const ScreenCfg c = screen_cfg(a.D);
+    const ScreenCfg c = screen_cfg(a.prec, a.D);
     const int tu = 32 * c.nw;
-    const size_t lds = thresh_screen_lds_cfg(a.D, c.nw, c.nb);
+    const size_t lds = thresh_screen_lds_cfg(a.prec, a.D, c.nw, c.nb);
     dim3 g((unsigned)((a.n + tu - 1) / tu), (unsigned)a.nsplit);
     if (a.ev0) (void)hipEventRecord(a.ev0, st);
-    if (c.nw == 4 && c.pf == 4) k_thresh_screen<4, 4, 2><<<g, 256, lds, st>>>(a);
-    else if (c.nw == 4 && c.pf == 8) k_thresh_screen<4, 8, 2><<<g, 256, lds, st>>>(a);
-    else if (c.nw == 4) k_thresh_screen<4, 0, 2><<<g, 256, lds, st>>>(a);
-    else if (c.nb == 2 && c.pf == 4) k_thresh_screen<2, 4, 2><<<g, 128, lds, st>>>(a);
-    else if (c.nb == 2 && c.pf == 8) k_thresh_screen<2, 8, 2><<<g, 128, lds, st>>>(a);
-    else if (c.nb == 2) k_thresh_screen<2, 0, 2><<<g, 128, lds, st>>>(a);
-    else k_thresh_screen<2, 0, 1><<<g, 128, lds, st>>>(a);
+#define RMIPS_SCREEN(P)                                                                   \
+    do {                                                                                  \
+        if (c.nw == 4 && c.pf == 4) k_thresh_screen<P, 4, 4, 2><<<g, 256, lds, st>>>(a);  \
+        else if (c.nw == 4 && c.pf == 8) k_thresh_screen<P, 4, 8, 2><<<g, 256, lds, st>>>(a); \
+        else if (c.nw == 4) k_thresh_screen<P, 4, 0, 2><<<g, 256, lds, st>>>(a);          \
+        else if (c.nb == 2 && c.pf == 4) k_thresh_screen<P, 2, 4, 2><<<g, 128, lds, st>>>(a); \
+        else if (c.nb == 2 && c.pf == 8) k_thresh_screen<P, 2, 8, 2><<<g, 128, lds, st>>>(a); \
+        else if (c.nb == 2) k_thresh_screen<P, 2, 0, 2><<<g, 128, lds, st>>>(a);          \
+        else k_thresh_screen<P, 2, 0, 1><<<g, 128, lds, st>>>(a);                         \
+    } while (0)
+    if (a.prec == PREC_FP32) RMIPS_SCREEN(PREC_FP32);
+    else if (a.prec == PREC_BF16) RMIPS_SCREEN(PREC_BF16);
+    else RMIPS_SCREEN(PREC_FP8);
+#undef RMIPS_SCREEN
     if (a.ev1) (void)hipEventRecord(a.ev1, st);
     const int capT = a.cap * a.nsplit;
-    const size_t lds_fin = (size_t)FIN_WAVES * capT * 24;
-    k_thresh_final<<<(unsigned)((a.n + FIN_WAVES - 1) / FIN_WAVES), 256, lds_fin, st>>>(a, capT);
+    int fw = (int)((150 * 1024) / ((size_t)capT * 24));  // waves whose lists fit in LDS
+    fw = fw < 1 ? 1 : (fw > FIN_WAVES ? FIN_WAVES : fw);
+    const size_t lds_fin = (size_t)fw * capT * 24;
+    k_thresh_final<<<(unsigned)((a.n + fw - 1) / fw), 64 * fw, lds_fin, st>>>(a, capT);
     int64_t fb = (a.n + FB_WAVES - 1) / FB_WAVES;
     if (fb > 1024) fb = 1024;
     k_thresh_fallback<<<(unsigned)fb, 64 * FB_WAVES, 0, st>>>(a);

@@ -32,6 +32,9 @@ def _g(x):
     return torch.from_numpy(np.ascontiguousarray(x)).to(_dev())
 
 
+PRECS = ["fp32", "bf16", "fp8"]
+
+
 def _check_thresholds(U, P, k, **kw):
     rm = _rm()
     tau, tid, topk = rm.thresholds(_g(U), _g(P), k, with_topk=True, **kw)
@@ -54,31 +57,35 @@ def _check_topn(U, P, k, N, topk_ref=None, **kw):
 
 
 # ------------------------------------------------------------ stage (a)
-def test_thresholds_tiny_workload():
-    _say("thresholds tiny 2000x1000x16 k=10")
+@pytest.mark.parametrize("prec", PRECS)
+def test_thresholds_tiny_workload(prec):
+    _say("thresholds tiny 2000x1000x16 k=10", prec)
     U, P = synth.make_config(0)
-    _check_thresholds(U, P, 10)
+    _check_thresholds(U, P, 10, prec=prec)
 
 
 @pytest.mark.parametrize("n,m,d,k", [(1, 1, 1, 1), (7, 3, 5, 3), (130, 65, 17, 32),
                                      (300, 64, 8, 1), (257, 129, 33, 7), (64, 500, 255, 20),
                                      (1000, 4097, 50, 10)])
-def test_thresholds_shapes(n, m, d, k):
-    _say("thresholds shape", n, m, d, k)
+@pytest.mark.parametrize("prec", PRECS)
+def test_thresholds_shapes(n, m, d, k, prec):
+    _say("thresholds shape", n, m, d, k, prec)
     rng = np.random.default_rng(n * 7 + m)
     U = synth.isotropic(rng, n, d, 0.3)
     P = synth.isotropic(rng, m, d, 0.6)
-    _check_thresholds(U, P, k)
+    _check_thresholds(U, P, k, prec=prec)
 
 
-def test_thresholds_forced_fallback():
-    _say("thresholds forced fallback cap=1")
+@pytest.mark.parametrize("prec", PRECS)
+def test_thresholds_forced_fallback(prec):
+    _say("thresholds forced fallback cap=1", prec)
     U, P = synth.make_config(0, n=600, m=900)
-    _check_thresholds(U, P, 10, cand_cap=1)
+    _check_thresholds(U, P, 10, cand_cap=1, prec=prec)
 
 
-def test_thresholds_ties_and_zeros():
-    _say("thresholds ties")
+@pytest.mark.parametrize("prec", PRECS)
+def test_thresholds_ties_and_zeros(prec):
+    _say("thresholds ties", prec)
     rng = np.random.default_rng(5)
     P = rng.integers(-2, 3, size=(200, 6)).astype(np.float32)
     P[100:150] = P[0:50]          # exact duplicates
@@ -86,7 +93,7 @@ def test_thresholds_ties_and_zeros():
     U = rng.integers(-2, 3, size=(300, 6)).astype(np.float32)
     U[:5] = 0.0                   # zero users: every item ties at 0
     for k in (1, 5, 17):
-        _check_thresholds(U, P, k)
+        _check_thresholds(U, P, k, prec=prec)
 
 
 def test_thresholds_onehot_golden(golden_dir):
@@ -103,33 +110,36 @@ def test_thresholds_onehot_golden(golden_dir):
         assert topk.cpu().numpy().tolist() == e["topk"]
 
 
-def test_thresholds_tiny_magnitudes():
+@pytest.mark.parametrize("prec", PRECS)
+def test_thresholds_tiny_magnitudes(prec):
     # entries in the FP32 subnormal range: the screen's bound must hold
-    _say("thresholds subnormal-range inputs")
+    _say("thresholds subnormal-range inputs", prec)
     rng = np.random.default_rng(8)
     U = (synth.isotropic(rng, 200, 12, 0.3).astype(np.float64) * 1e-20).astype(np.float32)
     P = (synth.isotropic(rng, 300, 12, 0.3).astype(np.float64) * 1e-20).astype(np.float32)
-    _check_thresholds(U, P, 5)
+    _check_thresholds(U, P, 5, prec=prec)
 
 
 # ------------------------------------------------------------ stage (b)
-def test_scores_all_items_equal_histogram():
-    _say("scores of all items, tiny workload")
+@pytest.mark.parametrize("prec", PRECS)
+def test_scores_all_items_equal_histogram(prec):
+    _say("scores of all items, tiny workload", prec)
     U, P = synth.make_config(0)
     rm = _rm()
     k = 10
     t, j, tk = orc.kmips_c(U, P, k)
     Ug = _g(U)
-    tau, tid = rm.thresholds(Ug, _g(P), k)
+    tau, tid = rm.thresholds(Ug, _g(P), k, prec=prec)
     s = rm.scores(Ug, tau, tid, _g(P), torch.arange(P.shape[0], dtype=torch.int32,
-                                                      device=_dev()))
+                                                      device=_dev()), prec=prec)
     h = orc.histogram_scores(tk, P.shape[0])
     assert np.array_equal(s.cpu().numpy(), h)
     assert int(s.sum()) == U.shape[0] * k
 
 
-def test_scores_external_and_duplicate_queries():
-    _say("scores external queries")
+@pytest.mark.parametrize("prec", PRECS)
+def test_scores_external_and_duplicate_queries(prec):
+    _say("scores external queries", prec)
     U, P = synth.make_config(0, n=800, m=300)
     rm = _rm()
     k = 7
@@ -141,15 +151,16 @@ def test_scores_external_and_duplicate_queries():
     qid[10:20] = np.arange(10, 20)        # members of P: tie rule by id
     Q[10:20] = P[10:20]
     ref = orc.reverse_counts_c(U, t, j, Q, qid)
-    s = rm.scores(_g(U), _g(t), _g(j), _g(Q), _g(qid))
+    s = rm.scores(_g(U), _g(t), _g(j), _g(Q), _g(qid), prec=prec)
     assert np.array_equal(s.cpu().numpy(), ref)
 
 
 # ------------------------------------------------------------ top-N
-def test_topn_tiny_workload():
-    _say("topn tiny")
+@pytest.mark.parametrize("prec", PRECS)
+def test_topn_tiny_workload(prec):
+    _say("topn tiny", prec)
     U, P = synth.make_config(0)
-    st = _check_topn(U, P, 10, 10)
+    st = _check_topn(U, P, 10, 10, prec=prec)
     assert st["visited_items"] <= P.shape[0]
 
 
@@ -167,20 +178,22 @@ def test_topn_parameters(k, N):
     _check_topn(U, P, k, N)
 
 
-def test_topn_ties():
-    _say("topn ties")
+@pytest.mark.parametrize("prec", PRECS)
+def test_topn_ties(prec):
+    _say("topn ties", prec)
     rng = np.random.default_rng(6)
     P = rng.integers(-2, 3, size=(120, 5)).astype(np.float32)
     P[60:] = P[:60]
     U = rng.integers(-2, 3, size=(500, 5)).astype(np.float32)
     for k, N in ((3, 10), (8, 60)):
-        _check_topn(U, P, k, N)
+        _check_topn(U, P, k, N, prec=prec)
 
 
-def test_topn_forced_fallback_and_small_batches():
-    _say("topn forced fallback")
+@pytest.mark.parametrize("prec", PRECS)
+def test_topn_forced_fallback_and_small_batches(prec):
+    _say("topn forced fallback", prec)
     U, P = synth.make_config(0, n=700, m=500)
-    _check_topn(U, P, 10, 10, cand_cap=2, batch=(8, 32))
+    _check_topn(U, P, 10, 10, cand_cap=2, batch=(8, 32), prec=prec)
 
 
 # ------------------------------------------------------------ full sizes
@@ -191,20 +204,22 @@ def mf_workload():
     return U, P, t, j, tk
 
 
-def test_mf_thresholds_full(mf_workload):
-    _say("mf thresholds 100000x20000x50")
+@pytest.mark.parametrize("prec", PRECS)
+def test_mf_thresholds_full(mf_workload, prec):
+    _say("mf thresholds 100000x20000x50", prec)
     U, P, t, j, tk = mf_workload
     rm = _rm()
-    tau, tid, topk = rm.thresholds(_g(U), _g(P), 10, with_topk=True)
+    tau, tid, topk = rm.thresholds(_g(U), _g(P), 10, with_topk=True, prec=prec)
     assert np.array_equal(tau.cpu().numpy().view(np.uint64), t.view(np.uint64))
     assert np.array_equal(tid.cpu().numpy(), j)
     assert np.array_equal(topk.cpu().numpy(), tk)
 
 
-def test_mf_topn_full(mf_workload):
-    _say("mf topn 100000x20000x50 k=10 N=10")
+@pytest.mark.parametrize("prec", PRECS)
+def test_mf_topn_full(mf_workload, prec):
+    _say("mf topn 100000x20000x50 k=10 N=10", prec)
     U, P, t, j, tk = mf_workload
     h = orc.histogram_scores(tk, P.shape[0])
     assert h.sum() == U.shape[0] * 10
-    st = _check_topn(U, P, 10, 10, topk_ref=tk)
+    st = _check_topn(U, P, 10, 10, topk_ref=tk, prec=prec)
     print("stats", st, flush=True)
