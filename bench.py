@@ -140,6 +140,8 @@ def main():
         "visited_items": avg("visited_items"), "batches": avg("batches"),
         "thresh_pairs": avg("thresh_pairs"), "count_pairs": avg("count_pairs"),
         "bound_pairs": avg("bound_pairs"), "recheck_pairs": avg("recheck_pairs"),
+        "cand_pairs": avg("cand_pairs"), "overflow_users": avg("overflow_users"),
+        "refine_users": avg("refine_users"),
         "top_ids": ids.tolist(), "top_scores": sc.tolist(),
     }
     if not args.no_cpu_baseline:

@@ -74,8 +74,10 @@ typedef struct rmips_ctx rmips_ctx;
 typedef struct {
     int64_t visited_items;    /* items whose exact score was computed */
     int64_t batches;          /* bound-ordered batches run */
-    int64_t cand_pairs;       /* stage (a): candidates rechecked in FP64 */
+    int64_t cand_pairs;       /* stage (a): candidates rechecked in FP64 (survivors) */
     int64_t overflow_users;   /* stage (a): users sent to the exact fallback */
+    int64_t refine_users;     /* stage (a): users screened again with a tighter
+                                 bound after their candidate lists overflowed */
     int64_t recheck_pairs;    /* stage (b): ambiguous pairs rechecked in FP64 */
     int64_t screened_pairs;   /* stage (a)+(b): pairs through the matrix cores */
     int64_t bound_pairs;      /* stage (c): pairs evaluated by the Eq. 3 bound */

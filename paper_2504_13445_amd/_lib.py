@@ -39,6 +39,7 @@ class RmipsError(RuntimeError):
 class Stats(ctypes.Structure):
     _fields_ = [("visited_items", ctypes.c_int64), ("batches", ctypes.c_int64),
                 ("cand_pairs", ctypes.c_int64), ("overflow_users", ctypes.c_int64),
+                ("refine_users", ctypes.c_int64),
                 ("recheck_pairs", ctypes.c_int64), ("screened_pairs", ctypes.c_int64),
                 ("bound_pairs", ctypes.c_int64), ("thresh_pairs", ctypes.c_int64),
                 ("count_pairs", ctypes.c_int64), ("count_launches", ctypes.c_int64),

@@ -199,6 +199,138 @@ template <> struct MM<PREC_FP8> {
     }
 };
 
+// Same products with the stationary operand held in registers: each lane's
+// half row as NCH 16-byte chunks (FP32: 4 elements, BF16: 8, FP8: 16);
+// nch <= NCH chunks are used.  rows2: c0 += A0 B^T, c1 += A1 B^T with B in
+// registers; cols2: c0 += A B0^T, c1 += A B1^T with A in registers.
+template <int PREC, int NCH> struct MMR;
+
+template <int NCH> struct MMR<PREC_FP32, NCH> {
+    static __device__ __forceinline__ void rows2(f32x16 &c0, f32x16 &c1, const uint8_t *A0,
+                                                 const uint8_t *A1, const uint4 (&b)[NCH],
+                                                 int ls, int nch, int D, int lane) {
+        const int off = (lane & 31) * ls + (lane >> 5) * (D / 2) * 4;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            if (c < nch) {
+            const f32x4 x0 = *reinterpret_cast<const f32x4 *>(A0 + off + 16 * c);
+            const f32x4 x1 = *reinterpret_cast<const f32x4 *>(A1 + off + 16 * c);
+            const float y[4] = {__uint_as_float(b[c].x), __uint_as_float(b[c].y),
+                                __uint_as_float(b[c].z), __uint_as_float(b[c].w)};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(x0[q], y[q], c0, 0, 0, 0);
+                c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(x1[q], y[q], c1, 0, 0, 0);
+            }
+            }
+        }
+    }
+    static __device__ __forceinline__ void cols2(f32x16 &c0, f32x16 &c1, const uint4 (&a)[NCH],
+                                                 const uint8_t *B0, const uint8_t *B1, int ls,
+                                                 int nch, int D, int lane) {
+        const int off = (lane & 31) * ls + (lane >> 5) * (D / 2) * 4;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            if (c < nch) {
+            const f32x4 y0 = *reinterpret_cast<const f32x4 *>(B0 + off + 16 * c);
+            const f32x4 y1 = *reinterpret_cast<const f32x4 *>(B1 + off + 16 * c);
+            const float x[4] = {__uint_as_float(a[c].x), __uint_as_float(a[c].y),
+                                __uint_as_float(a[c].z), __uint_as_float(a[c].w)};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(x[q], y0[q], c0, 0, 0, 0);
+                c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(x[q], y1[q], c1, 0, 0, 0);
+            }
+            }
+        }
+    }
+};
+
+template <int NCH> struct MMR<PREC_BF16, NCH> {
+    static __device__ __forceinline__ bf16x8 as_bf(const uint4 &v) {
+        return __builtin_bit_cast(bf16x8, v);
+    }
+    static __device__ __forceinline__ void rows2(f32x16 &c0, f32x16 &c1, const uint8_t *A0,
+                                                 const uint8_t *A1, const uint4 (&b)[NCH],
+                                                 int ls, int nch, int D, int lane) {
+        const int off = (lane & 31) * ls + (lane >> 5) * (D / 2) * 2;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            if (c < nch) {
+            const bf16x8 x0 = *reinterpret_cast<const bf16x8 *>(A0 + off + 16 * c);
+            const bf16x8 x1 = *reinterpret_cast<const bf16x8 *>(A1 + off + 16 * c);
+            c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x0, as_bf(b[c]), c0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x1, as_bf(b[c]), c1, 0, 0, 0);
+            }
+        }
+    }
+    static __device__ __forceinline__ void cols2(f32x16 &c0, f32x16 &c1, const uint4 (&a)[NCH],
+                                                 const uint8_t *B0, const uint8_t *B1, int ls,
+                                                 int nch, int D, int lane) {
+        const int off = (lane & 31) * ls + (lane >> 5) * (D / 2) * 2;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            if (c < nch) {
+            const bf16x8 y0 = *reinterpret_cast<const bf16x8 *>(B0 + off + 16 * c);
+            const bf16x8 y1 = *reinterpret_cast<const bf16x8 *>(B1 + off + 16 * c);
+            c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(a[c]), y0, c0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(a[c]), y1, c1, 0, 0, 0);
+            }
+        }
+    }
+};
+
+template <int NCH> struct MMR<PREC_FP8, NCH> {
+    static __device__ __forceinline__ i32x8 pair(const uint4 &lo, const uint4 &hi) {
+        return i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w,
+                     (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+    }
+    static __device__ __forceinline__ void rows2(f32x16 &c0, f32x16 &c1, const uint8_t *A0,
+                                                 const uint8_t *A1, const uint4 (&b)[NCH],
+                                                 int ls, int nch, int D, int lane) {
+        const int off = (lane & 31) * ls + (lane >> 5) * (D / 2);
+#pragma unroll
+        for (int c = 0; c + 1 < NCH; c += 2) {
+            if (c < nch) {
+            const i32x8 x0 = MM<PREC_FP8>::ld32(A0 + off + 16 * c);
+            const i32x8 x1 = MM<PREC_FP8>::ld32(A1 + off + 16 * c);
+            const i32x8 y = pair(b[c], b[c + 1]);
+            c0 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x0, y, c0, 0, 0, 0, 0x7f7f7f7f,
+                                                                 0, 0x7f7f7f7f);
+            c1 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x1, y, c1, 0, 0, 0, 0x7f7f7f7f,
+                                                                 0, 0x7f7f7f7f);
+            }
+        }
+    }
+    static __device__ __forceinline__ void cols2(f32x16 &c0, f32x16 &c1, const uint4 (&a)[NCH],
+                                                 const uint8_t *B0, const uint8_t *B1, int ls,
+                                                 int nch, int D, int lane) {
+        const int off = (lane & 31) * ls + (lane >> 5) * (D / 2);
+#pragma unroll
+        for (int c = 0; c + 1 < NCH; c += 2) {
+            if (c < nch) {
+            const i32x8 x = pair(a[c], a[c + 1]);
+            const i32x8 y0 = MM<PREC_FP8>::ld32(B0 + off + 16 * c);
+            const i32x8 y1 = MM<PREC_FP8>::ld32(B1 + off + 16 * c);
+            c0 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x, y0, c0, 0, 0, 0, 0x7f7f7f7f,
+                                                                 0, 0x7f7f7f7f);
+            c1 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x, y1, c1, 0, 0, 0, 0x7f7f7f7f,
+                                                                 0, 0x7f7f7f7f);
+            }
+        }
+    }
+};
+
+// Load this lane's half row (nch 16-byte chunks) of row `row` of a
+// quantized array with rows of rowb bytes; zeros when row is invalid.
+template <int NCH>
+__device__ __forceinline__ void load_half_row(uint4 (&r)[NCH], const uint8_t *X, int64_t row,
+                                              bool valid, int rowb, int nch, int lane) {
+    const uint4 *src = reinterpret_cast<const uint4 *>(X + row * rowb + (lane >> 5) * (rowb / 2));
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) r[c] = (valid && c < nch) ? src[c] : make_uint4(0, 0, 0, 0);
+}
+
 // Round to nearest even BF16; returns the bits, q = the value represented.
 __device__ __forceinline__ uint16_t to_bf16(float x, float &q) {
     uint32_t b = __float_as_uint(x);

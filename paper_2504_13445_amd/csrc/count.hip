@@ -24,36 +24,34 @@ __device__ __forceinline__ int half_sum(int x) {
     return x;
 }
 
-// Counting workgroup: NW waves, each owning 32 items (the row operand,
-// kept in LDS for the whole kernel); users stream through LDS 64 at a time
+// Counting workgroup: 4 waves, each owning 32 items (the row operand, kept
+// in registers for the whole kernel); users stream through LDS 64 at a time
 // (two column blocks), double-buffered where LDS allows, so the next chunk
 // loads while the current one is multiplied.
 constexpr int CNT_USERS = 64;            // users per chunk
 constexpr int AMB_CAP = 512;             // deferred FP64 rechecks per workgroup
 
-// Counting configuration: nw waves (32 items each), nb user buffers, pf
-// 16-byte vectors of a user chunk staged per thread.
-struct CountCfg { int nw, nb, pf; };
+// Counting configuration: 4 waves of 32 items (the items' rows stay in
+// registers), nb user-chunk buffers in LDS, pf 16-byte vectors of a chunk
+// staged per thread (0 = synchronous loads), nch 16-byte chunks per half row.
+constexpr int CNT_NW = 4;
+struct CountCfg { int nb, pf, nch; };
 
-size_t count_lds_cfg(int prec, int D, int nw, int nb) {
+size_t count_lds_cfg(int prec, int D, int nb) {
     const int ls = lds_row_bytes(prec, D);
-    return (size_t)(32 * nw + nb * CNT_USERS) * ls + AMB_CAP * sizeof(int2) +
-           32 * nw * sizeof(int) + 16;
+    return (size_t)nb * CNT_USERS * ls + AMB_CAP * sizeof(int2) + 32 * CNT_NW * sizeof(int) + 16;
 }
 
 CountCfg count_cfg(int prec, int D) {
-    CountCfg c{4, 2, 0};
-    if (count_lds_cfg(prec, D, 4, 2) > 96 * 1024) c.nw = 2;
-    if (count_lds_cfg(prec, D, c.nw, 2) > 160 * 1024) c.nb = 1;
-    const int need = CNT_USERS * D * elem_bytes(prec) / 16, nt = 64 * c.nw;
-    if (c.nb == 2) c.pf = (need <= 4 * nt) ? 4 : (need <= 8 * nt) ? 8 : 0;
+    CountCfg c{2, 0, 0};
+    if (count_lds_cfg(prec, D, 2) > 80 * 1024) c.nb = 1;
+    c.nch = D * elem_bytes(prec) / 32;
+    const int need = CNT_USERS * D * elem_bytes(prec) / 16, nt = 64 * CNT_NW;
+    if (c.nb == 2 && c.nch <= 8 && need <= 4 * nt) c.pf = 4;
     return c;
 }
 
-size_t count_lds(int prec, int D) {
-    CountCfg c = count_cfg(prec, D);
-    return count_lds_cfg(prec, D, c.nw, c.nb);
-}
+size_t count_lds(int prec, int D) { return count_lds_cfg(prec, D, count_cfg(prec, D).nb); }
 
 // FP64 decision of one (item row, user) pair by the tie rule.
 __device__ __forceinline__ bool recheck_pair(const CountArgs &a, int64_t row, int64_t us) {
@@ -73,13 +71,15 @@ __device__ __forceinline__ bool recheck_pair(const CountArgs &a, int64_t row, in
 // FP64 and decided by the tie rule.
 // NW waves of 32 items; NB user buffers; PF 16-byte vectors of a user chunk
 // staged per thread (0 = chunks are loaded synchronously into LDS).
-template <int PREC, int NW, int PF, int NB>
-__global__ __launch_bounds__(64 * NW) void k_count(CountArgs a) {
-    constexpr int NT = 64 * NW, CNT_ITEMS = 32 * NW;
+template <int PREC, int PF, int NB, int NCH>
+// two waves per SIMD where the row fits in 16 chunks
+__global__ __launch_bounds__(64 * CNT_NW) __attribute__((amdgpu_waves_per_eu(NCH <= 16 ? 2 : 1)))
+void k_count(CountArgs a) {
+    constexpr int NT = 64 * CNT_NW, CNT_ITEMS = 32 * CNT_NW;
     extern __shared__ __align__(16) uint8_t smem8[];
     const int D = a.D, ls = lds_row_bytes(PREC, D), w16 = D * elem_bytes(PREC) / 16;
-    uint8_t *Psh = smem8;
-    uint8_t *Ush0 = Psh + CNT_ITEMS * ls;
+    const int rowb = D * elem_bytes(PREC), nch = rowb / 32;
+    uint8_t *Ush0 = smem8;
     uint8_t *Ush1 = Ush0 + (NB - 1) * CNT_USERS * ls;
     int2 *amb = reinterpret_cast<int2 *>(Ush0 + NB * CNT_USERS * ls);
     int *cntl = reinterpret_cast<int *>(amb + AMB_CAP);
@@ -91,16 +91,16 @@ __global__ __launch_bounds__(64 * NW) void k_count(CountArgs a) {
     const uint4 *Pq = reinterpret_cast<const uint4 *>(a.Pq);
     const uint4 *Us = reinterpret_cast<const uint4 *>(a.Us);
 
-    for (int e = tid; e < CNT_ITEMS * w16; e += NT) {
-        int r = e / w16, c = e - r * w16;
-        int64_t it = ib + r;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (it < a.nb) {
-            int64_t row = a.rows ? a.rows[it] : it;
-            v = Pq[row * w16 + c];
-        }
-        *reinterpret_cast<uint4 *>(Psh + r * ls + 16 * c) = v;
+    // this lane's half of its item's row (row lane & 31 of the wave's 32),
+    // kept in registers for the whole kernel
+    uint4 ia[NCH];
+    {
+        const int64_t it = ib + w * 32 + (lane & 31);
+        const bool ok = it < a.nb;
+        const int64_t row = ok ? (a.rows ? a.rows[it] : it) : 0;
+        load_half_row<NCH>(ia, reinterpret_cast<const uint8_t *>(a.Pq), row, ok, rowb, nch, lane);
     }
+    (void)Pq;
     if (tid < CNT_ITEMS) cntl[tid] = 0;
     if (tid == 0) *ambn = 0;
 
@@ -204,7 +204,7 @@ __global__ __launch_bounds__(64 * NW) void k_count(CountArgs a) {
         if (c1) thresholds(us1, tin1, tout1);
         f32x16 acc0 = {0}, acc1 = {0};
         // rows: this wave's items (shared); columns: the two user blocks
-        MM<PREC>::cols2(acc0, acc1, Psh + w * 32 * ls, Ub, Ub + 32 * ls, ls, D, lane);
+        MMR<PREC, NCH>::cols2(acc0, acc1, ia, Ub, Ub + 32 * ls, ls, nch, D, lane);
         uint32_t ambm0 = 0, ambm1 = 0;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
@@ -267,25 +267,33 @@ __global__ __launch_bounds__(64 * NW) void k_count(CountArgs a) {
         atomicAdd(reinterpret_cast<unsigned long long *>(a.rechecks), (unsigned long long)nall);
 }
 
+template <int PREC, int NCH>
+void launch_count_n(const CountArgs &a, const CountCfg &c, dim3 g, size_t lds, hipStream_t st) {
+    if constexpr (NCH == 8) {
+        if (c.nb == 2 && c.pf == 4) {
+            k_count<PREC, 4, 2, NCH><<<g, 256, lds, st>>>(a);
+            return;
+        }
+    }
+    if (c.nb == 2) k_count<PREC, 0, 2, NCH><<<g, 256, lds, st>>>(a);
+    else k_count<PREC, 0, 1, NCH><<<g, 256, lds, st>>>(a);
+}
+
+template <int PREC>
+void launch_count_p(const CountArgs &a, const CountCfg &c, dim3 g, size_t lds, hipStream_t st) {
+    if (c.nch <= 8) launch_count_n<PREC, 8>(a, c, g, lds, st);
+    else if (c.nch <= 16) launch_count_n<PREC, 16>(a, c, g, lds, st);
+    else launch_count_n<PREC, 32>(a, c, g, lds, st);
+}
+
 void launch_count(const CountArgs &a, hipStream_t st) {
     if (a.nb <= 0) return;
     const CountCfg c = count_cfg(a.prec, a.D);
-    const size_t lds = count_lds_cfg(a.prec, a.D, c.nw, c.nb);
-    dim3 g((unsigned)((a.nb + 32 * c.nw - 1) / (32 * c.nw)), (unsigned)a.nsplit);
-#define RMIPS_COUNT(P)                                                                 \
-    do {                                                                               \
-        if (c.nw == 4 && c.pf == 4) k_count<P, 4, 4, 2><<<g, 256, lds, st>>>(a);       \
-        else if (c.nw == 4 && c.pf == 8) k_count<P, 4, 8, 2><<<g, 256, lds, st>>>(a);  \
-        else if (c.nw == 4) k_count<P, 4, 0, 2><<<g, 256, lds, st>>>(a);               \
-        else if (c.nb == 2 && c.pf == 4) k_count<P, 2, 4, 2><<<g, 128, lds, st>>>(a);  \
-        else if (c.nb == 2 && c.pf == 8) k_count<P, 2, 8, 2><<<g, 128, lds, st>>>(a);  \
-        else if (c.nb == 2) k_count<P, 2, 0, 2><<<g, 128, lds, st>>>(a);               \
-        else k_count<P, 2, 0, 1><<<g, 128, lds, st>>>(a);                              \
-    } while (0)
-    if (a.prec == PREC_FP32) RMIPS_COUNT(PREC_FP32);
-    else if (a.prec == PREC_BF16) RMIPS_COUNT(PREC_BF16);
-    else RMIPS_COUNT(PREC_FP8);
-#undef RMIPS_COUNT
+    const size_t lds = count_lds_cfg(a.prec, a.D, c.nb);
+    dim3 g((unsigned)((a.nb + 32 * CNT_NW - 1) / (32 * CNT_NW)), (unsigned)a.nsplit);
+    if (a.prec == PREC_FP32) launch_count_p<PREC_FP32>(a, c, g, lds, st);
+    else if (a.prec == PREC_BF16) launch_count_p<PREC_BF16>(a, c, g, lds, st);
+    else launch_count_p<PREC_FP8>(a, c, g, lds, st);
 }
 
 // Eq. (3)/(6) bound count over the users of the item tile's Cauchy-Schwarz

@@ -85,12 +85,32 @@ struct ThreshArgs {
     const float *U; const float *P; int d;      // original FP32 rows (recheck)
     int D; int k; int t0tiles; int nsplit; int cap;
     float c_err; float c2; float e_abs; float g64;
-    float2 *cand; int32_t *cand_cnt; int32_t *flag;
+    float2 *cand; int32_t *cand_cnt;
     double *tau; int32_t *tau_id; int32_t *topk;
-    unsigned long long *pairs;     // stats: screened pairs (may be NULL)
-    hipEvent_t ev0, ev1;           // recorded around the screening kernel (may be NULL)
+    // overflow handling: lists (3 x n: two refinement lists, the fallback
+    // list) with their counters (4 ints), refinement passes (0..2), and the
+    // per-user starting bound of the last pass
+    int32_t *lists; int32_t *lcnt; int refine; float *Luse;
+    // set per pass by launch_thresh
+    const int32_t *ulist; const int32_t *ulist_cnt;  // users of this pass (NULL = all)
+    int32_t *rlist; int32_t *rcnt;                   // out: users to screen again
+    int32_t *flist; int32_t *fcnt;                   // out: users for the exact fallback
+    // statistics (may be NULL), spread over CSTAT_SLOTS addresses:
+    // pairs[slot] screened pairs; cstats[slot][4] = candidates, rechecked,
+    // fallback users, refined users
+    unsigned long long *pairs;
+    unsigned long long *cstats;
+    hipEvent_t ev0, ev1;           // recorded around the first screening pass (may be NULL)
 };
+constexpr int CSTAT_SLOTS = 32;
 void launch_thresh(const ThreshArgs &a, hipStream_t st);
+// per-wave list stride of the final selection: the longest list rounded up
+// to a power of two (the in-LDS bitonic sorts pad to it)
+inline int final_stride(int capT) {
+    int p = 1;
+    while (p < capT) p <<= 1;
+    return p;
+}
 size_t thresh_screen_lds(int prec, int D);
 // per-tile maxima of Nh and R (64 items per tile)
 void launch_tile_max(const float *Nh, const float *R, int ntiles, float *tmax_nh, float *tmax_r,

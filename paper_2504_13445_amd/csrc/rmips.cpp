@@ -91,11 +91,12 @@ struct ThreshLayout {
     int32_t *perm;
     void *sort_scratch;
     float2 *cand;
-    int32_t *cand_cnt, *flag;
+    int32_t *cand_cnt, *lists, *lcnt;
+    float *Luse;
     int *bad;
 };
 
-void thresh_plan(int prec, int64_t n, int64_t m, int d, int cap_override, ThreshLayout &L,
+void thresh_plan(int prec, int64_t n, int64_t m, int d, int k, int cap_override, ThreshLayout &L,
                  Carve &cv) {
     L.prec = prec;
     L.D = padded_dim(prec, d);
@@ -107,8 +108,16 @@ void thresh_plan(int prec, int64_t n, int64_t m, int d, int cap_override, Thresh
     ns = std::max<int64_t>(1, std::min<int64_t>(ns, 8));
     ns = std::min<int64_t>(ns, L.ntiles);
     L.nsplit = (int)ns;
-    L.cap = cap_override > 0 ? cap_override : (prec == RMIPS_FP8_E4M3 ? 4 * CAP_DEFAULT
-                                                                      : CAP_DEFAULT);
+    // candidate capacity per user (all splits together): well above the
+    // candidate counts of typical users; users beyond it are screened again
+    // with a tighter bound.  FP8's wider error band needs longer lists.
+    if (cap_override > 0) {
+        L.cap = cap_override;
+    } else {
+        int64_t capU = std::max<int64_t>(256, 16 * (int64_t)k);
+        if (prec == RMIPS_FP8_E4M3) capU *= 4;
+        L.cap = (int)(((capU + L.nsplit - 1) / L.nsplit + 7) / 8 * 8);
+    }
     const int64_t npad = (n + 63) / 64 * 64;
     L.Uq = cv.take<uint8_t>((size_t)npad * L.rowb);
     L.Nu = cv.take<float>(npad);
@@ -128,8 +137,11 @@ void thresh_plan(int prec, int64_t n, int64_t m, int d, int cap_override, Thresh
     L.perm = cv.take<int32_t>(m);
     L.sort_scratch = cv.take<uint8_t>(radix_sort_scratch_bytes(m));
     L.cand = cv.take<float2>((size_t)n * L.nsplit * L.cap);
-    L.cand_cnt = cv.take<int32_t>((size_t)n * L.nsplit);
-    L.flag = cv.take<int32_t>(n);
+    // counts per (user, split); refinement passes use up to 8 splits
+    L.cand_cnt = cv.take<int32_t>((size_t)n * 8);
+    L.lists = cv.take<int32_t>((size_t)3 * n);
+    L.lcnt = cv.take<int32_t>(64);
+    L.Luse = cv.take<float>(n);
     L.bad = cv.take<int>(64);
 }
 
@@ -147,7 +159,7 @@ rmips_status run_thresholds(rmips_ctx *ctx, const float *U, int64_t n, const flo
                             int64_t m, int d, int k, ThreshLayout &L, double *tau,
                             int32_t *tau_id, int32_t *topk,
                             unsigned long long *pairs = nullptr, hipEvent_t ev0 = nullptr,
-                            hipEvent_t ev1 = nullptr) {
+                            hipEvent_t ev1 = nullptr, unsigned long long *cstats = nullptr) {
     hipStream_t st = ctx->stream;
     HIPTRY(hipMemsetAsync(L.bad, 0, sizeof(int), st));
     HIPTRY(hipMemsetAsync(L.rmax, 0, sizeof(unsigned int), st));
@@ -172,10 +184,11 @@ rmips_status run_thresholds(rmips_ctx *ctx, const float *U, int64_t n, const flo
     a.U = U; a.P = P; a.d = d;
     a.D = L.D; a.k = k; a.t0tiles = T0_TILES; a.nsplit = L.nsplit; a.cap = L.cap;
     a.c_err = ec.c; a.c2 = ec.c2; a.e_abs = E_ABS; a.g64 = ec.g64;
-    a.cand = L.cand; a.cand_cnt = L.cand_cnt; a.flag = L.flag;
+    a.cand = L.cand; a.cand_cnt = L.cand_cnt;
+    a.lists = L.lists; a.lcnt = L.lcnt; a.refine = 2; a.Luse = L.Luse;
     a.tau = tau; a.tau_id = tau_id; a.topk = topk;
-    a.pairs = pairs; a.ev0 = ev0; a.ev1 = ev1;
-    if (thresh_screen_lds(L.prec, L.D) > 160 * 1024 || (size_t)L.cap * L.nsplit * 24 > 150 * 1024)
+    a.pairs = pairs; a.ev0 = ev0; a.ev1 = ev1; a.cstats = cstats;
+    if (thresh_screen_lds(L.prec, L.D) > 160 * 1024 || (size_t)final_stride(L.cap * L.nsplit) * 24 > 150 * 1024)
         return fail(ctx, RMIPS_EUNSUPPORTED, "screening tile or candidate lists exceed LDS");
     launch_thresh(a, st);
     HIPTRY(hipGetLastError());
@@ -298,6 +311,13 @@ void top_eigvecs(const std::vector<double> &G, int d, int dp, std::vector<double
         for (int i = 0; i < d; ++i) W[(size_t)r * d + i] = X[(size_t)i * b + r];
 }
 
+// counters of rmips_topn (64-bit words): [0] stage (b) rechecks, [2] stage
+// (c) bound pairs, [8, 8 + CSTAT_SLOTS) stage (a) screened pairs,
+// [CTR_CS, CTR_CS + 4 * CSTAT_SLOTS) stage (a) candidate statistics
+constexpr int CTR_PAIRS = 8;
+constexpr int CTR_CS = CTR_PAIRS + CSTAT_SLOTS;
+constexpr int CTR_WORDS = CTR_CS + 4 * CSTAT_SLOTS;
+
 struct TopnLayout {
     ThreshLayout T;
     double *tau;
@@ -333,9 +353,9 @@ void user_side_plan(int64_t n, UserSide &us, Carve &cv) {
     us.uid = cv.take<int32_t>(n);
 }
 
-void topn_plan(int prec, int64_t n, int64_t m, int d, int cap_override, int bmax,
+void topn_plan(int prec, int64_t n, int64_t m, int d, int k, int cap_override, int bmax,
                TopnLayout &L, Carve &cv) {
-    thresh_plan(prec, n, m, d, cap_override, L.T, cv);
+    thresh_plan(prec, n, m, d, k, cap_override, L.T, cv);
     L.tau = cv.take<double>(n);
     L.tau_id = cv.take<int32_t>(n);
     L.ukeys = cv.take<uint32_t>(n);
@@ -365,7 +385,7 @@ void topn_plan(int prec, int64_t n, int64_t m, int d, int cap_override, int bmax
     L.batch_scores = cv.take<int32_t>(bmax);
     L.top = cv.take<uint64_t>(RMIPS_N_MAX);
     L.status = cv.take<int32_t>(64);
-    L.rechecks = cv.take<int64_t>(8);
+    L.rechecks = cv.take<int64_t>(CTR_WORDS);
 }
 
 int count_splits(int64_t nb, int64_t ulen, int maxs) {
@@ -395,7 +415,7 @@ rmips_status rmips_create(rmips_ctx **out, int device, void *hip_stream) {
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
     if (hipHostMalloc((void **)&c->h_status, 256, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&c->h_scalar, 256, hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void **)&c->h_scalar, 4096, hipHostMallocDefault) != hipSuccess) {
         delete c;
         return RMIPS_EDEVICE;
     }
@@ -444,7 +464,7 @@ size_t rmips_thresholds_workspace_size(int64_t n, int64_t m, int32_t d, int32_t 
         return 0;
     Carve cv(nullptr);
     ThreshLayout L;
-    thresh_plan(prec, n, m, d, 0, L, cv);
+    thresh_plan(prec, n, m, d, k, 0, L, cv);
     return cv.off + 256;
 }
 
@@ -489,7 +509,7 @@ size_t rmips_topn_workspace_size(int64_t n, int64_t m, int32_t d, int32_t k, int
         return 0;
     Carve cv(nullptr);
     TopnLayout L;
-    topn_plan(prec, n, m, d, 0, BATCH_MAX, L, cv);
+    topn_plan(prec, n, m, d, k, 0, BATCH_MAX, L, cv);
     return cv.off + 256;
 }
 
@@ -501,11 +521,11 @@ rmips_status rmips_thresholds(rmips_ctx *ctx, const float *U, int64_t n, const f
     if (!U || !P || !ws || !tau || !tau_id) return fail(ctx, RMIPS_EINVAL, "null pointer");
     Carve probe(nullptr);
     ThreshLayout L;
-    thresh_plan(prec, n, m, d, ctx->cap_override, L, probe);
+    thresh_plan(prec, n, m, d, k, ctx->cap_override, L, probe);
     if (ws_bytes < probe.off + 256) return fail(ctx, RMIPS_EWORKSPACE, "workspace too small");
     HIPTRY(hipSetDevice(ctx->device));
     Carve cv(ws);
-    thresh_plan(prec, n, m, d, ctx->cap_override, L, cv);
+    thresh_plan(prec, n, m, d, k, ctx->cap_override, L, cv);
     return run_thresholds(ctx, U, n, P, m, d, k, L, tau, tau_id, topk);
 }
 
@@ -570,7 +590,7 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     {
         Carve probe(nullptr);
         TopnLayout L0;
-        topn_plan(prec, n, m, d, ctx->cap_override, BATCH_MAX, L0, probe);
+        topn_plan(prec, n, m, d, k, ctx->cap_override, BATCH_MAX, L0, probe);
         if (ws_bytes < probe.off + 256)
             return fail(ctx, RMIPS_EWORKSPACE, "workspace too small");
     }
@@ -578,7 +598,7 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     hipStream_t st = ctx->stream;
     Carve cv(ws);
     TopnLayout L;
-    topn_plan(prec, n, m, d, ctx->cap_override, BATCH_MAX, L, cv);
+    topn_plan(prec, n, m, d, k, ctx->cap_override, BATCH_MAX, L, cv);
     const int D = L.T.D;
     const ErrConst ec = err_const(D, d);
 
@@ -590,12 +610,12 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     } guard{ev};
     for (auto &e : ev) HIPTRY(hipEventCreate(&e));
     unsigned long long *ctr = reinterpret_cast<unsigned long long *>(L.rechecks);
-    HIPTRY(hipMemsetAsync(ctr, 0, 8 * sizeof(unsigned long long), st));
+    HIPTRY(hipMemsetAsync(ctr, 0, CTR_WORDS * sizeof(unsigned long long), st));
     HIPTRY(hipEventRecord(ev[0], st));
 
     // ---- stage (a): exact thresholds
-    s = run_thresholds(ctx, U, n, P, m, d, k, L.T, L.tau, L.tau_id, nullptr, ctr + 1, ev[4],
-                       ev[5]);
+    s = run_thresholds(ctx, U, n, P, m, d, k, L.T, L.tau, L.tau_id, nullptr, ctr + CTR_PAIRS,
+                       ev[4], ev[5], ctr + CTR_CS);
     if (s != RMIPS_OK) return s;
     HIPTRY(hipEventRecord(ev[1], st));
 
@@ -703,7 +723,7 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     HIPTRY(hipEventRecord(ev[3], st));
     std::vector<uint64_t> top(N);
     HIPTRY(hipMemcpyAsync(top.data(), L.top, sizeof(uint64_t) * N, hipMemcpyDeviceToHost, st));
-    HIPTRY(hipMemcpyAsync(ctx->h_scalar, L.rechecks, 4 * sizeof(int64_t),
+    HIPTRY(hipMemcpyAsync(ctx->h_scalar, L.rechecks, CTR_WORDS * sizeof(int64_t),
                           hipMemcpyDeviceToHost, st));
     HIPTRY(hipStreamSynchronize(st));
     if (ctx->h_status[1] != N) return fail(ctx, RMIPS_EDEVICE, "top-N list incomplete");
@@ -715,13 +735,20 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
         std::memset(stats, 0, sizeof(*stats));
         stats->visited_items = visited;
         stats->batches = batches;
-        stats->cand_pairs = -1;
-        stats->overflow_users = -1;
-        stats->recheck_pairs = ctx->h_scalar[0];
-        stats->thresh_pairs = ctx->h_scalar[1];
-        stats->bound_pairs = ctx->h_scalar[2];
+        const int64_t *h = ctx->h_scalar;
+        int64_t tp = 0, cs[4] = {0, 0, 0, 0};
+        for (int i = 0; i < CSTAT_SLOTS; ++i) {
+            tp += h[CTR_PAIRS + i];
+            for (int j = 0; j < 4; ++j) cs[j] += h[CTR_CS + 4 * i + j];
+        }
+        stats->cand_pairs = cs[1];
+        stats->overflow_users = cs[2];
+        stats->refine_users = cs[3];
+        stats->recheck_pairs = h[0];
+        stats->thresh_pairs = tp;
+        stats->bound_pairs = h[2];
         stats->count_pairs = screened;
-        stats->screened_pairs = screened + ctx->h_scalar[1];
+        stats->screened_pairs = screened + tp;
         stats->count_launches = launches;
         float t01 = 0, t12 = 0, t23 = 0, t03 = 0, tsc = 0, tbd = 0;
         (void)hipEventElapsedTime(&t01, ev[0], ev[1]);

@@ -1,6 +1,6 @@
 // Stage (a): tau_u, the k-th largest u . p over all items (Def. 1), exact.
 //
-// Screening.  A workgroup holds 32 users per wave in LDS and streams the
+// Screening.  A workgroup holds 32 users per wave in registers and streams the
 // items in descending-norm order (Alg. 1 step (1)), 64 per tile, through
 // the matrix cores in FP32, BF16 or FP8 (e4m3, a power-of-two scale per
 // user and per item tile).  With N = ||x||, Nh = ||xq|| and R = ||x - xq||
@@ -70,29 +70,30 @@ __device__ __forceinline__ void merge32_desc(float (&v)[32]) {
     }
 }
 
-// Screening configuration: nw waves (32 users each), nb item-tile buffers
-// in LDS (2 = the next tile loads while the current one is used), pf 16-byte
-// vectors of a tile staged per thread (0 = tiles load synchronously).
-struct ScreenCfg { int nw, nb, pf; };
+// Screening configuration: 4 waves of 32 users (the users' rows stay in
+// registers), nb item-tile buffers in LDS (2 = the next tile loads while
+// the current one is used), pf 16-byte vectors of a tile staged per thread
+// (0 = tiles load synchronously), nch 16-byte chunks per half row.
+constexpr int SCR_NW = 4;
+struct ScreenCfg { int nb, pf, nch; };
 
-size_t thresh_screen_lds_cfg(int prec, int D, int nw, int nb) {
+size_t thresh_screen_lds_cfg(int prec, int D, int nb) {
     const int ls = lds_row_bytes(prec, D);
-    return (size_t)(32 * nw + nb * TILE_ITEMS) * ls + (size_t)nb * 3 * TILE_ITEMS * 4 +
-           32 * nw * sizeof(int) + 16 * sizeof(float);
+    return (size_t)nb * TILE_ITEMS * ls + (size_t)nb * 3 * TILE_ITEMS * 4 +
+           32 * SCR_NW * sizeof(int) + 16 * sizeof(float);
 }
 
 ScreenCfg screen_cfg(int prec, int D) {
-    ScreenCfg c{4, 2, 0};
-    if (thresh_screen_lds_cfg(prec, D, 4, 2) > 96 * 1024) c.nw = 2;
-    if (thresh_screen_lds_cfg(prec, D, c.nw, 2) > 160 * 1024) c.nb = 1;
-    const int need = TILE_ITEMS * D * elem_bytes(prec) / 16, nt = 64 * c.nw;
-    if (c.nb == 2) c.pf = (need <= 4 * nt) ? 4 : (need <= 8 * nt) ? 8 : 0;
+    ScreenCfg c{2, 0, 0};
+    if (thresh_screen_lds_cfg(prec, D, 2) > 80 * 1024) c.nb = 1;
+    c.nch = D * elem_bytes(prec) / 32;
+    const int need = TILE_ITEMS * D * elem_bytes(prec) / 16, nt = 64 * SCR_NW;
+    if (c.nb == 2 && c.nch <= 8 && need <= 4 * nt) c.pf = 4;
     return c;
 }
 
 size_t thresh_screen_lds(int prec, int D) {
-    ScreenCfg c = screen_cfg(prec, D);
-    return thresh_screen_lds_cfg(prec, D, c.nw, c.nb);
+    return thresh_screen_lds_cfg(prec, D, screen_cfg(prec, D).nb);
 }
 
 // Item tile t (64 rows of D elements, and per item N, Nh, R) into registers,
@@ -158,48 +159,55 @@ __device__ __forceinline__ void tile_load(const ThreshArgs &a, const TileIO &io,
     }
 }
 
-template <int PREC, int NW, int PF, int NB>
-__global__ __launch_bounds__(64 * NW) void k_thresh_screen(ThreshArgs a) {
-    constexpr int TU = 32 * NW, NT = 64 * NW;
+// Users of one screening workgroup: 32 per wave.  Without a user list the
+// grid covers all users once; with one (refinement passes) the workgroups
+// stride over the list, whose length is read on the device.
+__device__ __forceinline__ int64_t screen_blocks(const ThreshArgs &a, int tu) {
+    const int64_t cnt = a.ulist ? (int64_t)*a.ulist_cnt : a.n;
+    return (cnt + tu - 1) / tu;
+}
+
+// The next tile into the buffer not in use (NB = 2; from the registers
+// fetched earlier when PF > 0), or into the only buffer once every wave is
+// done with it (NB = 1).
+template <int PF, int NB, int PFN, int NT>
+__device__ __forceinline__ void tile_next(const uint4 (&pf)[PFN], const float (&pn)[3],
+                                          const ThreshArgs &a, const TileIO &io, int tn,
+                                          uint8_t *Pbase, float *Nbase, int buf, int tid) {
+    if (NB == 1) {
+        __syncthreads();
+        tile_load<NT>(a, io, tn, Pbase, Nbase, 0, tid);
+    } else if (PF > 0) {
+        tile_stash<PFN, NT>(pf, pn, Pbase, Nbase, buf ^ 1, io, tid);
+    } else {
+        tile_load<NT>(a, io, tn, Pbase, Nbase, buf ^ 1, tid);
+    }
+}
+
+template <int PREC, int PF, int NB, int NCH>
+// two waves per SIMD (the register budget of 256) where the row fits in
+// 16 chunks; longer FP32 rows keep all registers for one wave
+__global__ __launch_bounds__(64 * SCR_NW) __attribute__((amdgpu_waves_per_eu(NCH <= 16 ? 2 : 1)))
+void k_thresh_screen(ThreshArgs a) {
+    constexpr int NW = SCR_NW, TU = 32 * NW, NT = 64 * NW;
     extern __shared__ __align__(16) uint8_t smem8[];
     const int D = a.D, ls = lds_row_bytes(PREC, D), rowb = D * elem_bytes(PREC);
-    uint8_t *Ush = smem8;
-    uint8_t *Pbase = Ush + TU * ls;                                   // item tiles
+    const int nch = rowb / 32;
+    uint8_t *Pbase = smem8;                                           // item tiles
     float *Nbase = reinterpret_cast<float *>(Pbase + NB * TILE_ITEMS * ls);  // N, Nh, R
     int *cntsh = reinterpret_cast<int *>(Nbase + NB * 3 * TILE_ITEMS);
     float *red = reinterpret_cast<float *>(cntsh + TU);
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int64_t ubase = (int64_t)blockIdx.x * TU;
     const int split = blockIdx.y;
     const int w16 = rowb / 16;
-
-    for (int e = tid; e < TU * w16; e += NT) {
-        int r = e / w16, c = e - r * w16;
-        int64_t u = ubase + r;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (u < a.n) v = reinterpret_cast<const uint4 *>(a.Uq)[u * w16 + c];
-        *reinterpret_cast<uint4 *>(Ush + r * ls + 16 * c) = v;
-    }
-    if (tid < TU) cntsh[tid] = 0;
-
     const int ucol = w * 32 + (lane & 31);
-    const int64_t ug = ubase + ucol;
-    const bool uvalid = ug < a.n;
-    const float nu = uvalid ? a.Nu[ug] : 0.0f;
-    const float nhu = uvalid ? a.Nhu[ug] : 0.0f;
-    const float ru = uvalid ? a.Ru[ug] : 0.0f;
-    const float su = uvalid ? a.su[ug] : 1.0f;
-    const uint8_t *Bw = Ush + w * 32 * ls;
+    const bool listed = a.ulist != nullptr;
+    const int64_t nlist = listed ? (int64_t)*a.ulist_cnt : a.n;
+    const int64_t nblk = screen_blocks(a, TU);
     const float rmax = __uint_as_float(*a.rmax_bits);
-
-    // error bound of this user against a tile: E(u,p) <= eu(maxN, maxNh, maxR)
-    auto ebound = [&](float n_p, float nh_p, float r_p) {
-        return fmaf(ru, n_p, fmaf(nhu, r_p, fmaf(a.c_err * nhu, nh_p, fmaf(a.c2 * nu, n_p, a.e_abs))));
-    };
-
-    // tile sequence: phase 1 = tiles 0..t0-1, phase 2 = split, split+nsplit, ...
-    const int t0 = a.t0tiles < a.ntiles ? a.t0tiles : a.ntiles;
+    // phase 1 only without a list: listed users come with their bound
+    const int t0 = listed ? 0 : (a.t0tiles < a.ntiles ? a.t0tiles : a.ntiles);
     auto tile_of = [&](int it) { return it < t0 ? it : split + (it - t0) * a.nsplit; };
 
     TileIO io;
@@ -210,74 +218,128 @@ __global__ __launch_bounds__(64 * NW) void k_thresh_screen(ThreshArgs a) {
     constexpr int PFN = PF > 0 ? PF : 1;
     uint4 pf[PFN];
     float pn[3] = {0.f, 0.f, 0.f};
+    unsigned long long pacc = 0;  // statistics: phase-2 pairs screened
 
-    float M[32];
+    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        __syncthreads();  // the previous block's counts have been written out
+        if (tid < TU) cntsh[tid] = 0;
+        const int64_t pos = blk * TU + ucol;
+        const bool uvalid = pos < nlist;
+        const int64_t ug = uvalid ? (listed ? (int64_t)a.ulist[pos] : pos) : 0;
+        const int64_t nub = (nlist - blk * TU < TU) ? (nlist - blk * TU) : TU;
+        int64_t ntile_p2 = 0;
+        // this lane's half of its user's row, kept in registers for the whole scan
+        uint4 ub[NCH];
+        load_half_row<NCH>(ub, reinterpret_cast<const uint8_t *>(a.Uq), ug, uvalid, rowb, nch,
+                           lane);
+        const float nu = uvalid ? a.Nu[ug] : 0.0f;
+        const float nhu = uvalid ? a.Nhu[ug] : 0.0f;
+        const float ru = uvalid ? a.Ru[ug] : 0.0f;
+        const float su = uvalid ? a.su[ug] : 1.0f;
+
+        // error bound of this user against an item: E(u,p)
+        auto ebound = [&](float n_p, float nh_p, float r_p) {
+            return fmaf(ru, n_p,
+                        fmaf(nhu, r_p, fmaf(a.c_err * nhu, nh_p, fmaf(a.c2 * nu, n_p, a.e_abs))));
+        };
+        // exit ratio: vh + E <= K_u * N_p + 2 e_abs for every item p, so no
+        // item of norm below (L - 2 e_abs) / K_u reaches L
+        auto exit_ratio = [&](float L) {
+            float rr = INFINITY;
+            if (uvalid) {
+                const float K = nu * (1.0f + a.g64 + 2.0f * a.c2) + 2.0f * ru +
+                                2.0f * nhu * (rmax + a.c_err * (1.0f + rmax));
+                rr = (L > 2.0f * a.e_abs && K > 0.0f) ? (L - 2.0f * a.e_abs) / K * (1.0f - 0x1p-20f)
+                                                      : 0.0f;
+            }
+            return wave_min(rr);
+        };
+
+        float L0 = -INFINITY, rwg = INFINITY;
+        if (listed) {
+            L0 = uvalid ? a.Luse[ug] : INFINITY;
+            const float rr = exit_ratio(L0);
+            if (lane == 0) red[w] = rr;
+        }
+        float2 *mycand = a.cand + (ug * a.nsplit + split) * a.cap;
+
+        if (PF > 0) {
+            tile_fetch<PFN, NT>(pf, pn, a, io, tile_of(0), tid);
+            tile_stash<PFN, NT>(pf, pn, Pbase, Nbase, 0, io, tid);
+        } else {
+            tile_load<NT>(a, io, tile_of(0), Pbase, Nbase, 0, tid);
+        }
+        __syncthreads();
+        if (listed) {
+            rwg = red[0];
 #pragma unroll
-    for (int i = 0; i < 32; ++i) M[i] = -INFINITY;
-    float L0 = -INFINITY, rwg = INFINITY;
-    float2 *mycand = a.cand + ((int64_t)ug * a.nsplit + split) * a.cap;
-    int64_t ntile_p2 = 0;
-
-    if (PF > 0) {
-        tile_fetch<PFN, NT>(pf, pn, a, io, 0, tid);
-        tile_stash<PFN, NT>(pf, pn, Pbase, Nbase, 0, io, tid);
-    } else {
-        tile_load<NT>(a, io, 0, Pbase, Nbase, 0, tid);
-    }
-    __syncthreads();
-    int buf = 0;
-    for (int it = 0;; ++it) {
-        const int t = tile_of(it);
-        if (it >= t0) {
+            for (int q = 1; q < NW; ++q) rwg = fminf(rwg, red[q]);
+        }
+        int buf = 0;
+        // phase 1: per-slot maxima of the lower bounds vh - E over the first
+        // t0 tiles, then L0 = k-th largest of the user's 64 slot maxima
+        if (t0 > 0) {
+            float M[32];
+#pragma unroll
+            for (int i = 0; i < 32; ++i) M[i] = -INFINITY;
+            for (int it = 0; it < t0; ++it) {
+                const int t = it;
+                const int tn = tile_of(it + 1);
+                const bool pre = tn < a.ntiles;
+                if (PF > 0 && pre) tile_fetch<PFN, NT>(pf, pn, a, io, tn, tid);
+                const uint8_t *Psh = Pbase + buf * TILE_ITEMS * ls;
+                const float *Nsh = Nbase + buf * 3 * TILE_ITEMS;
+                const int64_t rb = (int64_t)t * TILE_ITEMS;
+                const float e_t = ebound(Nsh[0], a.tmax_nh[t], a.tmax_r[t]);
+                const float sc = su * a.sp[rb];
+                f32x16 acc0 = {0}, acc1 = {0};
+                MMR<PREC, NCH>::rows2(acc0, acc1, Psh, Psh + 32 * ls, ub, ls, nch, D, lane);
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int r = mfma32_row(i, lane);
+                    if (rb + r < a.m) M[i] = fmaxf(M[i], fmaf(acc0[i], sc, -e_t));
+                    if (rb + r + 32 < a.m) M[16 + i] = fmaxf(M[16 + i], fmaf(acc1[i], sc, -e_t));
+                }
+                if (pre) tile_next<PF, NB, PFN, NT>(pf, pn, a, io, tn, Pbase, Nbase, buf, tid);
+                __syncthreads();
+                if (NB == 2) buf ^= 1;
+            }
+            sort32_desc(M);
+            float Bv[32];
+#pragma unroll
+            for (int j = 0; j < 32; ++j) Bv[j] = __shfl_xor(M[31 - j], 32);
+#pragma unroll
+            for (int j = 0; j < 32; ++j) M[j] = fmaxf(M[j], Bv[j]);
+            merge32_desc(M);
+            L0 = M[0];
+#pragma unroll
+            for (int j = 1; j < 32; ++j)
+                if (j == a.k - 1) L0 = M[j];
+            const float rr = exit_ratio(L0);
+            if (lane == 0) red[w] = rr;
+            __syncthreads();
+            rwg = red[0];
+#pragma unroll
+            for (int q = 1; q < NW; ++q) rwg = fminf(rwg, red[q]);
+        }
+        // phase 2 (tiles split, split + nsplit, ...): candidates vh + E >= L0
+        for (int it = t0;; ++it) {
+            const int t = tile_of(it);
             if (t >= a.ntiles) break;
             if (a.Np[(int64_t)t * TILE_ITEMS] < rwg) break;  // Cauchy-Schwarz exit
             ++ntile_p2;
-        }
-        const int tn = tile_of(it + 1);
-        const bool pre = tn < a.ntiles;
-        if (PF > 0 && pre) tile_fetch<PFN, NT>(pf, pn, a, io, tn, tid);
-        const uint8_t *Psh = Pbase + buf * TILE_ITEMS * ls;
-        const float *Nsh = Nbase + buf * 3 * TILE_ITEMS;
-        const int64_t rb = (int64_t)t * TILE_ITEMS;
-        // tile maxima: N is sorted (first item), Nh and R from the precomputed arrays
-        const float e_t = ebound(Nsh[0], a.tmax_nh[t], a.tmax_r[t]);
-        const float sc = su * a.sp[rb];  // product scale of this (user, tile)
-        f32x16 acc0 = {0}, acc1 = {0};
-        MM<PREC>::rows2(acc0, acc1, Psh, Psh + 32 * ls, Bw, ls, D, lane);
-        if (it < t0) {
-            // phase 1: per-slot maxima of the lower bounds vh - E
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int r = mfma32_row(i, lane);
-                if (rb + r < a.m) M[i] = fmaxf(M[i], fmaf(acc0[i], sc, -e_t));
-                if (rb + r + 32 < a.m) M[16 + i] = fmaxf(M[16 + i], fmaf(acc1[i], sc, -e_t));
-            }
-            if (it == t0 - 1) {
-                sort32_desc(M);
-                float Bv[32];
-#pragma unroll
-                for (int j = 0; j < 32; ++j) Bv[j] = __shfl_xor(M[31 - j], 32);
-#pragma unroll
-                for (int j = 0; j < 32; ++j) M[j] = fmaxf(M[j], Bv[j]);
-                merge32_desc(M);
-                L0 = M[0];
-#pragma unroll
-                for (int j = 1; j < 32; ++j)
-                    if (j == a.k - 1) L0 = M[j];
-                // exit ratio: vh + E <= K_u * N_p + 2 e_abs for every item p
-                float rr = INFINITY;
-                if (uvalid) {
-                    const float K = nu * (1.0f + a.g64 + 2.0f * a.c2) + 2.0f * ru +
-                                    2.0f * nhu * (rmax + a.c_err * (1.0f + rmax));
-                    rr = (L0 > 2.0f * a.e_abs && K > 0.0f)
-                             ? (L0 - 2.0f * a.e_abs) / K * (1.0f - 0x1p-20f)
-                             : 0.0f;
-                }
-                rr = wave_min(rr);
-                if (lane == 0) red[w] = rr;
-            }
-        } else {
-            // phase 2: candidates vh + E >= L0, first on the tile bound
+            const int tn = tile_of(it + 1);
+            const bool pre = tn < a.ntiles;
+            if (PF > 0 && pre) tile_fetch<PFN, NT>(pf, pn, a, io, tn, tid);
+            const uint8_t *Psh = Pbase + buf * TILE_ITEMS * ls;
+            const float *Nsh = Nbase + buf * 3 * TILE_ITEMS;
+            const int64_t rb = (int64_t)t * TILE_ITEMS;
+            // tile maxima: N is sorted (first item), Nh and R from the precomputed arrays
+            const float e_t = ebound(Nsh[0], a.tmax_nh[t], a.tmax_r[t]);
+            const float sc = su * a.sp[rb];  // product scale of this (user, tile)
+            f32x16 acc0 = {0}, acc1 = {0};
+            MMR<PREC, NCH>::rows2(acc0, acc1, Psh, Psh + 32 * ls, ub, ls, nch, D, lane);
+            // first on the tile bound, then per item
             const float thr = (L0 - e_t) / sc;  // exact: sc is a power of two
             bool any = false;
 #pragma unroll
@@ -289,150 +351,246 @@ __global__ __launch_bounds__(64 * NW) void k_thresh_screen(ThreshArgs a) {
                     const int r = mfma32_row(i & 15, lane) + ((i < 16) ? 0 : 32);
                     const bool p = uvalid && ((i < 16) ? acc0[i] : acc1[i - 16]) >= thr &&
                                    rb + r < a.m;
+                    // keep the rare path's LDS reads in place (not hoisted
+                    // for all 32 slots at once, which costs registers)
+                    __asm__ volatile("" ::: "memory");
                     if (p) {
-                        const float h = v + ebound(Nsh[r], Nsh[TILE_ITEMS + r],
-                                                   Nsh[2 * TILE_ITEMS + r]);
+                        const float h =
+                            v + ebound(Nsh[r], Nsh[TILE_ITEMS + r], Nsh[2 * TILE_ITEMS + r]);
                         if (h >= L0) {
                             int s = atomicAdd(&cntsh[ucol], 1);
-                            if (s < a.cap)
-                                mycand[s] = make_float2(v, __int_as_float((int)(rb + r)));
+                            if (s < a.cap) mycand[s] = make_float2(v, __int_as_float((int)(rb + r)));
                         }
                     }
                 }
             }
-        }
-        if (pre) {
-            if (NB == 1) {
-                __syncthreads();  // every wave is done with the only buffer
-                tile_load<NT>(a, io, tn, Pbase, Nbase, 0, tid);
-            } else if (PF > 0) {
-                tile_stash<PFN, NT>(pf, pn, Pbase, Nbase, buf ^ 1, io, tid);
-            } else {
-                tile_load<NT>(a, io, tn, Pbase, Nbase, buf ^ 1, tid);
-            }
+            if (pre) tile_next<PF, NB, PFN, NT>(pf, pn, a, io, tn, Pbase, Nbase, buf, tid);
+            __syncthreads();
+            if (NB == 2) buf ^= 1;
         }
         __syncthreads();
-        if (it == t0 - 1) {
-            rwg = red[0];
-#pragma unroll
-            for (int q = 1; q < NW; ++q) rwg = fminf(rwg, red[q]);
+        if (tid < TU && blk * TU + tid < nlist) {
+            const int64_t p2 = blk * TU + tid;
+            const int64_t u = listed ? (int64_t)a.ulist[p2] : p2;
+            a.cand_cnt[u * a.nsplit + split] = cntsh[tid];
         }
-        if (NB == 2) buf ^= 1;
+        // the bound this pass used (equal for the two lanes of a user)
+        if (!listed && split == 0 && lane < 32 && uvalid) a.Luse[ug] = L0;
+        pacc += (unsigned long long)(ntile_p2 * TILE_ITEMS * nub);
     }
-    __syncthreads();
-    if (tid < TU && ubase + tid < a.n) a.cand_cnt[(ubase + tid) * a.nsplit + split] = cntsh[tid];
-    if (a.pairs && tid == 0) {
-        // statistics only: pairs of the phase-2 tiles this workgroup screened
-        const int64_t nu_valid = (a.n - ubase < TU) ? (a.n - ubase) : TU;
-        atomicAdd(a.pairs, (unsigned long long)(ntile_p2 * TILE_ITEMS * nu_valid));
-    }
+    if (a.pairs && tid == 0 && pacc)
+        atomicAdd(a.pairs + (blockIdx.x & (CSTAT_SLOTS - 1)), pacc);
 }
 
 // ------------------------------------------------------------------ final
+// Wave-level bitonic sort of n <= cap values in LDS, descending (the slots
+// from n up to the next power of two are filled with the fill value first).
+__device__ void wave_sort_desc(float *v, int n, int lane) {
+    int P2 = 1;
+    while (P2 < n) P2 <<= 1;
+    for (int i = n + lane; i < P2; i += 64) v[i] = -INFINITY;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    for (int kk = 2; kk <= P2; kk <<= 1)
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            for (int i = lane; i < P2; i += 64) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const float x = v[i], y = v[l];
+                    const bool desc = (i & kk) == 0;
+                    if ((x < y) == desc) {
+                        v[i] = y;
+                        v[l] = x;
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+        }
+}
+
+// Same for (value, id) pairs in the order (value desc, id asc).
+__device__ void wave_sort_pairs(double *v, int *id, int n, int lane) {
+    int P2 = 1;
+    while (P2 < n) P2 <<= 1;
+    for (int i = n + lane; i < P2; i += 64) {
+        v[i] = -INFINITY;
+        id[i] = 0x7fffffff;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    for (int kk = 2; kk <= P2; kk <<= 1)
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            for (int i = lane; i < P2; i += 64) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const double x = v[i], y = v[l];
+                    const int xi = id[i], yi = id[l];
+                    const bool y_first = (y > x) || (y == x && yi < xi);
+                    const bool desc = (i & kk) == 0;
+                    if (y_first == desc) {
+                        v[i] = y; v[l] = x;
+                        id[i] = yi; id[l] = xi;
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+        }
+}
+
+
 constexpr int FIN_WAVES = 4;
 
-__global__ __launch_bounds__(256) void k_thresh_final(ThreshArgs a, int capT) {
+// One wave per user.  The lists of the user's splits are gathered into
+// LDS with lower and upper bounds vh -/+ E; L* = k-th largest lower bound.
+// A user whose lists overflowed is not resolved here: the k-th largest lower
+// bound among its stored candidates (distinct items, so at most tau_u) is a
+// tighter starting bound for another screening pass, or, when it does not
+// improve on the bound used, the user goes to the exact fallback.
+// capT: longest candidate list taken; capP: array stride, capT rounded up
+// to a power of two so that the bitonic sorts can pad in place.
+__global__ __launch_bounds__(256) void k_thresh_final(ThreshArgs a, int capT, int capP) {
     extern __shared__ float smem[];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int nw = blockDim.x >> 6;  // waves per block (one user each)
-    const int64_t u = (int64_t)blockIdx.x * nw + w;
-    const bool valid = u < a.n;
-    // per-wave LDS: v64[capT] (double), lo, hi (float), cidx, sid (int)
-    uint8_t *base = reinterpret_cast<uint8_t *>(smem) + (size_t)w * capT * 24;
+    // per-wave LDS: v64[capP] (double), lo, hi (float), cidx, sid (int)
+    uint8_t *base = reinterpret_cast<uint8_t *>(smem) + (size_t)w * capP * 24;
     double *v64 = reinterpret_cast<double *>(base);
-    float *lo = reinterpret_cast<float *>(base + (size_t)capT * 8);
-    float *hi = lo + capT;
-    int *cidx = reinterpret_cast<int *>(hi + capT);
-    int *sid = cidx + capT;
+    float *lo = reinterpret_cast<float *>(base + (size_t)capP * 8);
+    float *hi = lo + capP;
+    int *cidx = reinterpret_cast<int *>(hi + capP);
+    int *sid = cidx + capP;
     __shared__ float Lstar[FIN_WAVES];
     __shared__ int nsurv[FIN_WAVES];
+    const bool listed = a.ulist != nullptr;
+    const int64_t nlist = listed ? (int64_t)*a.ulist_cnt : a.n;
+    unsigned long long *cs = a.cstats ? a.cstats + (blockIdx.x & (CSTAT_SLOTS - 1)) * 4 : nullptr;
 
-    int total = 0;
-    bool over = false;
-    if (valid) {
-        for (int s = 0; s < a.nsplit; ++s) {
-            int c = a.cand_cnt[u * a.nsplit + s];
-            over |= c > a.cap;
-            total += c;
-        }
-        if (total > capT) over = true;
-        if (lane == 0) a.flag[u] = over ? 1 : 0;
-    }
-    const bool work = valid && !over;
-    const float nu = valid ? a.Nu[u] : 0.0f;
-    const float nhu = valid ? a.Nhu[u] : 0.0f;
-    const float ru = valid ? a.Ru[u] : 0.0f;
-    if (lane == 0) Lstar[w] = -INFINITY;
-    if (work) {
-        int off = 0;
-        for (int s = 0; s < a.nsplit; ++s) {
-            const int c = a.cand_cnt[u * a.nsplit + s];
-            const float2 *src = a.cand + (u * a.nsplit + s) * a.cap;
-            for (int e = lane; e < c; e += 64) {
-                float2 cv = src[e];
-                int idx = __float_as_int(cv.y);
-                const float eb =
-                    fmaf(ru, a.Np[idx],
-                         fmaf(nhu, a.Rp[idx],
-                              fmaf(a.c_err * nhu, a.Nhp[idx], fmaf(a.c2 * nu, a.Np[idx], a.e_abs))));
-                lo[off + e] = cv.x - eb;
-                hi[off + e] = cv.x + eb;
-                cidx[off + e] = idx;
+    for (int64_t b0 = (int64_t)blockIdx.x * nw; b0 < nlist; b0 += (int64_t)gridDim.x * nw) {
+        const int64_t pos = b0 + w;
+        const bool valid = pos < nlist;
+        const int64_t u = valid ? (listed ? (int64_t)a.ulist[pos] : pos) : 0;
+        int total = 0, stored = 0;
+        bool over = false;
+        if (valid) {
+            for (int s = 0; s < a.nsplit; ++s) {
+                const int c = a.cand_cnt[u * a.nsplit + s];
+                over |= c > a.cap;
+                total += c;
+                stored += c < a.cap ? c : a.cap;
             }
-            off += c;
+            if (stored > capT) over = true;  // cannot happen: nsplit * cap <= capT
         }
-    }
-    __syncthreads();
-    // L* = k-th largest lower bound (rank by value desc, position asc)
-    if (work) {
-        for (int e = lane; e < total; e += 64) {
-            const float x = lo[e];
-            int rank = 0;
-            for (int f = 0; f < total; ++f) {
-                float y = lo[f];
-                rank += (y > x) || (y == x && f < e);
+        const float nu = valid ? a.Nu[u] : 0.0f;
+        const float nhu = valid ? a.Nhu[u] : 0.0f;
+        const float ru = valid ? a.Ru[u] : 0.0f;
+        __syncthreads();  // the previous users' LDS lists are consumed
+        if (lane == 0) Lstar[w] = -INFINITY;
+        if (valid && stored <= capT) {
+            int off = 0;
+            for (int s = 0; s < a.nsplit; ++s) {
+                int c = a.cand_cnt[u * a.nsplit + s];
+                c = c < a.cap ? c : a.cap;
+                const float2 *src = a.cand + (u * a.nsplit + s) * a.cap;
+                for (int e = lane; e < c; e += 64) {
+                    const float2 cv = src[e];
+                    const int idx = __float_as_int(cv.y);
+                    const float eb = fmaf(
+                        ru, a.Np[idx],
+                        fmaf(nhu, a.Rp[idx],
+                             fmaf(a.c_err * nhu, a.Nhp[idx], fmaf(a.c2 * nu, a.Np[idx], a.e_abs))));
+                    lo[off + e] = cv.x - eb;
+                    hi[off + e] = cv.x + eb;
+                    cidx[off + e] = idx;
+                }
+                off += c;
             }
-            if (rank == a.k - 1) Lstar[w] = x;
         }
-    }
-    __syncthreads();
-    // survivors: upper bound reaches L*; keep their caller ids
-    if (work) {
-        const float Ls = Lstar[w];
-        int cntw = 0;
-        for (int e0 = 0; e0 < total; e0 += 64) {
-            const int e = e0 + lane;
-            const bool keep = e < total && hi[e] >= Ls;
-            const uint64_t bal = __ballot(keep);
-            const int pos = cntw + __popcll(bal & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
-            if (keep) sid[pos] = a.perm[cidx[e]];
-            cntw += __popcll(bal);
+        __syncthreads();
+        // L* = k-th largest lower bound: by ranks for short lists, else by
+        // sorting the lower bounds (the upper bounds and rows stay in place)
+        if (valid && stored <= capT) {
+            if (stored <= 128) {
+                for (int e = lane; e < stored; e += 64) {
+                    const float x = lo[e];
+                    int rank = 0;
+                    for (int f = 0; f < stored; ++f) {
+                        const float y = lo[f];
+                        rank += (y > x) || (y == x && f < e);
+                    }
+                    if (rank == a.k - 1) Lstar[w] = x;
+                }
+            } else {
+                wave_sort_desc(lo, stored, lane);
+                if (lane == 0) Lstar[w] = lo[a.k - 1];
+            }
         }
-        if (lane == 0) nsurv[w] = cntw;
-    }
-    __syncthreads();
-    if (work) {
-        const int ns = nsurv[w];
-        const float *urow = a.U + u * a.d;
-        for (int s = lane; s < ns; s += 64)
-            v64[s] = ip64(urow, a.P + (int64_t)sid[s] * a.d, a.d);
-    }
-    __syncthreads();
-    if (work) {
-        const int ns = nsurv[w];
-        for (int s = lane; s < ns; s += 64) {
-            const double x = v64[s];
-            const int c = sid[s];
-            int rank = 0;
-            for (int f = 0; f < ns; ++f) {
-                double y = v64[f];
-                rank += (y > x) || (y == x && sid[f] < c);
+        __syncthreads();
+        if (valid && over) {
+            if (lane == 0) {
+                const float Lprev = a.Luse[u];
+                const float Lnew = stored >= a.k ? fmaxf(Lstar[w], Lprev) : Lprev;
+                if (a.rlist && Lnew > Lprev) {
+                    a.Luse[u] = Lnew;
+                    a.rlist[atomicAdd(a.rcnt, 1)] = (int)u;
+                    if (cs) atomicAdd(cs + 3, 1ull);
+                } else {
+                    a.flist[atomicAdd(a.fcnt, 1)] = (int)u;
+                    if (cs) atomicAdd(cs + 2, 1ull);
+                }
             }
-            if (rank == a.k - 1) {
-                a.tau[u] = x;
-                a.tau_id[u] = c;
+        }
+        const bool work = valid && !over;
+        if (work && cs && lane == 0) atomicAdd(cs, (unsigned long long)total);
+        // survivors: upper bound reaches L*; keep their caller ids
+        if (work) {
+            const float Ls = Lstar[w];
+            int cntw = 0;
+            for (int e0 = 0; e0 < total; e0 += 64) {
+                const int e = e0 + lane;
+                const bool keep = e < total && hi[e] >= Ls;
+                const uint64_t bal = __ballot(keep);
+                const int p = cntw + __popcll(bal & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+                if (keep) sid[p] = a.perm[cidx[e]];
+                cntw += __popcll(bal);
             }
-            if (a.topk && rank < a.k) a.topk[u * a.k + rank] = c;
+            if (lane == 0) nsurv[w] = cntw;
+            if (cs && lane == 0) atomicAdd(cs + 1, (unsigned long long)cntw);
+        }
+        __syncthreads();
+        if (work) {
+            const int ns = nsurv[w];
+            const float *urow = a.U + u * a.d;
+            for (int q = lane; q < ns; q += 64) v64[q] = ip64(urow, a.P + (int64_t)sid[q] * a.d, a.d);
+        }
+        __syncthreads();
+        if (work) {
+            const int ns = nsurv[w];
+            if (ns <= 128) {
+                for (int q = lane; q < ns; q += 64) {
+                    const double x = v64[q];
+                    const int c = sid[q];
+                    int rank = 0;
+                    for (int f = 0; f < ns; ++f) {
+                        const double y = v64[f];
+                        rank += (y > x) || (y == x && sid[f] < c);
+                    }
+                    if (rank == a.k - 1) {
+                        a.tau[u] = x;
+                        a.tau_id[u] = c;
+                    }
+                    if (a.topk && rank < a.k) a.topk[u * a.k + rank] = c;
+                }
+            } else {
+                wave_sort_pairs(v64, sid, ns, lane);
+                if (lane == 0) {
+                    a.tau[u] = v64[a.k - 1];
+                    a.tau_id[u] = sid[a.k - 1];
+                }
+                if (a.topk)
+                    for (int r = lane; r < a.k; r += 64) a.topk[u * a.k + r] = sid[r];
+            }
         }
     }
 }
@@ -448,9 +606,10 @@ __global__ __launch_bounds__(64 * FB_WAVES) void k_thresh_fallback(ThreshArgs a)
     __shared__ int li[FB_WAVES][64][KMAX];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int k = a.k;
-    for (int64_t u = (int64_t)blockIdx.x * FB_WAVES + w; u < a.n;
-         u += (int64_t)gridDim.x * FB_WAVES) {
-        if (a.flag[u] == 0) continue;
+    const int64_t nf = *a.fcnt;
+    for (int64_t i = (int64_t)blockIdx.x * FB_WAVES + w; i < nf;
+         i += (int64_t)gridDim.x * FB_WAVES) {
+        const int64_t u = a.flist[i];
         const float *urow = a.U + u * a.d;
         double *myv = lv[w][lane];
         int *myi = li[w][lane];
@@ -501,34 +660,79 @@ __global__ __launch_bounds__(64 * FB_WAVES) void k_thresh_fallback(ThreshArgs a)
     }
 }
 
-void launch_thresh(const ThreshArgs &a, hipStream_t st) {
-    const ScreenCfg c = screen_cfg(a.prec, a.D);
-    const int tu = 32 * c.nw;
-    const size_t lds = thresh_screen_lds_cfg(a.prec, a.D, c.nw, c.nb);
-    dim3 g((unsigned)((a.n + tu - 1) / tu), (unsigned)a.nsplit);
-    if (a.ev0) (void)hipEventRecord(a.ev0, st);
-#define RMIPS_SCREEN(P)                                                                   \
-    do {                                                                                  \
-        if (c.nw == 4 && c.pf == 4) k_thresh_screen<P, 4, 4, 2><<<g, 256, lds, st>>>(a);  \
-        else if (c.nw == 4 && c.pf == 8) k_thresh_screen<P, 4, 8, 2><<<g, 256, lds, st>>>(a); \
-        else if (c.nw == 4) k_thresh_screen<P, 4, 0, 2><<<g, 256, lds, st>>>(a);          \
-        else if (c.nb == 2 && c.pf == 4) k_thresh_screen<P, 2, 4, 2><<<g, 128, lds, st>>>(a); \
-        else if (c.nb == 2 && c.pf == 8) k_thresh_screen<P, 2, 8, 2><<<g, 128, lds, st>>>(a); \
-        else if (c.nb == 2) k_thresh_screen<P, 2, 0, 2><<<g, 128, lds, st>>>(a);          \
-        else k_thresh_screen<P, 2, 0, 1><<<g, 128, lds, st>>>(a);                         \
-    } while (0)
-    if (a.prec == PREC_FP32) RMIPS_SCREEN(PREC_FP32);
-    else if (a.prec == PREC_BF16) RMIPS_SCREEN(PREC_BF16);
-    else RMIPS_SCREEN(PREC_FP8);
-#undef RMIPS_SCREEN
-    if (a.ev1) (void)hipEventRecord(a.ev1, st);
-    const int capT = a.cap * a.nsplit;
-    int fw = (int)((150 * 1024) / ((size_t)capT * 24));  // waves whose lists fit in LDS
+template <int PREC, int NCH>
+void launch_screen_n(const ThreshArgs &a, const ScreenCfg &c, dim3 g, size_t lds, hipStream_t st) {
+    if constexpr (NCH == 8) {
+        if (c.nb == 2 && c.pf == 4) {
+            k_thresh_screen<PREC, 4, 2, NCH><<<g, 256, lds, st>>>(a);
+            return;
+        }
+    }
+    if (c.nb == 2) k_thresh_screen<PREC, 0, 2, NCH><<<g, 256, lds, st>>>(a);
+    else k_thresh_screen<PREC, 0, 1, NCH><<<g, 256, lds, st>>>(a);
+}
+
+template <int PREC>
+void launch_screen(const ThreshArgs &a, const ScreenCfg &c, dim3 g, size_t lds, hipStream_t st) {
+    if (c.nch <= 8) launch_screen_n<PREC, 8>(a, c, g, lds, st);
+    else if (c.nch <= 16) launch_screen_n<PREC, 16>(a, c, g, lds, st);
+    else launch_screen_n<PREC, 32>(a, c, g, lds, st);
+}
+
+void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
+    const ScreenCfg c = screen_cfg(a0.prec, a0.D);
+    const int tu = 32 * SCR_NW;
+    const size_t lds = thresh_screen_lds_cfg(a0.prec, a0.D, c.nb);
+    const int64_t ublocks = (a0.n + tu - 1) / tu;
+    const int capU = a0.cap * a0.nsplit;
+    const int capP = final_stride(capU);
+    int fw = (int)((150 * 1024) / ((size_t)capP * 24));  // waves whose lists fit in LDS
     fw = fw < 1 ? 1 : (fw > FIN_WAVES ? FIN_WAVES : fw);
-    const size_t lds_fin = (size_t)fw * capT * 24;
-    k_thresh_final<<<(unsigned)((a.n + fw - 1) / fw), 64 * fw, lds_fin, st>>>(a, capT);
-    int64_t fb = (a.n + FB_WAVES - 1) / FB_WAVES;
+    const size_t lds_fin = (size_t)fw * capP * 24;
+    const int64_t fblocks = (a0.n + fw - 1) / fw;
+    int32_t *LA = a0.lists, *LB = a0.lists + a0.n, *LF = a0.lists + 2 * a0.n;
+    (void)hipMemsetAsync(a0.lcnt, 0, 4 * sizeof(int32_t), st);
+    auto screen = [&](const ThreshArgs &a, dim3 g) {
+        if (a.prec == PREC_FP32) launch_screen<PREC_FP32>(a, c, g, lds, st);
+        else if (a.prec == PREC_BF16) launch_screen<PREC_BF16>(a, c, g, lds, st);
+        else launch_screen<PREC_FP8>(a, c, g, lds, st);
+    };
+    // pass 0: all users, bound from phase 1
+    ThreshArgs a = a0;
+    a.ulist = nullptr;
+    a.ulist_cnt = nullptr;
+    a.rlist = a0.refine > 0 ? LA : nullptr;
+    a.rcnt = a0.lcnt;
+    a.flist = LF;
+    a.fcnt = a0.lcnt + 2;
+    if (a.ev0) (void)hipEventRecord(a.ev0, st);
+    screen(a, dim3((unsigned)ublocks, (unsigned)a.nsplit));
+    if (a.ev1) (void)hipEventRecord(a.ev1, st);
+    k_thresh_final<<<(unsigned)fblocks, 64 * fw, lds_fin, st>>>(a, capU, capP);
+    // refinement passes over the users whose lists overflowed: the same
+    // per-user capacity in fewer, longer lists per split
+    int nsr = capU / 64;
+    nsr = nsr < 1 ? 1 : (nsr > 8 ? 8 : nsr);
+    for (int r = 1; r <= a0.refine && r <= 2; ++r) {
+        ThreshArgs b = a0;
+        b.ulist = (r == 1) ? LA : LB;
+        b.ulist_cnt = a0.lcnt + (r == 1 ? 0 : 1);
+        b.rlist = (r < a0.refine && r < 2) ? LB : nullptr;
+        b.rcnt = a0.lcnt + 1;
+        b.flist = LF;
+        b.fcnt = a0.lcnt + 2;
+        b.nsplit = nsr;
+        b.cap = capU / nsr;
+        b.t0tiles = 0;
+        const int64_t gx = ublocks < 1024 / nsr ? ublocks : 1024 / nsr;
+        screen(b, dim3((unsigned)gx, (unsigned)nsr));
+        const int64_t gf = fblocks < 2048 ? fblocks : 2048;
+        k_thresh_final<<<(unsigned)gf, 64 * fw, lds_fin, st>>>(b, b.nsplit * b.cap, capP);
+    }
+    int64_t fb = (a0.n + FB_WAVES - 1) / FB_WAVES;
     if (fb > 1024) fb = 1024;
+    a.flist = LF;
+    a.fcnt = a0.lcnt + 2;
     k_thresh_fallback<<<(unsigned)fb, 64 * FB_WAVES, 0, st>>>(a);
 }
 

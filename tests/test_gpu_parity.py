@@ -196,6 +196,23 @@ def test_topn_forced_fallback_and_small_batches(prec):
     _check_topn(U, P, 10, 10, cand_cap=2, batch=(8, 32), prec=prec)
 
 
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("cap", [2, 4])
+def test_topn_refinement_passes(prec, cap):
+    """Short candidate lists: users whose lists overflow are screened again
+    from the k-th largest lower bound among their stored candidates, the
+    rest go to the exact fallback; results stay exact either way."""
+    _say("topn refinement passes", prec, cap)
+    U, P = synth.make_config(1, n=3000, m=4000)
+    _, _, tk = orc.kmips_c(U, P, 10)
+    st = _check_topn(U, P, 10, 10, topk_ref=tk, cand_cap=cap, prec=prec)
+    print("stats", st, flush=True)
+    assert st["refine_users"] + st["overflow_users"] > 0
+    if cap >= 4:
+        assert st["refine_users"] > 0
+    _check_thresholds(U, P, 10, cand_cap=cap, prec=prec)
+
+
 # ------------------------------------------------------------ full sizes
 @pytest.fixture(scope="module")
 def mf_workload():
