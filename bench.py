@@ -109,17 +109,19 @@ def main():
     # dominant kernel of the step, by time measured with HIP events on the
     # library's stream around each launch
     launches = max(avg("count_launches"), 1.0)
+    # (total ms, launches, algorithmic flops per launch, dense matrix-core peak
+    # of the kernel's input type: the screening and counting kernels run in
+    # the screening precision, the bound kernel in FP32)
     kern = {
-        "k_thresh_screen": (avg("ms_screen"), 1.0, 2.0 * d * avg("thresh_pairs")),
+        "k_thresh_screen": (avg("ms_screen"), 1.0, 2.0 * d * avg("thresh_pairs"), PEAK[prec]),
         "k_count": (avg("ms_count_kernels"), launches,
-                    2.0 * d * avg("count_pairs") / launches),
-        "k_bound": (avg("ms_bound_kernel"), 1.0, 2.0 * 12 * avg("bound_pairs")),
+                    2.0 * d * avg("count_pairs") / launches, PEAK[prec]),
+        "k_bound": (avg("ms_bound_kernel"), 1.0, 2.0 * 12 * avg("bound_pairs"), PEAK["fp32"]),
     }
     name = max(kern, key=lambda x: kern[x][0])
-    tot_ms, nl, flops = kern[name]
+    tot_ms, nl, flops, peak = kern[name]
     per_launch_s = tot_ms / nl / 1e3
     achieved = flops / per_launch_s if per_launch_s > 0 else 0.0
-    peak = PEAK["fp32"]
     out = {
         "metric": "top-N end-to-end G user-item pairs/s (exact)",
         "value": value, "unit": "G pairs/s", "n_gpus": 1, "steps": args.steps,

@@ -321,6 +321,43 @@ template <int NCH> struct MMR<PREC_FP8, NCH> {
     }
 };
 
+// 1 / x for a power of two x whose reciprocal is a normal float: exact.
+__device__ __forceinline__ float pow2_rcp(float x) {
+    return __uint_as_float((254u << 23) - (__float_as_uint(x) & 0x7f800000u));
+}
+
+// Direct global-to-LDS copies (no registers): each lane copies 16 (or 4)
+// bytes from its own global address; lane l's bytes land at lds + 16 l (or
+// 4 l), lds being the wave's common LDS address.  They complete under the
+// vector-memory counter: dma_wait() before a barrier publishes them.
+__device__ __forceinline__ void dma16(const void *g, void *lds) {
+    __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void *)lds, 16, 0, 0);
+}
+__device__ __forceinline__ void dma4(const void *g, void *lds) {
+    __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void *)lds, 4, 0, 0);
+}
+__device__ __forceinline__ void dma_wait() { __builtin_amdgcn_s_waitcnt(0); }
+
+// Rows 0..63 (row r at src + min(r, rlast) * rowb) into LDS rows of ls =
+// rowb + 16 bytes: 64 * (w16 + 1) 16-byte slots, 64 per wave instruction,
+// wave w taking instructions w, w + nw, ...  The last slot of each LDS row
+// is padding and gets a copy of the row's last vector.  magic =
+// ceil(2^32 / (w16 + 1)) splits a slot index into (row, vector) exactly
+// for the slot counts used here (at most 64 * 129 slots).
+__device__ __forceinline__ void rows_dma(const uint8_t *src, int rowb, int w16, uint32_t magic,
+                                         int rlast, uint8_t *dst, int w, int nw, int lane) {
+    const int spr = w16 + 1;
+    for (int j = w; j < spr; j += nw) {
+        const uint32_t s = 64u * (uint32_t)j + (uint32_t)lane;
+        const uint32_t r = __umulhi(s, magic);
+        uint32_t c = s - r * (uint32_t)spr;
+        c = c < (uint32_t)w16 ? c : (uint32_t)(w16 - 1);
+        const uint32_t rr = r < (uint32_t)rlast ? r : (uint32_t)rlast;
+        dma16(src + (size_t)rr * rowb + 16 * c, dst + 1024 * j);
+    }
+}
+__host__ __device__ inline uint32_t slot_magic(int w16) { return 0xffffffffu / (uint32_t)(w16 + 1) + 1u; }
+
 // Load this lane's half row (nch 16-byte chunks) of row `row` of a
 // quantized array with rows of rowb bytes; zeros when row is invalid.
 template <int NCH>
@@ -370,11 +407,23 @@ __device__ __forceinline__ uint8_t to_e4m3(float y, float &q) {
 // Exact value of u . p: FP64 sum of the exact products of the FP32 inputs,
 // taken in index order from +0.0.  fma() adds the exact product with one
 // rounding, which is what a separate multiply (exact) and add would give.
+// The operands are loaded 16 at a time ahead of the dependent chain; the
+// zeros that pad the last block add +0, which leaves the sum unchanged (the
+// sum is never -0: it starts at +0 and +0 + -0 = +0).
 __device__ __forceinline__ double ip64(const float *__restrict__ u,
                                        const float *__restrict__ p, int d) {
     double acc = 0.0;
-    for (int i = 0; i < d; ++i)
-        acc = __fma_rn((double)u[i], (double)p[i], acc);
+    for (int i = 0; i < d; i += 16) {
+        float x[16], y[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const bool ok = i + j < d;
+            x[j] = ok ? u[i + j] : 0.0f;
+            y[j] = ok ? p[i + j] : 0.0f;
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc = __fma_rn((double)x[j], (double)y[j], acc);
+    }
     return acc;
 }
 

@@ -24,18 +24,22 @@ __device__ __forceinline__ int half_sum(int x) {
     return x;
 }
 
-// Counting workgroup: 4 waves, each owning 32 items (the row operand, kept
+// Counting workgroup: 8 waves, each owning 32 items (the row operand, kept
 // in registers for the whole kernel); users stream through LDS 64 at a time
 // (two column blocks), double-buffered where LDS allows, so the next chunk
 // loads while the current one is multiplied.
 constexpr int CNT_USERS = 64;            // users per chunk
-constexpr int AMB_CAP = 512;             // deferred FP64 rechecks per workgroup
+constexpr int AMB_CAP = 1024;            // deferred FP64 rechecks per workgroup
+constexpr int AMB_FLUSH = AMB_CAP / 2;   // list length that triggers a flush between chunks
 
-// Counting configuration: 4 waves of 32 items (the items' rows stay in
-// registers), nb user-chunk buffers in LDS, pf 16-byte vectors of a chunk
-// staged per thread (0 = synchronous loads), nch 16-byte chunks per half row.
-constexpr int CNT_NW = 4;
-struct CountCfg { int nb, pf, nch; };
+// Counting configuration: waves of 32 items (the items' rows stay in
+// registers), nb user-chunk buffers in LDS (2 = the next chunk is copied in
+// while the current one is used), nch 16-byte chunks per half row.  8 waves
+// while a half row fits in 16 chunks (two waves per SIMD, 256 registers
+// each), 4 for longer rows.
+constexpr int CNT_NW = 8;  // at most
+__host__ __device__ constexpr int count_waves(int nch) { return nch <= 16 ? 8 : 4; }
+struct CountCfg { int nb, nch; };
 
 size_t count_lds_cfg(int prec, int D, int nb) {
     const int ls = lds_row_bytes(prec, D);
@@ -43,11 +47,9 @@ size_t count_lds_cfg(int prec, int D, int nb) {
 }
 
 CountCfg count_cfg(int prec, int D) {
-    CountCfg c{2, 0, 0};
+    CountCfg c{2, 0};
     if (count_lds_cfg(prec, D, 2) > 80 * 1024) c.nb = 1;
     c.nch = D * elem_bytes(prec) / 32;
-    const int need = CNT_USERS * D * elem_bytes(prec) / 16, nt = 64 * CNT_NW;
-    if (c.nb == 2 && c.nch <= 8 && need <= 4 * nt) c.pf = 4;
     return c;
 }
 
@@ -71,11 +73,11 @@ __device__ __forceinline__ bool recheck_pair(const CountArgs &a, int64_t row, in
 // FP64 and decided by the tie rule.
 // NW waves of 32 items; NB user buffers; PF 16-byte vectors of a user chunk
 // staged per thread (0 = chunks are loaded synchronously into LDS).
-template <int PREC, int PF, int NB, int NCH>
+template <int PREC, int NB, int NCH>
 // two waves per SIMD where the row fits in 16 chunks
-__global__ __launch_bounds__(64 * CNT_NW) __attribute__((amdgpu_waves_per_eu(NCH <= 16 ? 2 : 1)))
+__global__ __launch_bounds__(64 * count_waves(NCH)) __attribute__((amdgpu_waves_per_eu(NCH <= 16 ? 2 : 1)))
 void k_count(CountArgs a) {
-    constexpr int NT = 64 * CNT_NW, CNT_ITEMS = 32 * CNT_NW;
+    constexpr int NW = count_waves(NCH), NT = 64 * NW, CNT_ITEMS = 32 * NW;
     extern __shared__ __align__(16) uint8_t smem8[];
     const int D = a.D, ls = lds_row_bytes(PREC, D), w16 = D * elem_bytes(PREC) / 16;
     const int rowb = D * elem_bytes(PREC), nch = rowb / 32;
@@ -88,8 +90,6 @@ void k_count(CountArgs a) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t ib = (int64_t)blockIdx.x * CNT_ITEMS;
     const int split = blockIdx.y;
-    const uint4 *Pq = reinterpret_cast<const uint4 *>(a.Pq);
-    const uint4 *Us = reinterpret_cast<const uint4 *>(a.Us);
 
     // this lane's half of its item's row (row lane & 31 of the wave's 32),
     // kept in registers for the whole kernel
@@ -100,7 +100,6 @@ void k_count(CountArgs a) {
         const int64_t row = ok ? (a.rows ? a.rows[it] : it) : 0;
         load_half_row<NCH>(ia, reinterpret_cast<const uint8_t *>(a.Pq), row, ok, rowb, nch, lane);
     }
-    (void)Pq;
     if (tid < CNT_ITEMS) cntl[tid] = 0;
     if (tid == 0) *ambn = 0;
 
@@ -137,87 +136,91 @@ void k_count(CountArgs a) {
     for (int i = 0; i < 16; ++i) cnt[i] = 0;
 
     const int64_t nchunks = (a.ulen + CNT_USERS - 1) / CNT_USERS;
-    const int nvec = CNT_USERS * w16;  // 16-byte vectors per chunk
-    constexpr int PFN = PF > 0 ? PF : 1;
-    int qrow[PFN], qg[PFN], ql[PFN];  // row in chunk, vector in row, LDS offset
-#pragma unroll
-    for (int q = 0; q < PFN; ++q) {
-        const int e = tid + q * NT;
-        const int r = e / w16, c = e - r * w16;
-        qrow[q] = (e < nvec) ? r : CNT_USERS;
-        qg[q] = c;
-        ql[q] = r * ls + 16 * c;
-    }
-    uint4 pf[PFN];
-    auto fetch = [&](int64_t ch) {
+    const uint32_t magic = slot_magic(w16);
+    // chunk ch of users into an LDS buffer by direct copies; rows past the
+    // last user repeat it (their columns are masked out)
+    auto chunk_copy = [&](int64_t ch, uint8_t *dst) {
         const int64_t u0 = ch * CNT_USERS;
-#pragma unroll
-        for (int q = 0; q < PFN; ++q) {
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (qrow[q] < CNT_USERS && u0 + qrow[q] < a.ulen) v = Us[(u0 + qrow[q]) * w16 + qg[q]];
-            pf[q] = v;
+        const int64_t left = a.ulen - u0;
+        const int rlast = (int)((left < CNT_USERS ? left : CNT_USERS) - 1);
+        rows_dma(reinterpret_cast<const uint8_t *>(a.Us) + u0 * rowb, rowb, w16, magic, rlast,
+                 dst, w, NW, lane);
+    };
+    // per-user fields of a chunk's two user columns, loaded one chunk ahead
+    const float mrh = fmaf(a.c_err, mh, mr);
+    float4 uq0 = make_float4(0.f, 0.f, 0.f, 0.f), uq1 = uq0;
+    float uqs0 = 1.0f, uqs1 = 1.0f;
+    auto user_fetch = [&](int64_t c) {
+        const int64_t v0 = c * CNT_USERS + (lane & 31), v1 = v0 + 32;
+        if (c < nchunks && v0 < a.ulen) {
+            uq0 = a.us.thr[v0];
+            uqs0 = a.us.sinv[v0];
+        }
+        if (c < nchunks && v1 < a.ulen) {
+            uq1 = a.us.thr[v1];
+            uqs1 = a.us.sinv[v1];
         }
     };
-    auto stash = [&](uint8_t *dst) {
-#pragma unroll
-        for (int q = 0; q < PFN; ++q)
-            if (qrow[q] < CNT_USERS) *reinterpret_cast<uint4 *>(dst + ql[q]) = pf[q];
-    };
-    auto load_sync = [&](int64_t ch, uint8_t *dst) {
-        const int64_t u0 = ch * CNT_USERS;
-        for (int e = tid; e < nvec; e += NT) {
-            const int r = e / w16, c = e - r * w16;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (u0 + r < a.ulen) v = Us[(u0 + r) * w16 + c];
-            *reinterpret_cast<uint4 *>(dst + r * ls + 16 * c) = v;
-        }
-    };
-    // thresholds of one user column against this wave's items (scaled units)
-    auto thresholds = [&](int64_t us, float &tin, float &tout) {
-        const float nu = a.us.N[us], nhu = a.us.Nh[us], ru = a.us.R[us], su = a.us.s[us];
-        const float e = fmaf(ru, mn, fmaf(nhu, mr, fmaf(a.c_err * nhu, mh, fmaf(a.c2 * nu, mn,
-                                                                                 a.e_abs))));
-        tin = (a.us.tau_hi[us] + e) / su;   // exact: su is a power of two
-        tout = (a.us.tau_lo[us] - e) / su;
+    // thresholds of one user column against this wave's items, in the
+    // units of the screened products (sinv = 1 / s exactly: s is a power of two)
+    auto thresholds = [&](const float4 &q, float sinv, float &tin, float &tout) {
+        const float e = fmaf(q.z, mn, fmaf(q.w, mrh, a.e_abs));
+        tin = (q.x + e) * sinv;
+        tout = (q.y - e) * sinv;
     };
 
-    int64_t ch = split;
-    if (ch < nchunks) {
-        if (PF > 0) {
-            fetch(ch);
-            stash(Ush0);
-        } else {
-            load_sync(ch, Ush0);
+    // FP64 rechecks of the first na listed pairs, spread over the workgroup
+    auto flush = [&](int na) {
+        for (int e = tid; e < na; e += NT) {
+            const int2 q = amb[e];
+            const int64_t row = a.rows ? a.rows[ib + q.x] : ib + q.x;
+            if (recheck_pair(a, row, q.y)) atomicAdd(&cntl[q.x], 1);
         }
-    }
+    };
+    int nall = 0;  // pairs listed (statistics)
+
+    int64_t ch = split;
+    user_fetch(ch);
+    if (ch < nchunks) chunk_copy(ch, Ush0);
+    dma_wait();
     __syncthreads();
     int buf = 0;
     for (; ch < nchunks; ch += a.nsplit) {
         const int64_t nxt = ch + a.nsplit;
-        if (PF > 0 && nxt < nchunks) fetch(nxt);
+        // the other buffer was last read before the previous barrier
+        if (NB == 2 && nxt < nchunks) chunk_copy(nxt, buf ? Ush0 : Ush1);
         const uint8_t *Ub = buf ? Ush1 : Ush0;
         const int64_t us0 = ch * CNT_USERS + (lane & 31), us1 = us0 + 32;
         // a column past the last user is "out" for every row: tout = +inf
         float tin0 = INFINITY, tout0 = INFINITY, tin1 = INFINITY, tout1 = INFINITY;
         const bool c0 = us0 < a.ulen, c1 = us1 < a.ulen;
-        if (c0) thresholds(us0, tin0, tout0);
-        if (c1) thresholds(us1, tin1, tout1);
+        if (c0) thresholds(uq0, uqs0, tin0, tout0);
+        if (c1) thresholds(uq1, uqs1, tin1, tout1);
+        user_fetch(nxt);
         f32x16 acc0 = {0}, acc1 = {0};
         // rows: this wave's items (shared); columns: the two user blocks
         MMR<PREC, NCH>::cols2(acc0, acc1, ia, Ub, Ub + 32 * ls, ls, nch, D, lane);
-        uint32_t ambm0 = 0, ambm1 = 0;
+        // counts, and whether any pair falls between the two thresholds
+        bool anyamb = false;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const float v0 = (PREC == PREC_FP8) ? acc0[i] * srow[i] : acc0[i];
             const float v1 = (PREC == PREC_FP8) ? acc1[i] * srow[i] : acc1[i];
             const bool in0 = v0 > tin0, in1 = v1 > tin1;
             cnt[i] += (in0 ? 1 : 0) + (in1 ? 1 : 0);
-            ambm0 |= (!in0 && !(v0 < tout0)) ? (1u << i) : 0u;
-            ambm1 |= (!in1 && !(v1 < tout1)) ? (1u << i) : 0u;
+            anyamb |= (!in0 && v0 >= tout0) || (!in1 && v1 >= tout1);
         }
-        ambm0 = c0 ? (ambm0 & rvalid) : 0u;
-        ambm1 = c1 ? (ambm1 & rvalid) : 0u;
-        if (__ballot((ambm0 | ambm1) != 0u) != 0ull) {
+        if (__ballot(anyamb) != 0ull) {
+            uint32_t ambm0 = 0, ambm1 = 0;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const float v0 = (PREC == PREC_FP8) ? acc0[i] * srow[i] : acc0[i];
+                const float v1 = (PREC == PREC_FP8) ? acc1[i] * srow[i] : acc1[i];
+                ambm0 |= (!(v0 > tin0) && v0 >= tout0) ? (1u << i) : 0u;
+                ambm1 |= (!(v1 > tin1) && v1 >= tout1) ? (1u << i) : 0u;
+            }
+            ambm0 = c0 ? (ambm0 & rvalid) : 0u;
+            ambm1 = c1 ? (ambm1 & rvalid) : 0u;
 #pragma unroll 1
             for (int i = 0; i < 32; ++i) {
                 const bool p = ((i < 16 ? ambm0 : ambm1) >> (i & 15)) & 1u;
@@ -234,26 +237,29 @@ void k_count(CountArgs a) {
                 }
             }
         }
-        if (nxt < nchunks) {
-            if (NB == 1) {
-                __syncthreads();  // every wave is done with the only buffer
-                load_sync(nxt, Ush0);
-            } else if (PF > 0) {
-                stash(buf ? Ush0 : Ush1);
-            } else {
-                load_sync(nxt, buf ? Ush0 : Ush1);
-            }
+        if (NB == 1 && nxt < nchunks) {
+            __syncthreads();  // every wave is done with the only buffer
+            chunk_copy(nxt, Ush0);
         }
+        if (nxt < nchunks) dma_wait();
         __syncthreads();
         if (NB == 2) buf ^= 1;
+        // a long list is rechecked by the whole workgroup now, so that the
+        // list rarely fills and rechecks rarely run inside one wave
+        const int nq = *ambn;  // the same for all threads after the barrier
+        if (nq >= AMB_FLUSH) {
+            flush(nq < AMB_CAP ? nq : AMB_CAP);
+            nall += nq;
+            __syncthreads();
+            if (tid == 0) *ambn = 0;
+            __syncthreads();
+        }
     }
     // deferred FP64 rechecks, spread over the whole workgroup
-    const int nall = *ambn;
-    const int na = nall < AMB_CAP ? nall : AMB_CAP;
-    for (int e = tid; e < na; e += NT) {
-        const int2 q = amb[e];
-        const int64_t row = a.rows ? a.rows[ib + q.x] : ib + q.x;
-        if (recheck_pair(a, row, q.y)) atomicAdd(&cntl[q.x], 1);
+    {
+        const int nq = *ambn;
+        flush(nq < AMB_CAP ? nq : AMB_CAP);
+        nall += nq;
     }
     __syncthreads();
 #pragma unroll
@@ -268,32 +274,27 @@ void k_count(CountArgs a) {
 }
 
 template <int PREC, int NCH>
-void launch_count_n(const CountArgs &a, const CountCfg &c, dim3 g, size_t lds, hipStream_t st) {
-    if constexpr (NCH == 8) {
-        if (c.nb == 2 && c.pf == 4) {
-            k_count<PREC, 4, 2, NCH><<<g, 256, lds, st>>>(a);
-            return;
-        }
-    }
-    if (c.nb == 2) k_count<PREC, 0, 2, NCH><<<g, 256, lds, st>>>(a);
-    else k_count<PREC, 0, 1, NCH><<<g, 256, lds, st>>>(a);
+void launch_count_n(const CountArgs &a, const CountCfg &c, size_t lds, hipStream_t st) {
+    constexpr int NW = count_waves(NCH);
+    dim3 g((unsigned)((a.nb + 32 * NW - 1) / (32 * NW)), (unsigned)a.nsplit);
+    if (c.nb == 2) k_count<PREC, 2, NCH><<<g, 64 * NW, lds, st>>>(a);
+    else k_count<PREC, 1, NCH><<<g, 64 * NW, lds, st>>>(a);
 }
 
 template <int PREC>
-void launch_count_p(const CountArgs &a, const CountCfg &c, dim3 g, size_t lds, hipStream_t st) {
-    if (c.nch <= 8) launch_count_n<PREC, 8>(a, c, g, lds, st);
-    else if (c.nch <= 16) launch_count_n<PREC, 16>(a, c, g, lds, st);
-    else launch_count_n<PREC, 32>(a, c, g, lds, st);
+void launch_count_p(const CountArgs &a, const CountCfg &c, size_t lds, hipStream_t st) {
+    if (c.nch <= 8) launch_count_n<PREC, 8>(a, c, lds, st);
+    else if (c.nch <= 16) launch_count_n<PREC, 16>(a, c, lds, st);
+    else launch_count_n<PREC, 32>(a, c, lds, st);
 }
 
 void launch_count(const CountArgs &a, hipStream_t st) {
     if (a.nb <= 0) return;
     const CountCfg c = count_cfg(a.prec, a.D);
     const size_t lds = count_lds_cfg(a.prec, a.D, c.nb);
-    dim3 g((unsigned)((a.nb + 32 * CNT_NW - 1) / (32 * CNT_NW)), (unsigned)a.nsplit);
-    if (a.prec == PREC_FP32) launch_count_p<PREC_FP32>(a, c, g, lds, st);
-    else if (a.prec == PREC_BF16) launch_count_p<PREC_BF16>(a, c, g, lds, st);
-    else launch_count_p<PREC_FP8>(a, c, g, lds, st);
+    if (a.prec == PREC_FP32) launch_count_p<PREC_FP32>(a, c, lds, st);
+    else if (a.prec == PREC_BF16) launch_count_p<PREC_BF16>(a, c, lds, st);
+    else launch_count_p<PREC_FP8>(a, c, lds, st);
 }
 
 // Eq. (3)/(6) bound count over the users of the item tile's Cauchy-Schwarz

@@ -38,16 +38,20 @@ struct UserSide {
     float *N;        // ||u|| rounded up
     float *Nh;       // ||u_q|| (quantized copy) rounded up
     float *R;        // ||u - u_q|| rounded up
-    float *s;        // power-of-two scale of the quantized copy
+    float *sinv;     // 1 / (power-of-two scale of the quantized copy), exact
     float *tau_hi;   // tau rounded up to FP32
     float *tau_lo;   // tau rounded down to FP32
     double *tau;     // exact tau
     int32_t *tau_id; // item id of the k-th element
     int32_t *uid;    // user id of this position
+    // the fields the counting kernel needs per user, in one 16-byte record:
+    // {tau_hi, tau_lo, R + c2 N, Nh}; with the items' largest N, Nh, R the
+    // bound is E = (R + c2 N) N_p + Nh (R_p + c Nh_p) + e_abs
+    float4 *thr;
 };
 void launch_user_side(const double *tau, const int32_t *tau_id, const float *Nu,
                       const float *Nhu, const float *Ru, const float *su,
-                      const int32_t *order, int64_t n, UserSide out, hipStream_t st);
+                      const int32_t *order, int64_t n, float c2, UserSide out, hipStream_t st);
 // Sort keys of the pruning ratio rho_u = tau_u / ||u|| rounded down to FP32
 // (-inf when tau_u <= 0 or ||u|| = 0), as ascending uint32 keys; val = user id.
 void launch_rho_keys(const double *tau, const float *Nu, int64_t n, uint32_t *key,

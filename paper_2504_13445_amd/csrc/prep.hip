@@ -218,7 +218,8 @@ void launch_invert_perm(const int32_t *perm, int64_t m, int32_t *inv, hipStream_
 __global__ void k_user_side(const double *__restrict__ tau, const int32_t *__restrict__ tau_id,
                             const float *__restrict__ Nu, const float *__restrict__ Nhu,
                             const float *__restrict__ Ru, const float *__restrict__ su,
-                            const int32_t *__restrict__ order, int64_t n, UserSide out) {
+                            const int32_t *__restrict__ order, int64_t n, float c2,
+                            UserSide out) {
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
     int64_t u = order ? order[r] : r;
@@ -226,19 +227,21 @@ __global__ void k_user_side(const double *__restrict__ tau, const int32_t *__res
     out.N[r] = Nu[u];
     out.Nh[r] = Nhu[u];
     out.R[r] = Ru[u];
-    out.s[r] = su[u];
+    out.sinv[r] = 1.0f / su[u];  // exact: su is a power of two
     out.tau_hi[r] = __double2float_ru(t);
     out.tau_lo[r] = __double2float_rd(t);
     out.tau[r] = t;
     out.tau_id[r] = tau_id[u];
     out.uid[r] = (int32_t)u;
+    out.thr[r] = make_float4(__double2float_ru(t), __double2float_rd(t), fmaf(c2, Nu[u], Ru[u]),
+                             Nhu[u]);
 }
 
 void launch_user_side(const double *tau, const int32_t *tau_id, const float *Nu,
                       const float *Nhu, const float *Ru, const float *su,
-                      const int32_t *order, int64_t n, UserSide out, hipStream_t st) {
+                      const int32_t *order, int64_t n, float c2, UserSide out, hipStream_t st) {
     k_user_side<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(tau, tau_id, Nu, Nhu, Ru, su, order,
-                                                             n, out);
+                                                             n, c2, out);
 }
 
 __global__ void k_rho_keys(const double *__restrict__ tau, const float *__restrict__ Nu,

@@ -103,8 +103,10 @@ void thresh_plan(int prec, int64_t n, int64_t m, int d, int k, int cap_override,
     L.rowb = L.D * elem_bytes(prec);
     L.ntiles = (int)((m + TILE_ITEMS - 1) / TILE_ITEMS);
     L.mpad = (int64_t)L.ntiles * TILE_ITEMS;
-    int64_t utiles = (n + 127) / 128;
-    int64_t ns = (3072 + utiles - 1) / utiles;
+    // splits of the item range: about six rounds of screening workgroups
+    // (256 users each, one per compute unit) over the whole chip
+    int64_t utiles = (n + 255) / 256;
+    int64_t ns = (1536 + utiles - 1) / utiles;
     ns = std::max<int64_t>(1, std::min<int64_t>(ns, 8));
     ns = std::min<int64_t>(ns, L.ntiles);
     L.nsplit = (int)ns;
@@ -345,12 +347,13 @@ void user_side_plan(int64_t n, UserSide &us, Carve &cv) {
     us.N = cv.take<float>(n);
     us.Nh = cv.take<float>(n);
     us.R = cv.take<float>(n);
-    us.s = cv.take<float>(n);
+    us.sinv = cv.take<float>(n);
     us.tau_hi = cv.take<float>(n);
     us.tau_lo = cv.take<float>(n);
     us.tau = cv.take<double>(n);
     us.tau_id = cv.take<int32_t>(n);
     us.uid = cv.take<int32_t>(n);
+    us.thr = cv.take<float4>(n);
 }
 
 void topn_plan(int prec, int64_t n, int64_t m, int d, int k, int cap_override, int bmax,
@@ -388,10 +391,13 @@ void topn_plan(int prec, int64_t n, int64_t m, int d, int k, int cap_override, i
     L.rechecks = cv.take<int64_t>(CTR_WORDS);
 }
 
+// splits of the user range of a counting launch: about four rounds of
+// counting workgroups (256 items each, one per compute unit), each split
+// with at least two 64-user chunks
 int count_splits(int64_t nb, int64_t ulen, int maxs) {
-    int64_t itiles = (nb + 63) / 64;
-    int64_t chunks = (ulen + 127) / 128;
-    int64_t s = (2048 + itiles - 1) / itiles;
+    int64_t iblocks = (nb + 255) / 256;
+    int64_t chunks = (ulen + 63) / 64;
+    int64_t s = (1024 + iblocks - 1) / iblocks;
     s = std::min<int64_t>(s, std::max<int64_t>(1, chunks / 2));
     return (int)std::max<int64_t>(1, std::min<int64_t>(s, maxs));
 }
@@ -558,7 +564,7 @@ rmips_status rmips_scores(rmips_ctx *ctx, const float *U, int64_t n, const doubl
         if (s != RMIPS_OK) return s;
     }
     const ErrConst ec = err_const(L.D, d);
-    launch_user_side(tau, tau_id, L.Nu, L.Nhu, L.Ru, L.su, nullptr, n, L.us, st);
+    launch_user_side(tau, tau_id, L.Nu, L.Nhu, L.Ru, L.su, nullptr, n, ec.c2, L.us, st);
     CountArgs a{};
     a.prec = prec;
     a.Pq = L.Qq; a.Np = L.Nq; a.Nhp = L.Nhq; a.Rp = L.Rq; a.sp = L.sq;
@@ -631,7 +637,8 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     launch_rho_keys(L.tau, L.T.Nu, n, L.ukeys, L.uperm, st);
     HIPTRY(radix_sort_u32(L.ukeys, L.uperm, n, L.usort, st));
     launch_cs_prefix(L.ukeys, n, L.T.Np, m, L.cs, st);
-    launch_user_side(L.tau, L.tau_id, L.T.Nu, L.T.Nhu, L.T.Ru, L.T.su, L.uperm, n, L.us, st);
+    launch_user_side(L.tau, L.tau_id, L.T.Nu, L.T.Nhu, L.T.Ru, L.T.su, L.uperm, n, ec.c2, L.us,
+                     st);
     launch_gather_padded(L.T.Uq, L.uperm, n, L.T.rowb, L.Us, st);
     HIPTRY(hipEventSynchronize(ev[3]));
     top_eigvecs(G, d, dp, W);

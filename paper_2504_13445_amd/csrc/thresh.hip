@@ -31,8 +31,6 @@
 
 namespace rmips {
 
-// Users per screening workgroup: 32 per wave, NW waves (4, or 2 when the
-// rows are long enough that four waves' users would not fit in LDS).
 
 // Bitonic sort of 32 registers, descending.
 __device__ __forceinline__ void cas_desc(float &a, float &b) {
@@ -70,25 +68,29 @@ __device__ __forceinline__ void merge32_desc(float (&v)[32]) {
     }
 }
 
-// Screening configuration: 4 waves of 32 users (the users' rows stay in
-// registers), nb item-tile buffers in LDS (2 = the next tile loads while
-// the current one is used), pf 16-byte vectors of a tile staged per thread
-// (0 = tiles load synchronously), nch 16-byte chunks per half row.
-constexpr int SCR_NW = 4;
-struct ScreenCfg { int nb, pf, nch; };
+// Screening configuration: 8 waves of 32 users (the users' rows stay in
+// registers), nb item-tile buffers in LDS (2 = the next tile is copied in
+// while the current one is used), nch 16-byte chunks per half row.
+constexpr int SCR_NW = 8;  // at most
+// 8 waves while a half row fits in 16 chunks (two waves per SIMD, 256
+// registers each); 4 for longer rows, whose waves need more registers
+__host__ __device__ constexpr int screen_waves(int nch) { return nch <= 16 ? 8 : 4; }
+// per tile buffer: N, Nh, R of the 64 items, then the tile's largest Nh and
+// R and its scale in the first three of 64 slots (copied in with the tile,
+// so that no global load is waited for)
+constexpr int NSTRIDE = 4 * TILE_ITEMS;
+struct ScreenCfg { int nb, nch; };
 
 size_t thresh_screen_lds_cfg(int prec, int D, int nb) {
     const int ls = lds_row_bytes(prec, D);
-    return (size_t)nb * TILE_ITEMS * ls + (size_t)nb * 3 * TILE_ITEMS * 4 +
+    return (size_t)nb * TILE_ITEMS * ls + (size_t)nb * NSTRIDE * 4 +
            32 * SCR_NW * sizeof(int) + 16 * sizeof(float);
 }
 
 ScreenCfg screen_cfg(int prec, int D) {
-    ScreenCfg c{2, 0, 0};
+    ScreenCfg c{2, 0};
     if (thresh_screen_lds_cfg(prec, D, 2) > 80 * 1024) c.nb = 1;
     c.nch = D * elem_bytes(prec) / 32;
-    const int need = TILE_ITEMS * D * elem_bytes(prec) / 16, nt = 64 * SCR_NW;
-    if (c.nb == 2 && c.nch <= 8 && need <= 4 * nt) c.pf = 4;
     return c;
 }
 
@@ -96,66 +98,23 @@ size_t thresh_screen_lds(int prec, int D) {
     return thresh_screen_lds_cfg(prec, D, screen_cfg(prec, D).nb);
 }
 
-// Item tile t (64 rows of D elements, and per item N, Nh, R) into registers,
-// then into LDS buffer b; or straight into LDS.
-struct TileIO {
-    const uint4 *src;   // the tile's rows, 16-byte vectors
-    int nvec;           // 16-byte vectors per tile
-    int w16;            // 16-byte vectors per row
-    int ls;             // LDS row stride (bytes)
-};
-
-template <int PFN, int NT>
-__device__ __forceinline__ void tile_fetch(uint4 (&pf)[PFN], float (&pn)[3], const ThreshArgs &a,
-                                           const TileIO &io, int t, int tid) {
-    const uint4 *src = io.src + (int64_t)t * io.nvec;
-#pragma unroll
-    for (int q = 0; q < PFN; ++q) {
-        const int e = tid + q * NT;
-        pf[q] = (e < io.nvec) ? src[e] : make_uint4(0, 0, 0, 0);
-    }
-    if (tid < TILE_ITEMS) {
-        const int64_t r = (int64_t)t * TILE_ITEMS + tid;
-        pn[0] = a.Np[r];
-        pn[1] = a.Nhp[r];
-        pn[2] = a.Rp[r];
-    }
-}
-
-template <int PFN, int NT>
-__device__ __forceinline__ void tile_stash(const uint4 (&pf)[PFN], const float (&pn)[3],
-                                           uint8_t *Pbase, float *Nbase, int b,
-                                           const TileIO &io, int tid) {
-#pragma unroll
-    for (int q = 0; q < PFN; ++q) {
-        const int e = tid + q * NT;
-        if (e < io.nvec) {
-            const int r = e / io.w16, c = e - r * io.w16;
-            *reinterpret_cast<uint4 *>(Pbase + (b * TILE_ITEMS + r) * io.ls + 16 * c) = pf[q];
-        }
-    }
-    if (tid < TILE_ITEMS) {
-        float *nb = Nbase + b * 3 * TILE_ITEMS;
-        nb[tid] = pn[0];
-        nb[TILE_ITEMS + tid] = pn[1];
-        nb[2 * TILE_ITEMS + tid] = pn[2];
-    }
-}
-
-template <int NT>
-__device__ __forceinline__ void tile_load(const ThreshArgs &a, const TileIO &io, int t,
-                                          uint8_t *Pbase, float *Nbase, int b, int tid) {
-    const uint4 *src = io.src + (int64_t)t * io.nvec;
-    for (int e = tid; e < io.nvec; e += NT) {
-        const int r = e / io.w16, c = e - r * io.w16;
-        *reinterpret_cast<uint4 *>(Pbase + (b * TILE_ITEMS + r) * io.ls + 16 * c) = src[e];
-    }
-    if (tid < TILE_ITEMS) {
-        const int64_t r = (int64_t)t * TILE_ITEMS + tid;
-        float *nb = Nbase + b * 3 * TILE_ITEMS;
-        nb[tid] = a.Np[r];
-        nb[TILE_ITEMS + tid] = a.Nhp[r];
-        nb[2 * TILE_ITEMS + tid] = a.Rp[r];
+// Item tile t (64 rows, and per item N, Nh, R, and the tile's scalars) into
+// LDS buffer b by direct copies; the last wave also takes the per-item
+// arrays.  Completion: dma_wait() and a barrier.
+template <int NW>
+__device__ __forceinline__ void tile_copy(const ThreshArgs &a, int t, int rowb, int w16,
+                                          uint32_t magic, int ls, uint8_t *Pbase, float *Nbase,
+                                          int b, int w, int lane) {
+    const int64_t rb = (int64_t)t * TILE_ITEMS;
+    rows_dma(reinterpret_cast<const uint8_t *>(a.Pq) + rb * rowb, rowb, w16, magic,
+             TILE_ITEMS - 1, Pbase + (size_t)b * TILE_ITEMS * ls, w, NW, lane);
+    if (w == NW - 1) {
+        float *nb = Nbase + b * NSTRIDE;
+        dma4(a.Np + rb + lane, nb);
+        dma4(a.Nhp + rb + lane, nb + TILE_ITEMS);
+        dma4(a.Rp + rb + lane, nb + 2 * TILE_ITEMS);
+        const float *sc = lane == 1 ? a.tmax_r + t : (lane == 2 ? a.sp + rb : a.tmax_nh + t);
+        dma4(sc, nb + 3 * TILE_ITEMS);
     }
 }
 
@@ -167,35 +126,18 @@ __device__ __forceinline__ int64_t screen_blocks(const ThreshArgs &a, int tu) {
     return (cnt + tu - 1) / tu;
 }
 
-// The next tile into the buffer not in use (NB = 2; from the registers
-// fetched earlier when PF > 0), or into the only buffer once every wave is
-// done with it (NB = 1).
-template <int PF, int NB, int PFN, int NT>
-__device__ __forceinline__ void tile_next(const uint4 (&pf)[PFN], const float (&pn)[3],
-                                          const ThreshArgs &a, const TileIO &io, int tn,
-                                          uint8_t *Pbase, float *Nbase, int buf, int tid) {
-    if (NB == 1) {
-        __syncthreads();
-        tile_load<NT>(a, io, tn, Pbase, Nbase, 0, tid);
-    } else if (PF > 0) {
-        tile_stash<PFN, NT>(pf, pn, Pbase, Nbase, buf ^ 1, io, tid);
-    } else {
-        tile_load<NT>(a, io, tn, Pbase, Nbase, buf ^ 1, tid);
-    }
-}
-
-template <int PREC, int PF, int NB, int NCH>
+template <int PREC, int NB, int NCH>
 // two waves per SIMD (the register budget of 256) where the row fits in
 // 16 chunks; longer FP32 rows keep all registers for one wave
-__global__ __launch_bounds__(64 * SCR_NW) __attribute__((amdgpu_waves_per_eu(NCH <= 16 ? 2 : 1)))
+__global__ __launch_bounds__(64 * screen_waves(NCH)) __attribute__((amdgpu_waves_per_eu(NCH <= 16 ? 2 : 1)))
 void k_thresh_screen(ThreshArgs a) {
-    constexpr int NW = SCR_NW, TU = 32 * NW, NT = 64 * NW;
+    constexpr int NW = screen_waves(NCH), TU = 32 * NW, NT = 64 * NW;
     extern __shared__ __align__(16) uint8_t smem8[];
     const int D = a.D, ls = lds_row_bytes(PREC, D), rowb = D * elem_bytes(PREC);
     const int nch = rowb / 32;
     uint8_t *Pbase = smem8;                                           // item tiles
     float *Nbase = reinterpret_cast<float *>(Pbase + NB * TILE_ITEMS * ls);  // N, Nh, R
-    int *cntsh = reinterpret_cast<int *>(Nbase + NB * 3 * TILE_ITEMS);
+    int *cntsh = reinterpret_cast<int *>(Nbase + NB * NSTRIDE);
     float *red = reinterpret_cast<float *>(cntsh + TU);
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -210,14 +152,7 @@ void k_thresh_screen(ThreshArgs a) {
     const int t0 = listed ? 0 : (a.t0tiles < a.ntiles ? a.t0tiles : a.ntiles);
     auto tile_of = [&](int it) { return it < t0 ? it : split + (it - t0) * a.nsplit; };
 
-    TileIO io;
-    io.src = reinterpret_cast<const uint4 *>(a.Pq);
-    io.w16 = w16;
-    io.nvec = TILE_ITEMS * w16;
-    io.ls = ls;
-    constexpr int PFN = PF > 0 ? PF : 1;
-    uint4 pf[PFN];
-    float pn[3] = {0.f, 0.f, 0.f};
+    const uint32_t magic = slot_magic(w16);
     unsigned long long pacc = 0;  // statistics: phase-2 pairs screened
 
     for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
@@ -236,6 +171,7 @@ void k_thresh_screen(ThreshArgs a) {
         const float nhu = uvalid ? a.Nhu[ug] : 0.0f;
         const float ru = uvalid ? a.Ru[ug] : 0.0f;
         const float su = uvalid ? a.su[ug] : 1.0f;
+        const float su_inv = pow2_rcp(su);
 
         // error bound of this user against an item: E(u,p)
         auto ebound = [&](float n_p, float nh_p, float r_p) {
@@ -263,12 +199,10 @@ void k_thresh_screen(ThreshArgs a) {
         }
         float2 *mycand = a.cand + (ug * a.nsplit + split) * a.cap;
 
-        if (PF > 0) {
-            tile_fetch<PFN, NT>(pf, pn, a, io, tile_of(0), tid);
-            tile_stash<PFN, NT>(pf, pn, Pbase, Nbase, 0, io, tid);
-        } else {
-            tile_load<NT>(a, io, tile_of(0), Pbase, Nbase, 0, tid);
-        }
+        // (the barrier at the top of this loop: the previous block is done
+        // with the tile buffers)
+        tile_copy<NW>(a, tile_of(0), rowb, w16, magic, ls, Pbase, Nbase, 0, w, lane);
+        dma_wait();
         __syncthreads();
         if (listed) {
             rwg = red[0];
@@ -286,12 +220,13 @@ void k_thresh_screen(ThreshArgs a) {
                 const int t = it;
                 const int tn = tile_of(it + 1);
                 const bool pre = tn < a.ntiles;
-                if (PF > 0 && pre) tile_fetch<PFN, NT>(pf, pn, a, io, tn, tid);
+                if (NB == 2 && pre)
+                    tile_copy<NW>(a, tn, rowb, w16, magic, ls, Pbase, Nbase, buf ^ 1, w, lane);
                 const uint8_t *Psh = Pbase + buf * TILE_ITEMS * ls;
-                const float *Nsh = Nbase + buf * 3 * TILE_ITEMS;
+                const float *Nsh = Nbase + buf * NSTRIDE;
                 const int64_t rb = (int64_t)t * TILE_ITEMS;
-                const float e_t = ebound(Nsh[0], a.tmax_nh[t], a.tmax_r[t]);
-                const float sc = su * a.sp[rb];
+                const float e_t = ebound(Nsh[0], Nsh[3 * TILE_ITEMS], Nsh[3 * TILE_ITEMS + 1]);
+                const float sc = su * Nsh[3 * TILE_ITEMS + 2];
                 f32x16 acc0 = {0}, acc1 = {0};
                 MMR<PREC, NCH>::rows2(acc0, acc1, Psh, Psh + 32 * ls, ub, ls, nch, D, lane);
 #pragma unroll
@@ -300,7 +235,11 @@ void k_thresh_screen(ThreshArgs a) {
                     if (rb + r < a.m) M[i] = fmaxf(M[i], fmaf(acc0[i], sc, -e_t));
                     if (rb + r + 32 < a.m) M[16 + i] = fmaxf(M[16 + i], fmaf(acc1[i], sc, -e_t));
                 }
-                if (pre) tile_next<PF, NB, PFN, NT>(pf, pn, a, io, tn, Pbase, Nbase, buf, tid);
+                if (NB == 1 && pre) {
+                    __syncthreads();  // every wave is done with the only buffer
+                    tile_copy<NW>(a, tn, rowb, w16, magic, ls, Pbase, Nbase, 0, w, lane);
+                }
+                if (pre) dma_wait();
                 __syncthreads();
                 if (NB == 2) buf ^= 1;
             }
@@ -326,25 +265,28 @@ void k_thresh_screen(ThreshArgs a) {
         for (int it = t0;; ++it) {
             const int t = tile_of(it);
             if (t >= a.ntiles) break;
-            if (a.Np[(int64_t)t * TILE_ITEMS] < rwg) break;  // Cauchy-Schwarz exit
+            const float *Nsh = Nbase + buf * NSTRIDE;
+            if (Nsh[0] < rwg) break;  // Cauchy-Schwarz exit (N is sorted: Nsh[0] is the largest)
             ++ntile_p2;
             const int tn = tile_of(it + 1);
             const bool pre = tn < a.ntiles;
-            if (PF > 0 && pre) tile_fetch<PFN, NT>(pf, pn, a, io, tn, tid);
+            if (NB == 2 && pre)
+                tile_copy<NW>(a, tn, rowb, w16, magic, ls, Pbase, Nbase, buf ^ 1, w, lane);
             const uint8_t *Psh = Pbase + buf * TILE_ITEMS * ls;
-            const float *Nsh = Nbase + buf * 3 * TILE_ITEMS;
             const int64_t rb = (int64_t)t * TILE_ITEMS;
-            // tile maxima: N is sorted (first item), Nh and R from the precomputed arrays
-            const float e_t = ebound(Nsh[0], a.tmax_nh[t], a.tmax_r[t]);
-            const float sc = su * a.sp[rb];  // product scale of this (user, tile)
+            // tile maxima: N is sorted (first item), Nh and R staged with the tile
+            const float e_t = ebound(Nsh[0], Nsh[3 * TILE_ITEMS], Nsh[3 * TILE_ITEMS + 1]);
+            const float sp_t = Nsh[3 * TILE_ITEMS + 2];
+            const float sc = su * sp_t;  // product scale of this (user, tile)
             f32x16 acc0 = {0}, acc1 = {0};
             MMR<PREC, NCH>::rows2(acc0, acc1, Psh, Psh + 32 * ls, ub, ls, nch, D, lane);
-            // first on the tile bound, then per item
-            const float thr = (L0 - e_t) / sc;  // exact: sc is a power of two
-            bool any = false;
+            // first on the tile bound, then per item; the scales are powers of
+            // two, so multiplying by their exact reciprocals divides exactly
+            const float thr = (L0 - e_t) * (su_inv * pow2_rcp(sp_t));
+            float vmax = fmaxf(acc0[0], acc1[0]);
 #pragma unroll
-            for (int i = 0; i < 16; ++i) any |= (acc0[i] >= thr) | (acc1[i] >= thr);
-            if (__ballot(any && uvalid) != 0ull) {
+            for (int i = 1; i < 16; ++i) vmax = fmaxf(vmax, fmaxf(acc0[i], acc1[i]));
+            if (__ballot(vmax >= thr && uvalid) != 0ull) {
 #pragma unroll
                 for (int i = 0; i < 32; ++i) {
                     const float v = ((i < 16) ? acc0[i] : acc1[i - 16]) * sc;
@@ -364,7 +306,11 @@ void k_thresh_screen(ThreshArgs a) {
                     }
                 }
             }
-            if (pre) tile_next<PF, NB, PFN, NT>(pf, pn, a, io, tn, Pbase, Nbase, buf, tid);
+            if (NB == 1 && pre) {
+                __syncthreads();  // every wave is done with the only buffer
+                tile_copy<NW>(a, tn, rowb, w16, magic, ls, Pbase, Nbase, 0, w, lane);
+            }
+            if (pre) dma_wait();
             __syncthreads();
             if (NB == 2) buf ^= 1;
         }
@@ -662,14 +608,8 @@ __global__ __launch_bounds__(64 * FB_WAVES) void k_thresh_fallback(ThreshArgs a)
 
 template <int PREC, int NCH>
 void launch_screen_n(const ThreshArgs &a, const ScreenCfg &c, dim3 g, size_t lds, hipStream_t st) {
-    if constexpr (NCH == 8) {
-        if (c.nb == 2 && c.pf == 4) {
-            k_thresh_screen<PREC, 4, 2, NCH><<<g, 256, lds, st>>>(a);
-            return;
-        }
-    }
-    if (c.nb == 2) k_thresh_screen<PREC, 0, 2, NCH><<<g, 256, lds, st>>>(a);
-    else k_thresh_screen<PREC, 0, 1, NCH><<<g, 256, lds, st>>>(a);
+    if (c.nb == 2) k_thresh_screen<PREC, 2, NCH><<<g, 64 * screen_waves(NCH), lds, st>>>(a);
+    else k_thresh_screen<PREC, 1, NCH><<<g, 64 * screen_waves(NCH), lds, st>>>(a);
 }
 
 template <int PREC>
@@ -681,7 +621,7 @@ void launch_screen(const ThreshArgs &a, const ScreenCfg &c, dim3 g, size_t lds, 
 
 void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
     const ScreenCfg c = screen_cfg(a0.prec, a0.D);
-    const int tu = 32 * SCR_NW;
+    const int tu = 32 * screen_waves(c.nch <= 8 ? 8 : (c.nch <= 16 ? 16 : 32));
     const size_t lds = thresh_screen_lds_cfg(a0.prec, a0.D, c.nb);
     const int64_t ublocks = (a0.n + tu - 1) / tu;
     const int capU = a0.cap * a0.nsplit;
