@@ -74,7 +74,7 @@ typedef struct rmips_ctx rmips_ctx;
 typedef struct {
     int64_t visited_items;    /* items whose exact score was computed */
     int64_t batches;          /* bound-ordered batches run */
-    int64_t cand_pairs;       /* stage (a): candidates rechecked in FP64 (survivors) */
+    int64_t cand_pairs;       /* stage (a): candidates recomputed in FP64 */
     int64_t overflow_users;   /* stage (a): users sent to the exact fallback */
     int64_t refine_users;     /* stage (a): users screened again with a tighter
                                  bound after their candidate lists overflowed */

@@ -407,12 +407,35 @@ __device__ __forceinline__ uint8_t to_e4m3(float y, float &q) {
 // Exact value of u . p: FP64 sum of the exact products of the FP32 inputs,
 // taken in index order from +0.0.  fma() adds the exact product with one
 // rounding, which is what a separate multiply (exact) and add would give.
-// The operands are loaded 16 at a time ahead of the dependent chain; the
-// zeros that pad the last block add +0, which leaves the sum unchanged (the
-// sum is never -0: it starts at +0 and +0 + -0 = +0).
+// The operands are loaded 16 at a time ahead of the dependent chain (as
+// 16-byte vectors when both rows are 16-byte aligned and d is a multiple
+// of 4); the zeros that pad the last block add +0, which leaves the sum
+// unchanged (the sum is never -0: it starts at +0 and +0 + -0 = +0).
 __device__ __forceinline__ double ip64(const float *__restrict__ u,
                                        const float *__restrict__ p, int d) {
     double acc = 0.0;
+    if ((d & 3) == 0 && ((reinterpret_cast<uintptr_t>(u) | reinterpret_cast<uintptr_t>(p)) & 15) == 0) {
+        const float4 *u4 = reinterpret_cast<const float4 *>(u);
+        const float4 *p4 = reinterpret_cast<const float4 *>(p);
+        const int d4 = d >> 2;
+        for (int i = 0; i < d4; i += 4) {
+            float4 x[4], y[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const bool ok = i + j < d4;
+                x[j] = ok ? u4[i + j] : make_float4(0.f, 0.f, 0.f, 0.f);
+                y[j] = ok ? p4[i + j] : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                acc = __fma_rn((double)x[j].x, (double)y[j].x, acc);
+                acc = __fma_rn((double)x[j].y, (double)y[j].y, acc);
+                acc = __fma_rn((double)x[j].z, (double)y[j].z, acc);
+                acc = __fma_rn((double)x[j].w, (double)y[j].w, acc);
+            }
+        }
+        return acc;
+    }
     for (int i = 0; i < d; i += 16) {
         float x[16], y[16];
 #pragma unroll

@@ -489,53 +489,100 @@ __global__ __launch_bounds__(256) void k_thresh_final(ThreshArgs a, int capT, in
         }
         const bool work = valid && !over;
         if (work && cs && lane == 0) atomicAdd(cs, (unsigned long long)total);
-        // survivors: upper bound reaches L*; keep their caller ids
+        // survivors: upper bound reaches L*; keep their caller ids, and
+        // their bounds in place (a survivor's slot is at most its index)
         if (work) {
             const float Ls = Lstar[w];
             int cntw = 0;
             for (int e0 = 0; e0 < total; e0 += 64) {
                 const int e = e0 + lane;
-                const bool keep = e < total && hi[e] >= Ls;
+                float l = 0.0f, h = 0.0f;
+                int c = 0;
+                if (e < total) {
+                    l = lo[e];
+                    h = hi[e];
+                    c = cidx[e];
+                }
+                const bool keep = e < total && h >= Ls;
                 const uint64_t bal = __ballot(keep);
                 const int p = cntw + __popcll(bal & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
-                if (keep) sid[p] = a.perm[cidx[e]];
+                __builtin_amdgcn_wave_barrier();
+                if (keep) {
+                    sid[p] = a.perm[c];
+                    lo[p] = l;
+                    hi[p] = h;
+                }
                 cntw += __popcll(bal);
             }
             if (lane == 0) nsurv[w] = cntw;
-            if (cs && lane == 0) atomicAdd(cs + 1, (unsigned long long)cntw);
         }
         __syncthreads();
+        // When only tau is asked for, a survivor whose lower bound exceeds the
+        // upper bounds of all but at most k - 2 others ranks above the k-th
+        // item; with A such survivors, tau is the (k - A)-th of the others, and
+        // only those are recomputed.  (Needs the lower bounds in candidate
+        // order, i.e. the rank path above.)
+        const bool band = a.topk == nullptr && stored <= 128;
+        int *rid = band ? cidx : sid;
         if (work) {
             const int ns = nsurv[w];
-            const float *urow = a.U + u * a.d;
-            for (int q = lane; q < ns; q += 64) v64[q] = ip64(urow, a.P + (int64_t)sid[q] * a.d, a.d);
-        }
-        __syncthreads();
-        if (work) {
-            const int ns = nsurv[w];
-            if (ns <= 128) {
-                for (int q = lane; q < ns; q += 64) {
-                    const double x = v64[q];
-                    const int c = sid[q];
-                    int rank = 0;
-                    for (int f = 0; f < ns; ++f) {
-                        const double y = v64[f];
-                        rank += (y > x) || (y == x && sid[f] < c);
+            int nrec = ns;
+            if (band) {
+                int cntb = 0;
+                for (int p0 = 0; p0 < ns; p0 += 64) {
+                    const int p = p0 + lane;
+                    bool unc = false;
+                    int id = 0;
+                    if (p < ns) {
+                        const float x = lo[p];
+                        int c = -1;  // the survivor itself
+                        for (int q = 0; q < ns; ++q) c += hi[q] >= x;
+                        unc = c > a.k - 2;
+                        id = sid[p];
                     }
-                    if (rank == a.k - 1) {
+                    const uint64_t bal = __ballot(unc);
+                    const int q = cntb + __popcll(bal & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+                    if (unc) cidx[q] = id;
+                    cntb += __popcll(bal);
+                }
+                nrec = cntb;
+            }
+            if (lane == 0) nsurv[w] = nrec | ((ns - nrec) << 16);
+            if (cs && lane == 0) atomicAdd(cs + 1, (unsigned long long)nrec);
+        }
+        __syncthreads();
+        if (work) {
+            const int nrec = nsurv[w] & 0xffff;
+            const float *urow = a.U + u * a.d;
+            for (int q = lane; q < nrec; q += 64) v64[q] = ip64(urow, a.P + (int64_t)rid[q] * a.d, a.d);
+        }
+        __syncthreads();
+        if (work) {
+            const int nrec = nsurv[w] & 0xffff, nabove = nsurv[w] >> 16;
+            const int tgt = a.k - 1 - nabove;  // rank of tau among the recomputed
+            if (nrec <= 128) {
+                for (int q = lane; q < nrec; q += 64) {
+                    const double x = v64[q];
+                    const int c = rid[q];
+                    int rank = 0;
+                    for (int f = 0; f < nrec; ++f) {
+                        const double y = v64[f];
+                        rank += (y > x) || (y == x && rid[f] < c);
+                    }
+                    if (rank == tgt) {
                         a.tau[u] = x;
                         a.tau_id[u] = c;
                     }
                     if (a.topk && rank < a.k) a.topk[u * a.k + rank] = c;
                 }
             } else {
-                wave_sort_pairs(v64, sid, ns, lane);
+                wave_sort_pairs(v64, rid, nrec, lane);
                 if (lane == 0) {
-                    a.tau[u] = v64[a.k - 1];
-                    a.tau_id[u] = sid[a.k - 1];
+                    a.tau[u] = v64[tgt];
+                    a.tau_id[u] = rid[tgt];
                 }
                 if (a.topk)
-                    for (int r = lane; r < a.k; r += 64) a.topk[u * a.k + r] = sid[r];
+                    for (int r = lane; r < a.k; r += 64) a.topk[u * a.k + r] = rid[r];
             }
         }
     }
