@@ -372,18 +372,39 @@ void launch_bound(const BoundArgs &a, hipStream_t st) {
     k_bound<<<g, 256, 0, st>>>(a);
 }
 
-__global__ void k_colsum(const int32_t *__restrict__ partial, int nsplit, int64_t cols,
-                         int32_t *__restrict__ out) {
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= cols) return;
+// out[j] = sum over q of partial[q][j].  A 256-thread block covers 16
+// columns with 16 threads each (a thread adds every 16th split, eight loads
+// in flight), then adds the 16 partial sums per column through LDS.
+__global__ __launch_bounds__(256) void k_colsum(const int32_t *__restrict__ partial, int nsplit,
+                                                int64_t cols, int32_t *__restrict__ out) {
+    __shared__ int part[16][17];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int64_t j = (int64_t)blockIdx.x * 16 + tx;
     int s = 0;
-    for (int q = 0; q < nsplit; ++q) s += partial[(int64_t)q * cols + j];
-    out[j] = s;
+    if (j < cols) {
+        int q = ty;
+        for (; q + 16 * 7 < nsplit; q += 16 * 8) {
+            int t[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) t[e] = partial[(int64_t)(q + 16 * e) * cols + j];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) s += t[e];
+        }
+        for (; q < nsplit; q += 16) s += partial[(int64_t)q * cols + j];
+    }
+    part[ty][tx] = s;
+    __syncthreads();
+    if (ty == 0 && j < cols) {
+        int t = 0;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) t += part[e][tx];
+        out[j] = t;
+    }
 }
 
 void launch_colsum(const int32_t *partial, int nsplit, int64_t cols, int32_t *out,
                    hipStream_t st) {
-    k_colsum<<<(unsigned)((cols + 255) / 256), 256, 0, st>>>(partial, nsplit, cols, out);
+    k_colsum<<<(unsigned)((cols + 15) / 16), 256, 0, st>>>(partial, nsplit, cols, out);
 }
 
 __global__ void k_visit_keys(const int32_t *__restrict__ us, const int32_t *__restrict__ inv,

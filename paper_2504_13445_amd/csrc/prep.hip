@@ -65,36 +65,47 @@ __global__ __launch_bounds__(256) void k_quant(const float *__restrict__ X,
                                                float *__restrict__ sc,
                                                unsigned int *__restrict__ rmax,
                                                int *__restrict__ flag) {
+    // 64 rows per block, 16 per wave; a row's values (D <= 256: at most 4
+    // per lane) stay in registers between the two passes
     __shared__ float rowmax[64];
+    __shared__ float rmx[4];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t r0 = (int64_t)blockIdx.x * 64;
-    // pass 1: max |x_i| per row
-    for (int i = w; i < 64; i += 4) {
-        const int64_t r = r0 + i;
-        float mx = 0.0f;
-        if (r < rows) {
-            const float *x = X + (int64_t)(order ? order[r] : r) * d;
-            bool bad = false;
-            for (int c = lane; c < d; c += 64) {
-                const float v = x[c];
-                bad |= !isfinite(v);
-                mx = fmaxf(mx, fabsf(v));
-            }
-            if (__ballot(bad) != 0ull && lane == 0) *flag = 1;
-        }
+    float v[16][4];
+    bool bad = false;
+    // pass 1: load, finiteness, max |x_i| per row
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
-        if (lane == 0) rowmax[i] = mx;
+    for (int j = 0; j < 16; ++j) {
+        const int64_t r = r0 + w + 4 * j;
+        const float *x = (r < rows) ? X + (int64_t)(order ? order[r] : r) * d : nullptr;
+        float mx = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = lane + 64 * q;
+            const float t = (x && c < d) ? x[c] : 0.0f;
+            v[j][q] = t;
+            bad |= !isfinite(t);
+            mx = fmaxf(mx, fabsf(t));
+        }
+        if (PREC == PREC_FP8) {
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+            if (lane == 0) rowmax[w + 4 * j] = mx;
+        }
     }
-    __syncthreads();
+    if (__ballot(bad) != 0ull && lane == 0) *flag = 1;
+    if (PREC == PREC_FP8) __syncthreads();
     // pass 2: quantize with the group's scale, residual sums in FP64
-    for (int i = w; i < 64; i += 4) {
+    float rrmax = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int i = w + 4 * j;
         const int64_t r = r0 + i;
         float s = 1.0f;
         if (PREC == PREC_FP8) {
             const int g0 = (i / group) * group;
             float mx = 0.0f;
-            for (int j = g0; j < g0 + group && j < 64; ++j) mx = fmaxf(mx, rowmax[j]);
+            for (int t = g0; t < g0 + group && t < 64; ++t) mx = fmaxf(mx, rowmax[t]);
             if (mx > 0.0f) {
                 // smallest power of two s with mx / s <= 448
                 int e;
@@ -105,32 +116,40 @@ __global__ __launch_bounds__(256) void k_quant(const float *__restrict__ X,
         }
         const float inv = 1.0f / s;  // exact: s is a power of two
         double sx = 0.0, sq = 0.0, sr = 0.0;
-        const float *x = (r < rows) ? X + (int64_t)(order ? order[r] : r) * d : nullptr;
-        for (int c = lane; c < D; c += 64) {
-            const float v = (x && c < d) ? x[c] : 0.0f;
-            float q;
-            if (PREC == PREC_FP32) {
-                q = v;
-                reinterpret_cast<float *>(Xq)[r * D + c] = v;
-            } else if (PREC == PREC_BF16) {
-                reinterpret_cast<uint16_t *>(Xq)[r * D + c] = to_bf16(v, q);
-            } else {
-                float yq;
-                Xq[r * D + c] = to_e4m3(v * inv, yq);
-                q = yq * s;
+        const bool live = r < rows_pad;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = lane + 64 * q;
+            if (c < D) {
+                const float t = v[j][q];
+                float qv;
+                if (PREC == PREC_FP32) {
+                    qv = t;
+                    if (live) reinterpret_cast<float *>(Xq)[r * D + c] = t;
+                } else if (PREC == PREC_BF16) {
+                    const uint16_t h = to_bf16(t, qv);
+                    if (live) reinterpret_cast<uint16_t *>(Xq)[r * D + c] = h;
+                } else {
+                    float yq;
+                    const uint8_t b8 = to_e4m3(t * inv, yq);
+                    if (live) Xq[r * D + c] = b8;
+                    qv = yq * s;
+                }
+                sx += (double)t * (double)t;
+                sq += (double)qv * (double)qv;
+                const double df = (double)t - (double)qv;  // exact: both are FP32
+                sr += df * df;
             }
-            sx += (double)v * (double)v;
-            sq += (double)q * (double)q;
-            const double df = (double)v - (double)q;  // exact: both are FP32
-            sr += df * df;
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
             sx += __shfl_xor(sx, o);
-            sq += __shfl_xor(sq, o);
-            sr += __shfl_xor(sr, o);
+            if (PREC != PREC_FP32) {
+                sq += __shfl_xor(sq, o);
+                sr += __shfl_xor(sr, o);
+            }
         }
-        if (lane == 0 && r < rows_pad) {
+        if (lane == 0 && live) {
             const double up = 1.0 + 0x1p-40;
             const float nx = __double2float_ru(sqrt(sx) * up);
             const float rr = (PREC == PREC_FP32) ? 0.0f : __double2float_ru(sqrt(sr) * up);
@@ -139,7 +158,18 @@ __global__ __launch_bounds__(256) void k_quant(const float *__restrict__ X,
             Nh[r] = (PREC == PREC_FP32) ? nx : __double2float_ru(sqrt(sq) * up);
             R[r] = rr;
             sc[r] = s;
-            if (rmax && nx > 0.0f) atomicMax(rmax, __float_as_uint(__double2float_ru((double)rr / (double)nx)));
+            if (nx > 0.0f && rr > 0.0f)
+                rrmax = fmaxf(rrmax, __double2float_ru((double)rr / (double)nx));
+        }
+    }
+    // largest R / N of the block, one atomic per block (non-negative floats
+    // order like their bit patterns)
+    if (rmax) {
+        if (lane == 0) rmx[w] = rrmax;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const float m = fmaxf(fmaxf(rmx[0], rmx[1]), fmaxf(rmx[2], rmx[3]));
+            if (m > 0.0f) atomicMax(rmax, __float_as_uint(m));
         }
     }
 }

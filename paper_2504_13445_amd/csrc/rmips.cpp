@@ -161,7 +161,8 @@ rmips_status run_thresholds(rmips_ctx *ctx, const float *U, int64_t n, const flo
                             int64_t m, int d, int k, ThreshLayout &L, double *tau,
                             int32_t *tau_id, int32_t *topk,
                             unsigned long long *pairs = nullptr, hipEvent_t ev0 = nullptr,
-                            hipEvent_t ev1 = nullptr, unsigned long long *cstats = nullptr) {
+                            hipEvent_t ev1 = nullptr, unsigned long long *cstats = nullptr,
+                            bool check_now = true) {
     hipStream_t st = ctx->stream;
     HIPTRY(hipMemsetAsync(L.bad, 0, sizeof(int), st));
     HIPTRY(hipMemsetAsync(L.rmax, 0, sizeof(unsigned int), st));
@@ -173,8 +174,12 @@ rmips_status run_thresholds(rmips_ctx *ctx, const float *U, int64_t n, const flo
     launch_quant(L.prec, U, nullptr, n, n, d, L.D, 1, L.Uq, L.Nu, L.Nhu, L.Ru, L.su, nullptr,
                  L.bad, st);
     HIPTRY(hipGetLastError());
-    rmips_status s = check_bad(ctx, L.bad);
-    if (s != RMIPS_OK) return s;
+    if (check_now) {
+        // (otherwise the caller reads L.bad at its next synchronisation;
+        // the kernels below stay in bounds whatever the values)
+        rmips_status s = check_bad(ctx, L.bad);
+        if (s != RMIPS_OK) return s;
+    }
 
     const ErrConst ec = err_const(L.D, d);
     ThreshArgs a{};
@@ -619,29 +624,32 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     HIPTRY(hipMemsetAsync(ctr, 0, CTR_WORDS * sizeof(unsigned long long), st));
     HIPTRY(hipEventRecord(ev[0], st));
 
-    // ---- stage (a): exact thresholds
-    s = run_thresholds(ctx, U, n, P, m, d, k, L.T, L.tau, L.tau_id, nullptr, ctr + CTR_PAIRS,
-                       ev[4], ev[5], ctr + CTR_CS);
-    if (s != RMIPS_OK) return s;
-    HIPTRY(hipEventRecord(ev[1], st));
-
-    // ---- stage (c): Cauchy-Schwarz prefix and Eq. (3)/(6) bound counts
-    // The rotation's Gram matrix goes to the host first; the host computes
-    // its eigenvectors while the GPU orders the users.
+    // The Gram matrix of a user sample (for the rotation of Eq. (3)) does
+    // not depend on tau: it goes to the host first, and the host computes
+    // its eigenvectors while the GPU runs stage (a).
     const int dp = std::min(DPRIME, d);
     const int64_t ns = std::min<int64_t>(n, GRAM_SAMPLE);
     launch_gram(U, ns, n / ns, d, L.G, L.Gs, st);
     std::vector<double> G((size_t)d * d), W;
     HIPTRY(hipMemcpyAsync(G.data(), L.G, sizeof(double) * d * d, hipMemcpyDeviceToHost, st));
     HIPTRY(hipEventRecord(ev[3], st));
+
+    // ---- stage (a): exact thresholds (the input check is read at the
+    // synchronisation before stage (b))
+    s = run_thresholds(ctx, U, n, P, m, d, k, L.T, L.tau, L.tau_id, nullptr, ctr + CTR_PAIRS,
+                       ev[4], ev[5], ctr + CTR_CS, false);
+    if (s != RMIPS_OK) return s;
+    HIPTRY(hipEventRecord(ev[1], st));
+    HIPTRY(hipEventSynchronize(ev[3]));
+    top_eigvecs(G, d, dp, W);
+
+    // ---- stage (c): Cauchy-Schwarz prefix and Eq. (3)/(6) bound counts
     launch_rho_keys(L.tau, L.T.Nu, n, L.ukeys, L.uperm, st);
     HIPTRY(radix_sort_u32(L.ukeys, L.uperm, n, L.usort, st));
     launch_cs_prefix(L.ukeys, n, L.T.Np, m, L.cs, st);
     launch_user_side(L.tau, L.tau_id, L.T.Nu, L.T.Nhu, L.T.Ru, L.T.su, L.uperm, n, ec.c2, L.us,
                      st);
     launch_gather_padded(L.T.Uq, L.uperm, n, L.T.rowb, L.Us, st);
-    HIPTRY(hipEventSynchronize(ev[3]));
-    top_eigvecs(G, d, dp, W);
     HIPTRY(hipMemcpyAsync(L.W, W.data(), sizeof(double) * dp * d, hipMemcpyHostToDevice, st));
     // slack of the bound: covers FP32 rounding of W x, of the tail and of
     // the 12-term matrix-core sum (each well below 2^-23 relative)
@@ -665,8 +673,11 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     std::vector<int32_t> h_us(m), h_cs(m);
     HIPTRY(hipMemcpyAsync(h_us.data(), L.vis_us, sizeof(int32_t) * m, hipMemcpyDeviceToHost, st));
     HIPTRY(hipMemcpyAsync(h_cs.data(), L.vis_cs, sizeof(int32_t) * m, hipMemcpyDeviceToHost, st));
+    HIPTRY(hipMemcpyAsync(ctx->h_status + 12, L.T.bad, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPTRY(hipEventRecord(ev[2], st));
     HIPTRY(hipStreamSynchronize(st));
+    if (ctx->h_status[12] != 0)
+        return fail(ctx, RMIPS_ENONFINITE, "input holds a NaN/Inf or a vector norm above 2^60");
 
     // ---- stage (b): exact scores in bound order, running top-N, stop rule
     ctx->h_status[8] = -1;  // N-th score unknown

@@ -388,6 +388,13 @@ __device__ void wave_sort_pairs(double *v, int *id, int n, int lane) {
 
 constexpr int FIN_WAVES = 4;
 
+// Orders this wave's LDS accesses (every list of the final selection is
+// private to one wave, so no workgroup barrier is needed).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // One wave per user.  The lists of the user's splits are gathered into
 // LDS with lower and upper bounds vh -/+ E; L* = k-th largest lower bound.
 // A user whose lists overflowed is not resolved here: the k-th largest lower
@@ -431,7 +438,7 @@ __global__ __launch_bounds__(256) void k_thresh_final(ThreshArgs a, int capT, in
         const float nu = valid ? a.Nu[u] : 0.0f;
         const float nhu = valid ? a.Nhu[u] : 0.0f;
         const float ru = valid ? a.Ru[u] : 0.0f;
-        __syncthreads();  // the previous users' LDS lists are consumed
+        wave_sync();  // this wave's previous user is done with its LDS lists
         if (lane == 0) Lstar[w] = -INFINITY;
         if (valid && stored <= capT) {
             int off = 0;
@@ -453,7 +460,7 @@ __global__ __launch_bounds__(256) void k_thresh_final(ThreshArgs a, int capT, in
                 off += c;
             }
         }
-        __syncthreads();
+        wave_sync();
         // L* = k-th largest lower bound: by ranks for short lists, else by
         // sorting the lower bounds (the upper bounds and rows stay in place)
         if (valid && stored <= capT) {
@@ -472,7 +479,7 @@ __global__ __launch_bounds__(256) void k_thresh_final(ThreshArgs a, int capT, in
                 if (lane == 0) Lstar[w] = lo[a.k - 1];
             }
         }
-        __syncthreads();
+        wave_sync();
         if (valid && over) {
             if (lane == 0) {
                 const float Lprev = a.Luse[u];
@@ -516,7 +523,7 @@ __global__ __launch_bounds__(256) void k_thresh_final(ThreshArgs a, int capT, in
             }
             if (lane == 0) nsurv[w] = cntw;
         }
-        __syncthreads();
+        wave_sync();
         // When only tau is asked for, a survivor whose lower bound exceeds the
         // upper bounds of all but at most k - 2 others ranks above the k-th
         // item; with A such survivors, tau is the (k - A)-th of the others, and
@@ -550,13 +557,13 @@ __global__ __launch_bounds__(256) void k_thresh_final(ThreshArgs a, int capT, in
             if (lane == 0) nsurv[w] = nrec | ((ns - nrec) << 16);
             if (cs && lane == 0) atomicAdd(cs + 1, (unsigned long long)nrec);
         }
-        __syncthreads();
+        wave_sync();
         if (work) {
             const int nrec = nsurv[w] & 0xffff;
             const float *urow = a.U + u * a.d;
             for (int q = lane; q < nrec; q += 64) v64[q] = ip64(urow, a.P + (int64_t)rid[q] * a.d, a.d);
         }
-        __syncthreads();
+        wave_sync();
         if (work) {
             const int nrec = nsurv[w] & 0xffff, nabove = nsurv[w] >> 16;
             const int tgt = a.k - 1 - nabove;  // rank of tau among the recomputed
