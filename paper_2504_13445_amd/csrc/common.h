@@ -407,7 +407,7 @@ __device__ __forceinline__ uint8_t to_e4m3(float y, float &q) {
 // Exact value of u . p: FP64 sum of the exact products of the FP32 inputs,
 // taken in index order from +0.0.  fma() adds the exact product with one
 // rounding, which is what a separate multiply (exact) and add would give.
-// The operands are loaded 16 at a time ahead of the dependent chain (as
+// The operands are loaded 8 at a time ahead of the dependent chain (as
 // 16-byte vectors when both rows are 16-byte aligned and d is a multiple
 // of 4); the zeros that pad the last block add +0, which leaves the sum
 // unchanged (the sum is never -0: it starts at +0 and +0 + -0 = +0).
@@ -418,16 +418,16 @@ __device__ __forceinline__ double ip64(const float *__restrict__ u,
         const float4 *u4 = reinterpret_cast<const float4 *>(u);
         const float4 *p4 = reinterpret_cast<const float4 *>(p);
         const int d4 = d >> 2;
-        for (int i = 0; i < d4; i += 4) {
-            float4 x[4], y[4];
+        for (int i = 0; i < d4; i += 2) {
+            float4 x[2], y[2];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < 2; ++j) {
                 const bool ok = i + j < d4;
                 x[j] = ok ? u4[i + j] : make_float4(0.f, 0.f, 0.f, 0.f);
                 y[j] = ok ? p4[i + j] : make_float4(0.f, 0.f, 0.f, 0.f);
             }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < 2; ++j) {
                 acc = __fma_rn((double)x[j].x, (double)y[j].x, acc);
                 acc = __fma_rn((double)x[j].y, (double)y[j].y, acc);
                 acc = __fma_rn((double)x[j].z, (double)y[j].z, acc);
@@ -436,16 +436,16 @@ __device__ __forceinline__ double ip64(const float *__restrict__ u,
         }
         return acc;
     }
-    for (int i = 0; i < d; i += 16) {
-        float x[16], y[16];
+    for (int i = 0; i < d; i += 8) {
+        float x[8], y[8];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
+        for (int j = 0; j < 8; ++j) {
             const bool ok = i + j < d;
             x[j] = ok ? u[i + j] : 0.0f;
             y[j] = ok ? p[i + j] : 0.0f;
         }
 #pragma unroll
-        for (int j = 0; j < 16; ++j) acc = __fma_rn((double)x[j], (double)y[j], acc);
+        for (int j = 0; j < 8; ++j) acc = __fma_rn((double)x[j], (double)y[j], acc);
     }
     return acc;
 }

@@ -89,7 +89,8 @@ struct ThreshArgs {
     const float *U; const float *P; int d;      // original FP32 rows (recheck)
     int D; int k; int t0tiles; int nsplit; int cap;
     float c_err; float c2; float e_abs; float g64;
-    float2 *cand; int32_t *cand_cnt;
+    // candidate lists: (screened value, its error bound E) and the caller's id
+    float2 *cand; int32_t *cand_id; int32_t *cand_cnt;
     double *tau; int32_t *tau_id; int32_t *topk;
     // overflow handling: lists (3 x n: two refinement lists, the fallback
     // list) with their counters (4 ints), refinement passes (0..2), and the

@@ -91,6 +91,7 @@ struct ThreshLayout {
     int32_t *perm;
     void *sort_scratch;
     float2 *cand;
+    int32_t *cand_id;
     int32_t *cand_cnt, *lists, *lcnt;
     float *Luse;
     int *bad;
@@ -139,6 +140,7 @@ void thresh_plan(int prec, int64_t n, int64_t m, int d, int k, int cap_override,
     L.perm = cv.take<int32_t>(m);
     L.sort_scratch = cv.take<uint8_t>(radix_sort_scratch_bytes(m));
     L.cand = cv.take<float2>((size_t)n * L.nsplit * L.cap);
+    L.cand_id = cv.take<int32_t>((size_t)n * L.nsplit * L.cap);
     // counts per (user, split); refinement passes use up to 8 splits
     L.cand_cnt = cv.take<int32_t>((size_t)n * 8);
     L.lists = cv.take<int32_t>((size_t)3 * n);
@@ -191,7 +193,7 @@ rmips_status run_thresholds(rmips_ctx *ctx, const float *U, int64_t n, const flo
     a.U = U; a.P = P; a.d = d;
     a.D = L.D; a.k = k; a.t0tiles = T0_TILES; a.nsplit = L.nsplit; a.cap = L.cap;
     a.c_err = ec.c; a.c2 = ec.c2; a.e_abs = E_ABS; a.g64 = ec.g64;
-    a.cand = L.cand; a.cand_cnt = L.cand_cnt;
+    a.cand = L.cand; a.cand_id = L.cand_id; a.cand_cnt = L.cand_cnt;
     a.lists = L.lists; a.lcnt = L.lcnt; a.refine = 2; a.Luse = L.Luse;
     a.tau = tau; a.tau_id = tau_id; a.topk = topk;
     a.pairs = pairs; a.ev0 = ev0; a.ev1 = ev1; a.cstats = cstats;

@@ -75,10 +75,10 @@ constexpr int SCR_NW = 8;  // at most
 // 8 waves while a half row fits in 16 chunks (two waves per SIMD, 256
 // registers each); 4 for longer rows, whose waves need more registers
 __host__ __device__ constexpr int screen_waves(int nch) { return nch <= 16 ? 8 : 4; }
-// per tile buffer: N, Nh, R of the 64 items, then the tile's largest Nh and
-// R and its scale in the first three of 64 slots (copied in with the tile,
-// so that no global load is waited for)
-constexpr int NSTRIDE = 4 * TILE_ITEMS;
+// per tile buffer: N, Nh, R of the 64 items, the tile's largest Nh and R
+// and its scale in the first three of 64 slots, and the items' caller ids
+// (copied in with the tile, so that no global load is waited for)
+constexpr int NSTRIDE = 5 * TILE_ITEMS;
 struct ScreenCfg { int nb, nch; };
 
 size_t thresh_screen_lds_cfg(int prec, int D, int nb) {
@@ -115,6 +115,8 @@ __device__ __forceinline__ void tile_copy(const ThreshArgs &a, int t, int rowb, 
         dma4(a.Rp + rb + lane, nb + 2 * TILE_ITEMS);
         const float *sc = lane == 1 ? a.tmax_r + t : (lane == 2 ? a.sp + rb : a.tmax_nh + t);
         dma4(sc, nb + 3 * TILE_ITEMS);
+        const int64_t pr = rb + lane < a.m ? rb + lane : a.m - 1;  // padding rows: never candidates
+        dma4(a.perm + pr, nb + 4 * TILE_ITEMS);
     }
 }
 
@@ -198,6 +200,7 @@ void k_thresh_screen(ThreshArgs a) {
             if (lane == 0) red[w] = rr;
         }
         float2 *mycand = a.cand + (ug * a.nsplit + split) * a.cap;
+        int32_t *mycid = a.cand_id + (ug * a.nsplit + split) * a.cap;
 
         // (the barrier at the top of this loop: the previous block is done
         // with the tile buffers)
@@ -297,11 +300,13 @@ void k_thresh_screen(ThreshArgs a) {
                     // for all 32 slots at once, which costs registers)
                     __asm__ volatile("" ::: "memory");
                     if (p) {
-                        const float h =
-                            v + ebound(Nsh[r], Nsh[TILE_ITEMS + r], Nsh[2 * TILE_ITEMS + r]);
-                        if (h >= L0) {
+                        const float eb = ebound(Nsh[r], Nsh[TILE_ITEMS + r], Nsh[2 * TILE_ITEMS + r]);
+                        if (v + eb >= L0) {
                             int s = atomicAdd(&cntsh[ucol], 1);
-                            if (s < a.cap) mycand[s] = make_float2(v, __int_as_float((int)(rb + r)));
+                            if (s < a.cap) {
+                                mycand[s] = make_float2(v, eb);
+                                mycid[s] = __float_as_int(Nsh[4 * TILE_ITEMS + r]);
+                            }
                         }
                     }
                 }
@@ -403,7 +408,8 @@ __device__ __forceinline__ void wave_sync() {
 // improve on the bound used, the user goes to the exact fallback.
 // capT: longest candidate list taken; capP: array stride, capT rounded up
 // to a power of two so that the bitonic sorts can pad in place.
-__global__ __launch_bounds__(256) void k_thresh_final(ThreshArgs a, int capT, int capP) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6)))
+void k_thresh_final(ThreshArgs a, int capT, int capP) {
     extern __shared__ float smem[];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int nw = blockDim.x >> 6;  // waves per block (one user each)
@@ -435,9 +441,6 @@ __global__ __launch_bounds__(256) void k_thresh_final(ThreshArgs a, int capT, in
             }
             if (stored > capT) over = true;  // cannot happen: nsplit * cap <= capT
         }
-        const float nu = valid ? a.Nu[u] : 0.0f;
-        const float nhu = valid ? a.Nhu[u] : 0.0f;
-        const float ru = valid ? a.Ru[u] : 0.0f;
         wave_sync();  // this wave's previous user is done with its LDS lists
         if (lane == 0) Lstar[w] = -INFINITY;
         if (valid && stored <= capT) {
@@ -446,16 +449,12 @@ __global__ __launch_bounds__(256) void k_thresh_final(ThreshArgs a, int capT, in
                 int c = a.cand_cnt[u * a.nsplit + s];
                 c = c < a.cap ? c : a.cap;
                 const float2 *src = a.cand + (u * a.nsplit + s) * a.cap;
+                const int32_t *sidp = a.cand_id + (u * a.nsplit + s) * a.cap;
                 for (int e = lane; e < c; e += 64) {
-                    const float2 cv = src[e];
-                    const int idx = __float_as_int(cv.y);
-                    const float eb = fmaf(
-                        ru, a.Np[idx],
-                        fmaf(nhu, a.Rp[idx],
-                             fmaf(a.c_err * nhu, a.Nhp[idx], fmaf(a.c2 * nu, a.Np[idx], a.e_abs))));
-                    lo[off + e] = cv.x - eb;
-                    hi[off + e] = cv.x + eb;
-                    cidx[off + e] = idx;
+                    const float2 cv = src[e];  // (screened value, its bound E)
+                    lo[off + e] = cv.x - cv.y;
+                    hi[off + e] = cv.x + cv.y;
+                    cidx[off + e] = sidp[e];
                 }
                 off += c;
             }
@@ -515,7 +514,7 @@ __global__ __launch_bounds__(256) void k_thresh_final(ThreshArgs a, int capT, in
                 const int p = cntw + __popcll(bal & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
                 __builtin_amdgcn_wave_barrier();
                 if (keep) {
-                    sid[p] = a.perm[c];
+                    sid[p] = c;
                     lo[p] = l;
                     hi[p] = h;
                 }
