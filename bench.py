@@ -35,7 +35,96 @@ def parse():
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run a plain copy of this many MiB first (counter calibration)")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the other screening precisions on the same workload")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this "
+                         "bench into profiles/traffic.json and exit")
     return ap.parse_args()
+
+
+# Sources whose change makes a committed traffic measurement stale.
+TRAFFIC_SOURCES = ["paper_2504_13445_amd/csrc/common.h", "paper_2504_13445_amd/csrc/kernels.h",
+                   "paper_2504_13445_amd/csrc/thresh.hip", "paper_2504_13445_amd/csrc/count.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def _sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def pmc_summary(fetch_dir, write_dir):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of each kernel in two
+    rocprofv3 --pmc runs of this bench that began with --calib-copy-mib: the
+    copy kernel of known size gives the counters' scale factors."""
+    import csv
+    import glob
+
+    def load(d, counter):
+        out = {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] != counter:
+                    continue
+                name = r["Kernel_Name"]
+                out.setdefault(name, []).append(float(r["Counter_Value"]))
+        return out
+
+    fetch, write = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
+
+    def copy_kib(tab):
+        # the calibration copy: the elementwise kernel with the largest value
+        vals = [max(v) for k, v in tab.items() if "elementwise" in k or "vectorized" in k]
+        return max(vals) if vals else None
+
+    calib = os.path.join(ROOT, "gpurun_out", "bench_calib.json")
+    info = json.load(open(calib)) if os.path.exists(calib) else {}
+    mib = info.get("copy_mib", 256)
+    kib = mib * 1024.0
+    cf, cw = copy_kib(fetch), copy_kib(write)
+    ff = kib / cf if cf else None
+    fw = kib / cw if cw else None
+    kernels = {}
+    for name in sorted(set(fetch) | set(write)):
+        if not name.startswith(("void rmips::", "rmips::")):
+            continue
+        short = name.split("(")[0].replace("void ", "").replace("rmips::", "")
+        f_ = fetch.get(name, [])
+        w_ = write.get(name, [])
+        kernels[short] = {
+            "dispatches": max(len(f_), len(w_)),
+            "fetch_kib_max": max(f_) if f_ else None,
+            "write_kib_max": max(w_) if w_ else None,
+            "fetch_bytes_max": max(f_) * 1024 * ff if f_ and ff else None,
+            "write_bytes_max": max(w_) * 1024 * fw if w_ and fw else None,
+        }
+    out = {"copy_mib": mib, "fetch_factor": ff, "write_factor": fw,
+           "src_sha256": _sources_hash(), "workload": info.get("workload"),
+           "prec": info.get("prec"), "kernels": kernels}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+
+
+def committed_traffic(kernel, workload, prec):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when it was taken on other sources, workload or precision."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get("src_sha256") != _sources_hash() or t.get("workload") != workload or \
+            t.get("prec") != prec:
+        return None
+    k = t["kernels"].get(kernel)
+    if not k or k.get("fetch_bytes_max") is None or k.get("write_bytes_max") is None:
+        return None
+    return k["fetch_bytes_max"] + k["write_bytes_max"]
 
 
 def cpu_baseline(U, P, k, target_s):
@@ -61,8 +150,26 @@ def cpu_baseline(U, P, k, target_s):
                       f"{n} users x all {m} items"}
 
 
+def run_topn(rm, Ug, Pg, k, N, prec, ws, steps, warmup):
+    """Time `steps` rmips_topn calls after `warmup` untimed ones."""
+    import torch
+    for _ in range(warmup):
+        rm.topn(Ug, Pg, k, N, prec, ws=ws)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ids, sc, st = rm.topn(Ug, Pg, k, N, prec, ws=ws)
+        stats.append(st)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return ids, sc, stats, dt
+
+
 def main():
     args = parse()
+    if args.pmc_summary:
+        return pmc_summary(*args.pmc_summary)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
               "(the path shards by users across GPUs only in design).", file=sys.stderr)
@@ -90,16 +197,7 @@ def main():
     ws = rm.topn_workspace(n, m, d, k, N, prec, dev)
     torch.cuda.synchronize()
 
-    for _ in range(args.warmup):
-        rm.topn(Ug, Pg, k, N, prec, ws=ws)
-    torch.cuda.synchronize()
-    stats = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ids, sc, st = rm.topn(Ug, Pg, k, N, prec, ws=ws)
-        stats.append(st)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    ids, sc, stats, dt = run_topn(rm, Ug, Pg, k, N, prec, ws, args.steps, args.warmup)
     ms = dt / args.steps * 1e3
     value = n * m / (dt / args.steps) / 1e9
 
@@ -122,17 +220,40 @@ def main():
     tot_ms, nl, flops, peak = kern[name]
     per_launch_s = tot_ms / nl / 1e3
     achieved = flops / per_launch_s if per_launch_s > 0 else 0.0
+    workload = (f"{cfg.name}: n={n} users, m={m} items, d={d}, k={k}, N={N}, "
+                f"seed {cfg.seed}")
+    traffic = committed_traffic(name, workload, prec)
+    if args.calib_copy_mib:
+        with open(os.path.join(ROOT, "gpurun_out", "bench_calib.json"), "w") as fh:
+            json.dump({"copy_mib": args.calib_copy_mib, "workload": workload, "prec": prec}, fh)
+    # the same workload through the other screening precisions (same steps),
+    # with identical integer outputs required
+    variants = {}
+    if not args.no_variants:
+        for vp in ("fp32", "bf16", "fp8"):
+            if vp == prec:
+                continue
+            wsv = rm.topn_workspace(n, m, d, k, N, vp, dev)
+            vids, vsc, vst, vdt = run_topn(rm, Ug, Pg, k, N, vp, wsv, args.steps, args.warmup)
+            del wsv
+            variants[vp] = {
+                "ms_per_step": vdt / args.steps * 1e3,
+                "value": n * m / (vdt / args.steps) / 1e9,
+                "same_top_n": vids.tolist() == ids.tolist() and vsc.tolist() == sc.tolist(),
+                "screen_kernel_ms": float(np.mean([x["ms_screen"] for x in vst])),
+                "count_kernels_ms": float(np.mean([x["ms_count_kernels"] for x in vst])),
+                "recheck_pairs": float(np.mean([x["recheck_pairs"] for x in vst])),
+            }
     out = {
         "metric": "top-N end-to-end G user-item pairs/s (exact)",
         "value": value, "unit": "G pairs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": prec, "data": "synthetic",
-        "config": {"workload": f"{cfg.name}: n={n} users, m={m} items, d={d}, k={k}, N={N}, "
-                               f"{prec} screening, seed {cfg.seed}",
+        "config": {"workload": workload, "screening": prec,
                    "n": n, "m": m, "d": d, "k": k, "N": N, "parallelism": "single GPU"},
         "roofline": {"kernel": name, "bound": "mfma",
                      "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": traffic,
                      "avg_launch_ms": per_launch_s * 1e3,
                      "algorithmic_flops_per_launch": flops},
         "stages_ms": {"thresholds": avg("ms_thresh"), "bounds": avg("ms_bound"),
@@ -145,6 +266,7 @@ def main():
         "cand_pairs": avg("cand_pairs"), "overflow_users": avg("overflow_users"),
         "refine_users": avg("refine_users"),
         "top_ids": ids.tolist(), "top_scores": sc.tolist(),
+        "variants": variants,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(U, P, k, args.cpu_seconds)
