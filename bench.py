@@ -121,8 +121,14 @@ def committed_traffic(kernel, workload, prec):
     if t.get("src_sha256") != _sources_hash() or t.get("workload") != workload or \
             t.get("prec") != prec:
         return None
-    k = t["kernels"].get(kernel)
-    if not k or k.get("fetch_bytes_max") is None or k.get("write_bytes_max") is None:
+    # the kernel's instantiation for the full user set (not the refinement
+    # passes over a user list, which are instantiated separately)
+    names = [x for x in t["kernels"] if x == kernel or
+             (x.startswith(kernel + "<") and not x.endswith("true>"))]
+    if not names:
+        return None
+    k = max((t["kernels"][x] for x in names), key=lambda v: v.get("fetch_bytes_max") or 0)
+    if k.get("fetch_bytes_max") is None or k.get("write_bytes_max") is None:
         return None
     return k["fetch_bytes_max"] + k["write_bytes_max"]
 

@@ -128,7 +128,8 @@ __device__ __forceinline__ int64_t screen_blocks(const ThreshArgs &a, int tu) {
     return (cnt + tu - 1) / tu;
 }
 
-template <int PREC, int NB, int NCH>
+// LISTED: a refinement pass over a user list (its own kernel symbol)
+template <int PREC, int NB, int NCH, bool LISTED>
 // two waves per SIMD (the register budget of 256) where the row fits in
 // 16 chunks; longer FP32 rows keep all registers for one wave
 __global__ __launch_bounds__(64 * screen_waves(NCH)) __attribute__((amdgpu_waves_per_eu(NCH <= 16 ? 2 : 1)))
@@ -146,7 +147,7 @@ void k_thresh_screen(ThreshArgs a) {
     const int split = blockIdx.y;
     const int w16 = rowb / 16;
     const int ucol = w * 32 + (lane & 31);
-    const bool listed = a.ulist != nullptr;
+    constexpr bool listed = LISTED;
     const int64_t nlist = listed ? (int64_t)*a.ulist_cnt : a.n;
     const int64_t nblk = screen_blocks(a, TU);
     const float rmax = __uint_as_float(*a.rmax_bits);
@@ -408,6 +409,7 @@ __device__ __forceinline__ void wave_sync() {
 // improve on the bound used, the user goes to the exact fallback.
 // capT: longest candidate list taken; capP: array stride, capT rounded up
 // to a power of two so that the bitonic sorts can pad in place.
+template <bool LISTED>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6)))
 void k_thresh_final(ThreshArgs a, int capT, int capP) {
     extern __shared__ float smem[];
@@ -422,7 +424,7 @@ void k_thresh_final(ThreshArgs a, int capT, int capP) {
     int *sid = cidx + capP;
     __shared__ float Lstar[FIN_WAVES];
     __shared__ int nsurv[FIN_WAVES];
-    const bool listed = a.ulist != nullptr;
+    constexpr bool listed = LISTED;
     const int64_t nlist = listed ? (int64_t)*a.ulist_cnt : a.n;
     unsigned long long *cs = a.cstats ? a.cstats + (blockIdx.x & (CSTAT_SLOTS - 1)) * 4 : nullptr;
 
@@ -661,8 +663,13 @@ __global__ __launch_bounds__(64 * FB_WAVES) void k_thresh_fallback(ThreshArgs a)
 
 template <int PREC, int NCH>
 void launch_screen_n(const ThreshArgs &a, const ScreenCfg &c, dim3 g, size_t lds, hipStream_t st) {
-    if (c.nb == 2) k_thresh_screen<PREC, 2, NCH><<<g, 64 * screen_waves(NCH), lds, st>>>(a);
-    else k_thresh_screen<PREC, 1, NCH><<<g, 64 * screen_waves(NCH), lds, st>>>(a);
+    if (a.ulist) {
+        if (c.nb == 2) k_thresh_screen<PREC, 2, NCH, true><<<g, 64 * screen_waves(NCH), lds, st>>>(a);
+        else k_thresh_screen<PREC, 1, NCH, true><<<g, 64 * screen_waves(NCH), lds, st>>>(a);
+    } else {
+        if (c.nb == 2) k_thresh_screen<PREC, 2, NCH, false><<<g, 64 * screen_waves(NCH), lds, st>>>(a);
+        else k_thresh_screen<PREC, 1, NCH, false><<<g, 64 * screen_waves(NCH), lds, st>>>(a);
+    }
 }
 
 template <int PREC>
@@ -701,7 +708,7 @@ void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
     if (a.ev0) (void)hipEventRecord(a.ev0, st);
     screen(a, dim3((unsigned)ublocks, (unsigned)a.nsplit));
     if (a.ev1) (void)hipEventRecord(a.ev1, st);
-    k_thresh_final<<<(unsigned)fblocks, 64 * fw, lds_fin, st>>>(a, capU, capP);
+    k_thresh_final<false><<<(unsigned)fblocks, 64 * fw, lds_fin, st>>>(a, capU, capP);
     // refinement passes over the users whose lists overflowed: the same
     // per-user capacity in fewer, longer lists per split
     int nsr = capU / 64;
@@ -720,7 +727,7 @@ void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
         const int64_t gx = ublocks < 1024 / nsr ? ublocks : 1024 / nsr;
         screen(b, dim3((unsigned)gx, (unsigned)nsr));
         const int64_t gf = fblocks < 2048 ? fblocks : 2048;
-        k_thresh_final<<<(unsigned)gf, 64 * fw, lds_fin, st>>>(b, b.nsplit * b.cap, capP);
+        k_thresh_final<true><<<(unsigned)gf, 64 * fw, lds_fin, st>>>(b, b.nsplit * b.cap, capP);
     }
     int64_t fb = (a0.n + FB_WAVES - 1) / FB_WAVES;
     if (fb > 1024) fb = 1024;
