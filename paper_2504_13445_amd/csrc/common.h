@@ -407,10 +407,12 @@ __device__ __forceinline__ uint8_t to_e4m3(float y, float &q) {
 // Exact value of u . p: FP64 sum of the exact products of the FP32 inputs,
 // taken in index order from +0.0.  fma() adds the exact product with one
 // rounding, which is what a separate multiply (exact) and add would give.
-// The operands are loaded 8 at a time ahead of the dependent chain (as
-// 16-byte vectors when both rows are 16-byte aligned and d is a multiple
-// of 4); the zeros that pad the last block add +0, which leaves the sum
-// unchanged (the sum is never -0: it starts at +0 and +0 + -0 = +0).
+// The operands are loaded a block at a time ahead of the dependent chain,
+// with no branch between the loads (as 16-byte vectors when both rows are
+// 16-byte aligned and d is a multiple of 4).  In the last, partial block
+// indexes past the end are clamped (every load stays in bounds) and their
+// values replaced by zeros, which add +0 and leave the sum unchanged (the
+// sum is never -0: it starts at +0 and +0 + -0 = +0).
 __device__ __forceinline__ double ip64(const float *__restrict__ u,
                                        const float *__restrict__ p, int d) {
     double acc = 0.0;
@@ -423,8 +425,10 @@ __device__ __forceinline__ double ip64(const float *__restrict__ u,
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
                 const bool ok = i + j < d4;
-                x[j] = ok ? u4[i + j] : make_float4(0.f, 0.f, 0.f, 0.f);
-                y[j] = ok ? p4[i + j] : make_float4(0.f, 0.f, 0.f, 0.f);
+                const int t = ok ? i + j : d4 - 1;
+                const float4 a = u4[t], b = p4[t];
+                x[j] = ok ? a : make_float4(0.f, 0.f, 0.f, 0.f);
+                y[j] = ok ? b : make_float4(0.f, 0.f, 0.f, 0.f);
             }
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
@@ -441,8 +445,10 @@ __device__ __forceinline__ double ip64(const float *__restrict__ u,
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const bool ok = i + j < d;
-            x[j] = ok ? u[i + j] : 0.0f;
-            y[j] = ok ? p[i + j] : 0.0f;
+            const int t = ok ? i + j : d - 1;
+            const float a = u[t], b = p[t];
+            x[j] = ok ? a : 0.0f;
+            y[j] = ok ? b : 0.0f;
         }
 #pragma unroll
         for (int j = 0; j < 8; ++j) acc = __fma_rn((double)x[j], (double)y[j], acc);

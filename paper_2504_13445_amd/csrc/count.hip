@@ -200,15 +200,19 @@ void k_count(CountArgs a) {
         f32x16 acc0 = {0}, acc1 = {0};
         // rows: this wave's items (shared); columns: the two user blocks
         MMR<PREC, NCH>::cols2(acc0, acc1, ia, Ub, Ub + 32 * ls, ls, nch, D, lane);
-        // counts, and whether any pair falls between the two thresholds
+        // counts, and whether any pair falls between the two thresholds:
+        // with e = med3(v, tout, tin) (tout <= tin), v > tin <=> v > e and
+        // tout <= v <= tin <=> v == e
         bool anyamb = false;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const float v0 = (PREC == PREC_FP8) ? acc0[i] * srow[i] : acc0[i];
             const float v1 = (PREC == PREC_FP8) ? acc1[i] * srow[i] : acc1[i];
-            const bool in0 = v0 > tin0, in1 = v1 > tin1;
-            cnt[i] += (in0 ? 1 : 0) + (in1 ? 1 : 0);
-            anyamb |= (!in0 && v0 >= tout0) || (!in1 && v1 >= tout1);
+            const float e0 = __builtin_amdgcn_fmed3f(v0, tout0, tin0);
+            const float e1 = __builtin_amdgcn_fmed3f(v1, tout1, tin1);
+            cnt[i] += (int)(v0 > e0);
+            cnt[i] += (int)(v1 > e1);
+            anyamb |= (v0 == e0) | (v1 == e1);
         }
         if (__ballot(anyamb) != 0ull) {
             uint32_t ambm0 = 0, ambm1 = 0;
@@ -216,8 +220,8 @@ void k_count(CountArgs a) {
             for (int i = 0; i < 16; ++i) {
                 const float v0 = (PREC == PREC_FP8) ? acc0[i] * srow[i] : acc0[i];
                 const float v1 = (PREC == PREC_FP8) ? acc1[i] * srow[i] : acc1[i];
-                ambm0 |= (!(v0 > tin0) && v0 >= tout0) ? (1u << i) : 0u;
-                ambm1 |= (!(v1 > tin1) && v1 >= tout1) ? (1u << i) : 0u;
+                ambm0 |= (v0 == __builtin_amdgcn_fmed3f(v0, tout0, tin0)) ? (1u << i) : 0u;
+                ambm1 |= (v1 == __builtin_amdgcn_fmed3f(v1, tout1, tin1)) ? (1u << i) : 0u;
             }
             ambm0 = c0 ? (ambm0 & rvalid) : 0u;
             ambm1 = c1 ? (ambm1 & rvalid) : 0u;
