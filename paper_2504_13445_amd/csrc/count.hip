@@ -225,19 +225,20 @@ void k_count(CountArgs a) {
             }
             ambm0 = c0 ? (ambm0 & rvalid) : 0u;
             ambm1 = c1 ? (ambm1 & rvalid) : 0u;
-#pragma unroll 1
-            for (int i = 0; i < 32; ++i) {
-                const bool p = ((i < 16 ? ambm0 : ambm1) >> (i & 15)) & 1u;
-                if (p) {
-                    const int rl = w * 32 + mfma32_row(i & 15, lane);
-                    const int64_t us = (i < 16) ? us0 : us1;
-                    const int s = atomicAdd(ambn, 1);
-                    if (s < AMB_CAP) {
-                        amb[s] = make_int2(rl, (int)us);
-                    } else {
-                        const int64_t row = a.rows ? a.rows[ib + rl] : ib + rl;
-                        if (recheck_pair(a, row, us)) atomicAdd(&cntl[rl], 1);
-                    }
+            // this lane's ambiguous pairs, one set bit at a time (bit i:
+            // register i & 15 of block i >> 4)
+            uint32_t pend = ambm0 | (ambm1 << 16);
+            while (pend != 0u) {
+                const int i = __builtin_ctz(pend);
+                pend &= pend - 1u;
+                const int rl = w * 32 + mfma32_row(i & 15, lane);
+                const int64_t us = (i < 16) ? us0 : us1;
+                const int s = atomicAdd(ambn, 1);
+                if (s < AMB_CAP) {
+                    amb[s] = make_int2(rl, (int)us);
+                } else {
+                    const int64_t row = a.rows ? a.rows[ib + rl] : ib + rl;
+                    if (recheck_pair(a, row, us)) atomicAdd(&cntl[rl], 1);
                 }
             }
         }
