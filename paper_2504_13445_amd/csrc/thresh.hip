@@ -120,6 +120,19 @@ __device__ __forceinline__ void tile_copy(const ThreshArgs &a, int t, int rowb, 
     }
 }
 
+// Element i (0..31) of the pair of accumulators (register i & 15 of block
+// i >> 4) for a per-lane i, by selects (no dynamic register index).
+__device__ __forceinline__ float pick32(const f32x16 &a0, const f32x16 &a1, int i) {
+    const int j = i & 15;
+    float x = a0[0], y = a1[0];
+#pragma unroll
+    for (int q = 1; q < 16; ++q) {
+        x = (j == q) ? a0[q] : x;
+        y = (j == q) ? a1[q] : y;
+    }
+    return (i & 16) ? y : x;
+}
+
 // Users of one screening workgroup: 32 per wave.  Without a user list the
 // grid covers all users once; with one (refinement passes) the workgroups
 // stride over the list, whose length is read on the device.
@@ -291,23 +304,27 @@ void k_thresh_screen(ThreshArgs a) {
 #pragma unroll
             for (int i = 1; i < 16; ++i) vmax = fmaxf(vmax, fmaxf(acc0[i], acc1[i]));
             if (__ballot(vmax >= thr && uvalid) != 0ull) {
+                // this lane's slots that pass the tile bound (bit i: register
+                // i & 15 of block i >> 4), then each of them once
+                uint32_t pend = 0u;
 #pragma unroll
-                for (int i = 0; i < 32; ++i) {
-                    const float v = ((i < 16) ? acc0[i] : acc1[i - 16]) * sc;
-                    const int r = mfma32_row(i & 15, lane) + ((i < 16) ? 0 : 32);
-                    const bool p = uvalid && ((i < 16) ? acc0[i] : acc1[i - 16]) >= thr &&
-                                   rb + r < a.m;
-                    // keep the rare path's LDS reads in place (not hoisted
-                    // for all 32 slots at once, which costs registers)
-                    __asm__ volatile("" ::: "memory");
-                    if (p) {
-                        const float eb = ebound(Nsh[r], Nsh[TILE_ITEMS + r], Nsh[2 * TILE_ITEMS + r]);
-                        if (v + eb >= L0) {
-                            int s = atomicAdd(&cntsh[ucol], 1);
-                            if (s < a.cap) {
-                                mycand[s] = make_float2(v, eb);
-                                mycid[s] = __float_as_int(Nsh[4 * TILE_ITEMS + r]);
-                            }
+                for (int i = 0; i < 16; ++i) {
+                    pend |= (acc0[i] >= thr) ? (1u << i) : 0u;
+                    pend |= (acc1[i] >= thr) ? (1u << (16 + i)) : 0u;
+                }
+                if (!uvalid) pend = 0u;
+                while (pend != 0u) {
+                    const int i = __builtin_ctz(pend);
+                    pend &= pend - 1u;
+                    const int r = mfma32_row(i & 15, lane) + (i >> 4) * 32;
+                    if (rb + r >= a.m) continue;  // padding rows of the last tile
+                    const float v = pick32(acc0, acc1, i) * sc;
+                    const float eb = ebound(Nsh[r], Nsh[TILE_ITEMS + r], Nsh[2 * TILE_ITEMS + r]);
+                    if (v + eb >= L0) {
+                        const int sl = atomicAdd(&cntsh[ucol], 1);
+                        if (sl < a.cap) {
+                            mycand[sl] = make_float2(v, eb);
+                            mycid[sl] = __float_as_int(Nsh[4 * TILE_ITEMS + r]);
                         }
                     }
                 }
