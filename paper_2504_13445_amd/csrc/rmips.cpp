@@ -94,6 +94,9 @@ struct ThreshLayout {
     int32_t *cand_id;
     int32_t *cand_cnt, *lists, *lcnt;
     float *Luse;
+    uint32_t *ukey;
+    int32_t *uord, *nall;
+    void *usort;
     int *bad;
 };
 
@@ -146,6 +149,10 @@ void thresh_plan(int prec, int64_t n, int64_t m, int d, int k, int cap_override,
     L.lists = cv.take<int32_t>((size_t)3 * n);
     L.lcnt = cv.take<int32_t>(64);
     L.Luse = cv.take<float>(n);
+    L.ukey = cv.take<uint32_t>(n);
+    L.uord = cv.take<int32_t>(n);
+    L.usort = cv.take<uint8_t>(radix_sort_scratch_bytes(n));
+    L.nall = cv.take<int32_t>(64);
     L.bad = cv.take<int>(64);
 }
 
@@ -195,6 +202,7 @@ rmips_status run_thresholds(rmips_ctx *ctx, const float *U, int64_t n, const flo
     a.c_err = ec.c; a.c2 = ec.c2; a.e_abs = E_ABS; a.g64 = ec.g64;
     a.cand = L.cand; a.cand_id = L.cand_id; a.cand_cnt = L.cand_cnt;
     a.lists = L.lists; a.lcnt = L.lcnt; a.refine = 2; a.Luse = L.Luse;
+    a.ukey = L.ukey; a.uord = L.uord; a.usort = L.usort; a.nall = L.nall;
     a.tau = tau; a.tau_id = tau_id; a.topk = topk;
     a.pairs = pairs; a.ev0 = ev0; a.ev1 = ev1; a.cstats = cstats;
     if (thresh_screen_lds(L.prec, L.D) > 160 * 1024 || (size_t)final_stride(L.cap * L.nsplit) * 24 > 150 * 1024)

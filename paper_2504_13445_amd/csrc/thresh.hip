@@ -278,6 +278,11 @@ void k_thresh_screen(ThreshArgs a) {
 #pragma unroll
             for (int q = 1; q < NW; ++q) rwg = fminf(rwg, red[q]);
         }
+        if (a.phase1_only) {
+            // the bounds-only pass: keep L0 and go to the next block
+            if (split == 0 && lane < 32 && uvalid) a.Luse[ug] = L0;
+            continue;
+        }
         // phase 2 (tiles split, split + nsplit, ...): candidates vh + E >= L0
         for (int it = t0;; ++it) {
             const int t = tile_of(it);
@@ -696,6 +701,21 @@ void launch_screen(const ThreshArgs &a, const ScreenCfg &c, dim3 g, size_t lds, 
     else launch_screen_n<PREC, 32>(a, c, g, lds, st);
 }
 
+// Sort keys of the users' early-exit ratios (ascending): the norm below
+// which no item reaches the user's starting bound, as in the screening
+// kernel; users whose bound is not positive scan every tile (ratio 0).
+__global__ void k_exit_keys(ThreshArgs a, uint32_t *__restrict__ key, int32_t *__restrict__ val) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= a.n) return;
+    const float rmax = __uint_as_float(*a.rmax_bits);
+    const float nu = a.Nu[u], nhu = a.Nhu[u], ru = a.Ru[u], L = a.Luse[u];
+    const float K = nu * (1.0f + a.g64 + 2.0f * a.c2) + 2.0f * ru +
+                    2.0f * nhu * (rmax + a.c_err * (1.0f + rmax));
+    const float rr = (L > 2.0f * a.e_abs && K > 0.0f) ? (L - 2.0f * a.e_abs) / K : 0.0f;
+    key[u] = float_key(rr);
+    val[u] = (int32_t)u;
+}
+
 void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
     const ScreenCfg c = screen_cfg(a0.prec, a0.D);
     const int tu = 32 * screen_waves(c.nch <= 8 ? 8 : (c.nch <= 16 ? 16 : 32));
@@ -714,10 +734,24 @@ void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
         else if (a.prec == PREC_BF16) launch_screen<PREC_BF16>(a, c, g, lds, st);
         else launch_screen<PREC_FP8>(a, c, g, lds, st);
     };
-    // pass 0: all users, bound from phase 1
+    // bounds-only pass: every user's L0 from the first tiles (phase 1)
+    ThreshArgs b0 = a0;
+    b0.ulist = nullptr;
+    b0.ulist_cnt = nullptr;
+    b0.phase1_only = 1;
+    b0.nsplit = 1;
+    b0.pairs = nullptr;
+    screen(b0, dim3((unsigned)ublocks, 1u));
+    // users in the order of their early-exit ratios, so that the users of a
+    // workgroup stop their scans at about the same tile
+    k_exit_keys<<<(unsigned)((a0.n + 255) / 256), 256, 0, st>>>(a0, a0.ukey, a0.uord);
+    (void)radix_sort_u32(a0.ukey, a0.uord, a0.n, a0.usort, st);
+    (void)hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(a0.nall), (int)a0.n, 1, st);
+    // main pass: all users, in that order, from their L0
     ThreshArgs a = a0;
-    a.ulist = nullptr;
-    a.ulist_cnt = nullptr;
+    a.ulist = a0.uord;
+    a.ulist_cnt = a0.nall;
+    a.phase1_only = 0;
     a.rlist = a0.refine > 0 ? LA : nullptr;
     a.rcnt = a0.lcnt;
     a.flist = LF;
@@ -725,7 +759,7 @@ void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
     if (a.ev0) (void)hipEventRecord(a.ev0, st);
     screen(a, dim3((unsigned)ublocks, (unsigned)a.nsplit));
     if (a.ev1) (void)hipEventRecord(a.ev1, st);
-    k_thresh_final<false><<<(unsigned)fblocks, 64 * fw, lds_fin, st>>>(a, capU, capP);
+    k_thresh_final<true><<<(unsigned)fblocks, 64 * fw, lds_fin, st>>>(a, capU, capP);
     // refinement passes over the users whose lists overflowed: the same
     // per-user capacity in fewer, longer lists per split
     int nsr = capU / 64;
