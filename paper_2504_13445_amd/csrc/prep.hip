@@ -414,12 +414,23 @@ __global__ __launch_bounds__(256) void k_rotate_aug(const float *__restrict__ X,
 #pragma unroll
     for (int j = 0; j < DP_MAX; ++j) y[j] = 0.0;
     double s = 0.0;
-    for (int i = 0; i < d; ++i) {
-        const double xi = (double)x[i];
-        s += xi * xi;
+    // the row in blocks of 16 values loaded ahead of the FP64 products
+    // (indexes past the end are clamped: every load stays in bounds)
+    for (int i0 = 0; i0 < d; i0 += 16) {
+        float xv[16];
 #pragma unroll
-        for (int j = 0; j < DP_MAX; ++j)
-            if (j < dp) y[j] += Ws[j * d + i] * xi;
+        for (int q = 0; q < 16; ++q) xv[q] = x[(i0 + q < d) ? i0 + q : d - 1];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            if (i0 + q < d) {
+                const int i = i0 + q;
+                const double xi = (double)xv[q];
+                s += xi * xi;
+#pragma unroll
+                for (int j = 0; j < DP_MAX; ++j)
+                    if (j < dp) y[j] += Ws[j * d + i] * xi;
+            }
+        }
     }
     double y2 = 0.0;
     float ov[16];
