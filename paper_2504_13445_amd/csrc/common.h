@@ -200,9 +200,15 @@ template <> struct MM<PREC_FP8> {
 };
 
 // Same products with the stationary operand held in registers: each lane's
-// half row as NCH 16-byte chunks (FP32: 4 elements, BF16: 8, FP8: 16);
-// nch <= NCH chunks are used.  rows2: c0 += A0 B^T, c1 += A1 B^T with B in
-// registers; cols2: c0 += A B0^T, c1 += A B1^T with A in registers.
+// half row as NCH 16-byte chunks (FP32: 4 elements, BF16: 8, FP8: 16).
+// rows2: c0 += A0 B^T, c1 += A1 B^T with B in registers; cols2: c0 += A
+// B0^T, c1 += A B1^T with A in registers.  FP32 stops after the row's nch
+// chunks (each read feeds four products).  BF16 and FP8 multiply all NCH
+// chunks, without branches, so that the LDS reads run ahead of the products:
+// the register chunks past nch are zero and add exact zeros, and the LDS
+// reads past a row end stay in the next row or in the LDS_GUARD bytes of
+// zeros that follow each buffer (finite values, so 0 * x = 0).
+constexpr int LDS_GUARD = 512;  // >= 16 * (32 - 1) bytes of overread
 template <int PREC, int NCH> struct MMR;
 
 template <int NCH> struct MMR<PREC_FP32, NCH> {
@@ -256,12 +262,10 @@ template <int NCH> struct MMR<PREC_BF16, NCH> {
         const int off = (lane & 31) * ls + (lane >> 5) * (D / 2) * 2;
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
-            if (c < nch) {
             const bf16x8 x0 = *reinterpret_cast<const bf16x8 *>(A0 + off + 16 * c);
             const bf16x8 x1 = *reinterpret_cast<const bf16x8 *>(A1 + off + 16 * c);
             c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x0, as_bf(b[c]), c0, 0, 0, 0);
             c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x1, as_bf(b[c]), c1, 0, 0, 0);
-            }
         }
     }
     static __device__ __forceinline__ void cols2(f32x16 &c0, f32x16 &c1, const uint4 (&a)[NCH],
@@ -270,12 +274,10 @@ template <int NCH> struct MMR<PREC_BF16, NCH> {
         const int off = (lane & 31) * ls + (lane >> 5) * (D / 2) * 2;
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
-            if (c < nch) {
             const bf16x8 y0 = *reinterpret_cast<const bf16x8 *>(B0 + off + 16 * c);
             const bf16x8 y1 = *reinterpret_cast<const bf16x8 *>(B1 + off + 16 * c);
             c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(a[c]), y0, c0, 0, 0, 0);
             c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(a[c]), y1, c1, 0, 0, 0);
-            }
         }
     }
 };
@@ -291,7 +293,6 @@ template <int NCH> struct MMR<PREC_FP8, NCH> {
         const int off = (lane & 31) * ls + (lane >> 5) * (D / 2);
 #pragma unroll
         for (int c = 0; c + 1 < NCH; c += 2) {
-            if (c < nch) {
             const i32x8 x0 = MM<PREC_FP8>::ld32(A0 + off + 16 * c);
             const i32x8 x1 = MM<PREC_FP8>::ld32(A1 + off + 16 * c);
             const i32x8 y = pair(b[c], b[c + 1]);
@@ -299,7 +300,6 @@ template <int NCH> struct MMR<PREC_FP8, NCH> {
                                                                  0, 0x7f7f7f7f);
             c1 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x1, y, c1, 0, 0, 0, 0x7f7f7f7f,
                                                                  0, 0x7f7f7f7f);
-            }
         }
     }
     static __device__ __forceinline__ void cols2(f32x16 &c0, f32x16 &c1, const uint4 (&a)[NCH],
@@ -308,7 +308,6 @@ template <int NCH> struct MMR<PREC_FP8, NCH> {
         const int off = (lane & 31) * ls + (lane >> 5) * (D / 2);
 #pragma unroll
         for (int c = 0; c + 1 < NCH; c += 2) {
-            if (c < nch) {
             const i32x8 x = pair(a[c], a[c + 1]);
             const i32x8 y0 = MM<PREC_FP8>::ld32(B0 + off + 16 * c);
             const i32x8 y1 = MM<PREC_FP8>::ld32(B1 + off + 16 * c);
@@ -316,10 +315,15 @@ template <int NCH> struct MMR<PREC_FP8, NCH> {
                                                                  0, 0x7f7f7f7f);
             c1 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x, y1, c1, 0, 0, 0, 0x7f7f7f7f,
                                                                  0, 0x7f7f7f7f);
-            }
         }
     }
 };
+
+// Index (0..3) of the SIMD that runs this wave: bits 5:4 of the HW_ID
+// hardware register.
+__device__ __forceinline__ int simd_id() {
+    return __builtin_amdgcn_s_getreg((1 << 11) | (4 << 6) | 4) & 3;  // hwreg(HW_ID, 4, 2)
+}
 
 // 1 / x for a power of two x whose reciprocal is a normal float: exact.
 __device__ __forceinline__ float pow2_rcp(float x) {

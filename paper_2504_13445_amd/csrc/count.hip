@@ -13,8 +13,6 @@
 
 namespace rmips {
 
-constexpr int CI = 64;    // items per bound-count workgroup
-constexpr int CU = 128;   // users per streamed chunk of the bound kernel
 
 // Sum of a per-slot count over the 32 lanes of each half-wave; afterwards
 // lanes 0 and 32 hold the totals of their rows.
@@ -43,7 +41,8 @@ struct CountCfg { int nb, nch; };
 
 size_t count_lds_cfg(int prec, int D, int nb) {
     const int ls = lds_row_bytes(prec, D);
-    return (size_t)nb * CNT_USERS * ls + AMB_CAP * sizeof(int2) + 32 * CNT_NW * sizeof(int) + 16;
+    return (size_t)nb * (CNT_USERS * ls + LDS_GUARD) + AMB_CAP * sizeof(int2) +
+           32 * CNT_NW * sizeof(int) + 32;
 }
 
 CountCfg count_cfg(int prec, int D) {
@@ -81,9 +80,11 @@ void k_count(CountArgs a) {
     extern __shared__ __align__(16) uint8_t smem8[];
     const int D = a.D, ls = lds_row_bytes(PREC, D), w16 = D * elem_bytes(PREC) / 16;
     const int rowb = D * elem_bytes(PREC), nch = rowb / 32;
+    // each user buffer is followed by LDS_GUARD bytes of zeros
+    const int bstride = CNT_USERS * ls + LDS_GUARD;
     uint8_t *Ush0 = smem8;
-    uint8_t *Ush1 = Ush0 + (NB - 1) * CNT_USERS * ls;
-    int2 *amb = reinterpret_cast<int2 *>(Ush0 + NB * CNT_USERS * ls);
+    uint8_t *Ush1 = Ush0 + (NB - 1) * bstride;
+    int2 *amb = reinterpret_cast<int2 *>(Ush0 + NB * bstride);
     int *cntl = reinterpret_cast<int *>(amb + AMB_CAP);
     int *ambn = cntl + CNT_ITEMS;
 
@@ -102,6 +103,10 @@ void k_count(CountArgs a) {
     }
     if (tid < CNT_ITEMS) cntl[tid] = 0;
     if (tid == 0) *ambn = 0;
+    if (tid < NB * LDS_GUARD / 16) {
+        const int g = tid / (LDS_GUARD / 16), e = tid % (LDS_GUARD / 16);
+        reinterpret_cast<uint4 *>(Ush0 + g * bstride + CNT_USERS * ls)[e] = make_uint4(0, 0, 0, 0);
+    }
 
     // largest N, Nh, R among this wave's 32 items; row validity bits; row scales
     float mn = 0.0f, mh = 0.0f, mr = 0.0f;
@@ -179,27 +184,35 @@ void k_count(CountArgs a) {
     };
     int nall = 0;  // pairs listed (statistics)
 
+    // Phases: the two waves that share a SIMD work in opposite order
+    // between the barriers.  An early wave multiplies chunk c and then
+    // classifies it; a late wave first classifies chunk c - 1 (products kept
+    // from the previous iteration) and then multiplies chunk c.  So one
+    // wave's matrix products overlap the other's vector work.  Roles come
+    // from the hardware SIMD id, one ticket per wave.
+    int *simdc = ambn + 1;
+    if (tid < 4) simdc[tid] = 0;
+
     int64_t ch = split;
     user_fetch(ch);
     if (ch < nchunks) chunk_copy(ch, Ush0);
     dma_wait();
     __syncthreads();
-    int buf = 0;
-    for (; ch < nchunks; ch += a.nsplit) {
-        const int64_t nxt = ch + a.nsplit;
-        // the other buffer was last read before the previous barrier
-        if (NB == 2 && nxt < nchunks) chunk_copy(nxt, buf ? Ush0 : Ush1);
-        const uint8_t *Ub = buf ? Ush1 : Ush0;
-        const int64_t us0 = ch * CNT_USERS + (lane & 31), us1 = us0 + 32;
-        // a column past the last user is "out" for every row: tout = +inf
-        float tin0 = INFINITY, tout0 = INFINITY, tin1 = INFINITY, tout1 = INFINITY;
+    bool late = false;
+    {
+        int t = 0;
+        if (lane == 0) t = atomicAdd(&simdc[simd_id()], 1);
+        late = (__builtin_amdgcn_readfirstlane(t) & 1) != 0;  // uniform in the wave
+    }
+    // the pending classification: products acc0/acc1 of the user columns
+    // pus0 and pus0 + 32 with their thresholds
+    f32x16 acc0 = {0}, acc1 = {0};
+    float ptin0 = INFINITY, ptout0 = INFINITY, ptin1 = INFINITY, ptout1 = INFINITY;
+    int64_t pus0 = 0;
+    bool pending = false;
+    auto classify = [&]() {
+        const int64_t us0 = pus0, us1 = pus0 + 32;
         const bool c0 = us0 < a.ulen, c1 = us1 < a.ulen;
-        if (c0) thresholds(uq0, uqs0, tin0, tout0);
-        if (c1) thresholds(uq1, uqs1, tin1, tout1);
-        user_fetch(nxt);
-        f32x16 acc0 = {0}, acc1 = {0};
-        // rows: this wave's items (shared); columns: the two user blocks
-        MMR<PREC, NCH>::cols2(acc0, acc1, ia, Ub, Ub + 32 * ls, ls, nch, D, lane);
         // counts, and whether any pair falls between the two thresholds:
         // with e = med3(v, tout, tin) (tout <= tin), v > tin <=> v > e and
         // tout <= v <= tin <=> v == e
@@ -208,8 +221,8 @@ void k_count(CountArgs a) {
         for (int i = 0; i < 16; ++i) {
             const float v0 = (PREC == PREC_FP8) ? acc0[i] * srow[i] : acc0[i];
             const float v1 = (PREC == PREC_FP8) ? acc1[i] * srow[i] : acc1[i];
-            const float e0 = __builtin_amdgcn_fmed3f(v0, tout0, tin0);
-            const float e1 = __builtin_amdgcn_fmed3f(v1, tout1, tin1);
+            const float e0 = __builtin_amdgcn_fmed3f(v0, ptout0, ptin0);
+            const float e1 = __builtin_amdgcn_fmed3f(v1, ptout1, ptin1);
             cnt[i] += (int)(v0 > e0);
             cnt[i] += (int)(v1 > e1);
             anyamb |= (v0 == e0) | (v1 == e1);
@@ -220,8 +233,8 @@ void k_count(CountArgs a) {
             for (int i = 0; i < 16; ++i) {
                 const float v0 = (PREC == PREC_FP8) ? acc0[i] * srow[i] : acc0[i];
                 const float v1 = (PREC == PREC_FP8) ? acc1[i] * srow[i] : acc1[i];
-                ambm0 |= (v0 == __builtin_amdgcn_fmed3f(v0, tout0, tin0)) ? (1u << i) : 0u;
-                ambm1 |= (v1 == __builtin_amdgcn_fmed3f(v1, tout1, tin1)) ? (1u << i) : 0u;
+                ambm0 |= (v0 == __builtin_amdgcn_fmed3f(v0, ptout0, ptin0)) ? (1u << i) : 0u;
+                ambm1 |= (v1 == __builtin_amdgcn_fmed3f(v1, ptout1, ptin1)) ? (1u << i) : 0u;
             }
             ambm0 = c0 ? (ambm0 & rvalid) : 0u;
             ambm1 = c1 ? (ambm1 & rvalid) : 0u;
@@ -242,6 +255,35 @@ void k_count(CountArgs a) {
                 }
             }
         }
+        pending = false;
+    };
+    int buf = 0;
+    for (; ch < nchunks; ch += a.nsplit) {
+        const int64_t nxt = ch + a.nsplit;
+        // the other buffer was last read before the previous barrier
+        if (NB == 2 && nxt < nchunks) chunk_copy(nxt, buf ? Ush0 : Ush1);
+        const uint8_t *Ub = buf ? Ush1 : Ush0;
+        const int64_t us0 = ch * CNT_USERS + (lane & 31), us1 = us0 + 32;
+        // a column past the last user is "out" for every row: tout = +inf
+        float tin0 = INFINITY, tout0 = INFINITY, tin1 = INFINITY, tout1 = INFINITY;
+        if (us0 < a.ulen) thresholds(uq0, uqs0, tin0, tout0);
+        if (us1 < a.ulen) thresholds(uq1, uqs1, tin1, tout1);
+        user_fetch(nxt);
+        // rows: this wave's items (shared); columns: the two user blocks
+        auto multiply = [&]() {
+            acc0 = f32x16{0};
+            acc1 = f32x16{0};
+            MMR<PREC, NCH>::cols2(acc0, acc1, ia, Ub, Ub + 32 * ls, ls, nch, D, lane);
+            ptin0 = tin0;
+            ptout0 = tout0;
+            ptin1 = tin1;
+            ptout1 = tout1;
+            pus0 = us0;
+            pending = true;
+        };
+        if (!late) multiply();
+        if (pending) classify();
+        if (late) multiply();
         if (NB == 1 && nxt < nchunks) {
             __syncthreads();  // every wave is done with the only buffer
             chunk_copy(nxt, Ush0);
@@ -260,6 +302,9 @@ void k_count(CountArgs a) {
             __syncthreads();
         }
     }
+    // a late wave's last chunk
+    if (pending) classify();
+    __syncthreads();
     // deferred FP64 rechecks, spread over the whole workgroup
     {
         const int nq = *ambn;
@@ -302,79 +347,130 @@ void launch_count(const CountArgs &a, hipStream_t st) {
     else launch_count_p<PREC_FP8>(a, c, lds, st);
 }
 
-// Eq. (3)/(6) bound count over the users of the item tile's Cauchy-Schwarz
-// prefix.  Rows are augmented so that one product gives the bound plus its
-// rounding slack: [W p, tail(p), ||p||] . [W u, tail(u), s ||u||].
-constexpr int BA = 16;            // augmented row length
-constexpr int BLD = BA + LDS_PAD;
+// Eq. (3)/(6) bound count over the users of the item block's Cauchy-Schwarz
+// prefix.  Rows are augmented so that one 16-term product gives the bound
+// plus its rounding slack: [W p, tail(p), ||p||] . [W u, tail(u), s ||u||],
+// each row stored as BF16 hi and lo parts (x = hi + lo + e, |e| <= 2^-16 |x|)
+// and multiplied as hi.hi + hi.lo + lo.hi: three BF16 matrix-core steps
+// instead of eight FP32 ones, the dropped terms being covered by s.
+//
+// A workgroup of BW waves holds BI items (four 32-row tiles, hi and lo) in
+// every wave's registers; each wave reads blocks of 32 users straight from
+// memory into registers (one block ahead), with no LDS and no barrier until
+// the final sum of the waves' counts.
+// The largest float below t (t finite).  For y = rn(x), pred(y) <= x: the
+// subtraction above is thus rounded down.
+__device__ __forceinline__ float float_pred(float t) {
+    const uint32_t b = __float_as_uint(t);
+    return __uint_as_float(t > 0.0f ? b - 1u : (t < 0.0f ? b + 1u : 0x80000001u));
+}
 
-__global__ __launch_bounds__(256) void k_bound(BoundArgs a) {
-    __shared__ float Psh[CI * BLD];
-    __shared__ float Ush[CU * BLD];
-    __shared__ int wsum[4 * CI];
+constexpr int BI = 128;  // items per bound workgroup
+constexpr int BW = 4;    // waves per bound workgroup
+
+__global__ __launch_bounds__(64 * BW) void k_bound(BoundArgs a) {
+    __shared__ int wsum[BW][BI];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int64_t ib = (int64_t)blockIdx.x * CI;
+    const int h = lane >> 5, col = lane & 31;
+    const int64_t ib = (int64_t)blockIdx.x * BI;
     const int split = blockIdx.y;
-    for (int e = tid; e < CI * 4; e += 256) {
-        int r = e >> 2, c = e & 3;
-        int64_t it = ib + r;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (it < a.m) v = reinterpret_cast<const float4 *>(a.Pa)[it * 4 + c];
-        *reinterpret_cast<float4 *>(Psh + r * BLD + 4 * c) = v;
-    }
-    int cnt[32];
+    // the items' hi and lo parts: row col of each tile, K half h
+    bf16x8 ah[4], al[4];
 #pragma unroll
-    for (int i = 0; i < 32; ++i) cnt[i] = 0;
-    const int64_t ulen = a.cs[ib];  // largest prefix of the tile (norm order)
-    const int64_t nchunks = (ulen + CU - 1) / CU;
-    for (int64_t ch = split; ch < nchunks; ch += a.nsplit) {
-        const int64_t u0 = ch * CU;
-        __syncthreads();
-        for (int e = tid; e < CU * 4; e += 256) {
-            int r = e >> 2, c = e & 3;
-            int64_t us = u0 + r;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (us < ulen) v = reinterpret_cast<const float4 *>(a.Ua)[us * 4 + c];
-            *reinterpret_cast<float4 *>(Ush + r * BLD + 4 * c) = v;
+    for (int t = 0; t < 4; ++t) {
+        const int64_t r = ib + 32 * t + col;
+        uint4 x = make_uint4(0, 0, 0, 0), y = x;
+        if (r < a.mpad) {
+            x = a.Pb[r * 4 + h];
+            y = a.Pb[r * 4 + 2 + h];
         }
-        __syncthreads();
-        const int64_t us = u0 + w * 32 + (lane & 31);
-        const float tlo = (us < ulen) ? a.tau_lo[us] : INFINITY;
-        f32x16 acc0 = {0}, acc1 = {0};
-        mfma32x2_f32(acc0, acc1, Psh, Psh + 32 * BLD, Ush + w * 32 * BLD, BLD, BA / 2, lane);
+        ah[t] = __builtin_bit_cast(bf16x8, x);
+        al[t] = __builtin_bit_cast(bf16x8, y);
+    }
+    int cnt[4][16];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) cnt[t][i] = 0;
+
+    const int64_t ulen = a.cs[ib];  // largest prefix of the block (norm order)
+    const int64_t nblk = (ulen + 31) / 32;
+    const int64_t step = (int64_t)a.nsplit * BW;
+    // one user column per lane: its hi and lo parts and its threshold,
+    // lowered by the absolute slack (clamped index: every load in bounds)
+    auto fetch = [&](int64_t j, uint4 &bh, uint4 &bl, float &tl) {
+        const int64_t us = j * 32 + col;
+        const bool ok = j < nblk && us < ulen;
+        const int64_t uc = ok ? us : 0;
+        bh = a.Ub[uc * 4 + h];
+        bl = a.Ub[uc * 4 + 2 + h];
+        tl = ok ? float_pred(a.tau_lo[uc] - a.abs_slack) : INFINITY;
+    };
+    int64_t j = (int64_t)split * BW + w;
+    uint4 bh, bl;
+    float tl;
+    fetch(j, bh, bl, tl);
+    int64_t npairs = 0;  // statistics: users of this wave's blocks
+    for (; j < nblk; j += step) {
+        uint4 nh, nl;
+        float nt;
+        fetch(j + step, nh, nl, nt);
+        const bf16x8 yh = __builtin_bit_cast(bf16x8, bh), yl = __builtin_bit_cast(bf16x8, bl);
+        // the products of tile t + 1 run while tile t's counts are taken
+        auto prod = [&](int t, f32x16 &acc) {
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t], yh, f32x16{0}, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t], yl, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[t], yh, acc, 0, 0, 0);
+        };
+        auto tally = [&](int t, const f32x16 &acc) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) cnt[t][i] += (acc[i] >= tl) ? 1 : 0;
+        };
+        f32x16 p0, p1;
+        prod(0, p0);
+        prod(1, p1);
+        tally(0, p0);
+        prod(2, p0);
+        tally(1, p1);
+        prod(3, p1);
+        tally(2, p0);
+        tally(3, p1);
+        npairs += (ulen - j * 32 < 32) ? (ulen - j * 32) : 32;
+        bh = nh;
+        bl = nl;
+        tl = nt;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            cnt[i] += (acc0[i] >= tlo) ? 1 : 0;
-            cnt[16 + i] += (acc1[i] >= tlo) ? 1 : 0;
+            const int s = half_sum(cnt[t][i]);
+            if (col == 0) wsum[w][32 * t + mfma32_row(i, lane)] = s;
         }
-    }
-#pragma unroll
-    for (int i = 0; i < 32; ++i) {
-        const int s = half_sum(cnt[i]);
-        const int r = mfma32_row(i & 15, lane) + ((i < 16) ? 0 : 32);
-        if ((lane & 31) == 0) wsum[w * CI + r] = s;
-    }
     __syncthreads();
-    if (tid < CI) {
+    if (tid < BI) {
         const int64_t it = ib + tid;
-        const int s = wsum[tid] + wsum[CI + tid] + wsum[2 * CI + tid] + wsum[3 * CI + tid];
+        int s = 0;
+#pragma unroll
+        for (int q = 0; q < BW; ++q) s += wsum[q][tid];
         if (it < a.m) a.partial[(int64_t)split * a.m + it] = s;
     }
-    if (a.pairs && tid == 0) {
-        // statistics only: pairs of the user chunks this workgroup evaluated
-        int64_t np = 0;
-        const int64_t rows = (a.m - ib < CI) ? (a.m - ib) : CI;
-        for (int64_t ch = split; ch < nchunks; ch += a.nsplit) {
-            const int64_t u0 = ch * CU;
-            np += rows * ((ulen - u0 < CU) ? (ulen - u0) : CU);
-        }
-        atomicAdd(a.pairs, (unsigned long long)np);
+    if (a.pairs && lane == 0 && npairs > 0) {
+        const int64_t rows = (a.m - ib < BI) ? (a.m - ib) : BI;
+        atomicAdd(a.pairs, (unsigned long long)(rows * npairs));
     }
 }
 
 void launch_bound(const BoundArgs &a, hipStream_t st) {
-    dim3 g((unsigned)((a.m + CI - 1) / CI), (unsigned)a.nsplit);
-    k_bound<<<g, 256, 0, st>>>(a);
+    dim3 g((unsigned)((a.m + BI - 1) / BI), (unsigned)a.nsplit);
+    k_bound<<<g, 64 * BW, 0, st>>>(a);
+}
+
+// splits of each item block's user prefix: about 4096 workgroups, 1 to 16
+int bound_splits(int64_t m) {
+    const int64_t blocks = (m + BI - 1) / BI;
+    const int64_t s = (4096 + blocks - 1) / blocks;
+    return (int)(s < 1 ? 1 : (s > 16 ? 16 : s));
 }
 
 // out[j] = sum over q of partial[q][j].  A 256-thread block covers 16

@@ -397,16 +397,16 @@ __global__ __launch_bounds__(256) void k_rotate_aug(const float *__restrict__ X,
                                                     const int32_t *__restrict__ order,
                                                     int64_t rows, int64_t rows_pad, int d,
                                                     const double *__restrict__ W, int dp,
-                                                    float scale, float *__restrict__ out) {
+                                                    float scale, uint4 *__restrict__ out) {
     __shared__ double Ws[DP_MAX * 256];
     for (int e = threadIdx.x; e < dp * d; e += blockDim.x) Ws[e] = W[e];
     __syncthreads();
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= rows_pad) return;
-    float *o = out + r * 16;
+    uint4 *o = out + r * 4;
     if (r >= rows) {
 #pragma unroll
-        for (int j = 0; j < 16; ++j) o[j] = 0.0f;
+        for (int q = 0; q < 4; ++q) o[q] = make_uint4(0, 0, 0, 0);
         return;
     }
     const float *x = X + (int64_t)(order ? order[r] : r) * d;
@@ -453,14 +453,24 @@ __global__ __launch_bounds__(256) void k_rotate_aug(const float *__restrict__ X,
         if (j == dp) ov[j] = tail;
         if (j == dp + 1) ov[j] = nrm;
     }
+    // BF16 split: hi = rn(a), lo = rn(a - hi) (a - hi is exact in FP32)
+    uint32_t hw[8], lw[8];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-        reinterpret_cast<float4 *>(o)[q] = make_float4(ov[4 * q], ov[4 * q + 1], ov[4 * q + 2],
-                                                       ov[4 * q + 3]);
+    for (int q = 0; q < 8; ++q) {
+        float h0, h1, l0, l1;
+        const uint16_t b0 = to_bf16(ov[2 * q], h0), b1 = to_bf16(ov[2 * q + 1], h1);
+        const uint16_t c0 = to_bf16(ov[2 * q] - h0, l0), c1 = to_bf16(ov[2 * q + 1] - h1, l1);
+        hw[q] = (uint32_t)b0 | ((uint32_t)b1 << 16);
+        lw[q] = (uint32_t)c0 | ((uint32_t)c1 << 16);
+    }
+    o[0] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+    o[1] = make_uint4(hw[4], hw[5], hw[6], hw[7]);
+    o[2] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+    o[3] = make_uint4(lw[4], lw[5], lw[6], lw[7]);
 }
 
 void launch_rotate_aug(const float *X, const int32_t *order, int64_t rows, int64_t rows_pad,
-                       int d, const double *W, int dp, float scale, float *out,
+                       int d, const double *W, int dp, float scale, uint4 *out,
                        hipStream_t st) {
     k_rotate_aug<<<(unsigned)((rows_pad + 255) / 256), 256, 0, st>>>(X, order, rows, rows_pad,
                                                                      d, W, dp, scale, out);

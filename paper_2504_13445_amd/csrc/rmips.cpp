@@ -30,7 +30,6 @@ namespace {
 
 constexpr int DPRIME = 10;              // split dimension of Eq. (3) (Sec. 5.1)
 constexpr int T0_TILES = 4;             // tiles of phase 1 of stage (a)
-constexpr int CAP_DEFAULT = 64;         // candidates per user and split
 constexpr int BATCH_FIRST = 512;
 constexpr int BATCH_MAX = 4096;
 constexpr int GRAM_SAMPLE = 16384;
@@ -346,7 +345,7 @@ struct TopnLayout {
     UserSide us;
     void *Us;
     double *G, *Gs, *W;
-    float *Pa, *Ua;
+    uint4 *Pa, *Ua;  // augmented BF16 hi | lo rows, 64 bytes each
     int nsplitB;
     int32_t *partialB, *uscore, *inv;
     uint32_t *vkeys;
@@ -385,11 +384,9 @@ void topn_plan(int prec, int64_t n, int64_t m, int d, int k, int cap_override, i
     L.G = cv.take<double>((size_t)d * d);
     L.Gs = cv.take<double>(gram_scratch_bytes(d) / sizeof(double));
     L.W = cv.take<double>((size_t)DPRIME * d);
-    L.Pa = cv.take<float>((size_t)L.T.mpad * 16);
-    L.Ua = cv.take<float>((size_t)n * 16);
-    int64_t itiles = (m + 63) / 64;
-    int64_t nb = std::max<int64_t>(1, std::min<int64_t>(8, (2048 + itiles - 1) / itiles));
-    L.nsplitB = (int)nb;
+    L.Pa = cv.take<uint4>((size_t)L.T.mpad * 4);
+    L.Ua = cv.take<uint4>((size_t)n * 4);
+    L.nsplitB = bound_splits(m);
     L.partialB = cv.take<int32_t>((size_t)L.nsplitB * m);
     L.uscore = cv.take<int32_t>(m);
     L.inv = cv.take<int32_t>(m);
@@ -661,13 +658,19 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
                      st);
     launch_gather_padded(L.T.Uq, L.uperm, n, L.T.rowb, L.Us, st);
     HIPTRY(hipMemcpyAsync(L.W, W.data(), sizeof(double) * dp * d, hipMemcpyHostToDevice, st));
-    // slack of the bound: covers FP32 rounding of W x, of the tail and of
-    // the 12-term matrix-core sum (each well below 2^-23 relative)
-    const float slack = 64.0f * 0x1p-23f;
+    // Relative slack s of the bound, in units of ||u|| ||p||: the BF16
+    // split drops at most 3.01 * 2^-16 |a_i||b_i| per term, the matrix-core
+    // sums of the 48 exact BF16 products add at most gamma_51 (unit 2^-23)
+    // times 1.02 sum |a_i||b_i|, and sum |a_i||b_i| <= ||a|| ||b|| <=
+    // 1.415 ||p|| ||u||: 5.6 * 2^-16 in all, below s = 2^-13; the FP32
+    // rounding of W x (2^-24 relative) is far below the margin.  The
+    // absolute slack covers BF16 and FP32 underflow (norms are below 2^60).
+    const float slack = 0x1p-13f;
     launch_rotate_aug(P, L.T.perm, m, L.T.mpad, d, L.W, dp, 1.0f, L.Pa, st);
     launch_rotate_aug(U, L.uperm, n, n, d, L.W, dp, slack, L.Ua, st);
     BoundArgs ba{};
-    ba.Pa = L.Pa; ba.m = m; ba.Ua = L.Ua; ba.tau_lo = L.us.tau_lo; ba.cs = L.cs;
+    ba.Pb = L.Pa; ba.m = m; ba.mpad = L.T.mpad; ba.Ub = L.Ua; ba.tau_lo = L.us.tau_lo;
+    ba.abs_slack = 0x1p-60f; ba.cs = L.cs;
     ba.nsplit = L.nsplitB; ba.partial = L.partialB; ba.pairs = ctr + 2;
     HIPTRY(hipEventRecord(ev[6], st));
     launch_bound(ba, st);

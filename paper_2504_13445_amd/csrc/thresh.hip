@@ -83,7 +83,7 @@ struct ScreenCfg { int nb, nch; };
 
 size_t thresh_screen_lds_cfg(int prec, int D, int nb) {
     const int ls = lds_row_bytes(prec, D);
-    return (size_t)nb * TILE_ITEMS * ls + (size_t)nb * NSTRIDE * 4 +
+    return (size_t)nb * (TILE_ITEMS * ls + LDS_GUARD) + (size_t)nb * NSTRIDE * 4 +
            32 * SCR_NW * sizeof(int) + 16 * sizeof(float);
 }
 
@@ -107,7 +107,7 @@ __device__ __forceinline__ void tile_copy(const ThreshArgs &a, int t, int rowb, 
                                           int b, int w, int lane) {
     const int64_t rb = (int64_t)t * TILE_ITEMS;
     rows_dma(reinterpret_cast<const uint8_t *>(a.Pq) + rb * rowb, rowb, w16, magic,
-             TILE_ITEMS - 1, Pbase + (size_t)b * TILE_ITEMS * ls, w, NW, lane);
+             TILE_ITEMS - 1, Pbase + (size_t)b * (TILE_ITEMS * ls + LDS_GUARD), w, NW, lane);
     if (w == NW - 1) {
         float *nb = Nbase + b * NSTRIDE;
         dma4(a.Np + rb + lane, nb);
@@ -147,12 +147,14 @@ template <int PREC, int NB, int NCH, bool LISTED>
 // 16 chunks; longer FP32 rows keep all registers for one wave
 __global__ __launch_bounds__(64 * screen_waves(NCH)) __attribute__((amdgpu_waves_per_eu(NCH <= 16 ? 2 : 1)))
 void k_thresh_screen(ThreshArgs a) {
-    constexpr int NW = screen_waves(NCH), TU = 32 * NW, NT = 64 * NW;
+    constexpr int NW = screen_waves(NCH), TU = 32 * NW;
     extern __shared__ __align__(16) uint8_t smem8[];
     const int D = a.D, ls = lds_row_bytes(PREC, D), rowb = D * elem_bytes(PREC);
     const int nch = rowb / 32;
-    uint8_t *Pbase = smem8;                                           // item tiles
-    float *Nbase = reinterpret_cast<float *>(Pbase + NB * TILE_ITEMS * ls);  // N, Nh, R
+    // item tiles, each followed by LDS_GUARD bytes of zeros; then N, Nh, R
+    const int bstride = TILE_ITEMS * ls + LDS_GUARD;
+    uint8_t *Pbase = smem8;
+    float *Nbase = reinterpret_cast<float *>(Pbase + NB * bstride);
     int *cntsh = reinterpret_cast<int *>(Nbase + NB * NSTRIDE);
     float *red = reinterpret_cast<float *>(cntsh + TU);
 
@@ -170,6 +172,11 @@ void k_thresh_screen(ThreshArgs a) {
 
     const uint32_t magic = slot_magic(w16);
     unsigned long long pacc = 0;  // statistics: phase-2 pairs screened
+    if (tid < NB * LDS_GUARD / 16) {
+        const int g = tid / (LDS_GUARD / 16), e = tid % (LDS_GUARD / 16);
+        reinterpret_cast<uint4 *>(Pbase + g * bstride + TILE_ITEMS * ls)[e] =
+            make_uint4(0, 0, 0, 0);
+    }
 
     for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
         __syncthreads();  // the previous block's counts have been written out
@@ -239,7 +246,7 @@ void k_thresh_screen(ThreshArgs a) {
                 const bool pre = tn < a.ntiles;
                 if (NB == 2 && pre)
                     tile_copy<NW>(a, tn, rowb, w16, magic, ls, Pbase, Nbase, buf ^ 1, w, lane);
-                const uint8_t *Psh = Pbase + buf * TILE_ITEMS * ls;
+                const uint8_t *Psh = Pbase + buf * bstride;
                 const float *Nsh = Nbase + buf * NSTRIDE;
                 const int64_t rb = (int64_t)t * TILE_ITEMS;
                 const float e_t = ebound(Nsh[0], Nsh[3 * TILE_ITEMS], Nsh[3 * TILE_ITEMS + 1]);
@@ -294,7 +301,7 @@ void k_thresh_screen(ThreshArgs a) {
             const bool pre = tn < a.ntiles;
             if (NB == 2 && pre)
                 tile_copy<NW>(a, tn, rowb, w16, magic, ls, Pbase, Nbase, buf ^ 1, w, lane);
-            const uint8_t *Psh = Pbase + buf * TILE_ITEMS * ls;
+            const uint8_t *Psh = Pbase + buf * bstride;
             const int64_t rb = (int64_t)t * TILE_ITEMS;
             // tile maxima: N is sorted (first item), Nh and R staged with the tile
             const float e_t = ebound(Nsh[0], Nsh[3 * TILE_ITEMS], Nsh[3 * TILE_ITEMS + 1]);
