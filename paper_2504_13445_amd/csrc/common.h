@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <type_traits>
 #include <stdint.h>
 
 namespace rmips {
@@ -209,6 +210,34 @@ template <> struct MM<PREC_FP8> {
 // reads past a row end stay in the next row or in the LDS_GUARD bytes of
 // zeros that follow each buffer (finite values, so 0 * x = 0).
 constexpr int LDS_GUARD = 512;  // >= 16 * (32 - 1) bytes of overread
+
+// Register-operand widths that are compiled: BF16 and FP8 rows are multiplied
+// over the smallest even chunk count >= nch (every even count up to the
+// largest row), FP32 rows over 8, 16 or 32 chunks with an early stop at
+// nch.  with_nch calls f(std::integral_constant<int, NCH>).
+template <int PREC, class F> void with_nch(int nch, F &&f) {
+    if constexpr (PREC == PREC_FP32) {
+        if (nch <= 8) f(std::integral_constant<int, 8>{});
+        else if (nch <= 16) f(std::integral_constant<int, 16>{});
+        else f(std::integral_constant<int, 32>{});
+    } else {
+        switch ((nch + 1) & ~1) {
+        case 2: f(std::integral_constant<int, 2>{}); break;
+        case 4: f(std::integral_constant<int, 4>{}); break;
+        case 6: f(std::integral_constant<int, 6>{}); break;
+        case 8: f(std::integral_constant<int, 8>{}); break;
+        default:
+            if constexpr (PREC == PREC_BF16) {  // FP8 rows have at most 8 chunks
+                switch ((nch + 1) & ~1) {
+                case 10: f(std::integral_constant<int, 10>{}); break;
+                case 12: f(std::integral_constant<int, 12>{}); break;
+                case 14: f(std::integral_constant<int, 14>{}); break;
+                default: f(std::integral_constant<int, 16>{}); break;
+                }
+            }
+        }
+    }
+}
 template <int PREC, int NCH> struct MMR;
 
 template <int NCH> struct MMR<PREC_FP32, NCH> {

@@ -31,28 +31,19 @@ constexpr int AMB_CAP = 1024;            // deferred FP64 rechecks per workgroup
 constexpr int AMB_FLUSH = AMB_CAP / 2;   // list length that triggers a flush between chunks
 
 // Counting configuration: waves of 32 items (the items' rows stay in
-// registers), nb user-chunk buffers in LDS (2 = the next chunk is copied in
-// while the current one is used), nch 16-byte chunks per half row.  8 waves
-// while a half row fits in 16 chunks (two waves per SIMD, 256 registers
-// each), 4 for longer rows.
+// registers), two user-chunk buffers in LDS (the next chunk is copied in
+// while the current one is used).  8 waves while a half row fits in 16
+// chunks (two waves per SIMD, 256 registers each), 4 for longer rows; either
+// way the registers allow one workgroup per CU, which has the LDS to itself
+// (at most 143 KB, for D = 256 in FP32).
 constexpr int CNT_NW = 8;  // at most
 __host__ __device__ constexpr int count_waves(int nch) { return nch <= 16 ? 8 : 4; }
-struct CountCfg { int nb, nch; };
 
-size_t count_lds_cfg(int prec, int D, int nb) {
+size_t count_lds(int prec, int D) {
     const int ls = lds_row_bytes(prec, D);
-    return (size_t)nb * (CNT_USERS * ls + LDS_GUARD) + AMB_CAP * sizeof(int2) +
+    return 2 * (size_t)(CNT_USERS * ls + LDS_GUARD) + AMB_CAP * sizeof(int2) +
            32 * CNT_NW * sizeof(int) + 32;
 }
-
-CountCfg count_cfg(int prec, int D) {
-    CountCfg c{2, 0};
-    if (count_lds_cfg(prec, D, 2) > 80 * 1024) c.nb = 1;
-    c.nch = D * elem_bytes(prec) / 32;
-    return c;
-}
-
-size_t count_lds(int prec, int D) { return count_lds_cfg(prec, D, count_cfg(prec, D).nb); }
 
 // FP64 decision of one (item row, user) pair by the tie rule.
 __device__ __forceinline__ bool recheck_pair(const CountArgs &a, int64_t row, int64_t us) {
@@ -70,9 +61,8 @@ __device__ __forceinline__ bool recheck_pair(const CountArgs &a, int64_t row, in
 // E is taken with the largest N, Nh and R of the wave's 32 items, so both
 // tests fold into two per-user thresholds; other pairs are recomputed in
 // FP64 and decided by the tie rule.
-// NW waves of 32 items; NB user buffers; PF 16-byte vectors of a user chunk
-// staged per thread (0 = chunks are loaded synchronously into LDS).
-template <int PREC, int NB, int NCH>
+// NW waves of 32 items; NCH: 16-byte chunks of the register operand.
+template <int PREC, int NCH>
 // two waves per SIMD where the row fits in 16 chunks
 __global__ __launch_bounds__(64 * count_waves(NCH)) __attribute__((amdgpu_waves_per_eu(NCH <= 16 ? 2 : 1)))
 void k_count(CountArgs a) {
@@ -83,8 +73,8 @@ void k_count(CountArgs a) {
     // each user buffer is followed by LDS_GUARD bytes of zeros
     const int bstride = CNT_USERS * ls + LDS_GUARD;
     uint8_t *Ush0 = smem8;
-    uint8_t *Ush1 = Ush0 + (NB - 1) * bstride;
-    int2 *amb = reinterpret_cast<int2 *>(Ush0 + NB * bstride);
+    uint8_t *Ush1 = Ush0 + bstride;
+    int2 *amb = reinterpret_cast<int2 *>(Ush0 + 2 * bstride);
     int *cntl = reinterpret_cast<int *>(amb + AMB_CAP);
     int *ambn = cntl + CNT_ITEMS;
 
@@ -103,7 +93,7 @@ void k_count(CountArgs a) {
     }
     if (tid < CNT_ITEMS) cntl[tid] = 0;
     if (tid == 0) *ambn = 0;
-    if (tid < NB * LDS_GUARD / 16) {
+    if (tid < 2 * LDS_GUARD / 16) {
         const int g = tid / (LDS_GUARD / 16), e = tid % (LDS_GUARD / 16);
         reinterpret_cast<uint4 *>(Ush0 + g * bstride + CNT_USERS * ls)[e] = make_uint4(0, 0, 0, 0);
     }
@@ -261,7 +251,7 @@ void k_count(CountArgs a) {
     for (; ch < nchunks; ch += a.nsplit) {
         const int64_t nxt = ch + a.nsplit;
         // the other buffer was last read before the previous barrier
-        if (NB == 2 && nxt < nchunks) chunk_copy(nxt, buf ? Ush0 : Ush1);
+        if (nxt < nchunks) chunk_copy(nxt, buf ? Ush0 : Ush1);
         const uint8_t *Ub = buf ? Ush1 : Ush0;
         const int64_t us0 = ch * CNT_USERS + (lane & 31), us1 = us0 + 32;
         // a column past the last user is "out" for every row: tout = +inf
@@ -284,13 +274,9 @@ void k_count(CountArgs a) {
         if (!late) multiply();
         if (pending) classify();
         if (late) multiply();
-        if (NB == 1 && nxt < nchunks) {
-            __syncthreads();  // every wave is done with the only buffer
-            chunk_copy(nxt, Ush0);
-        }
         if (nxt < nchunks) dma_wait();
         __syncthreads();
-        if (NB == 2) buf ^= 1;
+        buf ^= 1;
         // a long list is rechecked by the whole workgroup now, so that the
         // list rarely fills and rechecks rarely run inside one wave
         const int nq = *ambn;  // the same for all threads after the barrier
@@ -323,28 +309,21 @@ void k_count(CountArgs a) {
         atomicAdd(reinterpret_cast<unsigned long long *>(a.rechecks), (unsigned long long)nall);
 }
 
-template <int PREC, int NCH>
-void launch_count_n(const CountArgs &a, const CountCfg &c, size_t lds, hipStream_t st) {
-    constexpr int NW = count_waves(NCH);
-    dim3 g((unsigned)((a.nb + 32 * NW - 1) / (32 * NW)), (unsigned)a.nsplit);
-    if (c.nb == 2) k_count<PREC, 2, NCH><<<g, 64 * NW, lds, st>>>(a);
-    else k_count<PREC, 1, NCH><<<g, 64 * NW, lds, st>>>(a);
-}
-
 template <int PREC>
-void launch_count_p(const CountArgs &a, const CountCfg &c, size_t lds, hipStream_t st) {
-    if (c.nch <= 8) launch_count_n<PREC, 8>(a, c, lds, st);
-    else if (c.nch <= 16) launch_count_n<PREC, 16>(a, c, lds, st);
-    else launch_count_n<PREC, 32>(a, c, lds, st);
+void launch_count_p(const CountArgs &a, size_t lds, hipStream_t st) {
+    with_nch<PREC>(a.D * elem_bytes(PREC) / 32, [&](auto n) {
+        constexpr int NCH = decltype(n)::value, NW = count_waves(NCH);
+        dim3 g((unsigned)((a.nb + 32 * NW - 1) / (32 * NW)), (unsigned)a.nsplit);
+        k_count<PREC, NCH><<<g, 64 * NW, lds, st>>>(a);
+    });
 }
 
 void launch_count(const CountArgs &a, hipStream_t st) {
     if (a.nb <= 0) return;
-    const CountCfg c = count_cfg(a.prec, a.D);
-    const size_t lds = count_lds_cfg(a.prec, a.D, c.nb);
-    if (a.prec == PREC_FP32) launch_count_p<PREC_FP32>(a, c, lds, st);
-    else if (a.prec == PREC_BF16) launch_count_p<PREC_BF16>(a, c, lds, st);
-    else launch_count_p<PREC_FP8>(a, c, lds, st);
+    const size_t lds = count_lds(a.prec, a.D);
+    if (a.prec == PREC_FP32) launch_count_p<PREC_FP32>(a, lds, st);
+    else if (a.prec == PREC_BF16) launch_count_p<PREC_BF16>(a, lds, st);
+    else launch_count_p<PREC_FP8>(a, lds, st);
 }
 
 // Eq. (3)/(6) bound count over the users of the item block's Cauchy-Schwarz

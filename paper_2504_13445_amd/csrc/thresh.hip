@@ -69,8 +69,9 @@ __device__ __forceinline__ void merge32_desc(float (&v)[32]) {
 }
 
 // Screening configuration: 8 waves of 32 users (the users' rows stay in
-// registers), nb item-tile buffers in LDS (2 = the next tile is copied in
-// while the current one is used), nch 16-byte chunks per half row.
+// registers), two item-tile buffers in LDS (the next tile is copied in while
+// the current one is used; the registers allow one workgroup per CU, which
+// has the LDS to itself), nch 16-byte chunks per half row.
 constexpr int SCR_NW = 8;  // at most
 // 8 waves while a half row fits in 16 chunks (two waves per SIMD, 256
 // registers each); 4 for longer rows, whose waves need more registers
@@ -79,23 +80,10 @@ __host__ __device__ constexpr int screen_waves(int nch) { return nch <= 16 ? 8 :
 // and its scale in the first three of 64 slots, and the items' caller ids
 // (copied in with the tile, so that no global load is waited for)
 constexpr int NSTRIDE = 5 * TILE_ITEMS;
-struct ScreenCfg { int nb, nch; };
-
-size_t thresh_screen_lds_cfg(int prec, int D, int nb) {
-    const int ls = lds_row_bytes(prec, D);
-    return (size_t)nb * (TILE_ITEMS * ls + LDS_GUARD) + (size_t)nb * NSTRIDE * 4 +
-           32 * SCR_NW * sizeof(int) + 16 * sizeof(float);
-}
-
-ScreenCfg screen_cfg(int prec, int D) {
-    ScreenCfg c{2, 0};
-    if (thresh_screen_lds_cfg(prec, D, 2) > 80 * 1024) c.nb = 1;
-    c.nch = D * elem_bytes(prec) / 32;
-    return c;
-}
-
 size_t thresh_screen_lds(int prec, int D) {
-    return thresh_screen_lds_cfg(prec, D, screen_cfg(prec, D).nb);
+    const int ls = lds_row_bytes(prec, D);
+    return 2 * (size_t)(TILE_ITEMS * ls + LDS_GUARD) + 2 * (size_t)NSTRIDE * 4 +
+           32 * SCR_NW * sizeof(int) + 16 * sizeof(float);
 }
 
 // Item tile t (64 rows, and per item N, Nh, R, and the tile's scalars) into
@@ -142,7 +130,7 @@ __device__ __forceinline__ int64_t screen_blocks(const ThreshArgs &a, int tu) {
 }
 
 // LISTED: a refinement pass over a user list (its own kernel symbol)
-template <int PREC, int NB, int NCH, bool LISTED>
+template <int PREC, int NCH, bool LISTED>
 // two waves per SIMD (the register budget of 256) where the row fits in
 // 16 chunks; longer FP32 rows keep all registers for one wave
 __global__ __launch_bounds__(64 * screen_waves(NCH)) __attribute__((amdgpu_waves_per_eu(NCH <= 16 ? 2 : 1)))
@@ -154,8 +142,8 @@ void k_thresh_screen(ThreshArgs a) {
     // item tiles, each followed by LDS_GUARD bytes of zeros; then N, Nh, R
     const int bstride = TILE_ITEMS * ls + LDS_GUARD;
     uint8_t *Pbase = smem8;
-    float *Nbase = reinterpret_cast<float *>(Pbase + NB * bstride);
-    int *cntsh = reinterpret_cast<int *>(Nbase + NB * NSTRIDE);
+    float *Nbase = reinterpret_cast<float *>(Pbase + 2 * bstride);
+    int *cntsh = reinterpret_cast<int *>(Nbase + 2 * NSTRIDE);
     float *red = reinterpret_cast<float *>(cntsh + TU);
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -172,7 +160,7 @@ void k_thresh_screen(ThreshArgs a) {
 
     const uint32_t magic = slot_magic(w16);
     unsigned long long pacc = 0;  // statistics: phase-2 pairs screened
-    if (tid < NB * LDS_GUARD / 16) {
+    if (tid < 2 * LDS_GUARD / 16) {
         const int g = tid / (LDS_GUARD / 16), e = tid % (LDS_GUARD / 16);
         reinterpret_cast<uint4 *>(Pbase + g * bstride + TILE_ITEMS * ls)[e] =
             make_uint4(0, 0, 0, 0);
@@ -244,7 +232,7 @@ void k_thresh_screen(ThreshArgs a) {
                 const int t = it;
                 const int tn = tile_of(it + 1);
                 const bool pre = tn < a.ntiles;
-                if (NB == 2 && pre)
+                if (pre)
                     tile_copy<NW>(a, tn, rowb, w16, magic, ls, Pbase, Nbase, buf ^ 1, w, lane);
                 const uint8_t *Psh = Pbase + buf * bstride;
                 const float *Nsh = Nbase + buf * NSTRIDE;
@@ -259,13 +247,9 @@ void k_thresh_screen(ThreshArgs a) {
                     if (rb + r < a.m) M[i] = fmaxf(M[i], fmaf(acc0[i], sc, -e_t));
                     if (rb + r + 32 < a.m) M[16 + i] = fmaxf(M[16 + i], fmaf(acc1[i], sc, -e_t));
                 }
-                if (NB == 1 && pre) {
-                    __syncthreads();  // every wave is done with the only buffer
-                    tile_copy<NW>(a, tn, rowb, w16, magic, ls, Pbase, Nbase, 0, w, lane);
-                }
                 if (pre) dma_wait();
                 __syncthreads();
-                if (NB == 2) buf ^= 1;
+                buf ^= 1;
             }
             sort32_desc(M);
             float Bv[32];
@@ -299,7 +283,7 @@ void k_thresh_screen(ThreshArgs a) {
             ++ntile_p2;
             const int tn = tile_of(it + 1);
             const bool pre = tn < a.ntiles;
-            if (NB == 2 && pre)
+            if (pre)
                 tile_copy<NW>(a, tn, rowb, w16, magic, ls, Pbase, Nbase, buf ^ 1, w, lane);
             const uint8_t *Psh = Pbase + buf * bstride;
             const int64_t rb = (int64_t)t * TILE_ITEMS;
@@ -341,13 +325,9 @@ void k_thresh_screen(ThreshArgs a) {
                     }
                 }
             }
-            if (NB == 1 && pre) {
-                __syncthreads();  // every wave is done with the only buffer
-                tile_copy<NW>(a, tn, rowb, w16, magic, ls, Pbase, Nbase, 0, w, lane);
-            }
             if (pre) dma_wait();
             __syncthreads();
-            if (NB == 2) buf ^= 1;
+            buf ^= 1;
         }
         __syncthreads();
         if (tid < TU && blk * TU + tid < nlist) {
@@ -690,22 +670,13 @@ __global__ __launch_bounds__(64 * FB_WAVES) void k_thresh_fallback(ThreshArgs a)
     }
 }
 
-template <int PREC, int NCH>
-void launch_screen_n(const ThreshArgs &a, const ScreenCfg &c, dim3 g, size_t lds, hipStream_t st) {
-    if (a.ulist) {
-        if (c.nb == 2) k_thresh_screen<PREC, 2, NCH, true><<<g, 64 * screen_waves(NCH), lds, st>>>(a);
-        else k_thresh_screen<PREC, 1, NCH, true><<<g, 64 * screen_waves(NCH), lds, st>>>(a);
-    } else {
-        if (c.nb == 2) k_thresh_screen<PREC, 2, NCH, false><<<g, 64 * screen_waves(NCH), lds, st>>>(a);
-        else k_thresh_screen<PREC, 1, NCH, false><<<g, 64 * screen_waves(NCH), lds, st>>>(a);
-    }
-}
-
 template <int PREC>
-void launch_screen(const ThreshArgs &a, const ScreenCfg &c, dim3 g, size_t lds, hipStream_t st) {
-    if (c.nch <= 8) launch_screen_n<PREC, 8>(a, c, g, lds, st);
-    else if (c.nch <= 16) launch_screen_n<PREC, 16>(a, c, g, lds, st);
-    else launch_screen_n<PREC, 32>(a, c, g, lds, st);
+void launch_screen(const ThreshArgs &a, int nch, dim3 g, size_t lds, hipStream_t st) {
+    with_nch<PREC>(nch, [&](auto n) {
+        constexpr int NCH = decltype(n)::value;
+        if (a.ulist) k_thresh_screen<PREC, NCH, true><<<g, 64 * screen_waves(NCH), lds, st>>>(a);
+        else k_thresh_screen<PREC, NCH, false><<<g, 64 * screen_waves(NCH), lds, st>>>(a);
+    });
 }
 
 // Sort keys of the users' early-exit ratios (ascending): the norm below
@@ -724,9 +695,9 @@ __global__ void k_exit_keys(ThreshArgs a, uint32_t *__restrict__ key, int32_t *_
 }
 
 void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
-    const ScreenCfg c = screen_cfg(a0.prec, a0.D);
-    const int tu = 32 * screen_waves(c.nch <= 8 ? 8 : (c.nch <= 16 ? 16 : 32));
-    const size_t lds = thresh_screen_lds_cfg(a0.prec, a0.D, c.nb);
+    const int nch = a0.D * elem_bytes(a0.prec) / 32;
+    const int tu = 32 * screen_waves(nch);
+    const size_t lds = thresh_screen_lds(a0.prec, a0.D);
     const int64_t ublocks = (a0.n + tu - 1) / tu;
     const int capU = a0.cap * a0.nsplit;
     const int capP = final_stride(capU);
@@ -737,9 +708,9 @@ void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
     int32_t *LA = a0.lists, *LB = a0.lists + a0.n, *LF = a0.lists + 2 * a0.n;
     (void)hipMemsetAsync(a0.lcnt, 0, 4 * sizeof(int32_t), st);
     auto screen = [&](const ThreshArgs &a, dim3 g) {
-        if (a.prec == PREC_FP32) launch_screen<PREC_FP32>(a, c, g, lds, st);
-        else if (a.prec == PREC_BF16) launch_screen<PREC_BF16>(a, c, g, lds, st);
-        else launch_screen<PREC_FP8>(a, c, g, lds, st);
+        if (a.prec == PREC_FP32) launch_screen<PREC_FP32>(a, nch, g, lds, st);
+        else if (a.prec == PREC_BF16) launch_screen<PREC_BF16>(a, nch, g, lds, st);
+        else launch_screen<PREC_FP8>(a, nch, g, lds, st);
     };
     // bounds-only pass: every user's L0 from the first tiles (phase 1)
     ThreshArgs b0 = a0;
