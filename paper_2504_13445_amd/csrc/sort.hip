@@ -29,28 +29,69 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(
     counts[(int64_t)t * nblocks + blockIdx.x] = hist[t];
 }
 
-// Exclusive scan of counts[0, total) in place, one block of 1024 threads.
-__global__ __launch_bounds__(1024) void k_radix_scan(uint32_t *__restrict__ counts,
-                                                     int64_t total) {
-    __shared__ uint32_t part[1024];
+// Exclusive scan of counts[0, total) in place, in tiles of SCAN_TILE
+// entries: the first kernel sums each tile, the second scans each tile from
+// the sum of the tiles before it (at most a few dozen, read by every block).
+constexpr int SCAN_PER_THREAD = 16;
+constexpr int SCAN_TILE = SORT_THREADS * SCAN_PER_THREAD;
+
+__global__ __launch_bounds__(SORT_THREADS) void k_scan_reduce(const uint32_t *__restrict__ counts,
+                                                              int64_t total,
+                                                              uint32_t *__restrict__ tsum) {
+    __shared__ uint32_t ws[SORT_THREADS / WAVE];
     const int t = threadIdx.x;
-    const int64_t seg = (total + 1023) / 1024;
-    const int64_t s0 = t * seg, s1 = (s0 + seg < total) ? s0 + seg : total;
-    uint32_t sum = 0;
-    for (int64_t i = s0; i < s1; ++i) sum += counts[i];
-    part[t] = sum;
+    const int64_t b0 = (int64_t)blockIdx.x * SCAN_TILE;
+    uint32_t s = 0;
+#pragma unroll
+    for (int r = 0; r < SCAN_PER_THREAD; ++r) {
+        const int64_t e = b0 + (int64_t)r * SORT_THREADS + t;
+        s += (e < total) ? counts[e] : 0u;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if ((t & 63) == 0) ws[t >> 6] = s;
     __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        uint32_t v = (t >= o) ? part[t - o] : 0u;
+    if (t == 0) {
+        uint32_t x = 0;
+        for (int q = 0; q < SORT_THREADS / WAVE; ++q) x += ws[q];
+        tsum[blockIdx.x] = x;
+    }
+}
+
+__global__ __launch_bounds__(SORT_THREADS) void k_scan_down(uint32_t *__restrict__ counts,
+                                                            int64_t total,
+                                                            const uint32_t *__restrict__ tsum) {
+    __shared__ uint32_t tot[SORT_THREADS];
+    __shared__ uint32_t base;
+    const int t = threadIdx.x;
+    if (t == 0) {
+        uint32_t x = 0;
+        for (int q = 0; q < (int)blockIdx.x; ++q) x += tsum[q];
+        base = x;
+    }
+    // each thread: SCAN_PER_THREAD consecutive entries
+    const int64_t e0 = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)t * SCAN_PER_THREAD;
+    uint32_t v[SCAN_PER_THREAD];
+    uint32_t s = 0;
+#pragma unroll
+    for (int r = 0; r < SCAN_PER_THREAD; ++r) {
+        v[r] = (e0 + r < total) ? counts[e0 + r] : 0u;
+        s += v[r];
+    }
+    tot[t] = s;
+    __syncthreads();
+    // inclusive scan of the thread sums
+    for (int o = 1; o < SORT_THREADS; o <<= 1) {
+        const uint32_t y = (t >= o) ? tot[t - o] : 0u;
         __syncthreads();
-        part[t] += v;
+        tot[t] += y;
         __syncthreads();
     }
-    uint32_t run = part[t] - sum;  // exclusive prefix of this segment
-    for (int64_t i = s0; i < s1; ++i) {
-        uint32_t c = counts[i];
-        counts[i] = run;
-        run += c;
+    uint32_t run = base + tot[t] - s;
+#pragma unroll
+    for (int r = 0; r < SCAN_PER_THREAD; ++r) {
+        if (e0 + r < total) counts[e0 + r] = run;
+        run += v[r];
     }
 }
 
@@ -102,8 +143,9 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
 size_t radix_sort_scratch_bytes(int64_t n) {
     int64_t nblocks = (n + SORT_CHUNK - 1) / SORT_CHUNK;
     if (nblocks < 1) nblocks = 1;
+    const int64_t ntiles = (256 * nblocks + SCAN_TILE - 1) / SCAN_TILE;
     return (size_t)(256 * nblocks) * sizeof(uint32_t) +
-           (size_t)n * (sizeof(uint32_t) + sizeof(int32_t)) + 1024;
+           (size_t)n * (sizeof(uint32_t) + sizeof(int32_t)) + (size_t)ntiles * 4 + 1024;
 }
 
 // Sort (keys, vals) ascending by key, stably; `scratch` holds
@@ -118,12 +160,16 @@ hipError_t radix_sort_u32(uint32_t *keys, int32_t *vals, int64_t n,
     p = (uint8_t *)(((uintptr_t)p + 255) & ~(uintptr_t)255);
     uint32_t *ktmp = (uint32_t *)p;
     int32_t *vtmp = (int32_t *)(p + (size_t)n * sizeof(uint32_t));
+    uint32_t *tsum = (uint32_t *)(vtmp + n);
+    const int64_t total = (int64_t)256 * nblocks;
+    const int ntiles = (int)((total + SCAN_TILE - 1) / SCAN_TILE);
     uint32_t *ka = keys, *kb = ktmp;
     int32_t *va = vals, *vb = vtmp;
     for (int pass = 0; pass < 4; ++pass) {
         int shift = 8 * pass;
         k_radix_hist<<<nblocks, SORT_THREADS, 0, st>>>(ka, n, shift, nblocks, counts);
-        k_radix_scan<<<1, 1024, 0, st>>>(counts, (int64_t)256 * nblocks);
+        k_scan_reduce<<<ntiles, SORT_THREADS, 0, st>>>(counts, total, tsum);
+        k_scan_down<<<ntiles, SORT_THREADS, 0, st>>>(counts, total, tsum);
         k_radix_scatter<<<nblocks, SORT_THREADS, 0, st>>>(ka, va, kb, vb, n, shift,
                                                           nblocks, counts);
         uint32_t *tk = ka; ka = kb; kb = tk;
