@@ -327,48 +327,53 @@ void launch_count(const CountArgs &a, hipStream_t st) {
 }
 
 // Eq. (3)/(6) bound count over the users of the item block's Cauchy-Schwarz
-// prefix.  Rows are augmented so that one 16-term product gives the bound
+// prefix.  Rows are augmented so that one ka-term product gives the bound
 // plus its rounding slack: [W p, tail(p), ||p||] . [W u, tail(u), s ||u||],
 // each row stored as BF16 hi and lo parts (x = hi + lo + e, |e| <= 2^-16 |x|)
-// and multiplied as hi.hi + hi.lo + lo.hi: three BF16 matrix-core steps
-// instead of eight FP32 ones, the dropped terms being covered by s.
+// and multiplied as hi.hi + hi.lo + lo.hi: three BF16 matrix-core steps per
+// 16 terms, the dropped terms being covered by s.
 //
-// A workgroup of BW waves holds BI items (four 32-row tiles, hi and lo) in
-// every wave's registers; each wave reads blocks of 32 users straight from
+// A workgroup of BW waves holds 32 * TI items (TI 32-row tiles, hi and lo)
+// in every wave's registers; each wave reads blocks of 32 users straight from
 // memory into registers (one block ahead), with no LDS and no barrier until
-// the final sum of the waves' counts.
+// the final sum of the waves' counts.  KS = ka / 16 steps of K per product.
+constexpr int BW = 4;  // waves per bound workgroup
+__host__ __device__ constexpr int bound_tiles(int ks) { return ks <= 2 ? 4 : 2; }
+
 // The largest float below t (t finite).  For y = rn(x), pred(y) <= x: the
-// subtraction above is thus rounded down.
+// subtraction below is thus rounded down.
 __device__ __forceinline__ float float_pred(float t) {
     const uint32_t b = __float_as_uint(t);
     return __uint_as_float(t > 0.0f ? b - 1u : (t < 0.0f ? b + 1u : 0x80000001u));
 }
 
-constexpr int BI = 128;  // items per bound workgroup
-constexpr int BW = 4;    // waves per bound workgroup
-
+template <int KS>
 __global__ __launch_bounds__(64 * BW) void k_bound(BoundArgs a) {
+    constexpr int TI = bound_tiles(KS), BI = 32 * TI, RW = 4 * KS;  // RW: 16-byte words per row
     __shared__ int wsum[BW][BI];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int h = lane >> 5, col = lane & 31;
     const int64_t ib = (int64_t)blockIdx.x * BI;
     const int split = blockIdx.y;
-    // the items' hi and lo parts: row col of each tile, K half h
-    bf16x8 ah[4], al[4];
+    // the items' hi and lo parts: row col of each tile, K half h of each step
+    bf16x8 ah[TI][KS], al[TI][KS];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < TI; ++t) {
         const int64_t r = ib + 32 * t + col;
-        uint4 x = make_uint4(0, 0, 0, 0), y = x;
-        if (r < a.mpad) {
-            x = a.Pb[r * 4 + h];
-            y = a.Pb[r * 4 + 2 + h];
-        }
-        ah[t] = __builtin_bit_cast(bf16x8, x);
-        al[t] = __builtin_bit_cast(bf16x8, y);
-    }
-    int cnt[4][16];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+        for (int q = 0; q < KS; ++q) {
+            uint4 x = make_uint4(0, 0, 0, 0), y = x;
+            if (r < a.mpad) {
+                x = a.Pb[r * RW + 2 * q + h];
+                y = a.Pb[r * RW + 2 * KS + 2 * q + h];
+            }
+            ah[t][q] = __builtin_bit_cast(bf16x8, x);
+            al[t][q] = __builtin_bit_cast(bf16x8, y);
+        }
+    }
+    int cnt[TI][16];
+#pragma unroll
+    for (int t = 0; t < TI; ++t)
 #pragma unroll
         for (int i = 0; i < 16; ++i) cnt[t][i] = 0;
 
@@ -377,29 +382,37 @@ __global__ __launch_bounds__(64 * BW) void k_bound(BoundArgs a) {
     const int64_t step = (int64_t)a.nsplit * BW;
     // one user column per lane: its hi and lo parts and its threshold,
     // lowered by the absolute slack (clamped index: every load in bounds)
-    auto fetch = [&](int64_t j, uint4 &bh, uint4 &bl, float &tl) {
+    auto fetch = [&](int64_t j, uint4 (&bh)[KS], uint4 (&bl)[KS], float &tl) {
         const int64_t us = j * 32 + col;
         const bool ok = j < nblk && us < ulen;
         const int64_t uc = ok ? us : 0;
-        bh = a.Ub[uc * 4 + h];
-        bl = a.Ub[uc * 4 + 2 + h];
+#pragma unroll
+        for (int q = 0; q < KS; ++q) {
+            bh[q] = a.Ub[uc * RW + 2 * q + h];
+            bl[q] = a.Ub[uc * RW + 2 * KS + 2 * q + h];
+        }
         tl = ok ? float_pred(a.tau_lo[uc] - a.abs_slack) : INFINITY;
     };
     int64_t j = (int64_t)split * BW + w;
-    uint4 bh, bl;
+    uint4 bh[KS], bl[KS];
     float tl;
     fetch(j, bh, bl, tl);
     int64_t npairs = 0;  // statistics: users of this wave's blocks
     for (; j < nblk; j += step) {
-        uint4 nh, nl;
+        uint4 nh[KS], nl[KS];
         float nt;
         fetch(j + step, nh, nl, nt);
-        const bf16x8 yh = __builtin_bit_cast(bf16x8, bh), yl = __builtin_bit_cast(bf16x8, bl);
         // the products of tile t + 1 run while tile t's counts are taken
         auto prod = [&](int t, f32x16 &acc) {
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t], yh, f32x16{0}, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t], yl, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[t], yh, acc, 0, 0, 0);
+            acc = f32x16{0};
+#pragma unroll
+            for (int q = 0; q < KS; ++q) {
+                const bf16x8 yh = __builtin_bit_cast(bf16x8, bh[q]);
+                const bf16x8 yl = __builtin_bit_cast(bf16x8, bl[q]);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t][q], yh, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t][q], yl, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[t][q], yh, acc, 0, 0, 0);
+            }
         };
         auto tally = [&](int t, const f32x16 &acc) {
 #pragma unroll
@@ -409,30 +422,37 @@ __global__ __launch_bounds__(64 * BW) void k_bound(BoundArgs a) {
         prod(0, p0);
         prod(1, p1);
         tally(0, p0);
-        prod(2, p0);
-        tally(1, p1);
-        prod(3, p1);
-        tally(2, p0);
-        tally(3, p1);
+        if constexpr (TI == 4) {
+            prod(2, p0);
+            tally(1, p1);
+            prod(3, p1);
+            tally(2, p0);
+            tally(3, p1);
+        } else {
+            tally(1, p1);
+        }
         npairs += (ulen - j * 32 < 32) ? (ulen - j * 32) : 32;
-        bh = nh;
-        bl = nl;
+#pragma unroll
+        for (int q = 0; q < KS; ++q) {
+            bh[q] = nh[q];
+            bl[q] = nl[q];
+        }
         tl = nt;
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < TI; ++t)
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            const int s = half_sum(cnt[t][i]);
-            if (col == 0) wsum[w][32 * t + mfma32_row(i, lane)] = s;
+            const int sm = half_sum(cnt[t][i]);
+            if (col == 0) wsum[w][32 * t + mfma32_row(i, lane)] = sm;
         }
     __syncthreads();
     if (tid < BI) {
         const int64_t it = ib + tid;
-        int s = 0;
+        int sm = 0;
 #pragma unroll
-        for (int q = 0; q < BW; ++q) s += wsum[q][tid];
-        if (it < a.m) a.partial[(int64_t)split * a.m + it] = s;
+        for (int q = 0; q < BW; ++q) sm += wsum[q][tid];
+        if (it < a.m) a.partial[(int64_t)split * a.m + it] = sm;
     }
     if (a.pairs && lane == 0 && npairs > 0) {
         const int64_t rows = (a.m - ib < BI) ? (a.m - ib) : BI;
@@ -440,14 +460,136 @@ __global__ __launch_bounds__(64 * BW) void k_bound(BoundArgs a) {
     }
 }
 
+// Longer rows (KS >= 3): a workgroup of BLW waves holds 64 items per wave
+// (512 in all) in registers, and every stage of 64 users is copied into LDS
+// once (direct copies, double-buffered) and read by all the waves, so that a
+// user row is fetched once per 512 items.
+constexpr int BLW = 8;       // waves per workgroup
+constexpr int BL_USERS = 64;  // users per stage
+
+template <int KS>
+__global__ __launch_bounds__(64 * BLW) __attribute__((amdgpu_waves_per_eu(2)))
+void k_bound_lds(BoundArgs a) {
+    constexpr int TI = 2, BI = 32 * TI * BLW, RW = 4 * KS, LSL = RW + 1;  // LSL: LDS row slots
+    __shared__ __align__(16) uint4 ush[2][BL_USERS * LSL];
+    __shared__ float tsh[2][BL_USERS];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int h = lane >> 5, col = lane & 31;
+    const int64_t ib = (int64_t)blockIdx.x * BI;
+    const int split = blockIdx.y;
+    // this wave's items: rows ib + 64 w + 32 t + col, hi and lo, K half h
+    bf16x8 ah[TI][KS], al[TI][KS];
+#pragma unroll
+    for (int t = 0; t < TI; ++t) {
+        const int64_t r = ib + 64 * w + 32 * t + col;
+#pragma unroll
+        for (int q = 0; q < KS; ++q) {
+            uint4 x = make_uint4(0, 0, 0, 0), y = x;
+            if (r < a.mpad) {
+                x = a.Pb[r * RW + 2 * q + h];
+                y = a.Pb[r * RW + 2 * KS + 2 * q + h];
+            }
+            ah[t][q] = __builtin_bit_cast(bf16x8, x);
+            al[t][q] = __builtin_bit_cast(bf16x8, y);
+        }
+    }
+    int cnt[TI][16];
+#pragma unroll
+    for (int t = 0; t < TI; ++t)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) cnt[t][i] = 0;
+
+    const int64_t ulen = a.cs[ib];  // largest prefix of the block (norm order)
+    const int64_t nblk = (ulen + BL_USERS - 1) / BL_USERS;
+    const uint32_t magic = slot_magic(RW);
+    // stage j: users [64 j, 64 j + 64) (rows past the prefix repeat its last
+    // user and are masked out) and their thresholds
+    auto stage = [&](int64_t j, int b) {
+        const int64_t u0 = j * BL_USERS;
+        const int64_t left = ulen - u0;
+        const int rlast = (int)((left < BL_USERS ? left : BL_USERS) - 1);
+        rows_dma(reinterpret_cast<const uint8_t *>(a.Ub + u0 * RW), RW * 16, RW, magic, rlast,
+                 reinterpret_cast<uint8_t *>(ush[b]), w, BLW, lane);
+        if (w == BLW - 1) dma4(a.tau_lo + u0 + (lane < rlast ? lane : rlast), tsh[b]);
+    };
+    int64_t j = split;
+    int buf = 0;
+    if (j < nblk) stage(j, 0);
+    dma_wait();
+    __syncthreads();
+    int64_t npairs = 0;  // statistics: users of this workgroup's stages
+    for (; j < nblk; j += a.nsplit) {
+        const int64_t nx = j + a.nsplit;
+        if (nx < nblk) stage(nx, buf ^ 1);  // the other buffer was last read before the barrier
+        const uint4 *U = ush[buf];
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+            const int ul = 32 * cb + col;
+            const bool ok = j * BL_USERS + ul < ulen;
+            const float tl = ok ? float_pred(tsh[buf][ul] - a.abs_slack) : INFINITY;
+            bf16x8 yh[KS], yl[KS];
+#pragma unroll
+            for (int q = 0; q < KS; ++q) {
+                yh[q] = __builtin_bit_cast(bf16x8, U[ul * LSL + 2 * q + h]);
+                yl[q] = __builtin_bit_cast(bf16x8, U[ul * LSL + 2 * KS + 2 * q + h]);
+            }
+            auto prod = [&](int t, f32x16 &acc) {
+                acc = f32x16{0};
+#pragma unroll
+                for (int q = 0; q < KS; ++q) {
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t][q], yh[q], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t][q], yl[q], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[t][q], yh[q], acc, 0, 0, 0);
+                }
+            };
+            f32x16 p0, p1;
+            prod(0, p0);
+            prod(1, p1);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) cnt[0][i] += (p0[i] >= tl) ? 1 : 0;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) cnt[1][i] += (p1[i] >= tl) ? 1 : 0;
+        }
+        npairs += (ulen - j * BL_USERS < BL_USERS) ? (ulen - j * BL_USERS) : BL_USERS;
+        if (nx < nblk) dma_wait();
+        __syncthreads();
+        buf ^= 1;
+    }
+#pragma unroll
+    for (int t = 0; t < TI; ++t)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int sm = half_sum(cnt[t][i]);
+            const int64_t it = ib + 64 * w + 32 * t + mfma32_row(i, lane);
+            if (col == 0 && it < a.m) a.partial[(int64_t)split * a.m + it] = sm;
+        }
+    if (a.pairs && tid == 0 && npairs > 0) {
+        const int64_t rows = (a.m - ib < BI) ? (a.m - ib) : BI;
+        atomicAdd(a.pairs, (unsigned long long)(rows * npairs));
+    }
+}
+
+__host__ __device__ constexpr int bound_items(int ks) { return ks >= 3 ? 64 * BLW : 32 * bound_tiles(ks); }
+
 void launch_bound(const BoundArgs &a, hipStream_t st) {
-    dim3 g((unsigned)((a.m + BI - 1) / BI), (unsigned)a.nsplit);
-    k_bound<<<g, 64 * BW, 0, st>>>(a);
+    auto go = [&](auto ks) {
+        constexpr int KS = decltype(ks)::value, BI = bound_items(KS);
+        dim3 g((unsigned)((a.m + BI - 1) / BI), (unsigned)a.nsplit);
+        if constexpr (KS >= 3) k_bound_lds<KS><<<g, 64 * BLW, 0, st>>>(a);
+        else k_bound<KS><<<g, 64 * BW, 0, st>>>(a);
+    };
+    switch (a.ka / 16) {
+    case 1: go(std::integral_constant<int, 1>{}); break;
+    case 2: go(std::integral_constant<int, 2>{}); break;
+    case 3: go(std::integral_constant<int, 3>{}); break;
+    default: go(std::integral_constant<int, 4>{}); break;
+    }
 }
 
 // splits of each item block's user prefix: about 4096 workgroups, 1 to 16
-int bound_splits(int64_t m) {
-    const int64_t blocks = (m + BI - 1) / BI;
+int bound_splits(int64_t m, int ka) {
+    const int64_t bi = bound_items(ka / 16);
+    const int64_t blocks = (m + bi - 1) / bi;
     const int64_t s = (4096 + blocks - 1) / blocks;
     return (int)(s < 1 ? 1 : (s > 16 ? 16 : s));
 }

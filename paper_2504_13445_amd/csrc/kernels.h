@@ -67,14 +67,14 @@ void launch_cs_prefix(const uint32_t *rho_sorted_keys, int64_t n, const float *n
 size_t gram_scratch_bytes(int d);
 void launch_gram(const float *X, int64_t ns, int64_t stride, int d, double *G, double *scratch,
                  hipStream_t st);
-// Augmented rows for the Eq. (3) bound: the 16 FP32 values a = [W x (d'
-// values), tail(x), scale * ||x||, 0...], where W (d' x d, FP64) has
-// orthonormal rows and tail(x) = sqrt(||x||^2 - ||W x||^2) rounded up, stored
-// as 64 bytes per row: BF16 hi = rn(a) (32 bytes), then BF16 lo = rn(a - hi).
-// Rows are taken from X through `order` (NULL = identity); rows from `rows`
-// to `rows_pad` are zero.
+// Augmented rows for the Eq. (3) bound: the ka FP32 values a = [W x (dp
+// values), tail(x), scale * ||x||, 0...] (ka a multiple of 16, dp + 2 <= ka
+// <= 64), where W (dp x d, FP64, dp <= 62) has orthonormal rows and tail(x)
+// = sqrt(||x||^2 - ||W x||^2) rounded up, stored as 4 ka bytes per row: BF16
+// hi = rn(a) (2 ka bytes), then BF16 lo = rn(a - hi).  Rows are taken from X
+// through `order` (NULL = identity); rows from `rows` to `rows_pad` are zero.
 void launch_rotate_aug(const float *X, const int32_t *order, int64_t rows,
-                       int64_t rows_pad, int d, const double *W, int dp, float scale,
+                       int64_t rows_pad, int d, const double *W, int dp, int ka, float scale,
                        uint4 *out, hipStream_t st);
 
 // ---------------------------------------------------------- stage (a)
@@ -147,6 +147,7 @@ void launch_count(const CountArgs &a, hipStream_t st);
 size_t count_lds(int prec, int D);
 
 struct BoundArgs {
+    int ka;                            // augmented row length (16, 32, 48 or 64)
     const uint4 *Pb; int64_t m, mpad;  // augmented item rows (norm order), BF16 hi | lo
     const uint4 *Ub;                   // augmented user rows (rho order), BF16 hi | lo
     const float *tau_lo;               // per sorted user
@@ -156,7 +157,7 @@ struct BoundArgs {
     unsigned long long *pairs;         // stats: evaluated pairs (may be NULL)
 };
 void launch_bound(const BoundArgs &a, hipStream_t st);
-int bound_splits(int64_t m);
+int bound_splits(int64_t m, int ka);
 
 // partial[s][j] summed over s (fixed order) -> out[j]
 void launch_colsum(const int32_t *partial, int nsplit, int64_t cols, int32_t *out,

@@ -390,90 +390,107 @@ void launch_gram(const float *X, int64_t ns, int64_t stride, int d, double *G, d
     k_gram_sum<<<(d * d + 255) / 256, 256, 0, st>>>(scratch, d * d, G);
 }
 
-// One thread per row: W x in FP64 with W staged in LDS, norms in FP64.
-constexpr int DP_MAX = 14;
+// Augmented rows of the Eq. (3) bound, one thread per row over a
+// persistent grid: y = W x in FP64 with W (dp x d, FP64, orthonormal rows)
+// staged in LDS as its transpose; ||x||^2 in FP64.  Row layout: a = [y (dp
+// values, rounded to FP32), tail(x), scale * ||x||, 0...] (ka values, a
+// multiple of 16), stored as BF16 hi = rn(a) (2 ka bytes) then BF16 lo =
+// rn(a - hi) (2 ka bytes).  tail(x) = sqrt(||x||^2 - ||W x||^2), rounded up
+// and widened by 1e-12 ||x||^2 under the root for the FP64 rounding and the
+// departure of W from exact orthonormality.
+constexpr int DP_MAX = 62;
+constexpr int KA_MAX = 64;
+constexpr int ROT_THREADS = 512;
 
-__global__ __launch_bounds__(256) void k_rotate_aug(const float *__restrict__ X,
-                                                    const int32_t *__restrict__ order,
-                                                    int64_t rows, int64_t rows_pad, int d,
-                                                    const double *__restrict__ W, int dp,
-                                                    float scale, uint4 *__restrict__ out) {
-    __shared__ double Ws[DP_MAX * 256];
-    for (int e = threadIdx.x; e < dp * d; e += blockDim.x) Ws[e] = W[e];
-    __syncthreads();
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= rows_pad) return;
-    uint4 *o = out + r * 4;
-    if (r >= rows) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) o[q] = make_uint4(0, 0, 0, 0);
-        return;
+__global__ __launch_bounds__(ROT_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+void k_rotate_aug(const float *__restrict__ X, const int32_t *__restrict__ order, int64_t rows,
+                  int64_t rows_pad, int d, const double *__restrict__ W, int dp, int ka,
+                  float scale, uint4 *__restrict__ out) {
+    extern __shared__ double Wt[];  // Wt[i * DP_MAX + j] = W[j][i], zero for j >= dp
+    for (int e = threadIdx.x; e < d * DP_MAX; e += blockDim.x) {
+        const int i = e / DP_MAX, j = e - i * DP_MAX;
+        Wt[e] = (j < dp) ? W[(int64_t)j * d + i] : 0.0;
     }
-    const float *x = X + (int64_t)(order ? order[r] : r) * d;
-    double y[DP_MAX];
+    __syncthreads();
+    const int kw = ka / 8;  // 16-byte words per part (hi or lo)
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < rows_pad;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        uint4 *o = out + r * 2 * kw;
+        if (r >= rows) {
+            for (int q = 0; q < 2 * kw; ++q) o[q] = make_uint4(0, 0, 0, 0);
+            continue;
+        }
+        const float *x = X + (int64_t)(order ? order[r] : r) * d;
+        double y[DP_MAX];
 #pragma unroll
-    for (int j = 0; j < DP_MAX; ++j) y[j] = 0.0;
-    double s = 0.0;
-    // the row in blocks of 16 values loaded ahead of the FP64 products
-    // (indexes past the end are clamped: every load stays in bounds)
-    for (int i0 = 0; i0 < d; i0 += 16) {
-        float xv[16];
+        for (int j = 0; j < DP_MAX; ++j) y[j] = 0.0;
+        double s = 0.0;
+        // the row in blocks of 8 values loaded ahead of the FP64 products
+        // (indexes past the end are clamped: every load stays in bounds)
+        for (int i0 = 0; i0 < d; i0 += 8) {
+            float xv[8];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) xv[q] = x[(i0 + q < d) ? i0 + q : d - 1];
+            for (int q = 0; q < 8; ++q) xv[q] = x[(i0 + q < d) ? i0 + q : d - 1];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            if (i0 + q < d) {
-                const int i = i0 + q;
-                const double xi = (double)xv[q];
-                s += xi * xi;
+            for (int q = 0; q < 8; ++q) {
+                if (i0 + q < d) {
+                    const double xi = (double)xv[q];
+                    s = fma(xi, xi, s);
+                    const double2 *w2 = reinterpret_cast<const double2 *>(Wt + (i0 + q) * DP_MAX);
 #pragma unroll
-                for (int j = 0; j < DP_MAX; ++j)
-                    if (j < dp) y[j] += Ws[j * d + i] * xi;
+                    for (int j2 = 0; j2 < DP_MAX / 2; ++j2) {
+                        const double2 w = w2[j2];
+                        y[2 * j2] = fma(w.x, xi, y[2 * j2]);
+                        y[2 * j2 + 1] = fma(w.y, xi, y[2 * j2 + 1]);
+                    }
+                }
+            }
+        }
+        double y2 = 0.0;
+#pragma unroll
+        for (int j = 0; j < DP_MAX; ++j) y2 = fma(y[j], y[j], y2);
+        double t2 = s - y2;
+        if (t2 < 0.0) t2 = 0.0;
+        const float tail = __double2float_ru(sqrt(t2 + 1e-12 * s));
+        const float nrm = scale * __double2float_ru(sqrt(s) * (1.0 + 0x1p-40));
+        // the ka values, eight per 16-byte word, as BF16 hi and lo
+#pragma unroll
+        for (int q = 0; q < KA_MAX / 8; ++q) {
+            if (q < kw) {
+                uint32_t hw[4], lw[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    float v2[2];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int c = 8 * q + 2 * e + h;
+                        float v = (c < DP_MAX && c < dp) ? (float)y[c < DP_MAX ? c : 0] : 0.0f;
+                        v = (c == dp) ? tail : v;
+                        v = (c == dp + 1) ? nrm : v;
+                        v2[h] = v;
+                    }
+                    float h0, h1, l0, l1;
+                    const uint16_t b0 = to_bf16(v2[0], h0), b1 = to_bf16(v2[1], h1);
+                    const uint16_t c0 = to_bf16(v2[0] - h0, l0), c1 = to_bf16(v2[1] - h1, l1);
+                    hw[e] = (uint32_t)b0 | ((uint32_t)b1 << 16);
+                    lw[e] = (uint32_t)c0 | ((uint32_t)c1 << 16);
+                }
+                o[q] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+                o[kw + q] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
             }
         }
     }
-    double y2 = 0.0;
-    float ov[16];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) ov[j] = 0.0f;
-#pragma unroll
-    for (int j = 0; j < DP_MAX; ++j)
-        if (j < dp) {
-            y2 += y[j] * y[j];
-            ov[j] = (float)y[j];
-        }
-    // tail^2 = ||x||^2 - ||W x||^2, widened by 1e-12 ||x||^2 to cover the
-    // FP64 rounding and the departure of W from exact orthonormality
-    double t2 = s - y2;
-    if (t2 < 0.0) t2 = 0.0;
-    const float tail = __double2float_ru(sqrt(t2 + 1e-12 * s));
-    const float nrm = scale * __double2float_ru(sqrt(s) * (1.0 + 0x1p-40));
-#pragma unroll
-    for (int j = 0; j < DP_MAX + 2; ++j) {
-        if (j == dp) ov[j] = tail;
-        if (j == dp + 1) ov[j] = nrm;
-    }
-    // BF16 split: hi = rn(a), lo = rn(a - hi) (a - hi is exact in FP32)
-    uint32_t hw[8], lw[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        float h0, h1, l0, l1;
-        const uint16_t b0 = to_bf16(ov[2 * q], h0), b1 = to_bf16(ov[2 * q + 1], h1);
-        const uint16_t c0 = to_bf16(ov[2 * q] - h0, l0), c1 = to_bf16(ov[2 * q + 1] - h1, l1);
-        hw[q] = (uint32_t)b0 | ((uint32_t)b1 << 16);
-        lw[q] = (uint32_t)c0 | ((uint32_t)c1 << 16);
-    }
-    o[0] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
-    o[1] = make_uint4(hw[4], hw[5], hw[6], hw[7]);
-    o[2] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
-    o[3] = make_uint4(lw[4], lw[5], lw[6], lw[7]);
 }
 
+size_t rotate_lds_bytes(int d) { return (size_t)d * DP_MAX * sizeof(double); }
+
 void launch_rotate_aug(const float *X, const int32_t *order, int64_t rows, int64_t rows_pad,
-                       int d, const double *W, int dp, float scale, uint4 *out,
+                       int d, const double *W, int dp, int ka, float scale, uint4 *out,
                        hipStream_t st) {
-    k_rotate_aug<<<(unsigned)((rows_pad + 255) / 256), 256, 0, st>>>(X, order, rows, rows_pad,
-                                                                     d, W, dp, scale, out);
+    int64_t g = (rows_pad + ROT_THREADS - 1) / ROT_THREADS;
+    if (g > 512) g = 512;  // persistent: W is staged once per workgroup
+    k_rotate_aug<<<(unsigned)g, ROT_THREADS, rotate_lds_bytes(d), st>>>(X, order, rows, rows_pad,
+                                                                        d, W, dp, ka, scale, out);
 }
 
 }  // namespace rmips

@@ -28,7 +28,13 @@ struct rmips_ctx {
 
 namespace {
 
-constexpr int DPRIME = 10;              // split dimension of Eq. (3) (Sec. 5.1)
+// Split dimension d' of Eq. (3) (Sec. 5.1): min(d, DPRIME_MAX).  A larger
+// d' than the paper's tightens the bound (fewer items are visited in stage
+// (b)); the matrix-core bound pass pays for it in K only.  With d' = d the
+// rotation is the identity and the bound is the inner product itself.
+constexpr int DPRIME_MAX = 62;
+int dprime(int d) { return std::min(d, DPRIME_MAX); }
+int aug_len(int d) { return (dprime(d) + 2 + 15) & ~15; }  // ka: 16, 32, 48 or 64
 constexpr int T0_TILES = 4;             // tiles of phase 1 of stage (a)
 constexpr int BATCH_FIRST = 512;
 constexpr int BATCH_MAX = 4096;
@@ -223,108 +229,56 @@ rmips_status validate_common(rmips_ctx *ctx, int64_t n, int64_t m, int d, int k,
     return RMIPS_OK;
 }
 
-// Top eigenvectors of the symmetric G (d x d) by block power iteration with
-// Rayleigh-Ritz; returns W (dp x d) with orthonormal rows.  Any orthonormal
-// W keeps the Eq. (3) bound valid; the eigenvectors only make it tight.
+// An orthonormal basis of the dominant dp-dimensional eigenspace of the
+// symmetric G (d x d) by block power iteration; returns W (dp x d) with
+// orthonormal rows.  Any orthonormal W keeps the Eq. (3) bound valid; the
+// dominant eigenspace only makes it tight.
 void top_eigvecs(const std::vector<double> &G, int d, int dp, std::vector<double> &W) {
-    const int b = std::min(d, dp + 6);
-    // Q, Z: d x b row-major
+    const int b = dp;
+    // Q, Z: b columns of length d, each contiguous (column j at j * d)
     std::vector<double> Q((size_t)d * b), Z((size_t)d * b);
-    for (int i = 0; i < d; ++i)
-        for (int j = 0; j < b; ++j)
-            Q[(size_t)i * b + j] = (i == j) ? 1.0 : std::sin(1.0 + 0.7 * i + 1.3 * j) * 1e-3;
+    for (int j = 0; j < b; ++j)
+        for (int i = 0; i < d; ++i)
+            Q[(size_t)j * d + i] = (i == j) ? 1.0 : std::sin(1.0 + 0.7 * i + 1.3 * j) * 1e-3;
+    auto dot = [d](const double *x, const double *y) {  // eight partial sums
+        double p[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int i = 0;
+        for (; i + 8 <= d; i += 8)
+            for (int e = 0; e < 8; ++e) p[e] += x[i + e] * y[i + e];
+        for (; i < d; ++i) p[0] += x[i] * y[i];
+        return ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
+    };
     auto orth = [&](std::vector<double> &X) {
         // modified Gram-Schmidt over columns, twice for orthogonality to FP64 precision
         for (int pass = 0; pass < 2; ++pass)
             for (int j = 0; j < b; ++j) {
+                double *xj = &X[(size_t)j * d];
                 for (int q = 0; q < j; ++q) {
-                    double dot = 0;
-                    for (int i = 0; i < d; ++i) dot += X[(size_t)i * b + j] * X[(size_t)i * b + q];
-                    for (int i = 0; i < d; ++i) X[(size_t)i * b + j] -= dot * X[(size_t)i * b + q];
+                    const double *xq = &X[(size_t)q * d];
+                    const double c = dot(xj, xq);
+                    for (int i = 0; i < d; ++i) xj[i] -= c * xq[i];
                 }
-                double nrm = 0;
-                for (int i = 0; i < d; ++i) nrm += X[(size_t)i * b + j] * X[(size_t)i * b + j];
-                nrm = std::sqrt(nrm);
+                const double nrm = std::sqrt(dot(xj, xj));
                 const double inv = (nrm > 0) ? 1.0 / nrm : 0.0;
-                for (int i = 0; i < d; ++i) X[(size_t)i * b + j] *= inv;
+                for (int i = 0; i < d; ++i) xj[i] *= inv;
             }
     };
     auto gmul = [&](const std::vector<double> &X, std::vector<double> &Y) {
-        std::fill(Y.begin(), Y.end(), 0.0);
-        for (int i = 0; i < d; ++i) {
-            double *y = &Y[(size_t)i * b];
-            for (int l = 0; l < d; ++l) {
-                const double g = G[(size_t)i * d + l];
-                const double *x = &X[(size_t)l * b];
-                for (int j = 0; j < b; ++j) y[j] += g * x[j];
-            }
-        }
+        for (int j = 0; j < b; ++j)
+            for (int i = 0; i < d; ++i) Y[(size_t)j * d + i] = dot(&G[(size_t)i * d], &X[(size_t)j * d]);
     };
     orth(Q);
     // block power iteration; any orthonormal result keeps the bound valid,
-    // convergence only makes it tighter
-    for (int it = 0; it < 12; ++it) {
+    // and the bound depends only on the span of W's rows (a rotation within
+    // it changes nothing), so no Ritz vectors are needed
+    for (int it = 0; it < 6; ++it) {
         gmul(Q, Z);
         orth(Z);
         Q.swap(Z);
     }
-    // Rayleigh-Ritz: H = Q^T G Q (b x b), Jacobi eigen-decomposition
-    std::vector<double> GQ((size_t)d * b), H((size_t)b * b), V((size_t)b * b, 0.0);
-    gmul(Q, GQ);
-    for (int i = 0; i < b; ++i)
-        for (int j = 0; j < b; ++j) {
-            double s = 0;
-            for (int l = 0; l < d; ++l) s += Q[(size_t)l * b + i] * GQ[(size_t)l * b + j];
-            H[(size_t)i * b + j] = s;
-        }
-    for (int i = 0; i < b; ++i) V[(size_t)i * b + i] = 1.0;
-    for (int sweep = 0; sweep < 50; ++sweep) {
-        double off = 0;
-        for (int p = 0; p < b; ++p)
-            for (int q = p + 1; q < b; ++q) off += H[(size_t)p * b + q] * H[(size_t)p * b + q];
-        if (off < 1e-30) break;
-        for (int p = 0; p < b; ++p)
-            for (int q = p + 1; q < b; ++q) {
-                double apq = H[(size_t)p * b + q];
-                if (std::fabs(apq) < 1e-300) continue;
-                double theta = (H[(size_t)q * b + q] - H[(size_t)p * b + p]) / (2 * apq);
-                double t = (theta >= 0 ? 1.0 : -1.0) /
-                           (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-                double c = 1.0 / std::sqrt(t * t + 1), s = t * c;
-                for (int r = 0; r < b; ++r) {
-                    double hrp = H[(size_t)r * b + p], hrq = H[(size_t)r * b + q];
-                    H[(size_t)r * b + p] = c * hrp - s * hrq;
-                    H[(size_t)r * b + q] = s * hrp + c * hrq;
-                }
-                for (int r = 0; r < b; ++r) {
-                    double hpr = H[(size_t)p * b + r], hqr = H[(size_t)q * b + r];
-                    H[(size_t)p * b + r] = c * hpr - s * hqr;
-                    H[(size_t)q * b + r] = s * hpr + c * hqr;
-                }
-                for (int r = 0; r < b; ++r) {
-                    double vrp = V[(size_t)r * b + p], vrq = V[(size_t)r * b + q];
-                    V[(size_t)r * b + p] = c * vrp - s * vrq;
-                    V[(size_t)r * b + q] = s * vrp + c * vrq;
-                }
-            }
-    }
-    std::vector<int> order(b);
-    for (int j = 0; j < b; ++j) order[j] = j;
-    std::sort(order.begin(), order.end(), [&](int x, int y) {
-        return H[(size_t)x * b + x] > H[(size_t)y * b + y];
-    });
-    // W rows = Q * V[:, order[r]]; re-orthonormalised in FP64
     W.assign((size_t)dp * d, 0.0);
-    std::vector<double> X((size_t)d * b, 0.0);
-    for (int r = 0; r < b; ++r)
-        for (int i = 0; i < d; ++i) {
-            double s = 0;
-            for (int l = 0; l < b; ++l) s += Q[(size_t)i * b + l] * V[(size_t)l * b + order[r]];
-            X[(size_t)i * b + r] = s;
-        }
-    orth(X);
     for (int r = 0; r < dp; ++r)
-        for (int i = 0; i < d; ++i) W[(size_t)r * d + i] = X[(size_t)i * b + r];
+        for (int i = 0; i < d; ++i) W[(size_t)r * d + i] = Q[(size_t)r * d + i];
 }
 
 // counters of rmips_topn (64-bit words): [0] stage (b) rechecks, [2] stage
@@ -345,7 +299,7 @@ struct TopnLayout {
     UserSide us;
     void *Us;
     double *G, *Gs, *W;
-    uint4 *Pa, *Ua;  // augmented BF16 hi | lo rows, 64 bytes each
+    uint4 *Pa, *Ua;  // augmented BF16 hi | lo rows, 4 ka bytes each
     int nsplitB;
     int32_t *partialB, *uscore, *inv;
     uint32_t *vkeys;
@@ -383,10 +337,10 @@ void topn_plan(int prec, int64_t n, int64_t m, int d, int k, int cap_override, i
     L.Us = cv.take<uint8_t>((size_t)n * L.T.rowb);
     L.G = cv.take<double>((size_t)d * d);
     L.Gs = cv.take<double>(gram_scratch_bytes(d) / sizeof(double));
-    L.W = cv.take<double>((size_t)DPRIME * d);
-    L.Pa = cv.take<uint4>((size_t)L.T.mpad * 4);
-    L.Ua = cv.take<uint4>((size_t)n * 4);
-    L.nsplitB = bound_splits(m);
+    L.W = cv.take<double>((size_t)DPRIME_MAX * d);
+    L.Pa = cv.take<uint4>((size_t)L.T.mpad * aug_len(d) / 4);
+    L.Ua = cv.take<uint4>((size_t)n * aug_len(d) / 4);
+    L.nsplitB = bound_splits(m, aug_len(d));
     L.partialB = cv.take<int32_t>((size_t)L.nsplitB * m);
     L.uscore = cv.take<int32_t>(m);
     L.inv = cv.take<int32_t>(m);
@@ -633,12 +587,17 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
 
     // The Gram matrix of a user sample (for the rotation of Eq. (3)) does
     // not depend on tau: it goes to the host first, and the host computes
-    // its eigenvectors while the GPU runs stage (a).
-    const int dp = std::min(DPRIME, d);
-    const int64_t ns = std::min<int64_t>(n, GRAM_SAMPLE);
-    launch_gram(U, ns, n / ns, d, L.G, L.Gs, st);
-    std::vector<double> G((size_t)d * d), W;
-    HIPTRY(hipMemcpyAsync(G.data(), L.G, sizeof(double) * d * d, hipMemcpyDeviceToHost, st));
+    // its eigenvectors while the GPU runs stage (a).  With d' = d any
+    // orthonormal basis gives the same bound: the identity.
+    const int dp = dprime(d), ka = aug_len(d);
+    const bool rotate = dp < d;
+    std::vector<double> G, W;
+    if (rotate) {
+        const int64_t ns = std::min<int64_t>(n, GRAM_SAMPLE);
+        launch_gram(U, ns, n / ns, d, L.G, L.Gs, st);
+        G.resize((size_t)d * d);
+        HIPTRY(hipMemcpyAsync(G.data(), L.G, sizeof(double) * d * d, hipMemcpyDeviceToHost, st));
+    }
     HIPTRY(hipEventRecord(ev[3], st));
 
     // ---- stage (a): exact thresholds (the input check is read at the
@@ -647,8 +606,13 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
                        ev[4], ev[5], ctr + CTR_CS, false);
     if (s != RMIPS_OK) return s;
     HIPTRY(hipEventRecord(ev[1], st));
-    HIPTRY(hipEventSynchronize(ev[3]));
-    top_eigvecs(G, d, dp, W);
+    if (rotate) {
+        HIPTRY(hipEventSynchronize(ev[3]));
+        top_eigvecs(G, d, dp, W);
+    } else {
+        W.assign((size_t)d * d, 0.0);
+        for (int i = 0; i < d; ++i) W[(size_t)i * d + i] = 1.0;
+    }
 
     // ---- stage (c): Cauchy-Schwarz prefix and Eq. (3)/(6) bound counts
     launch_rho_keys(L.tau, L.T.Nu, n, L.ukeys, L.uperm, st);
@@ -659,16 +623,18 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     launch_gather_padded(L.T.Uq, L.uperm, n, L.T.rowb, L.Us, st);
     HIPTRY(hipMemcpyAsync(L.W, W.data(), sizeof(double) * dp * d, hipMemcpyHostToDevice, st));
     // Relative slack s of the bound, in units of ||u|| ||p||: the BF16
-    // split drops at most 3.01 * 2^-16 |a_i||b_i| per term, the matrix-core
-    // sums of the 48 exact BF16 products add at most gamma_51 (unit 2^-23)
-    // times 1.02 sum |a_i||b_i|, and sum |a_i||b_i| <= ||a|| ||b|| <=
-    // 1.415 ||p|| ||u||: 5.6 * 2^-16 in all, below s = 2^-13; the FP32
-    // rounding of W x (2^-24 relative) is far below the margin.  The
-    // absolute slack covers BF16 and FP32 underflow (norms are below 2^60).
-    const float slack = 0x1p-13f;
-    launch_rotate_aug(P, L.T.perm, m, L.T.mpad, d, L.W, dp, 1.0f, L.Pa, st);
-    launch_rotate_aug(U, L.uperm, n, n, d, L.W, dp, slack, L.Ua, st);
+    // split drops at most 3.01 * 2^-16 |a_i||b_i| per term; the matrix-core
+    // sums of the 3 ka <= 192 exact BF16 products (12 chained steps) add at
+    // most gamma_204 (unit 2^-23, 3.19 * 2^-16) times 1.02 sum |a_i||b_i|;
+    // and sum |a_i||b_i| <= ||a|| ||b|| <= 1.415 ||p|| ||u||: 8.9 * 2^-16 in
+    // all, below s = 2^-12; the FP32 rounding of W x (2^-24 relative) is far
+    // below the margin.  The absolute slack covers BF16 and FP32 underflow
+    // (norms are below 2^60).
+    const float slack = 0x1p-12f;
+    launch_rotate_aug(P, L.T.perm, m, L.T.mpad, d, L.W, dp, ka, 1.0f, L.Pa, st);
+    launch_rotate_aug(U, L.uperm, n, n, d, L.W, dp, ka, slack, L.Ua, st);
     BoundArgs ba{};
+    ba.ka = ka;
     ba.Pb = L.Pa; ba.m = m; ba.mpad = L.T.mpad; ba.Ub = L.Ua; ba.tau_lo = L.us.tau_lo;
     ba.abs_slack = 0x1p-60f; ba.cs = L.cs;
     ba.nsplit = L.nsplitB; ba.partial = L.partialB; ba.pairs = ctr + 2;
