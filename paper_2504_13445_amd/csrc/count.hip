@@ -461,11 +461,11 @@ __global__ __launch_bounds__(64 * BW) void k_bound(BoundArgs a) {
 }
 
 // Longer rows (KS >= 3): a workgroup of BLW waves holds 64 items per wave
-// (512 in all) in registers, and every stage of 64 users is copied into LDS
-// once (direct copies, double-buffered) and read by all the waves, so that a
-// user row is fetched once per 512 items.
+// (512 in all) in registers, and every stage of BL_USERS users is copied
+// into LDS once (direct copies, double-buffered) and read by all the waves,
+// so that a user row is fetched once per 512 items.
 constexpr int BLW = 8;       // waves per workgroup
-constexpr int BL_USERS = 64;  // users per stage
+constexpr int BL_USERS = 128;  // users per stage
 
 template <int KS>
 __global__ __launch_bounds__(64 * BLW) __attribute__((amdgpu_waves_per_eu(2)))
@@ -502,15 +502,20 @@ void k_bound_lds(BoundArgs a) {
     const int64_t ulen = a.cs[ib];  // largest prefix of the block (norm order)
     const int64_t nblk = (ulen + BL_USERS - 1) / BL_USERS;
     const uint32_t magic = slot_magic(RW);
-    // stage j: users [64 j, 64 j + 64) (rows past the prefix repeat its last
-    // user and are masked out) and their thresholds
+    // stage j: users [BL_USERS j, BL_USERS (j + 1)) in groups of 64 rows
+    // (rows past the prefix repeat its last user, groups wholly past it are
+    // not copied; those columns are masked out) and their thresholds
     auto stage = [&](int64_t j, int b) {
-        const int64_t u0 = j * BL_USERS;
-        const int64_t left = ulen - u0;
-        const int rlast = (int)((left < BL_USERS ? left : BL_USERS) - 1);
-        rows_dma(reinterpret_cast<const uint8_t *>(a.Ub + u0 * RW), RW * 16, RW, magic, rlast,
-                 reinterpret_cast<uint8_t *>(ush[b]), w, BLW, lane);
-        if (w == BLW - 1) dma4(a.tau_lo + u0 + (lane < rlast ? lane : rlast), tsh[b]);
+#pragma unroll
+        for (int g = 0; g < BL_USERS / 64; ++g) {
+            const int64_t u0 = j * BL_USERS + 64 * g;
+            const int64_t left = ulen - u0;
+            if (left <= 0) break;
+            const int rlast = (int)((left < 64 ? left : 64) - 1);
+            rows_dma(reinterpret_cast<const uint8_t *>(a.Ub + u0 * RW), RW * 16, RW, magic, rlast,
+                     reinterpret_cast<uint8_t *>(ush[b] + 64 * g * LSL), w, BLW, lane);
+            if (w == BLW - 1) dma4(a.tau_lo + u0 + (lane < rlast ? lane : rlast), tsh[b] + 64 * g);
+        }
     };
     int64_t j = split;
     int buf = 0;
@@ -522,34 +527,42 @@ void k_bound_lds(BoundArgs a) {
         const int64_t nx = j + a.nsplit;
         if (nx < nblk) stage(nx, buf ^ 1);  // the other buffer was last read before the barrier
         const uint4 *U = ush[buf];
+        // column blocks of 32 users: the products of block cb run while the
+        // counts of block cb - 1 are taken
+        f32x16 pc[2][TI];
+        float tprev = INFINITY;
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
+        for (int cb = 0; cb < BL_USERS / 32; ++cb) {
             const int ul = 32 * cb + col;
             const bool ok = j * BL_USERS + ul < ulen;
             const float tl = ok ? float_pred(tsh[buf][ul] - a.abs_slack) : INFINITY;
-            bf16x8 yh[KS], yl[KS];
+#pragma unroll
+            for (int t = 0; t < TI; ++t) pc[cb & 1][t] = f32x16{0};
 #pragma unroll
             for (int q = 0; q < KS; ++q) {
-                yh[q] = __builtin_bit_cast(bf16x8, U[ul * LSL + 2 * q + h]);
-                yl[q] = __builtin_bit_cast(bf16x8, U[ul * LSL + 2 * KS + 2 * q + h]);
-            }
-            auto prod = [&](int t, f32x16 &acc) {
-                acc = f32x16{0};
+                const bf16x8 yh = __builtin_bit_cast(bf16x8, U[ul * LSL + 2 * q + h]);
+                const bf16x8 yl = __builtin_bit_cast(bf16x8, U[ul * LSL + 2 * KS + 2 * q + h]);
 #pragma unroll
-                for (int q = 0; q < KS; ++q) {
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t][q], yh[q], acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t][q], yl[q], acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[t][q], yh[q], acc, 0, 0, 0);
+                for (int t = 0; t < TI; ++t) {
+                    f32x16 &acc = pc[cb & 1][t];
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t][q], yh, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t][q], yl, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[t][q], yh, acc, 0, 0, 0);
                 }
-            };
-            f32x16 p0, p1;
-            prod(0, p0);
-            prod(1, p1);
+            }
+            if (cb > 0) {
 #pragma unroll
-            for (int i = 0; i < 16; ++i) cnt[0][i] += (p0[i] >= tl) ? 1 : 0;
+                for (int t = 0; t < TI; ++t)
 #pragma unroll
-            for (int i = 0; i < 16; ++i) cnt[1][i] += (p1[i] >= tl) ? 1 : 0;
+                    for (int i = 0; i < 16; ++i) cnt[t][i] += (pc[(cb - 1) & 1][t][i] >= tprev) ? 1 : 0;
+            }
+            tprev = tl;
         }
+#pragma unroll
+        for (int t = 0; t < TI; ++t)
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                cnt[t][i] += (pc[(BL_USERS / 32 - 1) & 1][t][i] >= tprev) ? 1 : 0;
         npairs += (ulen - j * BL_USERS < BL_USERS) ? (ulen - j * BL_USERS) : BL_USERS;
         if (nx < nblk) dma_wait();
         __syncthreads();
