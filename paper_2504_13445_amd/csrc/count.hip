@@ -523,51 +523,65 @@ void k_bound_lds(BoundArgs a) {
     dma_wait();
     __syncthreads();
     int64_t npairs = 0;  // statistics: users of this workgroup's stages
+    // products of the last column block not counted yet (from the previous
+    // stage) and their thresholds; none at first
+    f32x16 pc[TI];
+#pragma unroll
+    for (int t = 0; t < TI; ++t) pc[t] = f32x16{0};
+    float tprev = INFINITY;
     for (; j < nblk; j += a.nsplit) {
         const int64_t nx = j + a.nsplit;
         if (nx < nblk) stage(nx, buf ^ 1);  // the other buffer was last read before the barrier
         const uint4 *U = ush[buf];
         // column blocks of 32 users: the products of block cb run while the
-        // counts of block cb - 1 are taken
-        f32x16 pc[2][TI];
-        float tprev = INFINITY;
+        // counts of block cb - 1 (for cb = 0: the previous stage's last
+        // block) are taken, one product and a few compares at a time
 #pragma unroll
         for (int cb = 0; cb < BL_USERS / 32; ++cb) {
             const int ul = 32 * cb + col;
             const bool ok = j * BL_USERS + ul < ulen;
             const float tl = ok ? float_pred(tsh[buf][ul] - a.abs_slack) : INFINITY;
+            f32x16 nc[TI];
 #pragma unroll
-            for (int t = 0; t < TI; ++t) pc[cb & 1][t] = f32x16{0};
+            for (int t = 0; t < TI; ++t) nc[t] = f32x16{0};
 #pragma unroll
             for (int q = 0; q < KS; ++q) {
                 const bf16x8 yh = __builtin_bit_cast(bf16x8, U[ul * LSL + 2 * q + h]);
                 const bf16x8 yl = __builtin_bit_cast(bf16x8, U[ul * LSL + 2 * KS + 2 * q + h]);
 #pragma unroll
                 for (int t = 0; t < TI; ++t) {
-                    f32x16 &acc = pc[cb & 1][t];
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t][q], yh, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t][q], yl, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[t][q], yh, acc, 0, 0, 0);
+                    nc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t][q], yh, nc[t], 0, 0, 0);
+                    nc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t][q], yl, nc[t], 0, 0, 0);
+                    nc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[t][q], yh, nc[t], 0, 0, 0);
                 }
             }
-            if (cb > 0) {
 #pragma unroll
-                for (int t = 0; t < TI; ++t)
+            for (int t = 0; t < TI; ++t)
 #pragma unroll
-                    for (int i = 0; i < 16; ++i) cnt[t][i] += (pc[(cb - 1) & 1][t][i] >= tprev) ? 1 : 0;
+                for (int i = 0; i < 16; ++i) cnt[t][i] += (pc[t][i] >= tprev) ? 1 : 0;
+#pragma unroll
+            for (int g = 0; g < 3 * KS * TI; ++g) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one product
+                __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);  // three vector ops
             }
+#pragma unroll
+            for (int t = 0; t < TI; ++t) pc[t] = nc[t];
             tprev = tl;
         }
+        // the counts are taken before the barrier (not moved past it)
 #pragma unroll
         for (int t = 0; t < TI; ++t)
 #pragma unroll
-            for (int i = 0; i < 16; ++i)
-                cnt[t][i] += (pc[(BL_USERS / 32 - 1) & 1][t][i] >= tprev) ? 1 : 0;
+            for (int i = 0; i < 16; ++i) asm volatile("" : "+v"(cnt[t][i]));
         npairs += (ulen - j * BL_USERS < BL_USERS) ? (ulen - j * BL_USERS) : BL_USERS;
         if (nx < nblk) dma_wait();
         __syncthreads();
         buf ^= 1;
     }
+#pragma unroll
+    for (int t = 0; t < TI; ++t)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) cnt[t][i] += (pc[t][i] >= tprev) ? 1 : 0;
 #pragma unroll
     for (int t = 0; t < TI; ++t)
 #pragma unroll
