@@ -215,12 +215,16 @@ def main():
     launches = max(avg("count_launches"), 1.0)
     # (total ms, launches, algorithmic flops per launch, dense matrix-core peak
     # of the kernel's input type: the screening and counting kernels run in
-    # the screening precision, the bound kernel in FP32)
+    # the screening precision; the bound kernel multiplies BF16 parts, and its
+    # algorithmic work is the (d' + 2)-term augmented product per pair, with
+    # d' = min(d, 62))
+    dprime = min(d, 62)
     kern = {
         "k_thresh_screen": (avg("ms_screen"), 1.0, 2.0 * d * avg("thresh_pairs"), PEAK[prec]),
         "k_count": (avg("ms_count_kernels"), launches,
                     2.0 * d * avg("count_pairs") / launches, PEAK[prec]),
-        "k_bound": (avg("ms_bound_kernel"), 1.0, 2.0 * 12 * avg("bound_pairs"), PEAK["fp32"]),
+        "k_bound": (avg("ms_bound_kernel"), 1.0, 2.0 * (dprime + 2) * avg("bound_pairs"),
+                    PEAK["bf16"]),
     }
     name = max(kern, key=lambda x: kern[x][0])
     tot_ms, nl, flops, peak = kern[name]
