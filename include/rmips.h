@@ -121,6 +121,15 @@ rmips_status rmips_set_candidate_cap(rmips_ctx *ctx, int32_t cap);
  */
 rmips_status rmips_set_batch(rmips_ctx *ctx, int32_t first, int32_t max);
 
+/*
+ * Testing knob: when `uscore` is not NULL (a device array of m int32),
+ * rmips_topn also writes the Eq. (3)/(6) bound count of every item in the
+ * caller's order (Sec. 4.2; the count over the users of the item's
+ * Cauchy-Schwarz prefix, Eq. 2), an upper bound of its exact score by
+ * Theorem 2.  NULL stops it.  The array must outlive the rmips_topn call.
+ */
+rmips_status rmips_set_bound_output(rmips_ctx *ctx, int32_t *uscore);
+
 /* Workspace bytes for rmips_thresholds / rmips_scores / rmips_topn with
  * these sizes (0 if the sizes are invalid). */
 size_t rmips_thresholds_workspace_size(int64_t n, int64_t m, int32_t d,

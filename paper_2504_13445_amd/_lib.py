@@ -22,7 +22,7 @@ K_MAX, N_MAX, D_MAX = 32, 1024, 256
 
 EXPORTS = [
     "rmips_create", "rmips_destroy", "rmips_last_error", "rmips_set_stream",
-    "rmips_set_candidate_cap", "rmips_set_batch",
+    "rmips_set_candidate_cap", "rmips_set_batch", "rmips_set_bound_output",
     "rmips_thresholds_workspace_size", "rmips_scores_workspace_size",
     "rmips_topn_workspace_size", "rmips_soft_workspace_size",
     "rmips_thresholds", "rmips_scores", "rmips_topn", "rmips_soft_fwd",
@@ -80,6 +80,8 @@ def load():
     lib.rmips_set_candidate_cap.restype = st
     lib.rmips_set_batch.argtypes = [vp, i32, i32]
     lib.rmips_set_batch.restype = st
+    lib.rmips_set_bound_output.argtypes = [vp, vp]
+    lib.rmips_set_bound_output.restype = st
     lib.rmips_thresholds_workspace_size.argtypes = [i64, i64, i32, i32, ctypes.c_int]
     lib.rmips_thresholds_workspace_size.restype = sz
     lib.rmips_scores_workspace_size.argtypes = [i64, i64, i32, ctypes.c_int]
@@ -197,8 +199,10 @@ def topn_workspace(n, m, d, k, N, prec="fp32", device=None):
                       device or torch.device("cuda"))
 
 
-def topn(U, P, k, N, prec="fp32", ws=None, cand_cap=None, batch=None):
-    """Top-N item ids and scores (host int32 numpy arrays) and a stats dict."""
+def topn(U, P, k, N, prec="fp32", ws=None, cand_cap=None, batch=None, bound_out=None):
+    """Top-N item ids and scores (host int32 numpy arrays) and a stats dict.
+    bound_out: optional int32 device tensor of m entries that receives the
+    Eq. (3)/(6) bound count of every item (caller order)."""
     import numpy as np
     U, P = _dev_f32(U, "U"), _dev_f32(P, "P")
     n, d = U.shape
@@ -215,11 +219,17 @@ def topn(U, P, k, N, prec="fp32", ws=None, cand_cap=None, batch=None):
     lib.rmips_set_candidate_cap(ctx, int(cand_cap or 0))
     b0, b1 = batch if batch else (0, 0)
     lib.rmips_set_batch(ctx, int(b0), int(b1))
+    if bound_out is not None:
+        if (bound_out.dtype != torch.int32 or bound_out.numel() != m or not bound_out.is_cuda
+                or not bound_out.is_contiguous()):
+            raise ValueError("bound_out must be a contiguous int32 device tensor of m entries")
+        lib.rmips_set_bound_output(ctx, _ptr(bound_out))
     status = lib.rmips_topn(ctx, _ptr(U), n, _ptr(P), m, d, k, N, p, _ptr(ws), ws.numel(),
                             ids.ctypes.data_as(ctypes.c_void_p),
                             sc.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st))
     lib.rmips_set_candidate_cap(ctx, 0)
     lib.rmips_set_batch(ctx, 0, 0)
+    lib.rmips_set_bound_output(ctx, None)
     _check(ctx, status)
     return ids, sc, st.as_dict()
 

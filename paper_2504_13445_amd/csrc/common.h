@@ -446,6 +446,8 @@ __device__ __forceinline__ uint8_t to_e4m3(float y, float &q) {
 // indexes past the end are clamped (every load stays in bounds) and their
 // values replaced by zeros, which add +0 and leave the sum unchanged (the
 // sum is never -0: it starts at +0 and +0 + -0 = +0).
+// RV: 16-byte vectors of each row per block (more in flight, more registers).
+template <int RV = 2>
 __device__ __forceinline__ double ip64(const float *__restrict__ u,
                                        const float *__restrict__ p, int d) {
     double acc = 0.0;
@@ -453,10 +455,10 @@ __device__ __forceinline__ double ip64(const float *__restrict__ u,
         const float4 *u4 = reinterpret_cast<const float4 *>(u);
         const float4 *p4 = reinterpret_cast<const float4 *>(p);
         const int d4 = d >> 2;
-        for (int i = 0; i < d4; i += 2) {
-            float4 x[2], y[2];
+        for (int i = 0; i < d4; i += RV) {
+            float4 x[RV], y[RV];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
+            for (int j = 0; j < RV; ++j) {
                 const bool ok = i + j < d4;
                 const int t = ok ? i + j : d4 - 1;
                 const float4 a = u4[t], b = p4[t];
@@ -464,7 +466,7 @@ __device__ __forceinline__ double ip64(const float *__restrict__ u,
                 y[j] = ok ? b : make_float4(0.f, 0.f, 0.f, 0.f);
             }
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
+            for (int j = 0; j < RV; ++j) {
                 acc = __fma_rn((double)x[j].x, (double)y[j].x, acc);
                 acc = __fma_rn((double)x[j].y, (double)y[j].y, acc);
                 acc = __fma_rn((double)x[j].z, (double)y[j].z, acc);

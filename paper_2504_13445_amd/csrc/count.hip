@@ -465,14 +465,17 @@ __global__ __launch_bounds__(64 * BW) void k_bound(BoundArgs a) {
 // into LDS once (direct copies, double-buffered) and read by all the waves,
 // so that a user row is fetched once per 512 items.
 constexpr int BLW = 8;       // waves per workgroup
-constexpr int BL_USERS = 128;  // users per stage
+constexpr int BL_USERS = 64;  // users per stage
 
 template <int KS>
 __global__ __launch_bounds__(64 * BLW) __attribute__((amdgpu_waves_per_eu(2)))
 void k_bound_lds(BoundArgs a) {
     constexpr int TI = 2, BI = 32 * TI * BLW, RW = 4 * KS, LSL = RW + 1;  // LSL: LDS row slots
-    __shared__ __align__(16) uint4 ush[2][BL_USERS * LSL];
-    __shared__ float tsh[2][BL_USERS];
+    // two stage buffers of user rows, then their thresholds (dynamic LDS,
+    // bound_lds_bytes(KS))
+    extern __shared__ __align__(16) uint8_t smem_b[];
+    uint4 (*ush)[BL_USERS * LSL] = reinterpret_cast<uint4 (*)[BL_USERS * LSL]>(smem_b);
+    float (*tsh)[BL_USERS] = reinterpret_cast<float (*)[BL_USERS]>(smem_b + 2 * BL_USERS * LSL * 16);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int h = lane >> 5, col = lane & 31;
     const int64_t ib = (int64_t)blockIdx.x * BI;
@@ -597,12 +600,13 @@ void k_bound_lds(BoundArgs a) {
 }
 
 __host__ __device__ constexpr int bound_items(int ks) { return ks >= 3 ? 64 * BLW : 32 * bound_tiles(ks); }
+constexpr size_t bound_lds_bytes(int ks) { return 2 * (size_t)BL_USERS * (4 * ks + 1) * 16 + 2 * BL_USERS * 4; }
 
 void launch_bound(const BoundArgs &a, hipStream_t st) {
     auto go = [&](auto ks) {
         constexpr int KS = decltype(ks)::value, BI = bound_items(KS);
         dim3 g((unsigned)((a.m + BI - 1) / BI), (unsigned)a.nsplit);
-        if constexpr (KS >= 3) k_bound_lds<KS><<<g, 64 * BLW, 0, st>>>(a);
+        if constexpr (KS >= 3) k_bound_lds<KS><<<g, 64 * BLW, bound_lds_bytes(KS), st>>>(a);
         else k_bound<KS><<<g, 64 * BW, 0, st>>>(a);
     };
     switch (a.ka / 16) {

@@ -22,6 +22,7 @@ struct rmips_ctx {
     std::string err;
     int32_t cap_override = 0;
     int32_t batch_first = 0, batch_max = 0;
+    int32_t *bound_out = nullptr;  // device, m int32 (testing knob)
     int32_t *h_status = nullptr;  // pinned, small
     int64_t *h_scalar = nullptr;  // pinned, small
 };
@@ -425,6 +426,12 @@ rmips_status rmips_set_batch(rmips_ctx *ctx, int32_t first, int32_t max) {
     return RMIPS_OK;
 }
 
+rmips_status rmips_set_bound_output(rmips_ctx *ctx, int32_t *uscore) {
+    if (!ctx) return RMIPS_EINVAL;
+    ctx->bound_out = uscore;
+    return RMIPS_OK;
+}
+
 static bool prec_ok(rmips_prec p) {
     return p == RMIPS_FP32 || p == RMIPS_BF16 || p == RMIPS_FP8_E4M3;
 }
@@ -644,6 +651,7 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     launch_colsum(L.partialB, L.nsplitB, m, L.uscore, st);
     // visit order: (uscore desc, id asc)
     launch_invert_perm(L.T.perm, m, L.inv, st);
+    if (ctx->bound_out) launch_gather_i32(L.uscore, L.inv, m, ctx->bound_out, st);
     launch_visit_keys(L.uscore, L.inv, m, L.vkeys, L.visit, st);
     HIPTRY(radix_sort_u32(L.vkeys, L.visit, m, L.usort, st));
     launch_gather_i32(L.uscore, L.visit, m, L.vis_us, st);

@@ -196,6 +196,41 @@ def test_topn_forced_fallback_and_small_batches(prec):
     _check_topn(U, P, 10, 10, cand_cap=2, batch=(8, 32), prec=prec)
 
 
+def _bound_case(shape):
+    if shape == "d50":        # d' = d: identity rotation
+        return synth.make_config(1, n=3000, m=2000), 10
+    if shape == "d100":       # d' = 62 < d: rotation onto the users' dominant eigenspace
+        return synth.make_config(2, n=4000, m=1500), 20
+    if shape == "d200":
+        return synth.make_config(3, n=3000, m=1000), 10
+    # subnormal range: the bound's absolute slack
+    (U, P), k = synth.make_config(2, n=2000, m=800), 10
+    return (U * np.float32(1e-19), P * np.float32(1e-19)), k
+
+
+@pytest.mark.parametrize("shape", ["d50", "d100", "d200", "tiny_values"])
+def test_topn_bound_counts_dominate_scores(shape):
+    """The Eq. (3)/(6) bound count of every item (BF16 hi/lo products with a
+    certified slack) is at least its exact score (Theorem 2); with d' = d it
+    is the score up to pairs inside the slack."""
+    _say("topn bound counts", shape)
+    rm = _rm()
+    (U, P), k = _bound_case(shape)
+    m = P.shape[0]
+    _, _, tk = orc.kmips_c(U, P, k)
+    score = orc.histogram_scores(tk, m)
+    us = torch.zeros(m, dtype=torch.int32, device=_dev())
+    ri, rs = orc.topn_from_scores(score, 10)
+    ids, sc, _ = rm.topn(_g(U), _g(P), k, 10, prec="bf16", bound_out=us)
+    assert ids.tolist() == ri.tolist() and sc.tolist() == rs.tolist()
+    us = us.cpu().numpy().astype(np.int64)
+    bad = np.nonzero(us < score)[0]
+    assert bad.size == 0, (bad[:10], us[bad[:10]], score[bad[:10]])
+    assert us.max() <= U.shape[0]
+    if shape == "d50":
+        assert (us - score).sum() <= 0.01 * score.sum(), ((us - score).sum(), score.sum())
+
+
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("cap", [2, 4])
 def test_topn_refinement_passes(prec, cap):
