@@ -8,8 +8,10 @@ namespace rmips {
 
 // ----------------------------------------------------------------- sort
 size_t radix_sort_scratch_bytes(int64_t n);
+// stable ascending sort by the key bits [lo_bit, hi_bit); the bits above
+// must agree in every key
 hipError_t radix_sort_u32(uint32_t *keys, int32_t *vals, int64_t n, void *scratch,
-                          hipStream_t st);
+                          hipStream_t st, int lo_bit = 0, int hi_bit = 32);
 
 // ----------------------------------------------------------------- prep
 // Norm of every row (FP64, rounded up to FP32), zero-padded FP32 copy with
@@ -70,7 +72,8 @@ void launch_gram(const float *X, int64_t ns, int64_t stride, int d, double *G, d
 // Augmented rows for the Eq. (3) bound: the ka FP32 values a = [W x (dp
 // values), tail(x), scale * ||x||, 0...] (ka a multiple of 16, dp + 2 <= ka
 // <= 64), where W (dp x d, FP64, dp <= 62) has orthonormal rows and tail(x)
-// = sqrt(||x||^2 - ||W x||^2) rounded up, stored as 4 ka bytes per row: BF16
+// = sqrt(||x||^2 - ||W x||^2) rounded up (W = nullptr: the identity, dp =
+// d), stored as 4 ka bytes per row: BF16
 // hi = rn(a) (2 ka bytes), then BF16 lo = rn(a - hi).  Rows are taken from X
 // through `order` (NULL = identity); rows from `rows` to `rows_pad` are zero.
 void launch_rotate_aug(const float *X, const int32_t *order, int64_t rows,

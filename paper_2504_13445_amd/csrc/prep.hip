@@ -482,11 +482,66 @@ void k_rotate_aug(const float *__restrict__ X, const int32_t *__restrict__ order
     }
 }
 
+// The same rows when W is the identity (dp = d): y = x exactly, and ||W x||^2
+// is the same FP64 sum as ||x||^2, so the tail is the widening alone.  The
+// output equals that of k_rotate_aug with W = I bit for bit.
+__global__ __launch_bounds__(256) void k_aug_ident(const float *__restrict__ X,
+                                                  const int32_t *__restrict__ order,
+                                                  int64_t rows, int64_t rows_pad, int d, int ka,
+                                                  float scale, uint4 *__restrict__ out) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows_pad) return;
+    const int kw = ka / 8;
+    uint4 *o = out + r * 2 * kw;
+    if (r >= rows) {
+        for (int q = 0; q < 2 * kw; ++q) o[q] = make_uint4(0, 0, 0, 0);
+        return;
+    }
+    const float *x = X + (int64_t)(order ? order[r] : r) * d;
+    double s = 0.0;
+    for (int i = 0; i < d; ++i) {
+        const double xi = (double)x[i];
+        s = fma(xi, xi, s);
+    }
+    const float tail = __double2float_ru(sqrt(0.0 + 1e-12 * s));
+    const float nrm = scale * __double2float_ru(sqrt(s) * (1.0 + 0x1p-40));
+#pragma unroll
+    for (int q = 0; q < KA_MAX / 8; ++q) {
+        if (q < kw) {
+            uint32_t hw[4], lw[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float v2[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int c = 8 * q + 2 * e + h;
+                    float v = (c < d) ? x[c < d ? c : 0] : 0.0f;
+                    v = (c == d) ? tail : v;
+                    v = (c == d + 1) ? nrm : v;
+                    v2[h] = v;
+                }
+                float h0, h1, l0, l1;
+                const uint16_t b0 = to_bf16(v2[0], h0), b1 = to_bf16(v2[1], h1);
+                const uint16_t c0 = to_bf16(v2[0] - h0, l0), c1 = to_bf16(v2[1] - h1, l1);
+                hw[e] = (uint32_t)b0 | ((uint32_t)b1 << 16);
+                lw[e] = (uint32_t)c0 | ((uint32_t)c1 << 16);
+            }
+            o[q] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+            o[kw + q] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+        }
+    }
+}
+
 size_t rotate_lds_bytes(int d) { return (size_t)d * DP_MAX * sizeof(double); }
 
 void launch_rotate_aug(const float *X, const int32_t *order, int64_t rows, int64_t rows_pad,
                        int d, const double *W, int dp, int ka, float scale, uint4 *out,
                        hipStream_t st) {
+    if (W == nullptr) {  // the identity, dp = d
+        k_aug_ident<<<(unsigned)((rows_pad + 255) / 256), 256, 0, st>>>(X, order, rows, rows_pad,
+                                                                       d, ka, scale, out);
+        return;
+    }
     int64_t g = (rows_pad + ROT_THREADS - 1) / ROT_THREADS;
     if (g > 512) g = 512;  // persistent: W is staged once per workgroup
     k_rotate_aug<<<(unsigned)g, ROT_THREADS, rotate_lds_bytes(d), st>>>(X, order, rows, rows_pad,

@@ -616,9 +616,6 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     if (rotate) {
         HIPTRY(hipEventSynchronize(ev[3]));
         top_eigvecs(G, d, dp, W);
-    } else {
-        W.assign((size_t)d * d, 0.0);
-        for (int i = 0; i < d; ++i) W[(size_t)i * d + i] = 1.0;
     }
 
     // ---- stage (c): Cauchy-Schwarz prefix and Eq. (3)/(6) bound counts
@@ -628,7 +625,8 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     launch_user_side(L.tau, L.tau_id, L.T.Nu, L.T.Nhu, L.T.Ru, L.T.su, L.uperm, n, ec.c2, L.us,
                      st);
     launch_gather_padded(L.T.Uq, L.uperm, n, L.T.rowb, L.Us, st);
-    HIPTRY(hipMemcpyAsync(L.W, W.data(), sizeof(double) * dp * d, hipMemcpyHostToDevice, st));
+    if (rotate)
+        HIPTRY(hipMemcpyAsync(L.W, W.data(), sizeof(double) * dp * d, hipMemcpyHostToDevice, st));
     // Relative slack s of the bound, in units of ||u|| ||p||: the BF16
     // split drops at most 3.01 * 2^-16 |a_i||b_i| per term; the matrix-core
     // sums of the 3 ka <= 192 exact BF16 products (12 chained steps) add at
@@ -638,8 +636,9 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     // below the margin.  The absolute slack covers BF16 and FP32 underflow
     // (norms are below 2^60).
     const float slack = 0x1p-12f;
-    launch_rotate_aug(P, L.T.perm, m, L.T.mpad, d, L.W, dp, ka, 1.0f, L.Pa, st);
-    launch_rotate_aug(U, L.uperm, n, n, d, L.W, dp, ka, slack, L.Ua, st);
+    const double *Wd = rotate ? L.W : nullptr;  // nullptr: the identity
+    launch_rotate_aug(P, L.T.perm, m, L.T.mpad, d, Wd, dp, ka, 1.0f, L.Pa, st);
+    launch_rotate_aug(U, L.uperm, n, n, d, Wd, dp, ka, slack, L.Ua, st);
     BoundArgs ba{};
     ba.ka = ka;
     ba.Pb = L.Pa; ba.m = m; ba.mpad = L.T.mpad; ba.Ub = L.Ua; ba.tau_lo = L.us.tau_lo;
@@ -653,7 +652,8 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     launch_invert_perm(L.T.perm, m, L.inv, st);
     if (ctx->bound_out) launch_gather_i32(L.uscore, L.inv, m, ctx->bound_out, st);
     launch_visit_keys(L.uscore, L.inv, m, L.vkeys, L.visit, st);
-    HIPTRY(radix_sort_u32(L.vkeys, L.visit, m, L.usort, st));
+    // the keys are ~uscore with 0 <= uscore <= n: only the bits of n vary
+    HIPTRY(radix_sort_u32(L.vkeys, L.visit, m, L.usort, st, 0, 32 - __builtin_clz((unsigned)n)));
     launch_gather_i32(L.uscore, L.visit, m, L.vis_us, st);
     launch_gather_i32(L.cs, L.visit, m, L.vis_cs, st);
     launch_gather_i32(L.T.perm, L.visit, m, L.vis_cid, st);

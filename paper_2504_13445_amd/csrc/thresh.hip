@@ -723,7 +723,9 @@ void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
     // users in the order of their early-exit ratios, so that the users of a
     // workgroup stop their scans at about the same tile
     k_exit_keys<<<(unsigned)((a0.n + 255) / 256), 256, 0, st>>>(a0, a0.ukey, a0.uord);
-    (void)radix_sort_u32(a0.ukey, a0.uord, a0.n, a0.usort, st);
+    // a grouping only: the top 16 bits of the ratio (sign, exponent and 7
+    // mantissa bits) are enough, ties stay in user order
+    (void)radix_sort_u32(a0.ukey, a0.uord, a0.n, a0.usort, st, 16, 32);
     (void)hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(a0.nall), (int)a0.n, 1, st);
     // main pass: all users, in that order, from their L0
     ThreshArgs a = a0;
