@@ -543,7 +543,11 @@ void k_bound_lds(BoundArgs a) {
         for (int cb = 0; cb < BL_USERS / 32; ++cb) {
             const int ul = 32 * cb + col;
             const bool ok = j * BL_USERS + ul < ulen;
-            const float tl = ok ? float_pred(tsh[buf][ul] - a.abs_slack) : INFINITY;
+            // read for every lane (stale past the prefix, then replaced), so
+            // that the block has no branch and the products and counts below
+            // can interleave
+            const float tv = float_pred(tsh[buf][ul] - a.abs_slack);
+            const float tl = ok ? tv : INFINITY;
             f32x16 nc[TI];
 #pragma unroll
             for (int t = 0; t < TI; ++t) nc[t] = f32x16{0};
