@@ -440,18 +440,22 @@ __device__ __forceinline__ uint8_t to_e4m3(float y, float &q) {
 // Exact value of u . p: FP64 sum of the exact products of the FP32 inputs,
 // taken in index order from +0.0.  fma() adds the exact product with one
 // rounding, which is what a separate multiply (exact) and add would give.
-// The operands are loaded a block at a time ahead of the dependent chain,
-// with no branch between the loads (as 16-byte vectors when both rows are
-// 16-byte aligned and d is a multiple of 4).  In the last, partial block
-// indexes past the end are clamped (every load stays in bounds) and their
-// values replaced by zeros, which add +0 and leave the sum unchanged (the
-// sum is never -0: it starts at +0 and +0 + -0 = +0).
-// RV: 16-byte vectors of each row per block (more in flight, more registers).
-template <int RV = 2>
+// The operands are loaded a block of 16 values per row at a time, ahead of
+// the dependent chain and with no branch between the loads: as 16-byte
+// vectors when both rows are 16-byte aligned and d is a multiple of 4, as
+// 8-byte vectors when they are 8-byte aligned and d is even, else one value
+// per load.  In the last, partial block indexes past the end are clamped
+// (every load stays in bounds) and their values replaced by zeros, which add
+// +0 and leave the sum unchanged (the sum is never -0: it starts at +0 and
+// +0 + -0 = +0).  BLK: values of each row per block (a multiple of 4).
+template <int BLK = 16>
 __device__ __forceinline__ double ip64(const float *__restrict__ u,
                                        const float *__restrict__ p, int d) {
+    static_assert(BLK % 4 == 0, "whole 16-byte vectors per block");
     double acc = 0.0;
-    if ((d & 3) == 0 && ((reinterpret_cast<uintptr_t>(u) | reinterpret_cast<uintptr_t>(p)) & 15) == 0) {
+    const uintptr_t al = reinterpret_cast<uintptr_t>(u) | reinterpret_cast<uintptr_t>(p);
+    if ((d & 3) == 0 && (al & 15) == 0) {
+        constexpr int RV = BLK / 4;
         const float4 *u4 = reinterpret_cast<const float4 *>(u);
         const float4 *p4 = reinterpret_cast<const float4 *>(p);
         const int d4 = d >> 2;
@@ -475,10 +479,33 @@ __device__ __forceinline__ double ip64(const float *__restrict__ u,
         }
         return acc;
     }
-    for (int i = 0; i < d; i += 8) {
-        float x[8], y[8];
+    if ((d & 1) == 0 && (al & 7) == 0) {
+        constexpr int RV = BLK / 2;
+        const float2 *u2 = reinterpret_cast<const float2 *>(u);
+        const float2 *p2 = reinterpret_cast<const float2 *>(p);
+        const int d2 = d >> 1;
+        for (int i = 0; i < d2; i += RV) {
+            float2 x[RV], y[RV];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+            for (int j = 0; j < RV; ++j) {
+                const bool ok = i + j < d2;
+                const int t = ok ? i + j : d2 - 1;
+                const float2 a = u2[t], b = p2[t];
+                x[j] = ok ? a : make_float2(0.f, 0.f);
+                y[j] = ok ? b : make_float2(0.f, 0.f);
+            }
+#pragma unroll
+            for (int j = 0; j < RV; ++j) {
+                acc = __fma_rn((double)x[j].x, (double)y[j].x, acc);
+                acc = __fma_rn((double)x[j].y, (double)y[j].y, acc);
+            }
+        }
+        return acc;
+    }
+    for (int i = 0; i < d; i += BLK) {
+        float x[BLK], y[BLK];
+#pragma unroll
+        for (int j = 0; j < BLK; ++j) {
             const bool ok = i + j < d;
             const int t = ok ? i + j : d - 1;
             const float a = u[t], b = p[t];
@@ -486,7 +513,7 @@ __device__ __forceinline__ double ip64(const float *__restrict__ u,
             y[j] = ok ? b : 0.0f;
         }
 #pragma unroll
-        for (int j = 0; j < 8; ++j) acc = __fma_rn((double)x[j], (double)y[j], acc);
+        for (int j = 0; j < BLK; ++j) acc = __fma_rn((double)x[j], (double)y[j], acc);
     }
     return acc;
 }

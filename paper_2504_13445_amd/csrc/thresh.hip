@@ -402,6 +402,8 @@ __device__ void wave_sort_pairs(double *v, int *id, int n, int lane) {
 
 
 constexpr int FIN_WAVES = 4;
+// recomputations per user handed from k_thresh_final to k_thresh_exact
+constexpr int EXACT_SLOTS = 8;
 
 // Orders this wave's LDS accesses (every list of the final selection is
 // private to one wave, so no workgroup barrier is needed).
@@ -436,38 +438,58 @@ void k_thresh_final(ThreshArgs a, int capT, int capP) {
     constexpr bool listed = LISTED;
     const int64_t nlist = listed ? (int64_t)*a.ulist_cnt : a.n;
     unsigned long long *cs = a.cstats ? a.cstats + (blockIdx.x & (CSTAT_SLOTS - 1)) * 4 : nullptr;
+    // statistics of this wave's users (candidates, recomputed), added to
+    // the counters once at the end
+    unsigned long long st_cand = 0, st_rec = 0;
 
     for (int64_t b0 = (int64_t)blockIdx.x * nw; b0 < nlist; b0 += (int64_t)gridDim.x * nw) {
         const int64_t pos = b0 + w;
         const bool valid = pos < nlist;
         const int64_t u = valid ? (listed ? (int64_t)a.ulist[pos] : pos) : 0;
-        int total = 0, stored = 0;
-        bool over = false;
-        if (valid) {
-            for (int s = 0; s < a.nsplit; ++s) {
-                const int c = a.cand_cnt[u * a.nsplit + s];
-                over |= c > a.cap;
-                total += c;
-                stored += c < a.cap ? c : a.cap;
-            }
-            if (stored > capT) over = true;  // cannot happen: nsplit * cap <= capT
+        // the split counts, one per lane (nsplit <= 64), and their sums;
+        // stored entries are laid out split after split
+        int cl = 0;
+        if (valid && lane < a.nsplit) cl = a.cand_cnt[u * a.nsplit + lane];
+        bool over = __ballot(cl > a.cap) != 0ull;
+        const int sl = cl < a.cap ? cl : a.cap;
+        int pre = sl;  // inclusive prefix of the stored counts
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(pre, o);
+            if (lane >= o) pre += y;
         }
+        const int stored = __builtin_amdgcn_readlane(pre, 63);
+        int total = 0;  // statistics: candidates found, stored or not
+        if (cs) {
+            int t = cl;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) t += __shfl_xor(t, o);
+            total = __builtin_amdgcn_readlane(t, 0);
+        }
+        if (stored > capT) over = true;  // cannot happen: nsplit * cap <= capT
         wave_sync();  // this wave's previous user is done with its LDS lists
         if (lane == 0) Lstar[w] = -INFINITY;
         if (valid && stored <= capT) {
-            int off = 0;
-            for (int s = 0; s < a.nsplit; ++s) {
-                int c = a.cand_cnt[u * a.nsplit + s];
-                c = c < a.cap ? c : a.cap;
-                const float2 *src = a.cand + (u * a.nsplit + s) * a.cap;
-                const int32_t *sidp = a.cand_id + (u * a.nsplit + s) * a.cap;
-                for (int e = lane; e < c; e += 64) {
-                    const float2 cv = src[e];  // (screened value, its bound E)
-                    lo[off + e] = cv.x - cv.y;
-                    hi[off + e] = cv.x + cv.y;
-                    cidx[off + e] = sidp[e];
+            // entry g of the joined list (64 at a time, from every split
+            // at once): split s = number of inclusive prefixes <= g, entry
+            // g - (prefix before s)
+            for (int g0 = 0; g0 < stored; g0 += 64) {
+                const int g = g0 + lane;
+                int sp = 0, before = 0;
+                for (int q = 0; q < a.nsplit; ++q) {
+                    const int pq = __builtin_amdgcn_readlane(pre, q);
+                    if (pq <= g) {
+                        sp = q + 1;
+                        before = pq;
+                    }
                 }
-                off += c;
+                if (g < stored) {
+                    const int64_t e = (u * a.nsplit + sp) * a.cap + (g - before);
+                    const float2 cv = a.cand[e];  // (screened value, its bound E)
+                    lo[g] = cv.x - cv.y;
+                    hi[g] = cv.x + cv.y;
+                    cidx[g] = a.cand_id[e];
+                }
             }
         }
         wave_sync();
@@ -505,22 +527,23 @@ void k_thresh_final(ThreshArgs a, int capT, int capP) {
             }
         }
         const bool work = valid && !over;
-        if (work && cs && lane == 0) atomicAdd(cs, (unsigned long long)total);
+        if (work) st_cand += (unsigned long long)total;
         // survivors: upper bound reaches L*; keep their caller ids, and
         // their bounds in place (a survivor's slot is at most its index)
         if (work) {
             const float Ls = Lstar[w];
             int cntw = 0;
-            for (int e0 = 0; e0 < total; e0 += 64) {
+            // (no list overflowed: every candidate is stored)
+            for (int e0 = 0; e0 < stored; e0 += 64) {
                 const int e = e0 + lane;
                 float l = 0.0f, h = 0.0f;
                 int c = 0;
-                if (e < total) {
+                if (e < stored) {
                     l = lo[e];
                     h = hi[e];
                     c = cidx[e];
                 }
-                const bool keep = e < total && h >= Ls;
+                const bool keep = e < stored && h >= Ls;
                 const uint64_t bal = __ballot(keep);
                 const int p = cntw + __popcll(bal & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
                 __builtin_amdgcn_wave_barrier();
@@ -565,16 +588,32 @@ void k_thresh_final(ThreshArgs a, int capT, int capP) {
                 nrec = cntb;
             }
             if (lane == 0) nsurv[w] = nrec | ((ns - nrec) << 16);
-            if (cs && lane == 0) atomicAdd(cs + 1, (unsigned long long)nrec);
+            st_rec += (unsigned long long)nrec;
         }
         wave_sync();
-        if (work) {
-            const int nrec = nsurv[w] & 0xffff;
+        // Only tau asked for and at most EXACT_SLOTS values to recompute: they
+        // are left to k_thresh_exact, which packs several users per wave.  The
+        // ids go to this user's candidate slots (read above), the target rank
+        // and the count to its first count slot; -1 there for every other
+        // user of the list.
+        const int nrec_w = nsurv[w] & 0xffff;
+        const bool defer = work && band && nrec_w <= EXACT_SLOTS;
+        if (valid) {
+            if (defer) {
+                const int64_t c0 = u * a.nsplit * (int64_t)a.cap;
+                if (lane < nrec_w) a.cand_id[c0 + lane] = rid[lane];
+                if (lane == 0)
+                    a.cand_cnt[u * a.nsplit] = (a.k - 1 - (nsurv[w] >> 16)) | (nrec_w << 8);
+            } else if (lane == 0) {
+                a.cand_cnt[u * a.nsplit] = -1;
+            }
+        }
+        if (work && !defer) {
             const float *urow = a.U + u * a.d;
-            for (int q = lane; q < nrec; q += 64) v64[q] = ip64(urow, a.P + (int64_t)rid[q] * a.d, a.d);
+            for (int q = lane; q < nrec_w; q += 64) v64[q] = ip64<4>(urow, a.P + (int64_t)rid[q] * a.d, a.d);
         }
         wave_sync();
-        if (work) {
+        if (work && !defer) {
             const int nrec = nsurv[w] & 0xffff, nabove = nsurv[w] >> 16;
             const int tgt = a.k - 1 - nabove;  // rank of tau among the recomputed
             if (nrec <= 128) {
@@ -601,6 +640,51 @@ void k_thresh_final(ThreshArgs a, int capT, int capP) {
                 if (a.topk)
                     for (int r = lane; r < a.k; r += 64) a.topk[u * a.k + r] = rid[r];
             }
+        }
+    }
+    if (cs && lane == 0) {
+        if (st_cand) atomicAdd(cs, st_cand);
+        if (st_rec) atomicAdd(cs + 1, st_rec);
+    }
+}
+
+// The recomputations left by k_thresh_final: EXACT_SLOTS lanes per user,
+// 64 / EXACT_SLOTS users per wave over the same list.  Lane q of a user with
+// n <= EXACT_SLOTS values to recompute takes the q-th id; the value of rank
+// tgt among the n, in the order (value desc, id asc), is tau_u.
+template <bool LISTED>
+__global__ __launch_bounds__(256) void k_thresh_exact(ThreshArgs a) {
+    constexpr int UPW = 64 / EXACT_SLOTS;  // users per wave
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int grp = lane / EXACT_SLOTS, q = lane % EXACT_SLOTS;
+    const int nw = blockDim.x >> 6;
+    const int64_t nlist = LISTED ? (int64_t)*a.ulist_cnt : a.n;
+    for (int64_t b0 = ((int64_t)blockIdx.x * nw + w) * UPW; b0 < nlist;
+         b0 += (int64_t)gridDim.x * nw * UPW) {
+        const int64_t pos = b0 + grp;
+        const bool valid = pos < nlist;
+        const int64_t u = valid ? (LISTED ? (int64_t)a.ulist[pos] : pos) : 0;
+        const int meta = valid ? a.cand_cnt[u * a.nsplit] : -1;
+        const int nrec = meta < 0 ? 0 : meta >> 8, tgt = meta & 255;
+        const bool have = q < nrec;
+        int id = 0;
+        double v = 0.0;
+        if (have) {
+            id = a.cand_id[u * a.nsplit * (int64_t)a.cap + q];
+            v = ip64<16>(a.U + u * a.d, a.P + (int64_t)id * a.d, a.d);
+        }
+        // rank among the user's values: the lanes of its group
+        int rank = 0;
+#pragma unroll
+        for (int j = 0; j < EXACT_SLOTS; ++j) {
+            const int src = grp * EXACT_SLOTS + j;
+            const double y = __shfl(v, src);
+            const int yi = __shfl(id, src);
+            rank += (j < nrec && ((y > v) || (y == v && yi < id))) ? 1 : 0;
+        }
+        if (have && rank == tgt) {
+            a.tau[u] = v;
+            a.tau_id[u] = id;
         }
     }
 }
@@ -704,7 +788,9 @@ void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
     int fw = (int)((150 * 1024) / ((size_t)capP * 24));  // waves whose lists fit in LDS
     fw = fw < 1 ? 1 : (fw > FIN_WAVES ? FIN_WAVES : fw);
     const size_t lds_fin = (size_t)fw * capP * 24;
-    const int64_t fblocks = (a0.n + fw - 1) / fw;
+    // a grid of at most 2048 workgroups: each wave takes many users in turn
+    const int64_t fblocks = std::min<int64_t>((a0.n + fw - 1) / fw, 2048);
+    const int64_t eblocks = (a0.n + 4 * (64 / EXACT_SLOTS) - 1) / (4 * (64 / EXACT_SLOTS));
     int32_t *LA = a0.lists, *LB = a0.lists + a0.n, *LF = a0.lists + 2 * a0.n;
     (void)hipMemsetAsync(a0.lcnt, 0, 4 * sizeof(int32_t), st);
     auto screen = [&](const ThreshArgs &a, dim3 g) {
@@ -740,6 +826,7 @@ void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
     screen(a, dim3((unsigned)ublocks, (unsigned)a.nsplit));
     if (a.ev1) (void)hipEventRecord(a.ev1, st);
     k_thresh_final<true><<<(unsigned)fblocks, 64 * fw, lds_fin, st>>>(a, capU, capP);
+    k_thresh_exact<true><<<(unsigned)eblocks, 256, 0, st>>>(a);
     // refinement passes over the users whose lists overflowed: the same
     // per-user capacity in fewer, longer lists per split
     int nsr = capU / 64;
@@ -759,6 +846,7 @@ void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
         screen(b, dim3((unsigned)gx, (unsigned)nsr));
         const int64_t gf = fblocks < 2048 ? fblocks : 2048;
         k_thresh_final<true><<<(unsigned)gf, 64 * fw, lds_fin, st>>>(b, b.nsplit * b.cap, capP);
+        k_thresh_exact<true><<<(unsigned)(eblocks < 1024 ? eblocks : 1024), 256, 0, st>>>(b);
     }
     int64_t fb = (a0.n + FB_WAVES - 1) / FB_WAVES;
     if (fb > 1024) fb = 1024;
