@@ -498,11 +498,14 @@ __global__ __launch_bounds__(256) void k_aug_ident(const float *__restrict__ X,
         return;
     }
     const float *x = X + (int64_t)(order ? order[r] : r) * d;
+    // the whole row in registers (d <= DP_MAX), loaded at once
+    float xr[DP_MAX];
+#pragma unroll
+    for (int c = 0; c < DP_MAX; ++c) xr[c] = (c < d) ? x[c] : 0.0f;
     double s = 0.0;
-    for (int i = 0; i < d; ++i) {
-        const double xi = (double)x[i];
-        s = fma(xi, xi, s);
-    }
+#pragma unroll
+    for (int c = 0; c < DP_MAX; ++c)
+        if (c < d) s = fma((double)xr[c], (double)xr[c], s);
     const float tail = __double2float_ru(sqrt(0.0 + 1e-12 * s));
     const float nrm = scale * __double2float_ru(sqrt(s) * (1.0 + 0x1p-40));
 #pragma unroll
@@ -515,7 +518,7 @@ __global__ __launch_bounds__(256) void k_aug_ident(const float *__restrict__ X,
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const int c = 8 * q + 2 * e + h;
-                    float v = (c < d) ? x[c < d ? c : 0] : 0.0f;
+                    float v = (c < d && c < DP_MAX) ? xr[c < DP_MAX ? c : 0] : 0.0f;
                     v = (c == d) ? tail : v;
                     v = (c == d + 1) ? nrm : v;
                     v2[h] = v;
@@ -537,7 +540,7 @@ size_t rotate_lds_bytes(int d) { return (size_t)d * DP_MAX * sizeof(double); }
 void launch_rotate_aug(const float *X, const int32_t *order, int64_t rows, int64_t rows_pad,
                        int d, const double *W, int dp, int ka, float scale, uint4 *out,
                        hipStream_t st) {
-    if (W == nullptr) {  // the identity, dp = d
+    if (W == nullptr) {  // the identity, dp = d <= DP_MAX
         k_aug_ident<<<(unsigned)((rows_pad + 255) / 256), 256, 0, st>>>(X, order, rows, rows_pad,
                                                                        d, ka, scale, out);
         return;

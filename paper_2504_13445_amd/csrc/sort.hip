@@ -33,10 +33,15 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(
     hist[t] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * SORT_CHUNK;
+    uint32_t kr[SORT_ROUNDS];
+#pragma unroll
     for (int r = 0; r < SORT_ROUNDS; ++r) {
-        int64_t e = base + (int64_t)r * SORT_THREADS + t;
-        if (e < n) atomicAdd(&hist[(keys[e] >> shift) & 255u], 1u);
+        const int64_t e = base + (int64_t)r * SORT_THREADS + t;
+        kr[r] = e < n ? keys[e] : 0u;
     }
+#pragma unroll
+    for (int r = 0; r < SORT_ROUNDS; ++r)
+        if (base + (int64_t)r * SORT_THREADS + t < n) atomicAdd(&hist[(kr[r] >> shift) & 255u], 1u);
     __syncthreads();
     const int64_t stride = (int64_t)256 * nblocks;
     const int64_t ci = count_index(small, t, blockIdx.x, nblocks);
@@ -126,6 +131,17 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     __shared__ uint32_t wsum[SORT_THREADS / WAVE];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const bool small = nblocks <= PREFIX_MAX_BLOCKS;
+    // this thread's elements of all rounds, loaded before the offsets are
+    // summed
+    const int64_t b0 = (int64_t)blockIdx.x * SORT_CHUNK;
+    uint32_t kr[SORT_ROUNDS];
+    int32_t vr[SORT_ROUNDS];
+#pragma unroll
+    for (int r = 0; r < SORT_ROUNDS; ++r) {
+        const int64_t e = b0 + (int64_t)r * SORT_THREADS + t;
+        kr[r] = e < n ? kin[e] : 0u;
+        vr[r] = e < n ? vin[e] : 0;
+    }
     if (small) {
         // wave w sums the rows w, w + 4, ...: lane l holds digits 4l..4l+3;
         // wcnt collects the rows before this block, ptot all rows
@@ -164,13 +180,13 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
         for (int q = 0; q < SORT_THREADS / WAVE; ++q) wcnt[q][t] = 0;
     }
     __syncthreads();
-    const int64_t b0 = (int64_t)blockIdx.x * SORT_CHUNK;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
     for (int r = 0; r < SORT_ROUNDS; ++r) {
         const int64_t e = b0 + (int64_t)r * SORT_THREADS + t;
         const bool active = e < n;
-        uint32_t key = active ? kin[e] : 0u;
-        int32_t val = active ? vin[e] : 0;
+        const uint32_t key = kr[r];
+        const int32_t val = vr[r];
         uint32_t dig = (key >> shift) & 255u;
         // lanes of this wave holding the same digit
         uint64_t peers = __ballot(active);

@@ -671,7 +671,7 @@ __global__ __launch_bounds__(256) void k_thresh_exact(ThreshArgs a) {
         double v = 0.0;
         if (have) {
             id = a.cand_id[u * a.nsplit * (int64_t)a.cap + q];
-            v = ip64<16>(a.U + u * a.d, a.P + (int64_t)id * a.d, a.d);
+            v = ip64<32>(a.U + u * a.d, a.P + (int64_t)id * a.d, a.d);
         }
         // rank among the user's values: the lanes of its group
         int rank = 0;
