@@ -215,10 +215,20 @@ constexpr int LDS_GUARD = 512;  // >= 16 * (32 - 1) bytes of overread
 // over the smallest even chunk count >= nch (every even count up to the
 // largest row), FP32 rows over 8, 16 or 32 chunks with an early stop at
 // nch.  with_nch calls f(std::integral_constant<int, NCH>).
+template <int LO, int HI, class F> void with_exact(int nch, F &&f) {
+    if constexpr (LO <= HI) {
+        if (nch == LO) f(std::integral_constant<int, LO>{});
+        else with_exact<LO + 1, HI>(nch, f);
+    }
+}
 template <int PREC, class F> void with_nch(int nch, F &&f) {
     if constexpr (PREC == PREC_FP32) {
-        if (nch <= 8) f(std::integral_constant<int, 8>{});
-        else if (nch <= 16) f(std::integral_constant<int, 16>{});
+        // every count up to 16 (each chunk costs eight FP32 products), then
+        // multiples of 4
+        if (nch <= 16) with_exact<1, 16>(nch, f);
+        else if (nch <= 20) f(std::integral_constant<int, 20>{});
+        else if (nch <= 24) f(std::integral_constant<int, 24>{});
+        else if (nch <= 28) f(std::integral_constant<int, 28>{});
         else f(std::integral_constant<int, 32>{});
     } else {
         switch ((nch + 1) & ~1) {
@@ -241,13 +251,15 @@ template <int PREC, class F> void with_nch(int nch, F &&f) {
 template <int PREC, int NCH> struct MMR;
 
 template <int NCH> struct MMR<PREC_FP32, NCH> {
+    // all NCH chunks without branches: chunks from nch on are zero in the
+    // register operand and add exact zeros (the LDS reads past a row end
+    // land in the next row, the row padding or the zero guard: finite)
     static __device__ __forceinline__ void rows2(f32x16 &c0, f32x16 &c1, const uint8_t *A0,
                                                  const uint8_t *A1, const uint4 (&b)[NCH],
                                                  int ls, int nch, int D, int lane) {
         const int off = (lane & 31) * ls + (lane >> 5) * (D / 2) * 4;
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
-            if (c < nch) {
             const f32x4 x0 = *reinterpret_cast<const f32x4 *>(A0 + off + 16 * c);
             const f32x4 x1 = *reinterpret_cast<const f32x4 *>(A1 + off + 16 * c);
             const float y[4] = {__uint_as_float(b[c].x), __uint_as_float(b[c].y),
@@ -257,7 +269,6 @@ template <int NCH> struct MMR<PREC_FP32, NCH> {
                 c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(x0[q], y[q], c0, 0, 0, 0);
                 c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(x1[q], y[q], c1, 0, 0, 0);
             }
-            }
         }
     }
     static __device__ __forceinline__ void cols2(f32x16 &c0, f32x16 &c1, const uint4 (&a)[NCH],
@@ -266,7 +277,6 @@ template <int NCH> struct MMR<PREC_FP32, NCH> {
         const int off = (lane & 31) * ls + (lane >> 5) * (D / 2) * 4;
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
-            if (c < nch) {
             const f32x4 y0 = *reinterpret_cast<const f32x4 *>(B0 + off + 16 * c);
             const f32x4 y1 = *reinterpret_cast<const f32x4 *>(B1 + off + 16 * c);
             const float x[4] = {__uint_as_float(a[c].x), __uint_as_float(a[c].y),
@@ -275,7 +285,6 @@ template <int NCH> struct MMR<PREC_FP32, NCH> {
             for (int q = 0; q < 4; ++q) {
                 c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(x[q], y0[q], c0, 0, 0, 0);
                 c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(x[q], y1[q], c1, 0, 0, 0);
-            }
             }
         }
     }

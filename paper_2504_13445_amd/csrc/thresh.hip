@@ -296,9 +296,12 @@ void k_thresh_screen(ThreshArgs a) {
             // first on the tile bound, then per item; the scales are powers of
             // two, so multiplying by their exact reciprocals divides exactly
             const float thr = (L0 - e_t) * (su_inv * pow2_rcp(sp_t));
-            float vmax = fmaxf(acc0[0], acc1[0]);
+            // (a linear chain: it compiles to three-input maxima)
+            float vmax = acc0[0];
 #pragma unroll
-            for (int i = 1; i < 16; ++i) vmax = fmaxf(vmax, fmaxf(acc0[i], acc1[i]));
+            for (int i = 1; i < 16; ++i) vmax = fmaxf(vmax, acc0[i]);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) vmax = fmaxf(vmax, acc1[i]);
             if (__ballot(vmax >= thr && uvalid) != 0ull) {
                 // this lane's slots that pass the tile bound (bit i: register
                 // i & 15 of block i >> 4), then each of them once
