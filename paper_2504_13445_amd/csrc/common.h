@@ -29,6 +29,18 @@ constexpr float E_ABS = 0x1p-99f;
 // each half-wave owns a contiguous half of the row, so D is a multiple of 8.
 __host__ __device__ inline int padded_dim_fp32(int d) { return (d + 7) & ~7; }
 
+// FP32 rows split at h = ceil(d / 2): values 0..h-1 open the first half
+// (D / 2 slots), values h..d-1 the second, each half padded with zeros at
+// its end, so that value slots 4c + q >= h of both halves are zero and their
+// matrix-core steps can be skipped.  Slot of value (or padding entry) c < D:
+__host__ __device__ inline int fp32_slot(int c, int d, int D) {
+    const int h = (d + 1) / 2, gap = D / 2 - h;  // zeros closing the first half
+    if (c < h) return c;
+    if (c < d) return D / 2 + (c - h);
+    if (c < d + gap) return h + (c - d);
+    return c;  // zeros closing the second half
+}
+
 // Padded dimensionality and element size per screening precision: each
 // half-wave owns half of the row; a BF16 step takes 8 elements per lane
 // (D multiple of 16), an FP8 step 32 (D multiple of 64).
@@ -254,9 +266,11 @@ template <int NCH> struct MMR<PREC_FP32, NCH> {
     // all NCH chunks without branches: chunks from nch on are zero in the
     // register operand and add exact zeros (the LDS reads past a row end
     // land in the next row, the row padding or the zero guard: finite)
+    // (h = ceil(d / 2): the steps of value slots 4c + q >= h multiply zeros
+    // in both halves, see fp32_slot, and are skipped in the last chunk)
     static __device__ __forceinline__ void rows2(f32x16 &c0, f32x16 &c1, const uint8_t *A0,
                                                  const uint8_t *A1, const uint4 (&b)[NCH],
-                                                 int ls, int nch, int D, int lane) {
+                                                 int ls, int nch, int D, int h, int lane) {
         const int off = (lane & 31) * ls + (lane >> 5) * (D / 2) * 4;
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
@@ -266,14 +280,16 @@ template <int NCH> struct MMR<PREC_FP32, NCH> {
                                 __uint_as_float(b[c].z), __uint_as_float(b[c].w)};
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(x0[q], y[q], c0, 0, 0, 0);
-                c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(x1[q], y[q], c1, 0, 0, 0);
+                if (c < NCH - 1 || 4 * c + q < h) {
+                    c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(x0[q], y[q], c0, 0, 0, 0);
+                    c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(x1[q], y[q], c1, 0, 0, 0);
+                }
             }
         }
     }
     static __device__ __forceinline__ void cols2(f32x16 &c0, f32x16 &c1, const uint4 (&a)[NCH],
                                                  const uint8_t *B0, const uint8_t *B1, int ls,
-                                                 int nch, int D, int lane) {
+                                                 int nch, int D, int h, int lane) {
         const int off = (lane & 31) * ls + (lane >> 5) * (D / 2) * 4;
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
@@ -283,8 +299,10 @@ template <int NCH> struct MMR<PREC_FP32, NCH> {
                                 __uint_as_float(a[c].z), __uint_as_float(a[c].w)};
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(x[q], y0[q], c0, 0, 0, 0);
-                c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(x[q], y1[q], c1, 0, 0, 0);
+                if (c < NCH - 1 || 4 * c + q < h) {
+                    c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(x[q], y0[q], c0, 0, 0, 0);
+                    c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(x[q], y1[q], c1, 0, 0, 0);
+                }
             }
         }
     }
@@ -296,7 +314,7 @@ template <int NCH> struct MMR<PREC_BF16, NCH> {
     }
     static __device__ __forceinline__ void rows2(f32x16 &c0, f32x16 &c1, const uint8_t *A0,
                                                  const uint8_t *A1, const uint4 (&b)[NCH],
-                                                 int ls, int nch, int D, int lane) {
+                                                 int ls, int nch, int D, int /*h*/, int lane) {
         const int off = (lane & 31) * ls + (lane >> 5) * (D / 2) * 2;
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
@@ -308,7 +326,7 @@ template <int NCH> struct MMR<PREC_BF16, NCH> {
     }
     static __device__ __forceinline__ void cols2(f32x16 &c0, f32x16 &c1, const uint4 (&a)[NCH],
                                                  const uint8_t *B0, const uint8_t *B1, int ls,
-                                                 int nch, int D, int lane) {
+                                                 int nch, int D, int /*h*/, int lane) {
         const int off = (lane & 31) * ls + (lane >> 5) * (D / 2) * 2;
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
@@ -327,7 +345,7 @@ template <int NCH> struct MMR<PREC_FP8, NCH> {
     }
     static __device__ __forceinline__ void rows2(f32x16 &c0, f32x16 &c1, const uint8_t *A0,
                                                  const uint8_t *A1, const uint4 (&b)[NCH],
-                                                 int ls, int nch, int D, int lane) {
+                                                 int ls, int nch, int D, int /*h*/, int lane) {
         const int off = (lane & 31) * ls + (lane >> 5) * (D / 2);
 #pragma unroll
         for (int c = 0; c + 1 < NCH; c += 2) {
@@ -342,7 +360,7 @@ template <int NCH> struct MMR<PREC_FP8, NCH> {
     }
     static __device__ __forceinline__ void cols2(f32x16 &c0, f32x16 &c1, const uint4 (&a)[NCH],
                                                  const uint8_t *B0, const uint8_t *B1, int ls,
-                                                 int nch, int D, int lane) {
+                                                 int nch, int D, int /*h*/, int lane) {
         const int off = (lane & 31) * ls + (lane >> 5) * (D / 2);
 #pragma unroll
         for (int c = 0; c + 1 < NCH; c += 2) {

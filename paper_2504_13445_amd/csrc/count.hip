@@ -263,7 +263,7 @@ void k_count(CountArgs a) {
         auto multiply = [&]() {
             acc0 = f32x16{0};
             acc1 = f32x16{0};
-            MMR<PREC, NCH>::cols2(acc0, acc1, ia, Ub, Ub + 32 * ls, ls, nch, D, lane);
+            MMR<PREC, NCH>::cols2(acc0, acc1, ia, Ub, Ub + 32 * ls, ls, nch, D, (a.d + 1) / 2, lane);
             ptin0 = tin0;
             ptout0 = tout0;
             ptin1 = tin1;

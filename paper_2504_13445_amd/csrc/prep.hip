@@ -125,7 +125,7 @@ __global__ __launch_bounds__(256) void k_quant(const float *__restrict__ X,
                 float qv;
                 if (PREC == PREC_FP32) {
                     qv = t;
-                    if (live) reinterpret_cast<float *>(Xq)[r * D + c] = t;
+                    if (live) reinterpret_cast<float *>(Xq)[r * D + fp32_slot(c, d, D)] = t;
                 } else if (PREC == PREC_BF16) {
                     const uint16_t h = to_bf16(t, qv);
                     if (live) reinterpret_cast<uint16_t *>(Xq)[r * D + c] = h;

@@ -240,7 +240,7 @@ void k_thresh_screen(ThreshArgs a) {
                 const float e_t = ebound(Nsh[0], Nsh[3 * TILE_ITEMS], Nsh[3 * TILE_ITEMS + 1]);
                 const float sc = su * Nsh[3 * TILE_ITEMS + 2];
                 f32x16 acc0 = {0}, acc1 = {0};
-                MMR<PREC, NCH>::rows2(acc0, acc1, Psh, Psh + 32 * ls, ub, ls, nch, D, lane);
+                MMR<PREC, NCH>::rows2(acc0, acc1, Psh, Psh + 32 * ls, ub, ls, nch, D, (a.d + 1) / 2, lane);
 #pragma unroll
                 for (int i = 0; i < 16; ++i) {
                     const int r = mfma32_row(i, lane);
@@ -292,7 +292,7 @@ void k_thresh_screen(ThreshArgs a) {
             const float sp_t = Nsh[3 * TILE_ITEMS + 2];
             const float sc = su * sp_t;  // product scale of this (user, tile)
             f32x16 acc0 = {0}, acc1 = {0};
-            MMR<PREC, NCH>::rows2(acc0, acc1, Psh, Psh + 32 * ls, ub, ls, nch, D, lane);
+            MMR<PREC, NCH>::rows2(acc0, acc1, Psh, Psh + 32 * ls, ub, ls, nch, D, (a.d + 1) / 2, lane);
             // first on the tile bound, then per item; the scales are powers of
             // two, so multiplying by their exact reciprocals divides exactly
             const float thr = (L0 - e_t) * (su_inv * pow2_rcp(sp_t));
