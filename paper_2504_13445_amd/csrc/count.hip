@@ -79,8 +79,9 @@ void k_count(CountArgs a) {
     int *ambn = cntl + CNT_ITEMS;
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int64_t ib = (int64_t)blockIdx.x * CNT_ITEMS;
-    const int split = blockIdx.y;
+    // item-block-major order: the blocks of the longest prefixes start first
+    const int64_t ib = (int64_t)(blockIdx.x / a.nsplit) * CNT_ITEMS;
+    const int split = (int)(blockIdx.x % a.nsplit);
 
     // this lane's half of its item's row (row lane & 31 of the wave's 32),
     // kept in registers for the whole kernel
@@ -313,7 +314,7 @@ template <int PREC>
 void launch_count_p(const CountArgs &a, size_t lds, hipStream_t st) {
     with_nch<PREC>(a.D * elem_bytes(PREC) / 32, [&](auto n) {
         constexpr int NCH = decltype(n)::value, NW = count_waves(NCH);
-        dim3 g((unsigned)((a.nb + 32 * NW - 1) / (32 * NW)), (unsigned)a.nsplit);
+        const unsigned g = (unsigned)((a.nb + 32 * NW - 1) / (32 * NW) * a.nsplit);
         k_count<PREC, NCH><<<g, 64 * NW, lds, st>>>(a);
     });
 }
@@ -353,8 +354,10 @@ __global__ __launch_bounds__(64 * BW) void k_bound(BoundArgs a) {
     __shared__ int wsum[BW][BI];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int h = lane >> 5, col = lane & 31;
-    const int64_t ib = (int64_t)blockIdx.x * BI;
-    const int split = blockIdx.y;
+    // workgroups in item-block-major order (all splits of a block, then the
+    // next block): the blocks of the longest prefixes start first
+    const int64_t ib = (int64_t)(blockIdx.x / a.nsplit) * BI;
+    const int split = (int)(blockIdx.x % a.nsplit);
     // the items' hi and lo parts: row col of each tile, K half h of each step
     bf16x8 ah[TI][KS], al[TI][KS];
 #pragma unroll
@@ -478,8 +481,10 @@ void k_bound_lds(BoundArgs a) {
     float (*tsh)[BL_USERS] = reinterpret_cast<float (*)[BL_USERS]>(smem_b + 2 * BL_USERS * LSL * 16);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int h = lane >> 5, col = lane & 31;
-    const int64_t ib = (int64_t)blockIdx.x * BI;
-    const int split = blockIdx.y;
+    // workgroups in item-block-major order (all splits of a block, then the
+    // next block): the blocks of the longest prefixes start first
+    const int64_t ib = (int64_t)(blockIdx.x / a.nsplit) * BI;
+    const int split = (int)(blockIdx.x % a.nsplit);
     // this wave's items: rows ib + 64 w + 32 t + col, hi and lo, K half h
     bf16x8 ah[TI][KS], al[TI][KS];
 #pragma unroll
@@ -609,7 +614,7 @@ constexpr size_t bound_lds_bytes(int ks) { return 2 * (size_t)BL_USERS * (4 * ks
 void launch_bound(const BoundArgs &a, hipStream_t st) {
     auto go = [&](auto ks) {
         constexpr int KS = decltype(ks)::value, BI = bound_items(KS);
-        dim3 g((unsigned)((a.m + BI - 1) / BI), (unsigned)a.nsplit);
+        const unsigned g = (unsigned)((a.m + BI - 1) / BI * a.nsplit);
         if constexpr (KS >= 3) k_bound_lds<KS><<<g, 64 * BLW, bound_lds_bytes(KS), st>>>(a);
         else k_bound<KS><<<g, 64 * BW, 0, st>>>(a);
     };
