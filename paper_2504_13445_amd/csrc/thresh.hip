@@ -72,10 +72,11 @@ __device__ __forceinline__ void merge32_desc(float (&v)[32]) {
 // registers), two item-tile buffers in LDS (the next tile is copied in while
 // the current one is used; the registers allow one workgroup per CU, which
 // has the LDS to itself), nch 16-byte chunks per half row.
-constexpr int SCR_NW = 8;  // at most
-// 8 waves while a half row fits in 16 chunks (two waves per SIMD, 256
-// registers each); 4 for longer rows, whose waves need more registers
-__host__ __device__ constexpr int screen_waves(int nch) { return nch <= 16 ? 8 : 4; }
+constexpr int SCR_NW = 12;  // at most
+// 12 waves while a half row fits in 8 chunks (three waves per SIMD, 168
+// registers each), 8 up to 16 chunks (two per SIMD, 256 registers each), 4
+// for longer rows, whose waves need more registers
+__host__ __device__ constexpr int screen_waves(int nch) { return nch <= 8 ? 12 : nch <= 16 ? 8 : 4; }
 // per tile buffer: N, Nh, R of the 64 items, the tile's largest Nh and R
 // and its scale in the first three of 64 slots, and the items' caller ids
 // (copied in with the tile, so that no global load is waited for)
@@ -133,7 +134,7 @@ __device__ __forceinline__ int64_t screen_blocks(const ThreshArgs &a, int tu) {
 template <int PREC, int NCH, bool LISTED>
 // two waves per SIMD (the register budget of 256) where the row fits in
 // 16 chunks; longer FP32 rows keep all registers for one wave
-__global__ __launch_bounds__(64 * screen_waves(NCH)) __attribute__((amdgpu_waves_per_eu(NCH <= 16 ? 2 : 1)))
+__global__ __launch_bounds__(64 * screen_waves(NCH)) __attribute__((amdgpu_waves_per_eu(screen_waves(NCH) / 4)))
 void k_thresh_screen(ThreshArgs a) {
     constexpr int NW = screen_waves(NCH), TU = 32 * NW;
     extern __shared__ __align__(16) uint8_t smem8[];
