@@ -25,6 +25,8 @@ struct rmips_ctx {
     int32_t *bound_out = nullptr;  // device, m int32 (testing knob)
     int32_t *h_status = nullptr;  // pinned, small
     int64_t *h_scalar = nullptr;  // pinned, small
+    int32_t *h_vis = nullptr;     // pinned: visit-order bounds and prefixes, top-N
+    int64_t h_vis_cap = 0;        // its size in int32 entries
 };
 
 namespace {
@@ -400,6 +402,7 @@ void rmips_destroy(rmips_ctx *ctx) {
     if (!ctx) return;
     if (ctx->h_status) (void)hipHostFree(ctx->h_status);
     if (ctx->h_scalar) (void)hipHostFree(ctx->h_scalar);
+    if (ctx->h_vis) (void)hipHostFree(ctx->h_vis);
     delete ctx;
 }
 
@@ -657,9 +660,19 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     launch_gather_i32(L.uscore, L.visit, m, L.vis_us, st);
     launch_gather_i32(L.cs, L.visit, m, L.vis_cs, st);
     launch_gather_i32(L.T.perm, L.visit, m, L.vis_cid, st);
-    std::vector<int32_t> h_us(m), h_cs(m);
-    HIPTRY(hipMemcpyAsync(h_us.data(), L.vis_us, sizeof(int32_t) * m, hipMemcpyDeviceToHost, st));
-    HIPTRY(hipMemcpyAsync(h_cs.data(), L.vis_cs, sizeof(int32_t) * m, hipMemcpyDeviceToHost, st));
+    // pinned host copies (grown once per larger m): bounds and prefixes in
+    // visit order, then room for the top-N list
+    const int64_t need = 2 * m + 2 * (int64_t)N;
+    if (ctx->h_vis_cap < need) {
+        if (ctx->h_vis) HIPTRY(hipHostFree(ctx->h_vis));
+        ctx->h_vis = nullptr;
+        ctx->h_vis_cap = 0;
+        HIPTRY(hipHostMalloc((void **)&ctx->h_vis, sizeof(int32_t) * need, hipHostMallocDefault));
+        ctx->h_vis_cap = need;
+    }
+    int32_t *h_us = ctx->h_vis, *h_cs = ctx->h_vis + m;
+    HIPTRY(hipMemcpyAsync(h_us, L.vis_us, sizeof(int32_t) * m, hipMemcpyDeviceToHost, st));
+    HIPTRY(hipMemcpyAsync(h_cs, L.vis_cs, sizeof(int32_t) * m, hipMemcpyDeviceToHost, st));
     HIPTRY(hipMemcpyAsync(ctx->h_status + 12, L.T.bad, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPTRY(hipEventRecord(ev[2], st));
     HIPTRY(hipStreamSynchronize(st));
@@ -726,8 +739,8 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
         bsz = std::min<int64_t>(e - r0, bmax);
     }
     HIPTRY(hipEventRecord(ev[3], st));
-    std::vector<uint64_t> top(N);
-    HIPTRY(hipMemcpyAsync(top.data(), L.top, sizeof(uint64_t) * N, hipMemcpyDeviceToHost, st));
+    uint64_t *top = reinterpret_cast<uint64_t *>(ctx->h_vis + 2 * m);
+    HIPTRY(hipMemcpyAsync(top, L.top, sizeof(uint64_t) * N, hipMemcpyDeviceToHost, st));
     HIPTRY(hipMemcpyAsync(ctx->h_scalar, L.rechecks, CTR_WORDS * sizeof(int64_t),
                           hipMemcpyDeviceToHost, st));
     HIPTRY(hipStreamSynchronize(st));
