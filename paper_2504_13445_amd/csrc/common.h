@@ -70,6 +70,7 @@ __device__ __forceinline__ void mfma32_f32(f32x16 &acc, const float *A,
     const int r = lane & 31, h = lane >> 5;
     const float *a = A + r * ld + h * ks;
     const float *b = B + r * ld + h * ks;
+#pragma unroll 4
     for (int s = 0; s < ks; s += 4) {
         f32x4 av = *reinterpret_cast<const f32x4 *>(a + s);
         f32x4 bv = *reinterpret_cast<const f32x4 *>(b + s);

@@ -23,18 +23,25 @@ struct SoftDims {
     int d, D, Dg, ld, ldw;  // dims, padded for Z (x8), padded for G (x32), LDS strides
 };
 
+// LDS row stride ld = D + LDS_PAD (not Dg): the gradient's last 32-wide dim
+// block then reads past a user row's end, into the next row or, from the
+// last row, into the weights that follow; those values are finite and only
+// reach dims >= d, which are dropped.  The smaller stride lets two
+// workgroups share a compute unit for d <= 104.
 __host__ __device__ inline SoftDims soft_dims(int d) {
     SoftDims s;
     s.d = d;
     s.D = (d + 7) & ~7;
     s.Dg = (d + 31) & ~31;
-    s.ld = s.Dg + LDS_PAD;
+    s.ld = s.D + LDS_PAD;
     s.ldw = SUC + LDS_PAD;
     return s;
 }
 
 size_t soft_lds(int d) {
     SoftDims s = soft_dims(d);
+    // Q and U rows, the weights, and the reads of the last dim block past U
+    // (which land in the weights: Dg - ld <= SQ * ldw floats)
     return (size_t)(2 * SQ * s.ld + SQ * s.ldw) * sizeof(float) + 4 * SQ * sizeof(float);
 }
 
@@ -69,8 +76,8 @@ __global__ __launch_bounds__(256) void k_soft(const float *__restrict__ U, int64
     const int64_t ub = (int64_t)split * per;
     const int64_t ue = (ub + per < n) ? ub + per : n;
 
-    for (int e = tid; e < SQ * sd.Dg; e += 256) {
-        const int r = e / sd.Dg, c = e - r * sd.Dg;
+    for (int e = tid; e < SQ * ld; e += 256) {
+        const int r = e / ld, c = e - r * ld;
         float v = 0.0f;
         if (q0 + r < nq && c < d) v = Q[(q0 + r) * d + c];
         Qsh[r * ld + c] = v;
@@ -111,7 +118,7 @@ __global__ __launch_bounds__(256) void k_soft(const float *__restrict__ U, int64
 #pragma unroll
             for (int j = 0; j < CPL; ++j) {
                 const int c = lane + 64 * j;
-                if (c < sd.Dg) Ush[(w + 4 * i) * ld + c] = pf[i][j];
+                if (c < ld) Ush[(w + 4 * i) * ld + c] = pf[i][j];
             }
     };
 
@@ -144,6 +151,7 @@ __global__ __launch_bounds__(256) void k_soft(const float *__restrict__ U, int64
             for (int j = 0; j < 4; ++j) {
                 const int cb = cbu + 2 * j;
                 if (cb < ncb) {
+#pragma unroll 8
                     for (int s2 = 0; s2 < SUC; s2 += 2)
                         g[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(
                             wa[s2 + h], Ush[(s2 + h) * ld + cb * 32 + r], g[j], 0, 0, 0);
