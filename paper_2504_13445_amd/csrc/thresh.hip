@@ -792,9 +792,13 @@ void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
     int fw = (int)((150 * 1024) / ((size_t)capP * 24));  // waves whose lists fit in LDS
     fw = fw < 1 ? 1 : (fw > FIN_WAVES ? FIN_WAVES : fw);
     const size_t lds_fin = (size_t)fw * capP * 24;
-    // a grid of at most 2048 workgroups: each wave takes many users in turn
-    const int64_t fblocks = std::min<int64_t>((a0.n + fw - 1) / fw, 2048);
-    const int64_t eblocks = (a0.n + 4 * (64 / EXACT_SLOTS) - 1) / (4 * (64 / EXACT_SLOTS));
+    // one resident round of workgroups (six per CU, fewer when their lists
+    // fill the LDS): each wave takes many users in turn
+    const int64_t fres = 256 * std::max<int64_t>(1, std::min<int64_t>(6, (160 * 1024) / lds_fin));
+    const int64_t fblocks = std::min<int64_t>((a0.n + fw - 1) / fw, fres);
+    // (three 4-wave workgroups per CU are resident)
+    const int64_t eblocks = std::min<int64_t>(
+        (a0.n + 4 * (64 / EXACT_SLOTS) - 1) / (4 * (64 / EXACT_SLOTS)), 3 * 256);
     int32_t *LA = a0.lists, *LB = a0.lists + a0.n, *LF = a0.lists + 2 * a0.n;
     (void)hipMemsetAsync(a0.lcnt, 0, 4 * sizeof(int32_t), st);
     auto screen = [&](const ThreshArgs &a, dim3 g) {
@@ -846,11 +850,12 @@ void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
         b.nsplit = nsr;
         b.cap = capU / nsr;
         b.t0tiles = 0;
-        const int64_t gx = ublocks < 1024 / nsr ? ublocks : 1024 / nsr;
+        // one resident round (one screening workgroup per CU): the lists
+        // are usually empty, and the workgroups loop over long ones
+        const int64_t gx = ublocks < 256 / nsr ? ublocks : 256 / nsr;
         screen(b, dim3((unsigned)gx, (unsigned)nsr));
-        const int64_t gf = fblocks < 2048 ? fblocks : 2048;
-        k_thresh_final<true><<<(unsigned)gf, 64 * fw, lds_fin, st>>>(b, b.nsplit * b.cap, capP);
-        k_thresh_exact<true><<<(unsigned)(eblocks < 1024 ? eblocks : 1024), 256, 0, st>>>(b);
+        k_thresh_final<true><<<(unsigned)fblocks, 64 * fw, lds_fin, st>>>(b, b.nsplit * b.cap, capP);
+        k_thresh_exact<true><<<(unsigned)eblocks, 256, 0, st>>>(b);
     }
     int64_t fb = (a0.n + FB_WAVES - 1) / FB_WAVES;
     if (fb > 1024) fb = 1024;
