@@ -366,7 +366,7 @@ void topn_plan(int prec, int64_t n, int64_t m, int d, int k, int cap_override, i
 int count_splits(int64_t nb, int64_t ulen, int maxs) {
     int64_t iblocks = (nb + 255) / 256;
     int64_t chunks = (ulen + 63) / 64;
-    int64_t s = (1024 + iblocks - 1) / iblocks;
+    int64_t s = (2048 + iblocks - 1) / iblocks;
     s = std::min<int64_t>(s, std::max<int64_t>(1, chunks / 2));
     return (int)std::max<int64_t>(1, std::min<int64_t>(s, maxs));
 }
