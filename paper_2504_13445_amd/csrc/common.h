@@ -24,11 +24,6 @@ constexpr int LDS_PAD = 4;        // floats added to an LDS row (bank spread)
 // products and sums that fall into the FP32 subnormal range.
 constexpr float E_ABS = 0x1p-99f;
 
-// Padded dimensionality of the FP32 matrix-core path: the 32x32x2 product
-// is fed four k-steps at a time from LDS (one 16-byte read per lane), and
-// each half-wave owns a contiguous half of the row, so D is a multiple of 8.
-__host__ __device__ inline int padded_dim_fp32(int d) { return (d + 7) & ~7; }
-
 // FP32 rows split at h = ceil(d / 2): values 0..h-1 open the first half
 // (D / 2 slots), values h..d-1 the second, each half padded with zeros at
 // its end, so that value slots 4c + q >= h of both halves are zero and their
@@ -81,153 +76,31 @@ __device__ __forceinline__ void mfma32_f32(f32x16 &acc, const float *A,
     }
 }
 
-// Two blocks sharing the B operand (rows rb0 and rb1 of A), interleaved so
-// the two accumulation chains overlap in the matrix pipeline.
-__device__ __forceinline__ void mfma32x2_f32(f32x16 &acc0, f32x16 &acc1,
-                                             const float *A0, const float *A1,
-                                             const float *B, int ld, int ks,
-                                             int lane) {
-    const int r = lane & 31, h = lane >> 5;
-    const float *a0 = A0 + r * ld + h * ks;
-    const float *a1 = A1 + r * ld + h * ks;
-    const float *b = B + r * ld + h * ks;
-    for (int s = 0; s < ks; s += 4) {
-        f32x4 av0 = *reinterpret_cast<const f32x4 *>(a0 + s);
-        f32x4 av1 = *reinterpret_cast<const f32x4 *>(a1 + s);
-        f32x4 bv = *reinterpret_cast<const f32x4 *>(b + s);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av0[q], bv[q], acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av1[q], bv[q], acc1, 0, 0, 0);
-        }
-    }
+// 32 bytes of FP8 (e4m3) values from LDS as the 8-register operand of the
+// FP8 matrix-core product (format code 0, unit block scales 0x7f = 2^0).
+__device__ __forceinline__ i32x8 ld_fp8x32(const uint8_t *p) {
+    const i32x4 lo = *reinterpret_cast<const i32x4 *>(p);
+    const i32x4 hi = *reinterpret_cast<const i32x4 *>(p + 16);
+    return i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
 }
 
-// Products over rows of length D held in LDS (byte pointers, row stride ls
-// bytes), for each precision.  As above, half-wave h feeds the dims
-// [h*D/2, (h+1)*D/2) of its row, which pairs the same dims of A and B.
-template <int PREC> struct MM;
-
-template <> struct MM<PREC_FP32> {
-    // acc0 += A0 B^T, acc1 += A1 B^T (32x32 blocks)
-    static __device__ __forceinline__ void rows2(f32x16 &c0, f32x16 &c1, const uint8_t *A0,
-                                                 const uint8_t *A1, const uint8_t *B, int ls,
-                                                 int D, int lane) {
-        const int r = lane & 31, h = lane >> 5, off = r * ls + h * (D / 2) * 4;
-        const float *a0 = reinterpret_cast<const float *>(A0 + off);
-        const float *a1 = reinterpret_cast<const float *>(A1 + off);
-        const float *b = reinterpret_cast<const float *>(B + off);
-        for (int s = 0; s < D / 2; s += 4) {
-            f32x4 x0 = *reinterpret_cast<const f32x4 *>(a0 + s);
-            f32x4 x1 = *reinterpret_cast<const f32x4 *>(a1 + s);
-            f32x4 y = *reinterpret_cast<const f32x4 *>(b + s);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(x0[q], y[q], c0, 0, 0, 0);
-                c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(x1[q], y[q], c1, 0, 0, 0);
-            }
-        }
-    }
-    // acc0 += A B0^T, acc1 += A B1^T
-    static __device__ __forceinline__ void cols2(f32x16 &c0, f32x16 &c1, const uint8_t *A,
-                                                 const uint8_t *B0, const uint8_t *B1, int ls,
-                                                 int D, int lane) {
-        const int r = lane & 31, h = lane >> 5, off = r * ls + h * (D / 2) * 4;
-        const float *a = reinterpret_cast<const float *>(A + off);
-        const float *b0 = reinterpret_cast<const float *>(B0 + off);
-        const float *b1 = reinterpret_cast<const float *>(B1 + off);
-        for (int s = 0; s < D / 2; s += 4) {
-            f32x4 x = *reinterpret_cast<const f32x4 *>(a + s);
-            f32x4 y0 = *reinterpret_cast<const f32x4 *>(b0 + s);
-            f32x4 y1 = *reinterpret_cast<const f32x4 *>(b1 + s);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(x[q], y0[q], c0, 0, 0, 0);
-                c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(x[q], y1[q], c1, 0, 0, 0);
-            }
-        }
-    }
-};
-
-template <> struct MM<PREC_BF16> {
-    static __device__ __forceinline__ void rows2(f32x16 &c0, f32x16 &c1, const uint8_t *A0,
-                                                 const uint8_t *A1, const uint8_t *B, int ls,
-                                                 int D, int lane) {
-        const int r = lane & 31, h = lane >> 5, off = r * ls + h * (D / 2) * 2;
-        const uint8_t *a0 = A0 + off, *a1 = A1 + off, *b = B + off;
-        for (int s = 0; s < D; s += 16) {  // bytes of 8 elements per step
-            bf16x8 x0 = *reinterpret_cast<const bf16x8 *>(a0 + s);
-            bf16x8 x1 = *reinterpret_cast<const bf16x8 *>(a1 + s);
-            bf16x8 y = *reinterpret_cast<const bf16x8 *>(b + s);
-            c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x0, y, c0, 0, 0, 0);
-            c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x1, y, c1, 0, 0, 0);
-        }
-    }
-    static __device__ __forceinline__ void cols2(f32x16 &c0, f32x16 &c1, const uint8_t *A,
-                                                 const uint8_t *B0, const uint8_t *B1, int ls,
-                                                 int D, int lane) {
-        const int r = lane & 31, h = lane >> 5, off = r * ls + h * (D / 2) * 2;
-        const uint8_t *a = A + off, *b0 = B0 + off, *b1 = B1 + off;
-        for (int s = 0; s < D; s += 16) {
-            bf16x8 x = *reinterpret_cast<const bf16x8 *>(a + s);
-            bf16x8 y0 = *reinterpret_cast<const bf16x8 *>(b0 + s);
-            bf16x8 y1 = *reinterpret_cast<const bf16x8 *>(b1 + s);
-            c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, y0, c0, 0, 0, 0);
-            c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, y1, c1, 0, 0, 0);
-        }
-    }
-};
-
-template <> struct MM<PREC_FP8> {
-    // OCP e4m3 operands (format code 0), unit block scales (E8M0 127 = 2^0)
-    static __device__ __forceinline__ i32x8 ld32(const uint8_t *p) {
-        i32x4 lo = *reinterpret_cast<const i32x4 *>(p);
-        i32x4 hi = *reinterpret_cast<const i32x4 *>(p + 16);
-        return i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-    }
-    static __device__ __forceinline__ void rows2(f32x16 &c0, f32x16 &c1, const uint8_t *A0,
-                                                 const uint8_t *A1, const uint8_t *B, int ls,
-                                                 int D, int lane) {
-        const int r = lane & 31, h = lane >> 5, off = r * ls + h * (D / 2);
-        const uint8_t *a0 = A0 + off, *a1 = A1 + off, *b = B + off;
-        for (int s = 0; s < D / 2; s += 32) {
-            i32x8 x0 = ld32(a0 + s), x1 = ld32(a1 + s), y = ld32(b + s);
-            c0 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x0, y, c0, 0, 0, 0, 0x7f7f7f7f,
-                                                                 0, 0x7f7f7f7f);
-            c1 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x1, y, c1, 0, 0, 0, 0x7f7f7f7f,
-                                                                 0, 0x7f7f7f7f);
-        }
-    }
-    static __device__ __forceinline__ void cols2(f32x16 &c0, f32x16 &c1, const uint8_t *A,
-                                                 const uint8_t *B0, const uint8_t *B1, int ls,
-                                                 int D, int lane) {
-        const int r = lane & 31, h = lane >> 5, off = r * ls + h * (D / 2);
-        const uint8_t *a = A + off, *b0 = B0 + off, *b1 = B1 + off;
-        for (int s = 0; s < D / 2; s += 32) {
-            i32x8 x = ld32(a + s), y0 = ld32(b0 + s), y1 = ld32(b1 + s);
-            c0 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x, y0, c0, 0, 0, 0, 0x7f7f7f7f,
-                                                                 0, 0x7f7f7f7f);
-            c1 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x, y1, c1, 0, 0, 0, 0x7f7f7f7f,
-                                                                 0, 0x7f7f7f7f);
-        }
-    }
-};
-
-// Same products with the stationary operand held in registers: each lane's
-// half row as NCH 16-byte chunks (FP32: 4 elements, BF16: 8, FP8: 16).
+// Products with the stationary operand held in registers: each lane's half
+// row as NCH 16-byte chunks (FP32: 4 elements, BF16: 8, FP8: 16), the other
+// operand's rows in LDS (row stride ls bytes; half-wave h feeds the dims
+// [h*D/2, (h+1)*D/2) of its row, which pairs the same dims of both rows).
 // rows2: c0 += A0 B^T, c1 += A1 B^T with B in registers; cols2: c0 += A
-// B0^T, c1 += A B1^T with A in registers.  FP32 stops after the row's nch
-// chunks (each read feeds four products).  BF16 and FP8 multiply all NCH
-// chunks, without branches, so that the LDS reads run ahead of the products:
-// the register chunks past nch are zero and add exact zeros, and the LDS
-// reads past a row end stay in the next row or in the LDS_GUARD bytes of
-// zeros that follow each buffer (finite values, so 0 * x = 0).
+// B0^T, c1 += A B1^T with A in registers.  All NCH chunks are multiplied
+// without branches, so that the LDS reads run ahead of the products: the
+// register chunks past nch are zero and add exact zeros, and the LDS reads
+// past a row end stay in the next row or in the LDS_GUARD bytes of zeros
+// that follow each buffer (finite values, so 0 * x = 0).  FP32 skips the
+// steps of the zero slots of its split layout in the last chunk.
 constexpr int LDS_GUARD = 512;  // >= 16 * (32 - 1) bytes of overread
 
 // Register-operand widths that are compiled: BF16 and FP8 rows are multiplied
 // over the smallest even chunk count >= nch (every even count up to the
-// largest row), FP32 rows over 8, 16 or 32 chunks with an early stop at
-// nch.  with_nch calls f(std::integral_constant<int, NCH>).
+// largest row), FP32 rows over every count up to 16 and multiples of 4
+// above.  with_nch calls f(std::integral_constant<int, NCH>).
 template <int LO, int HI, class F> void with_exact(int nch, F &&f) {
     if constexpr (LO <= HI) {
         if (nch == LO) f(std::integral_constant<int, LO>{});
@@ -350,8 +223,8 @@ template <int NCH> struct MMR<PREC_FP8, NCH> {
         const int off = (lane & 31) * ls + (lane >> 5) * (D / 2);
 #pragma unroll
         for (int c = 0; c + 1 < NCH; c += 2) {
-            const i32x8 x0 = MM<PREC_FP8>::ld32(A0 + off + 16 * c);
-            const i32x8 x1 = MM<PREC_FP8>::ld32(A1 + off + 16 * c);
+            const i32x8 x0 = ld_fp8x32(A0 + off + 16 * c);
+            const i32x8 x1 = ld_fp8x32(A1 + off + 16 * c);
             const i32x8 y = pair(b[c], b[c + 1]);
             c0 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x0, y, c0, 0, 0, 0, 0x7f7f7f7f,
                                                                  0, 0x7f7f7f7f);
@@ -366,8 +239,8 @@ template <int NCH> struct MMR<PREC_FP8, NCH> {
 #pragma unroll
         for (int c = 0; c + 1 < NCH; c += 2) {
             const i32x8 x = pair(a[c], a[c + 1]);
-            const i32x8 y0 = MM<PREC_FP8>::ld32(B0 + off + 16 * c);
-            const i32x8 y1 = MM<PREC_FP8>::ld32(B1 + off + 16 * c);
+            const i32x8 y0 = ld_fp8x32(B0 + off + 16 * c);
+            const i32x8 y1 = ld_fp8x32(B1 + off + 16 * c);
             c0 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x, y0, c0, 0, 0, 0, 0x7f7f7f7f,
                                                                  0, 0x7f7f7f7f);
             c1 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x, y1, c1, 0, 0, 0, 0x7f7f7f7f,
