@@ -39,7 +39,7 @@ constexpr int DPRIME_MAX = 62;
 int dprime(int d) { return std::min(d, DPRIME_MAX); }
 int aug_len(int d) { return (dprime(d) + 2 + 15) & ~15; }  // ka: 16, 32, 48 or 64
 constexpr int T0_TILES = 6;             // tiles of phase 1 of stage (a)
-constexpr int BATCH_FIRST = 512;
+constexpr int BATCH_FIRST = 256;
 constexpr int BATCH_MAX = 4096;
 constexpr int GRAM_SAMPLE = 16384;
 
