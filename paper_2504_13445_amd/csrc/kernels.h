@@ -104,7 +104,6 @@ struct ThreshArgs {
     // users grouped by their early-exit ratio before the main pass: sort
     // keys, the order, radix-sort scratch, and a device int holding n
     uint32_t *ukey; int32_t *uord; void *usort; int32_t *nall;
-    int phase1_only;  // set by launch_thresh for the bounds-only pass
     // set per pass by launch_thresh
     const int32_t *ulist; const int32_t *ulist_cnt;  // users of this pass (NULL = all)
     int32_t *rlist; int32_t *rcnt;                   // out: users to screen again

@@ -77,6 +77,15 @@ constexpr int SCR_NW = 12;  // at most
 // registers each), 8 up to 16 chunks (two per SIMD, 256 registers each), 4
 // for longer rows, whose waves need more registers
 __host__ __device__ constexpr int screen_waves(int nch) { return nch <= 8 ? 12 : nch <= 16 ? 8 : 4; }
+// the bounds-only pass (phase 1 alone, fewer registers): 8 waves, two
+// workgroups per CU (128 registers) while a half row fits in 8 chunks
+__host__ __device__ constexpr int screen_waves_p1(int nch) { return nch <= 8 ? 8 : screen_waves(nch); }
+template <bool LISTED> __host__ __device__ constexpr int screen_nw(int nch) {
+    return LISTED ? screen_waves(nch) : screen_waves_p1(nch);
+}
+template <bool LISTED> __host__ __device__ constexpr int screen_wpe(int nch) {
+    return (!LISTED && nch <= 8) ? 4 : screen_waves(nch) / 4;
+}
 // per tile buffer: N, Nh, R of the 64 items, the tile's largest Nh and R
 // and its scale in the first three of 64 slots, and the items' caller ids
 // (copied in with the tile, so that no global load is waited for)
@@ -134,9 +143,9 @@ __device__ __forceinline__ int64_t screen_blocks(const ThreshArgs &a, int tu) {
 template <int PREC, int NCH, bool LISTED>
 // two waves per SIMD (the register budget of 256) where the row fits in
 // 16 chunks; longer FP32 rows keep all registers for one wave
-__global__ __launch_bounds__(64 * screen_waves(NCH)) __attribute__((amdgpu_waves_per_eu(screen_waves(NCH) / 4)))
+__global__ __launch_bounds__(64 * screen_nw<LISTED>(NCH)) __attribute__((amdgpu_waves_per_eu(screen_wpe<LISTED>(NCH))))
 void k_thresh_screen(ThreshArgs a) {
-    constexpr int NW = screen_waves(NCH), TU = 32 * NW;
+    constexpr int NW = screen_nw<LISTED>(NCH), TU = 32 * NW;
     extern __shared__ __align__(16) uint8_t smem8[];
     const int D = a.D, ls = lds_row_bytes(PREC, D), rowb = D * elem_bytes(PREC);
     const int nch = rowb / 32;
@@ -270,8 +279,9 @@ void k_thresh_screen(ThreshArgs a) {
 #pragma unroll
             for (int q = 1; q < NW; ++q) rwg = fminf(rwg, red[q]);
         }
-        if (a.phase1_only) {
-            // the bounds-only pass: keep L0 and go to the next block
+        if constexpr (!LISTED) {
+            // the bounds-only pass (the launch without a user list): keep L0
+            // and go to the next block
             if (split == 0 && lane < 32 && uvalid) a.Luse[ug] = L0;
             continue;
         }
@@ -762,8 +772,8 @@ template <int PREC>
 void launch_screen(const ThreshArgs &a, int nch, dim3 g, size_t lds, hipStream_t st) {
     with_nch<PREC>(nch, [&](auto n) {
         constexpr int NCH = decltype(n)::value;
-        if (a.ulist) k_thresh_screen<PREC, NCH, true><<<g, 64 * screen_waves(NCH), lds, st>>>(a);
-        else k_thresh_screen<PREC, NCH, false><<<g, 64 * screen_waves(NCH), lds, st>>>(a);
+        if (a.ulist) k_thresh_screen<PREC, NCH, true><<<g, 64 * screen_nw<true>(NCH), lds, st>>>(a);
+        else k_thresh_screen<PREC, NCH, false><<<g, 64 * screen_nw<false>(NCH), lds, st>>>(a);
     });
 }
 
@@ -806,14 +816,15 @@ void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
         else if (a.prec == PREC_BF16) launch_screen<PREC_BF16>(a, nch, g, lds, st);
         else launch_screen<PREC_FP8>(a, nch, g, lds, st);
     };
-    // bounds-only pass: every user's L0 from the first tiles (phase 1)
+    // bounds-only pass (the launch without a user list): every user's L0
+    // from the first tiles (phase 1), in workgroups of its own size
     ThreshArgs b0 = a0;
     b0.ulist = nullptr;
     b0.ulist_cnt = nullptr;
-    b0.phase1_only = 1;
     b0.nsplit = 1;
     b0.pairs = nullptr;
-    screen(b0, dim3((unsigned)ublocks, 1u));
+    const int tu1 = 32 * screen_waves_p1(nch);
+    screen(b0, dim3((unsigned)((a0.n + tu1 - 1) / tu1), 1u));
     // users in the order of their early-exit ratios, so that the users of a
     // workgroup stop their scans at about the same tile
     k_exit_keys<<<(unsigned)((a0.n + 255) / 256), 256, 0, st>>>(a0, a0.ukey, a0.uord);
@@ -825,7 +836,6 @@ void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
     ThreshArgs a = a0;
     a.ulist = a0.uord;
     a.ulist_cnt = a0.nall;
-    a.phase1_only = 0;
     a.rlist = a0.refine > 0 ? LA : nullptr;
     a.rcnt = a0.lcnt;
     a.flist = LF;
