@@ -121,10 +121,12 @@ def committed_traffic(kernel, workload, prec):
     if t.get("src_sha256") != _sources_hash() or t.get("workload") != workload or \
             t.get("prec") != prec:
         return None
-    # the kernel's instantiation for the full user set (not the refinement
-    # passes over a user list, which are instantiated separately)
-    names = [x for x in t["kernels"] if x == kernel or
-             (x.startswith(kernel + "<") and not x.endswith("true>"))]
+    # the screening kernel's main pass is its listed instantiation (users in
+    # exit-ratio order; the unlisted one is the short bounds-only pass), and
+    # its largest dispatch (the refinement passes share the symbol and are
+    # empty or small); other kernels: all their instantiations
+    cands = [x for x in t["kernels"] if x == kernel or x.startswith(kernel + "<")]
+    names = [x for x in cands if x.endswith("true>")] or cands
     if not names:
         return None
     k = max((t["kernels"][x] for x in names), key=lambda v: v.get("fetch_bytes_max") or 0)
