@@ -216,20 +216,25 @@ def topn(U, P, k, N, prec="fp32", ws=None, cand_cap=None, batch=None, bound_out=
     ids = np.empty(N, np.int32)
     sc = np.empty(N, np.int32)
     st = Stats()
-    lib.rmips_set_candidate_cap(ctx, int(cand_cap or 0))
-    b0, b1 = batch if batch else (0, 0)
-    lib.rmips_set_batch(ctx, int(b0), int(b1))
+    # the testing knobs are set only when asked for, and reset after the call
     if bound_out is not None:
         if (bound_out.dtype != torch.int32 or bound_out.numel() != m or not bound_out.is_cuda
                 or not bound_out.is_contiguous()):
             raise ValueError("bound_out must be a contiguous int32 device tensor of m entries")
         lib.rmips_set_bound_output(ctx, _ptr(bound_out))
+    if cand_cap:
+        lib.rmips_set_candidate_cap(ctx, int(cand_cap))
+    if batch:
+        lib.rmips_set_batch(ctx, int(batch[0]), int(batch[1]))
     status = lib.rmips_topn(ctx, _ptr(U), n, _ptr(P), m, d, k, N, p, _ptr(ws), ws.numel(),
                             ids.ctypes.data_as(ctypes.c_void_p),
                             sc.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st))
-    lib.rmips_set_candidate_cap(ctx, 0)
-    lib.rmips_set_batch(ctx, 0, 0)
-    lib.rmips_set_bound_output(ctx, None)
+    if cand_cap:
+        lib.rmips_set_candidate_cap(ctx, 0)
+    if batch:
+        lib.rmips_set_batch(ctx, 0, 0)
+    if bound_out is not None:
+        lib.rmips_set_bound_output(ctx, None)
     _check(ctx, status)
     return ids, sc, st.as_dict()
 

@@ -674,16 +674,21 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     HIPTRY(hipMemcpyAsync(h_us, L.vis_us, sizeof(int32_t) * m, hipMemcpyDeviceToHost, st));
     HIPTRY(hipMemcpyAsync(h_cs, L.vis_cs, sizeof(int32_t) * m, hipMemcpyDeviceToHost, st));
     HIPTRY(hipMemcpyAsync(ctx->h_status + 12, L.T.bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    // the running top-N's status, set before the synchronisation (pinned
+    // source, not written again in this call)
+    ctx->h_status[8] = -1;  // N-th score unknown
+    ctx->h_status[9] = 0;   // entries kept
+    HIPTRY(hipMemcpyAsync(L.status, ctx->h_status + 8, 2 * sizeof(int32_t),
+                          hipMemcpyHostToDevice, st));
     HIPTRY(hipEventRecord(ev[2], st));
     HIPTRY(hipStreamSynchronize(st));
     if (ctx->h_status[12] != 0)
         return fail(ctx, RMIPS_ENONFINITE, "input holds a NaN/Inf or a vector norm above 2^60");
 
     // ---- stage (b): exact scores in bound order, running top-N, stop rule
-    ctx->h_status[8] = -1;  // N-th score unknown
-    ctx->h_status[9] = 0;   // entries kept
-    HIPTRY(hipMemcpyAsync(L.status, ctx->h_status + 8, 2 * sizeof(int32_t),
-                          hipMemcpyHostToDevice, st));
+    // (every batch ends with the status, the top-N list and the statistics
+    // copied to the host: the last batch's copies are the results)
+    uint64_t *top = reinterpret_cast<uint64_t *>(ctx->h_vis + 2 * m);
     int64_t r0 = 0, visited = 0, batches = 0, screened = 0, launches = 0;
     float ms_count_k = 0.0f;
     // First batch: the items with the largest bounds.  After it, the items
@@ -716,7 +721,11 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
         }
         launch_topn_merge(L.batch_scores, nb, L.vis_cid + r0, N, L.top, L.status, st);
         HIPTRY(hipGetLastError());
+        HIPTRY(hipEventRecord(ev[3], st));
         HIPTRY(hipMemcpyAsync(ctx->h_status, L.status, 2 * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, st));
+        HIPTRY(hipMemcpyAsync(top, L.top, sizeof(uint64_t) * N, hipMemcpyDeviceToHost, st));
+        HIPTRY(hipMemcpyAsync(ctx->h_scalar, L.rechecks, CTR_WORDS * sizeof(int64_t),
                               hipMemcpyDeviceToHost, st));
         HIPTRY(hipStreamSynchronize(st));
         if (ulen > 0) {
@@ -738,12 +747,7 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
         while (e < m && h_us[e] >= tauN) ++e;
         bsz = std::min<int64_t>(e - r0, bmax);
     }
-    HIPTRY(hipEventRecord(ev[3], st));
-    uint64_t *top = reinterpret_cast<uint64_t *>(ctx->h_vis + 2 * m);
-    HIPTRY(hipMemcpyAsync(top, L.top, sizeof(uint64_t) * N, hipMemcpyDeviceToHost, st));
-    HIPTRY(hipMemcpyAsync(ctx->h_scalar, L.rechecks, CTR_WORDS * sizeof(int64_t),
-                          hipMemcpyDeviceToHost, st));
-    HIPTRY(hipStreamSynchronize(st));
+    if (batches == 0) return fail(ctx, RMIPS_EDEVICE, "no item batch was scored");
     if (ctx->h_status[1] != N) return fail(ctx, RMIPS_EDEVICE, "top-N list incomplete");
     for (int i = 0; i < N; ++i) {
         top_scores[i] = (int32_t)(top[i] >> 32);
