@@ -68,23 +68,29 @@ __device__ __forceinline__ void merge32_desc(float (&v)[32]) {
     }
 }
 
-// Screening configuration: 8 waves of 32 users (the users' rows stay in
-// registers), two item-tile buffers in LDS (the next tile is copied in while
+// Screening configuration: up to 12 waves of 32 users (the users' rows stay
+// in registers), two item-tile buffers in LDS (the next tile is copied in while
 // the current one is used; the registers allow one workgroup per CU, which
 // has the LDS to itself), nch 16-byte chunks per half row.
 constexpr int SCR_NW = 12;  // at most
-// 12 waves while a half row fits in 8 chunks (three waves per SIMD, 168
-// registers each), 8 up to 16 chunks (two per SIMD, 256 registers each), 4
-// for longer rows, whose waves need more registers
-__host__ __device__ constexpr int screen_waves(int nch) { return nch <= 8 ? 12 : nch <= 16 ? 8 : 4; }
+// 12 waves while a half row fits in 8 chunks, or 14 in BF16 (three waves
+// per SIMD, 168 registers each: the FP32 rows take more matrix steps per
+// chunk, so a third wave gains nothing there and the longer rows spill), 8 up
+// to 16 chunks (two per SIMD, 256 registers each), 4 for longer rows, whose
+// waves need more registers
+__host__ __device__ constexpr int screen_waves(int prec, int nch) {
+    return (nch <= 8 || (prec == PREC_BF16 && nch <= 14)) ? 12 : nch <= 16 ? 8 : 4;
+}
 // the bounds-only pass (phase 1 alone, fewer registers): 8 waves, two
 // workgroups per CU (128 registers) while a half row fits in 8 chunks
-__host__ __device__ constexpr int screen_waves_p1(int nch) { return nch <= 8 ? 8 : screen_waves(nch); }
-template <bool LISTED> __host__ __device__ constexpr int screen_nw(int nch) {
-    return LISTED ? screen_waves(nch) : screen_waves_p1(nch);
+__host__ __device__ constexpr int screen_waves_p1(int prec, int nch) {
+    return nch <= 8 ? 8 : screen_waves(prec, nch);
 }
-template <bool LISTED> __host__ __device__ constexpr int screen_wpe(int nch) {
-    return (!LISTED && nch <= 8) ? 4 : screen_waves(nch) / 4;
+template <bool LISTED> __host__ __device__ constexpr int screen_nw(int prec, int nch) {
+    return LISTED ? screen_waves(prec, nch) : screen_waves_p1(prec, nch);
+}
+template <bool LISTED> __host__ __device__ constexpr int screen_wpe(int prec, int nch) {
+    return (!LISTED && nch <= 8) ? 4 : screen_waves(prec, nch) / 4;
 }
 // per tile buffer: N, Nh, R of the 64 items, the tile's largest Nh and R
 // and its scale in the first three of 64 slots, and the items' caller ids
@@ -141,11 +147,10 @@ __device__ __forceinline__ int64_t screen_blocks(const ThreshArgs &a, int tu) {
 
 // LISTED: a refinement pass over a user list (its own kernel symbol)
 template <int PREC, int NCH, bool LISTED>
-// two waves per SIMD (the register budget of 256) where the row fits in
-// 16 chunks; longer FP32 rows keep all registers for one wave
-__global__ __launch_bounds__(64 * screen_nw<LISTED>(NCH)) __attribute__((amdgpu_waves_per_eu(screen_wpe<LISTED>(NCH))))
+// three, two or one waves per SIMD, as the wave count above sets
+__global__ __launch_bounds__(64 * screen_nw<LISTED>(PREC, NCH)) __attribute__((amdgpu_waves_per_eu(screen_wpe<LISTED>(PREC, NCH))))
 void k_thresh_screen(ThreshArgs a) {
-    constexpr int NW = screen_nw<LISTED>(NCH), TU = 32 * NW;
+    constexpr int NW = screen_nw<LISTED>(PREC, NCH), TU = 32 * NW;
     extern __shared__ __align__(16) uint8_t smem8[];
     const int D = a.D, ls = lds_row_bytes(PREC, D), rowb = D * elem_bytes(PREC);
     const int nch = rowb / 32;
@@ -772,8 +777,8 @@ template <int PREC>
 void launch_screen(const ThreshArgs &a, int nch, dim3 g, size_t lds, hipStream_t st) {
     with_nch<PREC>(nch, [&](auto n) {
         constexpr int NCH = decltype(n)::value;
-        if (a.ulist) k_thresh_screen<PREC, NCH, true><<<g, 64 * screen_nw<true>(NCH), lds, st>>>(a);
-        else k_thresh_screen<PREC, NCH, false><<<g, 64 * screen_nw<false>(NCH), lds, st>>>(a);
+        if (a.ulist) k_thresh_screen<PREC, NCH, true><<<g, 64 * screen_nw<true>(PREC, NCH), lds, st>>>(a);
+        else k_thresh_screen<PREC, NCH, false><<<g, 64 * screen_nw<false>(PREC, NCH), lds, st>>>(a);
     });
 }
 
@@ -794,7 +799,7 @@ __global__ void k_exit_keys(ThreshArgs a, uint32_t *__restrict__ key, int32_t *_
 
 void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
     const int nch = a0.D * elem_bytes(a0.prec) / 32;
-    const int tu = 32 * screen_waves(nch);
+    const int tu = 32 * screen_waves(a0.prec, nch);
     const size_t lds = thresh_screen_lds(a0.prec, a0.D);
     const int64_t ublocks = (a0.n + tu - 1) / tu;
     const int capU = a0.cap * a0.nsplit;
@@ -823,7 +828,7 @@ void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
     b0.ulist_cnt = nullptr;
     b0.nsplit = 1;
     b0.pairs = nullptr;
-    const int tu1 = 32 * screen_waves_p1(nch);
+    const int tu1 = 32 * screen_waves_p1(a0.prec, nch);
     screen(b0, dim3((unsigned)((a0.n + tu1 - 1) / tu1), 1u));
     // users in the order of their early-exit ratios, so that the users of a
     // workgroup stop their scans at about the same tile
