@@ -61,9 +61,10 @@ void launch_rho_keys(const double *tau, const float *Nu, int64_t n, uint32_t *ke
 // Y[r] = X[order[r]], rows of row_bytes (a multiple of 16)
 void launch_gather_padded(const void *X, const int32_t *order, int64_t rows, int row_bytes,
                           void *Y, hipStream_t st);
-// cs[j] = number of sorted ratios rho <= norm[j] * (1 + 2^-18)
+// cs[j] = number of sorted ratio keys whose bits from lo_bit up are at most
+// those of norm[j] * (1 + 2^-18) (keys sorted by those bits)
 void launch_cs_prefix(const uint32_t *rho_sorted_keys, int64_t n, const float *norm,
-                      int64_t m, int32_t *cs, hipStream_t st);
+                      int64_t m, int lo_bit, int32_t *cs, hipStream_t st);
 // G = sum over sampled rows x x^T (FP64, d x d), rows u = s*stride, s < ns;
 // scratch holds gram_scratch_bytes(d) bytes of per-slice partial sums
 size_t gram_scratch_bytes(int d);

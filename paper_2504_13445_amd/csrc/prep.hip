@@ -69,97 +69,134 @@ __global__ __launch_bounds__(256) void k_quant(const float *__restrict__ X,
     // per lane) stay in registers between the two passes
     __shared__ float rowmax[64];
     __shared__ float rmx[4];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t r0 = (int64_t)blockIdx.x * 64;
+    // the source rows of the wave's 16 rows, all requested before the first
+    // is used (-1: past the end)
+    // (lane j < 16 loads the entry of row j; one load for all)
+    int64_t src[16];
+    {
+        const int64_t rl = r0 + w + 4 * (lane & 15);
+        const int32_t ol = (order && lane < 16 && rl < rows) ? order[rl] : (int32_t)rl;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int64_t r = r0 + w + 4 * j;
+            src[j] = (r < rows) ? (int64_t)__builtin_amdgcn_readlane(ol, j) : -1;
+        }
+    }
     float v[16][4];
+    float mx[16];
     bool bad = false;
     // pass 1: load, finiteness, max |x_i| per row
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-        const int64_t r = r0 + w + 4 * j;
-        const float *x = (r < rows) ? X + (int64_t)(order ? order[r] : r) * d : nullptr;
-        float mx = 0.0f;
+        const float *x = (src[j] >= 0) ? X + src[j] * d : nullptr;
+        mx[j] = 0.0f;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int c = lane + 64 * q;
             const float t = (x && c < d) ? x[c] : 0.0f;
             v[j][q] = t;
             bad |= !isfinite(t);
-            mx = fmaxf(mx, fabsf(t));
-        }
-        if (PREC == PREC_FP8) {
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
-            if (lane == 0) rowmax[w + 4 * j] = mx;
+            mx[j] = fmaxf(mx[j], fabsf(t));
         }
     }
     if (__ballot(bad) != 0ull && lane == 0) *flag = 1;
-    if (PREC == PREC_FP8) __syncthreads();
-    // pass 2: quantize with the group's scale, residual sums in FP64
+    if (PREC == PREC_FP8) {
+        // the 16 row maxima reduced together (a maximum in any order)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) mx[j] = fmaxf(mx[j], __shfl_xor(mx[j], o));
+        if (lane == 0)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) rowmax[w + 4 * j] = mx[j];
+        __syncthreads();
+    }
+    // pass 2: quantize with the group's scale, residual sums in FP64; four
+    // rows at a time, whose lane sums are reduced together (each row's sums
+    // in the same order as alone)
     float rrmax = 0.0f;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const int i = w + 4 * j;
-        const int64_t r = r0 + i;
-        float s = 1.0f;
-        if (PREC == PREC_FP8) {
-            const int g0 = (i / group) * group;
-            float mx = 0.0f;
-            for (int t = g0; t < g0 + group && t < 64; ++t) mx = fmaxf(mx, rowmax[t]);
-            if (mx > 0.0f) {
-                // smallest power of two s with mx / s <= 448
-                int e;
-                frexpf(mx / 448.0f, &e);  // mx/448 = f * 2^e, f in [0.5, 1)
-                s = ldexpf(1.0f, e);
-                if (mx / ldexpf(1.0f, e - 1) <= 448.0f) s = ldexpf(1.0f, e - 1);
-            }
-        }
-        const float inv = 1.0f / s;  // exact: s is a power of two
-        double sx = 0.0, sq = 0.0, sr = 0.0;
-        const bool live = r < rows_pad;
+    for (int g = 0; g < 4; ++g) {
+        double sx[4], sq[4], sr[4];
+        float sc4[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int c = lane + 64 * q;
-            if (c < D) {
-                const float t = v[j][q];
-                float qv;
-                if (PREC == PREC_FP32) {
-                    qv = t;
-                    if (live) reinterpret_cast<float *>(Xq)[r * D + fp32_slot(c, d, D)] = t;
-                } else if (PREC == PREC_BF16) {
-                    const uint16_t h = to_bf16(t, qv);
-                    if (live) reinterpret_cast<uint16_t *>(Xq)[r * D + c] = h;
-                } else {
-                    float yq;
-                    const uint8_t b8 = to_e4m3(t * inv, yq);
-                    if (live) Xq[r * D + c] = b8;
-                    qv = yq * s;
+        for (int jj = 0; jj < 4; ++jj) {
+            const int j = 4 * g + jj;
+            const int i = w + 4 * j;
+            const int64_t r = r0 + i;
+            float s = 1.0f;
+            if (PREC == PREC_FP8) {
+                const int g0 = (i / group) * group;
+                float m = 0.0f;
+                for (int t = g0; t < g0 + group && t < 64; ++t) m = fmaxf(m, rowmax[t]);
+                if (m > 0.0f) {
+                    // smallest power of two s with m / s <= 448
+                    int e;
+                    frexpf(m / 448.0f, &e);  // m/448 = f * 2^e, f in [0.5, 1)
+                    s = ldexpf(1.0f, e);
+                    if (m / ldexpf(1.0f, e - 1) <= 448.0f) s = ldexpf(1.0f, e - 1);
                 }
-                sx += (double)t * (double)t;
-                sq += (double)qv * (double)qv;
-                const double df = (double)t - (double)qv;  // exact: both are FP32
-                sr += df * df;
+            }
+            sc4[jj] = s;
+            const float inv = 1.0f / s;  // exact: s is a power of two
+            sx[jj] = 0.0;
+            sq[jj] = 0.0;
+            sr[jj] = 0.0;
+            const bool live = r < rows_pad;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int c = lane + 64 * q;
+                if (c < D) {
+                    const float t = v[j][q];
+                    float qv;
+                    if (PREC == PREC_FP32) {
+                        qv = t;
+                        if (live) reinterpret_cast<float *>(Xq)[r * D + fp32_slot(c, d, D)] = t;
+                    } else if (PREC == PREC_BF16) {
+                        const uint16_t h = to_bf16(t, qv);
+                        if (live) reinterpret_cast<uint16_t *>(Xq)[r * D + c] = h;
+                    } else {
+                        float yq;
+                        const uint8_t b8 = to_e4m3(t * inv, yq);
+                        if (live) Xq[r * D + c] = b8;
+                        qv = yq * s;
+                    }
+                    sx[jj] += (double)t * (double)t;
+                    sq[jj] += (double)qv * (double)qv;
+                    const double df = (double)t - (double)qv;  // exact: both are FP32
+                    sr[jj] += df * df;
+                }
             }
         }
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            sx += __shfl_xor(sx, o);
-            if (PREC != PREC_FP32) {
-                sq += __shfl_xor(sq, o);
-                sr += __shfl_xor(sr, o);
+        for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                sx[jj] += __shfl_xor(sx[jj], o);
+                if (PREC != PREC_FP32) {
+                    sq[jj] += __shfl_xor(sq[jj], o);
+                    sr[jj] += __shfl_xor(sr[jj], o);
+                }
             }
-        }
-        if (lane == 0 && live) {
-            const double up = 1.0 + 0x1p-40;
-            const float nx = __double2float_ru(sqrt(sx) * up);
-            const float rr = (PREC == PREC_FP32) ? 0.0f : __double2float_ru(sqrt(sr) * up);
-            if (!(nx <= 0x1p60f)) *flag = 1;
-            N[r] = nx;
-            Nh[r] = (PREC == PREC_FP32) ? nx : __double2float_ru(sqrt(sq) * up);
-            R[r] = rr;
-            sc[r] = s;
-            if (nx > 0.0f && rr > 0.0f)
-                rrmax = fmaxf(rrmax, __double2float_ru((double)rr / (double)nx));
+        if (lane == 0) {
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const int64_t r = r0 + w + 4 * (4 * g + jj);
+                if (r >= rows_pad) continue;
+                const double up = 1.0 + 0x1p-40;
+                const float nx = __double2float_ru(sqrt(sx[jj]) * up);
+                const float rr = (PREC == PREC_FP32) ? 0.0f : __double2float_ru(sqrt(sr[jj]) * up);
+                if (!(nx <= 0x1p60f)) *flag = 1;
+                N[r] = nx;
+                Nh[r] = (PREC == PREC_FP32) ? nx : __double2float_ru(sqrt(sq[jj]) * up);
+                R[r] = rr;
+                sc[r] = sc4[jj];
+                if (nx > 0.0f && rr > 0.0f)
+                    rrmax = fmaxf(rrmax, __double2float_ru((double)rr / (double)nx));
+            }
         }
     }
     // largest R / N of the block, one atomic per block (non-negative floats
@@ -309,25 +346,30 @@ void launch_gather_padded(const void *X, const int32_t *order, int64_t rows, int
         reinterpret_cast<const uint4 *>(X), order, rows, W16, reinterpret_cast<uint4 *>(Y));
 }
 
+// The keys are ordered by their bits from lo_bit up only: the prefix then
+// takes every user whose key agrees with the item's in those bits or is
+// below, a superset of the users of Eq. (2) (ratios up to 2^(lo_bit-23)
+// relative above the item's norm also come in).
 __global__ void k_cs_prefix(const uint32_t *__restrict__ keys, int64_t n,
-                            const float *__restrict__ norm, int64_t m,
+                            const float *__restrict__ norm, int64_t m, int lo_bit,
                             int32_t *__restrict__ cs) {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= m) return;
     // v <= (1 + d 2^-53) ||u|| ||p|| for the exact value; 2^-18 covers that
     // and the FP32 rounding of this product
-    uint32_t x = float_key(norm[j] * (1.0f + 0x1p-18f));
-    int64_t lo = 0, hi = n;  // first position with key > x
+    const uint32_t x = float_key(norm[j] * (1.0f + 0x1p-18f)) >> lo_bit;
+    int64_t lo = 0, hi = n;  // first position with a larger key
     while (lo < hi) {
         int64_t mid = (lo + hi) >> 1;
-        if (keys[mid] <= x) lo = mid + 1; else hi = mid;
+        if ((keys[mid] >> lo_bit) <= x) lo = mid + 1; else hi = mid;
     }
     cs[j] = (int32_t)lo;
 }
 
 void launch_cs_prefix(const uint32_t *rho_sorted_keys, int64_t n, const float *norm,
-                      int64_t m, int32_t *cs, hipStream_t st) {
-    k_cs_prefix<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(rho_sorted_keys, n, norm, m, cs);
+                      int64_t m, int lo_bit, int32_t *cs, hipStream_t st) {
+    k_cs_prefix<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(rho_sorted_keys, n, norm, m, lo_bit,
+                                                             cs);
 }
 
 // 32x32 tile of G per block over one slice of the sampled rows (blockIdx.z),

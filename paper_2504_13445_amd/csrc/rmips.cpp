@@ -41,6 +41,7 @@ int aug_len(int d) { return (dprime(d) + 2 + 15) & ~15; }  // ka: 16, 32, 48 or 
 constexpr int T0_TILES = 6;             // tiles of phase 1 of stage (a)
 constexpr int BATCH_FIRST = 256;
 constexpr int BATCH_MAX = 4096;
+constexpr int RHO_LO_BIT = 8;  // ratio key bits below this are not sorted on
 constexpr int GRAM_SAMPLE = 16384;
 
 rmips_status fail(rmips_ctx *c, rmips_status s, const std::string &msg) {
@@ -622,9 +623,12 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     }
 
     // ---- stage (c): Cauchy-Schwarz prefix and Eq. (3)/(6) bound counts
+    // users by their ratio keys without the low 8 bits (3 passes instead of
+    // 4): each item's prefix may take users whose ratio is up to 2^-15
+    // relative above its norm, which the bound and the count then test
     launch_rho_keys(L.tau, L.T.Nu, n, L.ukeys, L.uperm, st);
-    HIPTRY(radix_sort_u32(L.ukeys, L.uperm, n, L.usort, st));
-    launch_cs_prefix(L.ukeys, n, L.T.Np, m, L.cs, st);
+    HIPTRY(radix_sort_u32(L.ukeys, L.uperm, n, L.usort, st, RHO_LO_BIT, 32));
+    launch_cs_prefix(L.ukeys, n, L.T.Np, m, RHO_LO_BIT, L.cs, st);
     launch_user_side(L.tau, L.tau_id, L.T.Nu, L.T.Nhu, L.T.Ru, L.T.su, L.uperm, n, ec.c2, L.us,
                      st);
     launch_gather_padded(L.T.Uq, L.uperm, n, L.T.rowb, L.Us, st);

@@ -198,15 +198,28 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
         const uint32_t rank = __popcll(peers & lt);
         if (active && rank == 0) wcnt[w][dig] = __popcll(peers);
         __syncthreads();
+        uint32_t off = base[dig] + rank;
+        for (int q = 0; q < w; ++q) off += wcnt[q][dig];
         if (active) {
-            uint32_t off = base[dig] + rank;
-            for (int q = 0; q < w; ++q) off += wcnt[q][dig];
             kout[off] = key;
             vout[off] = val;
-            if (nshift >= 0)
-                atomicAdd(&cnext[count_index(small, (key >> nshift) & 255u, off / SORT_CHUNK,
-                                             nblocks)],
-                          1u);
+        }
+        if (nshift >= 0) {
+            // the next digits per destination block: one atomic per group of
+            // peers with the same next digit and block (a digit's peers fill
+            // consecutive slots, so they meet at most two blocks, told apart
+            // by the block's lowest bit)
+            const uint32_t nd = (key >> nshift) & 255u, db = off / SORT_CHUNK;
+            uint64_t grp = peers;
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const uint64_t bb = __ballot((nd >> b) & 1u);
+                grp &= ((nd >> b) & 1u) ? bb : ~bb;
+            }
+            const uint64_t bb = __ballot(db & 1u);
+            grp &= (db & 1u) ? bb : ~bb;
+            if (active && (grp & lt) == 0ull)
+                atomicAdd(&cnext[count_index(small, nd, db, nblocks)], (uint32_t)__popcll(grp));
         }
         __syncthreads();
         uint32_t add = 0;
