@@ -131,13 +131,14 @@ void k_count(CountArgs a) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) cnt[i] = 0;
 
-    const int64_t nchunks = (a.ulen + CNT_USERS - 1) / CNT_USERS;
+    const int64_t ulen = a.ulen_dev ? (int64_t)*a.ulen_dev : a.ulen;
+    const int64_t nchunks = (ulen + CNT_USERS - 1) / CNT_USERS;
     const uint32_t magic = slot_magic(w16);
     // chunk ch of users into an LDS buffer by direct copies; rows past the
     // last user repeat it (their columns are masked out)
     auto chunk_copy = [&](int64_t ch, uint8_t *dst) {
         const int64_t u0 = ch * CNT_USERS;
-        const int64_t left = a.ulen - u0;
+        const int64_t left = ulen - u0;
         const int rlast = (int)((left < CNT_USERS ? left : CNT_USERS) - 1);
         rows_dma(reinterpret_cast<const uint8_t *>(a.Us) + u0 * rowb, rowb, w16, magic, rlast,
                  dst, w, NW, lane);
@@ -148,11 +149,11 @@ void k_count(CountArgs a) {
     float uqs0 = 1.0f, uqs1 = 1.0f;
     auto user_fetch = [&](int64_t c) {
         const int64_t v0 = c * CNT_USERS + (lane & 31), v1 = v0 + 32;
-        if (c < nchunks && v0 < a.ulen) {
+        if (c < nchunks && v0 < ulen) {
             uq0 = a.us.thr[v0];
             uqs0 = a.us.sinv[v0];
         }
-        if (c < nchunks && v1 < a.ulen) {
+        if (c < nchunks && v1 < ulen) {
             uq1 = a.us.thr[v1];
             uqs1 = a.us.sinv[v1];
         }
@@ -203,7 +204,7 @@ void k_count(CountArgs a) {
     bool pending = false;
     auto classify = [&]() {
         const int64_t us0 = pus0, us1 = pus0 + 32;
-        const bool c0 = us0 < a.ulen, c1 = us1 < a.ulen;
+        const bool c0 = us0 < ulen, c1 = us1 < ulen;
         // counts, and whether any pair falls between the two thresholds:
         // with e = med3(v, tout, tin) (tout <= tin), v > tin <=> v > e and
         // tout <= v <= tin <=> v == e
@@ -257,8 +258,8 @@ void k_count(CountArgs a) {
         const int64_t us0 = ch * CNT_USERS + (lane & 31), us1 = us0 + 32;
         // a column past the last user is "out" for every row: tout = +inf
         float tin0 = INFINITY, tout0 = INFINITY, tin1 = INFINITY, tout1 = INFINITY;
-        if (us0 < a.ulen) thresholds(uq0, uqs0, tin0, tout0);
-        if (us1 < a.ulen) thresholds(uq1, uqs1, tin1, tout1);
+        if (us0 < ulen) thresholds(uq0, uqs0, tin0, tout0);
+        if (us1 < ulen) thresholds(uq1, uqs1, tin1, tout1);
         user_fetch(nxt);
         // rows: this wave's items (shared); columns: the two user blocks
         auto multiply = [&]() {
@@ -317,6 +318,22 @@ void launch_count_p(const CountArgs &a, size_t lds, hipStream_t st) {
         const unsigned g = (unsigned)((a.nb + 32 * NW - 1) / (32 * NW) * a.nsplit);
         k_count<PREC, NCH><<<g, 64 * NW, lds, st>>>(a);
     });
+}
+
+__global__ __launch_bounds__(256) void k_max_i32(const int32_t *__restrict__ x, int64_t n,
+                                                 int32_t *__restrict__ out) {
+    __shared__ int32_t wm[4];
+    int32_t v = 0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) v = max(v, x[i]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) *out = max(max(wm[0], wm[1]), max(wm[2], wm[3]));
+}
+
+void launch_max_i32(const int32_t *x, int64_t n, int32_t *out, hipStream_t st) {
+    k_max_i32<<<1, 256, 0, st>>>(x, n, out);
 }
 
 void launch_count(const CountArgs &a, hipStream_t st) {

@@ -140,13 +140,17 @@ struct CountArgs {
     const int32_t *item_tie;   // tie id per padded row (NULL = -1: outside P)
     const int32_t *item_orig;  // original row per padded row (NULL = identity)
     const float *Porig;        // original FP32 item rows
-    // users (columns): quantized rows, first ulen of them
+    // users (columns): quantized rows, first ulen of them; with ulen_dev
+    // the count is read on the device and ulen is only an upper bound
     const void *Us; int64_t ulen; UserSide us;
+    const int32_t *ulen_dev;
     const float *Uorig; int d; int D;
     float c_err; float c2; float e_abs;
     int nsplit; int32_t *partial; int64_t *rechecks;
 };
 void launch_count(const CountArgs &a, hipStream_t st);
+// *out = max(x[0], ..., x[n-1]) (0 when n = 0), one workgroup
+void launch_max_i32(const int32_t *x, int64_t n, int32_t *out, hipStream_t st);
 size_t count_lds(int prec, int D);
 
 struct BoundArgs {

@@ -313,6 +313,7 @@ struct TopnLayout {
     uint64_t *top;
     int32_t *status;
     int64_t *rechecks;
+    int32_t *ulen_dev;
 };
 
 void user_side_plan(int64_t n, UserSide &us, Carve &cv) {
@@ -359,6 +360,7 @@ void topn_plan(int prec, int64_t n, int64_t m, int d, int k, int cap_override, i
     L.top = cv.take<uint64_t>(RMIPS_N_MAX);
     L.status = cv.take<int32_t>(64);
     L.rechecks = cv.take<int64_t>(CTR_WORDS);
+    L.ulen_dev = cv.take<int32_t>(1);
 }
 
 // splits of the user range of a counting launch: about four rounds of
@@ -685,9 +687,9 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     HIPTRY(hipMemcpyAsync(L.status, ctx->h_status + 8, 2 * sizeof(int32_t),
                           hipMemcpyHostToDevice, st));
     HIPTRY(hipEventRecord(ev[2], st));
-    HIPTRY(hipStreamSynchronize(st));
-    if (ctx->h_status[12] != 0)
-        return fail(ctx, RMIPS_ENONFINITE, "input holds a NaN/Inf or a vector norm above 2^60");
+    // (no synchronisation here: the first batch goes out at once, and these
+    // copies arrive with its results; its input check is read then, before
+    // anything is returned)
 
     // ---- stage (b): exact scores in bound order, running top-N, stop rule
     // (every batch ends with the status, the top-N list and the statistics
@@ -702,14 +704,24 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     while (r0 < m && bsz > 0) {
         const int64_t r1 = std::min<int64_t>(m, r0 + bsz);
         const int64_t nb = r1 - r0;
+        // the batch's users: the longest prefix of its items; the first
+        // batch's is taken on the device (the host does not have the prefixes
+        // yet), with n for the launch shape
+        const bool first = batches == 0;
         int64_t ulen = 0;
-        for (int64_t r = r0; r < r1; ++r) ulen = std::max<int64_t>(ulen, h_cs[r]);
+        if (first) {
+            launch_max_i32(L.vis_cs, nb, L.ulen_dev, st);
+            ulen = n;
+        } else {
+            for (int64_t r = r0; r < r1; ++r) ulen = std::max<int64_t>(ulen, h_cs[r]);
+        }
         CountArgs a{};
         a.prec = prec;
         a.Pq = L.T.Pq; a.Np = L.T.Np; a.Nhp = L.T.Nhp; a.Rp = L.T.Rp; a.sp = L.T.sp;
         a.rows = L.visit + r0; a.nb = nb;
         a.item_tie = L.T.perm; a.item_orig = L.T.perm; a.Porig = P;
         a.Us = L.Us; a.ulen = ulen; a.us = L.us; a.Uorig = U; a.d = d; a.D = D;
+        a.ulen_dev = first ? L.ulen_dev : nullptr;
         a.c_err = ec.c; a.c2 = ec.c2; a.e_abs = E_ABS;
         a.nsplit = count_splits(nb, ulen, L.nsplitC_max);
         a.partial = L.partialC;
@@ -736,6 +748,13 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
             float t = 0.0f;
             (void)hipEventElapsedTime(&t, ev[8], ev[9]);
             ms_count_k += t;
+        }
+        if (first) {
+            if (ctx->h_status[12] != 0)
+                return fail(ctx, RMIPS_ENONFINITE,
+                            "input holds a NaN/Inf or a vector norm above 2^60");
+            ulen = 0;  // the batch's own user count, for the statistics
+            for (int64_t r = r0; r < r1; ++r) ulen = std::max<int64_t>(ulen, h_cs[r]);
         }
         visited += nb;
         ++batches;
