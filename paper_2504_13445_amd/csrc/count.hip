@@ -687,8 +687,13 @@ void launch_colsum(const int32_t *partial, int nsplit, int64_t cols, int32_t *ou
 }
 
 __global__ void k_visit_keys(const int32_t *__restrict__ us, const int32_t *__restrict__ inv,
-                             int64_t m, uint32_t *__restrict__ key, int32_t *__restrict__ val) {
+                             int64_t m, uint32_t *__restrict__ key, int32_t *__restrict__ val,
+                             int32_t *__restrict__ status) {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c == 0 && status) {  // a new running top-N: no N-th score, none kept
+        status[0] = -1;
+        status[1] = 0;
+    }
     if (c >= m) return;
     int r = inv[c];
     key[c] = ~(uint32_t)us[r];
@@ -696,8 +701,8 @@ __global__ void k_visit_keys(const int32_t *__restrict__ us, const int32_t *__re
 }
 
 void launch_visit_keys(const int32_t *uscore, const int32_t *inv, int64_t m, uint32_t *key,
-                       int32_t *val, hipStream_t st) {
-    k_visit_keys<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(uscore, inv, m, key, val);
+                       int32_t *val, int32_t *status, hipStream_t st) {
+    k_visit_keys<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(uscore, inv, m, key, val, status);
 }
 
 __global__ void k_gather_i32(const int32_t *__restrict__ src, const int32_t *__restrict__ idx,

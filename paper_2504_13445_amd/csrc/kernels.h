@@ -169,9 +169,10 @@ int bound_splits(int64_t m, int ka);
 // partial[s][j] summed over s (fixed order) -> out[j]
 void launch_colsum(const int32_t *partial, int nsplit, int64_t cols, int32_t *out,
                    hipStream_t st);
-// ~uscore keys in id order: key[c] = ~us[inv[c]], val[c] = inv[c]
+// ~uscore keys in id order: key[c] = ~us[inv[c]], val[c] = inv[c]; also
+// resets the running top-N status (when not NULL) to {-1, 0}
 void launch_visit_keys(const int32_t *uscore, const int32_t *inv, int64_t m,
-                       uint32_t *key, int32_t *val, hipStream_t st);
+                       uint32_t *key, int32_t *val, int32_t *status, hipStream_t st);
 void launch_gather_i32(const int32_t *src, const int32_t *idx, int64_t n, int32_t *dst,
                        hipStream_t st);
 

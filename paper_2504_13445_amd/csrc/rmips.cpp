@@ -24,7 +24,6 @@ struct rmips_ctx {
     int32_t batch_first = 0, batch_max = 0;
     int32_t *bound_out = nullptr;  // device, m int32 (testing knob)
     int32_t *h_status = nullptr;  // pinned, small
-    int64_t *h_scalar = nullptr;  // pinned, small
     int32_t *h_vis = nullptr;     // pinned: visit-order bounds and prefixes, top-N
     int64_t h_vis_cap = 0;        // its size in int32 entries
 };
@@ -146,7 +145,6 @@ void thresh_plan(int prec, int64_t n, int64_t m, int d, int k, int cap_override,
     L.sp = cv.take<float>(L.mpad);
     L.tmax_nh = cv.take<float>(L.ntiles);
     L.tmax_r = cv.take<float>(L.ntiles);
-    L.rmax = cv.take<unsigned int>(64);
     L.Npid = cv.take<float>(m);
     L.keys = cv.take<uint32_t>(m);
     L.perm = cv.take<int32_t>(m);
@@ -162,7 +160,9 @@ void thresh_plan(int prec, int64_t n, int64_t m, int d, int k, int cap_override,
     L.uord = cv.take<int32_t>(n);
     L.usort = cv.take<uint8_t>(radix_sort_scratch_bytes(n));
     L.nall = cv.take<int32_t>(64);
+    // the input flag and the largest R/N share a block (one fill clears both)
     L.bad = cv.take<int>(64);
+    L.rmax = reinterpret_cast<unsigned int *>(L.bad + 32);
 }
 
 rmips_status check_bad(rmips_ctx *ctx, int *bad) {
@@ -182,8 +182,7 @@ rmips_status run_thresholds(rmips_ctx *ctx, const float *U, int64_t n, const flo
                             hipEvent_t ev1 = nullptr, unsigned long long *cstats = nullptr,
                             bool check_now = true) {
     hipStream_t st = ctx->stream;
-    HIPTRY(hipMemsetAsync(L.bad, 0, sizeof(int), st));
-    HIPTRY(hipMemsetAsync(L.rmax, 0, sizeof(unsigned int), st));
+    HIPTRY(hipMemsetAsync(L.bad, 0, 33 * sizeof(int), st));  // bad and rmax
     launch_rows_prep(P, m, d, L.D, nullptr, L.Npid, L.keys, L.perm, L.bad, st);
     HIPTRY(radix_sort_u32(L.keys, L.perm, m, L.sort_scratch, st));
     launch_quant(L.prec, P, L.perm, m, L.mpad, d, L.D, TILE_ITEMS, L.Pq, L.Np, L.Nhp, L.Rp,
@@ -291,6 +290,9 @@ void top_eigvecs(const std::vector<double> &G, int d, int dp, std::vector<double
 constexpr int CTR_PAIRS = 8;
 constexpr int CTR_CS = CTR_PAIRS + CSTAT_SLOTS;
 constexpr int CTR_WORDS = CTR_CS + 4 * CSTAT_SLOTS;
+// block of a batch's results: status (64 words), top-N list, counters
+constexpr size_t RES_STATUS = 0, RES_TOP = 256, RES_CTR = RES_TOP + 8 * RMIPS_N_MAX,
+                 RES_BYTES = RES_CTR + 8 * CTR_WORDS;
 
 struct TopnLayout {
     ThreshLayout T;
@@ -351,15 +353,18 @@ void topn_plan(int prec, int64_t n, int64_t m, int d, int k, int cap_override, i
     L.inv = cv.take<int32_t>(m);
     L.vkeys = cv.take<uint32_t>(m);
     L.visit = cv.take<int32_t>(m);
-    L.vis_us = cv.take<int32_t>(m);
-    L.vis_cs = cv.take<int32_t>(m);
+    L.vis_us = cv.take<int32_t>(2 * m);  // bounds, then prefixes: one copy to the host
+    L.vis_cs = L.vis_us + m;
     L.vis_cid = cv.take<int32_t>(m);
     L.nsplitC_max = 256;
     L.partialC = cv.take<int32_t>((size_t)L.nsplitC_max * bmax);
     L.batch_scores = cv.take<int32_t>(bmax);
-    L.top = cv.take<uint64_t>(RMIPS_N_MAX);
-    L.status = cv.take<int32_t>(64);
-    L.rechecks = cv.take<int64_t>(CTR_WORDS);
+    // the results of a batch in one block, copied to the host at once:
+    // status, the top-N list, the counters
+    uint8_t *res = cv.take<uint8_t>(RES_BYTES);
+    L.status = reinterpret_cast<int32_t *>(res + RES_STATUS);
+    L.top = reinterpret_cast<uint64_t *>(res + RES_TOP);
+    L.rechecks = reinterpret_cast<int64_t *>(res + RES_CTR);
     L.ulen_dev = cv.take<int32_t>(1);
 }
 
@@ -392,8 +397,7 @@ rmips_status rmips_create(rmips_ctx **out, int device, void *hip_stream) {
     rmips_ctx *c = new rmips_ctx();
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
-    if (hipHostMalloc((void **)&c->h_status, 256, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&c->h_scalar, 4096, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void **)&c->h_status, 256, hipHostMallocDefault) != hipSuccess) {
         delete c;
         return RMIPS_EDEVICE;
     }
@@ -404,7 +408,6 @@ rmips_status rmips_create(rmips_ctx **out, int device, void *hip_stream) {
 void rmips_destroy(rmips_ctx *ctx) {
     if (!ctx) return;
     if (ctx->h_status) (void)hipHostFree(ctx->h_status);
-    if (ctx->h_scalar) (void)hipHostFree(ctx->h_scalar);
     if (ctx->h_vis) (void)hipHostFree(ctx->h_vis);
     delete ctx;
 }
@@ -660,15 +663,15 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     // visit order: (uscore desc, id asc)
     launch_invert_perm(L.T.perm, m, L.inv, st);
     if (ctx->bound_out) launch_gather_i32(L.uscore, L.inv, m, ctx->bound_out, st);
-    launch_visit_keys(L.uscore, L.inv, m, L.vkeys, L.visit, st);
+    launch_visit_keys(L.uscore, L.inv, m, L.vkeys, L.visit, L.status, st);
     // the keys are ~uscore with 0 <= uscore <= n: only the bits of n vary
     HIPTRY(radix_sort_u32(L.vkeys, L.visit, m, L.usort, st, 0, 32 - __builtin_clz((unsigned)n)));
     launch_gather_i32(L.uscore, L.visit, m, L.vis_us, st);
     launch_gather_i32(L.cs, L.visit, m, L.vis_cs, st);
     launch_gather_i32(L.T.perm, L.visit, m, L.vis_cid, st);
     // pinned host copies (grown once per larger m): bounds and prefixes in
-    // visit order, then room for the top-N list
-    const int64_t need = 2 * m + 2 * (int64_t)N;
+    // visit order, then room for a batch's result block
+    const int64_t need = 2 * m + (int64_t)(RES_BYTES / sizeof(int32_t));
     if (ctx->h_vis_cap < need) {
         if (ctx->h_vis) HIPTRY(hipHostFree(ctx->h_vis));
         ctx->h_vis = nullptr;
@@ -677,15 +680,8 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
         ctx->h_vis_cap = need;
     }
     int32_t *h_us = ctx->h_vis, *h_cs = ctx->h_vis + m;
-    HIPTRY(hipMemcpyAsync(h_us, L.vis_us, sizeof(int32_t) * m, hipMemcpyDeviceToHost, st));
-    HIPTRY(hipMemcpyAsync(h_cs, L.vis_cs, sizeof(int32_t) * m, hipMemcpyDeviceToHost, st));
+    HIPTRY(hipMemcpyAsync(h_us, L.vis_us, sizeof(int32_t) * 2 * m, hipMemcpyDeviceToHost, st));
     HIPTRY(hipMemcpyAsync(ctx->h_status + 12, L.T.bad, sizeof(int), hipMemcpyDeviceToHost, st));
-    // the running top-N's status, set before the synchronisation (pinned
-    // source, not written again in this call)
-    ctx->h_status[8] = -1;  // N-th score unknown
-    ctx->h_status[9] = 0;   // entries kept
-    HIPTRY(hipMemcpyAsync(L.status, ctx->h_status + 8, 2 * sizeof(int32_t),
-                          hipMemcpyHostToDevice, st));
     HIPTRY(hipEventRecord(ev[2], st));
     // (no synchronisation here: the first batch goes out at once, and these
     // copies arrive with its results; its input check is read then, before
@@ -694,7 +690,10 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     // ---- stage (b): exact scores in bound order, running top-N, stop rule
     // (every batch ends with the status, the top-N list and the statistics
     // copied to the host: the last batch's copies are the results)
-    uint64_t *top = reinterpret_cast<uint64_t *>(ctx->h_vis + 2 * m);
+    uint8_t *h_res = reinterpret_cast<uint8_t *>(ctx->h_vis + 2 * m);
+    const int32_t *h_st = reinterpret_cast<const int32_t *>(h_res + RES_STATUS);
+    const uint64_t *top = reinterpret_cast<const uint64_t *>(h_res + RES_TOP);
+    const int64_t *h_ctr = reinterpret_cast<const int64_t *>(h_res + RES_CTR);
     int64_t r0 = 0, visited = 0, batches = 0, screened = 0, launches = 0;
     float ms_count_k = 0.0f;
     // First batch: the items with the largest bounds.  After it, the items
@@ -738,11 +737,7 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
         launch_topn_merge(L.batch_scores, nb, L.vis_cid + r0, N, L.top, L.status, st);
         HIPTRY(hipGetLastError());
         HIPTRY(hipEventRecord(ev[3], st));
-        HIPTRY(hipMemcpyAsync(ctx->h_status, L.status, 2 * sizeof(int32_t),
-                              hipMemcpyDeviceToHost, st));
-        HIPTRY(hipMemcpyAsync(top, L.top, sizeof(uint64_t) * N, hipMemcpyDeviceToHost, st));
-        HIPTRY(hipMemcpyAsync(ctx->h_scalar, L.rechecks, CTR_WORDS * sizeof(int64_t),
-                              hipMemcpyDeviceToHost, st));
+        HIPTRY(hipMemcpyAsync(h_res, L.status, RES_BYTES, hipMemcpyDeviceToHost, st));
         HIPTRY(hipStreamSynchronize(st));
         if (ulen > 0) {
             float t = 0.0f;
@@ -759,7 +754,7 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
         visited += nb;
         ++batches;
         screened += nb * ulen;
-        const int tauN = ctx->h_status[0];
+        const int tauN = h_st[0];
         r0 = r1;
         if (tauN < 0) {
             bsz = bmax;  // fewer than N items seen so far
@@ -771,7 +766,7 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
         bsz = std::min<int64_t>(e - r0, bmax);
     }
     if (batches == 0) return fail(ctx, RMIPS_EDEVICE, "no item batch was scored");
-    if (ctx->h_status[1] != N) return fail(ctx, RMIPS_EDEVICE, "top-N list incomplete");
+    if (h_st[1] != N) return fail(ctx, RMIPS_EDEVICE, "top-N list incomplete");
     for (int i = 0; i < N; ++i) {
         top_scores[i] = (int32_t)(top[i] >> 32);
         top_ids[i] = (int32_t)(~(uint32_t)(top[i] & 0xffffffffu));
@@ -780,7 +775,7 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
         std::memset(stats, 0, sizeof(*stats));
         stats->visited_items = visited;
         stats->batches = batches;
-        const int64_t *h = ctx->h_scalar;
+        const int64_t *h = h_ctr;
         int64_t tp = 0, cs[4] = {0, 0, 0, 0};
         for (int i = 0; i < CSTAT_SLOTS; ++i) {
             tp += h[CTR_PAIRS + i];

@@ -787,6 +787,13 @@ void launch_screen(const ThreshArgs &a, int nch, dim3 g, size_t lds, hipStream_t
 // kernel; users whose bound is not positive scan every tile (ratio 0).
 __global__ void k_exit_keys(ThreshArgs a, uint32_t *__restrict__ key, int32_t *__restrict__ val) {
     const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u == 0) {  // the list counters of the passes that follow
+        a.lcnt[0] = 0;
+        a.lcnt[1] = 0;
+        a.lcnt[2] = 0;
+        a.lcnt[3] = 0;
+        *a.nall = (int32_t)a.n;  // the main pass takes every user
+    }
     if (u >= a.n) return;
     const float rmax = __uint_as_float(*a.rmax_bits);
     const float nu = a.Nu[u], nhu = a.Nhu[u], ru = a.Ru[u], L = a.Luse[u];
@@ -815,7 +822,6 @@ void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
     const int64_t eblocks = std::min<int64_t>(
         (a0.n + 4 * (64 / EXACT_SLOTS) - 1) / (4 * (64 / EXACT_SLOTS)), 3 * 256);
     int32_t *LA = a0.lists, *LB = a0.lists + a0.n, *LF = a0.lists + 2 * a0.n;
-    (void)hipMemsetAsync(a0.lcnt, 0, 4 * sizeof(int32_t), st);
     auto screen = [&](const ThreshArgs &a, dim3 g) {
         if (a.prec == PREC_FP32) launch_screen<PREC_FP32>(a, nch, g, lds, st);
         else if (a.prec == PREC_BF16) launch_screen<PREC_BF16>(a, nch, g, lds, st);
@@ -836,7 +842,6 @@ void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
     // a grouping only: the top 16 bits of the ratio (sign, exponent and 7
     // mantissa bits) are enough, ties stay in user order
     (void)radix_sort_u32(a0.ukey, a0.uord, a0.n, a0.usort, st, 16, 32);
-    (void)hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(a0.nall), (int)a0.n, 1, st);
     // main pass: all users, in that order, from their L0
     ThreshArgs a = a0;
     a.ulist = a0.uord;
