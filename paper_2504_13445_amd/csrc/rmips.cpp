@@ -180,9 +180,11 @@ rmips_status run_thresholds(rmips_ctx *ctx, const float *U, int64_t n, const flo
                             int32_t *tau_id, int32_t *topk,
                             unsigned long long *pairs = nullptr, hipEvent_t ev0 = nullptr,
                             hipEvent_t ev1 = nullptr, unsigned long long *cstats = nullptr,
-                            bool check_now = true) {
+                            bool check_now = true, bool clear_flags = true) {
     hipStream_t st = ctx->stream;
-    HIPTRY(hipMemsetAsync(L.bad, 0, 33 * sizeof(int), st));  // bad and rmax
+    // bad and rmax, 32 words apart in every layout (a caller may have
+    // cleared them already)
+    if (clear_flags) HIPTRY(hipMemsetAsync(L.bad, 0, 33 * sizeof(int), st));
     launch_rows_prep(P, m, d, L.D, nullptr, L.Npid, L.keys, L.perm, L.bad, st);
     HIPTRY(radix_sort_u32(L.keys, L.perm, m, L.sort_scratch, st));
     launch_quant(L.prec, P, L.perm, m, L.mpad, d, L.D, TILE_ITEMS, L.Pq, L.Np, L.Nhp, L.Rp,
@@ -290,9 +292,12 @@ void top_eigvecs(const std::vector<double> &G, int d, int dp, std::vector<double
 constexpr int CTR_PAIRS = 8;
 constexpr int CTR_CS = CTR_PAIRS + CSTAT_SLOTS;
 constexpr int CTR_WORDS = CTR_CS + 4 * CSTAT_SLOTS;
-// block of a batch's results: status (64 words), top-N list, counters
-constexpr size_t RES_STATUS = 0, RES_TOP = 256, RES_CTR = RES_TOP + 8 * RMIPS_N_MAX,
-                 RES_BYTES = RES_CTR + 8 * CTR_WORDS;
+// block of a batch's results: status (64 words: the running top-N's in
+// [0, 2), stage (a)'s input flag in [RES_BAD], its largest R/N in
+// [RES_RMAX]), the counters, the top-N list; one fill clears all but the list
+constexpr size_t RES_STATUS = 0, RES_CTR = 256, RES_TOP = RES_CTR + 8 * CTR_WORDS,
+                 RES_BYTES = RES_TOP + 8 * RMIPS_N_MAX;
+constexpr int RES_BAD = 12, RES_RMAX = 44;
 
 struct TopnLayout {
     ThreshLayout T;
@@ -365,6 +370,9 @@ void topn_plan(int prec, int64_t n, int64_t m, int d, int k, int cap_override, i
     L.status = reinterpret_cast<int32_t *>(res + RES_STATUS);
     L.top = reinterpret_cast<uint64_t *>(res + RES_TOP);
     L.rechecks = reinterpret_cast<int64_t *>(res + RES_CTR);
+    // stage (a)'s flags live in the status words (copied with every batch)
+    L.T.bad = L.status + RES_BAD;
+    L.T.rmax = reinterpret_cast<unsigned int *>(L.status + RES_RMAX);
     L.ulen_dev = cv.take<int32_t>(1);
 }
 
@@ -598,7 +606,8 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     } guard{ev};
     for (auto &e : ev) HIPTRY(hipEventCreate(&e));
     unsigned long long *ctr = reinterpret_cast<unsigned long long *>(L.rechecks);
-    HIPTRY(hipMemsetAsync(ctr, 0, CTR_WORDS * sizeof(unsigned long long), st));
+    // status words (with stage (a)'s flags) and counters in one fill
+    HIPTRY(hipMemsetAsync(L.status, 0, RES_TOP, st));
     HIPTRY(hipEventRecord(ev[0], st));
 
     // The Gram matrix of a user sample (for the rotation of Eq. (3)) does
@@ -619,7 +628,7 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     // ---- stage (a): exact thresholds (the input check is read at the
     // synchronisation before stage (b))
     s = run_thresholds(ctx, U, n, P, m, d, k, L.T, L.tau, L.tau_id, nullptr, ctr + CTR_PAIRS,
-                       ev[4], ev[5], ctr + CTR_CS, false);
+                       ev[4], ev[5], ctr + CTR_CS, false, false);
     if (s != RMIPS_OK) return s;
     HIPTRY(hipEventRecord(ev[1], st));
     if (rotate) {
@@ -681,7 +690,6 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     }
     int32_t *h_us = ctx->h_vis, *h_cs = ctx->h_vis + m;
     HIPTRY(hipMemcpyAsync(h_us, L.vis_us, sizeof(int32_t) * 2 * m, hipMemcpyDeviceToHost, st));
-    HIPTRY(hipMemcpyAsync(ctx->h_status + 12, L.T.bad, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPTRY(hipEventRecord(ev[2], st));
     // (no synchronisation here: the first batch goes out at once, and these
     // copies arrive with its results; its input check is read then, before
@@ -745,7 +753,7 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
             ms_count_k += t;
         }
         if (first) {
-            if (ctx->h_status[12] != 0)
+            if (h_st[RES_BAD] != 0)
                 return fail(ctx, RMIPS_ENONFINITE,
                             "input holds a NaN/Inf or a vector norm above 2^60");
             ulen = 0;  // the batch's own user count, for the statistics
