@@ -716,6 +716,24 @@ void launch_gather_i32(const int32_t *src, const int32_t *idx, int64_t n, int32_
     k_gather_i32<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(src, idx, n, dst);
 }
 
+__global__ void k_gather3_i32(const int32_t *__restrict__ a, const int32_t *__restrict__ b,
+                              const int32_t *__restrict__ c, const int32_t *__restrict__ idx,
+                              int64_t n, int32_t *__restrict__ da, int32_t *__restrict__ db,
+                              int32_t *__restrict__ dc) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t j = idx[i];
+    da[i] = a[j];
+    db[i] = b[j];
+    dc[i] = c[j];
+}
+
+void launch_gather3_i32(const int32_t *a, const int32_t *b, const int32_t *c,
+                        const int32_t *idx, int64_t n, int32_t *da, int32_t *db, int32_t *dc,
+                        hipStream_t st) {
+    k_gather3_i32<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(a, b, c, idx, n, da, db, dc);
+}
+
 // ------------------------------------------------------------------ top-N
 // One workgroup: the kept list plus the batch items that can enter it are
 // sorted (bitonic, descending keys score<<32 | ~id) in LDS.

@@ -175,6 +175,10 @@ void launch_visit_keys(const int32_t *uscore, const int32_t *inv, int64_t m,
                        uint32_t *key, int32_t *val, int32_t *status, hipStream_t st);
 void launch_gather_i32(const int32_t *src, const int32_t *idx, int64_t n, int32_t *dst,
                        hipStream_t st);
+// da[i] = a[idx[i]], db[i] = b[idx[i]], dc[i] = c[idx[i]] in one launch
+void launch_gather3_i32(const int32_t *a, const int32_t *b, const int32_t *c,
+                        const int32_t *idx, int64_t n, int32_t *da, int32_t *db, int32_t *dc,
+                        hipStream_t st);
 
 // Running top-N: merge the exact scores of a batch into the sorted list
 // `top` (keys score<<32 | ~id), keep N.  status[0] = N-th score (-1 while

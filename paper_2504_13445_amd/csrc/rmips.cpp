@@ -675,9 +675,7 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     launch_visit_keys(L.uscore, L.inv, m, L.vkeys, L.visit, L.status, st);
     // the keys are ~uscore with 0 <= uscore <= n: only the bits of n vary
     HIPTRY(radix_sort_u32(L.vkeys, L.visit, m, L.usort, st, 0, 32 - __builtin_clz((unsigned)n)));
-    launch_gather_i32(L.uscore, L.visit, m, L.vis_us, st);
-    launch_gather_i32(L.cs, L.visit, m, L.vis_cs, st);
-    launch_gather_i32(L.T.perm, L.visit, m, L.vis_cid, st);
+    launch_gather3_i32(L.uscore, L.cs, L.T.perm, L.visit, m, L.vis_us, L.vis_cs, L.vis_cid, st);
     // pinned host copies (grown once per larger m): bounds and prefixes in
     // visit order, then room for a batch's result block
     const int64_t need = 2 * m + (int64_t)(RES_BYTES / sizeof(int32_t));
