@@ -55,7 +55,7 @@ typedef enum {
     RMIPS_OK = 0,
     RMIPS_EINVAL = 1,       /* bad size, pointer or parameter */
     RMIPS_EWORKSPACE = 2,   /* ws_bytes below the *_workspace_size value */
-    RMIPS_ENONFINITE = 3,   /* NaN or Inf in an input vector */
+    RMIPS_ENONFINITE = 3,   /* NaN or Inf in an input vector, or a norm above 2^60 */
     RMIPS_EUNSUPPORTED = 4, /* precision or device not supported */
     RMIPS_EDEVICE = 5       /* HIP runtime error */
 } rmips_status;
@@ -173,13 +173,16 @@ rmips_status rmips_scores(rmips_ctx *ctx, const float *U, int64_t n,
 /*
  * Def. 3 by the paper's method (Sec. 4, Alg. 2 driven by exact thresholds):
  * stage (a), then the Cauchy-Schwarz (Eq. 2) and incremental-pruning
- * (Eq. 3 / Eq. 6, d' = 10 after a rotation of both sides) upper bounds on
- * every score, then exact scores of items visited in (bound desc, id asc)
+ * (Eq. 3 / Eq. 6) upper bounds on every score, with d' = min(d, 62) after a
+ * rotation of both sides onto the users' dominant eigenspace (none when
+ * d <= 62), then exact scores of items visited in (bound desc, id asc)
  * order until the next bound is below the current N-th score.
  *   1 <= N <= min(m, RMIPS_N_MAX).
  *   top_ids [N], top_scores [N]: HOST int32 out, (score desc, id asc).
  *   stats: HOST, may be NULL.
- * Synchronises the context's stream before returning.
+ * A NaN or Inf in U or P, or a row norm above 2^60, returns
+ * RMIPS_ENONFINITE; on any error top_ids, top_scores and stats are left
+ * as they were.  Synchronises the context's stream before returning.
  */
 rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n,
                         const float *P, int64_t m, int32_t d, int32_t k,
