@@ -434,99 +434,126 @@ void launch_gram(const float *X, int64_t ns, int64_t stride, int d, double *G, d
 
 // Augmented rows of the Eq. (3) bound, one thread per row over a
 // persistent grid: y = W x in FP64 with W (dp x d, FP64, orthonormal rows)
-// staged in LDS as its transpose; ||x||^2 in FP64.  Row layout: a = [y (dp
-// values, rounded to FP32), tail(x), scale * ||x||, 0...] (ka values, a
-// multiple of 16), stored as BF16 hi = rn(a) (2 ka bytes) then BF16 lo =
-// rn(a - hi) (2 ka bytes).  tail(x) = sqrt(||x||^2 - ||W x||^2), rounded up
-// and widened by 1e-12 ||x||^2 under the root for the FP64 rounding and the
-// departure of W from exact orthonormality.
+// on the FP64 matrix cores; ||x||^2 in FP64.  Row layout: a = [y (dp values,
+// rounded to FP32), tail(x), scale * ||x||, 0...] (ka values, a multiple of
+// 16), stored as BF16 hi = rn(a) (2 ka bytes) then BF16 lo = rn(a - hi)
+// (2 ka bytes).  tail(x) = sqrt(||x||^2 - ||W x||^2), rounded up and widened
+// by 1e-12 ||x||^2 under the root for the FP64 rounding (in any summation
+// order) and the departure of W from exact orthonormality.
+//
+// Each wave projects 16 rows at a time onto the 64 output columns (zero past
+// dp) with v_mfma_f64_16x16x4_f64, four column tiles of 16 per step of 4
+// terms.  Operand layout of that instruction: lane l feeds row l % 16 of A
+// and column l % 16 of B at k-slot l / 16, and holds result rows
+// l / 16 + 4 i (i = 0..3) of column l % 16.  k-slot g of a step s takes term
+// g * Kq + s (Kq = ceil(d / 4)), so each lane reads one contiguous quarter of
+// its row.  W is staged once per workgroup in LDS in the same order:
+// Wt[(s * 4 + g) * 64 + j] = W[j][g * Kq + s].
 constexpr int DP_MAX = 62;
 constexpr int KA_MAX = 64;
-constexpr int ROT_THREADS = 512;
+constexpr int ROT_WAVES = 8;
+typedef double d4_t __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(ROT_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ __launch_bounds__(64 * ROT_WAVES) __attribute__((amdgpu_waves_per_eu(2)))
 void k_rotate_aug(const float *__restrict__ X, const int32_t *__restrict__ order, int64_t rows,
                   int64_t rows_pad, int d, const double *__restrict__ W, int dp, int ka,
                   float scale, uint4 *__restrict__ out) {
-    extern __shared__ double Wt[];  // Wt[i * DP_MAX + j] = W[j][i], zero for j >= dp
-    for (int e = threadIdx.x; e < d * DP_MAX; e += blockDim.x) {
-        const int i = e / DP_MAX, j = e - i * DP_MAX;
-        Wt[e] = (j < dp) ? W[(int64_t)j * d + i] : 0.0;
+    extern __shared__ double Wt[];
+    const int Kq = (d + 3) / 4;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, c16 = lane & 15;
+    for (int e = threadIdx.x; e < 4 * Kq * 64; e += blockDim.x) {
+        const int ri = e >> 6, j = e & 63, k = (ri & 3) * Kq + (ri >> 2);
+        Wt[e] = (j < dp && k < d) ? W[(int64_t)j * d + k] : 0.0;
     }
     __syncthreads();
-    const int kw = ka / 8;  // 16-byte words per part (hi or lo)
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < rows_pad;
-         r += (int64_t)gridDim.x * blockDim.x) {
-        uint4 *o = out + r * 2 * kw;
-        if (r >= rows) {
-            for (int q = 0; q < 2 * kw; ++q) o[q] = make_uint4(0, 0, 0, 0);
-            continue;
-        }
-        const float *x = X + (int64_t)(order ? order[r] : r) * d;
-        double y[DP_MAX];
+    uint16_t *o16 = reinterpret_cast<uint16_t *>(out);
+    const int64_t rstride = (int64_t)gridDim.x * ROT_WAVES * 16;
+    for (int64_t r0 = ((int64_t)blockIdx.x * ROT_WAVES + w) * 16; r0 < rows_pad; r0 += rstride) {
+        // A operand: row r0 + c16, terms g * Kq .. g * Kq + Kq - 1 (zero past
+        // d and for padding rows), in blocks of 16 terms, the next block
+        // loaded while the current one is multiplied
+        const int64_t ra = r0 + c16;
+        const bool live = ra < rows;
+        const float *x = X + (int64_t)(live ? (order ? order[ra] : ra) : 0) * d;
+        // (unconditional loads of indexes clamped into the row, so that none
+        // waits for another; values past d and of padding rows are zero)
+        auto load16 = [&](float (&v)[16], int q0) {
 #pragma unroll
-        for (int j = 0; j < DP_MAX; ++j) y[j] = 0.0;
+            for (int j = 0; j < 16; ++j) {
+                const int k = g * Kq + q0 + j;
+                const bool ok = live && q0 + j < Kq && k < d;
+                const float t = x[ok ? k : 0];
+                v[j] = ok ? t : 0.0f;
+            }
+        };
         double s = 0.0;
-        // the row in blocks of 8 values loaded ahead of the FP64 products
-        // (indexes past the end are clamped: every load stays in bounds)
-        for (int i0 = 0; i0 < d; i0 += 8) {
-            float xv[8];
+        d4_t acc[4] = {};
+        float xa[16], xb[16];
+        load16(xa, 0);
+        for (int q0 = 0; q0 < Kq; q0 += 16) {
+            if (q0 + 16 < Kq) load16(xb, q0 + 16);  // (uniform)
 #pragma unroll
-            for (int q = 0; q < 8; ++q) xv[q] = x[(i0 + q < d) ? i0 + q : d - 1];
+            for (int j = 0; j < 16; ++j) {
+                if (q0 + j < Kq) {  // (uniform)
+                    const double a = (double)xa[j];
+                    s = fma(a, a, s);
+                    const double *wr = Wt + ((q0 + j) * 4 + g) * 64 + c16;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                if (i0 + q < d) {
-                    const double xi = (double)xv[q];
-                    s = fma(xi, xi, s);
-                    const double2 *w2 = reinterpret_cast<const double2 *>(Wt + (i0 + q) * DP_MAX);
-#pragma unroll
-                    for (int j2 = 0; j2 < DP_MAX / 2; ++j2) {
-                        const double2 w = w2[j2];
-                        y[2 * j2] = fma(w.x, xi, y[2 * j2]);
-                        y[2 * j2 + 1] = fma(w.y, xi, y[2 * j2 + 1]);
-                    }
+                    for (int t = 0; t < 4; ++t)
+                        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, wr[16 * t], acc[t], 0, 0,
+                                                                       0);
                 }
             }
+#pragma unroll
+            for (int j = 0; j < 16; ++j) xa[j] = xb[j];
         }
-        double y2 = 0.0;
+        // ||x||^2 of row c16 over the four k-slots, then of this lane's result
+        // rows g + 4 i (held by lane g + 4 i)
+        s += __shfl_xor(s, 16);
+        s += __shfl_xor(s, 32);
+        double y2[4], sr[4];
 #pragma unroll
-        for (int j = 0; j < DP_MAX; ++j) y2 = fma(y[j], y[j], y2);
-        double t2 = s - y2;
-        if (t2 < 0.0) t2 = 0.0;
-        const float tail = __double2float_ru(sqrt(t2 + 1e-12 * s));
-        const float nrm = scale * __double2float_ru(sqrt(s) * (1.0 + 0x1p-40));
-        // the ka values, eight per 16-byte word, as BF16 hi and lo
+        for (int i = 0; i < 4; ++i) {
+            double v = 0.0;
 #pragma unroll
-        for (int q = 0; q < KA_MAX / 8; ++q) {
-            if (q < kw) {
-                uint32_t hw[4], lw[4];
+            for (int t = 0; t < 4; ++t) v = fma(acc[t][i], acc[t][i], v);
+            y2[i] = v;
+            sr[i] = __shfl(s, g + 4 * i);
+        }
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    float v2[2];
+        for (int o = 1; o < 16; o <<= 1)
 #pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const int c = 8 * q + 2 * e + h;
-                        float v = (c < DP_MAX && c < dp) ? (float)y[c < DP_MAX ? c : 0] : 0.0f;
-                        v = (c == dp) ? tail : v;
-                        v = (c == dp + 1) ? nrm : v;
-                        v2[h] = v;
-                    }
-                    float h0, h1, l0, l1;
-                    const uint16_t b0 = to_bf16(v2[0], h0), b1 = to_bf16(v2[1], h1);
-                    const uint16_t c0 = to_bf16(v2[0] - h0, l0), c1 = to_bf16(v2[1] - h1, l1);
-                    hw[e] = (uint32_t)b0 | ((uint32_t)b1 << 16);
-                    lw[e] = (uint32_t)c0 | ((uint32_t)c1 << 16);
-                }
-                o[q] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
-                o[kw + q] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+            for (int i = 0; i < 4; ++i) y2[i] += __shfl_xor(y2[i], o);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t R = r0 + g + 4 * i;
+            if (R >= rows_pad) continue;
+            double t2 = sr[i] - y2[i];
+            if (t2 < 0.0) t2 = 0.0;
+            const float tail = __double2float_ru(sqrt(t2 + 1e-12 * sr[i]));
+            const float nrm = scale * __double2float_ru(sqrt(sr[i]) * (1.0 + 0x1p-40));
+            uint16_t *orow = o16 + R * 2 * ka;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int C = 16 * t + c16;
+                if (C >= ka) continue;
+                float v = (C < dp) ? (float)acc[t][i] : 0.0f;
+                v = (C == dp) ? tail : v;
+                v = (C == dp + 1) ? nrm : v;
+                float h, l;
+                const uint16_t bh = to_bf16(v, h);
+                const uint16_t bl = to_bf16(v - h, l);
+                orow[C] = bh;
+                orow[ka + C] = bl;
             }
         }
     }
 }
 
 // The same rows when W is the identity (dp = d): y = x exactly, and ||W x||^2
-// is the same FP64 sum as ||x||^2, so the tail is the widening alone.  The
-// output equals that of k_rotate_aug with W = I bit for bit.
+// is the same FP64 sum as ||x||^2, so the tail is the widening alone.  Up to
+// the FP64 summation order of the norm (both rounded up) these are the rows
+// k_rotate_aug gives with W = I.
 __global__ __launch_bounds__(256) void k_aug_ident(const float *__restrict__ X,
                                                   const int32_t *__restrict__ order,
                                                   int64_t rows, int64_t rows_pad, int d, int ka,
@@ -577,7 +604,7 @@ __global__ __launch_bounds__(256) void k_aug_ident(const float *__restrict__ X,
     }
 }
 
-size_t rotate_lds_bytes(int d) { return (size_t)d * DP_MAX * sizeof(double); }
+size_t rotate_lds_bytes(int d) { return (size_t)4 * ((d + 3) / 4) * 64 * sizeof(double); }
 
 void launch_rotate_aug(const float *X, const int32_t *order, int64_t rows, int64_t rows_pad,
                        int d, const double *W, int dp, int ka, float scale, uint4 *out,
@@ -587,10 +614,12 @@ void launch_rotate_aug(const float *X, const int32_t *order, int64_t rows, int64
                                                                        d, ka, scale, out);
         return;
     }
-    int64_t g = (rows_pad + ROT_THREADS - 1) / ROT_THREADS;
-    if (g > 512) g = 512;  // persistent: W is staged once per workgroup
-    k_rotate_aug<<<(unsigned)g, ROT_THREADS, rotate_lds_bytes(d), st>>>(X, order, rows, rows_pad,
-                                                                        d, W, dp, ka, scale, out);
+    // persistent: W is staged once per workgroup, one workgroup per compute
+    // unit (its LDS), 16 rows per wave at a time
+    int64_t g = (rows_pad + 16 * ROT_WAVES - 1) / (16 * ROT_WAVES);
+    if (g > 256) g = 256;
+    k_rotate_aug<<<(unsigned)g, 64 * ROT_WAVES, rotate_lds_bytes(d), st>>>(
+        X, order, rows, rows_pad, d, W, dp, ka, scale, out);
 }
 
 }  // namespace rmips
