@@ -190,17 +190,43 @@ __global__ __launch_bounds__(256) void k_soft(const float *__restrict__ U, int64
     }
 }
 
-// out[i] = scale_i * sum over slices of the partials (FP64, fixed order)
-__global__ void k_soft_reduce(const float *__restrict__ P, int nsplit, int64_t cols,
-                              int64_t ld_in, int64_t width, const float *__restrict__ dS,
-                              float *__restrict__ out, int64_t ld_out) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= cols * width) return;
-    const int64_t q = e / width, c = e - q * width;
+// out[q][c] = scale_q * (sum over slices k of P[k][q][c]) in FP64, for
+// c < width.  One workgroup per query and 64 columns: each of its four waves
+// adds a quarter of the slices in slice order (loads in batches of 8), then
+// the four partial sums are added in wave order, a fixed order in every call.
+__global__ __launch_bounds__(256) void k_soft_reduce(const float *__restrict__ P, int nsplit,
+                                                     int64_t cols, int64_t ld_in, int64_t width,
+                                                     const float *__restrict__ dS,
+                                                     float *__restrict__ out, int64_t ld_out) {
+    __shared__ double part[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t q = blockIdx.x;
+    const int64_t c = (int64_t)blockIdx.y * 64 + lane;
+    const bool ok = c < width;
+    const int per = (nsplit + 3) / 4, k0 = w * per, k1 = min(nsplit, k0 + per);
     double s = 0.0;
-    for (int k = 0; k < nsplit; ++k) s += (double)P[((int64_t)k * cols + q) * ld_in + c];
-    if (dS) s *= (double)dS[q];
-    out[q * ld_out + c] = (float)s;
+    if (ok) {
+        const float *p = P + q * ld_in + c;
+        const int64_t step = cols * ld_in;
+        int k = k0;
+        for (; k + 8 <= k1; k += 8) {
+            float v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = p[(int64_t)(k + j) * step];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s += (double)v[j];
+        }
+        for (; k < k1; ++k) s += (double)p[(int64_t)k * step];
+    }
+    part[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && ok) {
+        double t = part[0][lane] + part[1][lane];
+        t += part[2][lane];
+        t += part[3][lane];
+        if (dS) t *= (double)dS[q];
+        out[q * ld_out + c] = (float)t;
+    }
 }
 
 size_t soft_ws_bytes(int64_t n, int64_t nq, int d) {
@@ -228,16 +254,15 @@ void launch_soft(const float *U, int64_t n, const float *tau, const float *Q, in
         else if (cpl == 2) RMIPS_SOFT(true, 2);
         else if (cpl == 3) RMIPS_SOFT(true, 3);
         else RMIPS_SOFT(true, 4);
-        const int64_t tot = nq * d;
-        k_soft_reduce<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(part, nsplit, nq, sd.Dg, d,
-                                                                      dS, dQ, d);
+        k_soft_reduce<<<dim3((unsigned)nq, (unsigned)((d + 63) / 64)), 256, 0, st>>>(
+            part, nsplit, nq, sd.Dg, d, dS, dQ, d);
     } else {
         if (cpl == 1) RMIPS_SOFT(false, 1);
         else if (cpl == 2) RMIPS_SOFT(false, 2);
         else if (cpl == 3) RMIPS_SOFT(false, 3);
         else RMIPS_SOFT(false, 4);
-        k_soft_reduce<<<(unsigned)((nq + 255) / 256), 256, 0, st>>>(part, nsplit, nq, 1, 1,
-                                                                     nullptr, S, 1);
+        k_soft_reduce<<<dim3((unsigned)nq, 1u), 256, 0, st>>>(part, nsplit, nq, 1, 1, nullptr, S,
+                                                              1);
     }
 #undef RMIPS_SOFT
 }
