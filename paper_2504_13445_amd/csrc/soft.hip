@@ -86,6 +86,18 @@ __global__ __launch_bounds__(256) void k_soft(const float *__restrict__ U, int64
 
     // Z block of this wave: query rows rbq*32.., user columns cbu*32..
     const int rbq = w >> 1, cbu = w & 1;
+    // forward, up to 64 dims per half row (d <= 128): the wave's query
+    // operand stays in registers for the whole kernel (the same products, in
+    // the same order, as from LDS; the backward kernel keeps its registers
+    // for the gradient blocks)
+    constexpr bool QREG = !BWD && CPL <= 2;
+    float qa[QREG ? 32 * CPL : 1];
+    if constexpr (QREG) {
+        __syncthreads();  // the query tile is in LDS
+        const float *a = Qsh + (rbq * 32 + (lane & 31)) * ld + (lane >> 5) * ks;
+#pragma unroll
+        for (int q = 0; q < 32 * CPL; ++q) qa[q] = (q < ks) ? a[q] : 0.0f;
+    }
     float ssum[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) ssum[i] = 0.0f;
@@ -130,7 +142,21 @@ __global__ __launch_bounds__(256) void k_soft(const float *__restrict__ U, int64
         __syncthreads();
         if (u0 + SUC < ue) fetch(u0 + SUC);
         f32x16 z = {0};
-        mfma32_f32(z, Qsh + rbq * 32 * ld, Ush + cbu * 32 * ld, ld, ks, lane);
+        if constexpr (QREG) {
+            const float *b = Ush + (cbu * 32 + (lane & 31)) * ld + (lane >> 5) * ks;
+#pragma unroll
+            for (int q = 0; q < 32 * CPL; q += 4) {
+                if (q < ks) {  // (uniform; ks is a multiple of 4)
+                    const f32x4 bv = *reinterpret_cast<const f32x4 *>(b + q);
+                    z = __builtin_amdgcn_mfma_f32_32x32x2f32(qa[q], bv[0], z, 0, 0, 0);
+                    z = __builtin_amdgcn_mfma_f32_32x32x2f32(qa[q + 1], bv[1], z, 0, 0, 0);
+                    z = __builtin_amdgcn_mfma_f32_32x32x2f32(qa[q + 2], bv[2], z, 0, 0, 0);
+                    z = __builtin_amdgcn_mfma_f32_32x32x2f32(qa[q + 3], bv[3], z, 0, 0, 0);
+                }
+            }
+        } else {
+            mfma32_f32(z, Qsh + rbq * 32 * ld, Ush + cbu * 32 * ld, ld, ks, lane);
+        }
         const float tu = tsh[cbu * 32 + (lane & 31)];
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
