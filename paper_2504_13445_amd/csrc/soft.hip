@@ -17,7 +17,7 @@ namespace rmips {
 
 constexpr int SQ = 64;          // queries per workgroup
 constexpr int SUC = 64;         // users per chunk
-constexpr int S_SPLITS = 256;   // user slices (workgroups per query tile)
+constexpr int S_SPLITS = 128;   // user slices (workgroups per query tile)
 
 struct SoftDims {
     int d, D, Dg, ld, ldw;  // dims, padded for Z (x8), padded for G (x32), LDS strides
