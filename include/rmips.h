@@ -27,12 +27,13 @@
  *     caller's workspace `ws` of `ws_bytes` bytes (device memory, 256-byte
  *     aligned), sized by the matching *_workspace_size query.  Its contents
  *     are undefined after a call.
- *   - Work is enqueued on the context's HIP stream.  rmips_thresholds and
- *     rmips_scores wait once, after the input check (a few bytes read
- *     back), and return before their results are complete; rmips_soft_fwd
- *     and rmips_soft_bwd do not wait.  rmips_topn synchronises the stream
- *     (its bound-ordered loop reads a few bytes back per batch) and writes
- *     host arrays.
+ *   - Work is enqueued on the context's HIP stream.  rmips_thresholds,
+ *     rmips_scores, rmips_soft_fwd and rmips_soft_bwd never wait: they
+ *     return once their work is enqueued.  The input check of
+ *     rmips_thresholds and rmips_scores (NaN, Inf, a norm above 2^60) runs
+ *     on the device and is reported by the next rmips_sync on the context.
+ *     rmips_topn synchronises the stream (its bound-ordered loop reads a few
+ *     bytes back per batch), checks its own inputs and writes host arrays.
  *   - Arguments are validated before anything is launched.  On error the
  *     outputs are unspecified and rmips_last_error() describes the error.
  *   - A context is not thread-safe; use one context per stream.
@@ -75,15 +76,18 @@ typedef struct {
     int64_t visited_items;    /* items whose exact score was computed */
     int64_t batches;          /* bound-ordered batches run */
     int64_t cand_pairs;       /* stage (a): candidates recomputed in FP64 */
+    int64_t cand_listed;      /* stage (a): candidates listed by the screen */
     int64_t overflow_users;   /* stage (a): users sent to the exact fallback */
     int64_t refine_users;     /* stage (a): users screened again with a tighter
                                  bound after their candidate lists overflowed */
     int64_t recheck_pairs;    /* stage (b): ambiguous pairs rechecked in FP64 */
     int64_t screened_pairs;   /* stage (a)+(b): pairs through the matrix cores */
     int64_t bound_pairs;      /* stage (c): pairs evaluated by the Eq. 3 bound */
-    int64_t thresh_pairs;     /* stage (a): pairs screened after the early exit */
+    int64_t thresh_pairs;     /* stage (a): pairs screened by the main pass after
+                                 the early exit */
     int64_t count_pairs;      /* stage (b): (item, user) pairs screened */
     int64_t count_launches;   /* stage (b): counting kernel launches */
+    int64_t refine_pairs;     /* stage (a): pairs screened by refinement passes */
     float ms_thresh;          /* stage (a), all kernels */
     float ms_bound;           /* stage (c), all kernels and the host rotation */
     float ms_count;           /* stage (b) loop, including host round trips */
@@ -107,6 +111,33 @@ const char *rmips_last_error(const rmips_ctx *ctx);
 
 /* Change the stream a context enqueues on. */
 rmips_status rmips_set_stream(rmips_ctx *ctx, void *hip_stream);
+
+/*
+ * Wait for the context's stream and report the input checks of the
+ * rmips_thresholds and rmips_scores calls made since the last rmips_sync:
+ * RMIPS_ENONFINITE when any of them saw a NaN or an Inf, or a row norm
+ * above 2^60 (the outputs of that call are then unspecified), else
+ * RMIPS_OK.  The checks are cleared either way.  (With 63 checks pending,
+ * the next such call waits for them itself and returns their result.)
+ */
+rmips_status rmips_sync(rmips_ctx *ctx);
+
+/*
+ * Per-kernel timing.  With on != 0 (which also clears the totals), every
+ * kernel launch of the context's calls is bracketed by two HIP events on
+ * the context's stream, and their durations are summed per kernel name;
+ * on = 0 stops recording and keeps the totals.  Waits for the stream.
+ */
+rmips_status rmips_set_profiling(rmips_ctx *ctx, int32_t on);
+
+/*
+ * Entry i (0, 1, ... in the order the kernels first ran) of the totals:
+ * the kernel's name (NUL-terminated, at most name_cap bytes, into the
+ * host buffer `name`), its launch count and summed duration in ms (host
+ * outputs).  Waits for the stream.  RMIPS_EINVAL past the last entry.
+ */
+rmips_status rmips_profile_entry(rmips_ctx *ctx, int32_t i, char *name, int32_t name_cap,
+                                 int64_t *launches, double *ms_total);
 
 /*
  * Testing knob: capacity of the per-user candidate list of stage (a).

@@ -2,8 +2,9 @@
 
 Python side of the C ABI in include/rmips.h; see _lib for the calls.
 """
-from ._lib import (EXPORTS, K_MAX, N_MAX, D_MAX, RmipsError, SoftScore, load,
-                   scores, soft_bwd, soft_fwd, thresholds, topn, topn_workspace)
+from ._lib import (EXPORTS, K_MAX, N_MAX, D_MAX, RmipsError, SoftScore, load, profile,
+                   scores, set_profiling, soft_bwd, soft_fwd, sync, thresholds, topn,
+                   topn_workspace)
 
-__all__ = ["EXPORTS", "K_MAX", "N_MAX", "D_MAX", "RmipsError", "SoftScore", "load",
-           "scores", "soft_bwd", "soft_fwd", "thresholds", "topn", "topn_workspace"]
+__all__ = ["EXPORTS", "K_MAX", "N_MAX", "D_MAX", "RmipsError", "SoftScore", "load", "profile",
+           "scores", "set_profiling", "soft_bwd", "soft_fwd", "sync", "thresholds", "topn", "topn_workspace"]

@@ -21,7 +21,8 @@ PREC = {"fp32": 0, "bf16": 1, "fp8": 2, "fp8_e4m3": 2}
 K_MAX, N_MAX, D_MAX = 32, 1024, 256
 
 EXPORTS = [
-    "rmips_create", "rmips_destroy", "rmips_last_error", "rmips_set_stream",
+    "rmips_create", "rmips_destroy", "rmips_last_error", "rmips_set_stream", "rmips_sync",
+    "rmips_set_profiling", "rmips_profile_entry",
     "rmips_set_candidate_cap", "rmips_set_batch", "rmips_set_bound_output",
     "rmips_thresholds_workspace_size", "rmips_scores_workspace_size",
     "rmips_topn_workspace_size", "rmips_soft_workspace_size",
@@ -38,11 +39,13 @@ class RmipsError(RuntimeError):
 
 class Stats(ctypes.Structure):
     _fields_ = [("visited_items", ctypes.c_int64), ("batches", ctypes.c_int64),
-                ("cand_pairs", ctypes.c_int64), ("overflow_users", ctypes.c_int64),
+                ("cand_pairs", ctypes.c_int64), ("cand_listed", ctypes.c_int64),
+                ("overflow_users", ctypes.c_int64),
                 ("refine_users", ctypes.c_int64),
                 ("recheck_pairs", ctypes.c_int64), ("screened_pairs", ctypes.c_int64),
                 ("bound_pairs", ctypes.c_int64), ("thresh_pairs", ctypes.c_int64),
                 ("count_pairs", ctypes.c_int64), ("count_launches", ctypes.c_int64),
+                ("refine_pairs", ctypes.c_int64),
                 ("ms_thresh", ctypes.c_float), ("ms_bound", ctypes.c_float),
                 ("ms_count", ctypes.c_float), ("ms_total", ctypes.c_float),
                 ("ms_screen", ctypes.c_float), ("ms_count_kernels", ctypes.c_float),
@@ -76,6 +79,13 @@ def load():
     lib.rmips_last_error.restype = ctypes.c_char_p
     lib.rmips_set_stream.argtypes = [vp, vp]
     lib.rmips_set_stream.restype = st
+    lib.rmips_sync.argtypes = [vp]
+    lib.rmips_sync.restype = st
+    lib.rmips_set_profiling.argtypes = [vp, i32]
+    lib.rmips_set_profiling.restype = st
+    lib.rmips_profile_entry.argtypes = [vp, i32, ctypes.c_char_p, i32,
+                                        ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
+    lib.rmips_profile_entry.restype = st
     lib.rmips_set_candidate_cap.argtypes = [vp, i32]
     lib.rmips_set_candidate_cap.restype = st
     lib.rmips_set_batch.argtypes = [vp, i32, i32]
@@ -151,8 +161,41 @@ def _workspace(nbytes, device):
     return torch.empty(int(nbytes), dtype=torch.uint8, device=device)
 
 
-def thresholds(U, P, k, prec="fp32", with_topk=False, cand_cap=None):
-    """tau (float64), tau_id (int32) [, topk ids (int32, n x k)] on U's device."""
+def sync(device=None):
+    """rmips_sync: wait for the stream and raise if an input check of an
+    earlier thresholds / scores call failed."""
+    dev = device or torch.device("cuda", torch.cuda.current_device())
+    ctx = _context(dev)
+    _check(ctx, load().rmips_sync(ctx))
+
+
+def set_profiling(on, device=None):
+    """rmips_set_profiling on the device's context (on=True clears the totals)."""
+    dev = device or torch.device("cuda", torch.cuda.current_device())
+    ctx = _context(dev)
+    _check(ctx, load().rmips_set_profiling(ctx, 1 if on else 0))
+
+
+def profile(device=None):
+    """Per-kernel totals since profiling was switched on: a list of
+    (name, launches, total ms) in the order the kernels first ran."""
+    dev = device or torch.device("cuda", torch.cuda.current_device())
+    lib = load()
+    ctx = _context(dev)
+    out = []
+    buf = ctypes.create_string_buffer(128)
+    nl, ms = ctypes.c_int64(), ctypes.c_double()
+    i = 0
+    while lib.rmips_profile_entry(ctx, i, buf, 128, ctypes.byref(nl), ctypes.byref(ms)) == RMIPS_OK:
+        out.append((buf.value.decode(), int(nl.value), float(ms.value)))
+        i += 1
+    return out
+
+
+def thresholds(U, P, k, prec="fp32", with_topk=False, cand_cap=None, check=True):
+    """tau (float64), tau_id (int32) [, topk ids (int32, n x k)] on U's device.
+    check=True waits for the call (rmips_sync) and raises on bad input;
+    check=False returns at once (the check is reported by sync())."""
     U, P = _dev_f32(U, "U"), _dev_f32(P, "P")
     n, d = U.shape
     m = P.shape[0]
@@ -166,14 +209,18 @@ def thresholds(U, P, k, prec="fp32", with_topk=False, cand_cap=None):
     tau = torch.empty(n, dtype=torch.float64, device=U.device)
     tid = torch.empty(n, dtype=torch.int32, device=U.device)
     topk = torch.empty((n, k), dtype=torch.int32, device=U.device) if with_topk else None
-    _check(ctx, lib.rmips_thresholds(ctx, _ptr(U), n, _ptr(P), m, d, k, p, _ptr(ws),
-                                      ws.numel(), _ptr(tau), _ptr(tid), _ptr(topk)))
+    status = lib.rmips_thresholds(ctx, _ptr(U), n, _ptr(P), m, d, k, p, _ptr(ws),
+                                  ws.numel(), _ptr(tau), _ptr(tid), _ptr(topk))
     lib.rmips_set_candidate_cap(ctx, 0)
+    _check(ctx, status)
+    if check:
+        _check(ctx, lib.rmips_sync(ctx))
     return (tau, tid, topk) if with_topk else (tau, tid)
 
 
-def scores(U, tau, tau_id, Q, q_ids=None, prec="fp32"):
-    """|T_k(q)| for each row of Q (int32 on U's device)."""
+def scores(U, tau, tau_id, Q, q_ids=None, prec="fp32", check=True):
+    """|T_k(q)| for each row of Q (int32 on U's device); check as in
+    thresholds()."""
     U, Q = _dev_f32(U, "U"), _dev_f32(Q, "Q")
     n, d = U.shape
     nq = Q.shape[0]
@@ -190,6 +237,8 @@ def scores(U, tau, tau_id, Q, q_ids=None, prec="fp32"):
                                  _ptr(tau_id.contiguous()), _ptr(Q),
                                  _ptr(q_ids.contiguous()) if q_ids is not None else None,
                                  nq, d, p, _ptr(ws), ws.numel(), _ptr(out)))
+    if check:
+        _check(ctx, lib.rmips_sync(ctx))
     return out
 
 

@@ -205,6 +205,8 @@ void k_count(CountArgs a) {
     auto classify = [&]() {
         const int64_t us0 = pus0, us1 = pus0 + 32;
         const bool c0 = us0 < ulen, c1 = us1 < ulen;
+        // a column past the last user counts nothing (explicit validity)
+        const int m0 = c0 ? 1 : 0, m1 = c1 ? 1 : 0;
         // counts, and whether any pair falls between the two thresholds:
         // with e = med3(v, tout, tin) (tout <= tin), v > tin <=> v > e and
         // tout <= v <= tin <=> v == e
@@ -215,8 +217,8 @@ void k_count(CountArgs a) {
             const float v1 = (PREC == PREC_FP8) ? acc1[i] * srow[i] : acc1[i];
             const float e0 = __builtin_amdgcn_fmed3f(v0, ptout0, ptin0);
             const float e1 = __builtin_amdgcn_fmed3f(v1, ptout1, ptin1);
-            cnt[i] += (int)(v0 > e0);
-            cnt[i] += (int)(v1 > e1);
+            cnt[i] += (v0 > e0) ? m0 : 0;
+            cnt[i] += (v1 > e1) ? m1 : 0;
             anyamb |= (v0 == e0) | (v1 == e1);
         }
         if (__ballot(anyamb) != 0ull) {
@@ -256,7 +258,8 @@ void k_count(CountArgs a) {
         if (nxt < nchunks) chunk_copy(nxt, buf ? Ush0 : Ush1);
         const uint8_t *Ub = buf ? Ush1 : Ush0;
         const int64_t us0 = ch * CNT_USERS + (lane & 31), us1 = us0 + 32;
-        // a column past the last user is "out" for every row: tout = +inf
+        // (a column past the last user keeps these values; classify() counts
+        // nothing in it, whatever its products hold)
         float tin0 = INFINITY, tout0 = INFINITY, tin1 = INFINITY, tout1 = INFINITY;
         if (us0 < ulen) thresholds(uq0, uqs0, tin0, tout0);
         if (us1 < ulen) thresholds(uq1, uqs1, tin1, tout1);
@@ -316,6 +319,7 @@ void launch_count_p(const CountArgs &a, size_t lds, hipStream_t st) {
     with_nch<PREC>(a.D * elem_bytes(PREC) / 32, [&](auto n) {
         constexpr int NCH = decltype(n)::value, NW = count_waves(NCH);
         const unsigned g = (unsigned)((a.nb + 32 * NW - 1) / (32 * NW) * a.nsplit);
+        RMIPS_PROF(st, "k_count");
         k_count<PREC, NCH><<<g, 64 * NW, lds, st>>>(a);
     });
 }
@@ -333,6 +337,7 @@ __global__ __launch_bounds__(256) void k_max_i32(const int32_t *__restrict__ x, 
 }
 
 void launch_max_i32(const int32_t *x, int64_t n, int32_t *out, hipStream_t st) {
+    RMIPS_PROF(st, "k_max_i32");
     k_max_i32<<<1, 256, 0, st>>>(x, n, out);
 }
 
@@ -400,9 +405,11 @@ __global__ __launch_bounds__(64 * BW) void k_bound(BoundArgs a) {
     const int64_t ulen = a.cs[ib];  // largest prefix of the block (norm order)
     const int64_t nblk = (ulen + 31) / 32;
     const int64_t step = (int64_t)a.nsplit * BW;
-    // one user column per lane: its hi and lo parts and its threshold,
-    // lowered by the absolute slack (clamped index: every load in bounds)
-    auto fetch = [&](int64_t j, uint4 (&bh)[KS], uint4 (&bl)[KS], float &tl) {
+    // one user column per lane: its hi and lo parts, its threshold lowered
+    // by the absolute slack, and whether the column is a user of the prefix
+    // (vm = 1) or past it (vm = 0: nothing it holds is counted); clamped
+    // index, so every load is in bounds
+    auto fetch = [&](int64_t j, uint4 (&bh)[KS], uint4 (&bl)[KS], float &tl, int &vm) {
         const int64_t us = j * 32 + col;
         const bool ok = j < nblk && us < ulen;
         const int64_t uc = ok ? us : 0;
@@ -411,17 +418,20 @@ __global__ __launch_bounds__(64 * BW) void k_bound(BoundArgs a) {
             bh[q] = a.Ub[uc * RW + 2 * q + h];
             bl[q] = a.Ub[uc * RW + 2 * KS + 2 * q + h];
         }
-        tl = ok ? float_pred(a.tau_lo[uc] - a.abs_slack) : INFINITY;
+        tl = float_pred(a.tau_lo[uc] - a.abs_slack);
+        vm = ok ? 1 : 0;
     };
     int64_t j = (int64_t)split * BW + w;
     uint4 bh[KS], bl[KS];
     float tl;
-    fetch(j, bh, bl, tl);
+    int vm;
+    fetch(j, bh, bl, tl, vm);
     int64_t npairs = 0;  // statistics: users of this wave's blocks
     for (; j < nblk; j += step) {
         uint4 nh[KS], nl[KS];
         float nt;
-        fetch(j + step, nh, nl, nt);
+        int nvm;
+        fetch(j + step, nh, nl, nt, nvm);
         // the products of tile t + 1 run while tile t's counts are taken
         auto prod = [&](int t, f32x16 &acc) {
             acc = f32x16{0};
@@ -436,7 +446,7 @@ __global__ __launch_bounds__(64 * BW) void k_bound(BoundArgs a) {
         };
         auto tally = [&](int t, const f32x16 &acc) {
 #pragma unroll
-            for (int i = 0; i < 16; ++i) cnt[t][i] += (acc[i] >= tl) ? 1 : 0;
+            for (int i = 0; i < 16; ++i) cnt[t][i] += (acc[i] >= tl) ? vm : 0;
         };
         f32x16 p0, p1;
         prod(0, p0);
@@ -458,6 +468,7 @@ __global__ __launch_bounds__(64 * BW) void k_bound(BoundArgs a) {
             bl[q] = nl[q];
         }
         tl = nt;
+        vm = nvm;
     }
 #pragma unroll
     for (int t = 0; t < TI; ++t)
@@ -529,7 +540,9 @@ void k_bound_lds(BoundArgs a) {
     const uint32_t magic = slot_magic(RW);
     // stage j: users [BL_USERS j, BL_USERS (j + 1)) in groups of 64 rows
     // (rows past the prefix repeat its last user, groups wholly past it are
-    // not copied; those columns are masked out) and their thresholds
+    // not copied: their LDS rows hold whatever an earlier stage left, and
+    // only the columns' validity bits keep them out of the counts) and
+    // their thresholds
     auto stage = [&](int64_t j, int b) {
 #pragma unroll
         for (int g = 0; g < BL_USERS / 64; ++g) {
@@ -549,11 +562,13 @@ void k_bound_lds(BoundArgs a) {
     __syncthreads();
     int64_t npairs = 0;  // statistics: users of this workgroup's stages
     // products of the last column block not counted yet (from the previous
-    // stage) and their thresholds; none at first
+    // stage), their thresholds and the validity of their user column (none
+    // at first)
     f32x16 pc[TI];
 #pragma unroll
     for (int t = 0; t < TI; ++t) pc[t] = f32x16{0};
-    float tprev = INFINITY;
+    float tprev = 0.0f;
+    int vprev = 0;
     for (; j < nblk; j += a.nsplit) {
         const int64_t nx = j + a.nsplit;
         if (nx < nblk) stage(nx, buf ^ 1);  // the other buffer was last read before the barrier
@@ -564,12 +579,13 @@ void k_bound_lds(BoundArgs a) {
 #pragma unroll
         for (int cb = 0; cb < BL_USERS / 32; ++cb) {
             const int ul = 32 * cb + col;
-            const bool ok = j * BL_USERS + ul < ulen;
-            // read for every lane (stale past the prefix, then replaced), so
-            // that the block has no branch and the products and counts below
-            // can interleave
-            const float tv = float_pred(tsh[buf][ul] - a.abs_slack);
-            const float tl = ok ? tv : INFINITY;
+            // a column past the prefix counts nothing, whatever its LDS row
+            // and threshold hold (explicit validity, not a masking value)
+            const int vm = (j * BL_USERS + ul < ulen) ? 1 : 0;
+            // read for every lane (stale past the prefix, and then not
+            // counted), so that the block has no branch and the products and
+            // counts below can interleave
+            const float tl = float_pred(tsh[buf][ul] - a.abs_slack);
             f32x16 nc[TI];
 #pragma unroll
             for (int t = 0; t < TI; ++t) nc[t] = f32x16{0};
@@ -587,7 +603,7 @@ void k_bound_lds(BoundArgs a) {
 #pragma unroll
             for (int t = 0; t < TI; ++t)
 #pragma unroll
-                for (int i = 0; i < 16; ++i) cnt[t][i] += (pc[t][i] >= tprev) ? 1 : 0;
+                for (int i = 0; i < 16; ++i) cnt[t][i] += (pc[t][i] >= tprev) ? vprev : 0;
 #pragma unroll
             for (int g = 0; g < 3 * KS * TI; ++g) {
                 __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one product
@@ -596,6 +612,7 @@ void k_bound_lds(BoundArgs a) {
 #pragma unroll
             for (int t = 0; t < TI; ++t) pc[t] = nc[t];
             tprev = tl;
+            vprev = vm;
         }
         // the counts are taken before the barrier (not moved past it)
 #pragma unroll
@@ -610,7 +627,7 @@ void k_bound_lds(BoundArgs a) {
 #pragma unroll
     for (int t = 0; t < TI; ++t)
 #pragma unroll
-        for (int i = 0; i < 16; ++i) cnt[t][i] += (pc[t][i] >= tprev) ? 1 : 0;
+        for (int i = 0; i < 16; ++i) cnt[t][i] += (pc[t][i] >= tprev) ? vprev : 0;
 #pragma unroll
     for (int t = 0; t < TI; ++t)
 #pragma unroll
@@ -632,6 +649,7 @@ void launch_bound(const BoundArgs &a, hipStream_t st) {
     auto go = [&](auto ks) {
         constexpr int KS = decltype(ks)::value, BI = bound_items(KS);
         const unsigned g = (unsigned)((a.m + BI - 1) / BI * a.nsplit);
+        RMIPS_PROF(st, "k_bound");
         if constexpr (KS >= 3) k_bound_lds<KS><<<g, 64 * BLW, bound_lds_bytes(KS), st>>>(a);
         else k_bound<KS><<<g, 64 * BW, 0, st>>>(a);
     };
@@ -683,6 +701,7 @@ __global__ __launch_bounds__(256) void k_colsum(const int32_t *__restrict__ part
 
 void launch_colsum(const int32_t *partial, int nsplit, int64_t cols, int32_t *out,
                    hipStream_t st) {
+    RMIPS_PROF(st, "k_colsum");
     k_colsum<<<(unsigned)((cols + 15) / 16), 256, 0, st>>>(partial, nsplit, cols, out);
 }
 
@@ -702,6 +721,7 @@ __global__ void k_visit_keys(const int32_t *__restrict__ us, const int32_t *__re
 
 void launch_visit_keys(const int32_t *uscore, const int32_t *inv, int64_t m, uint32_t *key,
                        int32_t *val, int32_t *status, hipStream_t st) {
+    RMIPS_PROF(st, "k_visit_keys");
     k_visit_keys<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(uscore, inv, m, key, val, status);
 }
 
@@ -713,6 +733,7 @@ __global__ void k_gather_i32(const int32_t *__restrict__ src, const int32_t *__r
 
 void launch_gather_i32(const int32_t *src, const int32_t *idx, int64_t n, int32_t *dst,
                        hipStream_t st) {
+    RMIPS_PROF(st, "k_gather_i32");
     k_gather_i32<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(src, idx, n, dst);
 }
 
@@ -731,6 +752,7 @@ __global__ void k_gather3_i32(const int32_t *__restrict__ a, const int32_t *__re
 void launch_gather3_i32(const int32_t *a, const int32_t *b, const int32_t *c,
                         const int32_t *idx, int64_t n, int32_t *da, int32_t *db, int32_t *dc,
                         hipStream_t st) {
+    RMIPS_PROF(st, "k_gather3_i32");
     k_gather3_i32<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(a, b, c, idx, n, da, db, dc);
 }
 
@@ -791,6 +813,7 @@ __global__ __launch_bounds__(1024) void k_topn_merge(const int32_t *__restrict__
 
 void launch_topn_merge(const int32_t *scores, int64_t nb, const int32_t *batch_ids, int N,
                        uint64_t *top, int32_t *status, hipStream_t st) {
+    RMIPS_PROF(st, "k_topn_merge");
     k_topn_merge<<<1, 1024, 0, st>>>(scores, nb, batch_ids, N, top, status);
 }
 

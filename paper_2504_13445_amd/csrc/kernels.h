@@ -6,6 +6,27 @@
 
 namespace rmips {
 
+// ------------------------------------------------------------ profiling
+// While a context's profiling is on, each kernel launch records a HIP event
+// on its stream before and after itself (a ProfScope around the launch); the
+// durations are summed per kernel name once the stream has been waited for.
+// With profiling off a scope costs one thread-local load.
+struct ProfRecorder;
+extern thread_local ProfRecorder *g_prof;  // set by a C-ABI call while it enqueues
+void prof_begin(hipStream_t st, const char *name);
+void prof_end(hipStream_t st);
+struct ProfScope {
+    hipStream_t st;
+    bool on;
+    ProfScope(hipStream_t s, const char *name) : st(s), on(g_prof != nullptr) {
+        if (on) prof_begin(s, name);
+    }
+    ~ProfScope() {
+        if (on) prof_end(st);
+    }
+};
+#define RMIPS_PROF(st, name) ::rmips::ProfScope rmips_prof_scope_(st, name)
+
 // ----------------------------------------------------------------- sort
 size_t radix_sort_scratch_bytes(int64_t n);
 // stable ascending sort by the key bits [lo_bit, hi_bit); the bits above
@@ -110,9 +131,11 @@ struct ThreshArgs {
     int32_t *rlist; int32_t *rcnt;                   // out: users to screen again
     int32_t *flist; int32_t *fcnt;                   // out: users for the exact fallback
     // statistics (may be NULL), spread over CSTAT_SLOTS addresses:
-    // pairs[slot] screened pairs; cstats[slot][4] = candidates, rechecked,
-    // fallback users, refined users
+    // pairs[slot] pairs screened by the main pass, rpairs[slot] by the
+    // refinement passes; cstats[slot][4] = candidates, rechecked, fallback
+    // users, refined users
     unsigned long long *pairs;
+    unsigned long long *rpairs;
     unsigned long long *cstats;
     hipEvent_t ev0, ev1;           // recorded around the first screening pass (may be NULL)
 };

@@ -45,6 +45,7 @@ __global__ __launch_bounds__(256) void k_rows_prep(const float *__restrict__ X, 
 void launch_rows_prep(const float *X, int64_t rows, int d, int D, float *Xpad, float *norm,
                       uint32_t *key, int32_t *val, int *flag, hipStream_t st) {
     if (rows <= 0) return;
+    RMIPS_PROF(st, "k_rows_prep");
     k_rows_prep<<<(unsigned)((rows + 3) / 4), 256, 0, st>>>(X, rows, d, D, Xpad, norm, key,
                                                             val, flag);
 }
@@ -52,10 +53,18 @@ void launch_rows_prep(const float *X, int64_t rows, int d, int D, float *Xpad, f
 // Padded, quantized copy of rows, 64 rows per block (wave w takes rows w,
 // w+4, ...).  Row r of the output is row order[r] of X (identity if NULL);
 // rows past `rows` are zero.  Rows of a group share one power-of-two scale
-// s (FP8: the smallest with max |x_i| / s <= 448; FP32 and BF16: 1).  Per
-// row: N = ||x||, Nh = ||xq||, R = ||x - xq|| (FP64 sums, rounded up to
-// FP32), sc = s; the largest R/N of the rows goes to *rmax (a monotone
-// atomic maximum of non-negative floats).
+// s (FP8: the smallest with max |x_i| / s <= 448, but at least 2^-63 so
+// that 1/s and the product of two scales' reciprocals stay finite; FP32
+// and BF16: 1).  Per row: N = ||x||, Nh = ||xq||, R = ||x - xq|| (FP64
+// sums, rounded up to FP32), sc = s; the largest R/N of the rows goes to
+// *rmax (a monotone atomic maximum of non-negative floats).
+//
+// Subnormal operands: the matrix cores may flush them to zero, so the
+// copy never holds one.  An FP32 or BF16 value below 2^-126 in magnitude,
+// and an e4m3 code in the format's subnormal range (scaled magnitude below
+// 2^-6), is stored as zero and its whole value counts in R.  The error
+// bound, which takes the quantisation error from R by Cauchy-Schwarz, then
+// holds whatever the hardware does with subnormal inputs.
 template <int PREC>
 __global__ __launch_bounds__(256) void k_quant(const float *__restrict__ X,
                                                const int32_t *__restrict__ order, int64_t rows,
@@ -138,6 +147,7 @@ __global__ __launch_bounds__(256) void k_quant(const float *__restrict__ X,
                     frexpf(m / 448.0f, &e);  // m/448 = f * 2^e, f in [0.5, 1)
                     s = ldexpf(1.0f, e);
                     if (m / ldexpf(1.0f, e - 1) <= 448.0f) s = ldexpf(1.0f, e - 1);
+                    s = fmaxf(s, 0x1p-63f);
                 }
             }
             sc4[jj] = s;
@@ -152,15 +162,25 @@ __global__ __launch_bounds__(256) void k_quant(const float *__restrict__ X,
                 if (c < D) {
                     const float t = v[j][q];
                     float qv;
+                    // (values below 2^-126 are zero in the copy)
+                    const bool sub = fabsf(t) < 0x1p-126f;
                     if (PREC == PREC_FP32) {
-                        qv = t;
-                        if (live) reinterpret_cast<float *>(Xq)[r * D + fp32_slot(c, d, D)] = t;
+                        qv = sub ? 0.0f : t;
+                        if (live) reinterpret_cast<float *>(Xq)[r * D + fp32_slot(c, d, D)] = qv;
                     } else if (PREC == PREC_BF16) {
-                        const uint16_t h = to_bf16(t, qv);
+                        uint16_t h = to_bf16(t, qv);
+                        if (sub) {
+                            h = 0;
+                            qv = 0.0f;
+                        }
                         if (live) reinterpret_cast<uint16_t *>(Xq)[r * D + c] = h;
                     } else {
                         float yq;
-                        const uint8_t b8 = to_e4m3(t * inv, yq);
+                        uint8_t b8 = to_e4m3(t * inv, yq);
+                        if ((b8 & 0x78u) == 0u) {  // zero or an e4m3 subnormal code
+                            b8 = 0;
+                            yq = 0.0f;
+                        }
                         if (live) Xq[r * D + c] = b8;
                         qv = yq * s;
                     }
@@ -176,10 +196,8 @@ __global__ __launch_bounds__(256) void k_quant(const float *__restrict__ X,
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj) {
                 sx[jj] += __shfl_xor(sx[jj], o);
-                if (PREC != PREC_FP32) {
-                    sq[jj] += __shfl_xor(sq[jj], o);
-                    sr[jj] += __shfl_xor(sr[jj], o);
-                }
+                sq[jj] += __shfl_xor(sq[jj], o);
+                sr[jj] += __shfl_xor(sr[jj], o);
             }
         if (lane == 0) {
 #pragma unroll
@@ -188,10 +206,11 @@ __global__ __launch_bounds__(256) void k_quant(const float *__restrict__ X,
                 if (r >= rows_pad) continue;
                 const double up = 1.0 + 0x1p-40;
                 const float nx = __double2float_ru(sqrt(sx[jj]) * up);
-                const float rr = (PREC == PREC_FP32) ? 0.0f : __double2float_ru(sqrt(sr[jj]) * up);
+                // (FP32: R is zero unless the row holds subnormal values)
+                const float rr = __double2float_ru(sqrt(sr[jj]) * up);
                 if (!(nx <= 0x1p60f)) *flag = 1;
                 N[r] = nx;
-                Nh[r] = (PREC == PREC_FP32) ? nx : __double2float_ru(sqrt(sq[jj]) * up);
+                Nh[r] = __double2float_ru(sqrt(sq[jj]) * up);
                 R[r] = rr;
                 sc[r] = sc4[jj];
                 if (nx > 0.0f && rr > 0.0f)
@@ -216,6 +235,7 @@ void launch_quant(int prec, const float *X, const int32_t *order, int64_t rows,
                   float *R, float *sc, unsigned int *rmax, int *flag, hipStream_t st) {
     const unsigned g = (unsigned)((rows_pad + 63) / 64);
     uint8_t *q = reinterpret_cast<uint8_t *>(Xq);
+    RMIPS_PROF(st, "k_quant");
     if (prec == PREC_FP32)
         k_quant<PREC_FP32><<<g, 256, 0, st>>>(X, order, rows, rows_pad, d, D, group, q, N, Nh, R,
                                               sc, rmax, flag);
@@ -246,6 +266,7 @@ __global__ void k_tile_max(const float *__restrict__ Nh, const float *__restrict
 
 void launch_tile_max(const float *Nh, const float *R, int ntiles, float *tmax_nh, float *tmax_r,
                      hipStream_t st) {
+    RMIPS_PROF(st, "k_tile_max");
     k_tile_max<<<(unsigned)((ntiles + 3) / 4), 256, 0, st>>>(Nh, R, ntiles, tmax_nh, tmax_r);
 }
 
@@ -268,6 +289,7 @@ __global__ void k_gather_rows(const float *__restrict__ P, const int32_t *__rest
 void launch_gather_rows(const float *P, const int32_t *perm, const float *norm_by_id,
                         int64_t m, int64_t rows_pad, int d, int D, float *Pk, float *Np,
                         hipStream_t st) {
+    RMIPS_PROF(st, "k_gather_rows");
     k_gather_rows<<<(unsigned)((rows_pad + 3) / 4), 256, 0, st>>>(P, perm, norm_by_id, m,
                                                                   rows_pad, d, D, Pk, Np);
 }
@@ -279,6 +301,7 @@ __global__ void k_invert_perm(const int32_t *__restrict__ perm, int64_t m,
 }
 
 void launch_invert_perm(const int32_t *perm, int64_t m, int32_t *inv, hipStream_t st) {
+    RMIPS_PROF(st, "k_invert_perm");
     k_invert_perm<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(perm, m, inv);
 }
 
@@ -307,6 +330,7 @@ __global__ void k_user_side(const double *__restrict__ tau, const int32_t *__res
 void launch_user_side(const double *tau, const int32_t *tau_id, const float *Nu,
                       const float *Nhu, const float *Ru, const float *su,
                       const int32_t *order, int64_t n, float c2, UserSide out, hipStream_t st) {
+    RMIPS_PROF(st, "k_user_side");
     k_user_side<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(tau, tau_id, Nu, Nhu, Ru, su, order,
                                                              n, c2, out);
 }
@@ -326,6 +350,7 @@ __global__ void k_rho_keys(const double *__restrict__ tau, const float *__restri
 
 void launch_rho_keys(const double *tau, const float *Nu, int64_t n, uint32_t *key,
                      int32_t *val, hipStream_t st) {
+    RMIPS_PROF(st, "k_rho_keys");
     k_rho_keys<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(tau, Nu, n, key, val);
 }
 
@@ -342,6 +367,7 @@ void launch_gather_padded(const void *X, const int32_t *order, int64_t rows, int
                           void *Y, hipStream_t st) {
     const int W16 = row_bytes / 16;
     int64_t tot = rows * W16;
+    RMIPS_PROF(st, "k_gather_padded");
     k_gather_padded<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(
         reinterpret_cast<const uint4 *>(X), order, rows, W16, reinterpret_cast<uint4 *>(Y));
 }
@@ -368,6 +394,7 @@ __global__ void k_cs_prefix(const uint32_t *__restrict__ keys, int64_t n,
 
 void launch_cs_prefix(const uint32_t *rho_sorted_keys, int64_t n, const float *norm,
                       int64_t m, int lo_bit, int32_t *cs, hipStream_t st) {
+    RMIPS_PROF(st, "k_cs_prefix");
     k_cs_prefix<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(rho_sorted_keys, n, norm, m, lo_bit,
                                                              cs);
 }
@@ -428,7 +455,11 @@ size_t gram_scratch_bytes(int d) { return (size_t)GRAM_SLICES * d * d * sizeof(d
 void launch_gram(const float *X, int64_t ns, int64_t stride, int d, double *G, double *scratch,
                  hipStream_t st) {
     dim3 g((d + 31) / 32, (d + 31) / 32, GRAM_SLICES);
-    k_gram<<<g, 256, 0, st>>>(X, ns, stride, d, scratch);
+    {
+        RMIPS_PROF(st, "k_gram");
+        k_gram<<<g, 256, 0, st>>>(X, ns, stride, d, scratch);
+    }
+    RMIPS_PROF(st, "k_gram_sum");
     k_gram_sum<<<(d * d + 255) / 256, 256, 0, st>>>(scratch, d * d, G);
 }
 
@@ -610,6 +641,7 @@ void launch_rotate_aug(const float *X, const int32_t *order, int64_t rows, int64
                        int d, const double *W, int dp, int ka, float scale, uint4 *out,
                        hipStream_t st) {
     if (W == nullptr) {  // the identity, dp = d <= DP_MAX
+        RMIPS_PROF(st, "k_aug_ident");
         k_aug_ident<<<(unsigned)((rows_pad + 255) / 256), 256, 0, st>>>(X, order, rows, rows_pad,
                                                                        d, ka, scale, out);
         return;
@@ -618,6 +650,7 @@ void launch_rotate_aug(const float *X, const int32_t *order, int64_t rows, int64
     // unit (its LDS), 16 rows per wave at a time
     int64_t g = (rows_pad + 16 * ROT_WAVES - 1) / (16 * ROT_WAVES);
     if (g > 256) g = 256;
+    RMIPS_PROF(st, "k_rotate_aug");
     k_rotate_aug<<<(unsigned)g, 64 * ROT_WAVES, rotate_lds_bytes(d), st>>>(
         X, order, rows, rows_pad, d, W, dp, ka, scale, out);
 }

@@ -9,12 +9,82 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "common.h"
 #include "kernels.h"
 
 using namespace rmips;
+
+namespace rmips {
+
+// Per-launch timing: a pool of HIP events reused from call to call, the
+// launches recorded since the stream was last waited for, and the totals per
+// kernel name (in the order the names first appeared).
+struct ProfRecorder {
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    struct Rec { const char *name; size_t b, e; };
+    std::vector<Rec> recs;
+    std::vector<size_t> open;
+    std::vector<std::pair<std::string, std::pair<int64_t, double>>> totals;
+
+    size_t take() {
+        if (used == pool.size()) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) e = nullptr;
+            pool.push_back(e);
+        }
+        return used++;
+    }
+    // the stream must be idle: every recorded event has completed
+    void resolve() {
+        for (const Rec &r : recs) {
+            float ms = 0.0f;
+            if (pool[r.b] && pool[r.e] &&
+                hipEventElapsedTime(&ms, pool[r.b], pool[r.e]) != hipSuccess)
+                ms = 0.0f;
+            auto it = std::find_if(totals.begin(), totals.end(),
+                                   [&](const auto &t) { return t.first == r.name; });
+            if (it == totals.end()) {
+                totals.push_back({r.name, {0, 0.0}});
+                it = totals.end() - 1;
+            }
+            it->second.first += 1;
+            it->second.second += ms;
+        }
+        recs.clear();
+        open.clear();
+        used = 0;
+    }
+    ~ProfRecorder() {
+        for (hipEvent_t e : pool)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+thread_local ProfRecorder *g_prof = nullptr;
+
+void prof_begin(hipStream_t st, const char *name) {
+    ProfRecorder *p = g_prof;
+    const size_t b = p->take();
+    if (p->pool[b]) (void)hipEventRecord(p->pool[b], st);
+    p->recs.push_back({name, b, b});
+    p->open.push_back(p->recs.size() - 1);
+}
+
+void prof_end(hipStream_t st) {
+    ProfRecorder *p = g_prof;
+    const size_t e = p->take();
+    if (p->pool[e]) (void)hipEventRecord(p->pool[e], st);
+    if (!p->open.empty()) {
+        p->recs[p->open.back()].e = e;
+        p->open.pop_back();
+    }
+}
+
+}  // namespace rmips
 
 struct rmips_ctx {
     int device = 0;
@@ -26,7 +96,24 @@ struct rmips_ctx {
     int32_t *h_status = nullptr;  // pinned, small
     int32_t *h_vis = nullptr;     // pinned: visit-order bounds and prefixes, top-N
     int64_t h_vis_cap = 0;        // its size in int32 entries
+    // input checks of the calls that return without waiting: each copies
+    // its device flag into the next pinned slot h_status[1 + i]; rmips_sync
+    // reads them once the stream is done
+    int pending = 0;
+    // per-launch timing (rmips_set_profiling)
+    bool prof_on = false;
+    ProfRecorder prof;
 };
+
+namespace {
+// Points the launches of a C-ABI call at the context's recorder while the
+// call enqueues (when profiling is on).
+struct ProfGuard {
+    explicit ProfGuard(rmips_ctx *c) { g_prof = (c && c->prof_on) ? &c->prof : nullptr; }
+    ~ProfGuard() { g_prof = nullptr; }
+};
+}  // namespace
+constexpr int PENDING_SLOTS = 63;
 
 namespace {
 
@@ -165,11 +252,36 @@ void thresh_plan(int prec, int64_t n, int64_t m, int d, int k, int cap_override,
     L.rmax = reinterpret_cast<unsigned int *>(L.bad + 32);
 }
 
-rmips_status check_bad(rmips_ctx *ctx, int *bad) {
-    HIPTRY(hipMemcpyAsync(ctx->h_status, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+constexpr const char *BAD_INPUT = "input holds a NaN/Inf or a vector norm above 2^60";
+
+rmips_status sync_pending(rmips_ctx *ctx) {
     HIPTRY(hipStreamSynchronize(ctx->stream));
-    if (ctx->h_status[0] != 0)
-        return fail(ctx, RMIPS_ENONFINITE, "input holds a NaN/Inf or a vector norm above 2^60");
+    ctx->prof.resolve();
+    bool bad = false;
+    for (int i = 0; i < ctx->pending; ++i) bad |= ctx->h_status[1 + i] != 0;
+    ctx->pending = 0;
+    if (bad) return fail(ctx, RMIPS_ENONFINITE, BAD_INPUT);
+    return RMIPS_OK;
+}
+
+// The input check of a call that returns without waiting: the device flag
+// is copied into a pinned slot in stream order and read by rmips_sync (or
+// here, when every slot is taken, after waiting for the earlier ones).
+rmips_status defer_check(rmips_ctx *ctx, const int *bad) {
+    if (ctx->pending == PENDING_SLOTS) {
+        rmips_status s = sync_pending(ctx);
+        if (s != RMIPS_OK) {
+            // an earlier call's inputs were bad: report it now, and keep this
+            // call's check for later
+            HIPTRY(hipMemcpyAsync(ctx->h_status + 1, bad, sizeof(int), hipMemcpyDeviceToHost,
+                                  ctx->stream));
+            ctx->pending = 1;
+            return s;
+        }
+    }
+    HIPTRY(hipMemcpyAsync(ctx->h_status + 1 + ctx->pending, bad, sizeof(int),
+                          hipMemcpyDeviceToHost, ctx->stream));
+    ++ctx->pending;
     return RMIPS_OK;
 }
 
@@ -178,9 +290,10 @@ rmips_status check_bad(rmips_ctx *ctx, int *bad) {
 rmips_status run_thresholds(rmips_ctx *ctx, const float *U, int64_t n, const float *P,
                             int64_t m, int d, int k, ThreshLayout &L, double *tau,
                             int32_t *tau_id, int32_t *topk,
-                            unsigned long long *pairs = nullptr, hipEvent_t ev0 = nullptr,
+                            unsigned long long *pairs = nullptr,
+                            unsigned long long *rpairs = nullptr, hipEvent_t ev0 = nullptr,
                             hipEvent_t ev1 = nullptr, unsigned long long *cstats = nullptr,
-                            bool check_now = true, bool clear_flags = true) {
+                            bool clear_flags = true) {
     hipStream_t st = ctx->stream;
     // bad and rmax, 32 words apart in every layout (a caller may have
     // cleared them already)
@@ -193,12 +306,8 @@ rmips_status run_thresholds(rmips_ctx *ctx, const float *U, int64_t n, const flo
     launch_quant(L.prec, U, nullptr, n, n, d, L.D, 1, L.Uq, L.Nu, L.Nhu, L.Ru, L.su, nullptr,
                  L.bad, st);
     HIPTRY(hipGetLastError());
-    if (check_now) {
-        // (otherwise the caller reads L.bad at its next synchronisation;
-        // the kernels below stay in bounds whatever the values)
-        rmips_status s = check_bad(ctx, L.bad);
-        if (s != RMIPS_OK) return s;
-    }
+    // (the caller reads L.bad later, in stream order; the kernels below stay
+    // in bounds whatever the values)
 
     const ErrConst ec = err_const(L.D, d);
     ThreshArgs a{};
@@ -214,7 +323,7 @@ rmips_status run_thresholds(rmips_ctx *ctx, const float *U, int64_t n, const flo
     a.lists = L.lists; a.lcnt = L.lcnt; a.refine = 2; a.Luse = L.Luse;
     a.ukey = L.ukey; a.uord = L.uord; a.usort = L.usort; a.nall = L.nall;
     a.tau = tau; a.tau_id = tau_id; a.topk = topk;
-    a.pairs = pairs; a.ev0 = ev0; a.ev1 = ev1; a.cstats = cstats;
+    a.pairs = pairs; a.rpairs = rpairs; a.ev0 = ev0; a.ev1 = ev1; a.cstats = cstats;
     if (thresh_screen_lds(L.prec, L.D) > 160 * 1024 || (size_t)final_stride(L.cap * L.nsplit) * 24 > 150 * 1024)
         return fail(ctx, RMIPS_EUNSUPPORTED, "screening tile or candidate lists exceed LDS");
     launch_thresh(a, st);
@@ -287,10 +396,12 @@ void top_eigvecs(const std::vector<double> &G, int d, int dp, std::vector<double
 }
 
 // counters of rmips_topn (64-bit words): [0] stage (b) rechecks, [2] stage
-// (c) bound pairs, [8, 8 + CSTAT_SLOTS) stage (a) screened pairs,
-// [CTR_CS, CTR_CS + 4 * CSTAT_SLOTS) stage (a) candidate statistics
+// (c) bound pairs, [8, 8 + CSTAT_SLOTS) pairs screened by stage (a)'s main
+// pass, then by its refinement passes, [CTR_CS, CTR_CS + 4 * CSTAT_SLOTS)
+// stage (a) candidate statistics
 constexpr int CTR_PAIRS = 8;
-constexpr int CTR_CS = CTR_PAIRS + CSTAT_SLOTS;
+constexpr int CTR_RPAIRS = CTR_PAIRS + CSTAT_SLOTS;
+constexpr int CTR_CS = CTR_RPAIRS + CSTAT_SLOTS;
 constexpr int CTR_WORDS = CTR_CS + 4 * CSTAT_SLOTS;
 // block of a batch's results: status (64 words: the running top-N's in
 // [0, 2), stage (a)'s input flag in [RES_BAD], its largest R/N in
@@ -520,9 +631,12 @@ rmips_status rmips_thresholds(rmips_ctx *ctx, const float *U, int64_t n, const f
     thresh_plan(prec, n, m, d, k, ctx->cap_override, L, probe);
     if (ws_bytes < probe.off + 256) return fail(ctx, RMIPS_EWORKSPACE, "workspace too small");
     HIPTRY(hipSetDevice(ctx->device));
+    ProfGuard pguard(ctx);
     Carve cv(ws);
     thresh_plan(prec, n, m, d, k, ctx->cap_override, L, cv);
-    return run_thresholds(ctx, U, n, P, m, d, k, L, tau, tau_id, topk);
+    s = run_thresholds(ctx, U, n, P, m, d, k, L, tau, tau_id, topk);
+    if (s != RMIPS_OK) return s;
+    return defer_check(ctx, L.bad);
 }
 
 rmips_status rmips_scores(rmips_ctx *ctx, const float *U, int64_t n, const double *tau,
@@ -539,6 +653,7 @@ rmips_status rmips_scores(rmips_ctx *ctx, const float *U, int64_t n, const doubl
     if (ws_bytes < rmips_scores_workspace_size(n, nq, d, prec))
         return fail(ctx, RMIPS_EWORKSPACE, "workspace too small");
     HIPTRY(hipSetDevice(ctx->device));
+    ProfGuard pguard(ctx);
     hipStream_t st = ctx->stream;
     Carve cv(ws);
     ScoresLayout L;
@@ -549,10 +664,8 @@ rmips_status rmips_scores(rmips_ctx *ctx, const float *U, int64_t n, const doubl
     launch_quant(prec, Q, nullptr, nq, nq, d, L.D, 1, L.Qq, L.Nq, L.Nhq, L.Rq, L.sq, nullptr,
                  L.bad, st);
     HIPTRY(hipGetLastError());
-    {
-        rmips_status s = check_bad(ctx, L.bad);
-        if (s != RMIPS_OK) return s;
-    }
+    // (the input flag is read by rmips_sync; the kernels below stay in
+    // bounds whatever the values)
     const ErrConst ec = err_const(L.D, d);
     launch_user_side(tau, tau_id, L.Nu, L.Nhu, L.Ru, L.su, nullptr, n, ec.c2, L.us, st);
     CountArgs a{};
@@ -569,6 +682,37 @@ rmips_status rmips_scores(rmips_ctx *ctx, const float *U, int64_t n, const doubl
     launch_count(a, st);
     launch_colsum(L.partial, a.nsplit, nq, scores, st);
     HIPTRY(hipGetLastError());
+    return defer_check(ctx, L.bad);
+}
+
+rmips_status rmips_sync(rmips_ctx *ctx) {
+    if (!ctx) return RMIPS_EINVAL;
+    HIPTRY(hipSetDevice(ctx->device));
+    return sync_pending(ctx);
+}
+
+rmips_status rmips_set_profiling(rmips_ctx *ctx, int32_t on) {
+    if (!ctx) return RMIPS_EINVAL;
+    HIPTRY(hipSetDevice(ctx->device));
+    HIPTRY(hipStreamSynchronize(ctx->stream));
+    ctx->prof.resolve();
+    if (on) ctx->prof.totals.clear();
+    ctx->prof_on = on != 0;
+    return RMIPS_OK;
+}
+
+rmips_status rmips_profile_entry(rmips_ctx *ctx, int32_t i, char *name, int32_t name_cap,
+                                 int64_t *launches, double *ms_total) {
+    if (!ctx || !name || name_cap < 1 || !launches || !ms_total) return RMIPS_EINVAL;
+    HIPTRY(hipSetDevice(ctx->device));
+    HIPTRY(hipStreamSynchronize(ctx->stream));
+    ctx->prof.resolve();
+    if (i < 0 || (size_t)i >= ctx->prof.totals.size())
+        return fail(ctx, RMIPS_EINVAL, "no such profile entry");
+    const auto &t = ctx->prof.totals[(size_t)i];
+    std::snprintf(name, (size_t)name_cap, "%s", t.first.c_str());
+    *launches = t.second.first;
+    *ms_total = t.second.second;
     return RMIPS_OK;
 }
 
@@ -591,6 +735,7 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
             return fail(ctx, RMIPS_EWORKSPACE, "workspace too small");
     }
     HIPTRY(hipSetDevice(ctx->device));
+    ProfGuard pguard(ctx);
     hipStream_t st = ctx->stream;
     Carve cv(ws);
     TopnLayout L;
@@ -628,7 +773,7 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     // ---- stage (a): exact thresholds (the input check is read at the
     // synchronisation before stage (b))
     s = run_thresholds(ctx, U, n, P, m, d, k, L.T, L.tau, L.tau_id, nullptr, ctr + CTR_PAIRS,
-                       ev[4], ev[5], ctr + CTR_CS, false, false);
+                       ctr + CTR_RPAIRS, ev[4], ev[5], ctr + CTR_CS, false);
     if (s != RMIPS_OK) return s;
     HIPTRY(hipEventRecord(ev[1], st));
     if (rotate) {
@@ -751,9 +896,7 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
             ms_count_k += t;
         }
         if (first) {
-            if (h_st[RES_BAD] != 0)
-                return fail(ctx, RMIPS_ENONFINITE,
-                            "input holds a NaN/Inf or a vector norm above 2^60");
+            if (h_st[RES_BAD] != 0) return fail(ctx, RMIPS_ENONFINITE, BAD_INPUT);
             ulen = 0;  // the batch's own user count, for the statistics
             for (int64_t r = r0; r < r1; ++r) ulen = std::max<int64_t>(ulen, h_cs[r]);
         }
@@ -771,6 +914,7 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
         while (e < m && h_us[e] >= tauN) ++e;
         bsz = std::min<int64_t>(e - r0, bmax);
     }
+    ctx->prof.resolve();  // (the stream is idle after the last batch)
     if (batches == 0) return fail(ctx, RMIPS_EDEVICE, "no item batch was scored");
     if (h_st[1] != N) return fail(ctx, RMIPS_EDEVICE, "top-N list incomplete");
     for (int i = 0; i < N; ++i) {
@@ -782,19 +926,22 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
         stats->visited_items = visited;
         stats->batches = batches;
         const int64_t *h = h_ctr;
-        int64_t tp = 0, cs[4] = {0, 0, 0, 0};
+        int64_t tp = 0, rp = 0, cs[4] = {0, 0, 0, 0};
         for (int i = 0; i < CSTAT_SLOTS; ++i) {
             tp += h[CTR_PAIRS + i];
+            rp += h[CTR_RPAIRS + i];
             for (int j = 0; j < 4; ++j) cs[j] += h[CTR_CS + 4 * i + j];
         }
         stats->cand_pairs = cs[1];
+        stats->cand_listed = cs[0];
         stats->overflow_users = cs[2];
         stats->refine_users = cs[3];
         stats->recheck_pairs = h[0];
         stats->thresh_pairs = tp;
+        stats->refine_pairs = rp;
         stats->bound_pairs = h[2];
         stats->count_pairs = screened;
-        stats->screened_pairs = screened + tp;
+        stats->screened_pairs = screened + tp + rp;
         stats->count_launches = launches;
         float t01 = 0, t12 = 0, t23 = 0, t03 = 0, tsc = 0, tbd = 0;
         (void)hipEventElapsedTime(&t01, ev[0], ev[1]);
@@ -834,6 +981,7 @@ rmips_status rmips_soft_fwd(rmips_ctx *ctx, const float *U, int64_t n, const flo
     rmips_status s = soft_common(ctx, U, n, tau, Q, nq, d, T, ws, ws_bytes);
     if (s != RMIPS_OK) return s;
     if (!S) return fail(ctx, RMIPS_EINVAL, "null pointer");
+    ProfGuard pguard(ctx);
     launch_soft(U, n, tau, Q, nq, d, T, nullptr, S, nullptr, ws, ctx->stream);
     HIPTRY(hipGetLastError());
     return RMIPS_OK;
@@ -845,6 +993,7 @@ rmips_status rmips_soft_bwd(rmips_ctx *ctx, const float *U, int64_t n, const flo
     rmips_status s = soft_common(ctx, U, n, tau, Q, nq, d, T, ws, ws_bytes);
     if (s != RMIPS_OK) return s;
     if (!dS || !dQ) return fail(ctx, RMIPS_EINVAL, "null pointer");
+    ProfGuard pguard(ctx);
     launch_soft(U, n, tau, Q, nq, d, T, dS, nullptr, dQ, ws, ctx->stream);
     HIPTRY(hipGetLastError());
     return RMIPS_OK;

@@ -276,17 +276,25 @@ void launch_soft(const float *U, int64_t n, const float *tau, const float *Q, in
     k_soft<B, C><<<g, 256, lds, st>>>(U, n, tau, Q, nq, d, invT, B ? nullptr : part,   \
                                       B ? part : nullptr)
     if (dQ) {
-        if (cpl == 1) RMIPS_SOFT(true, 1);
-        else if (cpl == 2) RMIPS_SOFT(true, 2);
-        else if (cpl == 3) RMIPS_SOFT(true, 3);
-        else RMIPS_SOFT(true, 4);
+        {
+            RMIPS_PROF(st, "k_soft/bwd");
+            if (cpl == 1) RMIPS_SOFT(true, 1);
+            else if (cpl == 2) RMIPS_SOFT(true, 2);
+            else if (cpl == 3) RMIPS_SOFT(true, 3);
+            else RMIPS_SOFT(true, 4);
+        }
+        RMIPS_PROF(st, "k_soft_reduce");
         k_soft_reduce<<<dim3((unsigned)nq, (unsigned)((d + 63) / 64)), 256, 0, st>>>(
             part, nsplit, nq, sd.Dg, d, dS, dQ, d);
     } else {
-        if (cpl == 1) RMIPS_SOFT(false, 1);
-        else if (cpl == 2) RMIPS_SOFT(false, 2);
-        else if (cpl == 3) RMIPS_SOFT(false, 3);
-        else RMIPS_SOFT(false, 4);
+        {
+            RMIPS_PROF(st, "k_soft/fwd");
+            if (cpl == 1) RMIPS_SOFT(false, 1);
+            else if (cpl == 2) RMIPS_SOFT(false, 2);
+            else if (cpl == 3) RMIPS_SOFT(false, 3);
+            else RMIPS_SOFT(false, 4);
+        }
+        RMIPS_PROF(st, "k_soft_reduce");
         k_soft_reduce<<<dim3((unsigned)nq, 1u), 256, 0, st>>>(part, nsplit, nq, 1, 1, nullptr, S,
                                                               1);
     }

@@ -265,7 +265,10 @@ hipError_t radix_sort_u32(uint32_t *keys, int32_t *vals, int64_t n, void *scratc
     int32_t *v1 = (int32_t *)carve((size_t)n * 4), *v2 = (int32_t *)carve((size_t)n * 4);
     uint32_t *tsum = (uint32_t *)carve(0);
     const int ntiles = (int)((total + SCAN_TILE - 1) / SCAN_TILE);
-    k_radix_hist<<<nblocks, SORT_THREADS, 0, st>>>(keys, n, lo_bit, nblocks, npass, counts);
+    {
+        RMIPS_PROF(st, "k_radix_hist");
+        k_radix_hist<<<nblocks, SORT_THREADS, 0, st>>>(keys, n, lo_bit, nblocks, npass, counts);
+    }
     // the passes run keys -> 1 -> 2 -> 1 ... and the last one writes keys
     const uint32_t *ks = keys;
     const int32_t *vs = vals;
@@ -276,9 +279,11 @@ hipError_t radix_sort_u32(uint32_t *keys, int32_t *vals, int64_t n, void *scratc
         int32_t *vd = last ? vals : ((q & 1) ? v2 : v1);
         uint32_t *cq = counts + q * total;
         if (!small) {
+            RMIPS_PROF(st, "k_scan");
             k_scan_reduce<<<ntiles, SORT_THREADS, 0, st>>>(cq, total, tsum);
             k_scan_down<<<ntiles, SORT_THREADS, 0, st>>>(cq, total, tsum);
         }
+        RMIPS_PROF(st, "k_radix_scatter");
         k_radix_scatter<<<nblocks, SORT_THREADS, 0, st>>>(
             ks, vs, kd, vd, n, shift, last ? -1 : shift + 8, nblocks, cq, cq + total);
         ks = kd;

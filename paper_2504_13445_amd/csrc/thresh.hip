@@ -774,7 +774,9 @@ __global__ __launch_bounds__(64 * FB_WAVES) void k_thresh_fallback(ThreshArgs a)
 }
 
 template <int PREC>
-void launch_screen(const ThreshArgs &a, int nch, dim3 g, size_t lds, hipStream_t st) {
+void launch_screen(const ThreshArgs &a, int nch, dim3 g, size_t lds, hipStream_t st,
+                   const char *name) {
+    RMIPS_PROF(st, name);
     with_nch<PREC>(nch, [&](auto n) {
         constexpr int NCH = decltype(n)::value;
         if (a.ulist) k_thresh_screen<PREC, NCH, true><<<g, 64 * screen_nw<true>(PREC, NCH), lds, st>>>(a);
@@ -822,10 +824,18 @@ void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
     const int64_t eblocks = std::min<int64_t>(
         (a0.n + 4 * (64 / EXACT_SLOTS) - 1) / (4 * (64 / EXACT_SLOTS)), 3 * 256);
     int32_t *LA = a0.lists, *LB = a0.lists + a0.n, *LF = a0.lists + 2 * a0.n;
-    auto screen = [&](const ThreshArgs &a, dim3 g) {
-        if (a.prec == PREC_FP32) launch_screen<PREC_FP32>(a, nch, g, lds, st);
-        else if (a.prec == PREC_BF16) launch_screen<PREC_BF16>(a, nch, g, lds, st);
-        else launch_screen<PREC_FP8>(a, nch, g, lds, st);
+    auto screen = [&](const ThreshArgs &a, dim3 g, const char *name) {
+        if (a.prec == PREC_FP32) launch_screen<PREC_FP32>(a, nch, g, lds, st, name);
+        else if (a.prec == PREC_BF16) launch_screen<PREC_BF16>(a, nch, g, lds, st, name);
+        else launch_screen<PREC_FP8>(a, nch, g, lds, st, name);
+    };
+    auto final = [&](const ThreshArgs &a, int capT, const char *nf, const char *ne) {
+        {
+            RMIPS_PROF(st, nf);
+            k_thresh_final<true><<<(unsigned)fblocks, 64 * fw, lds_fin, st>>>(a, capT, capP);
+        }
+        RMIPS_PROF(st, ne);
+        k_thresh_exact<true><<<(unsigned)eblocks, 256, 0, st>>>(a);
     };
     // bounds-only pass (the launch without a user list): every user's L0
     // from the first tiles (phase 1), in workgroups of its own size
@@ -835,10 +845,13 @@ void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
     b0.nsplit = 1;
     b0.pairs = nullptr;
     const int tu1 = 32 * screen_waves_p1(a0.prec, nch);
-    screen(b0, dim3((unsigned)((a0.n + tu1 - 1) / tu1), 1u));
+    screen(b0, dim3((unsigned)((a0.n + tu1 - 1) / tu1), 1u), "k_thresh_screen/bounds");
     // users in the order of their early-exit ratios, so that the users of a
     // workgroup stop their scans at about the same tile
-    k_exit_keys<<<(unsigned)((a0.n + 255) / 256), 256, 0, st>>>(a0, a0.ukey, a0.uord);
+    {
+        RMIPS_PROF(st, "k_exit_keys");
+        k_exit_keys<<<(unsigned)((a0.n + 255) / 256), 256, 0, st>>>(a0, a0.ukey, a0.uord);
+    }
     // a grouping only: the top 16 bits of the ratio (sign, exponent and 7
     // mantissa bits) are enough, ties stay in user order
     (void)radix_sort_u32(a0.ukey, a0.uord, a0.n, a0.usort, st, 16, 32);
@@ -851,10 +864,9 @@ void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
     a.flist = LF;
     a.fcnt = a0.lcnt + 2;
     if (a.ev0) (void)hipEventRecord(a.ev0, st);
-    screen(a, dim3((unsigned)ublocks, (unsigned)a.nsplit));
+    screen(a, dim3((unsigned)ublocks, (unsigned)a.nsplit), "k_thresh_screen/main");
     if (a.ev1) (void)hipEventRecord(a.ev1, st);
-    k_thresh_final<true><<<(unsigned)fblocks, 64 * fw, lds_fin, st>>>(a, capU, capP);
-    k_thresh_exact<true><<<(unsigned)eblocks, 256, 0, st>>>(a);
+    final(a, capU, "k_thresh_final/main", "k_thresh_exact/main");
     // refinement passes over the users whose lists overflowed: the same
     // per-user capacity in fewer, longer lists per split
     int nsr = capU / 64;
@@ -870,17 +882,18 @@ void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
         b.nsplit = nsr;
         b.cap = capU / nsr;
         b.t0tiles = 0;
+        b.pairs = a0.rpairs;
         // one resident round (one screening workgroup per CU): the lists
         // are usually empty, and the workgroups loop over long ones
         const int64_t gx = ublocks < 256 / nsr ? ublocks : 256 / nsr;
-        screen(b, dim3((unsigned)gx, (unsigned)nsr));
-        k_thresh_final<true><<<(unsigned)fblocks, 64 * fw, lds_fin, st>>>(b, b.nsplit * b.cap, capP);
-        k_thresh_exact<true><<<(unsigned)eblocks, 256, 0, st>>>(b);
+        screen(b, dim3((unsigned)gx, (unsigned)nsr), "k_thresh_screen/refine");
+        final(b, b.nsplit * b.cap, "k_thresh_final/refine", "k_thresh_exact/refine");
     }
     int64_t fb = (a0.n + FB_WAVES - 1) / FB_WAVES;
     if (fb > 1024) fb = 1024;
     a.flist = LF;
     a.fcnt = a0.lcnt + 2;
+    RMIPS_PROF(st, "k_thresh_fallback");
     k_thresh_fallback<<<(unsigned)fb, 64 * FB_WAVES, 0, st>>>(a);
 }
 

@@ -4,8 +4,14 @@ The FP64 oracle checks tau and S_k(u) bit for bit on a seeded 1% user
 subsample; properties that hold at any size check the rest: every user's
 S_k has k items (sum of scores over all items = n k), the pruned top-N
 equals the top-N of the exact scores of all items (the unpruned method),
-and the integer outputs agree across screening precisions.
+and the integer outputs agree across screening precisions.  On the
+500,000-user workload the score of every item and the top-N are also
+compared with the full oracle, stored by tests/golden/make_bf16_workload_scores.py.
 """
+import hashlib
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -70,3 +76,30 @@ def test_bf16_workload_500k_users():
 
 def test_fp8_workload_2m_users():
     _run_workload(3, ["fp8", "bf16"])
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp32", "fp8"])
+def test_bf16_workload_full_oracle(golden_dir, prec):
+    """Score of each of the 50,000 items and the top-50 of the 500,000-user
+    workload, element by element against the full FP64 oracle (Def. 2 and
+    Def. 3; expected values written by the oracle alone)."""
+    import paper_2504_13445_amd as rm
+    g = json.load(open(os.path.join(golden_dir, "bf16_workload_scores.json")))
+    cfg = synth.CONFIGS[2]
+    print("[case] full-oracle scores", cfg.name, prec, flush=True)
+    U, P = synth.make_config(cfg)
+    assert hashlib.sha256(U.tobytes()).hexdigest() == g["sha256_U"], "generator changed"
+    assert hashlib.sha256(P.tobytes()).hexdigest() == g["sha256_P"], "generator changed"
+    n, m, k, N = U.shape[0], P.shape[0], g["k"], g["N"]
+    ref = np.array(g["scores"], np.int64)
+    Ug = torch.from_numpy(U).to(_dev())
+    Pg = torch.from_numpy(P).to(_dev())
+    del U, P
+    tau, tid = rm.thresholds(Ug, Pg, k, prec=prec)
+    sc = rm.scores(Ug, tau, tid, Pg, torch.arange(m, dtype=torch.int32, device=_dev()),
+                   prec=prec).cpu().numpy().astype(np.int64)
+    bad = np.nonzero(sc != ref)[0]
+    assert bad.size == 0, (prec, bad[:10], sc[bad[:10]], ref[bad[:10]])
+    ids, tsc, st = rm.topn(Ug, Pg, k, N, prec=prec)
+    print("stats", prec, st, flush=True)
+    assert ids.tolist() == g["top_ids"] and tsc.tolist() == g["top_scores"], prec

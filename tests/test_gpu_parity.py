@@ -112,12 +112,71 @@ def test_thresholds_onehot_golden(golden_dir):
 
 @pytest.mark.parametrize("prec", PRECS)
 def test_thresholds_tiny_magnitudes(prec):
-    # entries in the FP32 subnormal range: the screen's bound must hold
-    _say("thresholds subnormal-range inputs", prec)
+    # entries of about 1e-20 (normal FP32 values) whose products, about
+    # 1e-40, fall into the FP32 subnormal range: the absolute term of the
+    # screen's bound must cover the rounding there
+    _say("thresholds inputs with subnormal products", prec)
     rng = np.random.default_rng(8)
     U = (synth.isotropic(rng, 200, 12, 0.3).astype(np.float64) * 1e-20).astype(np.float32)
     P = (synth.isotropic(rng, 300, 12, 0.3).astype(np.float64) * 1e-20).astype(np.float32)
     _check_thresholds(U, P, 5, prec=prec)
+
+
+# ------------------------------------------------------------ subnormal operands
+def _subnormal(rng, shape):
+    """FP32 subnormal values: magnitudes log-uniform in [1e-45, 1e-38]
+    (1e-45 rounds to the smallest subnormal, 2^-149), random signs."""
+    mag = 10.0 ** rng.uniform(-45.0, -38.0, size=shape)
+    x = (mag * rng.choice([-1.0, 1.0], size=shape)).astype(np.float32)
+    x[x == 0] = np.float32(2.0 ** -149)
+    assert (np.abs(x) < np.float32(2.0 ** -126)).all()
+    return x
+
+
+def _subnormal_case(kind):
+    rng = np.random.default_rng({"all": 11, "users": 12, "mixed": 13}[kind])
+    d = 12
+    if kind == "all":            # every entry of every vector subnormal
+        return _subnormal(rng, (150, d)), _subnormal(rng, (200, d))
+    if kind == "users":
+        # all-subnormal user rows beside ordinary ones, against unit-norm
+        # items and items of norm about 2^40 (products up to ~1e-26, far
+        # above the bound's absolute term: only the residual term of the
+        # subnormal rows can cover them)
+        U = synth.isotropic(rng, 160, d, 0.3)
+        U[::2] = _subnormal(rng, (80, d))
+        P = synth.isotropic(rng, 240, d, 0.5)
+        P[::3] = (P[::3].astype(np.float64) * 2.0 ** 40).astype(np.float32)
+        return U, P
+    # mixed rows: a third of the entries subnormal, and items that differ
+    # from an earlier item in one subnormal entry only
+    U = synth.isotropic(rng, 200, d, 0.3)
+    P = synth.isotropic(rng, 260, d, 0.5)
+    for X in (U, P):
+        mask = rng.random(X.shape) < 1.0 / 3.0
+        X[mask] = _subnormal(rng, (int(mask.sum()),))
+    P[200:230] = P[0:30]
+    P[200:230, 5] = _subnormal(rng, (30,))
+    return U, P
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("kind", ["all", "users", "mixed"])
+def test_subnormal_operands(kind, prec):
+    """Subnormal inputs are zero in the screening copies and counted in the
+    residual R, so thresholds, scores and top-N stay exact whatever the
+    matrix cores do with subnormal operands."""
+    _say("subnormal operands", kind, prec)
+    U, P = _subnormal_case(kind)
+    m = P.shape[0]
+    for k in (1, 5):
+        t, j, tk = _check_thresholds(U, P, k, prec=prec)
+        rm = _rm()
+        s = rm.scores(_g(U), _g(t), _g(j), _g(P),
+                      torch.arange(m, dtype=torch.int32, device=_dev()), prec=prec)
+        h = orc.histogram_scores(tk, m)
+        assert np.array_equal(s.cpu().numpy(), h), kind
+        _check_topn(U, P, k, 10, topk_ref=tk, prec=prec)
 
 
 # ------------------------------------------------------------ stage (b)
