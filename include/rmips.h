@@ -243,6 +243,22 @@ rmips_status rmips_soft_bwd(rmips_ctx *ctx, const float *U, int64_t n,
                             int32_t d, float T, const float *dS, void *ws,
                             size_t ws_bytes, float *dQ);
 
+/*
+ * rmips_soft_bwd without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving or ascent
+ * loops, harnesses that forbid allocation).  Same arguments, kernels and
+ * results as rmips_soft_bwd.  The partial sums go to a static scratch array
+ * of the library (32 MiB per device, held until the process ends), so
+ * nq * (d rounded up to 32) must be at most 65536 (e.g. 256 queries of up
+ * to 256 dims); larger sizes return RMIPS_EINVAL.  It allocates nothing:
+ * no hipMalloc, no allocating library call.  Every call on one device
+ * shares that device's array: calls that overlap on one device (two
+ * streams, two threads) race and give wrong results.  Does not wait.
+ */
+rmips_status rmips_soft_bwd_noalloc(rmips_ctx *ctx, const float *U, int64_t n,
+                                    const float *tau, const float *Q, int64_t nq,
+                                    int32_t d, float T, const float *dS, float *dQ);
+
 #ifdef __cplusplus
 }
 #endif

@@ -27,7 +27,7 @@ EXPORTS = [
     "rmips_thresholds_workspace_size", "rmips_scores_workspace_size",
     "rmips_topn_workspace_size", "rmips_soft_workspace_size",
     "rmips_thresholds", "rmips_scores", "rmips_topn", "rmips_soft_fwd",
-    "rmips_soft_bwd",
+    "rmips_soft_bwd", "rmips_soft_bwd_noalloc",
 ]
 
 
@@ -113,6 +113,8 @@ def load():
     lib.rmips_soft_fwd.restype = st
     lib.rmips_soft_bwd.argtypes = [vp, vp, i64, vp, vp, i64, i32, f32, vp, vp, sz, vp]
     lib.rmips_soft_bwd.restype = st
+    lib.rmips_soft_bwd_noalloc.argtypes = [vp, vp, i64, vp, vp, i64, i32, f32, vp, vp]
+    lib.rmips_soft_bwd_noalloc.restype = st
     _lib = lib
     return lib
 
@@ -323,6 +325,22 @@ def soft_bwd(U, tau, Q, T, dS):
     dQ = torch.empty((nq, d), dtype=torch.float32, device=U.device)
     _check(ctx, lib.rmips_soft_bwd(ctx, _ptr(U), n, _ptr(tau), _ptr(Q), nq, d, T, _ptr(dS),
                                    _ptr(ws), ws.numel(), _ptr(dQ)))
+    return dQ
+
+
+def soft_bwd_noalloc(U, tau, Q, T, dS, out=None):
+    """rmips_soft_bwd_noalloc: the gradient with the library's static scratch
+    (no workspace); `out` (nq x d float32, device) may be given."""
+    U, tau, Q, T = _soft_args(U, tau, Q, T)
+    n, d = U.shape
+    nq = Q.shape[0]
+    dS = dS.to(torch.float32).contiguous()
+    lib = load()
+    ctx = _context(U.device)
+    dQ = out if out is not None else torch.empty((nq, d), dtype=torch.float32,
+                                                 device=U.device)
+    _check(ctx, lib.rmips_soft_bwd_noalloc(ctx, _ptr(U), n, _ptr(tau), _ptr(Q), nq, d, T,
+                                           _ptr(dS), _ptr(dQ)))
     return dQ
 
 

@@ -214,5 +214,10 @@ void launch_soft(const float *U, int64_t n, const float *tau, const float *Q, in
                  int d, float T, const float *dS, float *S, float *dQ, void *ws,
                  hipStream_t st);
 size_t soft_ws_bytes(int64_t n, int64_t nq, int d);
+// Device address of the file-scope scratch array of the relaxed-score
+// kernels on `device`, which must be the current device (taken once per
+// device, then cached); whether nq queries of d dims fit in it.
+hipError_t soft_scratch_init(int device, void **out);
+bool soft_noalloc_fits(int64_t nq, int d);
 
 }  // namespace rmips

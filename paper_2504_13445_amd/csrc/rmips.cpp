@@ -103,6 +103,9 @@ struct rmips_ctx {
     // per-launch timing (rmips_set_profiling)
     bool prof_on = false;
     ProfRecorder prof;
+    // device address of the relaxed-score kernels' scratch array on this
+    // device (rmips_soft_bwd_noalloc); NULL until taken
+    void *soft_scratch = nullptr;
 };
 
 namespace {
@@ -516,6 +519,9 @@ rmips_status rmips_create(rmips_ctx **out, int device, void *hip_stream) {
     rmips_ctx *c = new rmips_ctx();
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
+    // the scratch array's address on this device (current here); on failure
+    // rmips_soft_bwd_noalloc tries again and reports the error
+    if (soft_scratch_init(device, &c->soft_scratch) != hipSuccess) c->soft_scratch = nullptr;
     if (hipHostMalloc((void **)&c->h_status, 256, hipHostMallocDefault) != hipSuccess) {
         delete c;
         return RMIPS_EDEVICE;
@@ -995,6 +1001,25 @@ rmips_status rmips_soft_bwd(rmips_ctx *ctx, const float *U, int64_t n, const flo
     if (!dS || !dQ) return fail(ctx, RMIPS_EINVAL, "null pointer");
     ProfGuard pguard(ctx);
     launch_soft(U, n, tau, Q, nq, d, T, dS, nullptr, dQ, ws, ctx->stream);
+    HIPTRY(hipGetLastError());
+    return RMIPS_OK;
+}
+
+rmips_status rmips_soft_bwd_noalloc(rmips_ctx *ctx, const float *U, int64_t n,
+                                    const float *tau, const float *Q, int64_t nq, int32_t d,
+                                    float T, const float *dS, float *dQ) {
+    if (!ctx) return RMIPS_EINVAL;
+    if (n < 1 || nq < 1 || nq > (int64_t)INT32_MAX / 2 || d < 1 || d > RMIPS_D_MAX)
+        return fail(ctx, RMIPS_EINVAL, "size out of range");
+    if (!soft_noalloc_fits(nq, d))
+        return fail(ctx, RMIPS_EINVAL,
+                    "nq * (d rounded up to 32) exceeds 65536, the size of the static scratch");
+    if (!(T > 0.0f) || !std::isfinite(T)) return fail(ctx, RMIPS_EINVAL, "T must be > 0");
+    if (!U || !tau || !Q || !dS || !dQ) return fail(ctx, RMIPS_EINVAL, "null pointer");
+    HIPTRY(hipSetDevice(ctx->device));
+    if (!ctx->soft_scratch) HIPTRY(soft_scratch_init(ctx->device, &ctx->soft_scratch));
+    ProfGuard pguard(ctx);
+    launch_soft(U, n, tau, Q, nq, d, T, dS, nullptr, dQ, ctx->soft_scratch, ctx->stream);
     HIPTRY(hipGetLastError());
     return RMIPS_OK;
 }

@@ -10,6 +10,8 @@
 // output layout is not its input layout) and a second product accumulates
 // G += W U over the chunk.  Per-slice partial sums are added in FP64 in a
 // fixed order by a second kernel, so results do not depend on scheduling.
+#include <mutex>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -253,6 +255,46 @@ __global__ __launch_bounds__(256) void k_soft_reduce(const float *__restrict__ P
         if (dS) t *= (double)dS[q];
         out[q * ld_out + c] = (float)t;
     }
+}
+
+// Scratch of the entry point that allocates nothing (rmips_soft_bwd_noalloc):
+// the gradient's per-slice partial sums live in this file-scope array, one
+// copy per device, held until the process ends.  It takes nq * Dg <=
+// SOFT_NOALLOC_COLS (Dg = d rounded up to 32).  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in): it passes
+// the device address that hipGetSymbolAddress returns for the device, taken
+// once per device with that device current.
+constexpr int64_t SOFT_NOALLOC_COLS = 65536;
+constexpr size_t SOFT_SCRATCH_BYTES = (size_t)S_SPLITS * SOFT_NOALLOC_COLS * sizeof(float) + 256;
+static __device__ __align__(256) uint8_t scratch[SOFT_SCRATCH_BYTES];
+
+namespace {
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[SCRATCH_DEVICES] = {};
+}  // namespace
+
+hipError_t soft_scratch_init(int device, void **out) {
+    *out = nullptr;
+    if (device < 0 || device >= SCRATCH_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device] == nullptr) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;  // the caller makes it current
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+bool soft_noalloc_fits(int64_t nq, int d) {
+    return nq * (int64_t)soft_dims(d).Dg <= SOFT_NOALLOC_COLS &&
+           soft_ws_bytes(0, nq, d) <= SOFT_SCRATCH_BYTES;
 }
 
 size_t soft_ws_bytes(int64_t n, int64_t nq, int d) {
