@@ -65,10 +65,14 @@ void orc_inner_products(const float *U, const float *P, int64_t n, int64_t m,
  * kept one ranks after it and is not inserted.
  *   tau[u]    = value of the k-th element,
  *   tau_id[u] = its item index,
- *   topk[u*k + r] = item index of the r-th element (may be NULL).
+ *   topk[u*k + r] = item index of the r-th element (may be NULL),
+ *   topv[u*k + r] = its value (may be NULL): the r-th largest value, which
+ *                   is the threshold of S_{r+1}(u), so one scan with k =
+ *                   k_max gives the thresholds of every k <= k_max (the
+ *                   per-user lists A_i of Alg. 1, Sec. 4.2).
  */
 void orc_kmips(const float *U, const float *P, int64_t n, int64_t m, int d,
-               int k, double *tau, int32_t *tau_id, int32_t *topk)
+               int k, double *tau, int32_t *tau_id, int32_t *topk, double *topv)
 {
 #pragma omp parallel
     {
@@ -106,6 +110,9 @@ void orc_kmips(const float *U, const float *P, int64_t n, int64_t m, int d,
             if (topk)
                 for (int r = 0; r < k; ++r)
                     topk[u * k + r] = bj[r];
+            if (topv)
+                for (int r = 0; r < k; ++r)
+                    topv[u * k + r] = bv[r];
         }
         free(bv);
         free(bj);

@@ -19,7 +19,8 @@ import os
 import numpy as np
 
 __all__ = [
-    "inner_products", "inner_products_c", "kmips", "kmips_c", "histogram_scores",
+    "inner_products", "inner_products_c", "kmips", "kmips_c", "kmips_table",
+    "kmips_table_c", "topn_from_table", "histogram_scores",
     "reverse_counts", "reverse_counts_c", "topn_from_scores", "topn",
     "uscore_cs", "uscore_cs_c", "uscore_eq3", "topn_bound_ordered",
     "temperature", "soft_score", "soft_grad", "sigmoid",
@@ -42,7 +43,7 @@ def _c():
         i64, i32 = ctypes.c_int64, ctypes.c_int
         lib.orc_inner_products.argtypes = [f32p, f32p, i64, i64, i32, f64p]
         lib.orc_kmips.argtypes = [f32p, f32p, i64, i64, i32, i32, f64p, i32p,
-                                  ctypes.c_void_p]
+                                  ctypes.c_void_p, ctypes.c_void_p]
         lib.orc_reverse_counts.argtypes = [f32p, i64, i32, f64p, i32p, f32p,
                                            i32p, i64, i32p]
         lib.orc_uscore_cs.argtypes = [f32p, f32p, i64, i64, i32, f64p,
@@ -107,8 +108,41 @@ def kmips_c(U, P, k, with_topk=True):
     tau_id = np.empty(n, np.int32)
     topk = np.empty((n, k), np.int32) if with_topk else None
     _c().orc_kmips(U, P, n, m, d, k, tau, tau_id,
-                   topk.ctypes.data if with_topk else None)
+                   topk.ctypes.data if with_topk else None, None)
     return tau, tau_id, topk
+
+
+def kmips_table(U, P, kmax, V=None):
+    """Def. 1 for every k <= kmax at once (the per-user lists A_i of Alg. 1,
+    Sec. 4.2, with k_max entries): by fully sorting each user's row,
+    topv[u, r] is the (r+1)-th largest value and topk[u, r] its item index,
+    so (topv[u, k-1], topk[u, k-1]) is (tau_u, tau_id_u) for k and
+    topk[u, :k] is S_k(u)."""
+    if V is None:
+        V = inner_products(U, P)
+    order = _order_desc_id_asc(V)
+    topk = order[:, :kmax].astype(np.int32)
+    topv = np.take_along_axis(V, topk.astype(np.int64), axis=1)
+    return topv, topk
+
+
+def kmips_table_c(U, P, kmax):
+    """kmips_table by the linear scan in plain C (large inputs)."""
+    U, P = _f32(U), _f32(P)
+    n, d = U.shape
+    m = P.shape[0]
+    tau = np.empty(n, np.float64)
+    tau_id = np.empty(n, np.int32)
+    topk = np.empty((n, kmax), np.int32)
+    topv = np.empty((n, kmax), np.float64)
+    _c().orc_kmips(U, P, n, m, d, kmax, tau, tau_id, topk.ctypes.data, topv.ctypes.data)
+    return topv, topk
+
+
+def topn_from_table(topk_table, k, N, m):
+    """Def. 3 for one k <= kmax from the k_max lists: S_k(u) is the first k
+    entries of S_kmax(u) (the same tie order), then Baseline 1 and top-N."""
+    return topn_from_scores(histogram_scores(np.asarray(topk_table)[:, :k], m), N)
 
 
 def histogram_scores(topk, m):

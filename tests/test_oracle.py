@@ -167,6 +167,61 @@ def test_orthogonal_with_duplicates():
     assert topk3[:, 2].tolist() == [1, 0, 0, 0, 0, 0]
 
 
+# ------------------------------------------------------------ k_max table
+def test_kmax_table_onehot_golden(golden_dir):
+    # one scan with k_max = 3 (the per-user lists of Alg. 1, Sec. 4.2) holds
+    # the hand-worked answers of k = 1, 2 and 3
+    g = _golden(golden_dir, "onehot_case.json")
+    U = np.array(g["U"], np.float32)
+    P = np.array(g["P"], np.float32)
+    m = P.shape[0]
+    for fn in (orc.kmips_table, orc.kmips_table_c):
+        topv, topk = fn(U, P, 3)
+        for ks, e in g["k"].items():
+            k = int(ks)
+            assert topv[:, k - 1].tolist() == e["tau"], (k, topv)
+            assert topk[:, k - 1].tolist() == e["tau_id"], (k, topk)
+            assert topk[:, :k].tolist() == e["topk"], k
+            assert orc.histogram_scores(topk[:, :k], m).tolist() == e["scores"], k
+            if "top3_ids" in e:
+                ids, sc = orc.topn_from_table(topk, k, 3, m)
+                assert ids.tolist() == e["top3_ids"] and sc.tolist() == e["top3_scores"]
+
+
+@pytest.mark.parametrize("seed,kmax", [(0, 9), (1, 4)])
+def test_kmax_table_matches_python_brute_force(seed, kmax):
+    U, P = _rand(30 + seed, 10, 35, 5)
+    topv, topk = orc.kmips_table(U, P, kmax)
+    topv_c, topk_c = orc.kmips_table_c(U, P, kmax)
+    assert np.array_equal(topv_c.view(np.uint64), topv.view(np.uint64))
+    assert np.array_equal(topk_c, topk)
+    for k in range(1, kmax + 1):
+        bt, bj, bk = _brute_kmips(U, P, k)
+        assert np.array_equal(topv[:, k - 1], bt), k
+        assert np.array_equal(topk[:, k - 1], bj), k
+        assert np.array_equal(topk[:, :k], bk), k
+
+
+def test_kmax_table_sum_of_scores_every_k():
+    # Eq. (1): every S_k(u) holds k items, so the scores sum to n k for
+    # every k <= k_max; the k-th values do not increase with k
+    U, P = _rand(23, 400, 150, 7)
+    n, m, kmax = U.shape[0], P.shape[0], 25
+    topv, topk = orc.kmips_table_c(U, P, kmax)
+    assert (np.diff(topv, axis=1) <= 0).all()
+    for k in range(1, kmax + 1):
+        assert orc.histogram_scores(topk[:, :k], m).sum() == n * k, k
+    # with ties everywhere (small integers) as well
+    rng = np.random.default_rng(3)
+    Ui = rng.integers(-2, 3, size=(300, 4)).astype(np.float32)
+    Pi = rng.integers(-2, 3, size=(60, 4)).astype(np.float32)
+    tv, tk = orc.kmips_table_c(Ui, Pi, 25)
+    for k in (1, 7, 25):
+        assert orc.histogram_scores(tk[:, :k], 60).sum() == 300 * k
+        t, j, kk = orc.kmips(Ui, Pi, k)
+        assert np.array_equal(tk[:, :k], kk) and np.array_equal(tv[:, k - 1], t)
+
+
 # ------------------------------------------------------------ invariants
 def test_sum_of_scores_is_nk_and_special_k():
     U, P = _rand(5, 150, 80, 9)
