@@ -244,6 +244,75 @@ rmips_status rmips_soft_bwd(rmips_ctx *ctx, const float *U, int64_t n,
                             size_t ws_bytes, float *dQ);
 
 /*
+ * k_max index: the paper's offline stage (Sec. 4.2, Alg. 1), which keeps for
+ * every user the k_max largest inner products (the lists A_i; k_max = 25 in
+ * the paper's experiments, Sec. 5.1) and the upper-bound score uscore_k(p)
+ * of every item for every k <= k_max, so that the online stage (Sec. 4.3,
+ * Alg. 2) answers any (k <= k_max, N) without recomputing them.  Here the
+ * lists are exact (FP64-exact values, tie order as above), so every user is
+ * certified and the online stage is the bound-ordered exact scoring of
+ * rmips_topn with the thresholds of that k.
+ *
+ * The index lives in a caller-owned device buffer of rmips_index_size()
+ * bytes (256-byte aligned), written by rmips_index_build and read by the
+ * calls below; it stays valid while U and P are unchanged.  Every index
+ * call takes the same (n, m, d, kmax, prec) as the build; rmips_index_topn
+ * also takes the same U and P (it recomputes ambiguous pairs from them).
+ * Scratch: a workspace of rmips_index_workspace_size() bytes (for the build
+ * and for queries).  1 <= kmax <= min(m, RMIPS_K_MAX).
+ */
+size_t rmips_index_size(int64_t n, int64_t m, int32_t d, int32_t kmax, rmips_prec prec);
+size_t rmips_index_workspace_size(int64_t n, int64_t m, int32_t d, int32_t kmax,
+                                  rmips_prec prec);
+
+/*
+ * Build the index (Alg. 1's offline stage): stage (a) once with k = kmax
+ * (each user's kmax largest values and their ids), then for each k <= kmax
+ * the Cauchy-Schwarz prefix (Eq. 2) and the Eq. (3)/(6) bound count of
+ * every item.  U [n x d], P [m x d] device FP32.  Synchronises the stream;
+ * RMIPS_ENONFINITE for a NaN/Inf or a row norm above 2^60 (the index is then
+ * unusable).
+ */
+rmips_status rmips_index_build(rmips_ctx *ctx, const float *U, int64_t n, const float *P,
+                               int64_t m, int32_t d, int32_t kmax, rmips_prec prec,
+                               void *index, size_t index_bytes, void *ws, size_t ws_bytes);
+
+/*
+ * Def. 3 for one k <= kmax from the index (Alg. 2): items visited in
+ * (uscore_k desc, id asc) order, exact scores with the thresholds of S_k,
+ * strict stop; results as rmips_topn (host top_ids, top_scores, stats).
+ * Synchronises the stream.  The index's header is read back before
+ * anything is launched: RMIPS_EINVAL when the buffer does not hold an index
+ * that rmips_index_build completed with these sizes and precision.
+ */
+rmips_status rmips_index_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *P,
+                              int64_t m, int32_t d, int32_t kmax, rmips_prec prec,
+                              const void *index, size_t index_bytes, int32_t k, int32_t N,
+                              void *ws, size_t ws_bytes, int32_t *top_ids,
+                              int32_t *top_scores, rmips_stats *stats);
+
+/*
+ * The threshold of S_k(u) from the index (Def. 1): tau [n] device FP64 and
+ * tau_id [n] device int32, as rmips_thresholds gives them for this k.
+ * Waits once, to read the index's header (RMIPS_EINVAL as for
+ * rmips_index_topn), then returns without waiting for the copy.
+ */
+rmips_status rmips_index_thresholds(rmips_ctx *ctx, int64_t n, int64_t m, int32_t d,
+                                    int32_t kmax, rmips_prec prec, const void *index,
+                                    size_t index_bytes, int32_t k, double *tau,
+                                    int32_t *tau_id);
+
+/*
+ * The Eq. (3)/(6) bound count uscore_k(p) of every item (Sec. 4.2; an upper
+ * bound of score(p) for this k by Theorem 2), caller order: uscore [m]
+ * device int32.  Waits once, to read the index's header (RMIPS_EINVAL as
+ * for rmips_index_topn), then returns without waiting for the gather.
+ */
+rmips_status rmips_index_bounds(rmips_ctx *ctx, int64_t n, int64_t m, int32_t d, int32_t kmax,
+                                rmips_prec prec, const void *index, size_t index_bytes,
+                                int32_t k, int32_t *uscore);
+
+/*
  * rmips_soft_bwd without a workspace, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving or ascent
  * loops, harnesses that forbid allocation).  Same arguments, kernels and

@@ -2,9 +2,9 @@
 
 Python side of the C ABI in include/rmips.h; see _lib for the calls.
 """
-from ._lib import (EXPORTS, K_MAX, N_MAX, D_MAX, RmipsError, SoftScore, load, profile,
+from ._lib import (EXPORTS, K_MAX, N_MAX, D_MAX, Index, RmipsError, SoftScore, load, profile,
                    scores, set_profiling, soft_bwd, soft_fwd, sync, thresholds, topn,
                    topn_workspace)
 
-__all__ = ["EXPORTS", "K_MAX", "N_MAX", "D_MAX", "RmipsError", "SoftScore", "load", "profile",
+__all__ = ["EXPORTS", "K_MAX", "N_MAX", "D_MAX", "Index", "RmipsError", "SoftScore", "load", "profile",
            "scores", "set_profiling", "soft_bwd", "soft_fwd", "sync", "thresholds", "topn", "topn_workspace"]

@@ -28,6 +28,8 @@ EXPORTS = [
     "rmips_topn_workspace_size", "rmips_soft_workspace_size",
     "rmips_thresholds", "rmips_scores", "rmips_topn", "rmips_soft_fwd",
     "rmips_soft_bwd", "rmips_soft_bwd_noalloc",
+    "rmips_index_size", "rmips_index_workspace_size", "rmips_index_build",
+    "rmips_index_topn", "rmips_index_thresholds", "rmips_index_bounds",
 ]
 
 
@@ -115,6 +117,21 @@ def load():
     lib.rmips_soft_bwd.restype = st
     lib.rmips_soft_bwd_noalloc.argtypes = [vp, vp, i64, vp, vp, i64, i32, f32, vp, vp]
     lib.rmips_soft_bwd_noalloc.restype = st
+    lib.rmips_index_size.argtypes = [i64, i64, i32, i32, ctypes.c_int]
+    lib.rmips_index_size.restype = sz
+    lib.rmips_index_workspace_size.argtypes = [i64, i64, i32, i32, ctypes.c_int]
+    lib.rmips_index_workspace_size.restype = sz
+    lib.rmips_index_build.argtypes = [vp, vp, i64, vp, i64, i32, i32, ctypes.c_int, vp, sz,
+                                      vp, sz]
+    lib.rmips_index_build.restype = st
+    lib.rmips_index_topn.argtypes = [vp, vp, i64, vp, i64, i32, i32, ctypes.c_int, vp, sz,
+                                     i32, i32, vp, sz, vp, vp, ctypes.POINTER(Stats)]
+    lib.rmips_index_topn.restype = st
+    lib.rmips_index_thresholds.argtypes = [vp, i64, i64, i32, i32, ctypes.c_int, vp, sz, i32,
+                                           vp, vp]
+    lib.rmips_index_thresholds.restype = st
+    lib.rmips_index_bounds.argtypes = [vp, i64, i64, i32, i32, ctypes.c_int, vp, sz, i32, vp]
+    lib.rmips_index_bounds.restype = st
     _lib = lib
     return lib
 
@@ -326,6 +343,65 @@ def soft_bwd(U, tau, Q, T, dS):
     _check(ctx, lib.rmips_soft_bwd(ctx, _ptr(U), n, _ptr(tau), _ptr(Q), nq, d, T, _ptr(dS),
                                    _ptr(ws), ws.numel(), _ptr(dQ)))
     return dQ
+
+
+class Index:
+    """A k_max index (rmips_index_build) over device tensors U and P: each
+    user's kmax largest values and the bound of every item for every
+    k <= kmax, held in a device buffer; topn() answers any (k, N)."""
+
+    def __init__(self, U, P, kmax, prec="fp32"):
+        U, P = _dev_f32(U, "U"), _dev_f32(P, "P")
+        if P.shape[1] != U.shape[1]:
+            raise ValueError("U and P must have the same number of columns")
+        self.U, self.P = U, P
+        self.n, self.d = U.shape
+        self.m = P.shape[0]
+        self.kmax, self.prec, self.p = int(kmax), prec, PREC[prec]
+        lib = load()
+        ctx = _context(U.device)
+        self.buf = _workspace(lib.rmips_index_size(self.n, self.m, self.d, self.kmax, self.p),
+                              U.device)
+        self.ws = _workspace(lib.rmips_index_workspace_size(self.n, self.m, self.d, self.kmax,
+                                                            self.p), U.device)
+        _check(ctx, lib.rmips_index_build(ctx, _ptr(U), self.n, _ptr(P), self.m, self.d,
+                                          self.kmax, self.p, _ptr(self.buf), self.buf.numel(),
+                                          _ptr(self.ws), self.ws.numel()))
+
+    def _args(self):
+        return (self.n, self.m, self.d, self.kmax, self.p, _ptr(self.buf), self.buf.numel())
+
+    def topn(self, k, N):
+        """Top-N ids and scores (host int32 numpy arrays) for this k, and stats."""
+        import numpy as np
+        lib = load()
+        ctx = _context(self.U.device)
+        ids = np.empty(N, np.int32)
+        sc = np.empty(N, np.int32)
+        st = Stats()
+        _check(ctx, lib.rmips_index_topn(ctx, _ptr(self.U), self.n, _ptr(self.P), self.m,
+                                         self.d, self.kmax, self.p, _ptr(self.buf),
+                                         self.buf.numel(), int(k), int(N), _ptr(self.ws),
+                                         self.ws.numel(), ids.ctypes.data_as(ctypes.c_void_p),
+                                         sc.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st)))
+        return ids, sc, st.as_dict()
+
+    def thresholds(self, k):
+        """(tau, tau_id) of S_k on the device."""
+        lib = load()
+        ctx = _context(self.U.device)
+        tau = torch.empty(self.n, dtype=torch.float64, device=self.U.device)
+        tid = torch.empty(self.n, dtype=torch.int32, device=self.U.device)
+        _check(ctx, lib.rmips_index_thresholds(ctx, *self._args(), int(k), _ptr(tau), _ptr(tid)))
+        return tau, tid
+
+    def bounds(self, k):
+        """uscore_k of every item (caller order, int32 on the device)."""
+        lib = load()
+        ctx = _context(self.U.device)
+        out = torch.empty(self.m, dtype=torch.int32, device=self.U.device)
+        _check(ctx, lib.rmips_index_bounds(ctx, *self._args(), int(k), _ptr(out)))
+        return out
 
 
 def soft_bwd_noalloc(U, tau, Q, T, dS, out=None):

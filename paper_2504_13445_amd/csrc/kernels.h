@@ -75,6 +75,10 @@ struct UserSide {
 void launch_user_side(const double *tau, const int32_t *tau_id, const float *Nu,
                       const float *Nhu, const float *Ru, const float *su,
                       const int32_t *order, int64_t n, float c2, UserSide out, hipStream_t st);
+// tau[u] = topv[u * kmax + k - 1], tau_id likewise (the k-th column of the
+// users' lists of their kmax largest values)
+void launch_kth_column(const double *topv, const int32_t *topk, int64_t n, int kmax, int k,
+                       double *tau, int32_t *tau_id, hipStream_t st);
 // Sort keys of the pruning ratio rho_u = tau_u / ||u|| rounded down to FP32
 // (-inf when tau_u <= 0 or ||u|| = 0), as ascending uint32 keys; val = user id.
 void launch_rho_keys(const double *tau, const float *Nu, int64_t n, uint32_t *key,
@@ -118,7 +122,9 @@ struct ThreshArgs {
     float c_err; float c2; float e_abs; float g64;
     // candidate lists: (screened value, its error bound E) and the caller's id
     float2 *cand; int32_t *cand_id; int32_t *cand_cnt;
-    double *tau; int32_t *tau_id; int32_t *topk;
+    // outputs: the k-th value and its id; with topk (may be NULL) the ids of
+    // S_k(u) in order, and with topv (may be NULL, needs topk) their values
+    double *tau; int32_t *tau_id; int32_t *topk; double *topv;
     // overflow handling: lists (3 x n: two refinement lists, the fallback
     // list) with their counters (4 ints), refinement passes (0..2), and the
     // per-user starting bound of the last pass

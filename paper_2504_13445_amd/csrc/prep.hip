@@ -335,6 +335,24 @@ void launch_user_side(const double *tau, const int32_t *tau_id, const float *Nu,
                                                              n, c2, out);
 }
 
+// tau[u] = topv[u][k - 1], tau_id[u] = topk[u][k - 1]: the threshold of
+// S_k(u) from the user's list of its kmax largest values (kmax >= k).
+__global__ void k_kth_column(const double *__restrict__ topv, const int32_t *__restrict__ topk,
+                             int64_t n, int kmax, int k, double *__restrict__ tau,
+                             int32_t *__restrict__ tau_id) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    tau[u] = topv[u * kmax + (k - 1)];
+    tau_id[u] = topk[u * kmax + (k - 1)];
+}
+
+void launch_kth_column(const double *topv, const int32_t *topk, int64_t n, int kmax, int k,
+                       double *tau, int32_t *tau_id, hipStream_t st) {
+    RMIPS_PROF(st, "k_kth_column");
+    k_kth_column<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(topv, topk, n, kmax, k, tau,
+                                                               tau_id);
+}
+
 __global__ void k_rho_keys(const double *__restrict__ tau, const float *__restrict__ Nu,
                            int64_t n, uint32_t *__restrict__ key, int32_t *__restrict__ val) {
     int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

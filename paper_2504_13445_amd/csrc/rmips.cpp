@@ -198,13 +198,35 @@ struct ThreshLayout {
     int *bad;
 };
 
-void thresh_plan(int prec, int64_t n, int64_t m, int d, int k, int cap_override, ThreshLayout &L,
-                 Carve &cv) {
+// The prepared inputs: screening copies of users (caller order) and items
+// (norm order), their norms and scales, the item order.  An index keeps
+// them from its build to its queries.
+void prep_plan(int prec, int64_t n, int64_t m, int d, ThreshLayout &L, Carve &cv) {
     L.prec = prec;
     L.D = padded_dim(prec, d);
     L.rowb = L.D * elem_bytes(prec);
     L.ntiles = (int)((m + TILE_ITEMS - 1) / TILE_ITEMS);
     L.mpad = (int64_t)L.ntiles * TILE_ITEMS;
+    const int64_t npad = (n + 63) / 64 * 64;
+    L.Uq = cv.take<uint8_t>((size_t)npad * L.rowb);
+    L.Nu = cv.take<float>(npad);
+    L.Nhu = cv.take<float>(npad);
+    L.Ru = cv.take<float>(npad);
+    L.su = cv.take<float>(npad);
+    L.Pq = cv.take<uint8_t>((size_t)L.mpad * L.rowb);
+    L.Np = cv.take<float>(L.mpad);
+    L.Nhp = cv.take<float>(L.mpad);
+    L.Rp = cv.take<float>(L.mpad);
+    L.sp = cv.take<float>(L.mpad);
+    L.tmax_nh = cv.take<float>(L.ntiles);
+    L.tmax_r = cv.take<float>(L.ntiles);
+    L.Npid = cv.take<float>(m);
+    L.perm = cv.take<int32_t>(m);
+}
+
+// Stage (a)'s scratch: sort keys, candidate lists, refinement lists.
+void thresh_scratch_plan(int prec, int64_t n, int64_t m, int k, int cap_override,
+                         ThreshLayout &L, Carve &cv) {
     // splits of the item range: about six rounds of screening workgroups
     // (256 users each, one per compute unit) over the whole chip
     int64_t utiles = (n + 255) / 256;
@@ -222,22 +244,7 @@ void thresh_plan(int prec, int64_t n, int64_t m, int d, int k, int cap_override,
         if (prec == RMIPS_FP8_E4M3) capU *= 4;
         L.cap = (int)(((capU + L.nsplit - 1) / L.nsplit + 7) / 8 * 8);
     }
-    const int64_t npad = (n + 63) / 64 * 64;
-    L.Uq = cv.take<uint8_t>((size_t)npad * L.rowb);
-    L.Nu = cv.take<float>(npad);
-    L.Nhu = cv.take<float>(npad);
-    L.Ru = cv.take<float>(npad);
-    L.su = cv.take<float>(npad);
-    L.Pq = cv.take<uint8_t>((size_t)L.mpad * L.rowb);
-    L.Np = cv.take<float>(L.mpad);
-    L.Nhp = cv.take<float>(L.mpad);
-    L.Rp = cv.take<float>(L.mpad);
-    L.sp = cv.take<float>(L.mpad);
-    L.tmax_nh = cv.take<float>(L.ntiles);
-    L.tmax_r = cv.take<float>(L.ntiles);
-    L.Npid = cv.take<float>(m);
     L.keys = cv.take<uint32_t>(m);
-    L.perm = cv.take<int32_t>(m);
     L.sort_scratch = cv.take<uint8_t>(radix_sort_scratch_bytes(m));
     L.cand = cv.take<float2>((size_t)n * L.nsplit * L.cap);
     L.cand_id = cv.take<int32_t>((size_t)n * L.nsplit * L.cap);
@@ -253,6 +260,12 @@ void thresh_plan(int prec, int64_t n, int64_t m, int d, int k, int cap_override,
     // the input flag and the largest R/N share a block (one fill clears both)
     L.bad = cv.take<int>(64);
     L.rmax = reinterpret_cast<unsigned int *>(L.bad + 32);
+}
+
+void thresh_plan(int prec, int64_t n, int64_t m, int d, int k, int cap_override, ThreshLayout &L,
+                 Carve &cv) {
+    prep_plan(prec, n, m, d, L, cv);
+    thresh_scratch_plan(prec, n, m, k, cap_override, L, cv);
 }
 
 constexpr const char *BAD_INPUT = "input holds a NaN/Inf or a vector norm above 2^60";
@@ -292,7 +305,7 @@ rmips_status defer_check(rmips_ctx *ctx, const int *bad) {
 // arrays of L in the workspace for later stages.
 rmips_status run_thresholds(rmips_ctx *ctx, const float *U, int64_t n, const float *P,
                             int64_t m, int d, int k, ThreshLayout &L, double *tau,
-                            int32_t *tau_id, int32_t *topk,
+                            int32_t *tau_id, int32_t *topk, double *topv,
                             unsigned long long *pairs = nullptr,
                             unsigned long long *rpairs = nullptr, hipEvent_t ev0 = nullptr,
                             hipEvent_t ev1 = nullptr, unsigned long long *cstats = nullptr,
@@ -325,7 +338,7 @@ rmips_status run_thresholds(rmips_ctx *ctx, const float *U, int64_t n, const flo
     a.cand = L.cand; a.cand_id = L.cand_id; a.cand_cnt = L.cand_cnt;
     a.lists = L.lists; a.lcnt = L.lcnt; a.refine = 2; a.Luse = L.Luse;
     a.ukey = L.ukey; a.uord = L.uord; a.usort = L.usort; a.nall = L.nall;
-    a.tau = tau; a.tau_id = tau_id; a.topk = topk;
+    a.tau = tau; a.tau_id = tau_id; a.topk = topk; a.topv = topk ? topv : nullptr;
     a.pairs = pairs; a.rpairs = rpairs; a.ev0 = ev0; a.ev1 = ev1; a.cstats = cstats;
     if (thresh_screen_lds(L.prec, L.D) > 160 * 1024 || (size_t)final_stride(L.cap * L.nsplit) * 24 > 150 * 1024)
         return fail(ctx, RMIPS_EUNSUPPORTED, "screening tile or candidate lists exceed LDS");
@@ -413,8 +426,10 @@ constexpr size_t RES_STATUS = 0, RES_CTR = 256, RES_TOP = RES_CTR + 8 * CTR_WORD
                  RES_BYTES = RES_TOP + 8 * RMIPS_N_MAX;
 constexpr int RES_BAD = 12, RES_RMAX = 44;
 
-struct TopnLayout {
-    ThreshLayout T;
+// Users in the order of their pruning ratio rho_u = tau_u / ||u|| (stage
+// (c)): the order, each item's Cauchy-Schwarz prefix, the counting stage's
+// per-user records and screening rows in that order.
+struct PrefixLayout {
     double *tau;
     int32_t *tau_id;
     uint32_t *ukeys;
@@ -423,10 +438,21 @@ struct TopnLayout {
     int32_t *cs;
     UserSide us;
     void *Us;
-    double *G, *Gs, *W;
-    uint4 *Pa, *Ua;  // augmented BF16 hi | lo rows, 4 ka bytes each
+};
+
+// Eq. (3)/(6) bound counts: the Gram matrix of a user sample, the
+// augmented BF16 hi | lo rows (4 ka bytes each) and per-split partial counts.
+struct BoundLayout {
+    double *G, *Gs;
+    uint4 *Pa, *Ua;
     int nsplitB;
-    int32_t *partialB, *uscore, *inv;
+    int32_t *partialB;
+};
+
+// Stage (b): the visit order and its bounds, prefixes and ids, the batch
+// partial counts, and the block of a batch's results.
+struct CountLayout {
+    int32_t *inv;
     uint32_t *vkeys;
     int32_t *visit, *vis_us, *vis_cs, *vis_cid;
     int nsplitC_max;
@@ -435,6 +461,15 @@ struct TopnLayout {
     int32_t *status;
     int64_t *rechecks;
     int32_t *ulen_dev;
+};
+
+struct TopnLayout {
+    ThreshLayout T;
+    PrefixLayout X;
+    double *W;
+    BoundLayout B;
+    int32_t *uscore;
+    CountLayout C;
 };
 
 void user_side_plan(int64_t n, UserSide &us, Carve &cv) {
@@ -450,44 +485,109 @@ void user_side_plan(int64_t n, UserSide &us, Carve &cv) {
     us.thr = cv.take<float4>(n);
 }
 
-void topn_plan(int prec, int64_t n, int64_t m, int d, int k, int cap_override, int bmax,
-               TopnLayout &L, Carve &cv) {
-    thresh_plan(prec, n, m, d, k, cap_override, L.T, cv);
-    L.tau = cv.take<double>(n);
-    L.tau_id = cv.take<int32_t>(n);
-    L.ukeys = cv.take<uint32_t>(n);
-    L.uperm = cv.take<int32_t>(n);
-    L.usort = cv.take<uint8_t>(radix_sort_scratch_bytes(std::max(n, m)));
-    L.cs = cv.take<int32_t>(L.T.mpad);
-    user_side_plan(n, L.us, cv);
-    L.Us = cv.take<uint8_t>((size_t)n * L.T.rowb);
-    L.G = cv.take<double>((size_t)d * d);
-    L.Gs = cv.take<double>(gram_scratch_bytes(d) / sizeof(double));
-    L.W = cv.take<double>((size_t)DPRIME_MAX * d);
-    L.Pa = cv.take<uint4>((size_t)L.T.mpad * aug_len(d) / 4);
-    L.Ua = cv.take<uint4>((size_t)n * aug_len(d) / 4);
-    L.nsplitB = bound_splits(m, aug_len(d));
-    L.partialB = cv.take<int32_t>((size_t)L.nsplitB * m);
-    L.uscore = cv.take<int32_t>(m);
-    L.inv = cv.take<int32_t>(m);
-    L.vkeys = cv.take<uint32_t>(m);
-    L.visit = cv.take<int32_t>(m);
-    L.vis_us = cv.take<int32_t>(2 * m);  // bounds, then prefixes: one copy to the host
-    L.vis_cs = L.vis_us + m;
-    L.vis_cid = cv.take<int32_t>(m);
-    L.nsplitC_max = 256;
-    L.partialC = cv.take<int32_t>((size_t)L.nsplitC_max * bmax);
-    L.batch_scores = cv.take<int32_t>(bmax);
+void prefix_plan(int64_t n, int64_t m, int64_t mpad, int rowb, PrefixLayout &X, Carve &cv) {
+    X.tau = cv.take<double>(n);
+    X.tau_id = cv.take<int32_t>(n);
+    X.ukeys = cv.take<uint32_t>(n);
+    X.uperm = cv.take<int32_t>(n);
+    X.usort = cv.take<uint8_t>(radix_sort_scratch_bytes(std::max(n, m)));
+    X.cs = cv.take<int32_t>(mpad);
+    user_side_plan(n, X.us, cv);
+    X.Us = cv.take<uint8_t>((size_t)n * rowb);
+}
+
+void bound_plan(int64_t n, int64_t m, int64_t mpad, int d, BoundLayout &B, Carve &cv) {
+    B.G = cv.take<double>((size_t)d * d);
+    B.Gs = cv.take<double>(gram_scratch_bytes(d) / sizeof(double));
+    B.Pa = cv.take<uint4>((size_t)mpad * aug_len(d) / 4);
+    B.Ua = cv.take<uint4>((size_t)n * aug_len(d) / 4);
+    B.nsplitB = bound_splits(m, aug_len(d));
+    B.partialB = cv.take<int32_t>((size_t)B.nsplitB * m);
+}
+
+void count_plan(int64_t m, int bmax, CountLayout &C, Carve &cv, bool with_inv) {
+    C.inv = with_inv ? cv.take<int32_t>(m) : nullptr;
+    C.vkeys = cv.take<uint32_t>(m);
+    C.visit = cv.take<int32_t>(m);
+    C.vis_us = cv.take<int32_t>(2 * m);  // bounds, then prefixes: one copy to the host
+    C.vis_cs = C.vis_us + m;
+    C.vis_cid = cv.take<int32_t>(m);
+    C.nsplitC_max = 256;
+    C.partialC = cv.take<int32_t>((size_t)C.nsplitC_max * bmax);
+    C.batch_scores = cv.take<int32_t>(bmax);
     // the results of a batch in one block, copied to the host at once:
     // status, the top-N list, the counters
     uint8_t *res = cv.take<uint8_t>(RES_BYTES);
-    L.status = reinterpret_cast<int32_t *>(res + RES_STATUS);
-    L.top = reinterpret_cast<uint64_t *>(res + RES_TOP);
-    L.rechecks = reinterpret_cast<int64_t *>(res + RES_CTR);
+    C.status = reinterpret_cast<int32_t *>(res + RES_STATUS);
+    C.top = reinterpret_cast<uint64_t *>(res + RES_TOP);
+    C.rechecks = reinterpret_cast<int64_t *>(res + RES_CTR);
+    C.ulen_dev = cv.take<int32_t>(1);
+}
+
+void topn_plan(int prec, int64_t n, int64_t m, int d, int k, int cap_override, int bmax,
+               TopnLayout &L, Carve &cv) {
+    thresh_plan(prec, n, m, d, k, cap_override, L.T, cv);
+    prefix_plan(n, m, L.T.mpad, L.T.rowb, L.X, cv);
+    L.W = cv.take<double>((size_t)DPRIME_MAX * d);
+    bound_plan(n, m, L.T.mpad, d, L.B, cv);
+    L.uscore = cv.take<int32_t>(m);
+    count_plan(m, bmax, L.C, cv, true);
     // stage (a)'s flags live in the status words (copied with every batch)
-    L.T.bad = L.status + RES_BAD;
-    L.T.rmax = reinterpret_cast<unsigned int *>(L.status + RES_RMAX);
-    L.ulen_dev = cv.take<int32_t>(1);
+    L.T.bad = L.C.status + RES_BAD;
+    L.T.rmax = reinterpret_cast<unsigned int *>(L.C.status + RES_RMAX);
+}
+
+// A k_max index (Alg. 1's offline stage): the prepared inputs, each
+// user's k_max largest values and their ids (the lists A_i, exact), the
+// rotation W of Eq. (3), the inverse item order, the Eq. (3)/(6) bound of
+// every item for every k <= k_max (k-major, norm order), and a header.
+constexpr int32_t INDEX_MAGIC = 0x584d5200;  // with a version in the low byte
+constexpr int INDEX_HDR_WORDS = 8;
+struct IndexLayout {
+    ThreshLayout T;
+    double *topv;
+    int32_t *topk;
+    double *W;
+    int32_t *inv;
+    int32_t *table;
+    int32_t *hdr;
+};
+
+void index_plan(int prec, int64_t n, int64_t m, int d, int kmax, IndexLayout &I, Carve &cv) {
+    prep_plan(prec, n, m, d, I.T, cv);
+    I.topv = cv.take<double>((size_t)n * kmax);
+    I.topk = cv.take<int32_t>((size_t)n * kmax);
+    I.W = cv.take<double>((size_t)DPRIME_MAX * d);
+    I.inv = cv.take<int32_t>(m);
+    I.table = cv.take<int32_t>((size_t)kmax * m);
+    I.hdr = cv.take<int32_t>(INDEX_HDR_WORDS);
+}
+
+void index_header(int64_t n, int64_t m, int d, int kmax, int prec, int32_t (&h)[INDEX_HDR_WORDS]) {
+    h[0] = INDEX_MAGIC | 1;
+    h[1] = (int32_t)n;
+    h[2] = (int32_t)m;
+    h[3] = d;
+    h[4] = kmax;
+    h[5] = prec;
+    h[6] = 0;
+    h[7] = 0;
+}
+
+// scratch of an index build: stage (a)'s, the rho order, the bound's
+void index_build_plan(int prec, int64_t n, int64_t m, int d, int kmax, int cap_override,
+                      IndexLayout &I, PrefixLayout &X, BoundLayout &B, Carve &cv) {
+    thresh_scratch_plan(prec, n, m, kmax, cap_override, I.T, cv);
+    prefix_plan(n, m, I.T.mpad, I.T.rowb, X, cv);
+    bound_plan(n, m, I.T.mpad, d, B, cv);
+}
+
+// scratch of an index query: the rho order and stage (b)
+void index_query_plan(int64_t n, int64_t m, const IndexLayout &I, PrefixLayout &X,
+                      CountLayout &C, Carve &cv) {
+    prefix_plan(n, m, I.T.mpad, I.T.rowb, X, cv);
+    count_plan(m, BATCH_MAX, C, cv, false);
+    C.inv = I.inv;
 }
 
 // splits of the user range of a counting launch: about four rounds of
@@ -499,6 +599,185 @@ int count_splits(int64_t nb, int64_t ulen, int maxs) {
     int64_t s = (2048 + iblocks - 1) / iblocks;
     s = std::min<int64_t>(s, std::max<int64_t>(1, chunks / 2));
     return (int)std::max<int64_t>(1, std::min<int64_t>(s, maxs));
+}
+
+// Stage (c), first part: users sorted by their ratio keys without the low
+// 8 bits (3 passes instead of 4): each item's prefix may take users whose
+// ratio is up to 2^-15 relative above its norm, which the bound and the
+// count then test; the counting stage's per-user records and screening
+// rows in that order.  X.tau / X.tau_id hold the thresholds.
+void run_prefix(const ThreshLayout &T, PrefixLayout &X, int64_t n, int64_t m, float c2,
+                hipStream_t st, bool with_rows = true) {
+    launch_rho_keys(X.tau, T.Nu, n, X.ukeys, X.uperm, st);
+    (void)radix_sort_u32(X.ukeys, X.uperm, n, X.usort, st, RHO_LO_BIT, 32);
+    launch_cs_prefix(X.ukeys, n, T.Np, m, RHO_LO_BIT, X.cs, st);
+    launch_user_side(X.tau, X.tau_id, T.Nu, T.Nhu, T.Ru, T.su, X.uperm, n, c2, X.us, st);
+    if (with_rows) launch_gather_padded(T.Uq, X.uperm, n, T.rowb, X.Us, st);
+}
+
+// Relative slack s of the Eq. (3) bound, in units of ||u|| ||p||: the BF16
+// split drops at most 3.01 * 2^-16 |a_i||b_i| per term; the matrix-core sums
+// of the 3 ka <= 192 exact BF16 products (12 chained steps) add at most
+// gamma_204 (unit 2^-23, 3.19 * 2^-16) times 1.02 sum |a_i||b_i|; and sum
+// |a_i||b_i| <= ||a|| ||b|| <= 1.415 ||p|| ||u||: 8.9 * 2^-16 in all, below
+// s = 2^-12; the FP32 rounding of W x (2^-24 relative) is far below the
+// margin.  The absolute slack covers BF16 and FP32 underflow (norms are
+// below 2^60), subnormal operands flushed by the matrix cores included:
+// each such term is below 2^-126 * 2^60 * 1.42 in magnitude.
+constexpr float BOUND_SLACK = 0x1p-12f;
+constexpr float BOUND_ABS_SLACK = 0x1p-60f;
+
+// Stage (c), second part: the Eq. (3)/(6) bound count of every item (norm
+// order) into `uscore`, over the users of its prefix (users' augmented rows
+// in rho order; the items' rows must already be in B.Pa).
+void run_bound(const float *U, const PrefixLayout &X, const BoundLayout &B, const double *Wd,
+               int64_t n, int64_t m, int64_t mpad, int d, unsigned long long *pairs,
+               hipEvent_t e0, hipEvent_t e1, int32_t *uscore, hipStream_t st) {
+    const int dp = dprime(d), ka = aug_len(d);
+    launch_rotate_aug(U, X.uperm, n, n, d, Wd, dp, ka, BOUND_SLACK, B.Ua, st);
+    BoundArgs ba{};
+    ba.ka = ka;
+    ba.Pb = B.Pa; ba.m = m; ba.mpad = mpad; ba.Ub = B.Ua; ba.tau_lo = X.us.tau_lo;
+    ba.abs_slack = BOUND_ABS_SLACK; ba.cs = X.cs;
+    ba.nsplit = B.nsplitB; ba.partial = B.partialB; ba.pairs = pairs;
+    if (e0) (void)hipEventRecord(e0, st);
+    launch_bound(ba, st);
+    if (e1) (void)hipEventRecord(e1, st);
+    launch_colsum(B.partialB, B.nsplitB, m, uscore, st);
+}
+
+// Host side of stage (b): events and the counters a caller reports.
+struct CountRun {
+    hipEvent_t ev_vis, ev_end, ev_k0, ev_k1;  // visit order ready, last copy, kernel brackets
+    int64_t visited = 0, batches = 0, screened = 0, launches = 0;
+    float ms_count_k = 0.0f;
+};
+
+rmips_status run_count_topn(rmips_ctx *ctx, const float *U, const float *P,
+                            const ThreshLayout &T, const PrefixLayout &X, CountLayout &C,
+                            const int32_t *uscore, int64_t n, int64_t m, int d, int N,
+                            const ErrConst &ec, int bfirst, int bmax, CountRun &cr,
+                            int32_t *top_ids, int32_t *top_scores, const int32_t **h_ctr_out);
+
+}  // namespace
+
+namespace {
+
+// Stage (b) of Alg. 2 from the bounds `uscore` (norm order): the visit order
+// (uscore desc, id asc), then batches of exact scores with the running
+// top-N until the next bound is below the current N-th score.  The first
+// batch goes out without a host synchronisation; stage (a)'s input check
+// (status word RES_BAD) is read with its results.  On success writes the
+// top-N (host) and points *h_ctr_out at the host copy of the counters.
+rmips_status run_count_topn(rmips_ctx *ctx, const float *U, const float *P,
+                            const ThreshLayout &T, const PrefixLayout &X, CountLayout &C,
+                            const int32_t *uscore, int64_t n, int64_t m, int d, int N,
+                            const ErrConst &ec, int bfirst, int bmax, CountRun &cr,
+                            int32_t *top_ids, int32_t *top_scores, const int32_t **h_ctr_out) {
+    hipStream_t st = ctx->stream;
+    launch_visit_keys(uscore, C.inv, m, C.vkeys, C.visit, C.status, st);
+    // the keys are ~uscore with 0 <= uscore <= n: only the bits of n vary
+    HIPTRY(radix_sort_u32(C.vkeys, C.visit, m, X.usort, st, 0, 32 - __builtin_clz((unsigned)n)));
+    launch_gather3_i32(uscore, X.cs, T.perm, C.visit, m, C.vis_us, C.vis_cs, C.vis_cid, st);
+    // pinned host copies (grown once per larger m): bounds and prefixes in
+    // visit order, then room for a batch's result block
+    const int64_t need = 2 * m + (int64_t)(RES_BYTES / sizeof(int32_t));
+    if (ctx->h_vis_cap < need) {
+        if (ctx->h_vis) HIPTRY(hipHostFree(ctx->h_vis));
+        ctx->h_vis = nullptr;
+        ctx->h_vis_cap = 0;
+        HIPTRY(hipHostMalloc((void **)&ctx->h_vis, sizeof(int32_t) * need, hipHostMallocDefault));
+        ctx->h_vis_cap = need;
+    }
+    int32_t *h_us = ctx->h_vis, *h_cs = ctx->h_vis + m;
+    HIPTRY(hipMemcpyAsync(h_us, C.vis_us, sizeof(int32_t) * 2 * m, hipMemcpyDeviceToHost, st));
+    HIPTRY(hipEventRecord(cr.ev_vis, st));
+    // (no synchronisation here: the first batch goes out at once, and these
+    // copies arrive with its results; the input check is read then, before
+    // anything is returned)
+
+    // every batch ends with the status, the top-N list and the statistics
+    // copied to the host: the last batch's copies are the results
+    uint8_t *h_res = reinterpret_cast<uint8_t *>(ctx->h_vis + 2 * m);
+    const int32_t *h_st = reinterpret_cast<const int32_t *>(h_res + RES_STATUS);
+    const uint64_t *top = reinterpret_cast<const uint64_t *>(h_res + RES_TOP);
+    int64_t r0 = 0;
+    // First batch: the items with the largest bounds.  After it, the items
+    // that can still enter the top-N are exactly those whose bound reaches
+    // the current N-th score: a prefix of the visit order, scored next.
+    int64_t bsz = std::min(bfirst, bmax);
+    while (r0 < m && bsz > 0) {
+        const int64_t r1 = std::min<int64_t>(m, r0 + bsz);
+        const int64_t nb = r1 - r0;
+        // the batch's users: the longest prefix of its items; the first
+        // batch's is taken on the device (the host does not have the prefixes
+        // yet), with n for the launch shape
+        const bool first = cr.batches == 0;
+        int64_t ulen = 0;
+        if (first) {
+            launch_max_i32(C.vis_cs, nb, C.ulen_dev, st);
+            ulen = n;
+        } else {
+            for (int64_t r = r0; r < r1; ++r) ulen = std::max<int64_t>(ulen, h_cs[r]);
+        }
+        CountArgs a{};
+        a.prec = T.prec;
+        a.Pq = T.Pq; a.Np = T.Np; a.Nhp = T.Nhp; a.Rp = T.Rp; a.sp = T.sp;
+        a.rows = C.visit + r0; a.nb = nb;
+        a.item_tie = T.perm; a.item_orig = T.perm; a.Porig = P;
+        a.Us = X.Us; a.ulen = ulen; a.us = X.us; a.Uorig = U; a.d = d; a.D = T.D;
+        a.ulen_dev = first ? C.ulen_dev : nullptr;
+        a.c_err = ec.c; a.c2 = ec.c2; a.e_abs = E_ABS;
+        a.nsplit = count_splits(nb, ulen, C.nsplitC_max);
+        a.partial = C.partialC;
+        a.rechecks = C.rechecks;
+        if (ulen > 0) {
+            HIPTRY(hipEventRecord(cr.ev_k0, st));
+            launch_count(a, st);
+            HIPTRY(hipEventRecord(cr.ev_k1, st));
+            launch_colsum(C.partialC, a.nsplit, nb, C.batch_scores, st);
+            ++cr.launches;
+        } else {
+            HIPTRY(hipMemsetAsync(C.batch_scores, 0, sizeof(int32_t) * nb, st));
+        }
+        launch_topn_merge(C.batch_scores, nb, C.vis_cid + r0, N, C.top, C.status, st);
+        HIPTRY(hipGetLastError());
+        HIPTRY(hipEventRecord(cr.ev_end, st));
+        HIPTRY(hipMemcpyAsync(h_res, C.status, RES_BYTES, hipMemcpyDeviceToHost, st));
+        HIPTRY(hipStreamSynchronize(st));
+        if (ulen > 0) {
+            float t = 0.0f;
+            (void)hipEventElapsedTime(&t, cr.ev_k0, cr.ev_k1);
+            cr.ms_count_k += t;
+        }
+        if (first) {
+            if (h_st[RES_BAD] != 0) return fail(ctx, RMIPS_ENONFINITE, BAD_INPUT);
+            ulen = 0;  // the batch's own user count, for the statistics
+            for (int64_t r = r0; r < r1; ++r) ulen = std::max<int64_t>(ulen, h_cs[r]);
+        }
+        cr.visited += nb;
+        ++cr.batches;
+        cr.screened += nb * ulen;
+        const int tauN = h_st[0];
+        r0 = r1;
+        if (tauN < 0) {
+            bsz = bmax;  // fewer than N items seen so far
+            continue;
+        }
+        // items whose bound is strictly below the N-th score cannot enter
+        int64_t e = r0;
+        while (e < m && h_us[e] >= tauN) ++e;
+        bsz = std::min<int64_t>(e - r0, bmax);
+    }
+    ctx->prof.resolve();  // (the stream is idle after the last batch)
+    if (cr.batches == 0) return fail(ctx, RMIPS_EDEVICE, "no item batch was scored");
+    if (h_st[1] != N) return fail(ctx, RMIPS_EDEVICE, "top-N list incomplete");
+    for (int i = 0; i < N; ++i) {
+        top_scores[i] = (int32_t)(top[i] >> 32);
+        top_ids[i] = (int32_t)(~(uint32_t)(top[i] & 0xffffffffu));
+    }
+    *h_ctr_out = reinterpret_cast<const int32_t *>(h_res + RES_CTR);
+    return RMIPS_OK;
 }
 
 }  // namespace
@@ -522,7 +801,7 @@ rmips_status rmips_create(rmips_ctx **out, int device, void *hip_stream) {
     // the scratch array's address on this device (current here); on failure
     // rmips_soft_bwd_noalloc tries again and reports the error
     if (soft_scratch_init(device, &c->soft_scratch) != hipSuccess) c->soft_scratch = nullptr;
-    if (hipHostMalloc((void **)&c->h_status, 256, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void **)&c->h_status, 512, hipHostMallocDefault) != hipSuccess) {
         delete c;
         return RMIPS_EDEVICE;
     }
@@ -640,7 +919,7 @@ rmips_status rmips_thresholds(rmips_ctx *ctx, const float *U, int64_t n, const f
     ProfGuard pguard(ctx);
     Carve cv(ws);
     thresh_plan(prec, n, m, d, k, ctx->cap_override, L, cv);
-    s = run_thresholds(ctx, U, n, P, m, d, k, L, tau, tau_id, topk);
+    s = run_thresholds(ctx, U, n, P, m, d, k, L, tau, tau_id, topk, nullptr);
     if (s != RMIPS_OK) return s;
     return defer_check(ctx, L.bad);
 }
@@ -746,8 +1025,7 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     Carve cv(ws);
     TopnLayout L;
     topn_plan(prec, n, m, d, k, ctx->cap_override, BATCH_MAX, L, cv);
-    const int D = L.T.D;
-    const ErrConst ec = err_const(D, d);
+    const ErrConst ec = err_const(L.T.D, d);
 
     constexpr int NEV = 10;
     hipEvent_t ev[NEV] = {};
@@ -756,9 +1034,9 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
         ~EvGuard() { for (int i = 0; i < NEV; ++i) if (e[i]) (void)hipEventDestroy(e[i]); }
     } guard{ev};
     for (auto &e : ev) HIPTRY(hipEventCreate(&e));
-    unsigned long long *ctr = reinterpret_cast<unsigned long long *>(L.rechecks);
+    unsigned long long *ctr = reinterpret_cast<unsigned long long *>(L.C.rechecks);
     // status words (with stage (a)'s flags) and counters in one fill
-    HIPTRY(hipMemsetAsync(L.status, 0, RES_TOP, st));
+    HIPTRY(hipMemsetAsync(L.C.status, 0, RES_TOP, st));
     HIPTRY(hipEventRecord(ev[0], st));
 
     // The Gram matrix of a user sample (for the rotation of Eq. (3)) does
@@ -770,16 +1048,17 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     std::vector<double> G, W;
     if (rotate) {
         const int64_t ns = std::min<int64_t>(n, GRAM_SAMPLE);
-        launch_gram(U, ns, n / ns, d, L.G, L.Gs, st);
+        launch_gram(U, ns, n / ns, d, L.B.G, L.B.Gs, st);
         G.resize((size_t)d * d);
-        HIPTRY(hipMemcpyAsync(G.data(), L.G, sizeof(double) * d * d, hipMemcpyDeviceToHost, st));
+        HIPTRY(hipMemcpyAsync(G.data(), L.B.G, sizeof(double) * d * d, hipMemcpyDeviceToHost,
+                              st));
     }
     HIPTRY(hipEventRecord(ev[3], st));
 
     // ---- stage (a): exact thresholds (the input check is read at the
     // synchronisation before stage (b))
-    s = run_thresholds(ctx, U, n, P, m, d, k, L.T, L.tau, L.tau_id, nullptr, ctr + CTR_PAIRS,
-                       ctr + CTR_RPAIRS, ev[4], ev[5], ctr + CTR_CS, false);
+    s = run_thresholds(ctx, U, n, P, m, d, k, L.T, L.X.tau, L.X.tau_id, nullptr, nullptr,
+                       ctr + CTR_PAIRS, ctr + CTR_RPAIRS, ev[4], ev[5], ctr + CTR_CS, false);
     if (s != RMIPS_OK) return s;
     HIPTRY(hipEventRecord(ev[1], st));
     if (rotate) {
@@ -788,167 +1067,45 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     }
 
     // ---- stage (c): Cauchy-Schwarz prefix and Eq. (3)/(6) bound counts
-    // users by their ratio keys without the low 8 bits (3 passes instead of
-    // 4): each item's prefix may take users whose ratio is up to 2^-15
-    // relative above its norm, which the bound and the count then test
-    launch_rho_keys(L.tau, L.T.Nu, n, L.ukeys, L.uperm, st);
-    HIPTRY(radix_sort_u32(L.ukeys, L.uperm, n, L.usort, st, RHO_LO_BIT, 32));
-    launch_cs_prefix(L.ukeys, n, L.T.Np, m, RHO_LO_BIT, L.cs, st);
-    launch_user_side(L.tau, L.tau_id, L.T.Nu, L.T.Nhu, L.T.Ru, L.T.su, L.uperm, n, ec.c2, L.us,
-                     st);
-    launch_gather_padded(L.T.Uq, L.uperm, n, L.T.rowb, L.Us, st);
+    run_prefix(L.T, L.X, n, m, ec.c2, st);
     if (rotate)
         HIPTRY(hipMemcpyAsync(L.W, W.data(), sizeof(double) * dp * d, hipMemcpyHostToDevice, st));
-    // Relative slack s of the bound, in units of ||u|| ||p||: the BF16
-    // split drops at most 3.01 * 2^-16 |a_i||b_i| per term; the matrix-core
-    // sums of the 3 ka <= 192 exact BF16 products (12 chained steps) add at
-    // most gamma_204 (unit 2^-23, 3.19 * 2^-16) times 1.02 sum |a_i||b_i|;
-    // and sum |a_i||b_i| <= ||a|| ||b|| <= 1.415 ||p|| ||u||: 8.9 * 2^-16 in
-    // all, below s = 2^-12; the FP32 rounding of W x (2^-24 relative) is far
-    // below the margin.  The absolute slack covers BF16 and FP32 underflow
-    // (norms are below 2^60).
-    const float slack = 0x1p-12f;
     const double *Wd = rotate ? L.W : nullptr;  // nullptr: the identity
-    launch_rotate_aug(P, L.T.perm, m, L.T.mpad, d, Wd, dp, ka, 1.0f, L.Pa, st);
-    launch_rotate_aug(U, L.uperm, n, n, d, Wd, dp, ka, slack, L.Ua, st);
-    BoundArgs ba{};
-    ba.ka = ka;
-    ba.Pb = L.Pa; ba.m = m; ba.mpad = L.T.mpad; ba.Ub = L.Ua; ba.tau_lo = L.us.tau_lo;
-    ba.abs_slack = 0x1p-60f; ba.cs = L.cs;
-    ba.nsplit = L.nsplitB; ba.partial = L.partialB; ba.pairs = ctr + 2;
-    HIPTRY(hipEventRecord(ev[6], st));
-    launch_bound(ba, st);
-    HIPTRY(hipEventRecord(ev[7], st));
-    launch_colsum(L.partialB, L.nsplitB, m, L.uscore, st);
-    // visit order: (uscore desc, id asc)
-    launch_invert_perm(L.T.perm, m, L.inv, st);
-    if (ctx->bound_out) launch_gather_i32(L.uscore, L.inv, m, ctx->bound_out, st);
-    launch_visit_keys(L.uscore, L.inv, m, L.vkeys, L.visit, L.status, st);
-    // the keys are ~uscore with 0 <= uscore <= n: only the bits of n vary
-    HIPTRY(radix_sort_u32(L.vkeys, L.visit, m, L.usort, st, 0, 32 - __builtin_clz((unsigned)n)));
-    launch_gather3_i32(L.uscore, L.cs, L.T.perm, L.visit, m, L.vis_us, L.vis_cs, L.vis_cid, st);
-    // pinned host copies (grown once per larger m): bounds and prefixes in
-    // visit order, then room for a batch's result block
-    const int64_t need = 2 * m + (int64_t)(RES_BYTES / sizeof(int32_t));
-    if (ctx->h_vis_cap < need) {
-        if (ctx->h_vis) HIPTRY(hipHostFree(ctx->h_vis));
-        ctx->h_vis = nullptr;
-        ctx->h_vis_cap = 0;
-        HIPTRY(hipHostMalloc((void **)&ctx->h_vis, sizeof(int32_t) * need, hipHostMallocDefault));
-        ctx->h_vis_cap = need;
-    }
-    int32_t *h_us = ctx->h_vis, *h_cs = ctx->h_vis + m;
-    HIPTRY(hipMemcpyAsync(h_us, L.vis_us, sizeof(int32_t) * 2 * m, hipMemcpyDeviceToHost, st));
-    HIPTRY(hipEventRecord(ev[2], st));
-    // (no synchronisation here: the first batch goes out at once, and these
-    // copies arrive with its results; its input check is read then, before
-    // anything is returned)
+    launch_rotate_aug(P, L.T.perm, m, L.T.mpad, d, Wd, dp, ka, 1.0f, L.B.Pa, st);
+    run_bound(U, L.X, L.B, Wd, n, m, L.T.mpad, d, ctr + 2, ev[6], ev[7], L.uscore, st);
+    launch_invert_perm(L.T.perm, m, L.C.inv, st);
+    if (ctx->bound_out) launch_gather_i32(L.uscore, L.C.inv, m, ctx->bound_out, st);
+    HIPTRY(hipGetLastError());
 
     // ---- stage (b): exact scores in bound order, running top-N, stop rule
-    // (every batch ends with the status, the top-N list and the statistics
-    // copied to the host: the last batch's copies are the results)
-    uint8_t *h_res = reinterpret_cast<uint8_t *>(ctx->h_vis + 2 * m);
-    const int32_t *h_st = reinterpret_cast<const int32_t *>(h_res + RES_STATUS);
-    const uint64_t *top = reinterpret_cast<const uint64_t *>(h_res + RES_TOP);
-    const int64_t *h_ctr = reinterpret_cast<const int64_t *>(h_res + RES_CTR);
-    int64_t r0 = 0, visited = 0, batches = 0, screened = 0, launches = 0;
-    float ms_count_k = 0.0f;
-    // First batch: the items with the largest bounds.  After it, the items
-    // that can still enter the top-N are exactly those whose bound reaches
-    // the current N-th score: a prefix of the visit order, scored next.
-    int64_t bsz = std::min(bfirst, bmax);
-    while (r0 < m && bsz > 0) {
-        const int64_t r1 = std::min<int64_t>(m, r0 + bsz);
-        const int64_t nb = r1 - r0;
-        // the batch's users: the longest prefix of its items; the first
-        // batch's is taken on the device (the host does not have the prefixes
-        // yet), with n for the launch shape
-        const bool first = batches == 0;
-        int64_t ulen = 0;
-        if (first) {
-            launch_max_i32(L.vis_cs, nb, L.ulen_dev, st);
-            ulen = n;
-        } else {
-            for (int64_t r = r0; r < r1; ++r) ulen = std::max<int64_t>(ulen, h_cs[r]);
-        }
-        CountArgs a{};
-        a.prec = prec;
-        a.Pq = L.T.Pq; a.Np = L.T.Np; a.Nhp = L.T.Nhp; a.Rp = L.T.Rp; a.sp = L.T.sp;
-        a.rows = L.visit + r0; a.nb = nb;
-        a.item_tie = L.T.perm; a.item_orig = L.T.perm; a.Porig = P;
-        a.Us = L.Us; a.ulen = ulen; a.us = L.us; a.Uorig = U; a.d = d; a.D = D;
-        a.ulen_dev = first ? L.ulen_dev : nullptr;
-        a.c_err = ec.c; a.c2 = ec.c2; a.e_abs = E_ABS;
-        a.nsplit = count_splits(nb, ulen, L.nsplitC_max);
-        a.partial = L.partialC;
-        a.rechecks = L.rechecks;
-        if (ulen > 0) {
-            HIPTRY(hipEventRecord(ev[8], st));
-            launch_count(a, st);
-            HIPTRY(hipEventRecord(ev[9], st));
-            launch_colsum(L.partialC, a.nsplit, nb, L.batch_scores, st);
-            ++launches;
-        } else {
-            HIPTRY(hipMemsetAsync(L.batch_scores, 0, sizeof(int32_t) * nb, st));
-        }
-        launch_topn_merge(L.batch_scores, nb, L.vis_cid + r0, N, L.top, L.status, st);
-        HIPTRY(hipGetLastError());
-        HIPTRY(hipEventRecord(ev[3], st));
-        HIPTRY(hipMemcpyAsync(h_res, L.status, RES_BYTES, hipMemcpyDeviceToHost, st));
-        HIPTRY(hipStreamSynchronize(st));
-        if (ulen > 0) {
-            float t = 0.0f;
-            (void)hipEventElapsedTime(&t, ev[8], ev[9]);
-            ms_count_k += t;
-        }
-        if (first) {
-            if (h_st[RES_BAD] != 0) return fail(ctx, RMIPS_ENONFINITE, BAD_INPUT);
-            ulen = 0;  // the batch's own user count, for the statistics
-            for (int64_t r = r0; r < r1; ++r) ulen = std::max<int64_t>(ulen, h_cs[r]);
-        }
-        visited += nb;
-        ++batches;
-        screened += nb * ulen;
-        const int tauN = h_st[0];
-        r0 = r1;
-        if (tauN < 0) {
-            bsz = bmax;  // fewer than N items seen so far
-            continue;
-        }
-        // items whose bound is strictly below the N-th score cannot enter
-        int64_t e = r0;
-        while (e < m && h_us[e] >= tauN) ++e;
-        bsz = std::min<int64_t>(e - r0, bmax);
-    }
-    ctx->prof.resolve();  // (the stream is idle after the last batch)
-    if (batches == 0) return fail(ctx, RMIPS_EDEVICE, "no item batch was scored");
-    if (h_st[1] != N) return fail(ctx, RMIPS_EDEVICE, "top-N list incomplete");
-    for (int i = 0; i < N; ++i) {
-        top_scores[i] = (int32_t)(top[i] >> 32);
-        top_ids[i] = (int32_t)(~(uint32_t)(top[i] & 0xffffffffu));
-    }
+    CountRun cr;
+    cr.ev_vis = ev[2]; cr.ev_end = ev[3]; cr.ev_k0 = ev[8]; cr.ev_k1 = ev[9];
+    const int32_t *h = nullptr;
+    s = run_count_topn(ctx, U, P, L.T, L.X, L.C, L.uscore, n, m, d, N, ec, bfirst, bmax, cr,
+                       top_ids, top_scores, &h);
+    if (s != RMIPS_OK) return s;
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
-        stats->visited_items = visited;
-        stats->batches = batches;
-        const int64_t *h = h_ctr;
+        stats->visited_items = cr.visited;
+        stats->batches = cr.batches;
+        const int64_t *hc = reinterpret_cast<const int64_t *>(h);
         int64_t tp = 0, rp = 0, cs[4] = {0, 0, 0, 0};
         for (int i = 0; i < CSTAT_SLOTS; ++i) {
-            tp += h[CTR_PAIRS + i];
-            rp += h[CTR_RPAIRS + i];
-            for (int j = 0; j < 4; ++j) cs[j] += h[CTR_CS + 4 * i + j];
+            tp += hc[CTR_PAIRS + i];
+            rp += hc[CTR_RPAIRS + i];
+            for (int j = 0; j < 4; ++j) cs[j] += hc[CTR_CS + 4 * i + j];
         }
         stats->cand_pairs = cs[1];
         stats->cand_listed = cs[0];
         stats->overflow_users = cs[2];
         stats->refine_users = cs[3];
-        stats->recheck_pairs = h[0];
+        stats->recheck_pairs = hc[0];
         stats->thresh_pairs = tp;
         stats->refine_pairs = rp;
-        stats->bound_pairs = h[2];
-        stats->count_pairs = screened;
-        stats->screened_pairs = screened + tp + rp;
-        stats->count_launches = launches;
+        stats->bound_pairs = hc[2];
+        stats->count_pairs = cr.screened;
+        stats->screened_pairs = cr.screened + tp + rp;
+        stats->count_launches = cr.launches;
         float t01 = 0, t12 = 0, t23 = 0, t03 = 0, tsc = 0, tbd = 0;
         (void)hipEventElapsedTime(&t01, ev[0], ev[1]);
         (void)hipEventElapsedTime(&t12, ev[1], ev[2]);
@@ -961,9 +1118,252 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
         stats->ms_count = t23;
         stats->ms_total = t03;
         stats->ms_screen = tsc;
-        stats->ms_count_kernels = ms_count_k;
+        stats->ms_count_kernels = cr.ms_count_k;
         stats->ms_bound_kernel = tbd;
     }
+    return RMIPS_OK;
+}
+
+// ---------------------------------------------------------------- k_max index
+static bool index_sizes_ok(int64_t n, int64_t m, int32_t d, int32_t kmax, rmips_prec prec) {
+    return n >= 1 && n <= (int64_t)INT32_MAX && m >= 1 && m <= (int64_t)INT32_MAX / 2 && d >= 1 &&
+           d <= RMIPS_D_MAX && kmax >= 1 && kmax <= RMIPS_K_MAX && kmax <= m && prec_ok(prec);
+}
+
+size_t rmips_index_size(int64_t n, int64_t m, int32_t d, int32_t kmax, rmips_prec prec) {
+    if (!index_sizes_ok(n, m, d, kmax, prec)) return 0;
+    Carve cv(nullptr);
+    IndexLayout I;
+    index_plan(prec, n, m, d, kmax, I, cv);
+    return cv.off + 256;
+}
+
+size_t rmips_index_workspace_size(int64_t n, int64_t m, int32_t d, int32_t kmax,
+                                  rmips_prec prec) {
+    if (!index_sizes_ok(n, m, d, kmax, prec)) return 0;
+    Carve ci(nullptr);
+    IndexLayout I;
+    index_plan(prec, n, m, d, kmax, I, ci);
+    Carve cb(nullptr);
+    PrefixLayout X;
+    BoundLayout B;
+    index_build_plan(prec, n, m, d, kmax, 0, I, X, B, cb);
+    Carve cq(nullptr);
+    CountLayout C;
+    index_query_plan(n, m, I, X, C, cq);
+    return std::max(cb.off, cq.off) + 256;
+}
+
+// The index's header, read back (a synchronisation) before any launch that
+// takes item or user indices from the index: an index built with other
+// sizes has its arrays at other offsets, and those would not be indices.
+constexpr int H_HDR = 64;  // pinned status words that receive it
+static rmips_status check_index_header(rmips_ctx *ctx, const int32_t *hdr_dev, int64_t n,
+                                       int64_t m, int32_t d, int32_t kmax, rmips_prec prec) {
+    HIPTRY(hipMemcpyAsync(ctx->h_status + H_HDR, hdr_dev, sizeof(int32_t) * INDEX_HDR_WORDS,
+                          hipMemcpyDeviceToHost, ctx->stream));
+    HIPTRY(hipStreamSynchronize(ctx->stream));
+    int32_t want[INDEX_HDR_WORDS];
+    index_header(n, m, d, kmax, prec, want);
+    if (std::memcmp(ctx->h_status + H_HDR, want, sizeof(want)) != 0)
+        return fail(ctx, RMIPS_EINVAL,
+                    "index not built by rmips_index_build with these n, m, d, kmax, precision");
+    return RMIPS_OK;
+}
+
+static rmips_status index_args(rmips_ctx *ctx, int64_t n, int64_t m, int32_t d, int32_t kmax,
+                               rmips_prec prec, void *index, size_t index_bytes) {
+    if (!ctx) return RMIPS_EINVAL;
+    if (!index_sizes_ok(n, m, d, kmax, prec))
+        return fail(ctx, RMIPS_EINVAL, "sizes out of range (1 <= kmax <= min(m, 32))");
+    if (!index) return fail(ctx, RMIPS_EINVAL, "null pointer");
+    if (index_bytes < rmips_index_size(n, m, d, kmax, prec))
+        return fail(ctx, RMIPS_EWORKSPACE, "index buffer too small");
+    return RMIPS_OK;
+}
+
+rmips_status rmips_index_build(rmips_ctx *ctx, const float *U, int64_t n, const float *P,
+                               int64_t m, int32_t d, int32_t kmax, rmips_prec prec,
+                               void *index, size_t index_bytes, void *ws, size_t ws_bytes) {
+    rmips_status s = index_args(ctx, n, m, d, kmax, prec, index, index_bytes);
+    if (s != RMIPS_OK) return s;
+    if (!U || !P || !ws) return fail(ctx, RMIPS_EINVAL, "null pointer");
+    {
+        Carve ci(nullptr);
+        IndexLayout I0;
+        index_plan(prec, n, m, d, kmax, I0, ci);
+        Carve cb(nullptr);
+        PrefixLayout X0;
+        BoundLayout B0;
+        index_build_plan(prec, n, m, d, kmax, ctx->cap_override, I0, X0, B0, cb);
+        if (ws_bytes < cb.off + 256) return fail(ctx, RMIPS_EWORKSPACE, "workspace too small");
+    }
+    HIPTRY(hipSetDevice(ctx->device));
+    ProfGuard pguard(ctx);
+    hipStream_t st = ctx->stream;
+    Carve ci(index), cw(ws);
+    IndexLayout I;
+    index_plan(prec, n, m, d, kmax, I, ci);
+    PrefixLayout X;
+    BoundLayout B;
+    index_build_plan(prec, n, m, d, kmax, ctx->cap_override, I, X, B, cw);
+    ThreshLayout &T = I.T;
+    const ErrConst ec = err_const(T.D, d);
+    const int dp = dprime(d), ka = aug_len(d);
+    const bool rotate = dp < d;
+    // no valid header until the build has succeeded
+    HIPTRY(hipMemsetAsync(I.hdr, 0, sizeof(int32_t) * INDEX_HDR_WORDS, st));
+    hipEvent_t evg = nullptr;
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard() { if (*e) (void)hipEventDestroy(*e); }
+    } guard{&evg};
+    HIPTRY(hipEventCreate(&evg));
+    std::vector<double> G, W;
+    if (rotate) {
+        const int64_t ns = std::min<int64_t>(n, GRAM_SAMPLE);
+        launch_gram(U, ns, n / ns, d, B.G, B.Gs, st);
+        G.resize((size_t)d * d);
+        HIPTRY(hipMemcpyAsync(G.data(), B.G, sizeof(double) * d * d, hipMemcpyDeviceToHost, st));
+        HIPTRY(hipEventRecord(evg, st));
+    }
+    // stage (a) once with k = kmax: every user's kmax largest values and
+    // their ids (exact, in the tie order) go to the index
+    s = run_thresholds(ctx, U, n, P, m, d, kmax, T, X.tau, X.tau_id, I.topk, I.topv);
+    if (s != RMIPS_OK) return s;
+    if (rotate) {
+        HIPTRY(hipEventSynchronize(evg));
+        top_eigvecs(G, d, dp, W);
+        HIPTRY(hipMemcpyAsync(I.W, W.data(), sizeof(double) * dp * d, hipMemcpyHostToDevice, st));
+    }
+    const double *Wd = rotate ? I.W : nullptr;
+    launch_rotate_aug(P, T.perm, m, T.mpad, d, Wd, dp, ka, 1.0f, B.Pa, st);
+    launch_invert_perm(T.perm, m, I.inv, st);
+    // the bound of every item for each k: users in the rho order of that
+    // k's thresholds, one bound pass per k (row k - 1 of the table)
+    for (int k = 1; k <= kmax; ++k) {
+        launch_kth_column(I.topv, I.topk, n, kmax, k, X.tau, X.tau_id, st);
+        run_prefix(T, X, n, m, ec.c2, st, false);
+        run_bound(U, X, B, Wd, n, m, T.mpad, d, nullptr, nullptr, nullptr,
+                  I.table + (size_t)(k - 1) * m, st);
+    }
+    HIPTRY(hipGetLastError());
+    // the build waits for its work and reports its input check itself
+    HIPTRY(hipMemcpyAsync(ctx->h_status, T.bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPTRY(hipStreamSynchronize(st));
+    ctx->prof.resolve();
+    if (ctx->h_status[0] != 0) return fail(ctx, RMIPS_ENONFINITE, BAD_INPUT);
+    int32_t *hdr = ctx->h_status + H_HDR;  // pinned
+    int32_t want[INDEX_HDR_WORDS];
+    index_header(n, m, d, kmax, prec, want);
+    std::memcpy(hdr, want, sizeof(want));
+    HIPTRY(hipMemcpyAsync(I.hdr, hdr, sizeof(want), hipMemcpyHostToDevice, st));
+    HIPTRY(hipStreamSynchronize(st));
+    return RMIPS_OK;
+}
+
+rmips_status rmips_index_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *P,
+                              int64_t m, int32_t d, int32_t kmax, rmips_prec prec,
+                              const void *index, size_t index_bytes, int32_t k, int32_t N,
+                              void *ws, size_t ws_bytes, int32_t *top_ids, int32_t *top_scores,
+                              rmips_stats *stats) {
+    rmips_status s = index_args(ctx, n, m, d, kmax, prec, const_cast<void *>(index), index_bytes);
+    if (s != RMIPS_OK) return s;
+    if (k < 1 || k > kmax) return fail(ctx, RMIPS_EINVAL, "k out of range (1 <= k <= kmax)");
+    if (N < 1 || N > RMIPS_N_MAX || N > m) return fail(ctx, RMIPS_EINVAL, "N out of range");
+    if (!U || !P || !ws || !top_ids || !top_scores)
+        return fail(ctx, RMIPS_EINVAL, "null pointer");
+    if (ws_bytes < rmips_index_workspace_size(n, m, d, kmax, prec))
+        return fail(ctx, RMIPS_EWORKSPACE, "workspace too small");
+    const int bfirst = ctx->batch_first > 0 ? ctx->batch_first : BATCH_FIRST;
+    const int bmax = ctx->batch_max > 0 ? ctx->batch_max : BATCH_MAX;
+    HIPTRY(hipSetDevice(ctx->device));
+    ProfGuard pguard(ctx);
+    hipStream_t st = ctx->stream;
+    Carve ci(const_cast<void *>(index)), cw(ws);
+    IndexLayout I;
+    index_plan(prec, n, m, d, kmax, I, ci);
+    PrefixLayout X;
+    CountLayout C;
+    index_query_plan(n, m, I, X, C, cw);
+    s = check_index_header(ctx, I.hdr, n, m, d, kmax, prec);
+    if (s != RMIPS_OK) return s;
+    const ErrConst ec = err_const(I.T.D, d);
+    constexpr int NEV = 5;
+    hipEvent_t ev[NEV] = {};
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard() { for (int i = 0; i < NEV; ++i) if (e[i]) (void)hipEventDestroy(e[i]); }
+    } guard{ev};
+    for (auto &e : ev) HIPTRY(hipEventCreate(&e));
+    HIPTRY(hipMemsetAsync(C.status, 0, RES_TOP, st));
+    HIPTRY(hipEventRecord(ev[0], st));
+    // the thresholds of this k from the lists, then the rho order
+    launch_kth_column(I.topv, I.topk, n, kmax, k, X.tau, X.tau_id, st);
+    run_prefix(I.T, X, n, m, ec.c2, st);
+    CountRun cr;
+    cr.ev_vis = ev[1]; cr.ev_end = ev[2]; cr.ev_k0 = ev[3]; cr.ev_k1 = ev[4];
+    const int32_t *h = nullptr;
+    s = run_count_topn(ctx, U, P, I.T, X, C, I.table + (size_t)(k - 1) * m, n, m, d, N, ec,
+                       bfirst, bmax, cr, top_ids, top_scores, &h);
+    if (s != RMIPS_OK) return s;
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        const int64_t *hc = reinterpret_cast<const int64_t *>(h);
+        stats->visited_items = cr.visited;
+        stats->batches = cr.batches;
+        stats->recheck_pairs = hc[0];
+        stats->count_pairs = cr.screened;
+        stats->screened_pairs = cr.screened;
+        stats->count_launches = cr.launches;
+        float t01 = 0, t12 = 0, t02 = 0;
+        (void)hipEventElapsedTime(&t01, ev[0], ev[1]);
+        (void)hipEventElapsedTime(&t12, ev[1], ev[2]);
+        (void)hipEventElapsedTime(&t02, ev[0], ev[2]);
+        stats->ms_bound = t01;
+        stats->ms_count = t12;
+        stats->ms_total = t02;
+        stats->ms_count_kernels = cr.ms_count_k;
+    }
+    return RMIPS_OK;
+}
+
+rmips_status rmips_index_thresholds(rmips_ctx *ctx, int64_t n, int64_t m, int32_t d,
+                                    int32_t kmax, rmips_prec prec, const void *index,
+                                    size_t index_bytes, int32_t k, double *tau,
+                                    int32_t *tau_id) {
+    rmips_status s = index_args(ctx, n, m, d, kmax, prec, const_cast<void *>(index), index_bytes);
+    if (s != RMIPS_OK) return s;
+    if (k < 1 || k > kmax) return fail(ctx, RMIPS_EINVAL, "k out of range (1 <= k <= kmax)");
+    if (!tau || !tau_id) return fail(ctx, RMIPS_EINVAL, "null pointer");
+    HIPTRY(hipSetDevice(ctx->device));
+    ProfGuard pguard(ctx);
+    Carve ci(const_cast<void *>(index));
+    IndexLayout I;
+    index_plan(prec, n, m, d, kmax, I, ci);
+    s = check_index_header(ctx, I.hdr, n, m, d, kmax, prec);
+    if (s != RMIPS_OK) return s;
+    launch_kth_column(I.topv, I.topk, n, kmax, k, tau, tau_id, ctx->stream);
+    HIPTRY(hipGetLastError());
+    return RMIPS_OK;
+}
+
+rmips_status rmips_index_bounds(rmips_ctx *ctx, int64_t n, int64_t m, int32_t d, int32_t kmax,
+                                rmips_prec prec, const void *index, size_t index_bytes,
+                                int32_t k, int32_t *uscore) {
+    rmips_status s = index_args(ctx, n, m, d, kmax, prec, const_cast<void *>(index), index_bytes);
+    if (s != RMIPS_OK) return s;
+    if (k < 1 || k > kmax) return fail(ctx, RMIPS_EINVAL, "k out of range (1 <= k <= kmax)");
+    if (!uscore) return fail(ctx, RMIPS_EINVAL, "null pointer");
+    HIPTRY(hipSetDevice(ctx->device));
+    ProfGuard pguard(ctx);
+    Carve ci(const_cast<void *>(index));
+    IndexLayout I;
+    index_plan(prec, n, m, d, kmax, I, ci);
+    s = check_index_header(ctx, I.hdr, n, m, d, kmax, prec);
+    if (s != RMIPS_OK) return s;
+    launch_gather_i32(I.table + (size_t)(k - 1) * m, I.inv, m, uscore, ctx->stream);
+    HIPTRY(hipGetLastError());
     return RMIPS_OK;
 }
 

@@ -649,6 +649,7 @@ void k_thresh_final(ThreshArgs a, int capT, int capP) {
                         a.tau_id[u] = c;
                     }
                     if (a.topk && rank < a.k) a.topk[u * a.k + rank] = c;
+                    if (a.topv && rank < a.k) a.topv[u * a.k + rank] = x;
                 }
             } else {
                 wave_sort_pairs(v64, rid, nrec, lane);
@@ -658,6 +659,8 @@ void k_thresh_final(ThreshArgs a, int capT, int capP) {
                 }
                 if (a.topk)
                     for (int r = lane; r < a.k; r += 64) a.topk[u * a.k + r] = rid[r];
+                if (a.topv)
+                    for (int r = lane; r < a.k; r += 64) a.topv[u * a.k + r] = v64[r];
             }
         }
     }
@@ -764,6 +767,7 @@ __global__ __launch_bounds__(64 * FB_WAVES) void k_thresh_fallback(ThreshArgs a)
             if (lane == bl) ++head;
             if (lane == 0) {
                 if (a.topk) a.topk[u * k + r] = bi;
+                if (a.topv) a.topv[u * k + r] = bv;
                 if (r == k - 1) {
                     a.tau[u] = bv;
                     a.tau_id[u] = bi;
