@@ -155,6 +155,8 @@ inline int final_stride(int capT) {
     return p;
 }
 size_t thresh_screen_lds(int prec, int D);
+// LDS bytes per candidate-list entry of the final selection
+size_t final_entry_bytes();
 // per-tile maxima of Nh and R (64 items per tile)
 void launch_tile_max(const float *Nh, const float *R, int ntiles, float *tmax_nh, float *tmax_r,
                      hipStream_t st);

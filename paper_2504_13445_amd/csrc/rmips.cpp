@@ -237,8 +237,9 @@ void thresh_scratch_plan(int prec, int64_t n, int64_t m, int k, int cap_override
     // candidate capacity per user (all splits together): well above the
     // candidate counts of typical users; users beyond it are screened again
     // with a tighter bound.  FP8's wider error band needs longer lists.
+    // (even: each list is written as two halves)
     if (cap_override > 0) {
-        L.cap = cap_override;
+        L.cap = (cap_override + 1) & ~1;
     } else {
         int64_t capU = std::max<int64_t>(256, 16 * (int64_t)k);
         if (prec == RMIPS_FP8_E4M3) capU *= 4;
@@ -248,8 +249,8 @@ void thresh_scratch_plan(int prec, int64_t n, int64_t m, int k, int cap_override
     L.sort_scratch = cv.take<uint8_t>(radix_sort_scratch_bytes(m));
     L.cand = cv.take<float2>((size_t)n * L.nsplit * L.cap);
     L.cand_id = cv.take<int32_t>((size_t)n * L.nsplit * L.cap);
-    // counts per (user, split); refinement passes use up to 8 splits
-    L.cand_cnt = cv.take<int32_t>((size_t)n * 8);
+    // counts per (user, split, half); refinement passes use up to 8 splits
+    L.cand_cnt = cv.take<int32_t>((size_t)n * 16);
     L.lists = cv.take<int32_t>((size_t)3 * n);
     L.lcnt = cv.take<int32_t>(64);
     L.Luse = cv.take<float>(n);
@@ -340,7 +341,7 @@ rmips_status run_thresholds(rmips_ctx *ctx, const float *U, int64_t n, const flo
     a.ukey = L.ukey; a.uord = L.uord; a.usort = L.usort; a.nall = L.nall;
     a.tau = tau; a.tau_id = tau_id; a.topk = topk; a.topv = topk ? topv : nullptr;
     a.pairs = pairs; a.rpairs = rpairs; a.ev0 = ev0; a.ev1 = ev1; a.cstats = cstats;
-    if (thresh_screen_lds(L.prec, L.D) > 160 * 1024 || (size_t)final_stride(L.cap * L.nsplit) * 24 > 150 * 1024)
+    if (thresh_screen_lds(L.prec, L.D) > 160 * 1024 || (size_t)final_stride(L.cap * L.nsplit) * final_entry_bytes() > 150 * 1024)
         return fail(ctx, RMIPS_EUNSUPPORTED, "screening tile or candidate lists exceed LDS");
     launch_thresh(a, st);
     HIPTRY(hipGetLastError());

@@ -99,7 +99,7 @@ constexpr int NSTRIDE = 5 * TILE_ITEMS;
 size_t thresh_screen_lds(int prec, int D) {
     const int ls = lds_row_bytes(prec, D);
     return 2 * (size_t)(TILE_ITEMS * ls + LDS_GUARD) + 2 * (size_t)NSTRIDE * 4 +
-           32 * SCR_NW * sizeof(int) + 16 * sizeof(float);
+           16 * sizeof(float);
 }
 
 // Item tile t (64 rows, and per item N, Nh, R, and the tile's scalars) into
@@ -158,8 +158,7 @@ void k_thresh_screen(ThreshArgs a) {
     const int bstride = TILE_ITEMS * ls + LDS_GUARD;
     uint8_t *Pbase = smem8;
     float *Nbase = reinterpret_cast<float *>(Pbase + 2 * bstride);
-    int *cntsh = reinterpret_cast<int *>(Nbase + 2 * NSTRIDE);
-    float *red = reinterpret_cast<float *>(cntsh + TU);
+    float *red = reinterpret_cast<float *>(Nbase + 2 * NSTRIDE);
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int split = blockIdx.y;
@@ -182,8 +181,7 @@ void k_thresh_screen(ThreshArgs a) {
     }
 
     for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-        __syncthreads();  // the previous block's counts have been written out
-        if (tid < TU) cntsh[tid] = 0;
+        __syncthreads();  // the previous block is done with the tile buffers
         const int64_t pos = blk * TU + ucol;
         const bool uvalid = pos < nlist;
         const int64_t ug = uvalid ? (listed ? (int64_t)a.ulist[pos] : pos) : 0;
@@ -223,8 +221,14 @@ void k_thresh_screen(ThreshArgs a) {
             const float rr = exit_ratio(L0);
             if (lane == 0) red[w] = rr;
         }
-        float2 *mycand = a.cand + (ug * a.nsplit + split) * a.cap;
-        int32_t *mycid = a.cand_id + (ug * a.nsplit + split) * a.cap;
+        // the user's list for this split holds two halves of cap / 2 entries,
+        // one per half-wave (each half-wave sees other item rows), so that
+        // each lane appends to its own half with a register count: no
+        // atomics.  The final selection reads them as 2 * nsplit lists.
+        const int half = a.cap / 2, hw = lane >> 5;
+        float2 *mycand = a.cand + (ug * a.nsplit + split) * a.cap + hw * half;
+        int32_t *mycid = a.cand_id + (ug * a.nsplit + split) * a.cap + hw * half;
+        int myc = 0;  // candidates of this lane's half, stored or not
 
         // (the barrier at the top of this loop: the previous block is done
         // with the tile buffers)
@@ -336,11 +340,11 @@ void k_thresh_screen(ThreshArgs a) {
                     const float v = pick32(acc0, acc1, i) * sc;
                     const float eb = ebound(Nsh[r], Nsh[TILE_ITEMS + r], Nsh[2 * TILE_ITEMS + r]);
                     if (v + eb >= L0) {
-                        const int sl = atomicAdd(&cntsh[ucol], 1);
-                        if (sl < a.cap) {
-                            mycand[sl] = make_float2(v, eb);
-                            mycid[sl] = __float_as_int(Nsh[4 * TILE_ITEMS + r]);
+                        if (myc < half) {
+                            mycand[myc] = make_float2(v, eb);
+                            mycid[myc] = __float_as_int(Nsh[4 * TILE_ITEMS + r]);
                         }
+                        ++myc;
                     }
                 }
             }
@@ -348,12 +352,7 @@ void k_thresh_screen(ThreshArgs a) {
             __syncthreads();
             buf ^= 1;
         }
-        __syncthreads();
-        if (tid < TU && blk * TU + tid < nlist) {
-            const int64_t p2 = blk * TU + tid;
-            const int64_t u = listed ? (int64_t)a.ulist[p2] : p2;
-            a.cand_cnt[u * a.nsplit + split] = cntsh[tid];
-        }
+        if (listed && uvalid) a.cand_cnt[(ug * a.nsplit + split) * 2 + hw] = myc;
         // the bound this pass used (equal for the two lanes of a user)
         if (!listed && split == 0 && lane < 32 && uvalid) a.Luse[ug] = L0;
         pacc += (unsigned long long)(ntile_p2 * TILE_ITEMS * nub);
@@ -363,33 +362,9 @@ void k_thresh_screen(ThreshArgs a) {
 }
 
 // ------------------------------------------------------------------ final
-// Wave-level bitonic sort of n <= cap values in LDS, descending (the slots
-// from n up to the next power of two are filled with the fill value first).
-__device__ void wave_sort_desc(float *v, int n, int lane) {
-    int P2 = 1;
-    while (P2 < n) P2 <<= 1;
-    for (int i = n + lane; i < P2; i += 64) v[i] = -INFINITY;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    for (int kk = 2; kk <= P2; kk <<= 1)
-        for (int j = kk >> 1; j > 0; j >>= 1) {
-            for (int i = lane; i < P2; i += 64) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const float x = v[i], y = v[l];
-                    const bool desc = (i & kk) == 0;
-                    if ((x < y) == desc) {
-                        v[i] = y;
-                        v[l] = x;
-                    }
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-        }
-}
-
-// Same for (value, id) pairs in the order (value desc, id asc).
+// Wave-level bitonic sort of (value, id) pairs in LDS in the order (value
+// desc, id asc); the slots from n up to the next power of two are filled
+// first.
 __device__ void wave_sort_pairs(double *v, int *id, int n, int lane) {
     int P2 = 1;
     while (P2 < n) P2 <<= 1;
@@ -421,6 +396,9 @@ __device__ void wave_sort_pairs(double *v, int *id, int n, int lane) {
 
 
 constexpr int FIN_WAVES = 4;
+constexpr int FIN_WPE = 4;  // waves per SIMD of the final selection
+constexpr int FIN_ENTRY_BYTES = 16;  // LDS bytes per list entry of the final selection
+size_t final_entry_bytes() { return FIN_ENTRY_BYTES; }
 // recomputations per user handed from k_thresh_final to k_thresh_exact
 constexpr int EXACT_SLOTS = 8;
 
@@ -439,17 +417,21 @@ __device__ __forceinline__ void wave_sync() {
 // improve on the bound used, the user goes to the exact fallback.
 // capT: longest candidate list taken; capP: array stride, capT rounded up
 // to a power of two so that the bitonic sorts can pad in place.
+// Four waves per SIMD: the FP64 recomputations load 16 values per row at a
+// time (latency), which needs more than the registers of six.
 template <bool LISTED>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FIN_WPE)))
 void k_thresh_final(ThreshArgs a, int capT, int capP) {
     extern __shared__ float smem[];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int nw = blockDim.x >> 6;  // waves per block (one user each)
-    // per-wave LDS: v64[capP] (double), lo, hi (float), cidx, sid (int)
-    uint8_t *base = reinterpret_cast<uint8_t *>(smem) + (size_t)w * capP * 24;
-    double *v64 = reinterpret_cast<double *>(base);
-    float *lo = reinterpret_cast<float *>(base + (size_t)capP * 8);
+    // per-wave LDS (FIN_ENTRY_BYTES per entry): lo, hi (float), cidx, sid
+    // (int); the FP64 values v64 take the place of lo and hi once those are
+    // no longer read
+    uint8_t *base = reinterpret_cast<uint8_t *>(smem) + (size_t)w * capP * FIN_ENTRY_BYTES;
+    float *lo = reinterpret_cast<float *>(base);
     float *hi = lo + capP;
+    double *v64 = reinterpret_cast<double *>(base);
     int *cidx = reinterpret_cast<int *>(hi + capP);
     int *sid = cidx + capP;
     __shared__ float Lstar[FIN_WAVES];
@@ -513,7 +495,9 @@ void k_thresh_final(ThreshArgs a, int capT, int capP) {
         }
         wave_sync();
         // L* = k-th largest lower bound: by ranks for short lists, else by
-        // sorting the lower bounds (the upper bounds and rows stay in place)
+        // rounds of the largest value below the previous round's, counted
+        // with its repetitions, until k values are reached (the list stays
+        // in place, paired with the upper bounds and ids)
         if (valid && stored <= capT) {
             if (stored <= 128) {
                 for (int e = lane; e < stored; e += 64) {
@@ -526,8 +510,23 @@ void k_thresh_final(ThreshArgs a, int capT, int capP) {
                     if (rank == a.k - 1) Lstar[w] = x;
                 }
             } else {
-                wave_sort_desc(lo, stored, lane);
-                if (lane == 0) Lstar[w] = lo[a.k - 1];
+                float prev = INFINITY, Ls = -INFINITY;
+                int acc = 0;
+                for (int r = 0; r < a.k && acc < a.k; ++r) {
+                    float mx = -INFINITY;
+                    for (int e = lane; e < stored; e += 64) {
+                        const float x = lo[e];
+                        mx = (x < prev) ? fmaxf(mx, x) : mx;
+                    }
+#pragma unroll
+                    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+                    int c = 0;
+                    for (int e = lane; e < stored; e += 64) c += (lo[e] == mx) ? 1 : 0;
+                    acc += wave_sum(c);
+                    prev = mx;
+                    Ls = mx;
+                }
+                if (lane == 0) Lstar[w] = acc >= a.k ? Ls : -INFINITY;
             }
         }
         wave_sync();
@@ -579,9 +578,8 @@ void k_thresh_final(ThreshArgs a, int capT, int capP) {
         // When only tau is asked for, a survivor whose lower bound exceeds the
         // upper bounds of all but at most k - 2 others ranks above the k-th
         // item; with A such survivors, tau is the (k - A)-th of the others, and
-        // only those are recomputed.  (Needs the lower bounds in candidate
-        // order, i.e. the rank path above.)
-        const bool band = a.topk == nullptr && stored <= 128;
+        // only those are recomputed.
+        const bool band = a.topk == nullptr;
         int *rid = band ? cidx : sid;
         if (work) {
             const int ns = nsurv[w];
@@ -627,9 +625,11 @@ void k_thresh_final(ThreshArgs a, int capT, int capP) {
                 a.cand_cnt[u * a.nsplit] = -1;
             }
         }
+        wave_sync();  // (v64 takes the place of lo and hi)
         if (work && !defer) {
             const float *urow = a.U + u * a.d;
-            for (int q = lane; q < nrec_w; q += 64) v64[q] = ip64<4>(urow, a.P + (int64_t)rid[q] * a.d, a.d);
+            for (int q = lane; q < nrec_w; q += 64)
+                v64[q] = ip64<16>(urow, a.P + (int64_t)rid[q] * a.d, a.d);
         }
         wave_sync();
         if (work && !defer) {
@@ -817,12 +817,13 @@ void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
     const int64_t ublocks = (a0.n + tu - 1) / tu;
     const int capU = a0.cap * a0.nsplit;
     const int capP = final_stride(capU);
-    int fw = (int)((150 * 1024) / ((size_t)capP * 24));  // waves whose lists fit in LDS
+    int fw = (int)((150 * 1024) / ((size_t)capP * FIN_ENTRY_BYTES));  // waves whose lists fit in LDS
     fw = fw < 1 ? 1 : (fw > FIN_WAVES ? FIN_WAVES : fw);
-    const size_t lds_fin = (size_t)fw * capP * 24;
-    // one resident round of workgroups (six per CU, fewer when their lists
-    // fill the LDS): each wave takes many users in turn
-    const int64_t fres = 256 * std::max<int64_t>(1, std::min<int64_t>(6, (160 * 1024) / lds_fin));
+    const size_t lds_fin = (size_t)fw * capP * FIN_ENTRY_BYTES;
+    // one resident round of workgroups (FIN_WPE per CU, fewer when their
+    // lists fill the LDS): each wave takes many users in turn
+    const int64_t fres =
+        256 * std::max<int64_t>(1, std::min<int64_t>(FIN_WPE * 4 / fw, (160 * 1024) / lds_fin));
     const int64_t fblocks = std::min<int64_t>((a0.n + fw - 1) / fw, fres);
     // (three 4-wave workgroups per CU are resident)
     const int64_t eblocks = std::min<int64_t>(
@@ -833,13 +834,19 @@ void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
         else if (a.prec == PREC_BF16) launch_screen<PREC_BF16>(a, nch, g, lds, st, name);
         else launch_screen<PREC_FP8>(a, nch, g, lds, st, name);
     };
+    // the screening pass writes each (user, split) list as two halves of
+    // cap / 2 entries with their own counts: the final selection and the
+    // deferred recomputations read them as 2 * nsplit lists
     auto final = [&](const ThreshArgs &a, int capT, const char *nf, const char *ne) {
+        ThreshArgs h = a;
+        h.nsplit = 2 * a.nsplit;
+        h.cap = a.cap / 2;
         {
             RMIPS_PROF(st, nf);
-            k_thresh_final<true><<<(unsigned)fblocks, 64 * fw, lds_fin, st>>>(a, capT, capP);
+            k_thresh_final<true><<<(unsigned)fblocks, 64 * fw, lds_fin, st>>>(h, capT, capP);
         }
         RMIPS_PROF(st, ne);
-        k_thresh_exact<true><<<(unsigned)eblocks, 256, 0, st>>>(a);
+        k_thresh_exact<true><<<(unsigned)eblocks, 256, 0, st>>>(h);
     };
     // bounds-only pass (the launch without a user list): every user's L0
     // from the first tiles (phase 1), in workgroups of its own size
@@ -884,7 +891,7 @@ void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
         b.flist = LF;
         b.fcnt = a0.lcnt + 2;
         b.nsplit = nsr;
-        b.cap = capU / nsr;
+        b.cap = (capU / nsr) & ~1;  // (even: two halves per list)
         b.t0tiles = 0;
         b.pairs = a0.rpairs;
         // one resident round (one screening workgroup per CU): the lists
