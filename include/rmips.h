@@ -244,6 +244,23 @@ rmips_status rmips_soft_bwd(rmips_ctx *ctx, const float *U, int64_t n,
                             size_t ws_bytes, float *dQ);
 
 /*
+ * The relaxed score and its unscaled gradient in one pass (the inner
+ * products u . q_i are formed once):
+ *   S [nq] device FP32 out as rmips_soft_fwd,
+ *   G [nq x d] device FP32 out: G[i, :] = sum_u sigmoid'(z_ui) / T * u.
+ * A backward pass is then rmips_soft_scale (dQ = dS * G) instead of a second
+ * pass over the users.  Workspace: rmips_soft_workspace_size.
+ */
+rmips_status rmips_soft_fwd_grad(rmips_ctx *ctx, const float *U, int64_t n,
+                                 const float *tau, const float *Q, int64_t nq,
+                                 int32_t d, float T, void *ws, size_t ws_bytes,
+                                 float *S, float *G);
+
+/* dQ[i, :] = dS[i] * G[i, :] (device FP32; G from rmips_soft_fwd_grad). */
+rmips_status rmips_soft_scale(rmips_ctx *ctx, const float *G, int64_t nq, int32_t d,
+                              const float *dS, float *dQ);
+
+/*
  * k_max index: the paper's offline stage (Sec. 4.2, Alg. 1), which keeps for
  * every user the k_max largest inner products (the lists A_i; k_max = 25 in
  * the paper's experiments, Sec. 5.1) and the upper-bound score uscore_k(p)
@@ -317,8 +334,8 @@ rmips_status rmips_index_bounds(rmips_ctx *ctx, int64_t n, int64_t m, int32_t d,
  * device memory (code under HIP graph capture, tight serving or ascent
  * loops, harnesses that forbid allocation).  Same arguments, kernels and
  * results as rmips_soft_bwd.  The partial sums go to a static scratch array
- * of the library (32 MiB per device, held until the process ends), so
- * nq * (d rounded up to 32) must be at most 65536 (e.g. 256 queries of up
+ * of the library (48 MiB per device, held until the process ends), so
+ * nq * (d rounded up to 16) must be at most 65536 (e.g. 256 queries of up
  * to 256 dims); larger sizes return RMIPS_EINVAL.  It allocates nothing:
  * no hipMalloc, no allocating library call.  Every call on one device
  * shares that device's array: calls that overlap on one device (two

@@ -27,7 +27,7 @@ EXPORTS = [
     "rmips_thresholds_workspace_size", "rmips_scores_workspace_size",
     "rmips_topn_workspace_size", "rmips_soft_workspace_size",
     "rmips_thresholds", "rmips_scores", "rmips_topn", "rmips_soft_fwd",
-    "rmips_soft_bwd", "rmips_soft_bwd_noalloc",
+    "rmips_soft_bwd", "rmips_soft_bwd_noalloc", "rmips_soft_fwd_grad", "rmips_soft_scale",
     "rmips_index_size", "rmips_index_workspace_size", "rmips_index_build",
     "rmips_index_topn", "rmips_index_thresholds", "rmips_index_bounds",
 ]
@@ -117,6 +117,10 @@ def load():
     lib.rmips_soft_bwd.restype = st
     lib.rmips_soft_bwd_noalloc.argtypes = [vp, vp, i64, vp, vp, i64, i32, f32, vp, vp]
     lib.rmips_soft_bwd_noalloc.restype = st
+    lib.rmips_soft_fwd_grad.argtypes = [vp, vp, i64, vp, vp, i64, i32, f32, vp, sz, vp, vp]
+    lib.rmips_soft_fwd_grad.restype = st
+    lib.rmips_soft_scale.argtypes = [vp, vp, i64, i32, vp, vp]
+    lib.rmips_soft_scale.restype = st
     lib.rmips_index_size.argtypes = [i64, i64, i32, i32, ctypes.c_int]
     lib.rmips_index_size.restype = sz
     lib.rmips_index_workspace_size.argtypes = [i64, i64, i32, i32, ctypes.c_int]
@@ -404,6 +408,34 @@ class Index:
         return out
 
 
+def soft_fwd_grad(U, tau, Q, T):
+    """(S, G): the relaxed score and its unscaled gradient sum_u sigmoid'/T u,
+    float32 on U's device, in one pass."""
+    U, tau, Q, T = _soft_args(U, tau, Q, T)
+    n, d = U.shape
+    nq = Q.shape[0]
+    lib = load()
+    ctx = _context(U.device)
+    ws = _workspace(lib.rmips_soft_workspace_size(n, nq, d), U.device)
+    S = torch.empty(nq, dtype=torch.float32, device=U.device)
+    G = torch.empty((nq, d), dtype=torch.float32, device=U.device)
+    _check(ctx, lib.rmips_soft_fwd_grad(ctx, _ptr(U), n, _ptr(tau), _ptr(Q), nq, d, T,
+                                        _ptr(ws), ws.numel(), _ptr(S), _ptr(G)))
+    return S, G
+
+
+def soft_scale(G, dS):
+    """dQ = dS[:, None] * G in the library's kernel (float32, device)."""
+    G = G.contiguous()
+    nq, d = G.shape
+    dS = dS.to(torch.float32).contiguous()
+    lib = load()
+    ctx = _context(G.device)
+    dQ = torch.empty_like(G)
+    _check(ctx, lib.rmips_soft_scale(ctx, _ptr(G), nq, d, _ptr(dS), _ptr(dQ)))
+    return dQ
+
+
 def soft_bwd_noalloc(U, tau, Q, T, dS, out=None):
     """rmips_soft_bwd_noalloc: the gradient with the library's static scratch
     (no workspace); `out` (nq x d float32, device) may be given."""
@@ -421,16 +453,18 @@ def soft_bwd_noalloc(U, tau, Q, T, dS, out=None):
 
 
 class SoftScore(torch.autograd.Function):
-    """Relaxed score S(Q) with the library's backward kernel; the gradient
-    flows to Q only (users and thresholds are data)."""
+    """Relaxed score S(Q): the forward pass forms S and its unscaled gradient
+    in one pass over the users (rmips_soft_fwd_grad), the backward pass scales
+    the gradient by the upstream dS (rmips_soft_scale).  The gradient flows to
+    Q only (users and thresholds are data)."""
 
     @staticmethod
     def forward(ctx, Q, U, tau, T):
-        ctx.save_for_backward(Q, U, tau)
-        ctx.T = float(T)
-        return soft_fwd(U, tau, Q.contiguous(), T)
+        S, G = soft_fwd_grad(U, tau, Q.contiguous(), T)
+        ctx.save_for_backward(G)
+        return S
 
     @staticmethod
     def backward(ctx, dS):
-        Q, U, tau = ctx.saved_tensors
-        return soft_bwd(U, tau, Q.contiguous(), ctx.T, dS), None, None, None
+        (G,) = ctx.saved_tensors
+        return soft_scale(G, dS), None, None, None

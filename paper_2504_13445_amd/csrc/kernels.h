@@ -218,9 +218,18 @@ void launch_topn_merge(const int32_t *scores, int64_t nb, const int32_t *batch_i
                        uint64_t *top, int32_t *status, hipStream_t st);
 
 // ---------------------------------------------------------- relaxed score
+// S (may be NULL): the relaxed score; G (may be NULL): its gradient; dQ (may
+// be NULL): the gradient scaled by dS per query.  ws holds the per-slice
+// partial sums of at most max_splits user slices (soft_ws_bytes for
+// soft_max_splits()).
 void launch_soft(const float *U, int64_t n, const float *tau, const float *Q, int64_t nq,
-                 int d, float T, const float *dS, float *S, float *dQ, void *ws,
-                 hipStream_t st);
+                 int d, float T, const float *dS, float *S, float *G, float *dQ, void *ws,
+                 hipStream_t st, int max_splits);
+int soft_max_splits();
+int soft_noalloc_splits();
+// dQ[i][:] = dS[i] * G[i][:]
+void launch_soft_scale(const float *G, int64_t nq, int d, const float *dS, float *dQ,
+                       hipStream_t st);
 size_t soft_ws_bytes(int64_t n, int64_t nq, int d);
 // Device address of the file-scope scratch array of the relaxed-score
 // kernels on `device`, which must be the current device (taken once per

@@ -1389,7 +1389,8 @@ rmips_status rmips_soft_fwd(rmips_ctx *ctx, const float *U, int64_t n, const flo
     if (s != RMIPS_OK) return s;
     if (!S) return fail(ctx, RMIPS_EINVAL, "null pointer");
     ProfGuard pguard(ctx);
-    launch_soft(U, n, tau, Q, nq, d, T, nullptr, S, nullptr, ws, ctx->stream);
+    launch_soft(U, n, tau, Q, nq, d, T, nullptr, S, nullptr, nullptr, ws, ctx->stream,
+                soft_max_splits());
     HIPTRY(hipGetLastError());
     return RMIPS_OK;
 }
@@ -1401,7 +1402,8 @@ rmips_status rmips_soft_bwd(rmips_ctx *ctx, const float *U, int64_t n, const flo
     if (s != RMIPS_OK) return s;
     if (!dS || !dQ) return fail(ctx, RMIPS_EINVAL, "null pointer");
     ProfGuard pguard(ctx);
-    launch_soft(U, n, tau, Q, nq, d, T, dS, nullptr, dQ, ws, ctx->stream);
+    launch_soft(U, n, tau, Q, nq, d, T, dS, nullptr, nullptr, dQ, ws, ctx->stream,
+                soft_max_splits());
     HIPTRY(hipGetLastError());
     return RMIPS_OK;
 }
@@ -1414,13 +1416,40 @@ rmips_status rmips_soft_bwd_noalloc(rmips_ctx *ctx, const float *U, int64_t n,
         return fail(ctx, RMIPS_EINVAL, "size out of range");
     if (!soft_noalloc_fits(nq, d))
         return fail(ctx, RMIPS_EINVAL,
-                    "nq * (d rounded up to 32) exceeds 65536, the size of the static scratch");
+                    "nq * (d rounded up to 16) exceeds 65536, the size of the static scratch");
     if (!(T > 0.0f) || !std::isfinite(T)) return fail(ctx, RMIPS_EINVAL, "T must be > 0");
     if (!U || !tau || !Q || !dS || !dQ) return fail(ctx, RMIPS_EINVAL, "null pointer");
     HIPTRY(hipSetDevice(ctx->device));
     if (!ctx->soft_scratch) HIPTRY(soft_scratch_init(ctx->device, &ctx->soft_scratch));
     ProfGuard pguard(ctx);
-    launch_soft(U, n, tau, Q, nq, d, T, dS, nullptr, dQ, ctx->soft_scratch, ctx->stream);
+    launch_soft(U, n, tau, Q, nq, d, T, dS, nullptr, nullptr, dQ, ctx->soft_scratch,
+                ctx->stream, soft_noalloc_splits());
+    HIPTRY(hipGetLastError());
+    return RMIPS_OK;
+}
+
+rmips_status rmips_soft_fwd_grad(rmips_ctx *ctx, const float *U, int64_t n, const float *tau,
+                                 const float *Q, int64_t nq, int32_t d, float T, void *ws,
+                                 size_t ws_bytes, float *S, float *G) {
+    rmips_status s = soft_common(ctx, U, n, tau, Q, nq, d, T, ws, ws_bytes);
+    if (s != RMIPS_OK) return s;
+    if (!S || !G) return fail(ctx, RMIPS_EINVAL, "null pointer");
+    ProfGuard pguard(ctx);
+    launch_soft(U, n, tau, Q, nq, d, T, nullptr, S, G, nullptr, ws, ctx->stream,
+                soft_max_splits());
+    HIPTRY(hipGetLastError());
+    return RMIPS_OK;
+}
+
+rmips_status rmips_soft_scale(rmips_ctx *ctx, const float *G, int64_t nq, int32_t d,
+                              const float *dS, float *dQ) {
+    if (!ctx) return RMIPS_EINVAL;
+    if (nq < 1 || nq > (int64_t)INT32_MAX / 2 || d < 1 || d > RMIPS_D_MAX)
+        return fail(ctx, RMIPS_EINVAL, "size out of range");
+    if (!G || !dS || !dQ) return fail(ctx, RMIPS_EINVAL, "null pointer");
+    HIPTRY(hipSetDevice(ctx->device));
+    ProfGuard pguard(ctx);
+    launch_soft_scale(G, nq, d, dS, dQ, ctx->stream);
     HIPTRY(hipGetLastError());
     return RMIPS_OK;
 }

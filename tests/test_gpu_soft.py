@@ -57,6 +57,37 @@ def test_soft_matches_fp64(n, m, d, nq):
     _check(U, Q, tau, T)
 
 
+@pytest.mark.parametrize("n,m,d,nq", [(3000, 500, 100, 70), (900, 200, 8, 65), (1500, 300, 1, 3),
+                                      (1200, 300, 128, 40), (800, 200, 129, 9),
+                                      (700, 200, 256, 33), (4100, 300, 64, 128)])
+def test_soft_fwd_grad_matches_fp64(n, m, d, nq):
+    """S and its unscaled gradient from one pass (rmips_soft_fwd_grad), and
+    the backward pass as rmips_soft_scale of that gradient."""
+    print("[case] soft fwd+grad", n, m, d, nq, flush=True)
+    import paper_2504_13445_amd as rm
+    U, P, Q, tau, T = _case(n, m, d, nq)
+    Ug, Qg, tg = _g(U), _g(Q), _g(tau)
+    S, G = rm.soft_fwd_grad(Ug, tg, Qg, T)
+    S64 = orc.soft_score(U, tau.astype(np.float64), Q, T)
+    G64 = orc.soft_grad(U, tau.astype(np.float64), Q, T)
+    S = S.cpu().numpy().astype(np.float64)
+    rel = np.abs(S - S64) / np.maximum(S64, 1e-300)
+    assert (rel[S64 > 1e-30] <= 1e-4).all(), rel.max()
+    Gn = G.cpu().numpy().astype(np.float64)
+    num = np.linalg.norm(Gn - G64, axis=1)
+    den = np.linalg.norm(G64, axis=1)
+    ok = den > 1e-30
+    assert (num[ok] <= 1e-4 * den[ok]).all(), (num[ok] / den[ok]).max()
+    dS = np.linspace(0.5, 1.5, nq).astype(np.float32)
+    dQ = rm.soft_scale(G, _g(dS)).cpu().numpy()
+    assert np.array_equal(dQ, (G.cpu().numpy() * dS[:, None]).astype(np.float32))
+    # the fused pass forms the same sums as the separate calls
+    S1 = rm.soft_fwd(Ug, tg, Qg, T).cpu().numpy()
+    assert np.array_equal(S1.astype(np.float64), S)
+    G1 = rm.soft_bwd(Ug, tg, Qg, T, torch.ones(nq, device=_dev())).cpu().numpy()
+    assert np.array_equal(G1, G.cpu().numpy())
+
+
 def test_soft_closed_form_identical_users():
     print("[case] soft identical users", flush=True)
     rng = np.random.default_rng(1)
