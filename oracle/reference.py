@@ -24,6 +24,7 @@ __all__ = [
     "reverse_counts", "reverse_counts_c", "topn_from_scores", "topn",
     "uscore_cs", "uscore_cs_c", "uscore_eq3", "topn_bound_ordered",
     "temperature", "soft_score", "soft_grad", "sigmoid",
+    "budget_rotation", "budget_preprocess", "budget_query", "BUDGET_KINDS",
 ]
 
 # --------------------------------------------------------------------- C part
@@ -48,6 +49,13 @@ def _c():
                                            i32p, i64, i32p]
         lib.orc_uscore_cs.argtypes = [f32p, f32p, i64, i64, i32, f64p,
                                       ctypes.c_double, i32p]
+        i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+        dbl = ctypes.c_double
+        lib.orc_budget_pre.restype = ctypes.c_int
+        lib.orc_budget_pre.argtypes = [f32p, f32p, i64, i64, i32, i32, i64, i64, i32, dbl,
+                                       dbl, f64p, f64p, f64p, f64p, f64p, f64p, i32, dbl,
+                                       i32p, f64p, i32p, i64p, f64p, i32p, i64p, i64p,
+                                       i64p, f64p]
         _lib = lib
     return _lib
 
@@ -319,3 +327,210 @@ def soft_grad(U, tau, Q, T):
     for Ud, s in _soft_chunks(U, tau, Q, T):
         G += (s * (1.0 - s) / T) @ Ud
     return G
+
+
+# ------------------------------------------- budgeted offline stage (Alg. 1)
+BUDGET_KINDS = {"exp": 0, "uniform": 1, "linear": 2, "quadratic": 3}
+
+
+def budget_rotation(U, P):
+    """The orthogonal matrix of Alg. 1's second step (Sec. 4.2, "SVD
+    transformation"): the right singular vectors of U and P stacked, from
+    the eigenvectors of U^T U + P^T P by decreasing eigenvalue, so that the
+    first coordinates carry most of the energy.  Any orthogonal matrix keeps
+    Eq. (3) a bound; this one makes it tight."""
+    U64 = _f32(U).astype(np.float64)
+    P64 = _f32(P).astype(np.float64)
+    w, V = np.linalg.eigh(U64.T @ U64 + P64.T @ P64)
+    return V[:, np.argsort(-w, kind="stable")]
+
+
+def budget_preprocess(U, P, kmax, b1, B2, kind="exp", alpha=1.0, gamma=0.0, dprime=10,
+                      V=None, rel_slack=REL_SLACK):
+    """Alg. 1 (Sec. 4.2) under the budget B = b1 * n + B2: the uniform
+    step over the first b1 = B1/n items in norm order, U' and its ranks,
+    beta of Eq. (5), the dynamic step with Eq. (4)'s budgets and the pooled
+    budget B', U'' with pos_i, lambda_i of Eq. (7) and uscore_k for every
+    k <= kmax (Eq. 6 over the positions after pos_i, then the first k
+    entries of every list A_i).  kind: "exp" (Eq. 4), or Sec. 5.2's
+    "uniform", "linear", "quadratic".  The rotation V (default
+    budget_rotation) and the split d' = dprime define Eq. (3).
+
+    The steps run in plain C (oracle.c, orc_budget_pre) in the order of the
+    listing; the readings of its unclear points are stated there.  Returns a
+    dict of numpy arrays: order, Av, Aj, pos, lam, uscore (kmax x m), key,
+    rank, b2, nu2, np2, and the scalars of info."""
+    U, P = _f32(U), _f32(P)
+    n, d = U.shape
+    m = P.shape[0]
+    if V is None:
+        V = budget_rotation(U, P)
+    V = np.asarray(V, np.float64)
+    dp = int(min(dprime, d))
+    Ur = U.astype(np.float64) @ V
+    Pr = P.astype(np.float64) @ V
+    ul = np.ascontiguousarray(Ur[:, :dp])
+    pl = np.ascontiguousarray(Pr[:, :dp])
+    nru = np.sqrt((Ur[:, dp:] ** 2).sum(1))
+    nrp = np.sqrt((Pr[:, dp:] ** 2).sum(1))
+    nu, npn = _norms(U), _norms(P)
+    out = {
+        "order": np.empty(m, np.int32), "Av": np.empty((n, kmax), np.float64),
+        "Aj": np.empty((n, kmax), np.int32), "pos": np.empty(n, np.int64),
+        "lam": np.empty(n, np.float64), "uscore": np.empty((kmax, m), np.int32),
+        "key": np.empty(n, np.int64), "rank": np.empty(n, np.int64),
+        "b2": np.empty(n, np.int64),
+    }
+    info = np.zeros(8, np.float64)
+    rc = _c().orc_budget_pre(U, P, n, m, d, int(kmax), int(b1), int(B2), BUDGET_KINDS[kind],
+                             float(alpha), float(gamma), ul, np.ascontiguousarray(nru),
+                             np.ascontiguousarray(nu), pl, np.ascontiguousarray(nrp),
+                             np.ascontiguousarray(npn), dp, float(rel_slack), out["order"],
+                             out["Av"], out["Aj"], out["pos"], out["lam"], out["uscore"],
+                             out["key"], out["rank"], out["b2"], info)
+    if rc != 0:
+        raise ValueError("budget_preprocess: kmax <= b1 and kmax <= m are required")
+    out["uscore"] = out["uscore"].astype(np.int64)
+    U64, P64 = U.astype(np.float64), P.astype(np.float64)
+    out["nu2"] = _sqsum(U64)
+    out["np2"] = _sqsum(P64)
+    out["rot"] = {"ul": ul, "pl": pl, "nru": nru, "nrp": nrp, "nu": nu, "np": npn,
+                  "s": float(rel_slack)}
+    out["U_prime"], out["U_dprime"], out["beta"] = int(info[0]), int(info[1]), float(info[2])
+    out["ips3"], out["ips4"], out["scanned4"] = int(info[3]), int(info[4]), int(info[5])
+    out["cert3"], out["cert4"] = int(info[6]), int(info[7])
+    out["b1"], out["B2"], out["kind"], out["kmax"] = int(min(b1, m)), int(B2), kind, int(kmax)
+    return out
+
+
+def _sqsum(X64):
+    s = np.zeros(X64.shape[0])
+    for i in range(X64.shape[1]):
+        s += X64[:, i] * X64[:, i]
+    return s
+
+
+def _cs_below(nu2, np2, theta):
+    """Eq. (2) in squares with the oracle's relative slack 2^-36: true when
+    |u| |p| is certainly below theta (theta > 0)."""
+    return theta > 0.0 and (nu2 * np2) * (1.0 + 2.0 ** -36) < theta * theta
+
+
+def _ip64(u, p):
+    acc = 0.0
+    for a, b in zip(u.astype(np.float64), p.astype(np.float64)):
+        acc += a * b
+    return acc
+
+
+def budget_query(U, P, pre, k, N):
+    """Alg. 2 with Inc-RMIPS (Sec. 4.3) on the state of budget_preprocess.
+
+    (1) A user whose k-th value exceeds lambda_i (strictly: an unscanned
+    item with an equal value and a smaller index would outrank it) has
+    S_k = the first k entries of A_i, which are counted; the others form X.
+    (2) Items are visited by (uscore_k desc, index asc); the visit stops at
+    the first item whose uscore_k is below the N-th score (strict, for the
+    index order of ties).  The score of a visited item adds, for each user
+    of X, the decision of Inc-RMIPS:
+      - a scanned item (position <= pos_i) outside the first k entries of
+        A_i is out; one inside them, at rank r, is in when lambda_i is below
+        its value, else the user is rescanned;
+      - an unscanned item is out when Eq. (2), then Eq. (3), puts it below
+        the k-th value, or when its exact value ranks after the k-th entry;
+        otherwise it is in when lambda_i is below its value, else the user
+        is rescanned.
+    A rescan continues the user's scan from pos_i + 1 as in Alg. 1 (kmax
+    list, Eq. 2 stop on the k-th value, Eq. 3 filter) to the exact S_k;
+    the user leaves X, and the items of S_k not yet visited are credited
+    now (the visited ones were decided exactly before).
+    Small inputs only (pure Python over the pairs).
+    Returns (ids, scores, stats)."""
+    U, P = _f32(U), _f32(P)
+    n, m = U.shape[0], P.shape[0]
+    Av, Aj, pos, lam = pre["Av"], pre["Aj"], pre["pos"], pre["lam"]
+    order, nu2, np2 = pre["order"], pre["nu2"], pre["np2"]
+    rot = pre["rot"]
+    kmax = pre["kmax"]
+    posof = np.empty(m, np.int64)
+    posof[order] = np.arange(1, m + 1)
+    us = pre["uscore"][k - 1]
+    score = np.zeros(m, np.int64)
+    X = []
+    for i in range(n):
+        if Av[i, k - 1] > lam[i]:
+            score[Aj[i, :k]] += 1
+        else:
+            X.append(i)
+    x0 = len(X)
+
+    def eq3(u, p):
+        return float(rot["ul"][u] @ rot["pl"][p]) + rot["nru"][u] * rot["nrp"][p] + \
+            rot["s"] * (rot["nu"][u] * rot["np"][p])
+
+    def ranks_before(v1, i1, v2, i2):
+        return v1 > v2 or (v1 == v2 and i1 < i2)
+
+    def decide(u, p):
+        Ak, idk = Av[u, k - 1], int(Aj[u, k - 1])
+        if posof[p] <= pos[u]:
+            hit = np.nonzero(Aj[u, :k] == p)[0]
+            if hit.size == 0:
+                return "out"
+            return "in" if lam[u] < Av[u, hit[0]] else "rescan"
+        if _cs_below(nu2[u], np2[p], Ak):
+            return "out"
+        if eq3(u, p) < Ak:
+            return "out"
+        v = _ip64(U[u], P[p])
+        if not ranks_before(v, p, Ak, idk):
+            return "out"
+        return "in" if lam[u] < v else "rescan"
+
+    def rescan(u):
+        Lv, Lj = list(Av[u]), [int(x) for x in Aj[u]]
+        for j in range(int(pos[u]) + 1, m + 1):
+            p = int(order[j - 1])
+            if _cs_below(nu2[u], np2[p], Lv[k - 1]):
+                break
+            if eq3(u, p) < Lv[kmax - 1]:
+                continue
+            v = _ip64(U[u], P[p])
+            if ranks_before(v, p, Lv[-1], Lj[-1]):
+                t = len(Lv) - 1
+                while t > 0 and ranks_before(v, p, Lv[t - 1], Lj[t - 1]):
+                    Lv[t], Lj[t] = Lv[t - 1], Lj[t - 1]
+                    t -= 1
+                Lv[t], Lj[t] = v, p
+        return Lj[:k]
+
+    visit = np.lexsort((np.arange(m), -us))
+    visited = np.zeros(m, bool)
+    best = []
+    rescans = 0
+    nvis = 0
+    for p in visit:
+        p = int(p)
+        if len(best) == N and us[p] < best[-1][0]:
+            break
+        nvis += 1
+        c = int(score[p])
+        for u in list(X):
+            r = decide(u, p)
+            if r == "in":
+                c += 1
+            elif r == "rescan":
+                rescans += 1
+                X.remove(u)
+                for q in rescan(u):
+                    if q == p:
+                        c += 1
+                    elif not visited[q]:
+                        score[q] += 1
+        visited[p] = True
+        best.append((c, p))
+        best.sort(key=lambda t: (-t[0], t[1]))
+        best = best[:N]
+    ids = np.array([b[1] for b in best], np.int32)
+    sc = np.array([b[0] for b in best], np.int64)
+    return ids, sc, {"X0": x0, "rescans": rescans, "visited": nvis, "X_end": len(X)}
