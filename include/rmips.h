@@ -330,6 +330,129 @@ rmips_status rmips_index_bounds(rmips_ctx *ctx, int64_t n, int64_t m, int32_t d,
                                 int32_t k, int32_t *uscore);
 
 /*
+ * Budgeted index: the paper's offline stage under an inner-product budget
+ * (Sec. 4.2, Alg. 1) and its online stage with incremental reverse k-MIPS
+ * (Sec. 4.3, Alg. 2 with Inc-RMIPS).
+ *
+ * Positions 1..m are the items in descending order of |p|^2 (the FP64 sum
+ * of squares, ties by id).  The build, with B1/n = b1 and the dynamic budget
+ * B2:
+ *  (3) every user's list A_i = its k_max best items of positions 1..b1
+ *      (exact values, order (value desc, id asc)); users whose scan does not
+ *      settle there form U', each with key j' + 1 - b1, j' the first later
+ *      position whose Cauchy-Schwarz bound (Eq. 2) is below its k_max-th
+ *      value (m + 1 if none);
+ *  (4) U' in ascending (key, user) order, rank x_i from 1, gets
+ *      B_{2,i} = floor(f(x_i)) more positions plus the pooled budget B' that
+ *      earlier users left; f is Eq. (4) with beta solved from Eq. (5)
+ *      (RMIPS_BUDGET_EXP) or the uniform, linear and quadratic functions of
+ *      Sec. 5.2, each integrating to B2 over [0, |U'|].  A user whose scan
+ *      ends within b1 + 1 + B_{2,i} + B' has its exact list and leaves the
+ *      rest to B'; the others form U'' with pos_i = that position and B' = 0;
+ *  (5) lambda_i (Eq. 7) over the positions after pos_i up to the first whose
+ *      Eq. (2) bound is below the k_max-th value (Eq. 3 with d' = min(d, 10)
+ *      on a rotation), and uscore_k(p) for every k <= kmax: the first k
+ *      entries of every list plus the users of U'' with Eq. (6) >= A_i^k.
+ * Every "cannot be in" test is strict, so ties follow the id order.  The
+ * build reads the exact k_max-th values of U' (stage (a), screened at
+ * `prec`) to place each scan's end; the index keeps only what the budget
+ * gives (the lists of U'' stop at pos_i).
+ *
+ * The query (Alg. 2) for k <= kmax: users with A_i^k > lambda_i are counted
+ * from their lists; the others form X.  Items are visited in (uscore_k
+ * desc, id asc) order in batches, with the strict stop (an item's uscore_k
+ * below the N-th score); for each visited item Inc-RMIPS decides every user
+ * of X: an item among its first k entries is in when its value exceeds
+ * lambda_i; an unscanned item is out by Eq. (2), Eq. (3) or its exact
+ * value against the k-th entry; any other pair rescans the user, which
+ * gives its exact S_k (stage (a) at `prec`), credits the items not yet
+ * visited and removes it from X.  The result is Def. 3 exactly.
+ *
+ * Index: a caller-owned device buffer of rmips_budget_index_size() bytes
+ * (256-byte aligned), valid while U and P are unchanged; the query takes the
+ * same U, P, n, m, d, kmax.  Scratch: rmips_budget_workspace_size() bytes
+ * (build and query).  1 <= kmax <= min(m, RMIPS_K_MAX), kmax <= b1.
+ */
+typedef enum {
+    RMIPS_BUDGET_EXP = 0,       /* Eq. (4): alpha exp(beta x) + gamma, beta from Eq. (5) */
+    RMIPS_BUDGET_UNIFORM = 1,   /* B2 / |U'| */
+    RMIPS_BUDGET_LINEAR = 2,    /* 2 B2 x / |U'|^2 */
+    RMIPS_BUDGET_QUADRATIC = 3  /* 3 B2 x^2 / |U'|^3 */
+} rmips_budget_kind;
+
+typedef struct {
+    int64_t b1;     /* B1 / n: positions of step (3), >= kmax (more than m: m) */
+    int64_t B2;     /* dynamic budget of step (4), 0 <= B2 <= 2^62 */
+    int32_t kind;   /* rmips_budget_kind */
+    double alpha;   /* Eq. (4), finite, >= 0 (RMIPS_BUDGET_EXP) */
+    double gamma;   /* Eq. (4), finite, >= 0 (RMIPS_BUDGET_EXP) */
+} rmips_budget;
+
+typedef struct {
+    int64_t u_prime;   /* |U'| */
+    int64_t u_dprime;  /* |U''| */
+    int64_t cert3;     /* users settled by step (3) */
+    int64_t cert4;     /* users of U' settled by step (4) */
+    int64_t scanned4;  /* positions scanned in step (4) */
+    double beta;       /* Eq. (5)'s solution (-inf: f = gamma; 0 for other kinds) */
+    float ms_total;    /* build time, HIP events */
+} rmips_budget_info;
+
+typedef struct {
+    int64_t x0;               /* |X| at the start */
+    int64_t rescanned_users;  /* users rescanned (they leave X) */
+    int64_t rescan_calls;     /* batches that rescanned */
+    int64_t visited_items;    /* items Alg. 2 visits one by one up to its stop */
+    int64_t processed_items;  /* items scored (whole batches) */
+    int64_t batches;
+    float ms_init;            /* initialisation and visit order */
+    float ms_total;
+} rmips_budget_qstats;
+
+size_t rmips_budget_index_size(int64_t n, int64_t m, int32_t d, int32_t kmax);
+size_t rmips_budget_workspace_size(int64_t n, int64_t m, int32_t d, int32_t kmax,
+                                   rmips_prec prec);
+
+/*
+ * Build (Alg. 1 under the budget).  U [n x d], P [m x d] device FP32;
+ * budget and info (nullable) host.  Synchronises the stream.  RMIPS_EINVAL
+ * for a bad budget (b1 < kmax, B2 out of range, unknown kind, alpha or
+ * gamma negative or not finite); RMIPS_ENONFINITE for a NaN/Inf or a row
+ * norm above 2^60 (the index is then unusable).
+ */
+rmips_status rmips_budget_build(rmips_ctx *ctx, const float *U, int64_t n, const float *P,
+                                int64_t m, int32_t d, int32_t kmax, rmips_prec prec,
+                                const rmips_budget *budget, void *index, size_t index_bytes,
+                                void *ws, size_t ws_bytes, rmips_budget_info *info);
+
+/*
+ * Def. 3 for k <= kmax by Alg. 2 with Inc-RMIPS on the index: top_ids and
+ * top_scores (host, N each) in (score desc, id asc) order; stats (host,
+ * nullable).  Synchronises the stream (once per batch).  The index's header
+ * is read back first: RMIPS_EINVAL when the buffer does not hold an index
+ * that rmips_budget_build completed with these n, m, d, kmax.
+ */
+rmips_status rmips_budget_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *P,
+                               int64_t m, int32_t d, int32_t kmax, rmips_prec prec,
+                               const void *index, size_t index_bytes, int32_t k, int32_t N,
+                               void *ws, size_t ws_bytes, int32_t *top_ids, int32_t *top_scores,
+                               rmips_budget_qstats *stats);
+
+/*
+ * Copies of the index's state (device pointers, each nullable): order [m]
+ * (position j - 1 -> item id), pos [n] (pos_i, 0 outside U''), lam [n]
+ * (lambda_i, -inf outside U''), Av / Aj [n x kmax] (the lists: values, item
+ * ids), key [n] (j' + 1 - b1, 0 outside U'), rank [n] (x_i, 0 outside U'),
+ * b2 [n] (B_{2,i}, 0 outside U'), uscore [kmax x m] (row k - 1: uscore_k by
+ * item id).  Waits once to read the header (RMIPS_EINVAL as above), then
+ * returns without waiting for the copies.
+ */
+rmips_status rmips_budget_state(rmips_ctx *ctx, int64_t n, int64_t m, int32_t d, int32_t kmax,
+                                const void *index, size_t index_bytes, int32_t *order,
+                                int32_t *pos, double *lam, double *Av, int32_t *Aj, int32_t *key,
+                                int32_t *rank, int64_t *b2, int32_t *uscore);
+
+/*
  * rmips_soft_bwd without a workspace, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving or ascent
  * loops, harnesses that forbid allocation).  Same arguments, kernels and

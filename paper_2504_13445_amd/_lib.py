@@ -30,7 +30,10 @@ EXPORTS = [
     "rmips_soft_bwd", "rmips_soft_bwd_noalloc", "rmips_soft_fwd_grad", "rmips_soft_scale",
     "rmips_index_size", "rmips_index_workspace_size", "rmips_index_build",
     "rmips_index_topn", "rmips_index_thresholds", "rmips_index_bounds",
+    "rmips_budget_index_size", "rmips_budget_workspace_size", "rmips_budget_build",
+    "rmips_budget_topn", "rmips_budget_state",
 ]
+BUDGET_KINDS = {"exp": 0, "uniform": 1, "linear": 2, "quadratic": 3}
 
 
 class RmipsError(RuntimeError):
@@ -52,6 +55,31 @@ class Stats(ctypes.Structure):
                 ("ms_count", ctypes.c_float), ("ms_total", ctypes.c_float),
                 ("ms_screen", ctypes.c_float), ("ms_count_kernels", ctypes.c_float),
                 ("ms_bound_kernel", ctypes.c_float)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Budget(ctypes.Structure):
+    _fields_ = [("b1", ctypes.c_int64), ("B2", ctypes.c_int64), ("kind", ctypes.c_int32),
+                ("alpha", ctypes.c_double), ("gamma", ctypes.c_double)]
+
+
+class BudgetInfo(ctypes.Structure):
+    _fields_ = [("u_prime", ctypes.c_int64), ("u_dprime", ctypes.c_int64),
+                ("cert3", ctypes.c_int64), ("cert4", ctypes.c_int64),
+                ("scanned4", ctypes.c_int64), ("beta", ctypes.c_double),
+                ("ms_total", ctypes.c_float)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class BudgetQStats(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_int64), ("rescanned_users", ctypes.c_int64),
+                ("rescan_calls", ctypes.c_int64), ("visited_items", ctypes.c_int64),
+                ("processed_items", ctypes.c_int64), ("batches", ctypes.c_int64),
+                ("ms_init", ctypes.c_float), ("ms_total", ctypes.c_float)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -136,6 +164,20 @@ def load():
     lib.rmips_index_thresholds.restype = st
     lib.rmips_index_bounds.argtypes = [vp, i64, i64, i32, i32, ctypes.c_int, vp, sz, i32, vp]
     lib.rmips_index_bounds.restype = st
+    lib.rmips_budget_index_size.argtypes = [i64, i64, i32, i32]
+    lib.rmips_budget_index_size.restype = sz
+    lib.rmips_budget_workspace_size.argtypes = [i64, i64, i32, i32, ctypes.c_int]
+    lib.rmips_budget_workspace_size.restype = sz
+    lib.rmips_budget_build.argtypes = [vp, vp, i64, vp, i64, i32, i32, ctypes.c_int,
+                                       ctypes.POINTER(Budget), vp, sz, vp, sz,
+                                       ctypes.POINTER(BudgetInfo)]
+    lib.rmips_budget_build.restype = st
+    lib.rmips_budget_topn.argtypes = [vp, vp, i64, vp, i64, i32, i32, ctypes.c_int, vp, sz,
+                                      i32, i32, vp, sz, vp, vp, ctypes.POINTER(BudgetQStats)]
+    lib.rmips_budget_topn.restype = st
+    lib.rmips_budget_state.argtypes = [vp, i64, i64, i32, i32, vp, sz, vp, vp, vp, vp, vp, vp,
+                                       vp, vp, vp]
+    lib.rmips_budget_state.restype = st
     _lib = lib
     return lib
 
@@ -405,6 +447,75 @@ class Index:
         ctx = _context(self.U.device)
         out = torch.empty(self.m, dtype=torch.int32, device=self.U.device)
         _check(ctx, lib.rmips_index_bounds(ctx, *self._args(), int(k), _ptr(out)))
+        return out
+
+
+class BudgetIndex:
+    """The budgeted index (rmips_budget_build: Alg. 1 under an inner-product
+    budget, Sec. 4.2) over device tensors U and P; topn() runs Alg. 2 with
+    Inc-RMIPS (Sec. 4.3) for any k <= kmax.  b1 = B1/n positions per user in
+    step (3), B2 the dynamic budget, kind one of "exp" (Eq. 4, beta from
+    Eq. 5), "uniform", "linear", "quadratic"."""
+
+    def __init__(self, U, P, kmax, b1, B2, kind="exp", alpha=1.0, gamma=0.0, prec="fp32"):
+        U, P = _dev_f32(U, "U"), _dev_f32(P, "P")
+        if P.shape[1] != U.shape[1]:
+            raise ValueError("U and P must have the same number of columns")
+        self.U, self.P = U, P
+        self.n, self.d = U.shape
+        self.m = P.shape[0]
+        self.kmax, self.prec, self.p = int(kmax), prec, PREC[prec]
+        lib = load()
+        ctx = _context(U.device)
+        self.buf = _workspace(lib.rmips_budget_index_size(self.n, self.m, self.d, self.kmax),
+                              U.device)
+        self.ws = _workspace(lib.rmips_budget_workspace_size(self.n, self.m, self.d, self.kmax,
+                                                             self.p), U.device)
+        bud = Budget(int(b1), int(B2), BUDGET_KINDS[kind], float(alpha), float(gamma))
+        info = BudgetInfo()
+        _check(ctx, lib.rmips_budget_build(ctx, _ptr(U), self.n, _ptr(P), self.m, self.d,
+                                           self.kmax, self.p, ctypes.byref(bud), _ptr(self.buf),
+                                           self.buf.numel(), _ptr(self.ws), self.ws.numel(),
+                                           ctypes.byref(info)))
+        self.info = info.as_dict()
+
+    def topn(self, k, N):
+        """Top-N ids and scores (host int32 numpy arrays) for this k, and stats."""
+        import numpy as np
+        lib = load()
+        ctx = _context(self.U.device)
+        ids = np.empty(N, np.int32)
+        sc = np.empty(N, np.int32)
+        st = BudgetQStats()
+        _check(ctx, lib.rmips_budget_topn(ctx, _ptr(self.U), self.n, _ptr(self.P), self.m,
+                                          self.d, self.kmax, self.p, _ptr(self.buf),
+                                          self.buf.numel(), int(k), int(N), _ptr(self.ws),
+                                          self.ws.numel(), ids.ctypes.data_as(ctypes.c_void_p),
+                                          sc.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st)))
+        return ids, sc, st.as_dict()
+
+    def state(self):
+        """The index's per-user and per-item state as device tensors: order,
+        pos, lam, Av, Aj, key, rank, b2, uscore (kmax x m)."""
+        lib = load()
+        ctx = _context(self.U.device)
+        dev = self.U.device
+        n, m, kx = self.n, self.m, self.kmax
+        out = {
+            "order": torch.empty(m, dtype=torch.int32, device=dev),
+            "pos": torch.empty(n, dtype=torch.int32, device=dev),
+            "lam": torch.empty(n, dtype=torch.float64, device=dev),
+            "Av": torch.empty((n, kx), dtype=torch.float64, device=dev),
+            "Aj": torch.empty((n, kx), dtype=torch.int32, device=dev),
+            "key": torch.empty(n, dtype=torch.int32, device=dev),
+            "rank": torch.empty(n, dtype=torch.int32, device=dev),
+            "b2": torch.empty(n, dtype=torch.int64, device=dev),
+            "uscore": torch.empty((kx, m), dtype=torch.int32, device=dev),
+        }
+        _check(ctx, lib.rmips_budget_state(ctx, n, m, self.d, kx, _ptr(self.buf),
+                                           self.buf.numel(), *[_ptr(out[k]) for k in (
+                                               "order", "pos", "lam", "Av", "Aj", "key", "rank",
+                                               "b2", "uscore")]))
         return out
 
 

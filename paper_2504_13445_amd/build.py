@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librmips.so")
-SOURCES = ["sort.hip", "prep.hip", "thresh.hip", "count.hip", "soft.hip", "rmips.cpp"]
+SOURCES = ["sort.hip", "prep.hip", "thresh.hip", "count.hip", "soft.hip", "budget.hip", "rmips.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -237,4 +237,82 @@ size_t soft_ws_bytes(int64_t n, int64_t nq, int d);
 hipError_t soft_scratch_init(int device, void **out);
 bool soft_noalloc_fits(int64_t nq, int d);
 
+
+// ------------------------------------------------------ budgeted index
+// (Alg. 1 under an inner-product budget, Sec. 4.2; Alg. 2 with Inc-RMIPS,
+// Sec. 4.3).  Positions are 1-based in the descending order of the FP64 sum
+// of squares (ties by item id); "position order" arrays hold position j at
+// index j - 1.
+constexpr int BUDGET_DP_MAX = 16;      // largest d' of the index's Eq. (3)
+constexpr int BUDGET_BATCH_MAX = 256;  // items per visited batch of a query
+// x2[r] = FP64 sum of squares of row r (index order)
+void launch_sqnorm64(const float *X, int64_t rows, int d, double *x2, hipStream_t st);
+// rotated coordinates l = W x (dp values), remaining norm and norm (both
+// rounded up) of the rows X[order[r]] (order may be NULL)
+void launch_budget_rotate(const float *X, const int32_t *order, const double *x2_by_row,
+                          int64_t rows, int d, const double *W, int dp, double *L, double *nr,
+                          double *nn, hipStream_t st);
+// Y[r] = X[idx[r]], rows of d floats
+void launch_budget_gather(const float *X, const int32_t *idx, int64_t rows, int d, float *Y,
+                          hipStream_t st);
+// the kmax best (value desc, id asc) of positions 1..lim of each listed user
+// (users NULL: all; lims NULL: lim0), exact, into the user's row of Av / Aj;
+// Pg holds the items' rows in position order
+void launch_budget_prefix(const float *U, const float *Pg, const int32_t *order, int d,
+                          const int32_t *users, const int32_t *lims, int64_t lim0,
+                          int64_t nusers, int kmax, double *Av, int32_t *Aj, hipStream_t st);
+// key[u] = j' + 1 - b1 for a user whose first b1 positions did not settle
+// its list, else 0
+void launch_budget_classify(const double *Av, const double *nu2, const double *np2s, int64_t n,
+                            int64_t m, int kmax, int64_t b1, int32_t *key, hipStream_t st);
+// t[r] = natural stop of users[r] from its exact kmax-th value (topv row r)
+void launch_budget_tstop(const int32_t *users, const double *topv, const double *nu2,
+                         const double *np2s, int64_t X, int64_t m, int kmax, int64_t b1,
+                         int32_t *t, hipStream_t st);
+// exact lists (rows of topv/topk) to the users among `users` with pos 0
+void launch_budget_scatter(const int32_t *users, const int32_t *pos, const double *topv,
+                           const int32_t *topk, int64_t X, int kmax, double *Av, int32_t *Aj,
+                           hipStream_t st);
+// step (5): lambda of each listed user and the Eq. (6) counts into the
+// difference table diff (kmax x m, by item id)
+void launch_budget_step5(const int32_t *users, const int32_t *pos, int64_t nusers,
+                         const double *Av, const double *nu2, const double *Ul,
+                         const double *nru, const double *nun, const double *np2s,
+                         const double *Pl, const double *nrp, const double *npn,
+                         const int32_t *order, int64_t m, int kmax, int dp, double *lam,
+                         int32_t *diff, hipStream_t st);
+// the lists' entries into the difference table (entry r -> row r)
+void launch_budget_hist(const int32_t *Aj, int64_t n, int kmax, int64_t m, int32_t *diff,
+                        hipStream_t st);
+// difference table -> uscore (prefix sums over k, in place)
+void launch_budget_prefix_k(int32_t *t, int64_t m, int kmax, hipStream_t st);
+// query: certified users into base, the others into X (count in *xn)
+void launch_budget_xinit(const double *Av, const int32_t *Aj, const double *lam, int64_t n,
+                         int kmax, int k, int32_t *base, int32_t *X, int32_t *xn,
+                         hipStream_t st);
+void launch_budget_slots(const int32_t *bids, int nb, int32_t *slot, hipStream_t st);
+// Inc-RMIPS of X against a batch: ins into cnt (by batch slot), users that
+// need a rescan into R (count in *rn) with xflag set
+void launch_budget_inc(const int32_t *X, int64_t xn, const int32_t *bids, int nb,
+                       const int32_t *slot, const float *U, const float *P, int d,
+                       const double *Av, const int32_t *Aj, const double *lam,
+                       const int32_t *pos, const double *nu2, const double *Ul,
+                       const double *nru, const double *nun, const int32_t *posof,
+                       const double *np2s, const double *Pl, const double *nrp,
+                       const double *npn, int kmax, int k, int dp, int32_t *cnt, int32_t *R,
+                       int32_t *rn, uint8_t *xflag, hipStream_t st);
+// rescanned users' S_k (nr rows of k ids): unvisited items into base
+void launch_budget_apply(const int32_t *topk, int64_t nr, int k, const uint8_t *visited,
+                         int32_t *base, hipStream_t st);
+void launch_budget_xcompact(const int32_t *X, int64_t xn, const uint8_t *xflag, int32_t *Y,
+                            int32_t *yn, hipStream_t st);
+// score[s] = base + cnt of the batch's items; marks them visited, clears
+// their slots and counts
+void launch_budget_batch(const int32_t *bids, int nb, const int32_t *base, int32_t *cnt,
+                         uint8_t *visited, int32_t *slot, int32_t *score, hipStream_t st);
+void launch_budget_visit_keys(const int32_t *us, int64_t m, uint32_t *key, int32_t *val,
+                              hipStream_t st);
+void launch_fill_i32(int32_t *x, int64_t n, int32_t v, hipStream_t st);
+void launch_fill_f64(double *x, int64_t n, double v, hipStream_t st);
+
 }  // namespace rmips

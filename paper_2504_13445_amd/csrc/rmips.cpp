@@ -781,6 +781,164 @@ rmips_status run_count_topn(rmips_ctx *ctx, const float *U, const float *P,
     return RMIPS_OK;
 }
 
+
+// ------------------------------------------------------- budgeted index
+// Alg. 1 under an inner-product budget (Sec. 4.2) and Alg. 2 with
+// Inc-RMIPS (Sec. 4.3).  Positions j = 1..m are the items in descending
+// order of the FP64 sum of squares (ties by id).
+constexpr int32_t BUDGET_MAGIC = 0x42554400;  // with a version in the low byte
+constexpr int BUDGET_HDR_WORDS = 16;
+constexpr int H_BHDR = 96;   // pinned status words that receive the header
+constexpr int H_BCTR = 112;  // pinned status words for a query's counters
+constexpr int BUDGET_DP = 10;  // d' of Eq. (3) in the paper's experiments (Sec. 5.1)
+int budget_dp(int d) { return std::min(d, BUDGET_DP); }
+
+struct BudgetLayout {
+    int32_t *hdr;
+    double *info;                  // the build's figures (rmips_budget_info)
+    int32_t *order, *posof;        // position - 1 -> id, id -> position - 1
+    double *np2s, *Pl, *nrp, *npn; // items in position order: |p|^2, Eq. (3) data
+    double *nu2, *Ul, *nru, *nun;  // users: |u|^2, Eq. (3) data
+    double *W;                     // the rotation's first dp rows (dp x d)
+    double *Av;                    // lists A_i: values (n x kmax)
+    int32_t *Aj;                   //            item ids
+    int32_t *pos;                  // pos_i for users of U'', else 0
+    double *lam;                   // lambda_i (Eq. 7) for users of U'', else -inf
+    int32_t *key, *rank;           // j' + 1 - b1 and x_i for users of U', else 0
+    int64_t *b2;                   // B_{2,i} for users of U', else 0
+    int32_t *uscore;               // uscore_k(p): kmax x m, by item id
+};
+
+void budget_plan(int64_t n, int64_t m, int d, int kmax, BudgetLayout &B, Carve &cv) {
+    const int dp = budget_dp(d);
+    B.hdr = cv.take<int32_t>(BUDGET_HDR_WORDS);
+    B.info = cv.take<double>(8);
+    B.order = cv.take<int32_t>(m);
+    B.posof = cv.take<int32_t>(m);
+    B.np2s = cv.take<double>(m);
+    B.Pl = cv.take<double>((size_t)m * dp);
+    B.nrp = cv.take<double>(m);
+    B.npn = cv.take<double>(m);
+    B.nu2 = cv.take<double>(n);
+    B.Ul = cv.take<double>((size_t)n * dp);
+    B.nru = cv.take<double>(n);
+    B.nun = cv.take<double>(n);
+    B.W = cv.take<double>((size_t)dp * d);
+    B.Av = cv.take<double>((size_t)n * kmax);
+    B.Aj = cv.take<int32_t>((size_t)n * kmax);
+    B.pos = cv.take<int32_t>(n);
+    B.lam = cv.take<double>(n);
+    B.key = cv.take<int32_t>(n);
+    B.rank = cv.take<int32_t>(n);
+    B.b2 = cv.take<int64_t>(n);
+    B.uscore = cv.take<int32_t>((size_t)kmax * m);
+}
+
+void budget_header(int64_t n, int64_t m, int d, int kmax, int32_t (&h)[BUDGET_HDR_WORDS]) {
+    std::memset(h, 0, sizeof(h));
+    h[0] = BUDGET_MAGIC | 1;
+    h[1] = (int32_t)n;
+    h[2] = (int32_t)m;
+    h[3] = d;
+    h[4] = kmax;
+    h[5] = budget_dp(d);
+}
+
+// Scratch of a build and of a query (one workspace serves both): stage (a)
+// for up to n users with k <= kmax, gathered rows, and the query's sets.
+struct BudgetScratch {
+    ThreshLayout T;
+    float *Pg;           // item rows in position order
+    double *np2;         // item sums of squares by id
+    float *Ug;           // gathered user rows (U' at the build, rescans at a query)
+    double *topv, *tau;
+    int32_t *topk, *tau_id;
+    int32_t *ux, *t, *u2, *lims;
+    double *G, *Gs;
+    int32_t *X, *X2, *R, *ctr;
+    uint8_t *xflag, *visited;
+    int32_t *base, *slot, *cnt, *score;
+    uint32_t *vkey;
+    int32_t *vval;
+    void *vsort;
+};
+
+void budget_scratch_plan(int prec, int64_t n, int64_t m, int d, int kmax, int cap_override,
+                         BudgetScratch &S, Carve &cv) {
+    thresh_plan(prec, n, m, d, kmax, cap_override, S.T, cv);
+    S.Pg = cv.take<float>((size_t)m * d);
+    S.np2 = cv.take<double>(m);
+    S.Ug = cv.take<float>((size_t)n * d);
+    S.topv = cv.take<double>((size_t)n * kmax);
+    S.topk = cv.take<int32_t>((size_t)n * kmax);
+    S.tau = cv.take<double>(n);
+    S.tau_id = cv.take<int32_t>(n);
+    S.ux = cv.take<int32_t>(n);
+    S.t = cv.take<int32_t>(n);
+    S.u2 = cv.take<int32_t>(n);
+    S.lims = cv.take<int32_t>(n);
+    S.G = cv.take<double>((size_t)d * d);
+    S.Gs = reinterpret_cast<double *>(cv.take<uint8_t>(gram_scratch_bytes(d)));
+    S.X = cv.take<int32_t>(n);
+    S.X2 = cv.take<int32_t>(n);
+    S.R = cv.take<int32_t>(n);
+    S.ctr = cv.take<int32_t>(64);
+    S.xflag = cv.take<uint8_t>(n);
+    S.visited = cv.take<uint8_t>(m);
+    S.base = cv.take<int32_t>(m);
+    S.slot = cv.take<int32_t>(m);
+    S.cnt = cv.take<int32_t>(BUDGET_BATCH_MAX);
+    S.score = cv.take<int32_t>(BUDGET_BATCH_MAX);
+    S.vkey = cv.take<uint32_t>(m);
+    S.vval = cv.take<int32_t>(m);
+    S.vsort = cv.take<uint8_t>(radix_sort_scratch_bytes(m));
+}
+
+// beta of Eq. (5): alpha (exp(beta X) - 1) / beta + gamma X = B2.  The left
+// side grows with beta from gamma X (beta -> -inf) without bound, so the
+// root is bracketed by doubling and halved down to adjacent doubles; -inf
+// when B2 <= gamma X (then f(x) = gamma).
+double budget_solve_beta(double X, double B2, double alpha, double gamma) {
+    const double want = B2 - gamma * X;
+    if (!(want > 0.0) || !(alpha > 0.0)) return -INFINITY;
+    auto g = [&](double b) { return b == 0.0 ? alpha * X : alpha * std::expm1(b * X) / b; };
+    const double g0 = g(0.0);
+    if (g0 == want) return 0.0;
+    double lo, hi;
+    if (g0 < want) {
+        lo = 0.0;
+        hi = 1.0 / X;
+        while (g(hi) < want) hi *= 2.0;
+    } else {
+        hi = 0.0;
+        lo = -1.0 / X;
+        while (g(lo) > want) lo *= 2.0;
+    }
+    for (int it = 0; it < 400; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid == lo || mid == hi) break;
+        (g(mid) < want ? lo : hi) = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+// The budget B_{2,i} = floor(f(x)) of the user of rank x among X users of
+// U' (at most 2^40): Eq. (4), or the uniform, linear and quadratic
+// functions of Sec. 5.2, each with integral B2 over [0, X].
+int64_t budget_items(int kind, double x, double X, double B2, double alpha, double beta,
+                     double gamma) {
+    double f;
+    switch (kind) {
+    case RMIPS_BUDGET_EXP: f = alpha * std::exp(beta * x) + gamma; break;
+    case RMIPS_BUDGET_UNIFORM: f = B2 / X; break;
+    case RMIPS_BUDGET_LINEAR: f = 2.0 * B2 * x / (X * X); break;
+    default: f = 3.0 * B2 * x * x / (X * X * X); break;
+    }
+    if (!(f > 0.0)) return 0;
+    if (f >= 1099511627776.0) return 1099511627776LL;
+    return (int64_t)std::floor(f);
+}
+
 }  // namespace
 
 // ====================================================================== C ABI
@@ -1457,6 +1615,420 @@ rmips_status rmips_soft_scale(rmips_ctx *ctx, const float *G, int64_t nq, int32_
 size_t rmips_soft_workspace_size(int64_t n, int64_t nq, int32_t d) {
     if (n < 1 || nq < 1 || d < 1 || d > RMIPS_D_MAX) return 0;
     return soft_ws_bytes(n, nq, d);
+}
+
+
+// ------------------------------------------------------- budgeted index
+static bool budget_sizes_ok(int64_t n, int64_t m, int32_t d, int32_t kmax) {
+    return n >= 1 && n <= (int64_t)INT32_MAX / 2 && m >= 1 && m <= (int64_t)INT32_MAX / 2 &&
+           d >= 1 && d <= RMIPS_D_MAX && kmax >= 1 && kmax <= RMIPS_K_MAX && kmax <= m;
+}
+
+size_t rmips_budget_index_size(int64_t n, int64_t m, int32_t d, int32_t kmax) {
+    if (!budget_sizes_ok(n, m, d, kmax)) return 0;
+    Carve c(nullptr);
+    BudgetLayout B;
+    budget_plan(n, m, d, kmax, B, c);
+    return c.off + 256;
+}
+
+size_t rmips_budget_workspace_size(int64_t n, int64_t m, int32_t d, int32_t kmax,
+                                   rmips_prec prec) {
+    if (!budget_sizes_ok(n, m, d, kmax) || !prec_ok(prec)) return 0;
+    Carve c(nullptr);
+    BudgetScratch S;
+    budget_scratch_plan(prec, n, m, d, kmax, 0, S, c);
+    return c.off + 256;
+}
+
+static rmips_status budget_args(rmips_ctx *ctx, int64_t n, int64_t m, int32_t d, int32_t kmax,
+                                rmips_prec prec, const void *index, size_t index_bytes,
+                                const void *ws, size_t ws_bytes) {
+    if (!ctx) return RMIPS_EINVAL;
+    if (!budget_sizes_ok(n, m, d, kmax))
+        return fail(ctx, RMIPS_EINVAL, "sizes out of range (1 <= kmax <= min(m, 32))");
+    if (!prec_ok(prec)) return fail(ctx, RMIPS_EUNSUPPORTED, "unknown screening precision");
+    if (!index || !ws) return fail(ctx, RMIPS_EINVAL, "null pointer");
+    if (index_bytes < rmips_budget_index_size(n, m, d, kmax))
+        return fail(ctx, RMIPS_EWORKSPACE, "index buffer too small");
+    {
+        Carve c(nullptr);
+        BudgetScratch S;
+        budget_scratch_plan(prec, n, m, d, kmax, ctx->cap_override, S, c);
+        if (ws_bytes < c.off + 256) return fail(ctx, RMIPS_EWORKSPACE, "workspace too small");
+    }
+    return RMIPS_OK;
+}
+
+static rmips_status check_budget_header(rmips_ctx *ctx, const int32_t *hdr_dev, int64_t n,
+                                        int64_t m, int32_t d, int32_t kmax) {
+    HIPTRY(hipMemcpyAsync(ctx->h_status + H_BHDR, hdr_dev, sizeof(int32_t) * BUDGET_HDR_WORDS,
+                          hipMemcpyDeviceToHost, ctx->stream));
+    HIPTRY(hipStreamSynchronize(ctx->stream));
+    int32_t want[BUDGET_HDR_WORDS];
+    budget_header(n, m, d, kmax, want);
+    if (std::memcmp(ctx->h_status + H_BHDR, want, sizeof(want)) != 0)
+        return fail(ctx, RMIPS_EINVAL,
+                    "index not built by rmips_budget_build with these n, m, d, kmax");
+    return RMIPS_OK;
+}
+
+rmips_status rmips_budget_build(rmips_ctx *ctx, const float *U, int64_t n, const float *P,
+                                int64_t m, int32_t d, int32_t kmax, rmips_prec prec,
+                                const rmips_budget *budget, void *index, size_t index_bytes,
+                                void *ws, size_t ws_bytes, rmips_budget_info *info) {
+    rmips_status s = budget_args(ctx, n, m, d, kmax, prec, index, index_bytes, ws, ws_bytes);
+    if (s != RMIPS_OK) return s;
+    if (!U || !P || !budget) return fail(ctx, RMIPS_EINVAL, "null pointer");
+    const rmips_budget bud = *budget;
+    if (bud.b1 < kmax) return fail(ctx, RMIPS_EINVAL, "b1 below kmax");
+    if (bud.B2 < 0 || bud.B2 > ((int64_t)1 << 62)) return fail(ctx, RMIPS_EINVAL, "B2 out of range");
+    if (bud.kind < RMIPS_BUDGET_EXP || bud.kind > RMIPS_BUDGET_QUADRATIC)
+        return fail(ctx, RMIPS_EINVAL, "unknown budget function");
+    if (!(bud.alpha >= 0.0) || !(bud.gamma >= 0.0) || !std::isfinite(bud.alpha) ||
+        !std::isfinite(bud.gamma))
+        return fail(ctx, RMIPS_EINVAL, "alpha and gamma must be finite and >= 0");
+    const int64_t b1 = std::min<int64_t>(bud.b1, m);
+    HIPTRY(hipSetDevice(ctx->device));
+    ProfGuard pguard(ctx);
+    hipStream_t st = ctx->stream;
+    Carve ci(index), cw(ws);
+    BudgetLayout B;
+    budget_plan(n, m, d, kmax, B, ci);
+    BudgetScratch S;
+    budget_scratch_plan(prec, n, m, d, kmax, ctx->cap_override, S, cw);
+    const int dp = budget_dp(d);
+    hipEvent_t ev[2] = {};
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard() { for (int i = 0; i < 2; ++i) if (e[i]) (void)hipEventDestroy(e[i]); }
+    } guard{ev};
+    for (auto &e : ev) HIPTRY(hipEventCreate(&e));
+    HIPTRY(hipEventRecord(ev[0], st));
+    // no valid header until the build has succeeded
+    HIPTRY(hipMemsetAsync(B.hdr, 0, sizeof(int32_t) * BUDGET_HDR_WORDS, st));
+
+    // (1) norms and the norm order
+    launch_sqnorm64(U, n, d, B.nu2, st);
+    launch_sqnorm64(P, m, d, S.np2, st);
+    std::vector<double> nu2h(n), np2(m);
+    HIPTRY(hipMemcpyAsync(nu2h.data(), B.nu2, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    HIPTRY(hipMemcpyAsync(np2.data(), S.np2, sizeof(double) * m, hipMemcpyDeviceToHost, st));
+    HIPTRY(hipStreamSynchronize(st));
+    const double big = std::ldexp(1.0, 120);  // norms up to 2^60
+    for (double x : nu2h)
+        if (!(x <= big)) return fail(ctx, RMIPS_ENONFINITE, BAD_INPUT);
+    for (double x : np2)
+        if (!(x <= big)) return fail(ctx, RMIPS_ENONFINITE, BAD_INPUT);
+    std::vector<int32_t> order(m), posof(m);
+    for (int64_t j = 0; j < m; ++j) order[j] = (int32_t)j;
+    std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return np2[a] > np2[b] || (np2[a] == np2[b] && a < b);
+    });
+    std::vector<double> np2s(m);
+    for (int64_t j = 0; j < m; ++j) {
+        posof[order[j]] = (int32_t)j;
+        np2s[j] = np2[order[j]];
+    }
+    HIPTRY(hipMemcpyAsync(B.order, order.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, st));
+    HIPTRY(hipMemcpyAsync(B.posof, posof.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, st));
+    HIPTRY(hipMemcpyAsync(B.np2s, np2s.data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
+
+    // (2) the rotation of Eq. (3): the dominant eigenvectors of a sampled
+    // Gram matrix of U (any orthonormal rows keep the bound)
+    {
+        const int64_t ns = std::min<int64_t>(n, GRAM_SAMPLE);
+        launch_gram(U, ns, n / ns, d, S.G, S.Gs, st);
+        std::vector<double> G((size_t)d * d), W;
+        HIPTRY(hipMemcpyAsync(G.data(), S.G, sizeof(double) * d * d, hipMemcpyDeviceToHost, st));
+        HIPTRY(hipStreamSynchronize(st));
+        top_eigvecs(G, d, dp, W);
+        HIPTRY(hipMemcpyAsync(B.W, W.data(), sizeof(double) * dp * d, hipMemcpyHostToDevice, st));
+        HIPTRY(hipStreamSynchronize(st));  // W is a local vector
+    }
+    launch_budget_rotate(U, nullptr, B.nu2, n, d, B.W, dp, B.Ul, B.nru, B.nun, st);
+    launch_budget_rotate(P, B.order, S.np2, m, d, B.W, dp, B.Pl, B.nrp, B.npn, st);
+    launch_budget_gather(P, B.order, m, d, S.Pg, st);
+
+    // (3) uniform budget: positions 1..b1 for every user, then U' with its
+    // keys j' + 1 - b1
+    launch_budget_prefix(U, S.Pg, B.order, d, nullptr, nullptr, b1, n, kmax, B.Av, B.Aj, st);
+    launch_budget_classify(B.Av, B.nu2, B.np2s, n, m, kmax, b1, B.key, st);
+    std::vector<int32_t> key(n);
+    HIPTRY(hipMemcpyAsync(key.data(), B.key, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+    HIPTRY(hipStreamSynchronize(st));
+    // U' in ascending (key, user) order: a counting sort over the keys
+    std::vector<int64_t> start((size_t)(m + 3), 0);
+    int64_t X = 0;
+    for (int64_t u = 0; u < n; ++u)
+        if (key[u] > 0) {
+            ++start[key[u] + 1];
+            ++X;
+        }
+    for (size_t i = 1; i < start.size(); ++i) start[i] += start[i - 1];
+    std::vector<int32_t> ux(X);
+    for (int64_t u = 0; u < n; ++u)
+        if (key[u] > 0) ux[start[key[u]]++] = (int32_t)u;
+    const double beta = (bud.kind == RMIPS_BUDGET_EXP && X > 0)
+                            ? budget_solve_beta((double)X, (double)bud.B2, bud.alpha, bud.gamma)
+                            : 0.0;
+
+    // (4) dynamic budget.  A scan of user i stops at its natural stop t_i:
+    // the first position whose Eq. (2) bound is below its exact k_max-th
+    // value (stage (a) once over U'), so the budget recurrence with the
+    // pooled budget B' needs only t_i.
+    std::vector<int32_t> t(X), pos(n, 0), rank(n, 0), u2, lims;
+    std::vector<int64_t> b2(n, 0);
+    int64_t cert4 = 0, scanned4 = 0;
+    if (X > 0) {
+        HIPTRY(hipMemcpyAsync(S.ux, ux.data(), sizeof(int32_t) * X, hipMemcpyHostToDevice, st));
+        launch_budget_gather(U, S.ux, X, d, S.Ug, st);
+        s = run_thresholds(ctx, S.Ug, X, P, m, d, kmax, S.T, S.tau, S.tau_id, S.topk, S.topv);
+        if (s != RMIPS_OK) return s;
+        launch_budget_tstop(S.ux, S.topv, B.nu2, B.np2s, X, m, kmax, b1, S.t, st);
+        HIPTRY(hipMemcpyAsync(t.data(), S.t, sizeof(int32_t) * X, hipMemcpyDeviceToHost, st));
+        HIPTRY(hipMemcpyAsync(ctx->h_status, S.T.bad, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPTRY(hipStreamSynchronize(st));
+        if (ctx->h_status[0] != 0) return fail(ctx, RMIPS_ENONFINITE, BAD_INPUT);
+        int64_t pool = 0;
+        for (int64_t r = 0; r < X; ++r) {
+            const int32_t u = ux[r];
+            rank[u] = (int32_t)(r + 1);
+            b2[u] = budget_items(bud.kind, (double)(r + 1), (double)X, (double)bud.B2,
+                                 bud.alpha, beta, bud.gamma);
+            const int64_t e = b1 + 1 + b2[u] + pool;
+            if (t[r] <= e) {  // the scan stops within the budget: its list is exact
+                pool = e - t[r];
+                ++cert4;
+                scanned4 += t[r] - (b1 + 1);
+            } else {          // budget spent: pos_i = e (<= m), U''
+                pos[u] = (int32_t)e;
+                u2.push_back(u);
+                lims.push_back((int32_t)e);
+                pool = 0;
+                scanned4 += e - b1;
+            }
+        }
+    }
+    const int64_t nU2 = (int64_t)u2.size();
+    HIPTRY(hipMemcpyAsync(B.pos, pos.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+    HIPTRY(hipMemcpyAsync(B.rank, rank.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+    HIPTRY(hipMemcpyAsync(B.b2, b2.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, st));
+    launch_budget_scatter(S.ux, B.pos, S.topv, S.topk, X, kmax, B.Av, B.Aj, st);
+    if (nU2 > 0) {
+        HIPTRY(hipMemcpyAsync(S.u2, u2.data(), sizeof(int32_t) * nU2, hipMemcpyHostToDevice, st));
+        HIPTRY(hipMemcpyAsync(S.lims, lims.data(), sizeof(int32_t) * nU2, hipMemcpyHostToDevice,
+                              st));
+        launch_budget_prefix(U, S.Pg, B.order, d, S.u2, S.lims, 0, nU2, kmax, B.Av, B.Aj, st);
+    }
+
+    // (5) lambda_i and uscore_k: Eq. (6) over the unscanned positions of U'',
+    // then the first k entries of every list
+    launch_fill_f64(B.lam, n, -INFINITY, st);
+    HIPTRY(hipMemsetAsync(B.uscore, 0, sizeof(int32_t) * kmax * m, st));
+    launch_budget_step5(S.u2, B.pos, nU2, B.Av, B.nu2, B.Ul, B.nru, B.nun, B.np2s, B.Pl, B.nrp,
+                        B.npn, B.order, m, kmax, dp, B.lam, B.uscore, st);
+    launch_budget_hist(B.Aj, n, kmax, m, B.uscore, st);
+    launch_budget_prefix_k(B.uscore, m, kmax, st);
+    const int64_t cert3 = n - X;
+    double inf[8] = {(double)X, (double)nU2, beta, (double)cert3, (double)cert4,
+                     (double)scanned4, (double)b1, (double)bud.B2};
+    HIPTRY(hipMemcpyAsync(B.info, inf, sizeof(inf), hipMemcpyHostToDevice, st));
+    HIPTRY(hipEventRecord(ev[1], st));
+    HIPTRY(hipGetLastError());
+    HIPTRY(hipStreamSynchronize(st));
+    ctx->prof.resolve();
+    int32_t *hdr = ctx->h_status + H_BHDR;  // pinned
+    int32_t want[BUDGET_HDR_WORDS];
+    budget_header(n, m, d, kmax, want);
+    std::memcpy(hdr, want, sizeof(want));
+    HIPTRY(hipMemcpyAsync(B.hdr, hdr, sizeof(want), hipMemcpyHostToDevice, st));
+    HIPTRY(hipStreamSynchronize(st));
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->u_prime = X;
+        info->u_dprime = nU2;
+        info->cert3 = cert3;
+        info->cert4 = cert4;
+        info->scanned4 = scanned4;
+        info->beta = beta;
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
+        info->ms_total = ms;
+    }
+    return RMIPS_OK;
+}
+
+rmips_status rmips_budget_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *P,
+                               int64_t m, int32_t d, int32_t kmax, rmips_prec prec,
+                               const void *index, size_t index_bytes, int32_t k, int32_t N,
+                               void *ws, size_t ws_bytes, int32_t *top_ids, int32_t *top_scores,
+                               rmips_budget_qstats *stats) {
+    rmips_status s = budget_args(ctx, n, m, d, kmax, prec, index, index_bytes, ws, ws_bytes);
+    if (s != RMIPS_OK) return s;
+    if (k < 1 || k > kmax) return fail(ctx, RMIPS_EINVAL, "k out of range (1 <= k <= kmax)");
+    if (N < 1 || N > RMIPS_N_MAX || N > m) return fail(ctx, RMIPS_EINVAL, "N out of range");
+    if (!U || !P || !top_ids || !top_scores) return fail(ctx, RMIPS_EINVAL, "null pointer");
+    HIPTRY(hipSetDevice(ctx->device));
+    ProfGuard pguard(ctx);
+    hipStream_t st = ctx->stream;
+    Carve ci(const_cast<void *>(index)), cw(ws);
+    BudgetLayout B;
+    budget_plan(n, m, d, kmax, B, ci);
+    BudgetScratch S;
+    budget_scratch_plan(prec, n, m, d, kmax, ctx->cap_override, S, cw);
+    s = check_budget_header(ctx, B.hdr, n, m, d, kmax);
+    if (s != RMIPS_OK) return s;
+    const int dp = budget_dp(d);
+    hipEvent_t ev[3] = {};
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard() { for (int i = 0; i < 3; ++i) if (e[i]) (void)hipEventDestroy(e[i]); }
+    } guard{ev};
+    for (auto &e : ev) HIPTRY(hipEventCreate(&e));
+    HIPTRY(hipEventRecord(ev[0], st));
+    // (1) initialisation: certified users into the scores, the others into X
+    HIPTRY(hipMemsetAsync(S.base, 0, sizeof(int32_t) * m, st));
+    HIPTRY(hipMemsetAsync(S.visited, 0, m, st));
+    HIPTRY(hipMemsetAsync(S.xflag, 0, n, st));
+    HIPTRY(hipMemsetAsync(S.cnt, 0, sizeof(int32_t) * BUDGET_BATCH_MAX, st));
+    HIPTRY(hipMemsetAsync(S.ctr, 0, sizeof(int32_t) * 64, st));
+    launch_fill_i32(S.slot, m, -1, st);
+    launch_budget_xinit(B.Av, B.Aj, B.lam, n, kmax, k, S.base, S.X, S.ctr, st);
+    // (2) the visit order: (uscore_k desc, id asc)
+    launch_budget_visit_keys(B.uscore + (size_t)(k - 1) * m, m, S.vkey, S.vval, st);
+    HIPTRY(radix_sort_u32(S.vkey, S.vval, m, S.vsort, st));
+    std::vector<uint32_t> vkey(m);
+    std::vector<int32_t> vval(m);
+    HIPTRY(hipMemcpyAsync(vkey.data(), S.vkey, sizeof(uint32_t) * m, hipMemcpyDeviceToHost, st));
+    HIPTRY(hipMemcpyAsync(vval.data(), S.vval, sizeof(int32_t) * m, hipMemcpyDeviceToHost, st));
+    int32_t *hc = ctx->h_status + H_BCTR;  // pinned
+    HIPTRY(hipMemcpyAsync(hc, S.ctr, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPTRY(hipEventRecord(ev[1], st));
+    HIPTRY(hipStreamSynchronize(st));
+    int64_t xn = hc[0];
+    const int64_t x0 = xn;
+    auto uscore_at = [&](int64_t i) { return (int64_t)(~vkey[i]); };
+    std::vector<std::pair<int32_t, int32_t>> best;  // (score, id), (score desc, id asc)
+    std::vector<int32_t> scores;                    // of the processed items, in visit order
+    std::vector<int32_t> hs(BUDGET_BATCH_MAX);
+    int64_t off = 0, rescanned = 0, rescan_calls = 0, batches = 0;
+    int nb_next = 64;
+    int32_t *Xc = S.X, *Xn = S.X2;
+    while (off < m) {
+        if ((int64_t)best.size() == N && uscore_at(off) < best.back().first) break;
+        const int nb = (int)std::min<int64_t>(nb_next, m - off);
+        const int32_t *bids = S.vval + off;
+        launch_budget_slots(bids, nb, S.slot, st);
+        if (xn > 0) {
+            HIPTRY(hipMemsetAsync(S.ctr + 1, 0, 2 * sizeof(int32_t), st));
+            launch_budget_inc(Xc, xn, bids, nb, S.slot, U, P, d, B.Av, B.Aj, B.lam, B.pos,
+                              B.nu2, B.Ul, B.nru, B.nun, B.posof, B.np2s, B.Pl, B.nrp, B.npn,
+                              kmax, k, dp, S.cnt, S.R, S.ctr + 1, S.xflag, st);
+            HIPTRY(hipMemcpyAsync(hc + 1, S.ctr + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            HIPTRY(hipStreamSynchronize(st));
+            const int64_t rn = hc[1];
+            if (rn > 0) {
+                // rescans: the exact S_k of those users (stage (a)); their
+                // items not yet visited are credited now, and they leave X
+                launch_budget_gather(U, S.R, rn, d, S.Ug, st);
+                s = run_thresholds(ctx, S.Ug, rn, P, m, d, k, S.T, S.tau, S.tau_id, S.topk,
+                                   nullptr);
+                if (s != RMIPS_OK) return s;
+                launch_budget_apply(S.topk, rn, k, S.visited, S.base, st);
+                launch_budget_xcompact(Xc, xn, S.xflag, Xn, S.ctr + 2, st);
+                HIPTRY(hipMemcpyAsync(hc + 2, S.ctr + 2, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                      st));
+                HIPTRY(hipStreamSynchronize(st));
+                xn = hc[2];
+                std::swap(Xc, Xn);
+                rescanned += rn;
+                ++rescan_calls;
+            }
+        }
+        launch_budget_batch(bids, nb, S.base, S.cnt, S.visited, S.slot, S.score, st);
+        HIPTRY(hipMemcpyAsync(hs.data(), S.score, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, st));
+        HIPTRY(hipStreamSynchronize(st));
+        for (int i = 0; i < nb; ++i) {
+            scores.push_back(hs[i]);
+            best.emplace_back(hs[i], vval[off + i]);
+        }
+        std::sort(best.begin(), best.end(), [](const std::pair<int32_t, int32_t> &a,
+                                               const std::pair<int32_t, int32_t> &b) {
+            return a.first > b.first || (a.first == b.first && a.second < b.second);
+        });
+        if ((int64_t)best.size() > N) best.resize(N);
+        off += nb;
+        ++batches;
+        nb_next = std::min(2 * nb_next, BUDGET_BATCH_MAX);
+    }
+    HIPTRY(hipEventRecord(ev[2], st));
+    HIPTRY(hipGetLastError());
+    HIPTRY(hipStreamSynchronize(st));
+    ctx->prof.resolve();
+    for (int i = 0; i < N; ++i) {
+        top_scores[i] = best[i].first;
+        top_ids[i] = best[i].second;
+    }
+    if (stats) {
+        // the items Alg. 2 visits one at a time: up to its stop, replayed on
+        // the exact scores of the processed batches
+        int64_t visited = 0;
+        std::vector<int32_t> run;  // the N largest scores so far (desc)
+        for (int64_t i = 0; i < (int64_t)scores.size(); ++i) {
+            if ((int64_t)run.size() == N && uscore_at(i) < run.back()) break;
+            ++visited;
+            run.insert(std::upper_bound(run.begin(), run.end(), scores[i], std::greater<int32_t>()),
+                       scores[i]);
+            if ((int64_t)run.size() > N) run.pop_back();
+        }
+        std::memset(stats, 0, sizeof(*stats));
+        stats->x0 = x0;
+        stats->rescanned_users = rescanned;
+        stats->rescan_calls = rescan_calls;
+        stats->visited_items = visited;
+        stats->processed_items = off;
+        stats->batches = batches;
+        float t01 = 0, t02 = 0;
+        (void)hipEventElapsedTime(&t01, ev[0], ev[1]);
+        (void)hipEventElapsedTime(&t02, ev[0], ev[2]);
+        stats->ms_init = t01;
+        stats->ms_total = t02;
+    }
+    return RMIPS_OK;
+}
+
+rmips_status rmips_budget_state(rmips_ctx *ctx, int64_t n, int64_t m, int32_t d, int32_t kmax,
+                                const void *index, size_t index_bytes, int32_t *order,
+                                int32_t *pos, double *lam, double *Av, int32_t *Aj, int32_t *key,
+                                int32_t *rank, int64_t *b2, int32_t *uscore) {
+    if (!ctx) return RMIPS_EINVAL;
+    if (!budget_sizes_ok(n, m, d, kmax))
+        return fail(ctx, RMIPS_EINVAL, "sizes out of range (1 <= kmax <= min(m, 32))");
+    if (!index) return fail(ctx, RMIPS_EINVAL, "null pointer");
+    if (index_bytes < rmips_budget_index_size(n, m, d, kmax))
+        return fail(ctx, RMIPS_EWORKSPACE, "index buffer too small");
+    HIPTRY(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    Carve ci(const_cast<void *>(index));
+    BudgetLayout B;
+    budget_plan(n, m, d, kmax, B, ci);
+    rmips_status s = check_budget_header(ctx, B.hdr, n, m, d, kmax);
+    if (s != RMIPS_OK) return s;
+    auto cp = [&](void *dst, const void *src, size_t bytes) -> rmips_status {
+        if (dst) HIPTRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st));
+        return RMIPS_OK;
+    };
+    if ((s = cp(order, B.order, sizeof(int32_t) * m)) != RMIPS_OK) return s;
+    if ((s = cp(pos, B.pos, sizeof(int32_t) * n)) != RMIPS_OK) return s;
+    if ((s = cp(lam, B.lam, sizeof(double) * n)) != RMIPS_OK) return s;
+    if ((s = cp(Av, B.Av, sizeof(double) * n * kmax)) != RMIPS_OK) return s;
+    if ((s = cp(Aj, B.Aj, sizeof(int32_t) * n * kmax)) != RMIPS_OK) return s;
+    if ((s = cp(key, B.key, sizeof(int32_t) * n)) != RMIPS_OK) return s;
+    if ((s = cp(rank, B.rank, sizeof(int32_t) * n)) != RMIPS_OK) return s;
+    if ((s = cp(b2, B.b2, sizeof(int64_t) * n)) != RMIPS_OK) return s;
+    if ((s = cp(uscore, B.uscore, sizeof(int32_t) * kmax * m)) != RMIPS_OK) return s;
+    return RMIPS_OK;
 }
 
 }  // extern "C"

@@ -43,6 +43,11 @@ def test_workspace_queries_validate_sizes():
     assert lib.rmips_index_size(100, 20, 16, 25, 0) == 0                   # kmax > m
     assert lib.rmips_index_size(100, 50, 16, 33, 0) == 0                   # kmax > K_MAX
     assert lib.rmips_index_workspace_size(100, 50, 16, 0, 2) == 0          # kmax < 1
+    assert lib.rmips_budget_index_size(100, 50, 16, 25) > 0
+    assert lib.rmips_budget_workspace_size(100, 50, 16, 25, 2) > 0
+    assert lib.rmips_budget_index_size(100, 20, 16, 25) == 0               # kmax > m
+    assert lib.rmips_budget_workspace_size(100, 50, 16, 33, 0) == 0        # kmax > K_MAX
+    assert lib.rmips_budget_workspace_size(100, 50, 16, 10, 7) == 0        # unknown precision
 
 
 def test_oracle_and_library_share_no_code():
