@@ -51,6 +51,16 @@ def parse():
                     help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this "
                          "bench, started with --calib-copy-mib COPY_MIB, into "
                          "profiles/traffic_<workload>_<prec>.json and exit")
+    ap.add_argument("--budget", action="store_true",
+                    help="the budgeted index (Alg. 1 under an inner-product budget, Alg. 2 with "
+                         "Inc-RMIPS): build and query with each budget function (Sec. 5.2)")
+    ap.add_argument("--kmax", type=int, default=25, help="--budget: k_max of the index")
+    ap.add_argument("--budget-b1", type=int, default=0,
+                    help="--budget: B1/n positions per user (default 2 k_max)")
+    ap.add_argument("--budget-per-user", type=float, default=0.0,
+                    help="--budget: B2/n (default 8 k_max)")
+    ap.add_argument("--budget-k", type=int, default=10, help="--budget: query k")
+    ap.add_argument("--budget-N", type=int, default=20, help="--budget: query N")
     ap.add_argument("--label", default=None,
                     help="with --pmc-summary: workload label of the runs (e.g. fp8cfg_fp32)")
     return ap.parse_args()
@@ -274,6 +284,8 @@ def main():
         torch.cuda.synchronize()
         del x, y
     cfg = synth.CONFIGS[args.config]
+    if args.budget:
+        return bench_budget(args, cfg)
     if cfg.n_queries:
         return bench_soft(args, cfg)
     prec = args.prec or "fp32"
@@ -459,6 +471,82 @@ def bench_soft(args, cfg):
                    "S_mean_start": float(s_start.double().mean()),
                    "S_mean_end": float(s_end.double().mean()),
                    "max_norm_end": float(q.norm(dim=1).max()), "radius": R},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_budget(args, cfg):
+    """The budgeted index on one workload: for each budget function of
+    Sec. 5.2 (Eq. 4's exponential, uniform, linear, quadratic) at the same
+    budget B = (b1 + B2/n) n, one build (Alg. 1) and the query time of
+    Alg. 2 with Inc-RMIPS for (k, N) (the paper's defaults k = 10, N = 20),
+    the analogue of the paper's Table 4 on synthetic data.  A query is one
+    step; its screening precision for rescans is --prec (default bf16)."""
+    import numpy as np
+    import torch
+
+    import paper_2504_13445_amd as rm
+    import synth
+
+    prec = args.prec or "bf16"
+    U, P = synth.make_config(cfg)
+    n, m, d = U.shape[0], P.shape[0], cfg.d
+    kmax, k, N = args.kmax, args.budget_k, args.budget_N
+    b1 = args.budget_b1 or 2 * kmax
+    B2 = int((args.budget_per_user or 8 * kmax) * n)
+    dev = torch.device("cuda:0")
+    Ug = torch.from_numpy(U).to(dev)
+    Pg = torch.from_numpy(P).to(dev)
+    del U, P
+    table = {}
+    for kind in ("exp", "uniform", "linear", "quadratic"):
+        print(f"[bench] budget {kind}: build", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        rm.set_profiling(True)
+        t0 = time.perf_counter()
+        bi = rm.BudgetIndex(Ug, Pg, kmax, b1, B2, kind, prec=prec)
+        torch.cuda.synchronize()
+        t_build = time.perf_counter() - t0
+        bprof = sorted(rm.profile(), key=lambda x: -x[2])[:6]
+        rm.set_profiling(False)
+        print(f"[bench] budget {kind}: queries", file=sys.stderr, flush=True)
+        for _ in range(args.warmup):
+            ids, sc, st = bi.topn(k, N)
+        rm.set_profiling(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ids, sc, st = bi.topn(k, N)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        prof = rm.profile()
+        rm.set_profiling(False)
+        kern = {nm: {"launches_per_query": nl / args.steps, "ms_per_query": ms / args.steps}
+                for nm, nl, ms in prof}
+        top = sorted(kern.items(), key=lambda x: -x[1]["ms_per_query"])[:6]
+        table[kind] = {"build_s": t_build, "build_ms_events": bi.info["ms_total"],
+                       "query_ms": dt * 1e3, "U_prime": bi.info["u_prime"],
+                       "U_dprime": bi.info["u_dprime"], "cert3": bi.info["cert3"],
+                       "cert4": bi.info["cert4"], "beta": bi.info["beta"],
+                       "X0": st["x0"], "rescanned_users": st["rescanned_users"],
+                       "visited_items": st["visited_items"],
+                       "processed_items": st["processed_items"], "batches": st["batches"],
+                       "top_ids_head": ids[:5].tolist(), "kernels": dict(top),
+                       "build_kernels": {nm: {"launches": nl, "ms": ms} for nm, nl, ms in bprof}}
+        del bi
+        torch.cuda.empty_cache()
+    heads = {tuple(v["top_ids_head"]) for v in table.values()}
+    ex = table["exp"]
+    out = {
+        "metric": "budgeted index query time (Alg. 2 with Inc-RMIPS)",
+        "value": ex["query_ms"], "unit": "ms", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ex["query_ms"], "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": prec, "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: n={n} users, m={m} items, d={d}",
+                   "kmax": kmax, "k": k, "N": N, "b1": b1, "B2": B2,
+                   "budget_B": b1 * n + B2, "parallelism": "single GPU"},
+        "same_top_n": len(heads) == 1,
+        "table4": table,
     }
     print(json.dumps(out), flush=True)
 

@@ -162,12 +162,15 @@ void launch_budget_gather(const float *X, const int32_t *idx, int64_t rows, int 
 // For user u = users[w] (or w): the kmax best items of positions 1..lim
 // (lim = lims[w], or lim0) in the order (value desc, id asc), exact, into
 // row u of Av / Aj.  One wave per user: 64 positions per step, one per
-// lane, each value summed in index order by its lane; the step's keys are
-// sorted across the wave and merged with the 64 best so far.
+// lane, each value summed in index order by its lane (PgT holds the items
+// transposed, d x m in position order, so the lanes' loads are adjacent);
+// the step's keys are sorted across the wave and merged with the 64 best
+// so far.
 __global__ __launch_bounds__(256) void k_budget_prefix(
-    const float *__restrict__ U, const float *__restrict__ Pg, const int32_t *__restrict__ order,
-    int d, const int32_t *__restrict__ users, const int32_t *__restrict__ lims, int64_t lim0,
-    int64_t nusers, int kmax, double *__restrict__ Av, int32_t *__restrict__ Aj) {
+    const float *__restrict__ U, const float *__restrict__ PgT, int64_t m,
+    const int32_t *__restrict__ order, int d, const int32_t *__restrict__ users,
+    const int32_t *__restrict__ lims, int64_t lim0, int64_t nusers, int kmax,
+    double *__restrict__ Av, int32_t *__restrict__ Aj) {
     const int lane = threadIdx.x & 63;
     const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (w >= nusers) return;
@@ -182,7 +185,11 @@ __global__ __launch_bounds__(256) void k_budget_prefix(
         int id = INT32_MAX;
         if (q < lim) {
             id = order[q];
-            v = ip64_rows(uu, Pg + q * d, d);
+            const float *pc = PgT + q;
+            double acc = 0.0;
+            for (int i = 0; i < d; ++i)
+                acc = __fma_rn((double)uu[i], (double)pc[(int64_t)i * m], acc);
+            v = acc;
         }
         wave_sort64(v, id, lane);
         // the 64 best of both sorted sequences, as a bitonic sequence
@@ -202,13 +209,28 @@ __global__ __launch_bounds__(256) void k_budget_prefix(
     }
 }
 
-void launch_budget_prefix(const float *U, const float *Pg, const int32_t *order, int d,
-                          const int32_t *users, const int32_t *lims, int64_t lim0,
+void launch_budget_prefix(const float *U, const float *PgT, int64_t m, const int32_t *order,
+                          int d, const int32_t *users, const int32_t *lims, int64_t lim0,
                           int64_t nusers, int kmax, double *Av, int32_t *Aj, hipStream_t st) {
     if (nusers <= 0) return;
     RMIPS_PROF(st, "k_budget_prefix");
-    k_budget_prefix<<<(unsigned)((nusers + 3) / 4), 256, 0, st>>>(U, Pg, order, d, users, lims,
-                                                                   lim0, nusers, kmax, Av, Aj);
+    k_budget_prefix<<<(unsigned)((nusers + 3) / 4), 256, 0, st>>>(
+        U, PgT, m, order, d, users, lims, lim0, nusers, kmax, Av, Aj);
+}
+
+// PgT[i * m + q] = P[order[q] * d + i]: the items transposed, position order
+__global__ void k_budget_transpose(const float *__restrict__ P, const int32_t *__restrict__ order,
+                                   int64_t m, int d, float *__restrict__ PgT) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    const float *p = P + (int64_t)order[q] * d;
+    for (int i = 0; i < d; ++i) PgT[(int64_t)i * m + q] = p[i];
+}
+
+void launch_budget_transpose(const float *P, const int32_t *order, int64_t m, int d,
+                             float *PgT, hipStream_t st) {
+    RMIPS_PROF(st, "k_budget_transpose");
+    k_budget_transpose<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(P, order, m, d, PgT);
 }
 
 // first position j in [lo, m] whose Eq. (2) bound is below theta, m + 1
@@ -299,61 +321,148 @@ void launch_budget_scatter(const int32_t *users, const int32_t *pos, const doubl
 }
 
 // ---------------------------------------------------------------- step 5
-// For each user of U'' (users[w]): positions pos + 1.. until the first
-// whose Eq. (2) bound is below the user's k_max-th value; each gets the
-// Eq. (3) bound lam, the user's lambda (Eq. 7) is their maximum (-inf if
-// none), and the item counts for every k with lam >= A^k: those k form a
-// tail k0..kmax of 1..kmax (the list falls with k), so one count goes to
-// row k0 - 1 of the difference table diff (kmax x m, by item id).
-__global__ void k_budget_step5(const int32_t *__restrict__ users,
+// The range of step (5) for each user of U'' (users[w]): positions pos + 1
+// up to, not including, the first whose Eq. (2) bound is below the user's
+// k_max-th value (m + 1 if none): key[w] = that end, val[w] = the user.
+__global__ void k_budget_range(const int32_t *__restrict__ users,
                                const int32_t *__restrict__ pos, int64_t nusers,
                                const double *__restrict__ Av, const double *__restrict__ nu2,
-                               const double *__restrict__ Ul, const double *__restrict__ nru,
-                               const double *__restrict__ nun,
-                               const double *__restrict__ np2s, const double *__restrict__ Pl,
-                               const double *__restrict__ nrp, const double *__restrict__ npn,
-                               const int32_t *__restrict__ order, int64_t m, int kmax, int dp,
-                               double *__restrict__ lam, int32_t *__restrict__ diff) {
+                               const double *__restrict__ np2s, int64_t m, int kmax,
+                               uint32_t *__restrict__ key, int32_t *__restrict__ val) {
     const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= nusers) return;
     const int64_t u = users[w];
-    const double *A = Av + u * kmax;
-    const double thk = A[kmax - 1];
-    double ul[BUDGET_DP_MAX];
-#pragma unroll
-    for (int t = 0; t < BUDGET_DP_MAX; ++t) ul[t] = t < dp ? Ul[u * dp + t] : 0.0;
-    const double nr = nru[u], nn = nun[u], x2 = nu2[u];
-    double best = -INFINITY;
-    for (int64_t j = (int64_t)pos[u] + 1; j <= m; ++j) {
-        if (cs_below(x2, np2s[j - 1], thk)) break;
-        const double l = eq3_bound(ul, nr, nn, Pl + (j - 1) * dp, nrp[j - 1], npn[j - 1], dp);
-        best = fmax(best, l);
-        if (l >= thk) {
-            // smallest k with l >= A^k
-            int lo = 1, hi = kmax;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (l >= A[mid - 1])
-                    hi = mid;
-                else
-                    lo = mid + 1;
-            }
-            atomicAdd(&diff[(int64_t)(lo - 1) * m + order[j - 1]], 1);
-        }
-    }
-    lam[u] = best;
+    key[w] = (uint32_t)first_below(nu2[u], np2s, (int64_t)pos[u] + 1, m,
+                                   Av[u * kmax + kmax - 1]);
+    val[w] = (int32_t)u;
 }
 
-void launch_budget_step5(const int32_t *users, const int32_t *pos, int64_t nusers,
-                         const double *Av, const double *nu2, const double *Ul,
-                         const double *nru, const double *nun, const double *np2s,
-                         const double *Pl, const double *nrp, const double *npn,
-                         const int32_t *order, int64_t m, int kmax, int dp, double *lam,
-                         int32_t *diff, hipStream_t st) {
+void launch_budget_range(const int32_t *users, const int32_t *pos, int64_t nusers,
+                         const double *Av, const double *nu2, const double *np2s, int64_t m,
+                         int kmax, uint32_t *key, int32_t *val, hipStream_t st) {
+    if (nusers <= 0) return;
+    RMIPS_PROF(st, "k_budget_range");
+    k_budget_range<<<(unsigned)((nusers + 255) / 256), 256, 0, st>>>(users, pos, nusers, Av, nu2,
+                                                                      np2s, m, kmax, key, val);
+}
+
+// Step (5) over those ranges, users sorted by the range's end (similar
+// ranges share a wave).  Per tile of S5_TILE positions the items' Eq. (3)
+// data sit in LDS and a wave's lanes (one user each) take the positions in
+// step.  lambda (Eq. 7) is the largest bound over a user's range (-inf if
+// empty).  An item counts for user u and every k with the bound >= A_u^k;
+// per position the wave counts its lanes for each k (ballots), keeping the
+// count for k in lane k - 1, and adds them to the tile's LDS table (row
+// k - 1, no two lanes on one entry).  The table goes to the difference
+// table diff (kmax x m, by item id) as differences of consecutive rows,
+// once per tile.  A^k is compared rounded down to FP32: a lower threshold
+// can only add counts, so uscore_k stays an upper bound (Theorem 3).
+constexpr int S5_TILE = 256;
+constexpr int S5_THREADS = 512;
+__global__ __launch_bounds__(S5_THREADS) void k_budget_step5(
+    const int32_t *__restrict__ users, const uint32_t *__restrict__ hi_pos,
+    const int32_t *__restrict__ pos, int64_t nusers, const double *__restrict__ Av,
+    const double *__restrict__ Ul, const double *__restrict__ nru,
+    const double *__restrict__ nun, const double *__restrict__ Pl,
+    const double *__restrict__ nrp, const double *__restrict__ npn,
+    const int32_t *__restrict__ order, int64_t m, int kmax, int dp, double *__restrict__ lam,
+    int32_t *__restrict__ diff) {
+    __shared__ double t_pl[S5_TILE * BUDGET_DP_MAX];
+    __shared__ double t_nrp[S5_TILE], t_npn[S5_TILE];
+    __shared__ int32_t t_id[S5_TILE];
+    __shared__ int32_t cnt[KMAX * S5_TILE];
+    __shared__ int64_t s_lo, s_hi;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int64_t w = (int64_t)blockIdx.x * S5_THREADS + tid;
+    const bool valid = w < nusers;
+    int64_t u = 0, lo = INT64_MAX, hi = 0;
+    if (valid) {
+        u = users[w];
+        lo = (int64_t)pos[u] + 1;
+        hi = hi_pos[w];
+    }
+    if (tid == 0) {
+        s_lo = INT64_MAX;
+        s_hi = 0;
+    }
+    __syncthreads();
+    if (valid && lo < hi) {
+        atomicMin((unsigned long long *)&s_lo, (unsigned long long)lo);
+        atomicMax((unsigned long long *)&s_hi, (unsigned long long)hi);
+    }
+    __syncthreads();
+    const int64_t blo = s_lo, bhi = s_hi;
+    double ul[BUDGET_DP_MAX];
+#pragma unroll
+    for (int t = 0; t < BUDGET_DP_MAX; ++t) ul[t] = (valid && t < dp) ? Ul[u * dp + t] : 0.0;
+    const double nr = valid ? nru[u] : 0.0, nn = valid ? nun[u] : 0.0;
+    float af[KMAX];
+#pragma unroll
+    for (int r = 0; r < KMAX; ++r)
+        af[r] = (valid && r < kmax) ? __double2float_rd(Av[u * kmax + r]) : -INFINITY;
+    const double thk = valid ? Av[u * kmax + kmax - 1] : INFINITY;
+    double best = -INFINITY;
+    for (int64_t t0 = blo; t0 < bhi; t0 += S5_TILE) {
+        const int tn = (int)min<int64_t>(S5_TILE, m + 1 - t0);
+        for (int i = tid; i < tn; i += S5_THREADS) {
+            const int64_t j = t0 + i - 1;  // 0-based position
+            t_id[i] = order[j];
+            t_nrp[i] = nrp[j];
+            t_npn[i] = npn[j];
+            for (int t = 0; t < dp; ++t) t_pl[i * BUDGET_DP_MAX + t] = Pl[j * dp + t];
+        }
+        for (int e = tid; e < kmax * S5_TILE; e += S5_THREADS) cnt[e] = 0;
+        __syncthreads();
+        // the wave's positions: the union of its lanes' ranges in the tile
+        int64_t wa = valid ? max(lo, t0) : INT64_MAX, wb = valid ? min(hi, t0 + tn) : 0;
+        for (int o = 32; o > 0; o >>= 1) {
+            wa = min(wa, __shfl_xor(wa, o));
+            wb = max(wb, __shfl_xor(wb, o));
+        }
+        for (int64_t j = wa; j < wb; ++j) {
+            const int i = (int)(j - t0);
+            const bool act = valid && j >= lo && j < hi;
+            int k0 = KMAX + 1;
+            if (act) {
+                const double l =
+                    eq3_bound(ul, nr, nn, t_pl + i * BUDGET_DP_MAX, t_nrp[i], t_npn[i], dp);
+                best = fmax(best, l);
+                if (l >= thk) {
+                    // af[r] > lf >= l: a lower count, so a smaller k0 (safe)
+                    const float lf = __double2float_ru(l);
+                    k0 = 1;
+#pragma unroll
+                    for (int r = 0; r < KMAX; ++r) k0 += (af[r] > lf) ? 1 : 0;
+                }
+            }
+            if (__ballot(k0 <= kmax) == 0) continue;
+            int mine = 0;
+            for (int k = 1; k <= kmax; ++k) {
+                const int c = __popcll(__ballot(k0 <= k));
+                if (lane == k - 1) mine = c;
+            }
+            if (lane < kmax && mine) atomicAdd(&cnt[lane * S5_TILE + i], mine);
+        }
+        __syncthreads();
+        for (int e = tid; e < kmax * S5_TILE; e += S5_THREADS) {
+            const int r = e / S5_TILE, i = e - r * S5_TILE;
+            const int c = cnt[e] - (r ? cnt[e - S5_TILE] : 0);
+            if (c && i < tn) atomicAdd(&diff[(int64_t)r * m + t_id[i]], c);
+        }
+        __syncthreads();
+    }
+    if (valid) lam[u] = best;
+}
+
+void launch_budget_step5(const int32_t *users, const uint32_t *hi_pos, const int32_t *pos,
+                         int64_t nusers, const double *Av, const double *Ul, const double *nru,
+                         const double *nun, const double *Pl, const double *nrp,
+                         const double *npn, const int32_t *order, int64_t m, int kmax, int dp,
+                         double *lam, int32_t *diff, hipStream_t st) {
     if (nusers <= 0) return;
     RMIPS_PROF(st, "k_budget_step5");
-    k_budget_step5<<<(unsigned)((nusers + 127) / 128), 128, 0, st>>>(
-        users, pos, nusers, Av, nu2, Ul, nru, nun, np2s, Pl, nrp, npn, order, m, kmax, dp, lam,
+    k_budget_step5<<<(unsigned)((nusers + S5_THREADS - 1) / S5_THREADS), S5_THREADS, 0, st>>>(
+        users, hi_pos, pos, nusers, Av, Ul, nru, nun, Pl, nrp, npn, order, m, kmax, dp, lam,
         diff);
 }
 
@@ -425,14 +534,15 @@ __global__ void k_budget_slots(const int32_t *__restrict__ bids, int nb,
 // items.  Per user: an item of its first k entries whose value is above
 // lambda is in; one whose value is not needs a rescan.  An unscanned item
 // (position > pos) is out when Eq. (2), then Eq. (3), puts it below the
-// k-th value, or when its exact value ranks after the k-th entry; else the
-// user needs a rescan (the item is in only if its value exceeds lambda,
-// which bounds it).  A user that needs a rescan is appended to R and
-// counts nothing here; the others add their ins to the batch counts.
+// k-th value; any other unscanned item needs a rescan.  (The paper first
+// computes that pair's exact value, which can still rule it out; here the
+// rescan, one screened stage (a) pass for all flagged users, settles the
+// user's S_k for every later batch at once and costs less than exact
+// products against each of them.)  A user that needs a rescan is appended
+// to R and counts nothing here; the others add their ins to the counts.
 __global__ __launch_bounds__(256) void k_budget_inc(
     const int32_t *__restrict__ X, int64_t xn, const int32_t *__restrict__ bids, int nb,
-    const int32_t *__restrict__ slot, const float *__restrict__ U,
-    const float *__restrict__ P, int d, const double *__restrict__ Av,
+    const int32_t *__restrict__ slot, const double *__restrict__ Av,
     const int32_t *__restrict__ Aj, const double *__restrict__ lam,
     const int32_t *__restrict__ pos, const double *__restrict__ nu2,
     const double *__restrict__ Ul, const double *__restrict__ nru,
@@ -461,7 +571,6 @@ __global__ __launch_bounds__(256) void k_budget_inc(
     const double *A = Av + u * kmax;
     const int32_t *Ajr = Aj + u * kmax;
     const double lu = lam[u], Ak = A[k - 1];
-    const int idk = Ajr[k - 1];
     const int64_t pu = pos[u];
     bool rescan = false;
     // scanned items: the first k entries of the list
@@ -479,8 +588,6 @@ __global__ __launch_bounds__(256) void k_budget_inc(
             if (cs_below(x2, s_np2[s], Ak)) continue;
             if (eq3_bound(ul, nr, nn, s_pl + s * BUDGET_DP_MAX, s_nrp[s], s_npn[s], dp) < Ak)
                 continue;
-            const double v = ip64_rows(U + u * d, P + (int64_t)s_id[s] * d, d);
-            if (!ranks_before(v, s_id[s], Ak, idk)) continue;
             rescan = true;
             break;
         }
@@ -497,8 +604,7 @@ __global__ __launch_bounds__(256) void k_budget_inc(
 }
 
 void launch_budget_inc(const int32_t *X, int64_t xn, const int32_t *bids, int nb,
-                       const int32_t *slot, const float *U, const float *P, int d,
-                       const double *Av, const int32_t *Aj, const double *lam,
+                       const int32_t *slot, const double *Av, const int32_t *Aj, const double *lam,
                        const int32_t *pos, const double *nu2, const double *Ul,
                        const double *nru, const double *nun, const int32_t *posof,
                        const double *np2s, const double *Pl, const double *nrp,
@@ -507,7 +613,7 @@ void launch_budget_inc(const int32_t *X, int64_t xn, const int32_t *bids, int nb
     if (xn <= 0) return;
     RMIPS_PROF(st, "k_budget_inc");
     k_budget_inc<<<(unsigned)((xn + 255) / 256), 256, 0, st>>>(
-        X, xn, bids, nb, slot, U, P, d, Av, Aj, lam, pos, nu2, Ul, nru, nun, posof, np2s, Pl,
+        X, xn, bids, nb, slot, Av, Aj, lam, pos, nu2, Ul, nru, nun, posof, np2s, Pl,
         nrp, npn, kmax, k, dp, cnt, R, rn, xflag);
 }
 
@@ -562,13 +668,13 @@ __global__ void k_budget_batch(const int32_t *__restrict__ bids, int nb,
 
 void launch_budget_slots(const int32_t *bids, int nb, int32_t *slot, hipStream_t st) {
     RMIPS_PROF(st, "k_budget_slots");
-    k_budget_slots<<<1, BUDGET_BATCH_MAX, 0, st>>>(bids, nb, slot);
+    k_budget_slots<<<(nb + 255) / 256, 256, 0, st>>>(bids, nb, slot);
 }
 
 void launch_budget_batch(const int32_t *bids, int nb, const int32_t *base, int32_t *cnt,
                          uint8_t *visited, int32_t *slot, int32_t *score, hipStream_t st) {
     RMIPS_PROF(st, "k_budget_batch");
-    k_budget_batch<<<1, BUDGET_BATCH_MAX, 0, st>>>(bids, nb, base, cnt, visited, slot, score);
+    k_budget_batch<<<(nb + 255) / 256, 256, 0, st>>>(bids, nb, base, cnt, visited, slot, score);
 }
 
 // visit keys: ~uscore (ascending sort = descending uscore), ids as values

@@ -243,8 +243,9 @@ bool soft_noalloc_fits(int64_t nq, int d);
 // Sec. 4.3).  Positions are 1-based in the descending order of the FP64 sum
 // of squares (ties by item id); "position order" arrays hold position j at
 // index j - 1.
-constexpr int BUDGET_DP_MAX = 16;      // largest d' of the index's Eq. (3)
-constexpr int BUDGET_BATCH_MAX = 256;  // items per visited batch of a query
+constexpr int BUDGET_DP_MAX = 10;      // d' of the index's Eq. (3) (Sec. 5.1), at most
+constexpr int BUDGET_BATCH_MAX = 256;  // items per visited batch while X is not empty
+constexpr int BUDGET_BATCH_BIG = 4096; // items per visited batch once X is empty
 // x2[r] = FP64 sum of squares of row r (index order)
 void launch_sqnorm64(const float *X, int64_t rows, int d, double *x2, hipStream_t st);
 // rotated coordinates l = W x (dp values), remaining norm and norm (both
@@ -256,11 +257,13 @@ void launch_budget_rotate(const float *X, const int32_t *order, const double *x2
 void launch_budget_gather(const float *X, const int32_t *idx, int64_t rows, int d, float *Y,
                           hipStream_t st);
 // the kmax best (value desc, id asc) of positions 1..lim of each listed user
-// (users NULL: all; lims NULL: lim0), exact, into the user's row of Av / Aj;
-// Pg holds the items' rows in position order
-void launch_budget_prefix(const float *U, const float *Pg, const int32_t *order, int d,
-                          const int32_t *users, const int32_t *lims, int64_t lim0,
+// (users NULL: all; lims NULL: lim0), exact, into the user's row of Av / Aj
+void launch_budget_prefix(const float *U, const float *PgT, int64_t m, const int32_t *order,
+                          int d, const int32_t *users, const int32_t *lims, int64_t lim0,
                           int64_t nusers, int kmax, double *Av, int32_t *Aj, hipStream_t st);
+// PgT (d x m) = the items transposed, in position order
+void launch_budget_transpose(const float *P, const int32_t *order, int64_t m, int d,
+                             float *PgT, hipStream_t st);
 // key[u] = j' + 1 - b1 for a user whose first b1 positions did not settle
 // its list, else 0
 void launch_budget_classify(const double *Av, const double *nu2, const double *np2s, int64_t n,
@@ -273,14 +276,17 @@ void launch_budget_tstop(const int32_t *users, const double *topv, const double 
 void launch_budget_scatter(const int32_t *users, const int32_t *pos, const double *topv,
                            const int32_t *topk, int64_t X, int kmax, double *Av, int32_t *Aj,
                            hipStream_t st);
-// step (5): lambda of each listed user and the Eq. (6) counts into the
-// difference table diff (kmax x m, by item id)
-void launch_budget_step5(const int32_t *users, const int32_t *pos, int64_t nusers,
-                         const double *Av, const double *nu2, const double *Ul,
-                         const double *nru, const double *nun, const double *np2s,
-                         const double *Pl, const double *nrp, const double *npn,
-                         const int32_t *order, int64_t m, int kmax, int dp, double *lam,
-                         int32_t *diff, hipStream_t st);
+// step (5)'s range end of each user of U'' (key) with the user (val)
+void launch_budget_range(const int32_t *users, const int32_t *pos, int64_t nusers,
+                         const double *Av, const double *nu2, const double *np2s, int64_t m,
+                         int kmax, uint32_t *key, int32_t *val, hipStream_t st);
+// step (5): lambda of each listed user (sorted by range end hi_pos) and the
+// Eq. (6) counts into the difference table diff (kmax x m, by item id)
+void launch_budget_step5(const int32_t *users, const uint32_t *hi_pos, const int32_t *pos,
+                         int64_t nusers, const double *Av, const double *Ul, const double *nru,
+                         const double *nun, const double *Pl, const double *nrp,
+                         const double *npn, const int32_t *order, int64_t m, int kmax, int dp,
+                         double *lam, int32_t *diff, hipStream_t st);
 // the lists' entries into the difference table (entry r -> row r)
 void launch_budget_hist(const int32_t *Aj, int64_t n, int kmax, int64_t m, int32_t *diff,
                         hipStream_t st);
@@ -291,11 +297,10 @@ void launch_budget_xinit(const double *Av, const int32_t *Aj, const double *lam,
                          int kmax, int k, int32_t *base, int32_t *X, int32_t *xn,
                          hipStream_t st);
 void launch_budget_slots(const int32_t *bids, int nb, int32_t *slot, hipStream_t st);
-// Inc-RMIPS of X against a batch: ins into cnt (by batch slot), users that
-// need a rescan into R (count in *rn) with xflag set
+// Inc-RMIPS of X against a batch (nb <= BUDGET_BATCH_MAX): ins into cnt (by
+// batch slot), users that need a rescan into R (count in *rn), xflag set
 void launch_budget_inc(const int32_t *X, int64_t xn, const int32_t *bids, int nb,
-                       const int32_t *slot, const float *U, const float *P, int d,
-                       const double *Av, const int32_t *Aj, const double *lam,
+                       const int32_t *slot, const double *Av, const int32_t *Aj, const double *lam,
                        const int32_t *pos, const double *nu2, const double *Ul,
                        const double *nru, const double *nun, const int32_t *posof,
                        const double *np2s, const double *Pl, const double *nrp,

@@ -791,7 +791,7 @@ constexpr int BUDGET_HDR_WORDS = 16;
 constexpr int H_BHDR = 96;   // pinned status words that receive the header
 constexpr int H_BCTR = 112;  // pinned status words for a query's counters
 constexpr int BUDGET_DP = 10;  // d' of Eq. (3) in the paper's experiments (Sec. 5.1)
-int budget_dp(int d) { return std::min(d, BUDGET_DP); }
+int budget_dp(int d) { return std::min(d, std::min(BUDGET_DP, BUDGET_DP_MAX)); }
 
 struct BudgetLayout {
     int32_t *hdr;
@@ -848,7 +848,7 @@ void budget_header(int64_t n, int64_t m, int d, int kmax, int32_t (&h)[BUDGET_HD
 // for up to n users with k <= kmax, gathered rows, and the query's sets.
 struct BudgetScratch {
     ThreshLayout T;
-    float *Pg;           // item rows in position order
+    float *PgT;          // items transposed (d x m), position order
     double *np2;         // item sums of squares by id
     float *Ug;           // gathered user rows (U' at the build, rescans at a query)
     double *topv, *tau;
@@ -866,7 +866,7 @@ struct BudgetScratch {
 void budget_scratch_plan(int prec, int64_t n, int64_t m, int d, int kmax, int cap_override,
                          BudgetScratch &S, Carve &cv) {
     thresh_plan(prec, n, m, d, kmax, cap_override, S.T, cv);
-    S.Pg = cv.take<float>((size_t)m * d);
+    S.PgT = cv.take<float>((size_t)m * d);
     S.np2 = cv.take<double>(m);
     S.Ug = cv.take<float>((size_t)n * d);
     S.topv = cv.take<double>((size_t)n * kmax);
@@ -887,8 +887,8 @@ void budget_scratch_plan(int prec, int64_t n, int64_t m, int d, int kmax, int ca
     S.visited = cv.take<uint8_t>(m);
     S.base = cv.take<int32_t>(m);
     S.slot = cv.take<int32_t>(m);
-    S.cnt = cv.take<int32_t>(BUDGET_BATCH_MAX);
-    S.score = cv.take<int32_t>(BUDGET_BATCH_MAX);
+    S.cnt = cv.take<int32_t>(BUDGET_BATCH_BIG);
+    S.score = cv.take<int32_t>(BUDGET_BATCH_BIG);
     S.vkey = cv.take<uint32_t>(m);
     S.vval = cv.take<int32_t>(m);
     S.vsort = cv.take<uint8_t>(radix_sort_scratch_bytes(m));
@@ -1748,11 +1748,11 @@ rmips_status rmips_budget_build(rmips_ctx *ctx, const float *U, int64_t n, const
     }
     launch_budget_rotate(U, nullptr, B.nu2, n, d, B.W, dp, B.Ul, B.nru, B.nun, st);
     launch_budget_rotate(P, B.order, S.np2, m, d, B.W, dp, B.Pl, B.nrp, B.npn, st);
-    launch_budget_gather(P, B.order, m, d, S.Pg, st);
+    launch_budget_transpose(P, B.order, m, d, S.PgT, st);
 
     // (3) uniform budget: positions 1..b1 for every user, then U' with its
     // keys j' + 1 - b1
-    launch_budget_prefix(U, S.Pg, B.order, d, nullptr, nullptr, b1, n, kmax, B.Av, B.Aj, st);
+    launch_budget_prefix(U, S.PgT, m, B.order, d, nullptr, nullptr, b1, n, kmax, B.Av, B.Aj, st);
     launch_budget_classify(B.Av, B.nu2, B.np2s, n, m, kmax, b1, B.key, st);
     std::vector<int32_t> key(n);
     HIPTRY(hipMemcpyAsync(key.data(), B.key, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
@@ -1819,15 +1819,22 @@ rmips_status rmips_budget_build(rmips_ctx *ctx, const float *U, int64_t n, const
         HIPTRY(hipMemcpyAsync(S.u2, u2.data(), sizeof(int32_t) * nU2, hipMemcpyHostToDevice, st));
         HIPTRY(hipMemcpyAsync(S.lims, lims.data(), sizeof(int32_t) * nU2, hipMemcpyHostToDevice,
                               st));
-        launch_budget_prefix(U, S.Pg, B.order, d, S.u2, S.lims, 0, nU2, kmax, B.Av, B.Aj, st);
+        launch_budget_prefix(U, S.PgT, m, B.order, d, S.u2, S.lims, 0, nU2, kmax, B.Av, B.Aj,
+                             st);
     }
 
     // (5) lambda_i and uscore_k: Eq. (6) over the unscanned positions of U'',
     // then the first k entries of every list
     launch_fill_f64(B.lam, n, -INFINITY, st);
     HIPTRY(hipMemsetAsync(B.uscore, 0, sizeof(int32_t) * kmax * m, st));
-    launch_budget_step5(S.u2, B.pos, nU2, B.Av, B.nu2, B.Ul, B.nru, B.nun, B.np2s, B.Pl, B.nrp,
-                        B.npn, B.order, m, kmax, dp, B.lam, B.uscore, st);
+    // users of U'' sorted by the end of their step (5) range
+    uint32_t *rkey = reinterpret_cast<uint32_t *>(S.t);
+    launch_budget_range(S.u2, B.pos, nU2, B.Av, B.nu2, B.np2s, m, kmax, rkey, S.lims, st);
+    if (nU2 > 0)
+        HIPTRY(radix_sort_u32(rkey, S.lims, nU2, S.T.usort, st, 0,
+                              32 - __builtin_clz((unsigned)(m + 1))));
+    launch_budget_step5(S.lims, rkey, B.pos, nU2, B.Av, B.Ul, B.nru, B.nun, B.Pl, B.nrp, B.npn,
+                        B.order, m, kmax, dp, B.lam, B.uscore, st);
     launch_budget_hist(B.Aj, n, kmax, m, B.uscore, st);
     launch_budget_prefix_k(B.uscore, m, kmax, st);
     const int64_t cert3 = n - X;
@@ -1891,7 +1898,7 @@ rmips_status rmips_budget_topn(rmips_ctx *ctx, const float *U, int64_t n, const 
     HIPTRY(hipMemsetAsync(S.base, 0, sizeof(int32_t) * m, st));
     HIPTRY(hipMemsetAsync(S.visited, 0, m, st));
     HIPTRY(hipMemsetAsync(S.xflag, 0, n, st));
-    HIPTRY(hipMemsetAsync(S.cnt, 0, sizeof(int32_t) * BUDGET_BATCH_MAX, st));
+    HIPTRY(hipMemsetAsync(S.cnt, 0, sizeof(int32_t) * BUDGET_BATCH_BIG, st));
     HIPTRY(hipMemsetAsync(S.ctr, 0, sizeof(int32_t) * 64, st));
     launch_fill_i32(S.slot, m, -1, st);
     launch_budget_xinit(B.Av, B.Aj, B.lam, n, kmax, k, S.base, S.X, S.ctr, st);
@@ -1911,18 +1918,21 @@ rmips_status rmips_budget_topn(rmips_ctx *ctx, const float *U, int64_t n, const 
     auto uscore_at = [&](int64_t i) { return (int64_t)(~vkey[i]); };
     std::vector<std::pair<int32_t, int32_t>> best;  // (score, id), (score desc, id asc)
     std::vector<int32_t> scores;                    // of the processed items, in visit order
-    std::vector<int32_t> hs(BUDGET_BATCH_MAX);
+    std::vector<int32_t> hs(BUDGET_BATCH_BIG);
     int64_t off = 0, rescanned = 0, rescan_calls = 0, batches = 0;
     int nb_next = 64;
     int32_t *Xc = S.X, *Xn = S.X2;
     while (off < m) {
         if ((int64_t)best.size() == N && uscore_at(off) < best.back().first) break;
+        // batches stay small while X holds users (each is tested against
+        // all of X); once X is empty a batch is only a lookup
+        if (xn == 0) nb_next = std::max(nb_next, BUDGET_BATCH_BIG);
         const int nb = (int)std::min<int64_t>(nb_next, m - off);
         const int32_t *bids = S.vval + off;
         launch_budget_slots(bids, nb, S.slot, st);
         if (xn > 0) {
             HIPTRY(hipMemsetAsync(S.ctr + 1, 0, 2 * sizeof(int32_t), st));
-            launch_budget_inc(Xc, xn, bids, nb, S.slot, U, P, d, B.Av, B.Aj, B.lam, B.pos,
+            launch_budget_inc(Xc, xn, bids, nb, S.slot, B.Av, B.Aj, B.lam, B.pos,
                               B.nu2, B.Ul, B.nru, B.nun, B.posof, B.np2s, B.Pl, B.nrp, B.npn,
                               kmax, k, dp, S.cnt, S.R, S.ctr + 1, S.xflag, st);
             HIPTRY(hipMemcpyAsync(hc + 1, S.ctr + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -1960,7 +1970,7 @@ rmips_status rmips_budget_topn(rmips_ctx *ctx, const float *U, int64_t n, const 
         if ((int64_t)best.size() > N) best.resize(N);
         off += nb;
         ++batches;
-        nb_next = std::min(2 * nb_next, BUDGET_BATCH_MAX);
+        nb_next = std::min(2 * nb_next, xn > 0 ? BUDGET_BATCH_MAX : BUDGET_BATCH_BIG);
     }
     HIPTRY(hipEventRecord(ev[2], st));
     HIPTRY(hipGetLastError());
