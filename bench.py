@@ -67,9 +67,9 @@ def parse():
 
 
 # Sources whose change makes a committed traffic measurement stale.
-TRAFFIC_SOURCES = ["paper_2504_13445_amd/csrc/common.h", "paper_2504_13445_amd/csrc/kernels.h",
-                   "paper_2504_13445_amd/csrc/thresh.hip", "paper_2504_13445_amd/csrc/count.hip",
-                   "paper_2504_13445_amd/csrc/prep.hip", "paper_2504_13445_amd/csrc/sort.hip"]
+TRAFFIC_SOURCES = ["paper_2504_13445_amd/csrc/common.h", "paper_2504_13445_amd/csrc/thresh.hip",
+                   "paper_2504_13445_amd/csrc/count.hip", "paper_2504_13445_amd/csrc/prep.hip",
+                   "paper_2504_13445_amd/csrc/sort.hip"]
 
 
 def _sources_hash():
