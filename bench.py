@@ -192,14 +192,13 @@ def cpu_baseline(cfg, U, P, k, target_s):
 
 
 def run_topn(rm, Ug, Pg, k, N, prec, ws, steps, warmup, profile=False):
-    """Time `steps` rmips_topn calls after `warmup` untimed ones; with
-    profile, every launch of the timed calls is timed by HIP events."""
+    """Time `steps` rmips_topn calls after `warmup` untimed ones, with nothing
+    but the calls in the timed region; with profile, `steps` more calls then
+    time every launch by HIP events (the per-kernel table and its stats)."""
     import torch
     for _ in range(warmup):
         rm.topn(Ug, Pg, k, N, prec, ws=ws)
     torch.cuda.synchronize()
-    if profile:
-        rm.set_profiling(True)
     stats = []
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -207,11 +206,16 @@ def run_topn(rm, Ug, Pg, k, N, prec, ws, steps, warmup, profile=False):
         stats.append(st)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    prof = None
+    prof, pstats = None, stats
     if profile:
+        rm.set_profiling(True)
+        pstats = []
+        for _ in range(steps):
+            pstats.append(rm.topn(Ug, Pg, k, N, prec, ws=ws)[2])
+        torch.cuda.synchronize()
         prof = rm.profile()
         rm.set_profiling(False)
-    return ids, sc, stats, dt, prof
+    return ids, sc, stats, dt, prof, pstats
 
 
 def kernel_table(prof, stats, steps, n, m, d, k, prec):
@@ -298,15 +302,15 @@ def main():
     torch.cuda.synchronize()
 
     print(f"[bench] timing {prec}", file=sys.stderr, flush=True)
-    ids, sc, stats, dt, prof = run_topn(rm, Ug, Pg, k, N, prec, ws, args.steps, args.warmup,
-                                        profile=True)
+    ids, sc, stats, dt, prof, pstats = run_topn(rm, Ug, Pg, k, N, prec, ws, args.steps,
+                                                args.warmup, profile=True)
     ms = dt / args.steps * 1e3
     value = n * m / (dt / args.steps) / 1e9
 
     def avg(key):
         return float(np.mean([s[key] for s in stats]))
 
-    kernels = kernel_table(prof, stats, args.steps, n, m, d, k, prec)
+    kernels = kernel_table(prof, pstats, args.steps, n, m, d, k, prec)
     # dominant kernel of the step: the largest total time among all kernels
     name = max(kernels, key=lambda x: kernels[x]["ms_per_step"])
     dom = kernels[name]
@@ -334,11 +338,11 @@ def main():
                 continue
             print(f"[bench] variant {vp}", file=sys.stderr, flush=True)
             wsv = rm.topn_workspace(n, m, d, k, N, vp, dev)
-            vids, vsc, vst, vdt, vprof = run_topn(rm, Ug, Pg, k, N, vp, wsv, args.steps,
-                                                  args.warmup, profile=True)
+            vids, vsc, vst, vdt, vprof, vpst = run_topn(rm, Ug, Pg, k, N, vp, wsv, args.steps,
+                                                        args.warmup, profile=True)
             del wsv
             torch.cuda.empty_cache()
-            vk = kernel_table(vprof, vst, args.steps, n, m, d, k, vp)
+            vk = kernel_table(vprof, vpst, args.steps, n, m, d, k, vp)
             vname = max(vk, key=lambda x: vk[x]["ms_per_step"])
             variants[vp] = {
                 "ms_per_step": vdt / args.steps * 1e3,
@@ -418,13 +422,17 @@ def bench_soft(args, cfg):
         S, G = rm.soft_fwd_grad(Ug, tau, Qg, T)
         rm.soft_scale(G, ones)
     torch.cuda.synchronize()
-    rm.set_profiling(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         S, G = rm.soft_fwd_grad(Ug, tau, Qg, T)
         dQ = rm.soft_scale(G, ones)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
+    rm.set_profiling(True)   # per-kernel times from further, untimed steps
+    for _ in range(args.steps):
+        S, G = rm.soft_fwd_grad(Ug, tau, Qg, T)
+        dQ = rm.soft_scale(G, ones)
+    torch.cuda.synchronize()
     prof = rm.profile()
     rm.set_profiling(False)
     kern = {nm: {"launches_per_step": nl / args.steps, "ms_per_step": ms / args.steps,
@@ -512,13 +520,16 @@ def bench_budget(args, cfg):
         print(f"[bench] budget {kind}: queries", file=sys.stderr, flush=True)
         for _ in range(args.warmup):
             ids, sc, st = bi.topn(k, N)
-        rm.set_profiling(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
             ids, sc, st = bi.topn(k, N)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
+        rm.set_profiling(True)   # per-kernel times from further, untimed queries
+        for _ in range(args.steps):
+            bi.topn(k, N)
+        torch.cuda.synchronize()
         prof = rm.profile()
         rm.set_profiling(False)
         kern = {nm: {"launches_per_query": nl / args.steps, "ms_per_query": ms / args.steps}
