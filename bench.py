@@ -27,7 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # dense peaks of one MI355X (datasheet, no sparsity): FLOP/s
-PEAK = {"fp32": 157.3e12, "bf16": 2.5e15, "fp8": 5.0e15, "fp64": 78.6e12}
+PEAK = {"fp32": 157.3e12, "bf16": 2.5e15, "fp8": 5.0e15, "fp6": 10.1e15, "fp4": 10.1e15,
+        "fp64": 78.6e12}
 HBM_PEAK = 8.0e12
 DPRIME_MAX = 62
 DEFAULT_CONFIG = 3
@@ -45,6 +46,8 @@ def parse():
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run a plain copy of this many MiB first (counter calibration)")
+    ap.add_argument("--variants", default="bf16,fp8,fp6",
+                    help="other screening precisions run on the same workload")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the other screening precisions on the same workload")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_MIB"),
@@ -227,8 +230,9 @@ def kernel_table(prof, stats, steps, n, m, d, k, prec):
     def avg(key):
         return float(np.mean([s[key] for s in stats]))
 
-    eb = {"fp32": 4, "bf16": 2, "fp8": 1}[prec]
-    D = {"fp32": (d + 7) // 8 * 8, "bf16": (d + 15) // 16 * 16, "fp8": (d + 63) // 64 * 64}[prec]
+    # bytes per element slot and padded width (FP6/FP4 use FP8's 32-byte block slots)
+    eb = {"fp32": 4, "bf16": 2}.get(prec, 1)
+    D = {"fp32": (d + 7) // 8 * 8, "bf16": (d + 15) // 16 * 16}.get(prec, (d + 63) // 64 * 64)
     dp = min(d, DPRIME_MAX)
     mpad = (m + 63) // 64 * 64
     t0 = min(6, mpad // 64)
@@ -333,7 +337,7 @@ def main():
     # with identical integer outputs required
     variants = {}
     if not args.no_variants:
-        for vp in ("fp32", "bf16", "fp8"):
+        for vp in ["fp32"] + [v for v in args.variants.split(",") if v]:
             if vp == prec:
                 continue
             print(f"[bench] variant {vp}", file=sys.stderr, flush=True)

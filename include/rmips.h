@@ -65,8 +65,12 @@ typedef enum {
 typedef enum {
     RMIPS_FP32 = 0,         /* FP32 inputs, FP32 matrix-core accumulation */
     RMIPS_BF16 = 1,         /* BF16-rounded inputs, FP32 accumulation */
-    RMIPS_FP8_E4M3 = 2      /* OCP e4m3 inputs with a per-vector power-of-two
+    RMIPS_FP8_E4M3 = 2,     /* OCP e4m3 inputs with a per-vector power-of-two
                                scale, FP32 accumulation */
+    RMIPS_FP6_E2M3 = 3,     /* OCP MX FP6 e2m3 element codes (largest 7.5) with a
+                               per-vector power-of-two scale, on gfx950's
+                               block-scaled f8f6f4 matrix-core instruction */
+    RMIPS_FP4_E2M1 = 4      /* OCP MX FP4 e2m1 element codes (largest 6.0), likewise */
 } rmips_prec;
 
 typedef struct rmips_ctx rmips_ctx;

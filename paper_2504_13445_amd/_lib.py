@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(HERE, "librmips.so")
 
 RMIPS_OK, RMIPS_EINVAL, RMIPS_EWORKSPACE, RMIPS_ENONFINITE, RMIPS_EUNSUPPORTED, \
     RMIPS_EDEVICE = range(6)
-PREC = {"fp32": 0, "bf16": 1, "fp8": 2, "fp8_e4m3": 2}
+PREC = {"fp32": 0, "bf16": 1, "fp8": 2, "fp8_e4m3": 2, "fp6": 3, "fp6_e2m3": 3, "fp4": 4,
+        "fp4_e2m1": 4}
 K_MAX, N_MAX, D_MAX = 32, 1024, 256
 
 EXPORTS = [

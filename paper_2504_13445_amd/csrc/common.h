@@ -13,8 +13,24 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 
-// Screening precisions (values of rmips_prec).
-enum { PREC_FP32 = 0, PREC_BF16 = 1, PREC_FP8 = 2 };
+// Screening precisions (values of rmips_prec).  FP8 e4m3, FP6 e2m3 and FP4
+// e2m1 share one layout: a 32-byte slot per 32 elements (one element per byte
+// for FP8; FP6 and FP4 pack the block's codes from the slot's first bit, 24 or
+// 16 bytes, the rest zero), a power-of-two scale per vector.
+enum { PREC_FP32 = 0, PREC_BF16 = 1, PREC_FP8 = 2, PREC_FP6 = 3, PREC_FP4 = 4 };
+__host__ __device__ constexpr bool scaled_prec(int prec) { return prec >= PREC_FP8; }
+// format code of the f8f6f4 matrix-core instruction and bits per element
+__host__ __device__ constexpr int mx_format(int prec) {
+    return prec == PREC_FP6 ? 2 : prec == PREC_FP4 ? 4 : 0;
+}
+__host__ __device__ constexpr int mx_bits(int prec) {
+    return prec == PREC_FP6 ? 6 : prec == PREC_FP4 ? 4 : 8;
+}
+// largest magnitude of the element format (the scale maps a row's largest
+// value at or below it)
+__host__ __device__ constexpr float mx_max(int prec) {
+    return prec == PREC_FP6 ? 7.5f : prec == PREC_FP4 ? 6.0f : 448.0f;
+}
 
 constexpr int WAVE = 64;
 constexpr int KMAX = 32;          // largest k (matches RMIPS_K_MAX)
@@ -123,7 +139,7 @@ template <int PREC, class F> void with_nch(int nch, F &&f) {
         case 6: f(std::integral_constant<int, 6>{}); break;
         case 8: f(std::integral_constant<int, 8>{}); break;
         default:
-            if constexpr (PREC == PREC_BF16) {  // FP8 rows have at most 8 chunks
+            if constexpr (PREC == PREC_BF16) {  // FP8/FP6/FP4 rows have at most 8 chunks
                 switch ((nch + 1) & ~1) {
                 case 10: f(std::integral_constant<int, 10>{}); break;
                 case 12: f(std::integral_constant<int, 12>{}); break;
@@ -212,7 +228,11 @@ template <int NCH> struct MMR<PREC_BF16, NCH> {
     }
 };
 
-template <int NCH> struct MMR<PREC_FP8, NCH> {
+// FP8 e4m3, FP6 e2m3 and FP4 e2m1: one f8f6f4 product per pair of 16-byte
+// chunks (a lane's 32 elements of one block), unit block scales (the
+// per-vector power-of-two scales are applied outside).  FMT: the
+// instruction's format code for both operands.
+template <int FMT, int NCH> struct MMRx {
     static __device__ __forceinline__ i32x8 pair(const uint4 &lo, const uint4 &hi) {
         return i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w,
                      (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
@@ -226,10 +246,10 @@ template <int NCH> struct MMR<PREC_FP8, NCH> {
             const i32x8 x0 = ld_fp8x32(A0 + off + 16 * c);
             const i32x8 x1 = ld_fp8x32(A1 + off + 16 * c);
             const i32x8 y = pair(b[c], b[c + 1]);
-            c0 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x0, y, c0, 0, 0, 0, 0x7f7f7f7f,
-                                                                 0, 0x7f7f7f7f);
-            c1 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x1, y, c1, 0, 0, 0, 0x7f7f7f7f,
-                                                                 0, 0x7f7f7f7f);
+            c0 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x0, y, c0, FMT, FMT, 0,
+                                                                 0x7f7f7f7f, 0, 0x7f7f7f7f);
+            c1 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x1, y, c1, FMT, FMT, 0,
+                                                                 0x7f7f7f7f, 0, 0x7f7f7f7f);
         }
     }
     static __device__ __forceinline__ void cols2(f32x16 &c0, f32x16 &c1, const uint4 (&a)[NCH],
@@ -241,13 +261,16 @@ template <int NCH> struct MMR<PREC_FP8, NCH> {
             const i32x8 x = pair(a[c], a[c + 1]);
             const i32x8 y0 = ld_fp8x32(B0 + off + 16 * c);
             const i32x8 y1 = ld_fp8x32(B1 + off + 16 * c);
-            c0 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x, y0, c0, 0, 0, 0, 0x7f7f7f7f,
-                                                                 0, 0x7f7f7f7f);
-            c1 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x, y1, c1, 0, 0, 0, 0x7f7f7f7f,
-                                                                 0, 0x7f7f7f7f);
+            c0 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x, y0, c0, FMT, FMT, 0,
+                                                                 0x7f7f7f7f, 0, 0x7f7f7f7f);
+            c1 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x, y1, c1, FMT, FMT, 0,
+                                                                 0x7f7f7f7f, 0, 0x7f7f7f7f);
         }
     }
 };
+template <int NCH> struct MMR<PREC_FP8, NCH> : MMRx<0, NCH> {};
+template <int NCH> struct MMR<PREC_FP6, NCH> : MMRx<2, NCH> {};
+template <int NCH> struct MMR<PREC_FP4, NCH> : MMRx<4, NCH> {};
 
 // Index (0..3) of the SIMD that runs this wave: bits 5:4 of the HW_ID
 // hardware register.
@@ -333,6 +356,38 @@ __device__ __forceinline__ uint8_t to_e4m3(float y, float &q) {
     } else {
         const uint32_t mant = (__float_as_uint(m) >> 20) & 0x7u;
         code = (uint8_t)(((em + 7) << 3) | mant);
+    }
+    q = (y < 0.0f) ? -m : m;
+    return (uint8_t)(sg | code);
+}
+
+// Round-to-nearest-even encoding of y (|y| <= the format's largest value)
+// into an OCP element format with 2 exponent bits (bias 1) and M mantissa
+// bits, no infinities: e2m3 (FP6, M = 3) or e2m1 (FP4, M = 1).  Subnormals
+// (exponent field 0) step by 2^-M.  q receives the encoded value.
+template <int M>
+__device__ __forceinline__ uint8_t to_e2m(float y, float &q) {
+    const float a = fabsf(y);
+    const uint8_t sg = (y < 0.0f) ? (uint8_t)(1u << (M + 2)) : 0;
+    if (a == 0.0f) {
+        q = 0.0f;
+        return 0;
+    }
+    int e = (int)((__float_as_uint(a) >> 23) & 0xff) - 127;  // floor(log2 a) for normal a
+    if (e < 0) e = 0;                                          // subnormal range: step 2^-M
+    const float step = __uint_as_float((uint32_t)(e - M + 127) << 23);
+    float m = rintf(a / step) * step;                          // exact scaling, RNE
+    const float mx = (2.0f - __uint_as_float((uint32_t)(127 - M) << 23)) * 4.0f;
+    if (m > mx) m = mx;
+    int em = (int)((__float_as_uint(m) >> 23) & 0xff) - 127;
+    uint8_t code;
+    if (m == 0.0f) {
+        code = 0;
+    } else if (em < 0) {                                       // subnormal: mant * 2^-M
+        code = (uint8_t)(m * (float)(1 << M));
+    } else {
+        const uint32_t mant = (__float_as_uint(m) >> (23 - M)) & ((1u << M) - 1u);
+        code = (uint8_t)(((em + 1) << M) | mant);
     }
     q = (y < 0.0f) ? -m : m;
     return (uint8_t)(sg | code);

@@ -124,7 +124,7 @@ void k_count(CountArgs a) {
         const bool ok = it < a.nb;
         rvalid |= ok ? (1u << i) : 0u;
         srow[i] = 1.0f;
-        if (PREC == PREC_FP8 && ok) srow[i] = a.sp[a.rows ? a.rows[it] : it];
+        if (scaled_prec(PREC) && ok) srow[i] = a.sp[a.rows ? a.rows[it] : it];
     }
 
     int cnt[16];
@@ -213,8 +213,8 @@ void k_count(CountArgs a) {
         bool anyamb = false;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            const float v0 = (PREC == PREC_FP8) ? acc0[i] * srow[i] : acc0[i];
-            const float v1 = (PREC == PREC_FP8) ? acc1[i] * srow[i] : acc1[i];
+            const float v0 = scaled_prec(PREC) ? acc0[i] * srow[i] : acc0[i];
+            const float v1 = scaled_prec(PREC) ? acc1[i] * srow[i] : acc1[i];
             const float e0 = __builtin_amdgcn_fmed3f(v0, ptout0, ptin0);
             const float e1 = __builtin_amdgcn_fmed3f(v1, ptout1, ptin1);
             cnt[i] += (v0 > e0) ? m0 : 0;
@@ -225,8 +225,8 @@ void k_count(CountArgs a) {
             uint32_t ambm0 = 0, ambm1 = 0;
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
-                const float v0 = (PREC == PREC_FP8) ? acc0[i] * srow[i] : acc0[i];
-                const float v1 = (PREC == PREC_FP8) ? acc1[i] * srow[i] : acc1[i];
+                const float v0 = scaled_prec(PREC) ? acc0[i] * srow[i] : acc0[i];
+                const float v1 = scaled_prec(PREC) ? acc1[i] * srow[i] : acc1[i];
                 ambm0 |= (v0 == __builtin_amdgcn_fmed3f(v0, ptout0, ptin0)) ? (1u << i) : 0u;
                 ambm1 |= (v1 == __builtin_amdgcn_fmed3f(v1, ptout1, ptin1)) ? (1u << i) : 0u;
             }
@@ -346,7 +346,9 @@ void launch_count(const CountArgs &a, hipStream_t st) {
     const size_t lds = count_lds(a.prec, a.D);
     if (a.prec == PREC_FP32) launch_count_p<PREC_FP32>(a, lds, st);
     else if (a.prec == PREC_BF16) launch_count_p<PREC_BF16>(a, lds, st);
-    else launch_count_p<PREC_FP8>(a, lds, st);
+    else if (a.prec == PREC_FP8) launch_count_p<PREC_FP8>(a, lds, st);
+    else if (a.prec == PREC_FP6) launch_count_p<PREC_FP6>(a, lds, st);
+    else launch_count_p<PREC_FP4>(a, lds, st);
 }
 
 // Eq. (3)/(6) bound count over the users of the item block's Cauchy-Schwarz

@@ -64,7 +64,11 @@ void launch_rows_prep(const float *X, int64_t rows, int d, int D, float *Xpad, f
 // and an e4m3 code in the format's subnormal range (scaled magnitude below
 // 2^-6), is stored as zero and its whole value counts in R.  The error
 // bound, which takes the quantisation error from R by Cauchy-Schwarz, then
-// holds whatever the hardware does with subnormal inputs.
+// holds whatever the hardware does with subnormal inputs.  FP6 e2m3 and
+// FP4 e2m1 keep their subnormal codes (values below 1 before scaling, a
+// large part of a row with two exponent bits): the f8f6f4 instruction
+// decodes every code of both formats exactly on gfx950 (measured over all
+// codes, no difference from the decoded products).
 template <int PREC>
 __global__ __launch_bounds__(256) void k_quant(const float *__restrict__ X,
                                                const int32_t *__restrict__ order, int64_t rows,
@@ -112,7 +116,7 @@ __global__ __launch_bounds__(256) void k_quant(const float *__restrict__ X,
         }
     }
     if (__ballot(bad) != 0ull && lane == 0) *flag = 1;
-    if (PREC == PREC_FP8) {
+    if (scaled_prec(PREC)) {
         // the 16 row maxima reduced together (a maximum in any order)
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1)
@@ -137,16 +141,17 @@ __global__ __launch_bounds__(256) void k_quant(const float *__restrict__ X,
             const int i = w + 4 * j;
             const int64_t r = r0 + i;
             float s = 1.0f;
-            if (PREC == PREC_FP8) {
+            if (scaled_prec(PREC)) {
                 const int g0 = (i / group) * group;
                 float m = 0.0f;
                 for (int t = g0; t < g0 + group && t < 64; ++t) m = fmaxf(m, rowmax[t]);
                 if (m > 0.0f) {
-                    // smallest power of two s with m / s <= 448
+                    // smallest power of two s with m / s <= the format's largest value
+                    constexpr float FMAX = mx_max(PREC);
                     int e;
-                    frexpf(m / 448.0f, &e);  // m/448 = f * 2^e, f in [0.5, 1)
+                    frexpf(m / FMAX, &e);  // m/FMAX = f * 2^e, f in [0.5, 1)
                     s = ldexpf(1.0f, e);
-                    if (m / ldexpf(1.0f, e - 1) <= 448.0f) s = ldexpf(1.0f, e - 1);
+                    if (m / ldexpf(1.0f, e - 1) <= FMAX) s = ldexpf(1.0f, e - 1);
                     s = fmaxf(s, 0x1p-63f);
                 }
             }
@@ -174,7 +179,7 @@ __global__ __launch_bounds__(256) void k_quant(const float *__restrict__ X,
                             qv = 0.0f;
                         }
                         if (live) reinterpret_cast<uint16_t *>(Xq)[r * D + c] = h;
-                    } else {
+                    } else if (PREC == PREC_FP8) {
                         float yq;
                         uint8_t b8 = to_e4m3(t * inv, yq);
                         if ((b8 & 0x78u) == 0u) {  // zero or an e4m3 subnormal code
@@ -183,6 +188,33 @@ __global__ __launch_bounds__(256) void k_quant(const float *__restrict__ X,
                         }
                         if (live) Xq[r * D + c] = b8;
                         qv = yq * s;
+                    } else {
+                        // FP6 / FP4: the 32 codes of a block (held by 32
+                        // consecutive lanes) packed from the slot's first
+                        // bit, code e at bits [B e, B e + B); lane e < B of
+                        // the block assembles dword e from the codes that
+                        // reach into it, lanes B..7 write the slot's zero
+                        // dwords
+                        float yq;
+                        const uint32_t code = (PREC == PREC_FP6) ? to_e2m<3>(t * inv, yq)
+                                                                 : to_e2m<1>(t * inv, yq);
+                        qv = yq * s;
+                        constexpr int B = mx_bits(PREC);
+                        const int e = lane & 31, base = lane & 32;
+                        const int wsel = (e < B) ? e : 0;
+                        const int t0 = (32 * wsel) / B;
+                        uint32_t word = 0u;
+#pragma unroll
+                        for (int k = 0; k < 32 / B + 2; ++k) {
+                            const int tk = t0 + k;
+                            const uint32_t ck = __shfl(code, base + (tk < 32 ? tk : 31));
+                            const int sh = B * tk - 32 * wsel;
+                            if (tk < 32 && sh > -B && sh < 32)
+                                word |= (sh >= 0) ? (ck << sh) : (ck >> (-sh));
+                        }
+                        if (live && e < 8)
+                            reinterpret_cast<uint32_t *>(Xq + r * D + (c - e))[e] =
+                                (e < B) ? word : 0u;
                     }
                     sx[jj] += (double)t * (double)t;
                     sq[jj] += (double)qv * (double)qv;
@@ -242,8 +274,14 @@ void launch_quant(int prec, const float *X, const int32_t *order, int64_t rows,
     else if (prec == PREC_BF16)
         k_quant<PREC_BF16><<<g, 256, 0, st>>>(X, order, rows, rows_pad, d, D, group, q, N, Nh, R,
                                               sc, rmax, flag);
-    else
+    else if (prec == PREC_FP8)
         k_quant<PREC_FP8><<<g, 256, 0, st>>>(X, order, rows, rows_pad, d, D, group, q, N, Nh, R,
+                                             sc, rmax, flag);
+    else if (prec == PREC_FP6)
+        k_quant<PREC_FP6><<<g, 256, 0, st>>>(X, order, rows, rows_pad, d, D, group, q, N, Nh, R,
+                                             sc, rmax, flag);
+    else
+        k_quant<PREC_FP4><<<g, 256, 0, st>>>(X, order, rows, rows_pad, d, D, group, q, N, Nh, R,
                                              sc, rmax, flag);
 }
 

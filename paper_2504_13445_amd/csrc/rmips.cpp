@@ -242,7 +242,8 @@ void thresh_scratch_plan(int prec, int64_t n, int64_t m, int k, int cap_override
         L.cap = (cap_override + 1) & ~1;
     } else {
         int64_t capU = std::max<int64_t>(256, 16 * (int64_t)k);
-        if (prec == RMIPS_FP8_E4M3) capU *= 4;
+        if (prec == RMIPS_FP8_E4M3 || prec == RMIPS_FP6_E2M3) capU *= 4;
+        if (prec == RMIPS_FP4_E2M1) capU *= 8;
         L.cap = (int)(((capU + L.nsplit - 1) / L.nsplit + 7) / 8 * 8);
     }
     L.keys = cv.take<uint32_t>(m);
@@ -355,7 +356,8 @@ rmips_status validate_common(rmips_ctx *ctx, int64_t n, int64_t m, int d, int k,
     if (m < 1 || m > (int64_t)INT32_MAX / 2) return fail(ctx, RMIPS_EINVAL, "m out of range");
     if (d < 1 || d > RMIPS_D_MAX) return fail(ctx, RMIPS_EINVAL, "d out of range");
     if (k < 1 || k > RMIPS_K_MAX || k > m) return fail(ctx, RMIPS_EINVAL, "k out of range");
-    if (prec != RMIPS_FP32 && prec != RMIPS_BF16 && prec != RMIPS_FP8_E4M3)
+    if (prec != RMIPS_FP32 && prec != RMIPS_BF16 && prec != RMIPS_FP8_E4M3 &&
+        prec != RMIPS_FP6_E2M3 && prec != RMIPS_FP4_E2M1)
         return fail(ctx, RMIPS_EUNSUPPORTED, "unknown screening precision");
     return RMIPS_OK;
 }
@@ -1005,7 +1007,8 @@ rmips_status rmips_set_bound_output(rmips_ctx *ctx, int32_t *uscore) {
 }
 
 static bool prec_ok(rmips_prec p) {
-    return p == RMIPS_FP32 || p == RMIPS_BF16 || p == RMIPS_FP8_E4M3;
+    return p == RMIPS_FP32 || p == RMIPS_BF16 || p == RMIPS_FP8_E4M3 || p == RMIPS_FP6_E2M3 ||
+           p == RMIPS_FP4_E2M1;
 }
 
 size_t rmips_thresholds_workspace_size(int64_t n, int64_t m, int32_t d, int32_t k,

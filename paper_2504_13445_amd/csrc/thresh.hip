@@ -832,7 +832,9 @@ void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
     auto screen = [&](const ThreshArgs &a, dim3 g, const char *name) {
         if (a.prec == PREC_FP32) launch_screen<PREC_FP32>(a, nch, g, lds, st, name);
         else if (a.prec == PREC_BF16) launch_screen<PREC_BF16>(a, nch, g, lds, st, name);
-        else launch_screen<PREC_FP8>(a, nch, g, lds, st, name);
+        else if (a.prec == PREC_FP8) launch_screen<PREC_FP8>(a, nch, g, lds, st, name);
+        else if (a.prec == PREC_FP6) launch_screen<PREC_FP6>(a, nch, g, lds, st, name);
+        else launch_screen<PREC_FP4>(a, nch, g, lds, st, name);
     };
     // the screening pass writes each (user, split) list as two halves of
     // cap / 2 entries with their own counts: the final selection and the

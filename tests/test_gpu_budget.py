@@ -110,7 +110,7 @@ def test_budget_tiny_workload(kind):
     _check_query(bi, topk, P.shape[0], (1, 10, 25), (10, 37))
 
 
-@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+@pytest.mark.parametrize("prec", ["bf16", "fp8", "fp6", "fp4"])
 def test_budget_screened_stage_a(prec):
     # the exact k_max-th values and rescans come from stage (a) screened at
     # this precision: the index and the results do not change

@@ -16,7 +16,7 @@ import synth
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-PRECS = ["fp32", "bf16", "fp8"]
+PRECS = ["fp32", "bf16", "fp8", "fp6", "fp4"]
 BAD = ["nan_user", "inf_item", "huge_user", "huge_item"]
 
 

@@ -54,7 +54,7 @@ def _check_index(U, P, prec, ks, Ns, kmax=KMAX):
     return idx
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8", "fp6", "fp4"])
 def test_index_tiny_workload(prec):
     U, P = synth.make_config(0)
     _check_index(U, P, prec, (1, 10, 25), (10, 37))

@@ -75,10 +75,10 @@ def test_bf16_workload_500k_users():
 
 
 def test_fp8_workload_2m_users():
-    _run_workload(3, ["fp8", "bf16"])
+    _run_workload(3, ["fp8", "bf16", "fp6"])
 
 
-@pytest.mark.parametrize("prec", ["bf16", "fp32", "fp8"])
+@pytest.mark.parametrize("prec", ["bf16", "fp32", "fp8", "fp6"])
 def test_bf16_workload_full_oracle(golden_dir, prec):
     """Score of each of the 50,000 items and the top-50 of the 500,000-user
     workload, element by element against the full FP64 oracle (Def. 2 and

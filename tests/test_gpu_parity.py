@@ -32,7 +32,7 @@ def _g(x):
     return torch.from_numpy(np.ascontiguousarray(x)).to(_dev())
 
 
-PRECS = ["fp32", "bf16", "fp8"]
+PRECS = ["fp32", "bf16", "fp8", "fp6", "fp4"]
 
 
 def _check_thresholds(U, P, k, **kw):
@@ -302,7 +302,10 @@ def test_topn_refinement_passes(prec, cap):
     st = _check_topn(U, P, 10, 10, topk_ref=tk, cand_cap=cap, prec=prec)
     print("stats", st, flush=True)
     assert st["refine_users"] + st["overflow_users"] > 0
-    if cap >= 4:
+    if cap >= 4 and prec != "fp4":
+        # (with e2m1's band the lower bounds among a few stored candidates
+        # never improve on the starting bound: every overflowing user goes
+        # to the exact fallback instead)
         assert st["refine_users"] > 0
     _check_thresholds(U, P, 10, cand_cap=cap, prec=prec)
 
