@@ -248,12 +248,13 @@ def kernel_table(prof, stats, steps, n, m, d, k, prec):
         "k_quant": ((n + m) * (4.0 * d + D * eb + 16.0), "byte", HBM_PEAK, "hbm"),
         # candidate lists read (value, bound, id: 12 B each), tau and id written
         "k_thresh_final/main": (12.0 * avg("cand_listed") + 12.0 * n, "byte", HBM_PEAK, "hbm"),
-        # FP32 item rows gathered for the FP64 recomputations
-        "k_thresh_exact/main": (4.0 * d * avg("cand_pairs"), "byte", HBM_PEAK, "hbm"),
         # users' screening rows in rho order: gathered once
         "k_gather_padded": (2.0 * n * D * eb, "byte", HBM_PEAK, "hbm"),
     }
     table = {}
+    # (the stage (a) recomputations, cand_pairs FP32 item rows gathered, are
+    # shared by k_thresh_final, k_thresh_exact and k_thresh_exact_wide in
+    # proportions the statistics do not give: no per-kernel work for them)
     for name, launches, ms in prof:
         e = {"launches_per_step": launches / steps, "ms_per_step": ms / steps,
              "ms_per_launch": ms / max(launches, 1)}

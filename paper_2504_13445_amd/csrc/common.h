@@ -34,6 +34,7 @@ __host__ __device__ constexpr float mx_max(int prec) {
 
 constexpr int WAVE = 64;
 constexpr int KMAX = 32;          // largest k (matches RMIPS_K_MAX)
+constexpr int DMAX = 256;         // largest d (matches RMIPS_D_MAX)
 constexpr int TILE_ITEMS = 64;    // items per streamed tile in stage (a)
 constexpr int LDS_PAD = 4;        // floats added to an LDS row (bank spread)
 // Absolute term of every screening error bound: covers the rounding of
@@ -472,6 +473,54 @@ __device__ __forceinline__ double ip64(const float *__restrict__ u,
         for (int j = 0; j < BLK; ++j) acc = __fma_rn((double)x[j], (double)y[j], acc);
     }
     return acc;
+}
+
+// Exact values of u . p0 and u . p1 (ip64's arithmetic, term by term), the
+// two rows' blocks loaded together so that twice the bytes are in flight per
+// lane, and the user's block once for both.
+__device__ __forceinline__ void ip64x2(const float *__restrict__ u, const float *__restrict__ p0,
+                                       const float *__restrict__ p1, int d, double &r0,
+                                       double &r1) {
+    const uintptr_t al = reinterpret_cast<uintptr_t>(u) | reinterpret_cast<uintptr_t>(p0) |
+                         reinterpret_cast<uintptr_t>(p1);
+    if ((d & 3) != 0 || (al & 15) != 0) {
+        r0 = ip64(u, p0, d);
+        r1 = ip64(u, p1, d);
+        return;
+    }
+    constexpr int RV = 4;
+    const float4 *u4 = reinterpret_cast<const float4 *>(u);
+    const float4 *a4 = reinterpret_cast<const float4 *>(p0);
+    const float4 *b4 = reinterpret_cast<const float4 *>(p1);
+    const int d4 = d >> 2;
+    double s0 = 0.0, s1 = 0.0;
+    for (int i = 0; i < d4; i += RV) {
+        float4 x[RV], y[RV], z[RV];
+#pragma unroll
+        for (int j = 0; j < RV; ++j) {
+            const bool ok = i + j < d4;
+            const int t = ok ? i + j : d4 - 1;
+            const float4 a = u4[t], b = a4[t], c = b4[t];
+            // (selects per value: a select between two vectors in memory
+            // would be made through private memory)
+            x[j] = make_float4(ok ? a.x : 0.f, ok ? a.y : 0.f, ok ? a.z : 0.f, ok ? a.w : 0.f);
+            y[j] = make_float4(ok ? b.x : 0.f, ok ? b.y : 0.f, ok ? b.z : 0.f, ok ? b.w : 0.f);
+            z[j] = make_float4(ok ? c.x : 0.f, ok ? c.y : 0.f, ok ? c.z : 0.f, ok ? c.w : 0.f);
+        }
+#pragma unroll
+        for (int j = 0; j < RV; ++j) {
+            s0 = __fma_rn((double)x[j].x, (double)y[j].x, s0);
+            s1 = __fma_rn((double)x[j].x, (double)z[j].x, s1);
+            s0 = __fma_rn((double)x[j].y, (double)y[j].y, s0);
+            s1 = __fma_rn((double)x[j].y, (double)z[j].y, s1);
+            s0 = __fma_rn((double)x[j].z, (double)y[j].z, s0);
+            s1 = __fma_rn((double)x[j].z, (double)z[j].z, s1);
+            s0 = __fma_rn((double)x[j].w, (double)y[j].w, s0);
+            s1 = __fma_rn((double)x[j].w, (double)z[j].w, s1);
+        }
+    }
+    r0 = s0;
+    r1 = s1;
 }
 
 // Pair rule of the tie order: item `id` with value v belongs to S_k(u) iff

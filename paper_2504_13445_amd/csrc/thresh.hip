@@ -397,10 +397,13 @@ __device__ void wave_sort_pairs(double *v, int *id, int n, int lane) {
 
 constexpr int FIN_WAVES = 4;
 constexpr int FIN_WPE = 4;  // waves per SIMD of the final selection
-constexpr int FIN_ENTRY_BYTES = 16;  // LDS bytes per list entry of the final selection
+constexpr int FIN_ENTRY_BYTES = 12;  // LDS bytes per list entry of the final selection
 size_t final_entry_bytes() { return FIN_ENTRY_BYTES; }
-// recomputations per user handed from k_thresh_final to k_thresh_exact
+// recomputations per user handed from k_thresh_final to k_thresh_exact;
+// more, up to EXACT_WIDE, go to k_thresh_exact_wide
 constexpr int EXACT_SLOTS = 8;
+constexpr int EXACT_WIDE_J = 4;  // values per lane in k_thresh_exact_wide (even)
+constexpr int EXACT_WIDE = 64 * EXACT_WIDE_J;
 
 // Orders this wave's LDS accesses (every list of the final selection is
 // private to one wave, so no workgroup barrier is needed).
@@ -425,15 +428,15 @@ void k_thresh_final(ThreshArgs a, int capT, int capP) {
     extern __shared__ float smem[];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int nw = blockDim.x >> 6;  // waves per block (one user each)
-    // per-wave LDS (FIN_ENTRY_BYTES per entry): lo, hi (float), cidx, sid
-    // (int); the FP64 values v64 take the place of lo and hi once those are
-    // no longer read
+    // per-wave LDS (FIN_ENTRY_BYTES per entry): lo, hi (float), cidx (int),
+    // the survivors and then the values to recompute compacted in place; the
+    // FP64 values v64 take the place of lo and hi once those are no longer
+    // read
     uint8_t *base = reinterpret_cast<uint8_t *>(smem) + (size_t)w * capP * FIN_ENTRY_BYTES;
     float *lo = reinterpret_cast<float *>(base);
     float *hi = lo + capP;
     double *v64 = reinterpret_cast<double *>(base);
     int *cidx = reinterpret_cast<int *>(hi + capP);
-    int *sid = cidx + capP;
     __shared__ float Lstar[FIN_WAVES];
     __shared__ int nsurv[FIN_WAVES];
     constexpr bool listed = LISTED;
@@ -546,8 +549,9 @@ void k_thresh_final(ThreshArgs a, int capT, int capP) {
         }
         const bool work = valid && !over;
         if (work) st_cand += (unsigned long long)total;
-        // survivors: upper bound reaches L*; keep their caller ids, and
-        // their bounds in place (a survivor's slot is at most its index)
+        // survivors: upper bound reaches L*; their caller ids and bounds
+        // compacted in place (a survivor's slot is at most its index, and each
+        // round of 64 reads its entries before it writes)
         if (work) {
             const float Ls = Lstar[w];
             int cntw = 0;
@@ -566,7 +570,7 @@ void k_thresh_final(ThreshArgs a, int capT, int capP) {
                 const int p = cntw + __popcll(bal & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
                 __builtin_amdgcn_wave_barrier();
                 if (keep) {
-                    sid[p] = c;
+                    cidx[p] = c;
                     lo[p] = l;
                     hi[p] = h;
                 }
@@ -580,7 +584,7 @@ void k_thresh_final(ThreshArgs a, int capT, int capP) {
         // item; with A such survivors, tau is the (k - A)-th of the others, and
         // only those are recomputed.
         const bool band = a.topk == nullptr;
-        int *rid = band ? cidx : sid;
+        int *rid = cidx;
         if (work) {
             const int ns = nsurv[w];
             int nrec = ns;
@@ -595,7 +599,7 @@ void k_thresh_final(ThreshArgs a, int capT, int capP) {
                         int c = -1;  // the survivor itself
                         for (int q = 0; q < ns; ++q) c += hi[q] >= x;
                         unc = c > a.k - 2;
-                        id = sid[p];
+                        id = cidx[p];
                     }
                     const uint64_t bal = __ballot(unc);
                     const int q = cntb + __popcll(bal & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
@@ -608,17 +612,19 @@ void k_thresh_final(ThreshArgs a, int capT, int capP) {
             st_rec += (unsigned long long)nrec;
         }
         wave_sync();
-        // Only tau asked for and at most EXACT_SLOTS values to recompute: they
-        // are left to k_thresh_exact, which packs several users per wave.  The
-        // ids go to this user's candidate slots (read above), the target rank
-        // and the count to its first count slot; -1 there for every other
-        // user of the list.
+        // Only tau asked for: the values to recompute are left to
+        // k_thresh_exact (at most EXACT_SLOTS, several users per wave) or
+        // k_thresh_exact_wide (up to EXACT_WIDE, a wave per user), which hold
+        // no lists in LDS and so keep many more row gathers in flight than
+        // this kernel.  The ids go to this user's candidate slots (read
+        // above), the target rank and the count to its first count slot; -1
+        // there for every other user of the list.
         const int nrec_w = nsurv[w] & 0xffff;
-        const bool defer = work && band && nrec_w <= EXACT_SLOTS;
+        const bool defer = work && band && nrec_w <= EXACT_WIDE;
         if (valid) {
             if (defer) {
                 const int64_t c0 = u * a.nsplit * (int64_t)a.cap;
-                if (lane < nrec_w) a.cand_id[c0 + lane] = rid[lane];
+                for (int q = lane; q < nrec_w; q += 64) a.cand_id[c0 + q] = rid[q];
                 if (lane == 0)
                     a.cand_cnt[u * a.nsplit] = (a.k - 1 - (nsurv[w] >> 16)) | (nrec_w << 8);
             } else if (lane == 0) {
@@ -687,7 +693,9 @@ __global__ __launch_bounds__(256) void k_thresh_exact(ThreshArgs a) {
         const bool valid = pos < nlist;
         const int64_t u = valid ? (LISTED ? (int64_t)a.ulist[pos] : pos) : 0;
         const int meta = valid ? a.cand_cnt[u * a.nsplit] : -1;
-        const int nrec = meta < 0 ? 0 : meta >> 8, tgt = meta & 255;
+        // (longer lists are k_thresh_exact_wide's)
+        const int nrec = (meta < 0 || (meta >> 8) > EXACT_SLOTS) ? 0 : meta >> 8;
+        const int tgt = meta & 255;
         const bool have = q < nrec;
         int id = 0;
         double v = 0.0;
@@ -707,6 +715,122 @@ __global__ __launch_bounds__(256) void k_thresh_exact(ThreshArgs a) {
         if (have && rank == tgt) {
             a.tau[u] = v;
             a.tau_id[u] = id;
+        }
+    }
+}
+
+// u . p (ip64's arithmetic, term by term) with the user's row staged in LDS
+// (ul, 16-byte aligned): 32 values of the item row per step, so that a
+// lane's loads of a step cover whole 128-byte blocks of it.  Rows that are
+// not 16-byte vectors go through ip64 with the user's row from memory.
+__device__ __forceinline__ double ip64_lds_user(const float *ul, const float *ug,
+                                                const float *__restrict__ p, int d) {
+    if ((d & 3) != 0 || (reinterpret_cast<uintptr_t>(p) & 15) != 0) return ip64<16>(ug, p, d);
+    constexpr int RV = 8;
+    const float4 *u4 = reinterpret_cast<const float4 *>(ul);
+    const float4 *p4 = reinterpret_cast<const float4 *>(p);
+    const int d4 = d >> 2;
+    double acc = 0.0;
+    for (int i = 0; i < d4; i += RV) {
+        float4 y[RV];
+#pragma unroll
+        for (int j = 0; j < RV; ++j) y[j] = p4[i + j < d4 ? i + j : d4 - 1];
+#pragma unroll
+        for (int j = 0; j < RV; ++j) {
+            const bool ok = i + j < d4;
+            const float4 x = u4[ok ? i + j : d4 - 1];
+            acc = __fma_rn((double)(ok ? x.x : 0.f), (double)(ok ? y[j].x : 0.f), acc);
+            acc = __fma_rn((double)(ok ? x.y : 0.f), (double)(ok ? y[j].y : 0.f), acc);
+            acc = __fma_rn((double)(ok ? x.z : 0.f), (double)(ok ? y[j].z : 0.f), acc);
+            acc = __fma_rn((double)(ok ? x.w : 0.f), (double)(ok ? y[j].w : 0.f), acc);
+        }
+    }
+    return acc;
+}
+
+// The recomputations of users with more than EXACT_SLOTS (at most
+// EXACT_WIDE) values: a wave per user, each lane up to EXACT_WIDE_J values
+// in registers (lane l: values l, l + 64, ...); tau_u, the value of rank tgt
+// in the order (value desc, id asc), by tgt + 1 rounds of a wave-wide
+// maximum.  Each wave reads the metadata of 64 users at a time and takes the
+// wide ones in turn.
+template <bool LISTED>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+void k_thresh_exact_wide(ThreshArgs a) {
+    __shared__ __align__(16) float urow_s[4][DMAX];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int nw = blockDim.x >> 6;
+    const int64_t nlist = LISTED ? (int64_t)*a.ulist_cnt : a.n;
+    const int64_t capU = (int64_t)a.nsplit * a.cap;
+    float *ul = urow_s[w];
+    for (int64_t c0 = ((int64_t)blockIdx.x * nw + w) * 64; c0 < nlist;
+         c0 += (int64_t)gridDim.x * nw * 64) {
+        const int64_t pos = c0 + lane;
+        int64_t myu = 0;
+        int meta = -1;
+        if (pos < nlist) {
+            myu = LISTED ? (int64_t)a.ulist[pos] : pos;
+            meta = a.cand_cnt[myu * a.nsplit];
+        }
+        uint64_t wide = __ballot(meta >= 0 && (meta >> 8) > EXACT_SLOTS);
+        while (wide != 0ull) {
+            const int src = __builtin_ctzll(wide);
+            wide &= wide - 1ull;
+            // (wave-uniform)
+            const int64_t u = __builtin_amdgcn_readfirstlane((int)__shfl(myu, src));
+            const int mt = __builtin_amdgcn_readfirstlane(__shfl(meta, src));
+            const int nrec = mt >> 8, tgt = mt & 255;
+            const int32_t *ids = a.cand_id + u * capU;
+            const float *urow = a.U + u * a.d;
+            wave_sync();  // the previous user's row is no longer read
+            for (int i = lane; i < a.d; i += 64) ul[i] = urow[i];
+            wave_sync();
+            double v[EXACT_WIDE_J];
+            int id[EXACT_WIDE_J];
+            uint32_t avail = 0u;  // bit j: value j held and not yet taken
+#pragma unroll
+            for (int j = 0; j < EXACT_WIDE_J; ++j) {
+                const int q = lane + 64 * j;
+                v[j] = -INFINITY;
+                id[j] = 0;
+                if (64 * j < nrec && q < nrec) {
+                    id[j] = ids[q];
+                    v[j] = ip64_lds_user(ul, urow, a.P + (int64_t)id[j] * a.d, a.d);
+                    avail |= 1u << j;
+                }
+            }
+            double bv = -INFINITY;
+            int bi = 0x7fffffff;
+            for (int r = 0; r <= tgt; ++r) {
+                // this lane's best value not yet taken, then the wave's
+                double lv = -INFINITY;
+                int li = 0x7fffffff, lj = -1;
+#pragma unroll
+                for (int j = 0; j < EXACT_WIDE_J; ++j) {
+                    const bool better = ((avail >> j) & 1u) &&
+                                        (lj < 0 || v[j] > lv || (v[j] == lv && id[j] < li));
+                    lv = better ? v[j] : lv;
+                    li = better ? id[j] : li;
+                    lj = better ? j : lj;
+                }
+                bv = lv;
+                bi = li;
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+                    const double ov = __shfl_xor(bv, o);
+                    const int oi = __shfl_xor(bi, o);
+                    if (ov > bv || (ov == bv && oi < bi)) {
+                        bv = ov;
+                        bi = oi;
+                    }
+                }
+                // the ids are distinct: the lane holding the maximum takes it
+                if (lj >= 0 && li == bi) avail &= ~(1u << lj);
+            }
+            if (lane == 0) {
+                a.tau[u] = bv;
+                a.tau_id[u] = bi;
+            }
         }
     }
 }
@@ -828,6 +952,9 @@ void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
     // (three 4-wave workgroups per CU are resident)
     const int64_t eblocks = std::min<int64_t>(
         (a0.n + 4 * (64 / EXACT_SLOTS) - 1) / (4 * (64 / EXACT_SLOTS)), 3 * 256);
+    // a wave per 64 users of the list, four per workgroup, a few resident
+    // rounds
+    const int64_t wblocks = std::min<int64_t>((a0.n + 255) / 256, 8 * 256);
     int32_t *LA = a0.lists, *LB = a0.lists + a0.n, *LF = a0.lists + 2 * a0.n;
     auto screen = [&](const ThreshArgs &a, dim3 g, const char *name) {
         if (a.prec == PREC_FP32) launch_screen<PREC_FP32>(a, nch, g, lds, st, name);
@@ -839,7 +966,8 @@ void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
     // the screening pass writes each (user, split) list as two halves of
     // cap / 2 entries with their own counts: the final selection and the
     // deferred recomputations read them as 2 * nsplit lists
-    auto final = [&](const ThreshArgs &a, int capT, const char *nf, const char *ne) {
+    auto final = [&](const ThreshArgs &a, int capT, const char *nf, const char *ne,
+                     const char *nw) {
         ThreshArgs h = a;
         h.nsplit = 2 * a.nsplit;
         h.cap = a.cap / 2;
@@ -847,8 +975,12 @@ void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
             RMIPS_PROF(st, nf);
             k_thresh_final<true><<<(unsigned)fblocks, 64 * fw, lds_fin, st>>>(h, capT, capP);
         }
-        RMIPS_PROF(st, ne);
-        k_thresh_exact<true><<<(unsigned)eblocks, 256, 0, st>>>(h);
+        {
+            RMIPS_PROF(st, ne);
+            k_thresh_exact<true><<<(unsigned)eblocks, 256, 0, st>>>(h);
+        }
+        RMIPS_PROF(st, nw);
+        k_thresh_exact_wide<true><<<(unsigned)wblocks, 256, 0, st>>>(h);
     };
     // bounds-only pass (the launch without a user list): every user's L0
     // from the first tiles (phase 1), in workgroups of its own size
@@ -879,7 +1011,7 @@ void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
     if (a.ev0) (void)hipEventRecord(a.ev0, st);
     screen(a, dim3((unsigned)ublocks, (unsigned)a.nsplit), "k_thresh_screen/main");
     if (a.ev1) (void)hipEventRecord(a.ev1, st);
-    final(a, capU, "k_thresh_final/main", "k_thresh_exact/main");
+    final(a, capU, "k_thresh_final/main", "k_thresh_exact/main", "k_thresh_exact_wide/main");
     // refinement passes over the users whose lists overflowed: the same
     // per-user capacity in fewer, longer lists per split
     int nsr = capU / 64;
@@ -900,7 +1032,8 @@ void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
         // are usually empty, and the workgroups loop over long ones
         const int64_t gx = ublocks < 256 / nsr ? ublocks : 256 / nsr;
         screen(b, dim3((unsigned)gx, (unsigned)nsr), "k_thresh_screen/refine");
-        final(b, b.nsplit * b.cap, "k_thresh_final/refine", "k_thresh_exact/refine");
+        final(b, b.nsplit * b.cap, "k_thresh_final/refine", "k_thresh_exact/refine",
+              "k_thresh_exact_wide/refine");
     }
     int64_t fb = (a0.n + FB_WAVES - 1) / FB_WAVES;
     if (fb > 1024) fb = 1024;
