@@ -356,7 +356,9 @@ void launch_count(const CountArgs &a, hipStream_t st) {
 // plus its rounding slack: [W p, tail(p), ||p||] . [W u, tail(u), s ||u||],
 // each row stored as BF16 hi and lo parts (x = hi + lo + e, |e| <= 2^-16 |x|)
 // and multiplied as hi.hi + hi.lo + lo.hi: three BF16 matrix-core steps per
-// 16 terms, the dropped terms being covered by s.
+// 16 terms, the dropped terms being covered by s.  HI: hi.hi alone, one step
+// per 16 terms, for rows whose s also covers the lo parts (used where the
+// bound has a Cauchy-Schwarz tail, which the larger slack barely loosens).
 //
 // A workgroup of BW waves holds 32 * TI items (TI 32-row tiles, hi and lo)
 // in every wave's registers; each wave reads blocks of 32 users straight from
@@ -372,7 +374,7 @@ __device__ __forceinline__ float float_pred(float t) {
     return __uint_as_float(t > 0.0f ? b - 1u : (t < 0.0f ? b + 1u : 0x80000001u));
 }
 
-template <int KS>
+template <int KS, bool HI>
 __global__ __launch_bounds__(64 * BW) void k_bound(BoundArgs a) {
     constexpr int TI = bound_tiles(KS), BI = 32 * TI, RW = 4 * KS;  // RW: 16-byte words per row
     __shared__ int wsum[BW][BI];
@@ -392,7 +394,7 @@ __global__ __launch_bounds__(64 * BW) void k_bound(BoundArgs a) {
             uint4 x = make_uint4(0, 0, 0, 0), y = x;
             if (r < a.mpad) {
                 x = a.Pb[r * RW + 2 * q + h];
-                y = a.Pb[r * RW + 2 * KS + 2 * q + h];
+                if constexpr (!HI) y = a.Pb[r * RW + 2 * KS + 2 * q + h];
             }
             ah[t][q] = __builtin_bit_cast(bf16x8, x);
             al[t][q] = __builtin_bit_cast(bf16x8, y);
@@ -418,7 +420,7 @@ __global__ __launch_bounds__(64 * BW) void k_bound(BoundArgs a) {
 #pragma unroll
         for (int q = 0; q < KS; ++q) {
             bh[q] = a.Ub[uc * RW + 2 * q + h];
-            bl[q] = a.Ub[uc * RW + 2 * KS + 2 * q + h];
+            if constexpr (!HI) bl[q] = a.Ub[uc * RW + 2 * KS + 2 * q + h];
         }
         tl = float_pred(a.tau_lo[uc] - a.abs_slack);
         vm = ok ? 1 : 0;
@@ -442,8 +444,10 @@ __global__ __launch_bounds__(64 * BW) void k_bound(BoundArgs a) {
                 const bf16x8 yh = __builtin_bit_cast(bf16x8, bh[q]);
                 const bf16x8 yl = __builtin_bit_cast(bf16x8, bl[q]);
                 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t][q], yh, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t][q], yl, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[t][q], yh, acc, 0, 0, 0);
+                if constexpr (!HI) {
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t][q], yl, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[t][q], yh, acc, 0, 0, 0);
+                }
             }
         };
         auto tally = [&](int t, const f32x16 &acc) {
@@ -500,7 +504,7 @@ __global__ __launch_bounds__(64 * BW) void k_bound(BoundArgs a) {
 constexpr int BLW = 8;       // waves per workgroup
 constexpr int BL_USERS = 64;  // users per stage
 
-template <int KS>
+template <int KS, bool HI>
 __global__ __launch_bounds__(64 * BLW) __attribute__((amdgpu_waves_per_eu(2)))
 void k_bound_lds(BoundArgs a) {
     constexpr int TI = 2, BI = 32 * TI * BLW, RW = 4 * KS, LSL = RW + 1;  // LSL: LDS row slots
@@ -525,7 +529,7 @@ void k_bound_lds(BoundArgs a) {
             uint4 x = make_uint4(0, 0, 0, 0), y = x;
             if (r < a.mpad) {
                 x = a.Pb[r * RW + 2 * q + h];
-                y = a.Pb[r * RW + 2 * KS + 2 * q + h];
+                if constexpr (!HI) y = a.Pb[r * RW + 2 * KS + 2 * q + h];
             }
             ah[t][q] = __builtin_bit_cast(bf16x8, x);
             al[t][q] = __builtin_bit_cast(bf16x8, y);
@@ -594,22 +598,27 @@ void k_bound_lds(BoundArgs a) {
 #pragma unroll
             for (int q = 0; q < KS; ++q) {
                 const bf16x8 yh = __builtin_bit_cast(bf16x8, U[ul * LSL + 2 * q + h]);
-                const bf16x8 yl = __builtin_bit_cast(bf16x8, U[ul * LSL + 2 * KS + 2 * q + h]);
 #pragma unroll
                 for (int t = 0; t < TI; ++t) {
                     nc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t][q], yh, nc[t], 0, 0, 0);
-                    nc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t][q], yl, nc[t], 0, 0, 0);
-                    nc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[t][q], yh, nc[t], 0, 0, 0);
+                    if constexpr (!HI) {
+                        const bf16x8 yl =
+                            __builtin_bit_cast(bf16x8, U[ul * LSL + 2 * KS + 2 * q + h]);
+                        nc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t][q], yl, nc[t], 0, 0, 0);
+                        nc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[t][q], yh, nc[t], 0, 0, 0);
+                    }
                 }
             }
 #pragma unroll
             for (int t = 0; t < TI; ++t)
 #pragma unroll
                 for (int i = 0; i < 16; ++i) cnt[t][i] += (pc[t][i] >= tprev) ? vprev : 0;
+            // (HI: a third of the products, each with three times the vector ops)
+            constexpr int NPROD = (HI ? 1 : 3) * KS * TI, NV = HI ? 9 : 3;
 #pragma unroll
-            for (int g = 0; g < 3 * KS * TI; ++g) {
-                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one product
-                __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);  // three vector ops
+            for (int g = 0; g < NPROD; ++g) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one product
+                __builtin_amdgcn_sched_group_barrier(0x002, NV, 0);  // vector ops
             }
 #pragma unroll
             for (int t = 0; t < TI; ++t) pc[t] = nc[t];
@@ -652,8 +661,13 @@ void launch_bound(const BoundArgs &a, hipStream_t st) {
         constexpr int KS = decltype(ks)::value, BI = bound_items(KS);
         const unsigned g = (unsigned)((a.m + BI - 1) / BI * a.nsplit);
         RMIPS_PROF(st, "k_bound");
-        if constexpr (KS >= 3) k_bound_lds<KS><<<g, 64 * BLW, bound_lds_bytes(KS), st>>>(a);
-        else k_bound<KS><<<g, 64 * BW, 0, st>>>(a);
+        if constexpr (KS >= 3) {
+            if (a.hi_only) k_bound_lds<KS, true><<<g, 64 * BLW, bound_lds_bytes(KS), st>>>(a);
+            else k_bound_lds<KS, false><<<g, 64 * BLW, bound_lds_bytes(KS), st>>>(a);
+        } else {
+            if (a.hi_only) k_bound<KS, true><<<g, 64 * BW, 0, st>>>(a);
+            else k_bound<KS, false><<<g, 64 * BW, 0, st>>>(a);
+        }
     };
     switch (a.ka / 16) {
     case 1: go(std::integral_constant<int, 1>{}); break;

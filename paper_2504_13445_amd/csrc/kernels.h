@@ -188,6 +188,8 @@ struct BoundArgs {
     int ka;                            // augmented row length (16, 32, 48 or 64)
     const uint4 *Pb; int64_t m, mpad;  // augmented item rows (norm order), BF16 hi | lo
     const uint4 *Ub;                   // augmented user rows (rho order), BF16 hi | lo
+    int hi_only;                       // 1: products of the hi parts alone (the rows'
+                                       // relative slack must cover the lo parts)
     const float *tau_lo;               // per sorted user
     float abs_slack;                   // absolute slack of the bound
     const int32_t *cs;                 // CS prefix per item (non-increasing)

@@ -629,6 +629,15 @@ void run_prefix(const ThreshLayout &T, PrefixLayout &X, int64_t n, int64_t m, fl
 // each such term is below 2^-126 * 2^60 * 1.42 in magnitude.
 constexpr float BOUND_SLACK = 0x1p-12f;
 constexpr float BOUND_ABS_SLACK = 0x1p-60f;
+// With the hi parts alone (d > d', where the bound has a Cauchy-Schwarz
+// tail): each product hi(a) hi(b) is within (2 * 2^-9 + 2^-18) |a| |b| of
+// a b (round to nearest BF16: |x - hi(x)| <= 2^-9 |x|), at most 1.003 *
+// 2^-8 * 1.415 ||p|| ||u|| over the row (the norm column is not multiplied
+// by itself), plus the FP32 sums of <= 64 exact BF16 products (gamma_64,
+// 2^-18 of the same), while the slack column gives at least s (1 - 2^-9)^2
+// ||p|| ||u||: s = 2^-7 covers 1.43 * 2^-8 with room.
+constexpr float BOUND_SLACK_HI = 0x1p-7f;
+bool bound_hi_only(int d) { return d > DPRIME_MAX; }
 
 // Stage (c), second part: the Eq. (3)/(6) bound count of every item (norm
 // order) into `uscore`, over the users of its prefix (users' augmented rows
@@ -637,9 +646,12 @@ void run_bound(const float *U, const PrefixLayout &X, const BoundLayout &B, cons
                int64_t n, int64_t m, int64_t mpad, int d, unsigned long long *pairs,
                hipEvent_t e0, hipEvent_t e1, int32_t *uscore, hipStream_t st) {
     const int dp = dprime(d), ka = aug_len(d);
-    launch_rotate_aug(U, X.uperm, n, n, d, Wd, dp, ka, BOUND_SLACK, B.Ua, st);
+    const bool hi = bound_hi_only(d);
+    launch_rotate_aug(U, X.uperm, n, n, d, Wd, dp, ka, hi ? BOUND_SLACK_HI : BOUND_SLACK, B.Ua,
+                      st);
     BoundArgs ba{};
     ba.ka = ka;
+    ba.hi_only = hi ? 1 : 0;
     ba.Pb = B.Pa; ba.m = m; ba.mpad = mpad; ba.Ub = B.Ua; ba.tau_lo = X.us.tau_lo;
     ba.abs_slack = BOUND_ABS_SLACK; ba.cs = X.cs;
     ba.nsplit = B.nsplitB; ba.partial = B.partialB; ba.pairs = pairs;
