@@ -76,10 +76,11 @@ constexpr int SCR_NW = 12;  // at most
 // 12 waves while a half row fits in 8 chunks, or 14 in BF16 (three waves
 // per SIMD, 168 registers each: the FP32 rows take more matrix steps per
 // chunk, so a third wave gains nothing there and the longer rows spill), 8 up
-// to 16 chunks (two per SIMD, 256 registers each), 4 for longer rows, whose
-// waves need more registers
+// to 28 chunks (two per SIMD, 256 registers each: a wave's band test then
+// runs while the other wave of its SIMD multiplies), 4 for longer rows,
+// whose waves need more registers
 __host__ __device__ constexpr int screen_waves(int prec, int nch) {
-    return (nch <= 8 || (prec == PREC_BF16 && nch <= 14)) ? 12 : nch <= 16 ? 8 : 4;
+    return (nch <= 8 || (prec == PREC_BF16 && nch <= 14)) ? 12 : nch <= 28 ? 8 : 4;
 }
 // the bounds-only pass (phase 1 alone, fewer registers): 8 waves, two
 // workgroups per CU (128 registers) while a half row fits in 8 chunks
