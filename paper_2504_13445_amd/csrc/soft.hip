@@ -155,14 +155,32 @@ void k_soft(const float *__restrict__ U, int64_t n, const float *__restrict__ ta
 #pragma unroll
             for (int b = 0; b < QB; ++b) z[b] = f32x4{0.f, 0.f, 0.f, 0.f};
             const float *a = Uc + (ub * 16 + r16) * ld + k4;
+            // the reads of the next 8 steps issued before this group's
+            // products, none behind a branch: reads for steps past kq land at
+            // most 4 QN - 4 kq + 27 < 32 floats past a row end (the next row,
+            // the other buffer or the zero guard, all inside the LDS block)
+            // and are not multiplied
+            float av[2][8];
 #pragma unroll
-            for (int j = 0; j < QN; ++j) {
-                if (j < kq) {
-                    const float av = a[4 * j];
+            for (int j = 0; j < 8; ++j) av[0][j] = a[4 * j];
 #pragma unroll
-                    for (int b = 0; b < QB; ++b)
-                        z[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, qa[b][j], z[b], 0, 0, 0);
+            for (int j0 = 0; j0 < QN; j0 += 8) {
+                const int cg = (j0 / 8) & 1;
+                if (j0 + 8 < QN) {
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) av[cg ^ 1][j] = a[4 * (j0 + 8 + j)];
                 }
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    if (j0 + j < kq) {
+#pragma unroll
+                        for (int b = 0; b < QB; ++b)
+                            z[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[cg][j], qa[b][j0 + j],
+                                                                       z[b], 0, 0, 0);
+                    }
+                }
+                // (no read of a later group moves above this group)
+                __builtin_amdgcn_sched_barrier(0);
             }
             // register i: user ub * 16 + 4 k4 + i; a user past the slice
             // contributes nothing (explicit validity)
@@ -181,18 +199,29 @@ void k_soft(const float *__restrict__ U, int64_t n, const float *__restrict__ ta
                 }
             }
             if constexpr (WG) {
+                // (the next dim block's reads before this block's products, as
+                // above; blocks from ncb on read at most 16 NCB - ld < 32
+                // floats past a row end and are not multiplied)
+                const float *ur = Uc + (ub * 16 + 4 * k4) * ld + r16;
+                float uv[2][4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) uv[0][i] = ur[i * ld];
 #pragma unroll
                 for (int cb = 0; cb < NCB; ++cb) {
+                    if (cb + 1 < NCB) {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) uv[(cb + 1) & 1][i] = ur[i * ld + (cb + 1) * 16];
+                    }
                     if (cb < ncb) {
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
-                            const float uv = Uc[(ub * 16 + 4 * k4 + i) * ld + cb * 16 + r16];
 #pragma unroll
                             for (int b = 0; b < QB; ++b)
-                                g[b][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv[b][i], uv,
-                                                                              g[b][cb], 0, 0, 0);
+                                g[b][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                    wv[b][i], uv[cb & 1][i], g[b][cb], 0, 0, 0);
                         }
                     }
+                    __builtin_amdgcn_sched_barrier(0);
                 }
             }
         }
@@ -325,9 +354,14 @@ void launch_soft(const float *U, int64_t n, const float *tau, const float *Q, in
     // two query blocks per wave up to d = 128, one above (registers)
     const int qb = sd.kq <= 32 ? 2 : 1;
     const int64_t tiles = (nq + 64 * qb - 1) / (64 * qb);
-    // slices: about three workgroups per compute unit in all, at least one
-    // chunk of users each
-    int64_t ns = (768 + tiles - 1) / tiles;
+    // slices: one resident round of workgroups (each has one wave per SIMD,
+    // so as many per compute unit as the registers give waves per SIMD, at
+    // most as many as the LDS holds), at least one chunk of users each; a
+    // partial second round would leave compute units idle at the end
+    const int qn = 8 * ((sd.kq + 7) / 8);
+    const int resident =
+        std::max(1, std::min(soft_wpe(qn, qb), (int)((size_t)(160 * 1024) / soft_lds(d))));
+    int64_t ns = (256 * (int64_t)resident + tiles - 1) / tiles;
     ns = std::min<int64_t>(ns, std::min<int64_t>(max_splits, (n + SUC - 1) / SUC));
     const int nsplit = (int)std::max<int64_t>(1, ns);
     dim3 g((unsigned)tiles, (unsigned)nsplit);
