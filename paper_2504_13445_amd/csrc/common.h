@@ -227,6 +227,23 @@ template <int NCH> struct MMR<PREC_BF16, NCH> {
             c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(a[c]), y1, c1, 0, 0, 0);
         }
     }
+    // c[h][j] += A_j B_h^T for two register operands B_0, B_1: each chunk
+    // read from LDS feeds two products
+    static __device__ __forceinline__ void rows4(f32x16 (&c)[2][2], const uint8_t *A0,
+                                                 const uint8_t *A1, const uint4 (&b0)[NCH],
+                                                 const uint4 (&b1)[NCH], int ls, int D,
+                                                 int lane) {
+        const int off = (lane & 31) * ls + (lane >> 5) * (D / 2) * 2;
+#pragma unroll
+        for (int q = 0; q < NCH; ++q) {
+            const bf16x8 x0 = *reinterpret_cast<const bf16x8 *>(A0 + off + 16 * q);
+            const bf16x8 x1 = *reinterpret_cast<const bf16x8 *>(A1 + off + 16 * q);
+            c[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x0, as_bf(b0[q]), c[0][0], 0, 0, 0);
+            c[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x1, as_bf(b0[q]), c[0][1], 0, 0, 0);
+            c[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x0, as_bf(b1[q]), c[1][0], 0, 0, 0);
+            c[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x1, as_bf(b1[q]), c[1][1], 0, 0, 0);
+        }
+    }
 };
 
 // FP8 e4m3, FP6 e2m3 and FP4 e2m1: one f8f6f4 product per pair of 16-byte
@@ -266,6 +283,28 @@ template <int FMT, int NCH> struct MMRx {
                                                                  0x7f7f7f7f, 0, 0x7f7f7f7f);
             c1 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x, y1, c1, FMT, FMT, 0,
                                                                  0x7f7f7f7f, 0, 0x7f7f7f7f);
+        }
+    }
+    // as MMR<PREC_BF16>::rows4
+    static __device__ __forceinline__ void rows4(f32x16 (&c)[2][2], const uint8_t *A0,
+                                                 const uint8_t *A1, const uint4 (&b0)[NCH],
+                                                 const uint4 (&b1)[NCH], int ls, int D,
+                                                 int lane) {
+        const int off = (lane & 31) * ls + (lane >> 5) * (D / 2);
+#pragma unroll
+        for (int q = 0; q + 1 < NCH; q += 2) {
+            const i32x8 x0 = ld_fp8x32(A0 + off + 16 * q);
+            const i32x8 x1 = ld_fp8x32(A1 + off + 16 * q);
+            const i32x8 y0 = pair(b0[q], b0[q + 1]);
+            const i32x8 y1 = pair(b1[q], b1[q + 1]);
+            c[0][0] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x0, y0, c[0][0], FMT, FMT, 0,
+                                                                      0x7f7f7f7f, 0, 0x7f7f7f7f);
+            c[0][1] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x1, y0, c[0][1], FMT, FMT, 0,
+                                                                      0x7f7f7f7f, 0, 0x7f7f7f7f);
+            c[1][0] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x0, y1, c[1][0], FMT, FMT, 0,
+                                                                      0x7f7f7f7f, 0, 0x7f7f7f7f);
+            c[1][1] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x1, y1, c[1][1], FMT, FMT, 0,
+                                                                      0x7f7f7f7f, 0, 0x7f7f7f7f);
         }
     }
 };

@@ -362,6 +362,164 @@ void k_thresh_screen(ThreshArgs a) {
         atomicAdd(a.pairs + (blockIdx.x & (CSTAT_SLOTS - 1)), pacc);
 }
 
+// The passes with a user list (phase 2 alone) for BF16 and the f8f6f4
+// formats, with two blocks of 32 users per wave: each item chunk read from
+// LDS feeds four products (two item blocks x two user blocks), half the LDS
+// reads per product of k_thresh_screen.  8 waves of 64 users (two per SIMD:
+// both users' half rows stay in registers).  The band test, the candidate
+// lists and the exit are k_thresh_screen's, per user block.
+constexpr int SCR2_NW = 8;
+__host__ __device__ constexpr bool screen_u2(int prec, int nch) {
+    return prec != PREC_FP32 && nch <= 16;
+}
+template <int PREC, int NCH>
+__global__ __launch_bounds__(64 * SCR2_NW) __attribute__((amdgpu_waves_per_eu(2)))
+void k_thresh_screen_u2(ThreshArgs a) {
+    constexpr int NW = SCR2_NW, TU = 64 * NW;
+    extern __shared__ __align__(16) uint8_t smem8[];
+    const int D = a.D, ls = lds_row_bytes(PREC, D), rowb = D * elem_bytes(PREC);
+    const int nch = rowb / 32;
+    const int bstride = TILE_ITEMS * ls + LDS_GUARD;
+    uint8_t *Pbase = smem8;
+    float *Nbase = reinterpret_cast<float *>(Pbase + 2 * bstride);
+    float *red = reinterpret_cast<float *>(Nbase + 2 * NSTRIDE);
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int split = blockIdx.y;
+    const int w16 = rowb / 16;
+    const int64_t nlist = (int64_t)*a.ulist_cnt;
+    const int64_t nblk = (nlist + TU - 1) / TU;
+    const float rmax = __uint_as_float(*a.rmax_bits);
+    auto tile_of = [&](int it) { return split + it * a.nsplit; };
+
+    const uint32_t magic = slot_magic(w16);
+    unsigned long long pacc = 0;  // statistics: pairs screened
+    if (tid < 2 * LDS_GUARD / 16) {
+        const int g = tid / (LDS_GUARD / 16), e = tid % (LDS_GUARD / 16);
+        reinterpret_cast<uint4 *>(Pbase + g * bstride + TILE_ITEMS * ls)[e] =
+            make_uint4(0, 0, 0, 0);
+    }
+    const int half = a.cap / 2, hw = lane >> 5;
+
+    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        __syncthreads();  // the previous block is done with the tile buffers
+        const int64_t nub = (nlist - blk * TU < TU) ? (nlist - blk * TU) : TU;
+        int64_t ntile_p2 = 0;
+        // user block h of this wave: users w * 64 + 32 h + (lane & 31)
+        bool uvalid[2];
+        int64_t ug[2];
+        uint4 ub0[NCH], ub1[NCH];
+        float nu[2], nhu[2], ru[2], su[2], su_inv[2], L0[2];
+        float2 *mycand[2];
+        int32_t *mycid[2];
+        int myc[2] = {0, 0};
+        float rr = INFINITY;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int64_t pos = blk * TU + w * 64 + 32 * h + (lane & 31);
+            uvalid[h] = pos < nlist;
+            ug[h] = uvalid[h] ? (int64_t)a.ulist[pos] : 0;
+            nu[h] = uvalid[h] ? a.Nu[ug[h]] : 0.0f;
+            nhu[h] = uvalid[h] ? a.Nhu[ug[h]] : 0.0f;
+            ru[h] = uvalid[h] ? a.Ru[ug[h]] : 0.0f;
+            su[h] = uvalid[h] ? a.su[ug[h]] : 1.0f;
+            su_inv[h] = pow2_rcp(su[h]);
+            L0[h] = uvalid[h] ? a.Luse[ug[h]] : INFINITY;
+            mycand[h] = a.cand + (ug[h] * a.nsplit + split) * a.cap + hw * half;
+            mycid[h] = a.cand_id + (ug[h] * a.nsplit + split) * a.cap + hw * half;
+            // exit ratio as in k_thresh_screen
+            if (uvalid[h]) {
+                const float K = nu[h] * (1.0f + a.g64 + 2.0f * a.c2) + 2.0f * ru[h] +
+                                2.0f * nhu[h] * (rmax + a.c_err * (1.0f + rmax));
+                const float r = (L0[h] > 2.0f * a.e_abs && K > 0.0f)
+                                    ? (L0[h] - 2.0f * a.e_abs) / K * (1.0f - 0x1p-20f)
+                                    : 0.0f;
+                rr = fminf(rr, r);
+            }
+        }
+        load_half_row<NCH>(ub0, reinterpret_cast<const uint8_t *>(a.Uq), ug[0], uvalid[0], rowb,
+                           nch, lane);
+        load_half_row<NCH>(ub1, reinterpret_cast<const uint8_t *>(a.Uq), ug[1], uvalid[1], rowb,
+                           nch, lane);
+        rr = wave_min(rr);
+        if (lane == 0) red[w] = rr;
+        auto ebound = [&](int h, float n_p, float nh_p, float r_p) {
+            return fmaf(ru[h], n_p, fmaf(nhu[h], r_p,
+                                         fmaf(a.c_err * nhu[h], nh_p, fmaf(a.c2 * nu[h], n_p, a.e_abs))));
+        };
+        tile_copy<NW>(a, tile_of(0), rowb, w16, magic, ls, Pbase, Nbase, 0, w, lane);
+        dma_wait();
+        __syncthreads();
+        float rwg = red[0];
+#pragma unroll
+        for (int q = 1; q < NW; ++q) rwg = fminf(rwg, red[q]);
+        int buf = 0;
+        for (int it = 0;; ++it) {
+            const int t = tile_of(it);
+            if (t >= a.ntiles) break;
+            const float *Nsh = Nbase + buf * NSTRIDE;
+            if (Nsh[0] < rwg) break;  // Cauchy-Schwarz exit (N is sorted: Nsh[0] is the largest)
+            ++ntile_p2;
+            const int tn = tile_of(it + 1);
+            const bool pre = tn < a.ntiles;
+            if (pre)
+                tile_copy<NW>(a, tn, rowb, w16, magic, ls, Pbase, Nbase, buf ^ 1, w, lane);
+            const uint8_t *Psh = Pbase + buf * bstride;
+            const int64_t rb = (int64_t)t * TILE_ITEMS;
+            const float sp_t = Nsh[3 * TILE_ITEMS + 2];
+            f32x16 acc[2][2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) acc[h][0] = acc[h][1] = f32x16{0};
+            MMR<PREC, NCH>::rows4(acc, Psh, Psh + 32 * ls, ub0, ub1, ls, D, lane);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const float e_t = ebound(h, Nsh[0], Nsh[3 * TILE_ITEMS], Nsh[3 * TILE_ITEMS + 1]);
+                const float sc = su[h] * sp_t;
+                const float thr = (L0[h] - e_t) * (su_inv[h] * pow2_rcp(sp_t));
+                float vmax = acc[h][0][0];
+#pragma unroll
+                for (int i = 1; i < 16; ++i) vmax = fmaxf(vmax, acc[h][0][i]);
+#pragma unroll
+                for (int i = 0; i < 16; ++i) vmax = fmaxf(vmax, acc[h][1][i]);
+                if (__ballot(vmax >= thr && uvalid[h]) != 0ull) {
+                    uint32_t pend = 0u;
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        pend |= (acc[h][0][i] >= thr) ? (1u << i) : 0u;
+                        pend |= (acc[h][1][i] >= thr) ? (1u << (16 + i)) : 0u;
+                    }
+                    if (!uvalid[h]) pend = 0u;
+                    while (pend != 0u) {
+                        const int i = __builtin_ctz(pend);
+                        pend &= pend - 1u;
+                        const int r = mfma32_row(i & 15, lane) + (i >> 4) * 32;
+                        if (rb + r >= a.m) continue;  // padding rows of the last tile
+                        const float v = pick32(acc[h][0], acc[h][1], i) * sc;
+                        const float eb =
+                            ebound(h, Nsh[r], Nsh[TILE_ITEMS + r], Nsh[2 * TILE_ITEMS + r]);
+                        if (v + eb >= L0[h]) {
+                            if (myc[h] < half) {
+                                mycand[h][myc[h]] = make_float2(v, eb);
+                                mycid[h][myc[h]] = __float_as_int(Nsh[4 * TILE_ITEMS + r]);
+                            }
+                            ++myc[h];
+                        }
+                    }
+                }
+            }
+            if (pre) dma_wait();
+            __syncthreads();
+            buf ^= 1;
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            if (uvalid[h]) a.cand_cnt[(ug[h] * a.nsplit + split) * 2 + hw] = myc[h];
+        pacc += (unsigned long long)(ntile_p2 * TILE_ITEMS * nub);
+    }
+    if (a.pairs && tid == 0 && pacc)
+        atomicAdd(a.pairs + (blockIdx.x & (CSTAT_SLOTS - 1)), pacc);
+}
+
 // ------------------------------------------------------------------ final
 // Wave-level bitonic sort of (value, id) pairs in LDS in the order (value
 // desc, id asc); the slots from n up to the next power of two are filled
@@ -908,6 +1066,12 @@ void launch_screen(const ThreshArgs &a, int nch, dim3 g, size_t lds, hipStream_t
     RMIPS_PROF(st, name);
     with_nch<PREC>(nch, [&](auto n) {
         constexpr int NCH = decltype(n)::value;
+        if constexpr (screen_u2(PREC, NCH)) {
+            if (a.ulist) {
+                k_thresh_screen_u2<PREC, NCH><<<g, 64 * SCR2_NW, lds, st>>>(a);
+                return;
+            }
+        }
         if (a.ulist) k_thresh_screen<PREC, NCH, true><<<g, 64 * screen_nw<true>(PREC, NCH), lds, st>>>(a);
         else k_thresh_screen<PREC, NCH, false><<<g, 64 * screen_nw<false>(PREC, NCH), lds, st>>>(a);
     });
@@ -937,7 +1101,8 @@ __global__ void k_exit_keys(ThreshArgs a, uint32_t *__restrict__ key, int32_t *_
 
 void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
     const int nch = a0.D * elem_bytes(a0.prec) / 32;
-    const int tu = 32 * screen_waves(a0.prec, nch);
+    // users per workgroup of the passes with a user list
+    const int tu = screen_u2(a0.prec, nch) ? 64 * SCR2_NW : 32 * screen_waves(a0.prec, nch);
     const size_t lds = thresh_screen_lds(a0.prec, a0.D);
     const int64_t ublocks = (a0.n + tu - 1) / tu;
     const int capU = a0.cap * a0.nsplit;
