@@ -164,12 +164,13 @@ def committed_traffic(kernel_symbol, cfg_name, prec, listed):
 
 def cpu_baseline(cfg, U, P, k, target_s):
     """The CPU FP64 oracle (plain C, OpenMP over all host cores) on a
-    bounded sample of the seeded 1% user subsample of the same workload."""
+    bounded sample (about target_s seconds) of a seeded 3% user subsample of
+    the same workload."""
     import numpy as np
     import oracle
     import synth
     n, m = U.shape[0], P.shape[0]
-    sub = synth.subsample_users(cfg, 0.01) if n >= 100_000 else np.arange(n)
+    sub = synth.subsample_users(cfg, 0.03) if n >= 100_000 else np.arange(n)
     n0 = int(min(sub.size, 500))
     t = time.perf_counter()
     oracle.kmips_c(np.ascontiguousarray(U[sub[:n0]]), P, k, with_topk=True)
