@@ -151,9 +151,14 @@ def committed_traffic(kernel_symbol, cfg_name, prec, listed):
         return None
     if t.get("src_sha256") != _sources_hash():
         return None
-    cands = [x for x in t["kernels"] if x == kernel_symbol or x.startswith(kernel_symbol + "<")]
+    syms = [kernel_symbol]
+    if kernel_symbol == "k_thresh_screen" and listed:
+        syms.append("k_thresh_screen_u2")  # the listed passes with two user blocks per wave
+    cands = [x for x in t["kernels"] if any(x == s or x.startswith(s + "<") for s in syms)]
     if listed is not None:
-        cands = [x for x in cands if x.endswith("true>") == listed] or cands
+        def is_listed(x):
+            return x.startswith("k_thresh_screen_u2<") or x.endswith("true>")
+        cands = [x for x in cands if is_listed(x) == listed] or cands
     if not cands:
         return None
     k = max((t["kernels"][x] for x in cands), key=lambda v: v.get("fetch_bytes_max") or 0)
