@@ -351,6 +351,47 @@ void launch_count(const CountArgs &a, hipStream_t st) {
     else launch_count_p<PREC_FP4>(a, lds, st);
 }
 
+// The slots of one batch of the visit in item-row order: the rows index the
+// norm-ordered item arrays, so a counting wave's 32 items then have close
+// norms, and the error band it takes from their largest N, Nh and R is close
+// to each item's own (fewer pairs to recheck in FP64).  Rows and caller ids
+// move together, so each count still goes with its item.  One workgroup,
+// a bitonic sort of at most BATCH_ORDER_MAX (row, id) pairs in LDS.
+constexpr int BATCH_ORDER_MAX = 4096;
+__global__ __launch_bounds__(1024) void k_batch_order(int32_t *__restrict__ rows,
+                                                      int32_t *__restrict__ cid, int nb) {
+    __shared__ uint64_t kv[BATCH_ORDER_MAX];
+    int P2 = 1;
+    while (P2 < nb) P2 <<= 1;
+    for (int i = threadIdx.x; i < P2; i += blockDim.x)
+        kv[i] = i < nb ? ((uint64_t)(uint32_t)rows[i] << 32) | (uint32_t)cid[i] : ~0ull;
+    __syncthreads();
+    for (int kk = 2; kk <= P2; kk <<= 1)
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < P2; i += blockDim.x) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const uint64_t x = kv[i], y = kv[l];
+                    if ((x > y) == ((i & kk) == 0)) {
+                        kv[i] = y;
+                        kv[l] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+        rows[i] = (int32_t)(kv[i] >> 32);
+        cid[i] = (int32_t)(uint32_t)kv[i];
+    }
+}
+
+void launch_batch_order(int32_t *rows, int32_t *cid, int64_t nb, hipStream_t st) {
+    if (nb < 2 || nb > BATCH_ORDER_MAX) return;  // (larger batches keep the visit order)
+    RMIPS_PROF(st, "k_batch_order");
+    k_batch_order<<<1, 1024, 0, st>>>(rows, cid, (int)nb);
+}
+
 // Eq. (3)/(6) bound count over the users of the item block's Cauchy-Schwarz
 // prefix.  Rows are augmented so that one ka-term product gives the bound
 // plus its rounding slack: [W p, tail(p), ||p||] . [W u, tail(u), s ||u||],

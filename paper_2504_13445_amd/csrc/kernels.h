@@ -180,6 +180,9 @@ struct CountArgs {
     int nsplit; int32_t *partial; int64_t *rechecks;
 };
 void launch_count(const CountArgs &a, hipStream_t st);
+// a batch's slots (rows of the norm-ordered item arrays and their caller ids)
+// in row order, nb <= 4096
+void launch_batch_order(int32_t *rows, int32_t *cid, int64_t nb, hipStream_t st);
 // *out = max(x[0], ..., x[n-1]) (0 when n = 0), one workgroup
 void launch_max_i32(const int32_t *x, int64_t n, int32_t *out, hipStream_t st);
 size_t count_lds(int prec, int D);

@@ -735,6 +735,9 @@ rmips_status run_count_topn(rmips_ctx *ctx, const float *U, const float *P,
         } else {
             for (int64_t r = r0; r < r1; ++r) ulen = std::max<int64_t>(ulen, h_cs[r]);
         }
+        // the batch's slots in norm order (the host's copies of the bounds
+        // and prefixes stay in visit order; the batch is a set)
+        launch_batch_order(C.visit + r0, C.vis_cid + r0, nb, st);
         CountArgs a{};
         a.prec = T.prec;
         a.Pq = T.Pq; a.Np = T.Np; a.Nhp = T.Nhp; a.Rp = T.Rp; a.sp = T.sp;
