@@ -395,13 +395,11 @@ void launch_batch_order(int32_t *rows, int32_t *cid, int64_t nb, hipStream_t st)
 // Eq. (3)/(6) bound count over the users of the item block's Cauchy-Schwarz
 // prefix.  Rows are augmented so that one ka-term product gives the bound
 // plus its rounding slack: [W p, tail(p), ||p||] . [W u, tail(u), s ||u||],
-// each row stored as BF16 hi and lo parts (x = hi + lo + e, |e| <= 2^-16 |x|)
-// and multiplied as hi.hi + hi.lo + lo.hi: three BF16 matrix-core steps per
-// 16 terms, the dropped terms being covered by s.  HI: hi.hi alone, one step
-// per 16 terms, for rows whose s also covers the lo parts (used where the
-// bound has a Cauchy-Schwarz tail, which the larger slack barely loosens).
+// each row stored in BF16 (round to nearest) and multiplied in one BF16
+// matrix-core step per 16 terms, the rounding of the rows and of the sums
+// being covered by s.
 //
-// A workgroup of BW waves holds 32 * TI items (TI 32-row tiles, hi and lo)
+// A workgroup of BW waves holds 32 * TI items (TI 32-row tiles)
 // in every wave's registers; each wave reads blocks of 32 users straight from
 // memory into registers (one block ahead), with no LDS and no barrier until
 // the final sum of the waves' counts.  KS = ka / 16 steps of K per product.
@@ -415,9 +413,9 @@ __device__ __forceinline__ float float_pred(float t) {
     return __uint_as_float(t > 0.0f ? b - 1u : (t < 0.0f ? b + 1u : 0x80000001u));
 }
 
-template <int KS, bool HI>
+template <int KS>
 __global__ __launch_bounds__(64 * BW) void k_bound(BoundArgs a) {
-    constexpr int TI = bound_tiles(KS), BI = 32 * TI, RW = 4 * KS;  // RW: 16-byte words per row
+    constexpr int TI = bound_tiles(KS), BI = 32 * TI, RW = 2 * KS;  // RW: 16-byte words per row
     __shared__ int wsum[BW][BI];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int h = lane >> 5, col = lane & 31;
@@ -425,20 +423,16 @@ __global__ __launch_bounds__(64 * BW) void k_bound(BoundArgs a) {
     // next block): the blocks of the longest prefixes start first
     const int64_t ib = (int64_t)(blockIdx.x / a.nsplit) * BI;
     const int split = (int)(blockIdx.x % a.nsplit);
-    // the items' hi and lo parts: row col of each tile, K half h of each step
-    bf16x8 ah[TI][KS], al[TI][KS];
+    // the items' rows: row col of each tile, K half h of each step
+    bf16x8 ah[TI][KS];
 #pragma unroll
     for (int t = 0; t < TI; ++t) {
         const int64_t r = ib + 32 * t + col;
 #pragma unroll
         for (int q = 0; q < KS; ++q) {
-            uint4 x = make_uint4(0, 0, 0, 0), y = x;
-            if (r < a.mpad) {
-                x = a.Pb[r * RW + 2 * q + h];
-                if constexpr (!HI) y = a.Pb[r * RW + 2 * KS + 2 * q + h];
-            }
+            uint4 x = make_uint4(0, 0, 0, 0);
+            if (r < a.mpad) x = a.Pb[r * RW + 2 * q + h];
             ah[t][q] = __builtin_bit_cast(bf16x8, x);
-            al[t][q] = __builtin_bit_cast(bf16x8, y);
         }
     }
     int cnt[TI][16];
@@ -450,46 +444,37 @@ __global__ __launch_bounds__(64 * BW) void k_bound(BoundArgs a) {
     const int64_t ulen = a.cs[ib];  // largest prefix of the block (norm order)
     const int64_t nblk = (ulen + 31) / 32;
     const int64_t step = (int64_t)a.nsplit * BW;
-    // one user column per lane: its hi and lo parts, its threshold lowered
+    // one user column per lane: its row, its threshold lowered
     // by the absolute slack, and whether the column is a user of the prefix
     // (vm = 1) or past it (vm = 0: nothing it holds is counted); clamped
     // index, so every load is in bounds
-    auto fetch = [&](int64_t j, uint4 (&bh)[KS], uint4 (&bl)[KS], float &tl, int &vm) {
+    auto fetch = [&](int64_t j, uint4 (&bh)[KS], float &tl, int &vm) {
         const int64_t us = j * 32 + col;
         const bool ok = j < nblk && us < ulen;
         const int64_t uc = ok ? us : 0;
 #pragma unroll
-        for (int q = 0; q < KS; ++q) {
-            bh[q] = a.Ub[uc * RW + 2 * q + h];
-            if constexpr (!HI) bl[q] = a.Ub[uc * RW + 2 * KS + 2 * q + h];
-        }
+        for (int q = 0; q < KS; ++q) bh[q] = a.Ub[uc * RW + 2 * q + h];
         tl = float_pred(a.tau_lo[uc] - a.abs_slack);
         vm = ok ? 1 : 0;
     };
     int64_t j = (int64_t)split * BW + w;
-    uint4 bh[KS], bl[KS];
+    uint4 bh[KS];
     float tl;
     int vm;
-    fetch(j, bh, bl, tl, vm);
+    fetch(j, bh, tl, vm);
     int64_t npairs = 0;  // statistics: users of this wave's blocks
     for (; j < nblk; j += step) {
-        uint4 nh[KS], nl[KS];
+        uint4 nh[KS];
         float nt;
         int nvm;
-        fetch(j + step, nh, nl, nt, nvm);
+        fetch(j + step, nh, nt, nvm);
         // the products of tile t + 1 run while tile t's counts are taken
         auto prod = [&](int t, f32x16 &acc) {
             acc = f32x16{0};
 #pragma unroll
-            for (int q = 0; q < KS; ++q) {
-                const bf16x8 yh = __builtin_bit_cast(bf16x8, bh[q]);
-                const bf16x8 yl = __builtin_bit_cast(bf16x8, bl[q]);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t][q], yh, acc, 0, 0, 0);
-                if constexpr (!HI) {
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t][q], yl, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[t][q], yh, acc, 0, 0, 0);
-                }
-            }
+            for (int q = 0; q < KS; ++q)
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                    ah[t][q], __builtin_bit_cast(bf16x8, bh[q]), acc, 0, 0, 0);
         };
         auto tally = [&](int t, const f32x16 &acc) {
 #pragma unroll
@@ -510,10 +495,7 @@ __global__ __launch_bounds__(64 * BW) void k_bound(BoundArgs a) {
         }
         npairs += (ulen - j * 32 < 32) ? (ulen - j * 32) : 32;
 #pragma unroll
-        for (int q = 0; q < KS; ++q) {
-            bh[q] = nh[q];
-            bl[q] = nl[q];
-        }
+        for (int q = 0; q < KS; ++q) bh[q] = nh[q];
         tl = nt;
         vm = nvm;
     }
@@ -545,10 +527,10 @@ __global__ __launch_bounds__(64 * BW) void k_bound(BoundArgs a) {
 constexpr int BLW = 8;       // waves per workgroup
 constexpr int BL_USERS = 64;  // users per stage
 
-template <int KS, bool HI>
+template <int KS>
 __global__ __launch_bounds__(64 * BLW) __attribute__((amdgpu_waves_per_eu(2)))
 void k_bound_lds(BoundArgs a) {
-    constexpr int TI = 2, BI = 32 * TI * BLW, RW = 4 * KS, LSL = RW + 1;  // LSL: LDS row slots
+    constexpr int TI = 2, BI = 32 * TI * BLW, RW = 2 * KS, LSL = RW + 1;  // LSL: LDS row slots
     // two stage buffers of user rows, then their thresholds (dynamic LDS,
     // bound_lds_bytes(KS))
     extern __shared__ __align__(16) uint8_t smem_b[];
@@ -560,20 +542,16 @@ void k_bound_lds(BoundArgs a) {
     // next block): the blocks of the longest prefixes start first
     const int64_t ib = (int64_t)(blockIdx.x / a.nsplit) * BI;
     const int split = (int)(blockIdx.x % a.nsplit);
-    // this wave's items: rows ib + 64 w + 32 t + col, hi and lo, K half h
-    bf16x8 ah[TI][KS], al[TI][KS];
+    // this wave's items: rows ib + 64 w + 32 t + col, K half h
+    bf16x8 ah[TI][KS];
 #pragma unroll
     for (int t = 0; t < TI; ++t) {
         const int64_t r = ib + 64 * w + 32 * t + col;
 #pragma unroll
         for (int q = 0; q < KS; ++q) {
-            uint4 x = make_uint4(0, 0, 0, 0), y = x;
-            if (r < a.mpad) {
-                x = a.Pb[r * RW + 2 * q + h];
-                if constexpr (!HI) y = a.Pb[r * RW + 2 * KS + 2 * q + h];
-            }
+            uint4 x = make_uint4(0, 0, 0, 0);
+            if (r < a.mpad) x = a.Pb[r * RW + 2 * q + h];
             ah[t][q] = __builtin_bit_cast(bf16x8, x);
-            al[t][q] = __builtin_bit_cast(bf16x8, y);
         }
     }
     int cnt[TI][16];
@@ -640,22 +618,14 @@ void k_bound_lds(BoundArgs a) {
             for (int q = 0; q < KS; ++q) {
                 const bf16x8 yh = __builtin_bit_cast(bf16x8, U[ul * LSL + 2 * q + h]);
 #pragma unroll
-                for (int t = 0; t < TI; ++t) {
+                for (int t = 0; t < TI; ++t)
                     nc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t][q], yh, nc[t], 0, 0, 0);
-                    if constexpr (!HI) {
-                        const bf16x8 yl =
-                            __builtin_bit_cast(bf16x8, U[ul * LSL + 2 * KS + 2 * q + h]);
-                        nc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t][q], yl, nc[t], 0, 0, 0);
-                        nc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[t][q], yh, nc[t], 0, 0, 0);
-                    }
-                }
             }
 #pragma unroll
             for (int t = 0; t < TI; ++t)
 #pragma unroll
                 for (int i = 0; i < 16; ++i) cnt[t][i] += (pc[t][i] >= tprev) ? vprev : 0;
-            // (HI: a third of the products, each with three times the vector ops)
-            constexpr int NPROD = (HI ? 1 : 3) * KS * TI, NV = HI ? 9 : 3;
+            constexpr int NPROD = KS * TI, NV = 9;
 #pragma unroll
             for (int g = 0; g < NPROD; ++g) {
                 __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one product
@@ -695,20 +665,15 @@ void k_bound_lds(BoundArgs a) {
 }
 
 __host__ __device__ constexpr int bound_items(int ks) { return ks >= 3 ? 64 * BLW : 32 * bound_tiles(ks); }
-constexpr size_t bound_lds_bytes(int ks) { return 2 * (size_t)BL_USERS * (4 * ks + 1) * 16 + 2 * BL_USERS * 4; }
+constexpr size_t bound_lds_bytes(int ks) { return 2 * (size_t)BL_USERS * (2 * ks + 1) * 16 + 2 * BL_USERS * 4; }
 
 void launch_bound(const BoundArgs &a, hipStream_t st) {
     auto go = [&](auto ks) {
         constexpr int KS = decltype(ks)::value, BI = bound_items(KS);
         const unsigned g = (unsigned)((a.m + BI - 1) / BI * a.nsplit);
         RMIPS_PROF(st, "k_bound");
-        if constexpr (KS >= 3) {
-            if (a.hi_only) k_bound_lds<KS, true><<<g, 64 * BLW, bound_lds_bytes(KS), st>>>(a);
-            else k_bound_lds<KS, false><<<g, 64 * BLW, bound_lds_bytes(KS), st>>>(a);
-        } else {
-            if (a.hi_only) k_bound<KS, true><<<g, 64 * BW, 0, st>>>(a);
-            else k_bound<KS, false><<<g, 64 * BW, 0, st>>>(a);
-        }
+        if constexpr (KS >= 3) k_bound_lds<KS><<<g, 64 * BLW, bound_lds_bytes(KS), st>>>(a);
+        else k_bound<KS><<<g, 64 * BW, 0, st>>>(a);
     };
     switch (a.ka / 16) {
     case 1: go(std::integral_constant<int, 1>{}); break;

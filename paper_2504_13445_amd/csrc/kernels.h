@@ -99,8 +99,7 @@ void launch_gram(const float *X, int64_t ns, int64_t stride, int d, double *G, d
 // values), tail(x), scale * ||x||, 0...] (ka a multiple of 16, dp + 2 <= ka
 // <= 64), where W (dp x d, FP64, dp <= 62) has orthonormal rows and tail(x)
 // = sqrt(||x||^2 - ||W x||^2) rounded up (W = nullptr: the identity, dp =
-// d), stored as 4 ka bytes per row: BF16
-// hi = rn(a) (2 ka bytes), then BF16 lo = rn(a - hi).  Rows are taken from X
+// d), stored as 2 ka bytes per row: BF16 rn(a).  Rows are taken from X
 // through `order` (NULL = identity); rows from `rows` to `rows_pad` are zero.
 void launch_rotate_aug(const float *X, const int32_t *order, int64_t rows,
                        int64_t rows_pad, int d, const double *W, int dp, int ka, float scale,
@@ -189,10 +188,8 @@ size_t count_lds(int prec, int D);
 
 struct BoundArgs {
     int ka;                            // augmented row length (16, 32, 48 or 64)
-    const uint4 *Pb; int64_t m, mpad;  // augmented item rows (norm order), BF16 hi | lo
-    const uint4 *Ub;                   // augmented user rows (rho order), BF16 hi | lo
-    int hi_only;                       // 1: products of the hi parts alone (the rows'
-                                       // relative slack must cover the lo parts)
+    const uint4 *Pb; int64_t m, mpad;  // augmented item rows (norm order), BF16
+    const uint4 *Ub;                   // augmented user rows (rho order), BF16
     const float *tau_lo;               // per sorted user
     float abs_slack;                   // absolute slack of the bound
     const int32_t *cs;                 // CS prefix per item (non-increasing)

@@ -523,8 +523,8 @@ void launch_gram(const float *X, int64_t ns, int64_t stride, int d, double *G, d
 // persistent grid: y = W x in FP64 with W (dp x d, FP64, orthonormal rows)
 // on the FP64 matrix cores; ||x||^2 in FP64.  Row layout: a = [y (dp values,
 // rounded to FP32), tail(x), scale * ||x||, 0...] (ka values, a multiple of
-// 16), stored as BF16 hi = rn(a) (2 ka bytes) then BF16 lo = rn(a - hi)
-// (2 ka bytes).  tail(x) = sqrt(||x||^2 - ||W x||^2), rounded up and widened
+// 16), stored as BF16 rn(a) (2 ka bytes).  tail(x) = sqrt(||x||^2 -
+// ||W x||^2), rounded up and widened
 // by 1e-12 ||x||^2 under the root for the FP64 rounding (in any summation
 // order) and the departure of W from exact orthonormality.
 //
@@ -619,7 +619,7 @@ void k_rotate_aug(const float *__restrict__ X, const int32_t *__restrict__ order
             if (t2 < 0.0) t2 = 0.0;
             const float tail = __double2float_ru(sqrt(t2 + 1e-12 * sr[i]));
             const float nrm = scale * __double2float_ru(sqrt(sr[i]) * (1.0 + 0x1p-40));
-            uint16_t *orow = o16 + R * 2 * ka;
+            uint16_t *orow = o16 + R * ka;
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int C = 16 * t + c16;
@@ -627,11 +627,8 @@ void k_rotate_aug(const float *__restrict__ X, const int32_t *__restrict__ order
                 float v = (C < dp) ? (float)acc[t][i] : 0.0f;
                 v = (C == dp) ? tail : v;
                 v = (C == dp + 1) ? nrm : v;
-                float h, l;
-                const uint16_t bh = to_bf16(v, h);
-                const uint16_t bl = to_bf16(v - h, l);
-                orow[C] = bh;
-                orow[ka + C] = bl;
+                float h;
+                orow[C] = to_bf16(v, h);
             }
         }
     }
@@ -648,9 +645,9 @@ __global__ __launch_bounds__(256) void k_aug_ident(const float *__restrict__ X,
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= rows_pad) return;
     const int kw = ka / 8;
-    uint4 *o = out + r * 2 * kw;
+    uint4 *o = out + r * kw;
     if (r >= rows) {
-        for (int q = 0; q < 2 * kw; ++q) o[q] = make_uint4(0, 0, 0, 0);
+        for (int q = 0; q < kw; ++q) o[q] = make_uint4(0, 0, 0, 0);
         return;
     }
     const float *x = X + (int64_t)(order ? order[r] : r) * d;
@@ -667,7 +664,7 @@ __global__ __launch_bounds__(256) void k_aug_ident(const float *__restrict__ X,
 #pragma unroll
     for (int q = 0; q < KA_MAX / 8; ++q) {
         if (q < kw) {
-            uint32_t hw[4], lw[4];
+            uint32_t hw[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 float v2[2];
@@ -679,14 +676,11 @@ __global__ __launch_bounds__(256) void k_aug_ident(const float *__restrict__ X,
                     v = (c == d + 1) ? nrm : v;
                     v2[h] = v;
                 }
-                float h0, h1, l0, l1;
+                float h0, h1;
                 const uint16_t b0 = to_bf16(v2[0], h0), b1 = to_bf16(v2[1], h1);
-                const uint16_t c0 = to_bf16(v2[0] - h0, l0), c1 = to_bf16(v2[1] - h1, l1);
                 hw[e] = (uint32_t)b0 | ((uint32_t)b1 << 16);
-                lw[e] = (uint32_t)c0 | ((uint32_t)c1 << 16);
             }
             o[q] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
-            o[kw + q] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
         }
     }
 }

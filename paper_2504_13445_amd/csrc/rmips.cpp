@@ -444,7 +444,7 @@ struct PrefixLayout {
 };
 
 // Eq. (3)/(6) bound counts: the Gram matrix of a user sample, the
-// augmented BF16 hi | lo rows (4 ka bytes each) and per-split partial counts.
+// augmented BF16 rows (2 ka bytes each) and per-split partial counts.
 struct BoundLayout {
     double *G, *Gs;
     uint4 *Pa, *Ua;
@@ -502,8 +502,8 @@ void prefix_plan(int64_t n, int64_t m, int64_t mpad, int rowb, PrefixLayout &X, 
 void bound_plan(int64_t n, int64_t m, int64_t mpad, int d, BoundLayout &B, Carve &cv) {
     B.G = cv.take<double>((size_t)d * d);
     B.Gs = cv.take<double>(gram_scratch_bytes(d) / sizeof(double));
-    B.Pa = cv.take<uint4>((size_t)mpad * aug_len(d) / 4);
-    B.Ua = cv.take<uint4>((size_t)n * aug_len(d) / 4);
+    B.Pa = cv.take<uint4>((size_t)mpad * aug_len(d) / 8);  // ka BF16 values per row
+    B.Ua = cv.take<uint4>((size_t)n * aug_len(d) / 8);
     B.nsplitB = bound_splits(m, aug_len(d));
     B.partialB = cv.take<int32_t>((size_t)B.nsplitB * m);
 }
@@ -618,26 +618,19 @@ void run_prefix(const ThreshLayout &T, PrefixLayout &X, int64_t n, int64_t m, fl
     if (with_rows) launch_gather_padded(T.Uq, X.uperm, n, T.rowb, X.Us, st);
 }
 
-// Relative slack s of the Eq. (3) bound, in units of ||u|| ||p||: the BF16
-// split drops at most 3.01 * 2^-16 |a_i||b_i| per term; the matrix-core sums
-// of the 3 ka <= 192 exact BF16 products (12 chained steps) add at most
-// gamma_204 (unit 2^-23, 3.19 * 2^-16) times 1.02 sum |a_i||b_i|; and sum
-// |a_i||b_i| <= ||a|| ||b|| <= 1.415 ||p|| ||u||: 8.9 * 2^-16 in all, below
-// s = 2^-12; the FP32 rounding of W x (2^-24 relative) is far below the
-// margin.  The absolute slack covers BF16 and FP32 underflow (norms are
-// below 2^60), subnormal operands flushed by the matrix cores included:
-// each such term is below 2^-126 * 2^60 * 1.42 in magnitude.
-constexpr float BOUND_SLACK = 0x1p-12f;
+// Relative slack s of the Eq. (3) bound, in units of ||u|| ||p||: each
+// augmented value is stored as BF16 hi(x) = rn(x), |x - hi(x)| <= 2^-9 |x|,
+// so each product hi(a) hi(b) is within (2 * 2^-9 + 2^-18) |a| |b| of a b,
+// at most 1.003 * 2^-8 * 1.415 ||p|| ||u|| over a row (sum |a_i||b_i| <=
+// ||a|| ||b||); the matrix-core FP32 sums of <= 64 exact BF16 products add
+// gamma_64 (2^-18) of the same, and the FP32 rounding of W x (2^-24
+// relative) is far below; the slack column hi(||p||) hi(s ||u||) gives at
+// least s (1 - 2^-9)^2 ||p|| ||u||: s = 2^-7 covers 1.43 * 2^-8 with room.
+// The absolute slack covers BF16 and FP32 underflow (norms are below 2^60),
+// subnormal operands flushed by the matrix cores included: each such term
+// is below 2^-126 * 2^60 * 1.42 in magnitude.
+constexpr float BOUND_SLACK = 0x1p-7f;
 constexpr float BOUND_ABS_SLACK = 0x1p-60f;
-// With the hi parts alone (d > d', where the bound has a Cauchy-Schwarz
-// tail): each product hi(a) hi(b) is within (2 * 2^-9 + 2^-18) |a| |b| of
-// a b (round to nearest BF16: |x - hi(x)| <= 2^-9 |x|), at most 1.003 *
-// 2^-8 * 1.415 ||p|| ||u|| over the row (the norm column is not multiplied
-// by itself), plus the FP32 sums of <= 64 exact BF16 products (gamma_64,
-// 2^-18 of the same), while the slack column gives at least s (1 - 2^-9)^2
-// ||p|| ||u||: s = 2^-7 covers 1.43 * 2^-8 with room.
-constexpr float BOUND_SLACK_HI = 0x1p-7f;
-bool bound_hi_only(int d) { return d > DPRIME_MAX; }
 
 // Stage (c), second part: the Eq. (3)/(6) bound count of every item (norm
 // order) into `uscore`, over the users of its prefix (users' augmented rows
@@ -646,12 +639,9 @@ void run_bound(const float *U, const PrefixLayout &X, const BoundLayout &B, cons
                int64_t n, int64_t m, int64_t mpad, int d, unsigned long long *pairs,
                hipEvent_t e0, hipEvent_t e1, int32_t *uscore, hipStream_t st) {
     const int dp = dprime(d), ka = aug_len(d);
-    const bool hi = bound_hi_only(d);
-    launch_rotate_aug(U, X.uperm, n, n, d, Wd, dp, ka, hi ? BOUND_SLACK_HI : BOUND_SLACK, B.Ua,
-                      st);
+    launch_rotate_aug(U, X.uperm, n, n, d, Wd, dp, ka, BOUND_SLACK, B.Ua, st);
     BoundArgs ba{};
     ba.ka = ka;
-    ba.hi_only = hi ? 1 : 0;
     ba.Pb = B.Pa; ba.m = m; ba.mpad = mpad; ba.Ub = B.Ua; ba.tau_lo = X.us.tau_lo;
     ba.abs_slack = BOUND_ABS_SLACK; ba.cs = X.cs;
     ba.nsplit = B.nsplitB; ba.partial = B.partialB; ba.pairs = pairs;
