@@ -307,8 +307,14 @@ def main():
     U, P = synth.make_config(cfg)
     n, m, d, k, N = U.shape[0], P.shape[0], cfg.d, cfg.k, max(cfg.N, 1)
     dev = torch.device("cuda:0")
+    # host-to-device upload of U and P (pageable host memory), outside the
+    # timed region and reported on its own
+    torch.cuda.synchronize()
+    t_up = time.perf_counter()
     Ug = torch.from_numpy(U).to(dev)
     Pg = torch.from_numpy(P).to(dev)
+    torch.cuda.synchronize()
+    t_up = time.perf_counter() - t_up
     ws = rm.topn_workspace(n, m, d, k, N, prec, dev)
     torch.cuda.synchronize()
 
@@ -376,6 +382,9 @@ def main():
                    "n": n, "m": m, "d": d, "k": k, "N": N, "parallelism": "single GPU"},
         "roofline": roofline,
         "seconds_per_step": ms / 1e3,
+        "h2d_upload": {"seconds": t_up, "bytes": int(U.nbytes + P.nbytes),
+                       "GB_per_s": (U.nbytes + P.nbytes) / t_up / 1e9,
+                       "note": "U and P from pageable host memory, not part of value"},
         "stages_ms": {"thresholds": avg("ms_thresh"), "bounds": avg("ms_bound"),
                       "counting": avg("ms_count"), "screen_kernel": avg("ms_screen"),
                       "count_kernels": avg("ms_count_kernels"),
