@@ -525,7 +525,7 @@ __global__ __launch_bounds__(64 * BW) void k_bound(BoundArgs a) {
 // into LDS once (direct copies, double-buffered) and read by all the waves,
 // so that a user row is fetched once per 512 items.
 constexpr int BLW = 8;       // waves per workgroup
-constexpr int BL_USERS = 64;  // users per stage
+constexpr int BL_USERS = 256;  // users per stage
 
 template <int KS>
 __global__ __launch_bounds__(64 * BLW) __attribute__((amdgpu_waves_per_eu(2)))
