@@ -835,49 +835,6 @@ void k_thresh_final(ThreshArgs a, int capT, int capP) {
     }
 }
 
-// The recomputations left by k_thresh_final: EXACT_SLOTS lanes per user,
-// 64 / EXACT_SLOTS users per wave over the same list.  Lane q of a user with
-// n <= EXACT_SLOTS values to recompute takes the q-th id; the value of rank
-// tgt among the n, in the order (value desc, id asc), is tau_u.
-template <bool LISTED>
-__global__ __launch_bounds__(256) void k_thresh_exact(ThreshArgs a) {
-    constexpr int UPW = 64 / EXACT_SLOTS;  // users per wave
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int grp = lane / EXACT_SLOTS, q = lane % EXACT_SLOTS;
-    const int nw = blockDim.x >> 6;
-    const int64_t nlist = LISTED ? (int64_t)*a.ulist_cnt : a.n;
-    for (int64_t b0 = ((int64_t)blockIdx.x * nw + w) * UPW; b0 < nlist;
-         b0 += (int64_t)gridDim.x * nw * UPW) {
-        const int64_t pos = b0 + grp;
-        const bool valid = pos < nlist;
-        const int64_t u = valid ? (LISTED ? (int64_t)a.ulist[pos] : pos) : 0;
-        const int meta = valid ? a.cand_cnt[u * a.nsplit] : -1;
-        // (longer lists are k_thresh_exact_wide's)
-        const int nrec = (meta < 0 || (meta >> 8) > EXACT_SLOTS) ? 0 : meta >> 8;
-        const int tgt = meta & 255;
-        const bool have = q < nrec;
-        int id = 0;
-        double v = 0.0;
-        if (have) {
-            id = a.cand_id[u * a.nsplit * (int64_t)a.cap + q];
-            v = ip64<32>(a.U + u * a.d, a.P + (int64_t)id * a.d, a.d);
-        }
-        // rank among the user's values: the lanes of its group
-        int rank = 0;
-#pragma unroll
-        for (int j = 0; j < EXACT_SLOTS; ++j) {
-            const int src = grp * EXACT_SLOTS + j;
-            const double y = __shfl(v, src);
-            const int yi = __shfl(id, src);
-            rank += (j < nrec && ((y > v) || (y == v && yi < id))) ? 1 : 0;
-        }
-        if (have && rank == tgt) {
-            a.tau[u] = v;
-            a.tau_id[u] = id;
-        }
-    }
-}
-
 // u . p (ip64's arithmetic, term by term) with the user's row staged in LDS
 // (ul, 16-byte aligned): 32 values of the item row per step, so that a
 // lane's loads of a step cover whole 128-byte blocks of it.  Rows that are
@@ -905,6 +862,57 @@ __device__ __forceinline__ double ip64_lds_user(const float *ul, const float *ug
         }
     }
     return acc;
+}
+
+// The recomputations left by k_thresh_final: EXACT_SLOTS lanes per user,
+// 64 / EXACT_SLOTS users per wave over the same list.  Lane q of a user with
+// n <= EXACT_SLOTS values to recompute takes the q-th id; the value of rank
+// tgt among the n, in the order (value desc, id asc), is tau_u.  Each user's
+// row is staged in LDS once for its lanes (workgroups of four waves).
+template <bool LISTED>
+__global__ __launch_bounds__(256) void k_thresh_exact(ThreshArgs a) {
+    constexpr int UPW = 64 / EXACT_SLOTS;  // users per wave
+    __shared__ __align__(16) float urow_s[4][UPW][DMAX];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int grp = lane / EXACT_SLOTS, q = lane % EXACT_SLOTS;
+    const int nw = blockDim.x >> 6;
+    const int64_t nlist = LISTED ? (int64_t)*a.ulist_cnt : a.n;
+    for (int64_t b0 = ((int64_t)blockIdx.x * nw + w) * UPW; b0 < nlist;
+         b0 += (int64_t)gridDim.x * nw * UPW) {
+        const int64_t pos = b0 + grp;
+        const bool valid = pos < nlist;
+        const int64_t u = valid ? (LISTED ? (int64_t)a.ulist[pos] : pos) : 0;
+        const int meta = valid ? a.cand_cnt[u * a.nsplit] : -1;
+        // (longer lists are k_thresh_exact_wide's)
+        const int nrec = (meta < 0 || (meta >> 8) > EXACT_SLOTS) ? 0 : meta >> 8;
+        const int tgt = meta & 255;
+        const bool have = q < nrec;
+        const float *ug = a.U + u * a.d;
+        float *ul = urow_s[w][grp];
+        wave_sync();  // the previous users' rows are no longer read
+        if (nrec > 0)
+            for (int i = q; i < a.d; i += EXACT_SLOTS) ul[i] = ug[i];
+        wave_sync();
+        int id = 0;
+        double v = 0.0;
+        if (have) {
+            id = a.cand_id[u * a.nsplit * (int64_t)a.cap + q];
+            v = ip64_lds_user(ul, ug, a.P + (int64_t)id * a.d, a.d);
+        }
+        // rank among the user's values: the lanes of its group
+        int rank = 0;
+#pragma unroll
+        for (int j = 0; j < EXACT_SLOTS; ++j) {
+            const int src = grp * EXACT_SLOTS + j;
+            const double y = __shfl(v, src);
+            const int yi = __shfl(id, src);
+            rank += (j < nrec && ((y > v) || (y == v && yi < id))) ? 1 : 0;
+        }
+        if (have && rank == tgt) {
+            a.tau[u] = v;
+            a.tau_id[u] = id;
+        }
+    }
 }
 
 // The recomputations of users with more than EXACT_SLOTS (at most
@@ -1115,9 +1123,9 @@ void launch_thresh(const ThreshArgs &a0, hipStream_t st) {
     const int64_t fres =
         256 * std::max<int64_t>(1, std::min<int64_t>(FIN_WPE * 4 / fw, (160 * 1024) / lds_fin));
     const int64_t fblocks = std::min<int64_t>((a0.n + fw - 1) / fw, fres);
-    // (three 4-wave workgroups per CU are resident)
+    // (four 4-wave workgroups per CU are resident)
     const int64_t eblocks = std::min<int64_t>(
-        (a0.n + 4 * (64 / EXACT_SLOTS) - 1) / (4 * (64 / EXACT_SLOTS)), 3 * 256);
+        (a0.n + 4 * (64 / EXACT_SLOTS) - 1) / (4 * (64 / EXACT_SLOTS)), 4 * 256);
     // a wave per 64 users of the list, four per workgroup, a few resident
     // rounds
     const int64_t wblocks = std::min<int64_t>((a0.n + 255) / 256, 8 * 256);
