@@ -30,7 +30,6 @@ sys.path.insert(0, ROOT)
 PEAK = {"fp32": 157.3e12, "bf16": 2.5e15, "fp8": 5.0e15, "fp6": 10.1e15, "fp4": 10.1e15,
         "fp64": 78.6e12}
 HBM_PEAK = 8.0e12
-DPRIME_MAX = 62
 DEFAULT_CONFIG = 3
 
 
@@ -239,7 +238,8 @@ def kernel_table(prof, stats, steps, n, m, d, k, prec):
     # bytes per element slot and padded width (FP6/FP4 use FP8's 32-byte block slots)
     eb = {"fp32": 4, "bf16": 2}.get(prec, 1)
     D = {"fp32": (d + 7) // 8 * 8, "bf16": (d + 15) // 16 * 16}.get(prec, (d + 63) // 64 * 64)
-    dp = min(d, DPRIME_MAX)
+    dp = d  # d' of the bound: the library's default, no rotation
+    ka = (dp + 2 + 15) // 16 * 16
     mpad = (m + 63) // 64 * 64
     t0 = min(6, mpad // 64)
     # per step: (work, unit, peak, bound)
@@ -249,7 +249,8 @@ def kernel_table(prof, stats, steps, n, m, d, k, prec):
         "k_thresh_screen/refine": (2.0 * d * avg("refine_pairs"), "flop", PEAK[prec], "mfma"),
         "k_count": (2.0 * d * avg("count_pairs"), "flop", PEAK[prec], "mfma"),
         "k_bound": (2.0 * (dp + 2) * avg("bound_pairs"), "flop", PEAK["bf16"], "mfma"),
-        "k_rotate_aug": (2.0 * d * dp * (n + mpad), "flop", PEAK["fp64"], "mfma"),
+        # FP32 rows read, the bound's BF16 rows (ka values) written
+        "k_aug_ident": ((n + m) * 4.0 * d + (n + mpad) * 2.0 * ka, "byte", HBM_PEAK, "hbm"),
         # bytes: FP32 rows read, screening copies and four per-row floats written
         "k_quant": ((n + m) * (4.0 * d + D * eb + 16.0), "byte", HBM_PEAK, "hbm"),
         # candidate lists read (value, bound, id: 12 B each), tau and id written

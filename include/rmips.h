@@ -157,6 +157,18 @@ rmips_status rmips_set_candidate_cap(rmips_ctx *ctx, int32_t cap);
 rmips_status rmips_set_batch(rmips_ctx *ctx, int32_t first, int32_t max);
 
 /*
+ * Split dimension d' of the Eq. (3) bound (Sec. 4.2; the paper's
+ * experiments use d' = 10, Sec. 5.1) for rmips_topn and rmips_index_build.
+ * 0 (the default): d' = d, the bound is the inner product itself with its
+ * certified slack (no rotation).  1 <= dprime <= 62: both sides are rotated
+ * onto the top-d' eigenvectors of a user sample's Gram matrix and the
+ * residual norms carry the rest, as in the paper (dprime >= d means d).
+ * Results do not change; the bound's tightness (how many items stage (b)
+ * counts) and its cost do.  RMIPS_EINVAL outside [0, 62].
+ */
+rmips_status rmips_set_dprime(rmips_ctx *ctx, int32_t dprime);
+
+/*
  * Testing knob: when `uscore` is not NULL (a device array of m int32),
  * rmips_topn also writes the Eq. (3)/(6) bound count of every item in the
  * caller's order (Sec. 4.2; the count over the users of the item's
@@ -208,10 +220,10 @@ rmips_status rmips_scores(rmips_ctx *ctx, const float *U, int64_t n,
 /*
  * Def. 3 by the paper's method (Sec. 4, Alg. 2 driven by exact thresholds):
  * stage (a), then the Cauchy-Schwarz (Eq. 2) and incremental-pruning
- * (Eq. 3 / Eq. 6) upper bounds on every score, with d' = min(d, 62) after a
- * rotation of both sides onto the users' dominant eigenspace (none when
- * d <= 62), then exact scores of items visited in (bound desc, id asc)
- * order until the next bound is below the current N-th score.
+ * (Eq. 3 / Eq. 6) upper bounds on every score (d' = d unless
+ * rmips_set_dprime chose a rotation onto the users' dominant eigenspace),
+ * then exact scores of items visited in (bound desc, id asc) order until
+ * the next bound is below the current N-th score.
  *   1 <= N <= min(m, RMIPS_N_MAX).
  *   top_ids [N], top_scores [N]: HOST int32 out, (score desc, id asc).
  *   stats: HOST, may be NULL.

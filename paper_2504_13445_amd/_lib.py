@@ -24,7 +24,7 @@ K_MAX, N_MAX, D_MAX = 32, 1024, 256
 EXPORTS = [
     "rmips_create", "rmips_destroy", "rmips_last_error", "rmips_set_stream", "rmips_sync",
     "rmips_set_profiling", "rmips_profile_entry",
-    "rmips_set_candidate_cap", "rmips_set_batch", "rmips_set_bound_output",
+    "rmips_set_candidate_cap", "rmips_set_batch", "rmips_set_bound_output", "rmips_set_dprime",
     "rmips_thresholds_workspace_size", "rmips_scores_workspace_size",
     "rmips_topn_workspace_size", "rmips_soft_workspace_size",
     "rmips_thresholds", "rmips_scores", "rmips_topn", "rmips_soft_fwd",
@@ -123,6 +123,8 @@ def load():
     lib.rmips_set_batch.restype = st
     lib.rmips_set_bound_output.argtypes = [vp, vp]
     lib.rmips_set_bound_output.restype = st
+    lib.rmips_set_dprime.argtypes = [vp, i32]
+    lib.rmips_set_dprime.restype = st
     lib.rmips_thresholds_workspace_size.argtypes = [i64, i64, i32, i32, ctypes.c_int]
     lib.rmips_thresholds_workspace_size.restype = sz
     lib.rmips_scores_workspace_size.argtypes = [i64, i64, i32, ctypes.c_int]
@@ -314,10 +316,13 @@ def topn_workspace(n, m, d, k, N, prec="fp32", device=None):
                       device or torch.device("cuda"))
 
 
-def topn(U, P, k, N, prec="fp32", ws=None, cand_cap=None, batch=None, bound_out=None):
+def topn(U, P, k, N, prec="fp32", ws=None, cand_cap=None, batch=None, bound_out=None,
+         dprime=None):
     """Top-N item ids and scores (host int32 numpy arrays) and a stats dict.
     bound_out: optional int32 device tensor of m entries that receives the
-    Eq. (3)/(6) bound count of every item (caller order)."""
+    Eq. (3)/(6) bound count of every item (caller order).  dprime: the split
+    dimension d' of that bound (None or 0: d' = d; 1..62: a rotation onto
+    the users' top-d' eigenvectors)."""
     import numpy as np
     U, P = _dev_f32(U, "U"), _dev_f32(P, "P")
     n, d = U.shape
@@ -331,7 +336,10 @@ def topn(U, P, k, N, prec="fp32", ws=None, cand_cap=None, batch=None, bound_out=
     ids = np.empty(N, np.int32)
     sc = np.empty(N, np.int32)
     st = Stats()
-    # the testing knobs are set only when asked for, and reset after the call
+    # the knobs are set only when asked for, and reset after the call (d'
+    # first: an invalid value then leaves nothing set)
+    if dprime:
+        _check(ctx, lib.rmips_set_dprime(ctx, int(dprime)))
     if bound_out is not None:
         if (bound_out.dtype != torch.int32 or bound_out.numel() != m or not bound_out.is_cuda
                 or not bound_out.is_contiguous()):
@@ -348,6 +356,8 @@ def topn(U, P, k, N, prec="fp32", ws=None, cand_cap=None, batch=None, bound_out=
         lib.rmips_set_candidate_cap(ctx, 0)
     if batch:
         lib.rmips_set_batch(ctx, 0, 0)
+    if dprime:
+        lib.rmips_set_dprime(ctx, 0)
     if bound_out is not None:
         lib.rmips_set_bound_output(ctx, None)
     _check(ctx, status)
@@ -397,7 +407,7 @@ class Index:
     user's kmax largest values and the bound of every item for every
     k <= kmax, held in a device buffer; topn() answers any (k, N)."""
 
-    def __init__(self, U, P, kmax, prec="fp32"):
+    def __init__(self, U, P, kmax, prec="fp32", dprime=None):
         U, P = _dev_f32(U, "U"), _dev_f32(P, "P")
         if P.shape[1] != U.shape[1]:
             raise ValueError("U and P must have the same number of columns")
@@ -411,9 +421,15 @@ class Index:
                               U.device)
         self.ws = _workspace(lib.rmips_index_workspace_size(self.n, self.m, self.d, self.kmax,
                                                             self.p), U.device)
-        _check(ctx, lib.rmips_index_build(ctx, _ptr(U), self.n, _ptr(P), self.m, self.d,
-                                          self.kmax, self.p, _ptr(self.buf), self.buf.numel(),
-                                          _ptr(self.ws), self.ws.numel()))
+        if dprime:
+            _check(ctx, lib.rmips_set_dprime(ctx, int(dprime)))
+        try:
+            _check(ctx, lib.rmips_index_build(ctx, _ptr(U), self.n, _ptr(P), self.m, self.d,
+                                              self.kmax, self.p, _ptr(self.buf),
+                                              self.buf.numel(), _ptr(self.ws), self.ws.numel()))
+        finally:
+            if dprime:
+                lib.rmips_set_dprime(ctx, 0)
 
     def _args(self):
         return (self.n, self.m, self.d, self.kmax, self.p, _ptr(self.buf), self.buf.numel())

@@ -521,16 +521,27 @@ __global__ __launch_bounds__(64 * BW) void k_bound(BoundArgs a) {
 }
 
 // Longer rows (KS >= 3): a workgroup of BLW waves holds 64 items per wave
-// (512 in all) in registers, and every stage of BL_USERS users is copied
-// into LDS once (direct copies, double-buffered) and read by all the waves,
-// so that a user row is fetched once per 512 items.
-constexpr int BLW = 8;       // waves per workgroup
-constexpr int BL_USERS = 256;  // users per stage
+// (512 in all) in registers, and every stage of bl_users(KS) users is
+// copied into LDS once (direct copies, double-buffered) and read by all the
+// waves, so that a user row is fetched once per 512 items.
+constexpr int BLW = 8;  // waves per workgroup
+// users per stage: 256 while two such stages (rows of 2 KS + 1 16-byte
+// slots) and their thresholds fit in the 160 KB of LDS, else 128
+__host__ __device__ constexpr int bl_users(int ks) {
+    return 2 * 256 * (2 * ks + 1) * 16 + 2 * 256 * 4 <= 160 * 1024 ? 256 : 128;
+}
+constexpr size_t bound_lds_bytes(int ks) {
+    return 2 * (size_t)bl_users(ks) * (2 * ks + 1) * 16 + 2 * (size_t)bl_users(ks) * 4;
+}
 
 template <int KS>
 __global__ __launch_bounds__(64 * BLW) __attribute__((amdgpu_waves_per_eu(2)))
 void k_bound_lds(BoundArgs a) {
     constexpr int TI = 2, BI = 32 * TI * BLW, RW = 2 * KS, LSL = RW + 1;  // LSL: LDS row slots
+    constexpr int BL_USERS = bl_users(KS);
+    // a second set of products in flight while one is counted, where the
+    // registers allow it (the items' rows take 8 KS of the 256)
+    constexpr bool PIPE = KS <= 11;
     // two stage buffers of user rows, then their thresholds (dynamic LDS,
     // bound_lds_bytes(KS))
     extern __shared__ __align__(16) uint8_t smem_b[];
@@ -598,9 +609,11 @@ void k_bound_lds(BoundArgs a) {
         const int64_t nx = j + a.nsplit;
         if (nx < nblk) stage(nx, buf ^ 1);  // the other buffer was last read before the barrier
         const uint4 *U = ush[buf];
-        // column blocks of 32 users: the products of block cb run while the
-        // counts of block cb - 1 (for cb = 0: the previous stage's last
-        // block) are taken, one product and a few compares at a time
+        // column blocks of 32 users: with PIPE, the products of block cb run
+        // while the counts of block cb - 1 (for cb = 0: the previous stage's
+        // last block) are taken, one product and a few compares at a time;
+        // without, each block is counted after its products (the other wave
+        // of the SIMD multiplies meanwhile)
 #pragma unroll
         for (int cb = 0; cb < BL_USERS / 32; ++cb) {
             const int ul = 32 * cb + col;
@@ -614,27 +627,68 @@ void k_bound_lds(BoundArgs a) {
             f32x16 nc[TI];
 #pragma unroll
             for (int t = 0; t < TI; ++t) nc[t] = f32x16{0};
+            if constexpr (PIPE) {
 #pragma unroll
-            for (int q = 0; q < KS; ++q) {
-                const bf16x8 yh = __builtin_bit_cast(bf16x8, U[ul * LSL + 2 * q + h]);
+                for (int q = 0; q < KS; ++q) {
+                    const bf16x8 yh = __builtin_bit_cast(bf16x8, U[ul * LSL + 2 * q + h]);
+#pragma unroll
+                    for (int t = 0; t < TI; ++t)
+                        nc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t][q], yh, nc[t], 0, 0, 0);
+                }
+            } else {
+                // the user row in groups of BL_G steps: the reads of group g + 1
+                // are issued after the first step of group g, so their latency
+                // hides behind the group's other products (the scheduling
+                // fences keep that order)
+                constexpr int BL_G = KS <= 14 ? 3 : KS <= 16 ? 2 : 1, NG = (KS + BL_G - 1) / BL_G;
+                bf16x8 yg[2][BL_G];
+                auto rd = [&](int g, bf16x8 (&y)[BL_G]) {
+#pragma unroll
+                    for (int e = 0; e < BL_G; ++e)
+                        if (g * BL_G + e < KS)
+                            y[e] = __builtin_bit_cast(bf16x8, U[ul * LSL + 2 * (g * BL_G + e) + h]);
+                };
+                auto mm = [&](int q, const bf16x8 &y) {
+#pragma unroll
+                    for (int t = 0; t < TI; ++t)
+                        nc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t][q], y, nc[t], 0, 0, 0);
+                };
+                rd(0, yg[0]);
+#pragma unroll
+                for (int g = 0; g < NG; ++g) {
+                    __builtin_amdgcn_sched_barrier(0);
+                    mm(g * BL_G, yg[g & 1][0]);
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (g + 1 < NG) rd(g + 1, yg[(g + 1) & 1]);
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int e = 1; e < BL_G; ++e)
+                        if (g * BL_G + e < KS) mm(g * BL_G + e, yg[g & 1][e]);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if constexpr (PIPE) {
 #pragma unroll
                 for (int t = 0; t < TI; ++t)
-                    nc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t][q], yh, nc[t], 0, 0, 0);
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) cnt[t][i] += (pc[t][i] >= tprev) ? vprev : 0;
+                // the counts (about 72 vector instructions) spread over the products
+                constexpr int NPROD = KS * TI, NV = (72 + NPROD - 1) / NPROD;
+#pragma unroll
+                for (int g = 0; g < NPROD; ++g) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one product
+                    __builtin_amdgcn_sched_group_barrier(0x002, NV, 0);  // vector ops
+                }
+#pragma unroll
+                for (int t = 0; t < TI; ++t) pc[t] = nc[t];
+                tprev = tl;
+                vprev = vm;
+            } else {
+#pragma unroll
+                for (int t = 0; t < TI; ++t)
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) cnt[t][i] += (nc[t][i] >= tl) ? vm : 0;
             }
-#pragma unroll
-            for (int t = 0; t < TI; ++t)
-#pragma unroll
-                for (int i = 0; i < 16; ++i) cnt[t][i] += (pc[t][i] >= tprev) ? vprev : 0;
-            constexpr int NPROD = KS * TI, NV = 9;
-#pragma unroll
-            for (int g = 0; g < NPROD; ++g) {
-                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one product
-                __builtin_amdgcn_sched_group_barrier(0x002, NV, 0);  // vector ops
-            }
-#pragma unroll
-            for (int t = 0; t < TI; ++t) pc[t] = nc[t];
-            tprev = tl;
-            vprev = vm;
         }
         // the counts are taken before the barrier (not moved past it)
 #pragma unroll
@@ -646,10 +700,12 @@ void k_bound_lds(BoundArgs a) {
         __syncthreads();
         buf ^= 1;
     }
+    if constexpr (PIPE) {
 #pragma unroll
-    for (int t = 0; t < TI; ++t)
+        for (int t = 0; t < TI; ++t)
 #pragma unroll
-        for (int i = 0; i < 16; ++i) cnt[t][i] += (pc[t][i] >= tprev) ? vprev : 0;
+            for (int i = 0; i < 16; ++i) cnt[t][i] += (pc[t][i] >= tprev) ? vprev : 0;
+    }
 #pragma unroll
     for (int t = 0; t < TI; ++t)
 #pragma unroll
@@ -665,7 +721,6 @@ void k_bound_lds(BoundArgs a) {
 }
 
 __host__ __device__ constexpr int bound_items(int ks) { return ks >= 3 ? 64 * BLW : 32 * bound_tiles(ks); }
-constexpr size_t bound_lds_bytes(int ks) { return 2 * (size_t)BL_USERS * (2 * ks + 1) * 16 + 2 * BL_USERS * 4; }
 
 void launch_bound(const BoundArgs &a, hipStream_t st) {
     auto go = [&](auto ks) {
@@ -675,11 +730,15 @@ void launch_bound(const BoundArgs &a, hipStream_t st) {
         if constexpr (KS >= 3) k_bound_lds<KS><<<g, 64 * BLW, bound_lds_bytes(KS), st>>>(a);
         else k_bound<KS><<<g, 64 * BW, 0, st>>>(a);
     };
+    // ka = 16 KS <= 272 (d' <= 256 values and two more columns)
     switch (a.ka / 16) {
-    case 1: go(std::integral_constant<int, 1>{}); break;
-    case 2: go(std::integral_constant<int, 2>{}); break;
-    case 3: go(std::integral_constant<int, 3>{}); break;
-    default: go(std::integral_constant<int, 4>{}); break;
+#define RMIPS_BOUND_KS(K) case K: go(std::integral_constant<int, K>{}); break;
+        RMIPS_BOUND_KS(1) RMIPS_BOUND_KS(2) RMIPS_BOUND_KS(3) RMIPS_BOUND_KS(4)
+        RMIPS_BOUND_KS(5) RMIPS_BOUND_KS(6) RMIPS_BOUND_KS(7) RMIPS_BOUND_KS(8)
+        RMIPS_BOUND_KS(9) RMIPS_BOUND_KS(10) RMIPS_BOUND_KS(11) RMIPS_BOUND_KS(12)
+        RMIPS_BOUND_KS(13) RMIPS_BOUND_KS(14) RMIPS_BOUND_KS(15) RMIPS_BOUND_KS(16)
+#undef RMIPS_BOUND_KS
+    default: go(std::integral_constant<int, 17>{}); break;
     }
 }
 

@@ -634,55 +634,57 @@ void k_rotate_aug(const float *__restrict__ X, const int32_t *__restrict__ order
     }
 }
 
-// The same rows when W is the identity (dp = d): y = x exactly, and ||W x||^2
-// is the same FP64 sum as ||x||^2, so the tail is the widening alone.  Up to
-// the FP64 summation order of the norm (both rounded up) these are the rows
-// k_rotate_aug gives with W = I.
-__global__ __launch_bounds__(256) void k_aug_ident(const float *__restrict__ X,
-                                                  const int32_t *__restrict__ order,
-                                                  int64_t rows, int64_t rows_pad, int d, int ka,
-                                                  float scale, uint4 *__restrict__ out) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// The same rows when W is the identity (dp = d <= 256, ka <= 272): y = x
+// exactly, and ||W x||^2 is the same FP64 sum as ||x||^2, so the tail is the
+// widening alone.  Up to the FP64 summation order of the norm (both rounded
+// up) these are the rows k_rotate_aug gives with W = I.  One wave per row:
+// lane j holds values 8j .. 8j + 7 of the augmented row and writes its
+// 16-byte word j.
+constexpr int AUG_ROWS = 4;  // rows (waves) per workgroup
+__global__ __launch_bounds__(64 * AUG_ROWS) void k_aug_ident(const float *__restrict__ X,
+                                                            const int32_t *__restrict__ order,
+                                                            int64_t rows, int64_t rows_pad, int d,
+                                                            int ka, float scale,
+                                                            uint4 *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * AUG_ROWS + (threadIdx.x >> 6);
     if (r >= rows_pad) return;
     const int kw = ka / 8;
     uint4 *o = out + r * kw;
     if (r >= rows) {
-        for (int q = 0; q < kw; ++q) o[q] = make_uint4(0, 0, 0, 0);
+        if (lane < kw) o[lane] = make_uint4(0, 0, 0, 0);
         return;
     }
     const float *x = X + (int64_t)(order ? order[r] : r) * d;
-    // the whole row in registers (d <= DP_MAX), loaded at once
-    float xr[DP_MAX];
-#pragma unroll
-    for (int c = 0; c < DP_MAX; ++c) xr[c] = (c < d) ? x[c] : 0.0f;
+    float v[8];
     double s = 0.0;
 #pragma unroll
-    for (int c = 0; c < DP_MAX; ++c)
-        if (c < d) s = fma((double)xr[c], (double)xr[c], s);
+    for (int e = 0; e < 8; ++e) {
+        const int c = 8 * lane + e;
+        v[e] = c < d ? x[c] : 0.0f;
+        s = fma((double)v[e], (double)v[e], s);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
     const float tail = __double2float_ru(sqrt(0.0 + 1e-12 * s));
     const float nrm = scale * __double2float_ru(sqrt(s) * (1.0 + 0x1p-40));
+    if (lane >= kw) return;
+    uint32_t hw[4];
 #pragma unroll
-    for (int q = 0; q < KA_MAX / 8; ++q) {
-        if (q < kw) {
-            uint32_t hw[4];
+    for (int e = 0; e < 4; ++e) {
+        uint16_t b[2];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                float v2[2];
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int c = 8 * q + 2 * e + h;
-                    float v = (c < d && c < DP_MAX) ? xr[c < DP_MAX ? c : 0] : 0.0f;
-                    v = (c == d) ? tail : v;
-                    v = (c == d + 1) ? nrm : v;
-                    v2[h] = v;
-                }
-                float h0, h1;
-                const uint16_t b0 = to_bf16(v2[0], h0), b1 = to_bf16(v2[1], h1);
-                hw[e] = (uint32_t)b0 | ((uint32_t)b1 << 16);
-            }
-            o[q] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+        for (int h = 0; h < 2; ++h) {
+            const int c = 8 * lane + 2 * e + h;
+            float y = v[2 * e + h];
+            y = (c == d) ? tail : y;
+            y = (c == d + 1) ? nrm : y;
+            float q;
+            b[h] = to_bf16(y, q);
         }
+        hw[e] = (uint32_t)b[0] | ((uint32_t)b[1] << 16);
     }
+    o[lane] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
 }
 
 size_t rotate_lds_bytes(int d) { return (size_t)4 * ((d + 3) / 4) * 64 * sizeof(double); }
@@ -690,10 +692,10 @@ size_t rotate_lds_bytes(int d) { return (size_t)4 * ((d + 3) / 4) * 64 * sizeof(
 void launch_rotate_aug(const float *X, const int32_t *order, int64_t rows, int64_t rows_pad,
                        int d, const double *W, int dp, int ka, float scale, uint4 *out,
                        hipStream_t st) {
-    if (W == nullptr) {  // the identity, dp = d <= DP_MAX
+    if (W == nullptr) {  // the identity, dp = d
         RMIPS_PROF(st, "k_aug_ident");
-        k_aug_ident<<<(unsigned)((rows_pad + 255) / 256), 256, 0, st>>>(X, order, rows, rows_pad,
-                                                                       d, ka, scale, out);
+        k_aug_ident<<<(unsigned)((rows_pad + AUG_ROWS - 1) / AUG_ROWS), 64 * AUG_ROWS, 0, st>>>(
+            X, order, rows, rows_pad, d, ka, scale, out);
         return;
     }
     // persistent: W is staged once per workgroup, one workgroup per compute

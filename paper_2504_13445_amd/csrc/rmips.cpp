@@ -92,6 +92,7 @@ struct rmips_ctx {
     std::string err;
     int32_t cap_override = 0;
     int32_t batch_first = 0, batch_max = 0;
+    int32_t dprime = 0;  // d' of the Eq. (3) bound (0: d' = d)
     int32_t *bound_out = nullptr;  // device, m int32 (testing knob)
     int32_t *h_status = nullptr;  // pinned, small
     int32_t *h_vis = nullptr;     // pinned: visit-order bounds and prefixes, top-N
@@ -120,13 +121,18 @@ constexpr int PENDING_SLOTS = 63;
 
 namespace {
 
-// Split dimension d' of Eq. (3) (Sec. 5.1): min(d, DPRIME_MAX).  A larger
-// d' than the paper's tightens the bound (fewer items are visited in stage
-// (b)); the matrix-core bound pass pays for it in K only.  With d' = d the
-// rotation is the identity and the bound is the inner product itself.
-constexpr int DPRIME_MAX = 62;
-int dprime(int d) { return std::min(d, DPRIME_MAX); }
-int aug_len(int d) { return (dprime(d) + 2 + 15) & ~15; }  // ka: 16, 32, 48 or 64
+// Split dimension d' of Eq. (3) (Sec. 4.2; d' = 10 in the paper's
+// experiments, Sec. 5.1).  By default d' = d: the rotation is then the
+// identity and the bound is the inner product itself plus the certified
+// slack, so that stage (b) counts little more than the items that can reach
+// the N-th score; the matrix-core bound pass pays for the larger d' in K
+// only.  rmips_set_dprime selects a rotation onto the top-d' eigenvectors
+// of a user sample instead (d' <= DPRIME_ROT_MAX).
+constexpr int DPRIME_ROT_MAX = 62;
+int dprime(const rmips_ctx *c, int d) { return (c->dprime > 0 && c->dprime < d) ? c->dprime : d; }
+// augmented row length ka = 16 KS for d' values and two more columns
+// (KS <= 17 for d' <= 256); the identity's (d' = d) is the longest
+int aug_len(int dp) { return (dp + 2 + 15) & ~15; }
 constexpr int T0_TILES = 6;             // tiles of phase 1 of stage (a)
 constexpr int BATCH_FIRST = 256;
 constexpr int BATCH_MAX = 4096;
@@ -502,7 +508,8 @@ void prefix_plan(int64_t n, int64_t m, int64_t mpad, int rowb, PrefixLayout &X, 
 void bound_plan(int64_t n, int64_t m, int64_t mpad, int d, BoundLayout &B, Carve &cv) {
     B.G = cv.take<double>((size_t)d * d);
     B.Gs = cv.take<double>(gram_scratch_bytes(d) / sizeof(double));
-    B.Pa = cv.take<uint4>((size_t)mpad * aug_len(d) / 8);  // ka BF16 values per row
+    // ka BF16 values per row, for the longest rows (d' = d)
+    B.Pa = cv.take<uint4>((size_t)mpad * aug_len(d) / 8);
     B.Ua = cv.take<uint4>((size_t)n * aug_len(d) / 8);
     B.nsplitB = bound_splits(m, aug_len(d));
     B.partialB = cv.take<int32_t>((size_t)B.nsplitB * m);
@@ -531,7 +538,7 @@ void topn_plan(int prec, int64_t n, int64_t m, int d, int k, int cap_override, i
                TopnLayout &L, Carve &cv) {
     thresh_plan(prec, n, m, d, k, cap_override, L.T, cv);
     prefix_plan(n, m, L.T.mpad, L.T.rowb, L.X, cv);
-    L.W = cv.take<double>((size_t)DPRIME_MAX * d);
+    L.W = cv.take<double>((size_t)DPRIME_ROT_MAX * d);
     bound_plan(n, m, L.T.mpad, d, L.B, cv);
     L.uscore = cv.take<int32_t>(m);
     count_plan(m, bmax, L.C, cv, true);
@@ -560,20 +567,24 @@ void index_plan(int prec, int64_t n, int64_t m, int d, int kmax, IndexLayout &I,
     prep_plan(prec, n, m, d, I.T, cv);
     I.topv = cv.take<double>((size_t)n * kmax);
     I.topk = cv.take<int32_t>((size_t)n * kmax);
-    I.W = cv.take<double>((size_t)DPRIME_MAX * d);
+    I.W = cv.take<double>((size_t)DPRIME_ROT_MAX * d);
     I.inv = cv.take<int32_t>(m);
     I.table = cv.take<int32_t>((size_t)kmax * m);
     I.hdr = cv.take<int32_t>(INDEX_HDR_WORDS);
 }
 
-void index_header(int64_t n, int64_t m, int d, int kmax, int prec, int32_t (&h)[INDEX_HDR_WORDS]) {
+// header words: version, n, m, d, kmax, precision, the d' of the build's
+// bound (a record only: queries accept any), 0
+constexpr int INDEX_HDR_DPRIME = 6;
+void index_header(int64_t n, int64_t m, int d, int kmax, int prec, int dp,
+                  int32_t (&h)[INDEX_HDR_WORDS]) {
     h[0] = INDEX_MAGIC | 1;
     h[1] = (int32_t)n;
     h[2] = (int32_t)m;
     h[3] = d;
     h[4] = kmax;
     h[5] = prec;
-    h[6] = 0;
+    h[INDEX_HDR_DPRIME] = dp;
     h[7] = 0;
 }
 
@@ -622,23 +633,26 @@ void run_prefix(const ThreshLayout &T, PrefixLayout &X, int64_t n, int64_t m, fl
 // augmented value is stored as BF16 hi(x) = rn(x), |x - hi(x)| <= 2^-9 |x|,
 // so each product hi(a) hi(b) is within (2 * 2^-9 + 2^-18) |a| |b| of a b,
 // at most 1.003 * 2^-8 * 1.415 ||p|| ||u|| over a row (sum |a_i||b_i| <=
-// ||a|| ||b||); the matrix-core FP32 sums of <= 64 exact BF16 products add
-// gamma_64 (2^-18) of the same, and the FP32 rounding of W x (2^-24
-// relative) is far below; the slack column hi(||p||) hi(s ||u||) gives at
-// least s (1 - 2^-9)^2 ||p|| ||u||: s = 2^-7 covers 1.43 * 2^-8 with room.
-// The absolute slack covers BF16 and FP32 underflow (norms are below 2^60),
-// subnormal operands flushed by the matrix cores included: each such term
-// is below 2^-126 * 2^60 * 1.42 in magnitude.
+// ||a|| ||b|| <= 1.415 ||p|| ||u||); the matrix-core FP32 sums of <= 272
+// exact BF16 products add gamma_272 (< 2^-15.9) of the same, and the FP32
+// rounding of W x (2^-24 relative) is far below: 1.43 * 2^-8 in all.  The
+// slack column hi(||p||) hi(s ||u||) gives at least s (1 - 2^-9)^2 ||p||
+// ||u||: s = 2^-7 covers that with room.  The absolute slack covers BF16
+// and FP32 underflow (norms are below 2^60), subnormal operands flushed by
+// the matrix cores included: the flushed terms of a row sum to at most
+// 2^-126 sqrt(ka) 1.42 * 2^60 < 2^-61, and products that underflow FP32 to
+// far less.
 constexpr float BOUND_SLACK = 0x1p-7f;
 constexpr float BOUND_ABS_SLACK = 0x1p-60f;
 
 // Stage (c), second part: the Eq. (3)/(6) bound count of every item (norm
 // order) into `uscore`, over the users of its prefix (users' augmented rows
-// in rho order; the items' rows must already be in B.Pa).
+// in rho order; the items' rows must already be in B.Pa).  Wd: the rotation
+// (dp x d), NULL for the identity (dp = d).
 void run_bound(const float *U, const PrefixLayout &X, const BoundLayout &B, const double *Wd,
-               int64_t n, int64_t m, int64_t mpad, int d, unsigned long long *pairs,
+               int dp, int64_t n, int64_t m, int64_t mpad, int d, unsigned long long *pairs,
                hipEvent_t e0, hipEvent_t e1, int32_t *uscore, hipStream_t st) {
-    const int dp = dprime(d), ka = aug_len(d);
+    const int ka = aug_len(dp);
     launch_rotate_aug(U, X.uperm, n, n, d, Wd, dp, ka, BOUND_SLACK, B.Ua, st);
     BoundArgs ba{};
     ba.ka = ka;
@@ -1005,6 +1019,12 @@ rmips_status rmips_set_batch(rmips_ctx *ctx, int32_t first, int32_t max) {
     return RMIPS_OK;
 }
 
+rmips_status rmips_set_dprime(rmips_ctx *ctx, int32_t dprime) {
+    if (!ctx || dprime < 0 || dprime > DPRIME_ROT_MAX) return RMIPS_EINVAL;
+    ctx->dprime = dprime;
+    return RMIPS_OK;
+}
+
 rmips_status rmips_set_bound_output(rmips_ctx *ctx, int32_t *uscore) {
     if (!ctx) return RMIPS_EINVAL;
     ctx->bound_out = uscore;
@@ -1210,7 +1230,7 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     // not depend on tau: it goes to the host first, and the host computes
     // its eigenvectors while the GPU runs stage (a).  With d' = d any
     // orthonormal basis gives the same bound: the identity.
-    const int dp = dprime(d), ka = aug_len(d);
+    const int dp = dprime(ctx, d), ka = aug_len(dp);
     const bool rotate = dp < d;
     std::vector<double> G, W;
     if (rotate) {
@@ -1239,7 +1259,7 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
         HIPTRY(hipMemcpyAsync(L.W, W.data(), sizeof(double) * dp * d, hipMemcpyHostToDevice, st));
     const double *Wd = rotate ? L.W : nullptr;  // nullptr: the identity
     launch_rotate_aug(P, L.T.perm, m, L.T.mpad, d, Wd, dp, ka, 1.0f, L.B.Pa, st);
-    run_bound(U, L.X, L.B, Wd, n, m, L.T.mpad, d, ctr + 2, ev[6], ev[7], L.uscore, st);
+    run_bound(U, L.X, L.B, Wd, dp, n, m, L.T.mpad, d, ctr + 2, ev[6], ev[7], L.uscore, st);
     launch_invert_perm(L.T.perm, m, L.C.inv, st);
     if (ctx->bound_out) launch_gather_i32(L.uscore, L.C.inv, m, ctx->bound_out, st);
     HIPTRY(hipGetLastError());
@@ -1331,8 +1351,9 @@ static rmips_status check_index_header(rmips_ctx *ctx, const int32_t *hdr_dev, i
                           hipMemcpyDeviceToHost, ctx->stream));
     HIPTRY(hipStreamSynchronize(ctx->stream));
     int32_t want[INDEX_HDR_WORDS];
-    index_header(n, m, d, kmax, prec, want);
-    if (std::memcmp(ctx->h_status + H_HDR, want, sizeof(want)) != 0)
+    const int32_t *got = ctx->h_status + H_HDR;
+    index_header(n, m, d, kmax, prec, got[INDEX_HDR_DPRIME], want);
+    if (std::memcmp(got, want, sizeof(want)) != 0)
         return fail(ctx, RMIPS_EINVAL,
                     "index not built by rmips_index_build with these n, m, d, kmax, precision");
     return RMIPS_OK;
@@ -1376,7 +1397,7 @@ rmips_status rmips_index_build(rmips_ctx *ctx, const float *U, int64_t n, const 
     index_build_plan(prec, n, m, d, kmax, ctx->cap_override, I, X, B, cw);
     ThreshLayout &T = I.T;
     const ErrConst ec = err_const(T.D, d);
-    const int dp = dprime(d), ka = aug_len(d);
+    const int dp = dprime(ctx, d), ka = aug_len(dp);
     const bool rotate = dp < d;
     // no valid header until the build has succeeded
     HIPTRY(hipMemsetAsync(I.hdr, 0, sizeof(int32_t) * INDEX_HDR_WORDS, st));
@@ -1411,7 +1432,7 @@ rmips_status rmips_index_build(rmips_ctx *ctx, const float *U, int64_t n, const 
     for (int k = 1; k <= kmax; ++k) {
         launch_kth_column(I.topv, I.topk, n, kmax, k, X.tau, X.tau_id, st);
         run_prefix(T, X, n, m, ec.c2, st, false);
-        run_bound(U, X, B, Wd, n, m, T.mpad, d, nullptr, nullptr, nullptr,
+        run_bound(U, X, B, Wd, dp, n, m, T.mpad, d, nullptr, nullptr, nullptr,
                   I.table + (size_t)(k - 1) * m, st);
     }
     HIPTRY(hipGetLastError());
@@ -1422,7 +1443,7 @@ rmips_status rmips_index_build(rmips_ctx *ctx, const float *U, int64_t n, const 
     if (ctx->h_status[0] != 0) return fail(ctx, RMIPS_ENONFINITE, BAD_INPUT);
     int32_t *hdr = ctx->h_status + H_HDR;  // pinned
     int32_t want[INDEX_HDR_WORDS];
-    index_header(n, m, d, kmax, prec, want);
+    index_header(n, m, d, kmax, prec, dp, want);
     std::memcpy(hdr, want, sizeof(want));
     HIPTRY(hipMemcpyAsync(I.hdr, hdr, sizeof(want), hipMemcpyHostToDevice, st));
     HIPTRY(hipStreamSynchronize(st));

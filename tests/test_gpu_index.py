@@ -25,11 +25,11 @@ def _g(x):
     return torch.from_numpy(np.ascontiguousarray(x)).to(_dev())
 
 
-def _check_index(U, P, prec, ks, Ns, kmax=KMAX):
+def _check_index(U, P, prec, ks, Ns, kmax=KMAX, dprime=None):
     import paper_2504_13445_amd as rm
     n, m = U.shape[0], P.shape[0]
     topv, topk = orc.kmips_table_c(U, P, kmax)
-    idx = rm.Index(_g(U), _g(P), kmax, prec)
+    idx = rm.Index(_g(U), _g(P), kmax, prec, dprime=dprime)
     prev = None
     for k in range(1, kmax + 1):
         score = orc.histogram_scores(topk[:, :k], m)
@@ -66,11 +66,13 @@ def test_index_mf_workload(prec):
     _check_index(U, P, prec, (1, 10, 25), (10,))
 
 
-def test_index_rotation_and_ties():
-    # d > 62: the bound table is built on the rotated, split rows; integer
-    # inputs with duplicated items give exact ties everywhere
+@pytest.mark.parametrize("dprime", [None, 62])
+def test_index_rotation_and_ties(dprime):
+    # d = 200: the bound table on the full rows (d' = d) and on the rotated,
+    # split rows (d' = 62); integer inputs with duplicated items give exact
+    # ties everywhere
     U, P = synth.make_config(3, n=3000, m=900)
-    _check_index(U, P, "bf16", (1, 7, 25), (10,))
+    _check_index(U, P, "bf16", (1, 7, 25), (10,), dprime=dprime)
     rng = np.random.default_rng(4)
     Pi = rng.integers(-2, 3, size=(90, 5)).astype(np.float32)
     Pi[45:] = Pi[:45]

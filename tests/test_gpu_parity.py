@@ -256,25 +256,36 @@ def test_topn_forced_fallback_and_small_batches(prec):
 
 
 def _bound_case(shape):
-    if shape == "d50":        # d' = d: identity rotation
+    if shape == "d50":
         return synth.make_config(1, n=3000, m=2000), 10
-    if shape == "d100":       # d' = 62 < d: rotation onto the users' dominant eigenspace
+    if shape == "d100":
         return synth.make_config(2, n=4000, m=1500), 20
     if shape == "d200":
         return synth.make_config(3, n=3000, m=1000), 10
+    if shape in ("d240", "d256"):
+        # the longest augmented rows (ka = 256 and 272: the bound kernel's
+        # two- and one-step read groups)
+        d = int(shape[1:])
+        rng = np.random.default_rng(d)
+        U = rng.standard_normal((2000, d)) * rng.lognormal(0.0, 0.25, (2000, 1))
+        P = rng.standard_normal((700, d)) * rng.lognormal(0.0, 0.8, (700, 1))
+        return (U.astype(np.float32), P.astype(np.float32)), 10
     # subnormal range: the bound's absolute slack
     (U, P), k = synth.make_config(2, n=2000, m=800), 10
     return (U * np.float32(1e-19), P * np.float32(1e-19)), k
 
 
-@pytest.mark.parametrize("shape", ["d50", "d100", "d200", "tiny_values"])
-def test_topn_bound_counts_dominate_scores(shape):
+@pytest.mark.parametrize("dprime", [0, 10, 62])
+@pytest.mark.parametrize("shape", ["d50", "d100", "d200", "d240", "d256", "tiny_values"])
+def test_topn_bound_counts_dominate_scores(shape, dprime):
     """The Eq. (3)/(6) bound count of every item (BF16 products with a
-    certified slack) is at least its exact score (Theorem 2); with d' = d it
-    counts no user whose exact value is below tau_u by more than twice the
-    relative slack 2^-7 of ||u|| ||p|| (the bound is then the inner product
-    plus that slack, up to BF16 rounding that the slack covers)."""
-    _say("topn bound counts", shape)
+    certified slack) is at least its exact score (Theorem 2), with d' = d
+    (dprime 0: no rotation) and with the users' top-d' eigenvectors (d' = 10,
+    62); with d' = d it counts no user whose exact value is below tau_u by
+    more than twice the relative slack 2^-7 of ||u|| ||p|| (the bound is then
+    the inner product plus that slack, up to BF16 rounding that the slack
+    covers).  The top-N is the same for every d'."""
+    _say("topn bound counts", shape, "dprime", dprime)
     rm = _rm()
     (U, P), k = _bound_case(shape)
     m = P.shape[0]
@@ -282,13 +293,13 @@ def test_topn_bound_counts_dominate_scores(shape):
     score = orc.histogram_scores(tk, m)
     us = torch.zeros(m, dtype=torch.int32, device=_dev())
     ri, rs = orc.topn_from_scores(score, 10)
-    ids, sc, _ = rm.topn(_g(U), _g(P), k, 10, prec="bf16", bound_out=us)
+    ids, sc, _ = rm.topn(_g(U), _g(P), k, 10, prec="bf16", bound_out=us, dprime=dprime)
     assert ids.tolist() == ri.tolist() and sc.tolist() == rs.tolist()
     us = us.cpu().numpy().astype(np.int64)
     bad = np.nonzero(us < score)[0]
     assert bad.size == 0, (bad[:10], us[bad[:10]], score[bad[:10]])
     assert us.max() <= U.shape[0]
-    if shape == "d50":
+    if dprime == 0:
         U64, P64 = U.astype(np.float64), P.astype(np.float64)
         V = U64 @ P64.T
         slack = 2.0 ** -6 * np.linalg.norm(U64, axis=1)[:, None] * np.linalg.norm(P64, axis=1)
