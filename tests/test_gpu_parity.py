@@ -308,6 +308,30 @@ def test_topn_bound_counts_dominate_scores(shape, dprime):
         assert over.size == 0, (over[:10], us[over[:10]], reach[over[:10]])
 
 
+@pytest.mark.parametrize("d", [20, 33, 70, 130, 150, 190, 230])
+def test_topn_bound_counts_every_row_length(d):
+    """The bound kernels of every augmented row length in between (ka = 32
+    to 240: register-resident users, LDS stages of 256 and 128 users, the
+    pipelined and the grouped-read forms): bound counts at or above the exact
+    scores and the exact top-N, with d' = d."""
+    _say("topn bound counts, d", d)
+    rm = _rm()
+    rng = np.random.default_rng(1000 + d)
+    U = (rng.standard_normal((1500, d)) * rng.lognormal(0.0, 0.25, (1500, 1))).astype(np.float32)
+    P = (rng.standard_normal((1100, d)) * rng.lognormal(0.0, 0.8, (1100, 1))).astype(np.float32)
+    m = P.shape[0]
+    _, _, tk = orc.kmips_c(U, P, 10)
+    score = orc.histogram_scores(tk, m)
+    us = torch.zeros(m, dtype=torch.int32, device=_dev())
+    ri, rs = orc.topn_from_scores(score, 20)
+    ids, sc, _ = rm.topn(_g(U), _g(P), 10, 20, prec="bf16", bound_out=us)
+    assert ids.tolist() == ri.tolist() and sc.tolist() == rs.tolist()
+    us = us.cpu().numpy().astype(np.int64)
+    bad = np.nonzero(us < score)[0]
+    assert bad.size == 0, (bad[:10], us[bad[:10]], score[bad[:10]])
+    assert us.max() <= U.shape[0]
+
+
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("cap", [2, 4])
 def test_topn_refinement_passes(prec, cap):
