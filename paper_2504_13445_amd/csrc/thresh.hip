@@ -571,6 +571,29 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// The k-th largest of x[0..n) counting repetitions (-inf when n < k), by
+// rounds of the largest value below the previous round's, each counted with
+// its repetitions, until k values are reached: 2k passes over the list.
+__device__ float wave_kth_largest(const float *x, int n, int k, int lane) {
+    float prev = INFINITY, v = -INFINITY;
+    int acc = 0;
+    for (int r = 0; r < k && acc < k; ++r) {
+        float mx = -INFINITY;
+        for (int e = lane; e < n; e += 64) {
+            const float y = x[e];
+            mx = (y < prev) ? fmaxf(mx, y) : mx;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+        int c = 0;
+        for (int e = lane; e < n; e += 64) c += (x[e] == mx) ? 1 : 0;
+        acc += wave_sum(c);
+        prev = mx;
+        v = mx;
+    }
+    return acc >= k ? v : -INFINITY;
+}
+
 // One wave per user.  The lists of the user's splits are gathered into
 // LDS with lower and upper bounds vh -/+ E; L* = k-th largest lower bound.
 // A user whose lists overflowed is not resolved here: the k-th largest lower
@@ -672,23 +695,8 @@ void k_thresh_final(ThreshArgs a, int capT, int capP) {
                     if (rank == a.k - 1) Lstar[w] = x;
                 }
             } else {
-                float prev = INFINITY, Ls = -INFINITY;
-                int acc = 0;
-                for (int r = 0; r < a.k && acc < a.k; ++r) {
-                    float mx = -INFINITY;
-                    for (int e = lane; e < stored; e += 64) {
-                        const float x = lo[e];
-                        mx = (x < prev) ? fmaxf(mx, x) : mx;
-                    }
-#pragma unroll
-                    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
-                    int c = 0;
-                    for (int e = lane; e < stored; e += 64) c += (lo[e] == mx) ? 1 : 0;
-                    acc += wave_sum(c);
-                    prev = mx;
-                    Ls = mx;
-                }
-                if (lane == 0) Lstar[w] = acc >= a.k ? Ls : -INFINITY;
+                const float Ls = wave_kth_largest(lo, stored, a.k, lane);
+                if (lane == 0) Lstar[w] = Ls;
             }
         }
         wave_sync();
@@ -741,13 +749,18 @@ void k_thresh_final(ThreshArgs a, int capT, int capP) {
         // When only tau is asked for, a survivor whose lower bound exceeds the
         // upper bounds of all but at most k - 2 others ranks above the k-th
         // item; with A such survivors, tau is the (k - A)-th of the others, and
-        // only those are recomputed.
+        // only those are recomputed.  A survivor p is such another one when
+        // at least k upper bounds (its own included) reach lo[p], that is
+        // when lo[p] <= H_k, the k-th largest upper bound of the survivors
+        // (counted directly for short lists, where that is cheaper).
         const bool band = a.topk == nullptr;
         int *rid = cidx;
         if (work) {
             const int ns = nsurv[w];
             int nrec = ns;
             if (band) {
+                const bool direct = ns <= 128;
+                const float Hk = direct ? 0.0f : wave_kth_largest(hi, ns, a.k, lane);
                 int cntb = 0;
                 for (int p0 = 0; p0 < ns; p0 += 64) {
                     const int p = p0 + lane;
@@ -755,9 +768,13 @@ void k_thresh_final(ThreshArgs a, int capT, int capP) {
                     int id = 0;
                     if (p < ns) {
                         const float x = lo[p];
-                        int c = -1;  // the survivor itself
-                        for (int q = 0; q < ns; ++q) c += hi[q] >= x;
-                        unc = c > a.k - 2;
+                        if (direct) {
+                            int c = 0;
+                            for (int q = 0; q < ns; ++q) c += hi[q] >= x;
+                            unc = c >= a.k;
+                        } else {
+                            unc = x <= Hk;
+                        }
                         id = cidx[p];
                     }
                     const uint64_t bal = __ballot(unc);
