@@ -571,25 +571,76 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// Wave-wide maximum and sum by DPP steps (no LDS traffic): quad_perm
+// [1,0,3,2] and [2,3,0,1] combine the lanes of each quad, row_half_mirror
+// and row_mirror the quads of each row of 16, row_bcast:15 (rows 1, 3) and
+// row_bcast:31 (rows 2, 3) the rows; lane 63 then holds the result, read
+// back as a wave-uniform value.  Lanes left out of a step keep `old`, the
+// operation's identity.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_from(int identity, int v) {
+    return __builtin_amdgcn_update_dpp(identity, v, CTRL, ROWS, 0xf, false);
+}
+__device__ __forceinline__ float dpp_wave_max(float x) {
+    const int id = __float_as_int(-INFINITY);
+    x = fmaxf(x, __int_as_float(dpp_from<0xB1, 0xf>(id, __float_as_int(x))));
+    x = fmaxf(x, __int_as_float(dpp_from<0x4E, 0xf>(id, __float_as_int(x))));
+    x = fmaxf(x, __int_as_float(dpp_from<0x141, 0xf>(id, __float_as_int(x))));
+    x = fmaxf(x, __int_as_float(dpp_from<0x140, 0xf>(id, __float_as_int(x))));
+    x = fmaxf(x, __int_as_float(dpp_from<0x142, 0xa>(id, __float_as_int(x))));
+    x = fmaxf(x, __int_as_float(dpp_from<0x143, 0xc>(id, __float_as_int(x))));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
+__device__ __forceinline__ int dpp_wave_sum(int x) {
+    x += dpp_from<0xB1, 0xf>(0, x);
+    x += dpp_from<0x4E, 0xf>(0, x);
+    x += dpp_from<0x141, 0xf>(0, x);
+    x += dpp_from<0x140, 0xf>(0, x);
+    x += dpp_from<0x142, 0xa>(0, x);
+    x += dpp_from<0x143, 0xc>(0, x);
+    return __builtin_amdgcn_readlane(x, 63);
+}
+
 // The k-th largest of x[0..n) counting repetitions (-inf when n < k), by
 // rounds of the largest value below the previous round's, each counted with
-// its repetitions, until k values are reached: 2k passes over the list.
+// its repetitions, until k values are reached.  Lists of up to 64 KR values
+// are held in registers for the rounds (lane l: values l, l + 64, ...; the
+// -inf padding can only be counted once every value is taken, and then the
+// result is -inf anyway); longer ones are read from LDS in every round.
+constexpr int KTH_KR = 12;
 __device__ float wave_kth_largest(const float *x, int n, int k, int lane) {
     float prev = INFINITY, v = -INFINITY;
     int acc = 0;
-    for (int r = 0; r < k && acc < k; ++r) {
-        float mx = -INFINITY;
-        for (int e = lane; e < n; e += 64) {
-            const float y = x[e];
-            mx = (y < prev) ? fmaxf(mx, y) : mx;
-        }
+    if (n <= 64 * KTH_KR) {
+        float r[KTH_KR];
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
-        int c = 0;
-        for (int e = lane; e < n; e += 64) c += (x[e] == mx) ? 1 : 0;
-        acc += wave_sum(c);
-        prev = mx;
-        v = mx;
+        for (int j = 0; j < KTH_KR; ++j) r[j] = (lane + 64 * j < n) ? x[lane + 64 * j] : -INFINITY;
+        for (int rd = 0; rd < k && acc < k; ++rd) {
+            float mx = -INFINITY;
+#pragma unroll
+            for (int j = 0; j < KTH_KR; ++j) mx = (r[j] < prev) ? fmaxf(mx, r[j]) : mx;
+            mx = dpp_wave_max(mx);
+            int c = 0;
+#pragma unroll
+            for (int j = 0; j < KTH_KR; ++j) c += (r[j] == mx) ? 1 : 0;
+            acc += dpp_wave_sum(c);
+            prev = mx;
+            v = mx;
+        }
+    } else {
+        for (int rd = 0; rd < k && acc < k; ++rd) {
+            float mx = -INFINITY;
+            for (int e = lane; e < n; e += 64) {
+                const float y = x[e];
+                mx = (y < prev) ? fmaxf(mx, y) : mx;
+            }
+            mx = dpp_wave_max(mx);
+            int c = 0;
+            for (int e = lane; e < n; e += 64) c += (x[e] == mx) ? 1 : 0;
+            acc += dpp_wave_sum(c);
+            prev = mx;
+            v = mx;
+        }
     }
     return acc >= k ? v : -INFINITY;
 }
@@ -658,23 +709,39 @@ void k_thresh_final(ThreshArgs a, int capT, int capP) {
         if (valid && stored <= capT) {
             // entry g of the joined list (64 at a time, from every split
             // at once): split s = number of inclusive prefixes <= g, entry
-            // g - (prefix before s)
-            for (int g0 = 0; g0 < stored; g0 += 64) {
-                const int g = g0 + lane;
-                int sp = 0, before = 0;
-                for (int q = 0; q < a.nsplit; ++q) {
-                    const int pq = __builtin_amdgcn_readlane(pre, q);
-                    if (pq <= g) {
-                        sp = q + 1;
-                        before = pq;
+            // g - (prefix before s); FIN_GU rounds of loads are issued before
+            // their entries are stored, so that their latencies overlap
+            constexpr int FIN_GU = 4;
+            for (int g0 = 0; g0 < stored; g0 += 64 * FIN_GU) {
+                float2 cv[FIN_GU];  // (screened value, its bound E)
+                int ci[FIN_GU];
+#pragma unroll
+                for (int t = 0; t < FIN_GU; ++t) {
+                    const int g = g0 + 64 * t + lane;
+                    int sp = 0, before = 0;
+                    for (int q = 0; q < a.nsplit; ++q) {
+                        const int pq = __builtin_amdgcn_readlane(pre, q);
+                        if (pq <= g) {
+                            sp = q + 1;
+                            before = pq;
+                        }
+                    }
+                    cv[t] = make_float2(0.0f, 0.0f);
+                    ci[t] = 0;
+                    if (g < stored) {
+                        const int64_t e = (u * a.nsplit + sp) * a.cap + (g - before);
+                        cv[t] = a.cand[e];
+                        ci[t] = a.cand_id[e];
                     }
                 }
-                if (g < stored) {
-                    const int64_t e = (u * a.nsplit + sp) * a.cap + (g - before);
-                    const float2 cv = a.cand[e];  // (screened value, its bound E)
-                    lo[g] = cv.x - cv.y;
-                    hi[g] = cv.x + cv.y;
-                    cidx[g] = a.cand_id[e];
+#pragma unroll
+                for (int t = 0; t < FIN_GU; ++t) {
+                    const int g = g0 + 64 * t + lane;
+                    if (g < stored) {
+                        lo[g] = cv[t].x - cv[t].y;
+                        hi[g] = cv[t].x + cv[t].y;
+                        cidx[g] = ci[t];
+                    }
                 }
             }
         }
