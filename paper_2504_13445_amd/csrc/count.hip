@@ -39,10 +39,52 @@ constexpr int AMB_FLUSH = AMB_CAP / 2;   // list length that triggers a flush be
 constexpr int CNT_NW = 8;  // at most
 __host__ __device__ constexpr int count_waves(int nch) { return nch <= 16 ? 8 : 4; }
 
+// The wide-band precisions (e4m3, e2m3, e2m1) leave a large share of the
+// pairs ambiguous (about one in six at d = 200): their rechecks are taken
+// chunk by chunk with the chunk's FP32 user rows staged in LDS once, instead
+// of one user-row gather per pair.  A lane's ambiguous pairs of a chunk are
+// one 32-bit word (16 rows x two user columns) in LDS.
+__host__ __device__ constexpr bool count_staged(int prec) { return prec >= PREC_FP8; }
+__host__ __device__ inline int staged_stride(int D) { return D + 4; }  // floats per staged row
+
 size_t count_lds(int prec, int D) {
     const int ls = lds_row_bytes(prec, D);
-    return 2 * (size_t)(CNT_USERS * ls + LDS_GUARD) + AMB_CAP * sizeof(int2) +
-           32 * CNT_NW * sizeof(int) + 32;
+    size_t b = 2 * (size_t)(CNT_USERS * ls + LDS_GUARD) + AMB_CAP * sizeof(int2) +
+               32 * CNT_NW * sizeof(int) + 32;
+    if (count_staged(prec))
+        b += 64 * CNT_NW * sizeof(uint32_t) + (size_t)CNT_USERS * staged_stride(D) * sizeof(float) +
+             2 * 32 * CNT_NW * sizeof(int);
+    return b;
+}
+
+// u . p (ip64's arithmetic: FP64 fused multiply-adds in index order) with
+// u staged in LDS, 16-byte aligned; p's 16-byte vectors are read four at a
+// time.  Rows that are not whole vectors take one value at a time.
+__device__ __forceinline__ double ip64_staged(const float *ul, const float *__restrict__ p, int d) {
+    double acc = 0.0;
+    if ((d & 3) == 0 && (reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+        constexpr int RV = 4;
+        const float4 *u4 = reinterpret_cast<const float4 *>(ul);
+        const float4 *p4 = reinterpret_cast<const float4 *>(p);
+        const int d4 = d >> 2;
+        for (int i = 0; i < d4; i += RV) {
+            float4 y[RV];
+#pragma unroll
+            for (int j = 0; j < RV; ++j) y[j] = p4[i + j < d4 ? i + j : d4 - 1];
+#pragma unroll
+            for (int j = 0; j < RV; ++j) {
+                const bool ok = i + j < d4;
+                const float4 x = u4[ok ? i + j : d4 - 1];
+                acc = __fma_rn((double)(ok ? x.x : 0.f), (double)(ok ? y[j].x : 0.f), acc);
+                acc = __fma_rn((double)(ok ? x.y : 0.f), (double)(ok ? y[j].y : 0.f), acc);
+                acc = __fma_rn((double)(ok ? x.z : 0.f), (double)(ok ? y[j].z : 0.f), acc);
+                acc = __fma_rn((double)(ok ? x.w : 0.f), (double)(ok ? y[j].w : 0.f), acc);
+            }
+        }
+        return acc;
+    }
+    for (int i = 0; i < d; ++i) acc = __fma_rn((double)ul[i], (double)p[i], acc);
+    return acc;
 }
 
 // FP64 decision of one (item row, user) pair by the tie rule.
@@ -77,6 +119,16 @@ void k_count(CountArgs a) {
     int2 *amb = reinterpret_cast<int2 *>(Ush0 + 2 * bstride);
     int *cntl = reinterpret_cast<int *>(amb + AMB_CAP);
     int *ambn = cntl + CNT_ITEMS;
+    // (wide bands) the lanes' ambiguity words and the chunk's FP32 user
+    // rows, after the fixed part of count_lds (16-byte aligned)
+    constexpr bool STAGED = count_staged(PREC);
+    uint32_t *ambw = reinterpret_cast<uint32_t *>(smem8 + (2 * (size_t)bstride + AMB_CAP * sizeof(int2) +
+                                                           32 * CNT_NW * sizeof(int) + 32));
+    float *urow_s = reinterpret_cast<float *>(ambw + 64 * CNT_NW);
+    const int ustride = staged_stride(D);
+    // (wide bands) each item row's original row and tie id
+    int *orow_s = reinterpret_cast<int *>(urow_s + (size_t)CNT_USERS * ustride);
+    int *tie_s = orow_s + CNT_NW * 32;
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     // item-block-major order: the blocks of the longest prefixes start first
@@ -93,6 +145,20 @@ void k_count(CountArgs a) {
         load_half_row<NCH>(ia, reinterpret_cast<const uint8_t *>(a.Pq), row, ok, rowb, nch, lane);
     }
     if (tid < CNT_ITEMS) cntl[tid] = 0;
+    if constexpr (STAGED) {
+        if (tid < CNT_ITEMS) {
+            const int64_t it = ib + tid;
+            int orow = 0, tie = 0x7fffffff;
+            if (it < a.nb) {
+                const int64_t row = a.rows ? a.rows[it] : it;
+                orow = (int)(a.item_orig ? a.item_orig[row] : row);
+                tie = a.item_tie ? a.item_tie[row] : -1;
+                if (tie < 0) tie = 0x7fffffff;  // outside P: after every item of P
+            }
+            orow_s[tid] = orow;
+            tie_s[tid] = tie;
+        }
+    }
     if (tid == 0) *ambn = 0;
     if (tid < 2 * LDS_GUARD / 16) {
         const int g = tid / (LDS_GUARD / 16), e = tid % (LDS_GUARD / 16);
@@ -175,6 +241,7 @@ void k_count(CountArgs a) {
         }
     };
     int nall = 0;  // pairs listed (statistics)
+    int nst = 0;   // (wide bands) this thread's rechecks from staged rows
 
     // Phases: the two waves that share a SIMD work in opposite order
     // between the barriers.  An early wave multiplies chunk c and then
@@ -195,6 +262,9 @@ void k_count(CountArgs a) {
         int t = 0;
         if (lane == 0) t = atomicAdd(&simdc[simd_id()], 1);
         late = (__builtin_amdgcn_readfirstlane(t) & 1) != 0;  // uniform in the wave
+        // (wide bands: every wave classifies its chunk before the barrier,
+        // so that all the words of a chunk are there after it)
+        if (STAGED) late = false;
     }
     // the pending classification: products acc0/acc1 of the user columns
     // pus0 and pus0 + 32 with their thresholds
@@ -221,7 +291,25 @@ void k_count(CountArgs a) {
             cnt[i] += (v1 > e1) ? m1 : 0;
             anyamb |= (v0 == e0) | (v1 == e1);
         }
-        if (__ballot(anyamb) != 0ull) {
+        if constexpr (STAGED) {
+            // this lane's ambiguous pairs as one word, rechecked after the
+            // chunk's barrier (bit i: register i & 15 of block i >> 4)
+            uint32_t word = 0u;
+            if (__ballot(anyamb) != 0ull) {
+                uint32_t ambm0 = 0, ambm1 = 0;
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const float v0 = scaled_prec(PREC) ? acc0[i] * srow[i] : acc0[i];
+                    const float v1 = scaled_prec(PREC) ? acc1[i] * srow[i] : acc1[i];
+                    ambm0 |= (v0 == __builtin_amdgcn_fmed3f(v0, ptout0, ptin0)) ? (1u << i) : 0u;
+                    ambm1 |= (v1 == __builtin_amdgcn_fmed3f(v1, ptout1, ptin1)) ? (1u << i) : 0u;
+                }
+                ambm0 = c0 ? (ambm0 & rvalid) : 0u;
+                ambm1 = c1 ? (ambm1 & rvalid) : 0u;
+                word = ambm0 | (ambm1 << 16);
+            }
+            ambw[w * 64 + lane] = word;
+        } else if (__ballot(anyamb) != 0ull) {
             uint32_t ambm0 = 0, ambm1 = 0;
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
@@ -282,6 +370,36 @@ void k_count(CountArgs a) {
         if (nxt < nchunks) dma_wait();
         __syncthreads();
         buf ^= 1;
+        if constexpr (STAGED) {
+            // the chunk's rechecks: its users' FP32 rows staged once (a wave
+            // per row at a time), then each thread takes the word of the lane
+            // with its index, its items' original rows and tie ids from LDS
+            const uint32_t myw = ambw[tid];
+            if (__syncthreads_or(myw != 0u)) {
+                const int64_t u0 = ch * CNT_USERS;
+                for (int sl = w; sl < CNT_USERS; sl += NW) {
+                    if (u0 + sl >= ulen) break;
+                    const float *src = a.Uorig + (int64_t)a.us.uid[u0 + sl] * a.d;
+                    for (int i = lane; i < a.d; i += 64) urow_s[sl * ustride + i] = src[i];
+                }
+                __syncthreads();
+                uint32_t bits = myw;
+                const int wv = tid >> 6, ln = tid & 63;
+                while (bits != 0u) {
+                    const int i = __builtin_ctz(bits);
+                    bits &= bits - 1u;
+                    const int rl = wv * 32 + mfma32_row(i & 15, ln);
+                    const int sl = (ln & 31) + (i >= 16 ? 32 : 0);
+                    const int64_t usr = u0 + sl;
+                    const double v = ip64_staged(urow_s + sl * ustride,
+                                                 a.Porig + (int64_t)orow_s[rl] * a.d, a.d);
+                    if (in_topk(v, tie_s[rl], a.us.tau[usr], a.us.tau_id[usr]))
+                        atomicAdd(&cntl[rl], 1);
+                    ++nst;
+                }
+                __syncthreads();  // (the words and rows of the next chunk)
+            }
+        }
         // a long list is rechecked by the whole workgroup now, so that the
         // list rarely fills and rechecks rarely run inside one wave
         const int nq = *ambn;  // the same for all threads after the barrier
@@ -312,6 +430,11 @@ void k_count(CountArgs a) {
     }
     if (a.rechecks && tid == 0 && nall > 0)
         atomicAdd(reinterpret_cast<unsigned long long *>(a.rechecks), (unsigned long long)nall);
+    if constexpr (STAGED) {
+        const int ws = wave_sum(nst);
+        if (a.rechecks && lane == 0 && ws > 0)
+            atomicAdd(reinterpret_cast<unsigned long long *>(a.rechecks), (unsigned long long)ws);
+    }
 }
 
 template <int PREC>
