@@ -561,7 +561,7 @@ size_t final_entry_bytes() { return FIN_ENTRY_BYTES; }
 // recomputations per user handed from k_thresh_final to k_thresh_exact;
 // more, up to EXACT_WIDE, go to k_thresh_exact_wide
 constexpr int EXACT_SLOTS = 8;
-constexpr int EXACT_WIDE_J = 4;  // values per lane in k_thresh_exact_wide (even)
+constexpr int EXACT_WIDE_J = 16;  // values per lane in k_thresh_exact_wide
 constexpr int EXACT_WIDE = 64 * EXACT_WIDE_J;
 
 // Orders this wave's LDS accesses (every list of the final selection is
@@ -1000,20 +1000,24 @@ __global__ __launch_bounds__(256) void k_thresh_exact(ThreshArgs a) {
 }
 
 // The recomputations of users with more than EXACT_SLOTS (at most
-// EXACT_WIDE) values: a wave per user, each lane up to EXACT_WIDE_J values
-// in registers (lane l: values l, l + 64, ...); tau_u, the value of rank tgt
-// in the order (value desc, id asc), by tgt + 1 rounds of a wave-wide
-// maximum.  Each wave reads the metadata of 64 users at a time and takes the
-// wide ones in turn.
+// EXACT_WIDE) values: a wave per user, lane l computing values l, l + 64,
+// ... (up to EXACT_WIDE_J of them) into the wave's LDS slice; tau_u, the value
+// of rank tgt in the order (value desc, id asc), by tgt + 1 rounds of a
+// wave-wide maximum over the values not yet taken.  Each wave reads the
+// metadata of 64 users at a time and takes the wide ones in turn.
 template <bool LISTED>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 void k_thresh_exact_wide(ThreshArgs a) {
     __shared__ __align__(16) float urow_s[4][DMAX];
+    __shared__ double val_s[4][EXACT_WIDE];
+    __shared__ int id_s[4][EXACT_WIDE];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int nw = blockDim.x >> 6;
     const int64_t nlist = LISTED ? (int64_t)*a.ulist_cnt : a.n;
     const int64_t capU = (int64_t)a.nsplit * a.cap;
     float *ul = urow_s[w];
+    double *vw = val_s[w];
+    int *iw = id_s[w];
     for (int64_t c0 = ((int64_t)blockIdx.x * nw + w) * 64; c0 < nlist;
          c0 += (int64_t)gridDim.x * nw * 64) {
         const int64_t pos = c0 + lane;
@@ -1033,36 +1037,36 @@ void k_thresh_exact_wide(ThreshArgs a) {
             const int nrec = mt >> 8, tgt = mt & 255;
             const int32_t *ids = a.cand_id + u * capU;
             const float *urow = a.U + u * a.d;
-            wave_sync();  // the previous user's row is no longer read
+            wave_sync();  // the previous user's row and values are no longer read
             for (int i = lane; i < a.d; i += 64) ul[i] = urow[i];
             wave_sync();
-            double v[EXACT_WIDE_J];
-            int id[EXACT_WIDE_J];
-            uint32_t avail = 0u;  // bit j: value j held and not yet taken
-#pragma unroll
-            for (int j = 0; j < EXACT_WIDE_J; ++j) {
+            uint32_t avail = 0u;  // bit j: value lane + 64 j held and not yet taken
+            for (int j = 0; j < EXACT_WIDE_J && 64 * j < nrec; ++j) {
                 const int q = lane + 64 * j;
-                v[j] = -INFINITY;
-                id[j] = 0;
-                if (64 * j < nrec && q < nrec) {
-                    id[j] = ids[q];
-                    v[j] = ip64_lds_user(ul, urow, a.P + (int64_t)id[j] * a.d, a.d);
+                if (q < nrec) {
+                    const int id = ids[q];
+                    vw[q] = ip64_lds_user(ul, urow, a.P + (int64_t)id * a.d, a.d);
+                    iw[q] = id;
                     avail |= 1u << j;
                 }
             }
+            // (each lane reads back only the values it wrote)
+            const int jn = (nrec + 63) / 64;
             double bv = -INFINITY;
             int bi = 0x7fffffff;
             for (int r = 0; r <= tgt; ++r) {
                 // this lane's best value not yet taken, then the wave's
                 double lv = -INFINITY;
                 int li = 0x7fffffff, lj = -1;
-#pragma unroll
-                for (int j = 0; j < EXACT_WIDE_J; ++j) {
-                    const bool better = ((avail >> j) & 1u) &&
-                                        (lj < 0 || v[j] > lv || (v[j] == lv && id[j] < li));
-                    lv = better ? v[j] : lv;
-                    li = better ? id[j] : li;
-                    lj = better ? j : lj;
+                for (int j = 0; j < jn; ++j) {
+                    if (!((avail >> j) & 1u)) continue;
+                    const double x = vw[lane + 64 * j];
+                    const int xi = iw[lane + 64 * j];
+                    if (lj < 0 || x > lv || (x == lv && xi < li)) {
+                        lv = x;
+                        li = xi;
+                        lj = j;
+                    }
                 }
                 bv = lv;
                 bi = li;
