@@ -662,9 +662,7 @@ __global__ __launch_bounds__(64 * BLW) __attribute__((amdgpu_waves_per_eu(2)))
 void k_bound_lds(BoundArgs a) {
     constexpr int TI = 2, BI = 32 * TI * BLW, RW = 2 * KS, LSL = RW + 1;  // LSL: LDS row slots
     constexpr int BL_USERS = bl_users(KS);
-    // a second set of products in flight while one is counted, where the
-    // registers allow it (the items' rows take 8 KS of the 256)
-    constexpr bool PIPE = KS <= 11;
+    static_assert(KS <= 11, "longer rows take k_bound16");
     // two stage buffers of user rows, then their thresholds (dynamic LDS,
     // bound_lds_bytes(KS))
     extern __shared__ __align__(16) uint8_t smem_b[];
@@ -732,11 +730,9 @@ void k_bound_lds(BoundArgs a) {
         const int64_t nx = j + a.nsplit;
         if (nx < nblk) stage(nx, buf ^ 1);  // the other buffer was last read before the barrier
         const uint4 *U = ush[buf];
-        // column blocks of 32 users: with PIPE, the products of block cb run
-        // while the counts of block cb - 1 (for cb = 0: the previous stage's
-        // last block) are taken, one product and a few compares at a time;
-        // without, each block is counted after its products (the other wave
-        // of the SIMD multiplies meanwhile)
+        // column blocks of 32 users: the products of block cb run while the
+        // counts of block cb - 1 (for cb = 0: the previous stage's last
+        // block) are taken, one product and a few compares at a time
 #pragma unroll
         for (int cb = 0; cb < BL_USERS / 32; ++cb) {
             const int ul = 32 * cb + col;
@@ -750,68 +746,28 @@ void k_bound_lds(BoundArgs a) {
             f32x16 nc[TI];
 #pragma unroll
             for (int t = 0; t < TI; ++t) nc[t] = f32x16{0};
-            if constexpr (PIPE) {
 #pragma unroll
-                for (int q = 0; q < KS; ++q) {
-                    const bf16x8 yh = __builtin_bit_cast(bf16x8, U[ul * LSL + 2 * q + h]);
-#pragma unroll
-                    for (int t = 0; t < TI; ++t)
-                        nc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t][q], yh, nc[t], 0, 0, 0);
-                }
-            } else {
-                // the user row in groups of BL_G steps: the reads of group g + 1
-                // are issued after the first step of group g, so their latency
-                // hides behind the group's other products (the scheduling
-                // fences keep that order)
-                constexpr int BL_G = KS <= 14 ? 3 : KS <= 16 ? 2 : 1, NG = (KS + BL_G - 1) / BL_G;
-                bf16x8 yg[2][BL_G];
-                auto rd = [&](int g, bf16x8 (&y)[BL_G]) {
-#pragma unroll
-                    for (int e = 0; e < BL_G; ++e)
-                        if (g * BL_G + e < KS)
-                            y[e] = __builtin_bit_cast(bf16x8, U[ul * LSL + 2 * (g * BL_G + e) + h]);
-                };
-                auto mm = [&](int q, const bf16x8 &y) {
-#pragma unroll
-                    for (int t = 0; t < TI; ++t)
-                        nc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t][q], y, nc[t], 0, 0, 0);
-                };
-                rd(0, yg[0]);
-#pragma unroll
-                for (int g = 0; g < NG; ++g) {
-                    __builtin_amdgcn_sched_barrier(0);
-                    mm(g * BL_G, yg[g & 1][0]);
-                    __builtin_amdgcn_sched_barrier(0);
-                    if (g + 1 < NG) rd(g + 1, yg[(g + 1) & 1]);
-                    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                    for (int e = 1; e < BL_G; ++e)
-                        if (g * BL_G + e < KS) mm(g * BL_G + e, yg[g & 1][e]);
-                }
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            if constexpr (PIPE) {
+            for (int q = 0; q < KS; ++q) {
+                const bf16x8 yh = __builtin_bit_cast(bf16x8, U[ul * LSL + 2 * q + h]);
 #pragma unroll
                 for (int t = 0; t < TI; ++t)
-#pragma unroll
-                    for (int i = 0; i < 16; ++i) cnt[t][i] += (pc[t][i] >= tprev) ? vprev : 0;
-                // the counts (about 72 vector instructions) spread over the products
-                constexpr int NPROD = KS * TI, NV = (72 + NPROD - 1) / NPROD;
-#pragma unroll
-                for (int g = 0; g < NPROD; ++g) {
-                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one product
-                    __builtin_amdgcn_sched_group_barrier(0x002, NV, 0);  // vector ops
-                }
-#pragma unroll
-                for (int t = 0; t < TI; ++t) pc[t] = nc[t];
-                tprev = tl;
-                vprev = vm;
-            } else {
-#pragma unroll
-                for (int t = 0; t < TI; ++t)
-#pragma unroll
-                    for (int i = 0; i < 16; ++i) cnt[t][i] += (nc[t][i] >= tl) ? vm : 0;
+                    nc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[t][q], yh, nc[t], 0, 0, 0);
             }
+#pragma unroll
+            for (int t = 0; t < TI; ++t)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) cnt[t][i] += (pc[t][i] >= tprev) ? vprev : 0;
+            // the counts (about 72 vector instructions) spread over the products
+            constexpr int NPROD = KS * TI, NV = (72 + NPROD - 1) / NPROD;
+#pragma unroll
+            for (int g = 0; g < NPROD; ++g) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one product
+                __builtin_amdgcn_sched_group_barrier(0x002, NV, 0);  // vector ops
+            }
+#pragma unroll
+            for (int t = 0; t < TI; ++t) pc[t] = nc[t];
+            tprev = tl;
+            vprev = vm;
         }
         // the counts are taken before the barrier (not moved past it)
 #pragma unroll
@@ -823,12 +779,10 @@ void k_bound_lds(BoundArgs a) {
         __syncthreads();
         buf ^= 1;
     }
-    if constexpr (PIPE) {
 #pragma unroll
-        for (int t = 0; t < TI; ++t)
+    for (int t = 0; t < TI; ++t)
 #pragma unroll
-            for (int i = 0; i < 16; ++i) cnt[t][i] += (pc[t][i] >= tprev) ? vprev : 0;
-    }
+        for (int i = 0; i < 16; ++i) cnt[t][i] += (pc[t][i] >= tprev) ? vprev : 0;
 #pragma unroll
     for (int t = 0; t < TI; ++t)
 #pragma unroll
@@ -843,25 +797,171 @@ void k_bound_lds(BoundArgs a) {
     }
 }
 
-__host__ __device__ constexpr int bound_items(int ks) { return ks >= 3 ? 64 * BLW : 32 * bound_tiles(ks); }
+// The longest rows (ka = 32 KT > 176, KT = 6..9 steps of 32 terms): the
+// 16x16x32 matrix-core step, so that a wave's items (48: three tiles of 16
+// rows) take 12 KT registers and, up to KT = 7, three waves fit on a SIMD (a
+// workgroup of 12 waves, 576 items; two waves and 384 items for longer
+// rows).  User stages of 128 rows are copied into LDS as in k_bound_lds.  Operand layout of v_mfma_f32_16x16x32_bf16: lane l feeds
+// row (or column) l % 16 with terms 8 (l / 16) .. 8 (l / 16) + 7 of the step,
+// and holds result rows 4 (l / 16) + i (i = 0..3) of column l % 16.  Each
+// 32-user block is counted right after its products (the other waves of the
+// SIMD multiply meanwhile).
+__host__ __device__ constexpr int b16_waves(int kt) { return kt <= 7 ? 12 : 8; }  // per workgroup
+constexpr int B16_TI = 3;       // 16-row item tiles per wave
+constexpr int B16_USERS = 128;  // users per stage
+constexpr size_t bound16_lds_bytes(int kt) {
+    return 2 * (size_t)B16_USERS * (4 * kt + 1) * 16 + 2 * (size_t)B16_USERS * 4;
+}
+
+template <int KT>
+__global__ __launch_bounds__(64 * b16_waves(KT)) __attribute__((amdgpu_waves_per_eu(b16_waves(KT) / 4)))
+void k_bound16(BoundArgs a) {
+    constexpr int B16_W = b16_waves(KT);
+    constexpr int BI = 16 * B16_TI * B16_W, RW = 4 * KT, LSL = RW + 1;  // LSL: LDS row slots
+    extern __shared__ __align__(16) uint8_t smem_b[];
+    uint4 (*ush)[B16_USERS * LSL] = reinterpret_cast<uint4 (*)[B16_USERS * LSL]>(smem_b);
+    float (*tsh)[B16_USERS] = reinterpret_cast<float (*)[B16_USERS]>(smem_b + 2 * B16_USERS * LSL * 16);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int c16 = lane & 15, kq = lane >> 4;  // row / column, term block of a step
+    const int64_t ib = (int64_t)(blockIdx.x / a.nsplit) * BI;
+    const int split = (int)(blockIdx.x % a.nsplit);
+    // this wave's items: rows ib + 48 w + 16 t + c16, term block kq of each step
+    bf16x8 ah[B16_TI][KT];
+#pragma unroll
+    for (int t = 0; t < B16_TI; ++t) {
+        const int64_t r = ib + 48 * w + 16 * t + c16;
+#pragma unroll
+        for (int q = 0; q < KT; ++q) {
+            uint4 x = make_uint4(0, 0, 0, 0);
+            if (r < a.mpad) x = a.Pb[r * RW + 4 * q + kq];
+            ah[t][q] = __builtin_bit_cast(bf16x8, x);
+        }
+    }
+    // counts per item row held by this lane: rows 16 t + 4 kq + i
+    int cnt[B16_TI][4];
+#pragma unroll
+    for (int t = 0; t < B16_TI; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) cnt[t][i] = 0;
+
+    const int64_t ulen = a.cs[ib];  // largest prefix of the block (norm order)
+    const int64_t nblk = (ulen + B16_USERS - 1) / B16_USERS;
+    const uint32_t magic = slot_magic(RW);
+    // stage j: users [128 j, 128 (j + 1)) in groups of 64 rows (rows past
+    // the prefix repeat its last user, groups wholly past it are not copied:
+    // only the columns' validity bits keep them out of the counts) and their
+    // thresholds
+    auto stage = [&](int64_t j, int b) {
+#pragma unroll
+        for (int g = 0; g < B16_USERS / 64; ++g) {
+            const int64_t u0 = j * B16_USERS + 64 * g;
+            const int64_t left = ulen - u0;
+            if (left <= 0) break;
+            const int rlast = (int)((left < 64 ? left : 64) - 1);
+            rows_dma(reinterpret_cast<const uint8_t *>(a.Ub + u0 * RW), RW * 16, RW, magic, rlast,
+                     reinterpret_cast<uint8_t *>(ush[b] + 64 * g * LSL), w, B16_W, lane);
+            if (w == B16_W - 1) dma4(a.tau_lo + u0 + (lane < rlast ? lane : rlast), tsh[b] + 64 * g);
+        }
+    };
+    int64_t j = split;
+    int buf = 0;
+    if (j < nblk) stage(j, 0);
+    dma_wait();
+    __syncthreads();
+    int64_t npairs = 0;  // statistics: users of this workgroup's stages
+    for (; j < nblk; j += a.nsplit) {
+        const int64_t nx = j + a.nsplit;
+        if (nx < nblk) stage(nx, buf ^ 1);  // the other buffer was last read before the barrier
+        const uint4 *U = ush[buf];
+#pragma unroll
+        for (int cb = 0; cb < B16_USERS / 32; ++cb) {
+            // the two 16-user columns of this block held by this lane, their
+            // validity (explicit, not a masking value) and thresholds (read
+            // for every lane, so that the block has no branch)
+            int vm[2];
+            float tl[2];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int ul = 32 * cb + 16 * c + c16;
+                vm[c] = (j * B16_USERS + ul < ulen) ? 1 : 0;
+                tl[c] = float_pred(tsh[buf][ul] - a.abs_slack);
+            }
+            f32x4 acc[B16_TI][2];
+#pragma unroll
+            for (int t = 0; t < B16_TI; ++t) acc[t][0] = acc[t][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int q = 0; q < KT; ++q) {
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const bf16x8 yb = __builtin_bit_cast(
+                        bf16x8, U[(32 * cb + 16 * c + c16) * LSL + 4 * q + kq]);
+#pragma unroll
+                    for (int t = 0; t < B16_TI; ++t)
+                        acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[t][q], yb, acc[t][c], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < B16_TI; ++t)
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) cnt[t][i] += (acc[t][c][i] >= tl[c]) ? vm[c] : 0;
+        }
+        // the counts are taken before the barrier (not moved past it)
+#pragma unroll
+        for (int t = 0; t < B16_TI; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) asm volatile("" : "+v"(cnt[t][i]));
+        npairs += (ulen - j * B16_USERS < B16_USERS) ? (ulen - j * B16_USERS) : B16_USERS;
+        if (nx < nblk) dma_wait();
+        __syncthreads();
+        buf ^= 1;
+    }
+    // each row's count: the sum over the 16 lanes of its term block
+#pragma unroll
+    for (int t = 0; t < B16_TI; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            int x = cnt[t][i];
+#pragma unroll
+            for (int o = 8; o > 0; o >>= 1) x += __shfl_xor(x, o);
+            const int64_t it = ib + 48 * w + 16 * t + 4 * kq + i;
+            if (c16 == 0 && it < a.m) a.partial[(int64_t)split * a.m + it] = x;
+        }
+    if (a.pairs && tid == 0 && npairs > 0) {
+        const int64_t rows = (a.m - ib < BI) ? (a.m - ib) : BI;
+        atomicAdd(a.pairs, (unsigned long long)(rows * npairs));
+    }
+}
+
+__host__ __device__ constexpr int bound_items(int ks) {
+    return ks >= 12 ? 16 * B16_TI * b16_waves(ks / 2) : ks >= 3 ? 64 * BLW : 32 * bound_tiles(ks);
+}
 
 void launch_bound(const BoundArgs &a, hipStream_t st) {
     auto go = [&](auto ks) {
         constexpr int KS = decltype(ks)::value, BI = bound_items(KS);
         const unsigned g = (unsigned)((a.m + BI - 1) / BI * a.nsplit);
         RMIPS_PROF(st, "k_bound");
-        if constexpr (KS >= 3) k_bound_lds<KS><<<g, 64 * BLW, bound_lds_bytes(KS), st>>>(a);
-        else k_bound<KS><<<g, 64 * BW, 0, st>>>(a);
+        if constexpr (KS >= 12) {
+            static_assert(KS % 2 == 0, "rows past 176 terms come in steps of 32");
+            k_bound16<KS / 2><<<g, 64 * b16_waves(KS / 2), bound16_lds_bytes(KS / 2), st>>>(a);
+        } else if constexpr (KS >= 3) {
+            k_bound_lds<KS><<<g, 64 * BLW, bound_lds_bytes(KS), st>>>(a);
+        } else {
+            k_bound<KS><<<g, 64 * BW, 0, st>>>(a);
+        }
     };
-    // ka = 16 KS <= 272 (d' <= 256 values and two more columns)
+    // ka = 16 KS: KS <= 11, or an even KS up to 18 (rows past 176 terms are
+    // padded to a multiple of 32)
     switch (a.ka / 16) {
 #define RMIPS_BOUND_KS(K) case K: go(std::integral_constant<int, K>{}); break;
         RMIPS_BOUND_KS(1) RMIPS_BOUND_KS(2) RMIPS_BOUND_KS(3) RMIPS_BOUND_KS(4)
         RMIPS_BOUND_KS(5) RMIPS_BOUND_KS(6) RMIPS_BOUND_KS(7) RMIPS_BOUND_KS(8)
         RMIPS_BOUND_KS(9) RMIPS_BOUND_KS(10) RMIPS_BOUND_KS(11) RMIPS_BOUND_KS(12)
-        RMIPS_BOUND_KS(13) RMIPS_BOUND_KS(14) RMIPS_BOUND_KS(15) RMIPS_BOUND_KS(16)
+        RMIPS_BOUND_KS(14) RMIPS_BOUND_KS(16)
 #undef RMIPS_BOUND_KS
-    default: go(std::integral_constant<int, 17>{}); break;
+    default: go(std::integral_constant<int, 18>{}); break;
     }
 }
 

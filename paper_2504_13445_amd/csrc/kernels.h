@@ -99,7 +99,7 @@ void launch_gram(const float *X, int64_t ns, int64_t stride, int d, double *G, d
 // values), tail(x), scale * ||x||, 0...] (ka a multiple of 16, dp + 2 <=
 // ka), where W (dp x d, FP64, dp <= 62, ka <= 64) has orthonormal rows and
 // tail(x) = sqrt(||x||^2 - ||W x||^2) rounded up (W = nullptr: the
-// identity, dp = d <= 256, ka <= 272), stored as 2 ka bytes per row: BF16
+// identity, dp = d <= 256, ka <= 288), stored as 2 ka bytes per row: BF16
 // rn(a).  Rows are taken from X
 // through `order` (NULL = identity); rows from `rows` to `rows_pad` are zero.
 void launch_rotate_aug(const float *X, const int32_t *order, int64_t rows,
@@ -188,7 +188,7 @@ void launch_max_i32(const int32_t *x, int64_t n, int32_t *out, hipStream_t st);
 size_t count_lds(int prec, int D);
 
 struct BoundArgs {
-    int ka;                            // augmented row length 16 KS, KS <= 17
+    int ka;                            // augmented row length 16 KS: KS <= 11, or even up to 18
     const uint4 *Pb; int64_t m, mpad;  // augmented item rows (norm order), BF16
     const uint4 *Ub;                   // augmented user rows (rho order), BF16
     const float *tau_lo;               // per sorted user

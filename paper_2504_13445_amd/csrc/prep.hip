@@ -634,12 +634,12 @@ void k_rotate_aug(const float *__restrict__ X, const int32_t *__restrict__ order
     }
 }
 
-// The same rows when W is the identity (dp = d <= 256, ka <= 272): y = x
+// The same rows when W is the identity (dp = d <= 256, ka <= 288): y = x
 // exactly, and ||W x||^2 is the same FP64 sum as ||x||^2, so the tail is the
 // widening alone.  Up to the FP64 summation order of the norm (both rounded
 // up) these are the rows k_rotate_aug gives with W = I.  One wave per row:
 // lane j holds values 8j .. 8j + 7 of the augmented row and writes its
-// 16-byte word j.
+// 16-byte word j (at most 36 words).
 constexpr int AUG_ROWS = 4;  // rows (waves) per workgroup
 __global__ __launch_bounds__(64 * AUG_ROWS) void k_aug_ident(const float *__restrict__ X,
                                                             const int32_t *__restrict__ order,

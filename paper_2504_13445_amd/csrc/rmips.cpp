@@ -130,9 +130,13 @@ namespace {
 // of a user sample instead (d' <= DPRIME_ROT_MAX).
 constexpr int DPRIME_ROT_MAX = 62;
 int dprime(const rmips_ctx *c, int d) { return (c->dprime > 0 && c->dprime < d) ? c->dprime : d; }
-// augmented row length ka = 16 KS for d' values and two more columns
-// (KS <= 17 for d' <= 256); the identity's (d' = d) is the longest
-int aug_len(int dp) { return (dp + 2 + 15) & ~15; }
+// augmented row length ka for d' values and two more columns: a multiple of
+// 16, of 32 past 176 (the bound kernel of the longest rows takes 32 terms a
+// step), at most 288 for d' <= 256; the identity's (d' = d) is the longest
+int aug_len(int dp) {
+    const int k16 = (dp + 2 + 15) & ~15;
+    return k16 > 176 ? (dp + 2 + 31) & ~31 : k16;
+}
 constexpr int T0_TILES = 6;             // tiles of phase 1 of stage (a)
 constexpr int BATCH_FIRST = 256;
 constexpr int BATCH_MAX = 4096;
@@ -633,8 +637,8 @@ void run_prefix(const ThreshLayout &T, PrefixLayout &X, int64_t n, int64_t m, fl
 // augmented value is stored as BF16 hi(x) = rn(x), |x - hi(x)| <= 2^-9 |x|,
 // so each product hi(a) hi(b) is within (2 * 2^-9 + 2^-18) |a| |b| of a b,
 // at most 1.003 * 2^-8 * 1.415 ||p|| ||u|| over a row (sum |a_i||b_i| <=
-// ||a|| ||b|| <= 1.415 ||p|| ||u||); the matrix-core FP32 sums of <= 272
-// exact BF16 products add gamma_272 (< 2^-15.9) of the same, and the FP32
+// ||a|| ||b|| <= 1.415 ||p|| ||u||); the matrix-core FP32 sums of <= 288
+// exact BF16 products add gamma_288 (< 2^-15.8) of the same, and the FP32
 // rounding of W x (2^-24 relative) is far below: 1.43 * 2^-8 in all.  The
 // slack column hi(||p||) hi(s ||u||) gives at least s (1 - 2^-9)^2 ||p||
 // ||u||: s = 2^-7 covers that with room.  The absolute slack covers BF16

@@ -311,9 +311,9 @@ def test_topn_bound_counts_dominate_scores(shape, dprime):
 @pytest.mark.parametrize("d", [20, 33, 70, 130, 150, 190, 230])
 def test_topn_bound_counts_every_row_length(d):
     """The bound kernels of every augmented row length in between (ka = 32
-    to 240: register-resident users, LDS stages of 256 and 128 users, the
-    pipelined and the grouped-read forms): bound counts at or above the exact
-    scores and the exact top-N, with d' = d."""
+    to 256: register-resident users, LDS stages of 256 and 128 users, the
+    32x32 and the 16x16 matrix-core forms): bound counts at or above the
+    exact scores and the exact top-N, with d' = d."""
     _say("topn bound counts, d", d)
     rm = _rm()
     rng = np.random.default_rng(1000 + d)
