@@ -657,13 +657,20 @@ __global__ __launch_bounds__(64 * AUG_ROWS) void k_aug_ident(const float *__rest
     }
     const float *x = X + (int64_t)(order ? order[r] : r) * d;
     float v[8];
+    if ((d & 3) == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0) {  // 16-byte vectors: two loads per lane
+        const float4 *x4 = reinterpret_cast<const float4 *>(x);
+        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 y0 = 8 * lane < d ? x4[2 * lane] : z;
+        const float4 y1 = 8 * lane + 4 < d ? x4[2 * lane + 1] : z;
+        v[0] = y0.x; v[1] = y0.y; v[2] = y0.z; v[3] = y0.w;
+        v[4] = y1.x; v[5] = y1.y; v[6] = y1.z; v[7] = y1.w;
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = 8 * lane + e < d ? x[8 * lane + e] : 0.0f;
+    }
     double s = 0.0;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const int c = 8 * lane + e;
-        v[e] = c < d ? x[c] : 0.0f;
-        s = fma((double)v[e], (double)v[e], s);
-    }
+    for (int e = 0; e < 8; ++e) s = fma((double)v[e], (double)v[e], s);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
     const float tail = __double2float_ru(sqrt(0.0 + 1e-12 * s));
