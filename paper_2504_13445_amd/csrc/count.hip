@@ -801,11 +801,12 @@ void k_bound_lds(BoundArgs a) {
 // 16x16x32 matrix-core step, so that a wave's items (48: three tiles of 16
 // rows) take 12 KT registers and, up to KT = 7, three waves fit on a SIMD (a
 // workgroup of 12 waves, 576 items; two waves and 384 items for longer
-// rows).  User stages of 128 rows are copied into LDS as in k_bound_lds.  Operand layout of v_mfma_f32_16x16x32_bf16: lane l feeds
-// row (or column) l % 16 with terms 8 (l / 16) .. 8 (l / 16) + 7 of the step,
-// and holds result rows 4 (l / 16) + i (i = 0..3) of column l % 16.  Each
-// 32-user block is counted right after its products (the other waves of the
-// SIMD multiply meanwhile).
+// rows).  User stages of 128 rows are copied into LDS as in k_bound_lds.
+// Operand layout of v_mfma_f32_16x16x32_bf16: lane l feeds row (or column)
+// l % 16 with terms 8 (l / 16) .. 8 (l / 16) + 7 of the step, and holds
+// result rows 4 (l / 16) + i (i = 0..3) of column l % 16.  Each 32-user
+// block is counted right after its products (the other waves of the SIMD
+// multiply meanwhile).
 __host__ __device__ constexpr int b16_waves(int kt) { return kt <= 7 ? 12 : 8; }  // per workgroup
 constexpr int B16_TI = 3;       // 16-row item tiles per wave
 constexpr int B16_USERS = 128;  // users per stage
