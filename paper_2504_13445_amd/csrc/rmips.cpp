@@ -235,7 +235,7 @@ void prep_plan(int prec, int64_t n, int64_t m, int d, ThreshLayout &L, Carve &cv
 }
 
 // Stage (a)'s scratch: sort keys, candidate lists, refinement lists.
-void thresh_scratch_plan(int prec, int64_t n, int64_t m, int k, int cap_override,
+void thresh_scratch_plan(int prec, int64_t n, int64_t m, int d, int k, int cap_override,
                          ThreshLayout &L, Carve &cv) {
     // splits of the item range: about six rounds of screening workgroups
     // (256 users each, one per compute unit) over the whole chip
@@ -246,14 +246,19 @@ void thresh_scratch_plan(int prec, int64_t n, int64_t m, int k, int cap_override
     L.nsplit = (int)ns;
     // candidate capacity per user (all splits together): well above the
     // candidate counts of typical users; users beyond it are screened again
-    // with a tighter bound.  FP8's wider error band needs longer lists.
+    // with a tighter bound.  The wider error bands need longer lists: four
+    // times for e4m3 (longer lists cost its final selection more than its
+    // refinements save) and for e2m3 up to d = 128, eight for e2m3 beyond
+    // (at d = 200 half of the users overflowed four times and went to the
+    // exact fallback; at d = 50 and 100 the longer lists only slow the final
+    // selection) and for e2m1.
     // (even: each list is written as two halves)
     if (cap_override > 0) {
         L.cap = (cap_override + 1) & ~1;
     } else {
         int64_t capU = std::max<int64_t>(256, 16 * (int64_t)k);
-        if (prec == RMIPS_FP8_E4M3 || prec == RMIPS_FP6_E2M3) capU *= 4;
-        if (prec == RMIPS_FP4_E2M1) capU *= 8;
+        if (prec == RMIPS_FP8_E4M3 || (prec == RMIPS_FP6_E2M3 && d <= 128)) capU *= 4;
+        if ((prec == RMIPS_FP6_E2M3 && d > 128) || prec == RMIPS_FP4_E2M1) capU *= 8;
         L.cap = (int)(((capU + L.nsplit - 1) / L.nsplit + 7) / 8 * 8);
     }
     L.keys = cv.take<uint32_t>(m);
@@ -277,7 +282,7 @@ void thresh_scratch_plan(int prec, int64_t n, int64_t m, int k, int cap_override
 void thresh_plan(int prec, int64_t n, int64_t m, int d, int k, int cap_override, ThreshLayout &L,
                  Carve &cv) {
     prep_plan(prec, n, m, d, L, cv);
-    thresh_scratch_plan(prec, n, m, k, cap_override, L, cv);
+    thresh_scratch_plan(prec, n, m, d, k, cap_override, L, cv);
 }
 
 constexpr const char *BAD_INPUT = "input holds a NaN/Inf or a vector norm above 2^60";
@@ -595,7 +600,7 @@ void index_header(int64_t n, int64_t m, int d, int kmax, int prec, int dp,
 // scratch of an index build: stage (a)'s, the rho order, the bound's
 void index_build_plan(int prec, int64_t n, int64_t m, int d, int kmax, int cap_override,
                       IndexLayout &I, PrefixLayout &X, BoundLayout &B, Carve &cv) {
-    thresh_scratch_plan(prec, n, m, kmax, cap_override, I.T, cv);
+    thresh_scratch_plan(prec, n, m, d, kmax, cap_override, I.T, cv);
     prefix_plan(n, m, I.T.mpad, I.T.rowb, X, cv);
     bound_plan(n, m, I.T.mpad, d, B, cv);
 }
