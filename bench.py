@@ -238,9 +238,15 @@ def kernel_table(prof, stats, steps, n, m, d, k, prec):
     # bytes per element slot and padded width (FP6/FP4 use FP8's 32-byte block slots)
     eb = {"fp32": 4, "bf16": 2}.get(prec, 1)
     D = {"fp32": (d + 7) // 8 * 8, "bf16": (d + 15) // 16 * 16}.get(prec, (d + 63) // 64 * 64)
-    dp = d  # d' of the bound: the library's default, no rotation
-    ka = (dp + 2 + 15) // 16 * 16
+    # d' of the first bound: the rotated pre-pass where the library takes one
+    # (d >= 111 by default), else d; the items it leaves open get d' = d
+    dpre = int(avg("prepass_dprime"))
+    dp = dpre if dpre > 0 else d
+    ka = (d + 2 + 15) // 16 * 16 if d + 2 <= 176 else (d + 2 + 31) // 32 * 32
     mpad = (m + 63) // 64 * 64
+    # rows given identity (d' = d) augmented rows: all, or the users and the
+    # re-bounded items
+    aug_rows = (n + avg("rebound_items"), n + avg("rebound_items")) if dpre > 0 else (n + m, n + mpad)
     t0 = min(6, mpad // 64)
     # per step: (work, unit, peak, bound)
     work = {
@@ -249,8 +255,9 @@ def kernel_table(prof, stats, steps, n, m, d, k, prec):
         "k_thresh_screen/refine": (2.0 * d * avg("refine_pairs"), "flop", PEAK[prec], "mfma"),
         "k_count": (2.0 * d * avg("count_pairs"), "flop", PEAK[prec], "mfma"),
         "k_bound": (2.0 * (dp + 2) * avg("bound_pairs"), "flop", PEAK["bf16"], "mfma"),
+        "k_bound/rebound": (2.0 * (d + 2) * avg("rebound_pairs"), "flop", PEAK["bf16"], "mfma"),
         # FP32 rows read, the bound's BF16 rows (ka values) written
-        "k_aug_ident": ((n + m) * 4.0 * d + (n + mpad) * 2.0 * ka, "byte", HBM_PEAK, "hbm"),
+        "k_aug_ident": (aug_rows[0] * 4.0 * d + aug_rows[1] * 2.0 * ka, "byte", HBM_PEAK, "hbm"),
         # bytes: FP32 rows read, screening copies and four per-row floats written
         "k_quant": ((n + m) * (4.0 * d + D * eb + 16.0), "byte", HBM_PEAK, "hbm"),
         # candidate lists read (value, bound, id: 12 B each), tau and id written
@@ -393,6 +400,8 @@ def main():
         "visited_items": avg("visited_items"), "batches": avg("batches"),
         "thresh_pairs": avg("thresh_pairs"), "refine_pairs": avg("refine_pairs"),
         "count_pairs": avg("count_pairs"), "bound_pairs": avg("bound_pairs"),
+        "prepass_dprime": avg("prepass_dprime"), "rebound_items": avg("rebound_items"),
+        "rebound_pairs": avg("rebound_pairs"),
         "recheck_pairs": avg("recheck_pairs"), "cand_listed": avg("cand_listed"),
         "cand_pairs": avg("cand_pairs"), "overflow_users": avg("overflow_users"),
         "refine_users": avg("refine_users"),

@@ -99,6 +99,9 @@ typedef struct {
     float ms_screen;          /* stage (a) screening kernel alone */
     float ms_count_kernels;   /* stage (b) counting kernels alone, summed */
     float ms_bound_kernel;    /* stage (c) bound-count kernel alone */
+    int64_t rebound_items;    /* items given the d' = d bound after a pre-pass */
+    int64_t rebound_pairs;    /* pairs of that second bound */
+    int32_t prepass_dprime;   /* d' of the pre-pass bound (0: no pre-pass) */
 } rmips_stats;
 
 /*
@@ -169,11 +172,28 @@ rmips_status rmips_set_batch(rmips_ctx *ctx, int32_t first, int32_t max);
 rmips_status rmips_set_dprime(rmips_ctx *ctx, int32_t dprime);
 
 /*
+ * Pre-pass of rmips_topn's Eq. (3) bound when d' = d (Sec. 4.2): every item
+ * is first bounded after a rotation onto the top-`dprime` eigenvectors of a
+ * user sample, as rmips_set_dprime describes, and once the first batch has
+ * given an N-th score, the items whose pre-pass bound still reaches it (the
+ * only ones that can still enter the top-N) are bounded again with d' = d;
+ * each keeps the smaller of its two counts.  -1 (the default): automatic,
+ * dprime = 62 with FP32 or BF16 screening where the d' = d rows are at
+ * least twice as long as the rotated ones (d >= 111); 0: no pre-pass;
+ * 1 <= dprime <= 62 (and below d): that d'.  No effect with a rotation chosen by rmips_set_dprime, or in
+ * rmips_index_build.  Results do not change; the cost of the bounds does.
+ * RMIPS_EINVAL outside [-1, 62].
+ */
+rmips_status rmips_set_prepass(rmips_ctx *ctx, int32_t dprime);
+
+/*
  * Testing knob: when `uscore` is not NULL (a device array of m int32),
  * rmips_topn also writes the Eq. (3)/(6) bound count of every item in the
  * caller's order (Sec. 4.2; the count over the users of the item's
  * Cauchy-Schwarz prefix, Eq. 2), an upper bound of its exact score by
- * Theorem 2.  NULL stops it.  The array must outlive the rmips_topn call.
+ * Theorem 2: with a pre-pass (rmips_set_prepass), the pre-pass count, or
+ * for the items bounded again the smaller of the two.  NULL stops it.  The
+ * array must outlive the rmips_topn call.
  */
 rmips_status rmips_set_bound_output(rmips_ctx *ctx, int32_t *uscore);
 

@@ -25,6 +25,7 @@ EXPORTS = [
     "rmips_create", "rmips_destroy", "rmips_last_error", "rmips_set_stream", "rmips_sync",
     "rmips_set_profiling", "rmips_profile_entry",
     "rmips_set_candidate_cap", "rmips_set_batch", "rmips_set_bound_output", "rmips_set_dprime",
+    "rmips_set_prepass",
     "rmips_thresholds_workspace_size", "rmips_scores_workspace_size",
     "rmips_topn_workspace_size", "rmips_soft_workspace_size",
     "rmips_thresholds", "rmips_scores", "rmips_topn", "rmips_soft_fwd",
@@ -55,7 +56,8 @@ class Stats(ctypes.Structure):
                 ("ms_thresh", ctypes.c_float), ("ms_bound", ctypes.c_float),
                 ("ms_count", ctypes.c_float), ("ms_total", ctypes.c_float),
                 ("ms_screen", ctypes.c_float), ("ms_count_kernels", ctypes.c_float),
-                ("ms_bound_kernel", ctypes.c_float)]
+                ("ms_bound_kernel", ctypes.c_float), ("rebound_items", ctypes.c_int64),
+                ("rebound_pairs", ctypes.c_int64), ("prepass_dprime", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -125,6 +127,8 @@ def load():
     lib.rmips_set_bound_output.restype = st
     lib.rmips_set_dprime.argtypes = [vp, i32]
     lib.rmips_set_dprime.restype = st
+    lib.rmips_set_prepass.argtypes = [vp, i32]
+    lib.rmips_set_prepass.restype = st
     lib.rmips_thresholds_workspace_size.argtypes = [i64, i64, i32, i32, ctypes.c_int]
     lib.rmips_thresholds_workspace_size.restype = sz
     lib.rmips_scores_workspace_size.argtypes = [i64, i64, i32, ctypes.c_int]
@@ -317,12 +321,13 @@ def topn_workspace(n, m, d, k, N, prec="fp32", device=None):
 
 
 def topn(U, P, k, N, prec="fp32", ws=None, cand_cap=None, batch=None, bound_out=None,
-         dprime=None):
+         dprime=None, prepass=None):
     """Top-N item ids and scores (host int32 numpy arrays) and a stats dict.
     bound_out: optional int32 device tensor of m entries that receives the
     Eq. (3)/(6) bound count of every item (caller order).  dprime: the split
     dimension d' of that bound (None or 0: d' = d; 1..62: a rotation onto
-    the users' top-d' eigenvectors)."""
+    the users' top-d' eigenvectors).  prepass: d' of the rotated pre-pass
+    before the d' = d bound (None: automatic, 0: none, 1..62)."""
     import numpy as np
     U, P = _dev_f32(U, "U"), _dev_f32(P, "P")
     n, d = U.shape
@@ -338,12 +343,18 @@ def topn(U, P, k, N, prec="fp32", ws=None, cand_cap=None, batch=None, bound_out=
     st = Stats()
     # the knobs are set only when asked for, and reset after the call (d'
     # first: an invalid value then leaves nothing set)
+    if bound_out is not None and (bound_out.dtype != torch.int32 or bound_out.numel() != m
+                                  or not bound_out.is_cuda or not bound_out.is_contiguous()):
+        raise ValueError("bound_out must be a contiguous int32 device tensor of m entries")
     if dprime:
         _check(ctx, lib.rmips_set_dprime(ctx, int(dprime)))
+    if prepass is not None:
+        s = lib.rmips_set_prepass(ctx, int(prepass))
+        if s != 0:
+            if dprime:
+                lib.rmips_set_dprime(ctx, 0)
+            _check(ctx, s)
     if bound_out is not None:
-        if (bound_out.dtype != torch.int32 or bound_out.numel() != m or not bound_out.is_cuda
-                or not bound_out.is_contiguous()):
-            raise ValueError("bound_out must be a contiguous int32 device tensor of m entries")
         lib.rmips_set_bound_output(ctx, _ptr(bound_out))
     if cand_cap:
         lib.rmips_set_candidate_cap(ctx, int(cand_cap))
@@ -358,6 +369,8 @@ def topn(U, P, k, N, prec="fp32", ws=None, cand_cap=None, batch=None, bound_out=
         lib.rmips_set_batch(ctx, 0, 0)
     if dprime:
         lib.rmips_set_dprime(ctx, 0)
+    if prepass is not None:
+        lib.rmips_set_prepass(ctx, -1)
     if bound_out is not None:
         lib.rmips_set_bound_output(ctx, None)
     _check(ctx, status)

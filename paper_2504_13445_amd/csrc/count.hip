@@ -939,11 +939,11 @@ __host__ __device__ constexpr int bound_items(int ks) {
     return ks >= 12 ? 16 * B16_TI * b16_waves(ks / 2) : ks >= 3 ? 64 * BLW : 32 * bound_tiles(ks);
 }
 
-void launch_bound(const BoundArgs &a, hipStream_t st) {
+void launch_bound(const BoundArgs &a, hipStream_t st, const char *prof_name) {
     auto go = [&](auto ks) {
         constexpr int KS = decltype(ks)::value, BI = bound_items(KS);
         const unsigned g = (unsigned)((a.m + BI - 1) / BI * a.nsplit);
-        RMIPS_PROF(st, "k_bound");
+        RMIPS_PROF(st, prof_name);
         if constexpr (KS >= 12) {
             static_assert(KS % 2 == 0, "rows past 176 terms come in steps of 32");
             k_bound16<KS / 2><<<g, 64 * b16_waves(KS / 2), bound16_lds_bytes(KS / 2), st>>>(a);
@@ -966,12 +966,12 @@ void launch_bound(const BoundArgs &a, hipStream_t st) {
     }
 }
 
-// splits of each item block's user prefix: about 4096 workgroups, 1 to 16
-int bound_splits(int64_t m, int ka) {
+// splits of each item block's user prefix: about 4096 workgroups, 1 to smax
+int bound_splits(int64_t m, int ka, int smax) {
     const int64_t bi = bound_items(ka / 16);
     const int64_t blocks = (m + bi - 1) / bi;
     const int64_t s = (4096 + blocks - 1) / blocks;
-    return (int)(s < 1 ? 1 : (s > 16 ? 16 : s));
+    return (int)(s < 1 ? 1 : (s > smax ? smax : s));
 }
 
 // out[j] = sum over q of partial[q][j].  A 256-thread block covers 16
@@ -1059,6 +1059,38 @@ void launch_gather3_i32(const int32_t *a, const int32_t *b, const int32_t *c,
                         hipStream_t st) {
     RMIPS_PROF(st, "k_gather3_i32");
     k_gather3_i32<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(a, b, c, idx, n, da, db, dc);
+}
+
+// A segment of the visit order re-bounded: key[i] = id[i], val[i] = i
+// (the local slots, to be sorted by id), and the bound of each slot tightened
+// to the smaller of its two counts, also written to the norm-order array.
+__global__ void k_seg_init(const int32_t *__restrict__ id, int64_t n, uint32_t *__restrict__ key,
+                           int32_t *__restrict__ val) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    key[i] = (uint32_t)id[i];
+    val[i] = (int32_t)i;
+}
+
+void launch_seg_init(const int32_t *id, int64_t n, uint32_t *key, int32_t *val, hipStream_t st) {
+    RMIPS_PROF(st, "k_seg_init");
+    k_seg_init<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(id, n, key, val);
+}
+
+__global__ void k_seg_bound(int32_t *__restrict__ b, const int32_t *__restrict__ b0,
+                            const int32_t *__restrict__ rows, int64_t n,
+                            int32_t *__restrict__ uscore) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t v = min(b[i], b0[i]);
+    b[i] = v;
+    uscore[rows[i]] = v;
+}
+
+void launch_seg_bound(int32_t *b, const int32_t *b0, const int32_t *rows, int64_t n,
+                      int32_t *uscore, hipStream_t st) {
+    RMIPS_PROF(st, "k_seg_bound");
+    k_seg_bound<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(b, b0, rows, n, uscore);
 }
 
 // ------------------------------------------------------------------ top-N

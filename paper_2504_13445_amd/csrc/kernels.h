@@ -197,8 +197,8 @@ struct BoundArgs {
     int nsplit; int32_t *partial;
     unsigned long long *pairs;         // stats: evaluated pairs (may be NULL)
 };
-void launch_bound(const BoundArgs &a, hipStream_t st);
-int bound_splits(int64_t m, int ka);
+void launch_bound(const BoundArgs &a, hipStream_t st, const char *prof_name = "k_bound");
+int bound_splits(int64_t m, int ka, int smax = 16);
 
 // partial[s][j] summed over s (fixed order) -> out[j]
 void launch_colsum(const int32_t *partial, int nsplit, int64_t cols, int32_t *out,
@@ -213,6 +213,12 @@ void launch_gather_i32(const int32_t *src, const int32_t *idx, int64_t n, int32_
 void launch_gather3_i32(const int32_t *a, const int32_t *b, const int32_t *c,
                         const int32_t *idx, int64_t n, int32_t *da, int32_t *db, int32_t *dc,
                         hipStream_t st);
+
+// key[i] = id[i], val[i] = i for i < n
+void launch_seg_init(const int32_t *id, int64_t n, uint32_t *key, int32_t *val, hipStream_t st);
+// b[i] = min(b[i], b0[i]) and uscore[rows[i]] = b[i] for i < n
+void launch_seg_bound(int32_t *b, const int32_t *b0, const int32_t *rows, int64_t n,
+                      int32_t *uscore, hipStream_t st);
 
 // Running top-N: merge the exact scores of a batch into the sorted list
 // `top` (keys score<<32 | ~id), keep N.  status[0] = N-th score (-1 while

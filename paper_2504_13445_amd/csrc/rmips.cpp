@@ -93,6 +93,7 @@ struct rmips_ctx {
     int32_t cap_override = 0;
     int32_t batch_first = 0, batch_max = 0;
     int32_t dprime = 0;  // d' of the Eq. (3) bound (0: d' = d)
+    int32_t prepass = -1;  // d' of rmips_topn's pre-pass (-1: automatic, 0: none)
     int32_t *bound_out = nullptr;  // device, m int32 (testing knob)
     int32_t *h_status = nullptr;  // pinned, small
     int32_t *h_vis = nullptr;     // pinned: visit-order bounds and prefixes, top-N
@@ -130,6 +131,25 @@ namespace {
 // of a user sample instead (d' <= DPRIME_ROT_MAX).
 constexpr int DPRIME_ROT_MAX = 62;
 int dprime(const rmips_ctx *c, int d) { return (c->dprime > 0 && c->dprime < d) ? c->dprime : d; }
+// Pre-pass of rmips_topn with the d' = d bound: every item's bound is first
+// taken with a rotation onto DPRIME_ROT_MAX dimensions (a quarter of the
+// terms at d = 200), and the d' = d bound only for the items whose pre-pass
+// bound still reaches the N-th score after the first batch.  Automatic
+// where the identity rows are at least twice as long as the rotated ones and
+// the screening precision is FP32 or BF16: the items that the pre-pass
+// leaves above the first batch's N-th score usually take a second, small
+// batch, which streams every user again; with the wide bands of the 8-, 6-
+// and 4-bit formats that batch costs more than the pre-pass saves.
+int aug_len(int dp);
+int prepass_dim(const rmips_ctx *c, int d, int dmain, int prec) {
+    if (dmain < d || c->prepass == 0) return 0;
+    const int dp = c->prepass > 0 ? c->prepass : DPRIME_ROT_MAX;
+    if (dp >= d) return 0;
+    if (c->prepass < 0 &&
+        (aug_len(d) < 2 * aug_len(dp) || (prec != RMIPS_FP32 && prec != RMIPS_BF16)))
+        return 0;
+    return dp;
+}
 // augmented row length ka for d' values and two more columns: a multiple of
 // 16, of 32 past 176 (the bound kernel of the longest rows takes 32 terms a
 // step), at most 288 for d' <= 256; the identity's (d' = d) is the longest
@@ -430,7 +450,8 @@ void top_eigvecs(const std::vector<double> &G, int d, int dp, std::vector<double
 }
 
 // counters of rmips_topn (64-bit words): [0] stage (b) rechecks, [2] stage
-// (c) bound pairs, [8, 8 + CSTAT_SLOTS) pairs screened by stage (a)'s main
+// (c) bound pairs, [3] those of the d' = d bound after a pre-pass,
+// [8, 8 + CSTAT_SLOTS) pairs screened by stage (a)'s main
 // pass, then by its refinement passes, [CTR_CS, CTR_CS + 4 * CSTAT_SLOTS)
 // stage (a) candidate statistics
 constexpr int CTR_PAIRS = 8;
@@ -479,6 +500,9 @@ struct CountLayout {
     int32_t *status;
     int64_t *rechecks;
     int32_t *ulen_dev;
+    // a re-bounded segment of the visit order (local slots): norm-order rows,
+    // prefixes, caller ids, both bounds, slot orders
+    int32_t *sg_row, *sg_cs, *sg_id, *sg_b0, *sg_b, *sg_v1, *sg_v2;
 };
 
 struct TopnLayout {
@@ -541,6 +565,9 @@ void count_plan(int64_t m, int bmax, CountLayout &C, Carve &cv, bool with_inv) {
     C.top = reinterpret_cast<uint64_t *>(res + RES_TOP);
     C.rechecks = reinterpret_cast<int64_t *>(res + RES_CTR);
     C.ulen_dev = cv.take<int32_t>(1);
+    int32_t *sg = cv.take<int32_t>((size_t)7 * m);
+    C.sg_row = sg; C.sg_cs = sg + m; C.sg_id = sg + 2 * m; C.sg_b0 = sg + 3 * m;
+    C.sg_b = sg + 4 * m; C.sg_v1 = sg + 5 * m; C.sg_v2 = sg + 6 * m;
 }
 
 void topn_plan(int prec, int64_t n, int64_t m, int d, int k, int cap_override, int bmax,
@@ -674,10 +701,74 @@ void run_bound(const float *U, const PrefixLayout &X, const BoundLayout &B, cons
     launch_colsum(B.partialB, B.nsplitB, m, uscore, st);
 }
 
+// The second bound of rmips_topn's pre-pass (see prepass_dim): what the
+// d' = d bound of a segment of the visit order needs.
+struct Refine {
+    const float *U, *P;
+    const ThreshLayout *T;
+    const PrefixLayout *X;
+    const BoundLayout *B;
+    int64_t n, m;
+    int d;
+    int32_t *uscore;                 // norm order: tightened in place
+    unsigned long long *pairs;       // stats (may be NULL)
+};
+
+// Positions [r0, r1) of the visit order hold every item whose pre-pass bound
+// reaches the current N-th score and that is not yet scored.  Their d' = d
+// bounds (the identity rows, items in norm order so that each block's first
+// prefix is its longest), each tightened to the smaller of its two bounds,
+// then the segment re-sorted in place by (bound desc, id asc), with its
+// prefixes and ids.  Items past r1 keep pre-pass bounds below that score.
+hipError_t refine_segment(const Refine &R, CountLayout &C, int64_t r0, int64_t r1,
+                          hipStream_t st) {
+    const int64_t ns = r1 - r0;
+    const int ka = aug_len(R.d);
+    uint32_t *key = C.vkeys;  // free once the visit order is sorted
+    const int mbits = 32 - __builtin_clz((unsigned)R.m);
+    hipError_t e = hipMemcpyAsync(C.sg_row, C.visit + r0, sizeof(int32_t) * ns,
+                                  hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(key, C.visit + r0, sizeof(int32_t) * ns, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return e;
+    e = radix_sort_u32(key, C.sg_row, ns, R.X->usort, st, 0, mbits);  // norm order
+    if (e != hipSuccess) return e;
+    launch_gather3_i32(R.X->cs, R.T->perm, R.uscore, C.sg_row, ns, C.sg_cs, C.sg_id, C.sg_b0,
+                       st);
+    launch_rotate_aug(R.P, C.sg_id, ns, ns, R.d, nullptr, R.d, ka, 1.0f, R.B->Pa, st);
+    launch_rotate_aug(R.U, R.X->uperm, R.n, R.n, R.d, nullptr, R.d, ka, BOUND_SLACK, R.B->Ua,
+                      st);
+    BoundArgs ba{};
+    ba.ka = ka;
+    ba.Pb = R.B->Pa; ba.m = ns; ba.mpad = ns; ba.Ub = R.B->Ua; ba.tau_lo = R.X->us.tau_lo;
+    ba.abs_slack = BOUND_ABS_SLACK; ba.cs = C.sg_cs;
+    // few items: more splits of each block's users than the full pass takes,
+    // within the partial counts' room
+    const int64_t room = (int64_t)R.B->nsplitB * R.m / ns;
+    ba.nsplit = bound_splits(ns, ka, (int)std::min<int64_t>(256, room));
+    ba.partial = R.B->partialB; ba.pairs = R.pairs;
+    launch_bound(ba, st, "k_bound/rebound");
+    launch_colsum(R.B->partialB, ba.nsplit, ns, C.sg_b, st);
+    launch_seg_bound(C.sg_b, C.sg_b0, C.sg_row, ns, R.uscore, st);
+    // (bound desc, id asc): the slots by id, then stably by ~bound
+    launch_seg_init(C.sg_id, ns, key, C.sg_v1, st);
+    e = radix_sort_u32(key, C.sg_v1, ns, R.X->usort, st, 0, mbits);
+    if (e != hipSuccess) return e;
+    launch_visit_keys(C.sg_b, C.sg_v1, ns, key, C.sg_v2, nullptr, st);
+    e = radix_sort_u32(key, C.sg_v2, ns, R.X->usort, st, 0,
+                       32 - __builtin_clz((unsigned)R.n));
+    if (e != hipSuccess) return e;
+    launch_gather3_i32(C.sg_row, C.sg_b, C.sg_cs, C.sg_v2, ns, C.visit + r0, C.vis_us + r0,
+                       C.vis_cs + r0, st);
+    launch_gather_i32(C.sg_id, C.sg_v2, ns, C.vis_cid + r0, st);
+    return hipGetLastError();
+}
+
 // Host side of stage (b): events and the counters a caller reports.
 struct CountRun {
     hipEvent_t ev_vis, ev_end, ev_k0, ev_k1;  // visit order ready, last copy, kernel brackets
     int64_t visited = 0, batches = 0, screened = 0, launches = 0;
+    int64_t rebound = 0;  // items of the re-bounded segment
     float ms_count_k = 0.0f;
 };
 
@@ -685,7 +776,8 @@ rmips_status run_count_topn(rmips_ctx *ctx, const float *U, const float *P,
                             const ThreshLayout &T, const PrefixLayout &X, CountLayout &C,
                             const int32_t *uscore, int64_t n, int64_t m, int d, int N,
                             const ErrConst &ec, int bfirst, int bmax, CountRun &cr,
-                            int32_t *top_ids, int32_t *top_scores, const int32_t **h_ctr_out);
+                            int32_t *top_ids, int32_t *top_scores, const int32_t **h_ctr_out,
+                            const Refine *rf);
 
 }  // namespace
 
@@ -697,11 +789,15 @@ namespace {
 // batch goes out without a host synchronisation; stage (a)'s input check
 // (status word RES_BAD) is read with its results.  On success writes the
 // top-N (host) and points *h_ctr_out at the host copy of the counters.
+// With `rf` (bounds from a pre-pass), the items still open once an N-th
+// score is known are re-bounded with d' = d (refine_segment) before the
+// next batch.
 rmips_status run_count_topn(rmips_ctx *ctx, const float *U, const float *P,
                             const ThreshLayout &T, const PrefixLayout &X, CountLayout &C,
                             const int32_t *uscore, int64_t n, int64_t m, int d, int N,
                             const ErrConst &ec, int bfirst, int bmax, CountRun &cr,
-                            int32_t *top_ids, int32_t *top_scores, const int32_t **h_ctr_out) {
+                            int32_t *top_ids, int32_t *top_scores, const int32_t **h_ctr_out,
+                            const Refine *rf) {
     hipStream_t st = ctx->stream;
     launch_visit_keys(uscore, C.inv, m, C.vkeys, C.visit, C.status, st);
     // the keys are ~uscore with 0 <= uscore <= n: only the bits of n vary
@@ -730,6 +826,7 @@ rmips_status run_count_topn(rmips_ctx *ctx, const float *U, const float *P,
     const int32_t *h_st = reinterpret_cast<const int32_t *>(h_res + RES_STATUS);
     const uint64_t *top = reinterpret_cast<const uint64_t *>(h_res + RES_TOP);
     int64_t r0 = 0;
+    bool refined = rf == nullptr;
     // First batch: the items with the largest bounds.  After it, the items
     // that can still enter the top-N are exactly those whose bound reaches
     // the current N-th score: a prefix of the visit order, scored next.
@@ -798,6 +895,21 @@ rmips_status run_count_topn(rmips_ctx *ctx, const float *U, const float *P,
         // items whose bound is strictly below the N-th score cannot enter
         int64_t e = r0;
         while (e < m && h_us[e] >= tauN) ++e;
+        if (!refined && e > r0) {
+            refined = true;
+            cr.rebound = e - r0;
+            HIPTRY(refine_segment(*rf, C, r0, e, st));
+            // (the counters again, in case no batch follows)
+            HIPTRY(hipMemcpyAsync(h_res + RES_CTR, C.status + RES_CTR / sizeof(int32_t),
+                                  RES_TOP - RES_CTR, hipMemcpyDeviceToHost, st));
+            HIPTRY(hipMemcpyAsync(h_us + r0, C.vis_us + r0, sizeof(int32_t) * (e - r0),
+                                  hipMemcpyDeviceToHost, st));
+            HIPTRY(hipMemcpyAsync(h_cs + r0, C.vis_cs + r0, sizeof(int32_t) * (e - r0),
+                                  hipMemcpyDeviceToHost, st));
+            HIPTRY(hipStreamSynchronize(st));
+            e = r0;
+            while (e < m && h_us[e] >= tauN) ++e;
+        }
         bsz = std::min<int64_t>(e - r0, bmax);
     }
     ctx->prof.resolve();  // (the stream is idle after the last batch)
@@ -1034,6 +1146,12 @@ rmips_status rmips_set_dprime(rmips_ctx *ctx, int32_t dprime) {
     return RMIPS_OK;
 }
 
+rmips_status rmips_set_prepass(rmips_ctx *ctx, int32_t dprime) {
+    if (!ctx || dprime < -1 || dprime > DPRIME_ROT_MAX) return RMIPS_EINVAL;
+    ctx->prepass = dprime;
+    return RMIPS_OK;
+}
+
 rmips_status rmips_set_bound_output(rmips_ctx *ctx, int32_t *uscore) {
     if (!ctx) return RMIPS_EINVAL;
     ctx->bound_out = uscore;
@@ -1238,8 +1356,11 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     // The Gram matrix of a user sample (for the rotation of Eq. (3)) does
     // not depend on tau: it goes to the host first, and the host computes
     // its eigenvectors while the GPU runs stage (a).  With d' = d any
-    // orthonormal basis gives the same bound: the identity.
-    const int dp = dprime(ctx, d), ka = aug_len(dp);
+    // orthonormal basis gives the same bound: the identity.  With a
+    // pre-pass the rotated bound comes first and d' = d follows for the
+    // items it leaves open.
+    const int dmain = dprime(ctx, d), dpre = prepass_dim(ctx, d, dmain, prec);
+    const int dp = dpre > 0 ? dpre : dmain, ka = aug_len(dp);
     const bool rotate = dp < d;
     std::vector<double> G, W;
     if (rotate) {
@@ -1270,16 +1391,21 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
     launch_rotate_aug(P, L.T.perm, m, L.T.mpad, d, Wd, dp, ka, 1.0f, L.B.Pa, st);
     run_bound(U, L.X, L.B, Wd, dp, n, m, L.T.mpad, d, ctr + 2, ev[6], ev[7], L.uscore, st);
     launch_invert_perm(L.T.perm, m, L.C.inv, st);
-    if (ctx->bound_out) launch_gather_i32(L.uscore, L.C.inv, m, ctx->bound_out, st);
     HIPTRY(hipGetLastError());
 
     // ---- stage (b): exact scores in bound order, running top-N, stop rule
     CountRun cr;
     cr.ev_vis = ev[2]; cr.ev_end = ev[3]; cr.ev_k0 = ev[8]; cr.ev_k1 = ev[9];
     const int32_t *h = nullptr;
+    Refine rf{U, P, &L.T, &L.X, &L.B, n, m, d, L.uscore, ctr + 3};
     s = run_count_topn(ctx, U, P, L.T, L.X, L.C, L.uscore, n, m, d, N, ec, bfirst, bmax, cr,
-                       top_ids, top_scores, &h);
+                       top_ids, top_scores, &h, dpre > 0 ? &rf : nullptr);
     if (s != RMIPS_OK) return s;
+    if (ctx->bound_out) {
+        launch_gather_i32(L.uscore, L.C.inv, m, ctx->bound_out, st);
+        HIPTRY(hipGetLastError());
+        HIPTRY(hipStreamSynchronize(st));
+    }
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
         stats->visited_items = cr.visited;
@@ -1316,6 +1442,9 @@ rmips_status rmips_topn(rmips_ctx *ctx, const float *U, int64_t n, const float *
         stats->ms_screen = tsc;
         stats->ms_count_kernels = cr.ms_count_k;
         stats->ms_bound_kernel = tbd;
+        stats->rebound_items = cr.rebound;
+        stats->rebound_pairs = hc[3];
+        stats->prepass_dprime = dpre;
     }
     return RMIPS_OK;
 }
@@ -1502,7 +1631,7 @@ rmips_status rmips_index_topn(rmips_ctx *ctx, const float *U, int64_t n, const f
     cr.ev_vis = ev[1]; cr.ev_end = ev[2]; cr.ev_k0 = ev[3]; cr.ev_k1 = ev[4];
     const int32_t *h = nullptr;
     s = run_count_topn(ctx, U, P, I.T, X, C, I.table + (size_t)(k - 1) * m, n, m, d, N, ec,
-                       bfirst, bmax, cr, top_ids, top_scores, &h);
+                       bfirst, bmax, cr, top_ids, top_scores, &h, nullptr);
     if (s != RMIPS_OK) return s;
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));

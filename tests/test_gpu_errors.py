@@ -123,6 +123,21 @@ def test_topn_rejects_sizes_out_of_range():
     assert ids.tolist() == ri.tolist() and sc.tolist() == rs.tolist()
 
 
+def test_set_prepass_rejects_out_of_range():
+    """rmips_set_prepass takes -1 (automatic), 0 (none) or 1..62."""
+    _say("set_prepass out of range")
+    rm, lib = _rm()
+    U, P = synth.make_config(0, n=100, m=50)
+    for dp in (-2, 63):
+        with pytest.raises(rm.RmipsError) as e:
+            rm.topn(_g(U), _g(P), 5, 5, prepass=dp)
+        assert e.value.status == lib.RMIPS_EINVAL, dp
+    ri, rs = _topn_ref(U, P, 5, 5)
+    for dp in (None, 0, 3):
+        ids, sc, _ = rm.topn(_g(U), _g(P), 5, 5, prepass=dp)
+        assert ids.tolist() == ri.tolist() and sc.tolist() == rs.tolist(), dp
+
+
 def test_set_dprime_rejects_out_of_range():
     """rmips_set_dprime takes 0 (d' = d) or a rotation to 1..62 dimensions."""
     _say("set_dprime out of range")

@@ -293,7 +293,9 @@ def test_topn_bound_counts_dominate_scores(shape, dprime):
     score = orc.histogram_scores(tk, m)
     us = torch.zeros(m, dtype=torch.int32, device=_dev())
     ri, rs = orc.topn_from_scores(score, 10)
-    ids, sc, _ = rm.topn(_g(U), _g(P), k, 10, prec="bf16", bound_out=us, dprime=dprime)
+    # (no pre-pass: the d' = d bound of every item)
+    ids, sc, _ = rm.topn(_g(U), _g(P), k, 10, prec="bf16", bound_out=us, dprime=dprime,
+                         prepass=0)
     assert ids.tolist() == ri.tolist() and sc.tolist() == rs.tolist()
     us = us.cpu().numpy().astype(np.int64)
     bad = np.nonzero(us < score)[0]
@@ -313,7 +315,7 @@ def test_topn_bound_counts_every_row_length(d):
     """The bound kernels of every augmented row length in between (ka = 32
     to 256: register-resident users, LDS stages of 256 and 128 users, the
     32x32 and the 16x16 matrix-core forms): bound counts at or above the
-    exact scores and the exact top-N, with d' = d."""
+    exact scores and the exact top-N, with d' = d (every item, no pre-pass)."""
     _say("topn bound counts, d", d)
     rm = _rm()
     rng = np.random.default_rng(1000 + d)
@@ -324,12 +326,66 @@ def test_topn_bound_counts_every_row_length(d):
     score = orc.histogram_scores(tk, m)
     us = torch.zeros(m, dtype=torch.int32, device=_dev())
     ri, rs = orc.topn_from_scores(score, 20)
-    ids, sc, _ = rm.topn(_g(U), _g(P), 10, 20, prec="bf16", bound_out=us)
+    ids, sc, _ = rm.topn(_g(U), _g(P), 10, 20, prec="bf16", bound_out=us, prepass=0)
     assert ids.tolist() == ri.tolist() and sc.tolist() == rs.tolist()
     us = us.cpu().numpy().astype(np.int64)
     bad = np.nonzero(us < score)[0]
     assert bad.size == 0, (bad[:10], us[bad[:10]], score[bad[:10]])
     assert us.max() <= U.shape[0]
+
+
+@pytest.mark.parametrize("d,prepass,batch,prec", [
+    (50, 10, (16, 64), "bf16"), (130, -1, (16, 64), "bf16"), (200, -1, (16, 64), "fp32"),
+    (200, 30, (4, 8), "bf16"), (240, 62, (16, 64), "fp8"), (256, -1, None, "bf16")])
+def test_topn_prepass(d, prepass, batch, prec):
+    """The rotated pre-pass before the d' = d bound (Eq. 3 with a rotation,
+    then with the identity for the items it leaves open once the first
+    batches give an N-th score): the exact top-N, bound counts at or above
+    the exact scores, and every item's count either the pre-pass one (the
+    bound of the same rotation alone) or, for the items bounded again, the
+    smaller of that and the d' = d count (the bound without a pre-pass).  A
+    first batch of 4 items (N = 10) takes the N-th score from a later
+    batch."""
+    _say("topn prepass, d", d, "prepass", prepass, "batch", batch, prec)
+    rm = _rm()
+    rng = np.random.default_rng(2000 + d)
+    C = rng.standard_normal((12, d))
+    U = (C[rng.integers(0, 12, 3000)] + 0.7 * rng.standard_normal((3000, d)))
+    U = (U * rng.lognormal(0.0, 0.25, (3000, 1))).astype(np.float32)
+    P = (rng.standard_normal((1500, d)) * rng.lognormal(0.0, 0.8, (1500, 1))).astype(np.float32)
+    m = P.shape[0]
+    _, _, tk = orc.kmips_c(U, P, 10)
+    score = orc.histogram_scores(tk, m)
+    ri, rs = orc.topn_from_scores(score, 10)
+    us = torch.zeros(m, dtype=torch.int32, device=_dev())
+    u0 = torch.zeros(m, dtype=torch.int32, device=_dev())
+    ids, sc, st = rm.topn(_g(U), _g(P), 10, 10, prec=prec, bound_out=us, prepass=prepass,
+                          batch=batch)
+    print("stats", st, flush=True)
+    assert ids.tolist() == ri.tolist() and sc.tolist() == rs.tolist()
+    assert st["prepass_dprime"] == (62 if prepass == -1 else prepass)
+    if prepass == -1:  # automatic: FP32 and BF16 screening only
+        _, _, s8 = rm.topn(_g(U), _g(P), 10, 10, prec="fp8")
+        assert s8["prepass_dprime"] == 0 and s8["rebound_items"] == 0
+    assert st["rebound_items"] > 0 and st["rebound_pairs"] > 0
+    ids0, sc0, st0 = rm.topn(_g(U), _g(P), 10, 10, prec=prec, bound_out=u0, prepass=0,
+                             batch=batch)
+    assert st0["prepass_dprime"] == 0 and st0["rebound_items"] == 0
+    assert ids0.tolist() == ri.tolist() and sc0.tolist() == rs.tolist()
+    dpre = st["prepass_dprime"]
+    ur = torch.zeros(m, dtype=torch.int32, device=_dev())
+    ids1, sc1, _ = rm.topn(_g(U), _g(P), 10, 10, prec=prec, bound_out=ur, dprime=dpre,
+                           batch=batch)
+    assert ids1.tolist() == ri.tolist() and sc1.tolist() == rs.tolist()
+    us = us.cpu().numpy().astype(np.int64)
+    u0 = u0.cpu().numpy().astype(np.int64)
+    ur = ur.cpu().numpy().astype(np.int64)
+    bad = np.nonzero(us < score)[0]
+    assert bad.size == 0, (bad[:10], us[bad[:10]], score[bad[:10]])
+    assert us.max() <= U.shape[0]
+    ok = (us == ur) | (us == np.minimum(ur, u0))
+    assert ok.all(), np.nonzero(~ok)[0][:10]
+    assert (us < ur).any()
 
 
 @pytest.mark.parametrize("prec", PRECS)
