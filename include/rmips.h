@@ -241,7 +241,8 @@ rmips_status rmips_scores(rmips_ctx *ctx, const float *U, int64_t n,
  * Def. 3 by the paper's method (Sec. 4, Alg. 2 driven by exact thresholds):
  * stage (a), then the Cauchy-Schwarz (Eq. 2) and incremental-pruning
  * (Eq. 3 / Eq. 6) upper bounds on every score (d' = d unless
- * rmips_set_dprime chose a rotation onto the users' dominant eigenspace),
+ * rmips_set_dprime chose a rotation onto the users' dominant eigenspace;
+ * d' = d after a rotated pre-pass where rmips_set_prepass says so),
  * then exact scores of items visited in (bound desc, id asc) order until
  * the next bound is below the current N-th score.
  *   1 <= N <= min(m, RMIPS_N_MAX).
