@@ -1,9 +1,10 @@
 """GPU parity over a seeded sweep of small random problems: rmips_topn's
 ids and scores and rmips_thresholds' tau (bit for bit) and tau ids against
 the CPU FP64 oracle, at every screening precision, with d' = d and with the
-paper's rotation, on Gaussian, integer-valued (exact ties, duplicated
-items), wide-scale and clustered inputs, at n, m, d, k and N drawn across
-their ranges (d up to 256, k up to 32)."""
+paper's rotation, with and without a rotated pre-pass before the d' = d
+bound, with default and small batches, on Gaussian, integer-valued (exact
+ties, duplicated items), wide-scale and clustered inputs, at n, m, d, k and
+N drawn across their ranges (d up to 256, k up to 32)."""
 import numpy as np
 import pytest
 
@@ -47,17 +48,28 @@ def _case(seed):
         C = rng.standard_normal((8, d))
         U = C[rng.integers(0, 8, n)] + 0.3 * rng.standard_normal((n, d))
         P = rng.standard_normal((m, d)) * rng.lognormal(0, 0.6, (m, 1))
-    return U.astype(np.float32), P.astype(np.float32), k, N, prec, dprime
+    # the bound's pre-pass and the batch sizes of the counting loop, from a
+    # stream of their own (the problems above stay as they were): automatic,
+    # none or a rotation to 1..62 dimensions; first batches from 1 item, so
+    # that the items still open are often re-bounded after a later batch
+    r2 = np.random.default_rng(17000 + seed)
+    prepass = -1 if r2.random() < 0.4 else (0 if r2.random() < 0.3 else int(r2.integers(1, 63)))
+    batch = None
+    if r2.random() < 0.5:
+        first = int(r2.integers(1, 65))
+        batch = (first, int(r2.integers(first, 257)))
+    return U.astype(np.float32), P.astype(np.float32), k, N, prec, dprime, prepass, batch
 
 
 @pytest.mark.parametrize("seed", range(100))
 def test_random_problem(seed):
     import paper_2504_13445_amd as rm
-    U, P, k, N, prec, dprime = _case(seed)
-    print("[case] sweep", seed, U.shape, P.shape, k, N, prec, dprime, flush=True)
+    U, P, k, N, prec, dprime, prepass, batch = _case(seed)
+    print("[case] sweep", seed, U.shape, P.shape, k, N, prec, dprime, prepass, batch, flush=True)
     tau, tid, tk = orc.kmips_c(U, P, k)
     ri, rs = orc.topn_from_scores(orc.histogram_scores(tk, P.shape[0]), N)
-    ids, sc, _ = rm.topn(_g(U), _g(P), k, N, prec=prec, dprime=dprime)
+    ids, sc, _ = rm.topn(_g(U), _g(P), k, N, prec=prec, dprime=dprime, prepass=prepass,
+                         batch=batch)
     assert ids.tolist() == ri.tolist() and sc.tolist() == rs.tolist()
     t, j = rm.thresholds(_g(U), _g(P), k, prec=prec)
     assert np.array_equal(t.cpu().numpy().view(np.uint64), tau.view(np.uint64))
